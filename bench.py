@@ -1,0 +1,171 @@
+"""Benchmark of the opacity + k-distribution hot path on one MI355X.
+
+A step is one pass of the whole path over the mid-scale binary64 workload
+(1e6 synthetic lines over 0-30000 cm^-1, 0.01 cm^-1 grid of 3e6 points,
+100 cm^-1 cutoff, T = 1500 K, P = 1 atm, 300 bins x 20 Gauss-Legendre g):
+per-line scaling and windows, the Voigt evaluation and accumulation kernel,
+and the per-bin sort and k(g).  The line list is resident on the device
+before timing starts.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOAD = "lines1e6_grid3e6"
+PEAK_FP64_TFLOPS = 78.6  # MI355X binary64 vector peak
+# Algorithmic flops per line-point evaluation, by region, counted from the
+# formulas as written (+, -, *, / and each exp/sin/cos/erfcx as one flop, an
+# fma as two): 1-node rule S G/(pi (dv^2 + G^2)) plus the offset and the
+# accumulation: 5; 3-node rule, three Lorentzians with weights: 16; core
+# series with its average of 24 terms at 10 flops each plus 18 of set-up: 258.
+FLOPS_PER_EVAL = {"gh1": 5, "gh3": 16, "core": 258}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "opacity_f64_lines1e6_grid3e6_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1503_03806_amd", "csrc", "opacity_f64.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_digest() -> str:
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the opacity kernel from the committed counter
+    summary, or None if the kernel source changed since it was taken."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha256_16") != kernel_digest():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(w, points: int):
+    import oracle
+    lines, cond, grid = w.lines(), w.conditions(), w.grid()
+    N = grid["n_points"]
+    ppb = w.points_per_bin
+    j0 = (N // 2 // ppb) * ppb
+    j1 = min(j0 + points, N)
+    g, _ = oracle.g_nodes(w.n_g)
+    t0 = time.perf_counter()
+    kap, evals = oracle.opacity(lines, cond, grid, j0, j1)
+    oracle.kdist(kap, ppb, g)
+    dt = time.perf_counter() - t0
+    return {"value": evals / dt, "unit": "evals/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "grid points %d..%d (%d of %d bins) of %s, all %d lines: %d evals "
+                      "in %.2f s, opacity + k(g)" % (j0, j1, (j1 - j0) // ppb, N // ppb,
+                                                    w.name, len(lines["nu"]), evals, dt)}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-points", type=int, default=150000,
+                    help="grid points in the oracle's timed sample")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after timing, run one plain device copy of this size (counter "
+                         "calibration)")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(got --gpus %d)" % a.gpus, file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1503_03806_amd as hk
+    import synth
+
+    w = synth.WORKLOADS[WORKLOAD]
+    lines, cond, grid = w.lines(), w.conditions(), w.grid()
+    state = {k: cond[k] for k in ("T", "P", "P_self", "q_ratio")}
+    N, ppb = grid["n_points"], w.points_per_bin
+    n_bins = -(-N // ppb)
+    log("bench: %s, %d lines, %d points" % (w.name, len(lines["nu"]), N))
+
+    ctx = hk.Context(0)
+    ctx.load_lines(lines, cond["mass_amu"], cond["T0"])
+    g, _ = hk.hk_gauss_legendre(w.n_g)
+    kappa = torch.empty(N, dtype=torch.float64, device="cuda")
+    k_out = torch.empty((n_bins, w.n_g), dtype=torch.float64, device="cuda")
+
+    def step():
+        hk.hk_opacity(ctx.h, state, grid, hk.HK_F64, kappa)
+        hk.hk_kdist(ctx.h, kappa, hk.HK_F64, N, ppb, g, k_out)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tm = ctx.timing()
+    ctx.set_timing(False)
+    if a.calib_copy_mib:
+        n = a.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d bytes read, %d bytes written" % (8 * n, 8 * n))
+
+    evals = st["evals"]
+    ms_step = 1e3 * elapsed / a.steps
+    op_ms = tm["opacity"][0] / max(tm["opacity"][1], 1)
+    flops = (FLOPS_PER_EVAL["gh1"] * st["evals_gh1"] + FLOPS_PER_EVAL["gh3"] * st["evals_gh3"] +
+             FLOPS_PER_EVAL["core"] * st["evals_core"])
+    achieved = flops / (op_ms * 1e-3) / 1e12
+    rec = {
+        "metric": "Voigt line-point evals/s (opacity + k(g) wall time per step in ms_per_step)",
+        "value": evals * a.steps / elapsed,
+        "unit": "evals/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "n_lines": len(lines["nu"]), "n_points": N,
+                   "dnu": grid["dnu"], "cutoff": grid["cutoff"], "T": cond["T"],
+                   "P_atm": cond["P"], "n_bins": n_bins, "n_g": w.n_g, "precision": "f64",
+                   "evals_per_step": evals, "evals_core": st["evals_core"],
+                   "evals_gh3": st["evals_gh3"], "evals_gh1": st["evals_gh1"]},
+        "stage_ms": {k: v[0] / max(v[1], 1) for k, v in tm.items()},
+        "roofline": {"bound": "alu", "kernel": "opacity_f64_kernel",
+                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(),
+                     "flops_per_launch": flops, "launch_ms": op_ms},
+    }
+    if not a.no_cpu_baseline:
+        log("bench: timing the oracle on a sample")
+        rec["cpu_baseline"] = cpu_baseline(w, a.cpu_points)
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,198 @@
+/*
+ * hk.h -- C ABI of the MI355X (gfx950) line-by-line opacity and
+ * k-distribution library.
+ *
+ * The method is that of Grimm & Heng (2015), "HELIOS-K: an ultrafast,
+ * open-source opacity calculator for radiative transfer", arXiv:1503.03806:
+ * a line list goes in; for given temperature and pressure every line's
+ * strength and widths are scaled (§2.3), its Voigt profile is evaluated at
+ * every grid point within the line-wing cutoff and summed into the opacity
+ * function (§2.4, §2.5), and each wavenumber bin is reduced to its
+ * k-distribution (§2.2, §2.6).
+ *
+ * Conventions
+ *  - Every call returns an int status: HK_OK (0) or a negative HK_E* code.
+ *    hk_last_error() gives a message.  No C++ exception crosses the ABI.
+ *  - Host pointers are marked [host], device pointers [device].  The caller
+ *    owns every buffer it passes; the context owns only its private device
+ *    copy of the line list and its scratch space.
+ *  - Device work is enqueued on the context's HIP stream (hk_set_stream) and
+ *    is asynchronous; hk_sync() waits for it.  Calls on one context must not
+ *    overlap (one host thread per context).
+ *  - Units: wavenumber, widths, cutoff in cm^-1; gamma in cm^-1/atm; pressure
+ *    in atm (the reference pressure P0 is 1 atm); temperature in K; line
+ *    strength S in cm/molecule; the opacity written is a cross section in
+ *    cm^2/molecule (divide by the molecular mass for cm^2/g, §2.3).
+ *  - Grid points are nu_j = nu_min + j * dnu, j = 0 .. n_points-1 (uniform
+ *    spacing, §2.2).
+ */
+#ifndef HK_H
+#define HK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HK_OK 0
+#define HK_EINVAL (-1)        /* invalid argument; nothing was enqueued */
+#define HK_ENOMEM (-2)        /* device or host allocation failed */
+#define HK_EDEVICE (-3)       /* a HIP runtime call failed */
+#define HK_EUNSUPPORTED (-4)  /* valid request this build does not provide */
+#define HK_ENOTREADY (-5)     /* call order: e.g. opacity before lines */
+
+#define HK_MAX_G 64           /* most g values per k-distribution */
+
+typedef struct hk_ctx hk_ctx;
+
+/* Arithmetic of the profile evaluation and accumulation. */
+typedef enum {
+    HK_F64 = 0,        /* everything in binary64 */
+    HK_F32_KAHAN = 1   /* binary32 profiles, compensated binary32 sums;
+                          line strengths and g in binary64 */
+} hk_precision;
+
+/* Line list, §2.3 (the HITRAN/HITEMP fields the method uses).  [host]
+ * arrays of n values each.  Optional arrays may be NULL. */
+typedef struct {
+    int64_t n;
+    const double* nu;         /* line centre at zero pressure, > 0 */
+    const double* S_ref;      /* line strength at T_ref, >= 0 */
+    const double* E_lower;    /* lower-state energy E'' (the paper's Delta E) */
+    const double* gamma_air;  /* air-broadened HWHM at T_ref and P0, >= 0 */
+    const double* n_air;      /* temperature exponent of the widths */
+    const double* gamma_self; /* self-broadened HWHM; NULL: gamma_air */
+    const double* delta;      /* pressure shift per atm (eq. 21); NULL: 0 */
+    const double* A21;        /* Einstein A coefficient, s^-1; NULL: 0 */
+} hk_lines;
+
+typedef struct {
+    double T_ref;     /* reference temperature of S_ref, gamma (296 K) */
+    double mass_amu;  /* molecular mass in atomic mass units, > 0 */
+} hk_species;
+
+/* One thermodynamic state. */
+typedef struct {
+    double T;        /* K, > 0 */
+    double P;        /* total pressure, atm, >= 0 */
+    double P_self;   /* self-broadening partial pressure, 0 <= P_self <= P */
+    double q_ratio;  /* partition-function ratio Q(T_ref)/Q(T), > 0 */
+} hk_state;
+
+typedef struct {
+    double nu_min;     /* first grid point */
+    double dnu;        /* spacing, > 0 */
+    int64_t n_points;  /* 0 <= n_points <= HK_MAX_POINTS */
+    double cutoff;     /* absolute line-wing cutoff, >= 0 (§2.4, §3.4) */
+} hk_grid;
+#define HK_MAX_POINTS ((int64_t)1 << 30)
+
+/* Bins of consecutive grid points and the g values at which k(g) is
+ * reported.  The last bin may hold fewer than points_per_bin points. */
+typedef struct {
+    int64_t points_per_bin;  /* >= 1 */
+    int32_t n_g;             /* 1 .. HK_MAX_G */
+    const double* g;         /* [host] n_g values, each in (0, 1) */
+} hk_bins;
+
+/* Counts of line-point evaluations of the last hk_opacity call. */
+typedef struct {
+    int64_t evals;       /* sum over lines of |cutoff window ∩ grid| */
+    int64_t evals_core;  /* a^2 + u^2 < 100: series (Algorithm 916 form) */
+    int64_t evals_gh3;   /* 100 <= a^2 + u^2 < 1e6: 3-node Gauss-Hermite */
+    int64_t evals_gh1;   /* a^2 + u^2 >= 1e6: 1-node Gauss-Hermite */
+    int64_t n_lines;     /* lines in the context */
+} hk_run_stats;
+
+/* ---- context ------------------------------------------------------------ */
+
+int hk_version(void); /* major * 10000 + minor * 100 + patch */
+
+/* Create a context on HIP device `device` with its own stream.  *out is set
+ * to NULL on failure. */
+int hk_create(int device, hk_ctx** out);
+int hk_destroy(hk_ctx* ctx);
+
+/* Use `hip_stream` (a hipStream_t, e.g. torch's current stream) for all
+ * later work.  NULL is HIP's null (legacy default) stream, which is what
+ * PyTorch reports for its default stream.  Until this is called the context
+ * uses a non-blocking stream of its own. */
+int hk_set_stream(hk_ctx* ctx, void* hip_stream);
+int hk_sync(hk_ctx* ctx);
+
+/* Message of the last failed call on ctx (ctx may be NULL: last failure on
+ * this thread).  Never NULL; valid until the next call. */
+const char* hk_last_error(const hk_ctx* ctx);
+
+/* Copy a line list to the device, ordered by ascending (nu, input index),
+ * replacing any earlier one.  Inputs are validated (finite values, nu > 0,
+ * S_ref, gamma >= 0); rejected lists leave the context unchanged.
+ * Synchronous with respect to the host arrays: they may be freed on return. */
+int hk_load_lines(hk_ctx* ctx, const hk_lines* lines, const hk_species* species);
+
+/* ---- §2.3-§2.5: opacity function ---------------------------------------- */
+
+/* Opacity kappa(nu_j) on the grid for one state.  For every line: S(T) by
+ * eq. (18), Gamma_D and the Voigt parameters by eq. (19), Gamma_L by
+ * eq. (20), centre shifted by eq. (21); then kappa_j = sum of S Phi(nu_j)
+ * (eq. (16)) over the lines whose cutoff window contains j.  The window is
+ * the closed index interval [ceil((nu0' - cutoff - nu_min)/dnu),
+ * floor((nu0' + cutoff - nu_min)/dnu)].  H_V(a,u) uses the series form of
+ * the Faddeeva function for a^2+u^2 < 100 and 3-node / 1-node Gauss-Hermite
+ * quadrature for a^2+u^2 < 1e6 / >= 1e6 (§2.4).  Each point sums its lines
+ * in ascending (nu, input index) order, with no atomics: results are
+ * bitwise reproducible.
+ *
+ * precision HK_F64: kappa is [device] double[n_points]; comp must be NULL.
+ * precision HK_F32_KAHAN: kappa is [device] float[n_points] and comp a
+ *   [device] float[n_points] compensation term (kappa + comp is the value).
+ * accumulate != 0 adds to the values already in kappa (and comp), e.g. to
+ * process a line list in chunks; accumulate == 0 overwrites them. */
+int hk_opacity(hk_ctx* ctx, const hk_state* state, const hk_grid* grid,
+               int precision, void* kappa, void* comp, int accumulate);
+
+/* ---- §2.2, §2.6: k-distribution ------------------------------------------ */
+
+/* For each bin of consecutive points: sort the opacities ascending, form the
+ * cumulative coordinate g_i = (i+1)/M of the i-th smallest of the bin's M
+ * values (eq. (14) with eq. (15)'s uniform step 1/N_nu), and resample
+ * k(g_q) = kappa_sorted[ceil(g_q M) - 1] at the requested g values.
+ * kappa: [device] double (HK_F64) or float (HK_F32_KAHAN) [n_points], all
+ * values >= 0 (a NaN sorts last).  k_out: [device] double[n_bins][n_g] with
+ * n_bins = ceil(n_points / points_per_bin).  sorted_out: NULL, or [device]
+ * array of kappa's type [n_points] receiving each bin sorted in place order
+ * (the k-distribution function kappa(y) of §2.1.1). */
+int hk_kdist(hk_ctx* ctx, const void* kappa, int precision, int64_t n_points,
+             const hk_bins* bins, double* k_out, void* sorted_out);
+
+/* ---- helpers -------------------------------------------------------------- */
+
+/* Gauss-Legendre nodes and weights mapped to (0, 1): [host] g[n], w[n],
+ * nodes ascending, weights summing to 1.  n in 1 .. 256. */
+int hk_gauss_legendre(int32_t n, double* g, double* w);
+
+/* Evaluation counts of the last hk_opacity call (synchronises the stream). */
+int hk_stats(hk_ctx* ctx, hk_run_stats* out);
+
+/* Per-stage device time, measured with HIP events recorded on the context's
+ * stream around each kernel while timing is enabled, summed over calls since
+ * the last reset.  Stage indices: */
+#define HK_STAGE_LINE_PREP 0  /* per-line S(T), widths, windows, tile ranges */
+#define HK_STAGE_OPACITY 1    /* Voigt evaluation and accumulation kernel */
+#define HK_STAGE_KDIST 2      /* per-bin sort and k(g) */
+#define HK_N_STAGES 3
+typedef struct {
+    double ms[HK_N_STAGES];     /* summed milliseconds */
+    int64_t calls[HK_N_STAGES]; /* number of timed launches */
+} hk_timing;
+/* enable != 0 starts timing (and resets the sums); 0 stops it. */
+int hk_set_timing(hk_ctx* ctx, int enable);
+/* Synchronises the stream and returns the sums. */
+int hk_get_timing(hk_ctx* ctx, hk_timing* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HK_H */

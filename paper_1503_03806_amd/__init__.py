@@ -1,0 +1,276 @@
+"""Python binding of libhk, the MI355X line-by-line opacity and
+k-distribution library (Grimm & Heng 2015, HELIOS-K, arXiv:1503.03806).
+
+Argument marshalling only: every numerical step runs in the HIP kernels of
+``libhk.so`` behind the C ABI of ``include/hk.h``; the functions below carry
+the same names.  PyTorch supplies device memory and streams.  There is no CPU
+fallback: importing this package fails if ``libhk.so`` has not been built
+(``python -m paper_1503_03806_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+__all__ = ["HK_OK", "HK_EINVAL", "HK_ENOMEM", "HK_EDEVICE", "HK_EUNSUPPORTED", "HK_ENOTREADY",
+           "HK_F64", "HK_F32_KAHAN", "HK_MAX_G", "HKError", "lib", "hk_version", "hk_create",
+           "hk_destroy", "hk_set_stream", "hk_sync", "hk_last_error", "hk_load_lines",
+           "hk_opacity", "hk_kdist", "hk_gauss_legendre", "hk_stats", "hk_set_timing",
+           "hk_get_timing", "Context", "LIB_PATH"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhk.so")
+
+HK_OK, HK_EINVAL, HK_ENOMEM, HK_EDEVICE, HK_EUNSUPPORTED, HK_ENOTREADY = 0, -1, -2, -3, -4, -5
+HK_F64, HK_F32_KAHAN = 0, 1
+HK_MAX_G = 64
+HK_MAX_POINTS = 1 << 30
+
+_pd = C.POINTER(C.c_double)
+
+
+class hk_lines(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(f, _pd) for f in (
+        "nu", "S_ref", "E_lower", "gamma_air", "n_air", "gamma_self", "delta", "A21")]
+
+
+class hk_species(C.Structure):
+    _fields_ = [("T_ref", C.c_double), ("mass_amu", C.c_double)]
+
+
+class hk_state(C.Structure):
+    _fields_ = [("T", C.c_double), ("P", C.c_double), ("P_self", C.c_double),
+                ("q_ratio", C.c_double)]
+
+
+class hk_grid(C.Structure):
+    _fields_ = [("nu_min", C.c_double), ("dnu", C.c_double), ("n_points", C.c_int64),
+                ("cutoff", C.c_double)]
+
+
+class hk_bins(C.Structure):
+    _fields_ = [("points_per_bin", C.c_int64), ("n_g", C.c_int32), ("g", _pd)]
+
+
+class hk_run_stats(C.Structure):
+    _fields_ = [(f, C.c_int64) for f in ("evals", "evals_core", "evals_gh3", "evals_gh1",
+                                         "n_lines")]
+
+
+HK_STAGE_LINE_PREP, HK_STAGE_OPACITY, HK_STAGE_KDIST, HK_N_STAGES = 0, 1, 2, 3
+STAGE_NAMES = ("line_prep", "opacity", "kdist")
+
+
+class hk_timing(C.Structure):
+    _fields_ = [("ms", C.c_double * HK_N_STAGES), ("calls", C.c_int64 * HK_N_STAGES)]
+
+
+class HKError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libhk error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libhk.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libhk.so is not built; run `python -m paper_1503_03806_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int, C.c_int64
+        L.hk_version.argtypes = []; L.hk_version.restype = i32
+        L.hk_create.argtypes = [i32, C.POINTER(vp)]; L.hk_create.restype = i32
+        L.hk_destroy.argtypes = [vp]; L.hk_destroy.restype = i32
+        L.hk_set_stream.argtypes = [vp, vp]; L.hk_set_stream.restype = i32
+        L.hk_sync.argtypes = [vp]; L.hk_sync.restype = i32
+        L.hk_last_error.argtypes = [vp]; L.hk_last_error.restype = C.c_char_p
+        L.hk_load_lines.argtypes = [vp, C.POINTER(hk_lines), C.POINTER(hk_species)]
+        L.hk_load_lines.restype = i32
+        L.hk_opacity.argtypes = [vp, C.POINTER(hk_state), C.POINTER(hk_grid), i32, vp, vp, i32]
+        L.hk_opacity.restype = i32
+        L.hk_kdist.argtypes = [vp, vp, i32, i64, C.POINTER(hk_bins), vp, vp]
+        L.hk_kdist.restype = i32
+        L.hk_gauss_legendre.argtypes = [C.c_int32, _pd, _pd]; L.hk_gauss_legendre.restype = i32
+        L.hk_stats.argtypes = [vp, C.POINTER(hk_run_stats)]; L.hk_stats.restype = i32
+        L.hk_set_timing.argtypes = [vp, i32]; L.hk_set_timing.restype = i32
+        L.hk_get_timing.argtypes = [vp, C.POINTER(hk_timing)]; L.hk_get_timing.restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(rc, ctx=None):
+    if rc != HK_OK:
+        raise HKError(rc, hk_last_error(ctx))
+    return rc
+
+
+def _ptr(t):
+    """Raw pointer of a tensor / numpy array (None -> NULL)."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return t.data_ptr()
+    return t.ctypes.data
+
+
+def hk_version() -> int:
+    return lib().hk_version()
+
+
+def hk_last_error(ctx=None) -> str:
+    s = lib().hk_last_error(ctx)
+    return s.decode() if s else ""
+
+
+def hk_create(device: int = 0):
+    h = C.c_void_p()
+    _check(lib().hk_create(device, C.byref(h)))
+    return h
+
+
+def hk_destroy(ctx):
+    return lib().hk_destroy(ctx)
+
+
+def hk_set_stream(ctx, stream_ptr):
+    _check(lib().hk_set_stream(ctx, stream_ptr), ctx)
+
+
+def hk_sync(ctx):
+    _check(lib().hk_sync(ctx), ctx)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def hk_load_lines(ctx, lines: dict, species: dict):
+    """lines: dict of host arrays (nu, S_ref, E_lower, gamma_air, n_air and
+    optional gamma_self, delta, A21); species: {T_ref, mass_amu}."""
+    keep = {k: _f64(lines.get(k)) for k in ("nu", "S_ref", "E_lower", "gamma_air", "n_air",
+                                            "gamma_self", "delta", "A21")}
+    n = len(keep["nu"])
+    for k, v in keep.items():
+        if v is not None and len(v) != n:
+            raise ValueError("line field %s has %d values, expected %d" % (k, len(v), n))
+    fld = [None if v is None else v.ctypes.data_as(_pd) for v in keep.values()]
+    s = hk_lines(n, *fld)
+    sp = hk_species(float(species.get("T_ref", 296.0)), float(species["mass_amu"]))
+    _check(lib().hk_load_lines(ctx, C.byref(s), C.byref(sp)), ctx)
+
+
+def _state(st: dict) -> hk_state:
+    P = float(st["P"])
+    return hk_state(float(st["T"]), P, float(st.get("P_self", 0.5 * P)),
+                    float(st.get("q_ratio", 1.0)))
+
+
+def _grid(g: dict) -> hk_grid:
+    return hk_grid(float(g["nu_min"]), float(g["dnu"]), int(g["n_points"]), float(g["cutoff"]))
+
+
+def hk_opacity(ctx, state: dict, grid: dict, precision: int, kappa, comp=None,
+               accumulate: bool = False):
+    st, gr = _state(state), _grid(grid)
+    _check(lib().hk_opacity(ctx, C.byref(st), C.byref(gr), int(precision), _ptr(kappa),
+                            _ptr(comp), 1 if accumulate else 0), ctx)
+
+
+def hk_kdist(ctx, kappa, precision: int, n_points: int, points_per_bin: int, g, k_out,
+             sorted_out=None):
+    gg = _f64(g)
+    b = hk_bins(int(points_per_bin), len(gg), gg.ctypes.data_as(_pd))
+    _check(lib().hk_kdist(ctx, _ptr(kappa), int(precision), int(n_points), C.byref(b),
+                          _ptr(k_out), _ptr(sorted_out)), ctx)
+
+
+def hk_gauss_legendre(n: int):
+    g = np.empty(n); w = np.empty(n)
+    _check(lib().hk_gauss_legendre(int(n), g.ctypes.data_as(_pd), w.ctypes.data_as(_pd)))
+    return g, w
+
+
+def hk_stats(ctx) -> dict:
+    s = hk_run_stats()
+    _check(lib().hk_stats(ctx, C.byref(s)), ctx)
+    return {f: int(getattr(s, f)) for f, _ in hk_run_stats._fields_}
+
+
+def hk_set_timing(ctx, enable: bool):
+    _check(lib().hk_set_timing(ctx, 1 if enable else 0), ctx)
+
+
+def hk_get_timing(ctx) -> dict:
+    t = hk_timing()
+    _check(lib().hk_get_timing(ctx, C.byref(t)), ctx)
+    return {name: (float(t.ms[i]), int(t.calls[i])) for i, name in enumerate(STAGE_NAMES)}
+
+
+class Context:
+    """A libhk context bound to a CUDA/HIP device and torch's current stream.
+
+    Allocates outputs as torch tensors; everything else is the C ABI."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self._torch = torch
+        self.device = device
+        self.h = hk_create(device)
+        self.use_current_stream()
+
+    def use_current_stream(self):
+        torch = self._torch
+        with torch.cuda.device(self.device):
+            hk_set_stream(self.h, torch.cuda.current_stream().cuda_stream)
+
+    def close(self):
+        if self.h is not None:
+            hk_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_lines(self, lines: dict, mass_amu: float, T_ref: float = 296.0):
+        hk_load_lines(self.h, lines, {"T_ref": T_ref, "mass_amu": mass_amu})
+
+    def opacity(self, state: dict, grid: dict, precision: int = HK_F64, out=None, comp=None,
+                accumulate: bool = False):
+        torch = self._torch
+        n = int(grid["n_points"])
+        dt = torch.float64 if precision == HK_F64 else torch.float32
+        if out is None:
+            out = torch.empty(max(n, 1), dtype=dt, device="cuda:%d" % self.device)[:n]
+        if precision == HK_F32_KAHAN and comp is None:
+            comp = torch.zeros(max(n, 1), dtype=dt, device="cuda:%d" % self.device)[:n]
+        hk_opacity(self.h, state, grid, precision, out, comp, accumulate)
+        return out if precision == HK_F64 else (out, comp)
+
+    def kdist(self, kappa, points_per_bin: int, g, precision: int = HK_F64, sorted_out=None):
+        torch = self._torch
+        n = kappa.numel()
+        n_bins = -(-n // points_per_bin)
+        k = torch.empty((max(n_bins, 1), len(g)), dtype=torch.float64,
+                        device="cuda:%d" % self.device)[:n_bins]
+        hk_kdist(self.h, kappa, precision, n, points_per_bin, g, k, sorted_out)
+        return k
+
+    def sync(self):
+        hk_sync(self.h)
+
+    def stats(self) -> dict:
+        return hk_stats(self.h)
+
+    def set_timing(self, enable: bool = True):
+        hk_set_timing(self.h, enable)
+
+    def timing(self) -> dict:
+        return hk_get_timing(self.h)

@@ -1,0 +1,527 @@
+// hk_api.cpp -- the C ABI of libhk (include/hk.h): argument checking,
+// context and device memory, and the stream-ordered launch sequence of each
+// call.  Every numerical step runs in the HIP kernels of this directory.
+#include "../../include/hk.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "hk_internal.h"
+
+using namespace hk;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    hipError_t ensure(size_t bytes)
+    {
+        if (bytes <= cap) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        cap = bytes;
+        return hipSuccess;
+    }
+};
+
+struct hk_ctx {
+    int device = 0;
+    hipStream_t own = nullptr;     // created with the context
+    hipStream_t stream = nullptr;  // where work is enqueued (may be the null stream)
+    int64_t lds_bytes = 65536;
+    std::string err;
+    // line list, ascending (nu, index)
+    int64_t n_lines = 0;
+    bool lines_loaded = false;
+    bool has_self = false, has_delta = false, has_A = false;
+    double max_abs_delta = 0.0;
+    hk_species species{296.0, 0.0};
+    DevBuf lines;  // 8 arrays of n doubles
+    // per-state records and tile ranges
+    DevBuf wing, core, ranges;
+    DevBuf partial;
+    DevBuf kscratch;
+    bool have_run = false;
+    // stage timing: events recorded around each timed launch, resolved
+    // lazily (pending pairs) so timing adds no host synchronisation
+    bool timing = false;
+    hk_timing tsum{};
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> free_events;
+};
+
+namespace {
+
+thread_local std::string t_err;
+
+int fail(hk_ctx* ctx, int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    if (ctx) ctx->err = buf;
+    return code;
+}
+
+int hip_fail(hk_ctx* ctx, hipError_t e, const char* what)
+{
+    return fail(ctx, e == hipErrorOutOfMemory ? HK_ENOMEM : HK_EDEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+#define HK_HIP(ctx, call, what)                         \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+    } while (0)
+
+bool isfin(double v) { return std::isfinite(v); }
+
+int check_ctx(hk_ctx* ctx)
+{
+    if (!ctx) return fail(nullptr, HK_EINVAL, "context is NULL");
+    return HK_OK;
+}
+
+int check_state(hk_ctx* ctx, const hk_state* st)
+{
+    if (!st) return fail(ctx, HK_EINVAL, "state is NULL");
+    if (!isfin(st->T) || !(st->T > 0.0)) return fail(ctx, HK_EINVAL, "T must be finite and > 0 (got %g)", st->T);
+    if (!isfin(st->P) || !(st->P >= 0.0)) return fail(ctx, HK_EINVAL, "P must be finite and >= 0 (got %g)", st->P);
+    if (!isfin(st->P_self) || !(st->P_self >= 0.0) || !(st->P_self <= st->P))
+        return fail(ctx, HK_EINVAL, "P_self must satisfy 0 <= P_self <= P (got %g, P = %g)", st->P_self, st->P);
+    if (!isfin(st->q_ratio) || !(st->q_ratio > 0.0))
+        return fail(ctx, HK_EINVAL, "q_ratio must be finite and > 0 (got %g)", st->q_ratio);
+    return HK_OK;
+}
+
+int check_grid(hk_ctx* ctx, const hk_grid* g)
+{
+    if (!g) return fail(ctx, HK_EINVAL, "grid is NULL");
+    if (!isfin(g->nu_min)) return fail(ctx, HK_EINVAL, "nu_min must be finite");
+    if (!isfin(g->dnu) || !(g->dnu > 0.0)) return fail(ctx, HK_EINVAL, "dnu must be finite and > 0 (got %g)", g->dnu);
+    if (g->n_points < 0 || g->n_points > HK_MAX_POINTS)
+        return fail(ctx, HK_EINVAL, "n_points must be in [0, %lld] (got %lld)", (long long)HK_MAX_POINTS,
+                    (long long)g->n_points);
+    if (!isfin(g->cutoff) || !(g->cutoff >= 0.0))
+        return fail(ctx, HK_EINVAL, "cutoff must be finite and >= 0 (got %g)", g->cutoff);
+    double last = g->nu_min + (double)(g->n_points > 0 ? g->n_points - 1 : 0) * g->dnu;
+    if (!isfin(last)) return fail(ctx, HK_EINVAL, "grid end is not finite");
+    return HK_OK;
+}
+
+int check_bins(hk_ctx* ctx, const hk_bins* b, GValues* gv)
+{
+    if (!b) return fail(ctx, HK_EINVAL, "bins is NULL");
+    if (b->points_per_bin < 1) return fail(ctx, HK_EINVAL, "points_per_bin must be >= 1");
+    if (b->n_g < 1 || b->n_g > HK_MAX_G) return fail(ctx, HK_EINVAL, "n_g must be in [1, %d]", HK_MAX_G);
+    if (!b->g) return fail(ctx, HK_EINVAL, "g is NULL");
+    gv->n = b->n_g;
+    for (int q = 0; q < b->n_g; ++q) {
+        if (!isfin(b->g[q]) || !(b->g[q] > 0.0) || !(b->g[q] < 1.0))
+            return fail(ctx, HK_EINVAL, "g[%d] = %g is not in (0, 1)", q, b->g[q]);
+        gv->g[q] = b->g[q];
+    }
+    for (int q = b->n_g; q < 64; ++q) gv->g[q] = 0.5;
+    return HK_OK;
+}
+
+hipEvent_t take_event(hk_ctx* ctx)
+{
+    if (!ctx->free_events.empty()) {
+        hipEvent_t e = ctx->free_events.back();
+        ctx->free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one stage's launches with events when timing is on.
+struct StageTimer {
+    hk_ctx* ctx;
+    int stage;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageTimer(hk_ctx* c, int s) : ctx(c), stage(s)
+    {
+        if (!ctx->timing) return;
+        a = take_event(ctx);
+        b = take_event(ctx);
+        if (a && b) (void)hipEventRecord(a, ctx->stream);
+    }
+    void stop()
+    {
+        if (!a || !b) return;
+        (void)hipEventRecord(b, ctx->stream);
+        ctx->pending.push_back({stage, {a, b}});
+        a = b = nullptr;
+    }
+    ~StageTimer()
+    {
+        if (a) ctx->free_events.push_back(a);
+        if (b) ctx->free_events.push_back(b);
+    }
+};
+
+double* lines_field(hk_ctx* ctx, int k) { return static_cast<double*>(ctx->lines.p) + (size_t)k * ctx->n_lines; }
+
+}  // namespace
+
+extern "C" {
+
+int hk_version(void) { return 100; }
+
+const char* hk_last_error(const hk_ctx* ctx)
+{
+    if (ctx) return ctx->err.c_str();
+    return t_err.c_str();
+}
+
+int hk_create(int device, hk_ctx** out)
+{
+    if (!out) return fail(nullptr, HK_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0)
+        return fail(nullptr, HK_EDEVICE, "no HIP device available (%s)", hipGetErrorString(e));
+    if (device < 0 || device >= n) return fail(nullptr, HK_EINVAL, "device %d out of range [0, %d)", device, n);
+    hk_ctx* ctx = new (std::nothrow) hk_ctx();
+    if (!ctx) return fail(nullptr, HK_ENOMEM, "out of host memory");
+    ctx->device = device;
+    e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        int rc = hip_fail(nullptr, e, "hk_create");
+        delete ctx;
+        return rc;
+    }
+    ctx->stream = ctx->own;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+        ctx->lds_bytes = lds;
+    *out = ctx;
+    return HK_OK;
+}
+
+int hk_destroy(hk_ctx* ctx)
+{
+    if (!ctx) return HK_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->lines.release();
+    ctx->wing.release();
+    ctx->core.release();
+    ctx->ranges.release();
+    ctx->partial.release();
+    ctx->kscratch.release();
+    for (auto& p : ctx->pending) {
+        (void)hipEventDestroy(p.second.first);
+        (void)hipEventDestroy(p.second.second);
+    }
+    for (hipEvent_t e : ctx->free_events) (void)hipEventDestroy(e);
+    if (ctx->own) (void)hipStreamDestroy(ctx->own);
+    delete ctx;
+    return HK_OK;
+}
+
+int hk_set_stream(hk_ctx* ctx, void* hip_stream)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return HK_OK;
+}
+
+int hk_sync(hk_ctx* ctx)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    return HK_OK;
+}
+
+int hk_load_lines(hk_ctx* ctx, const hk_lines* L, const hk_species* sp)
+{
+    if (!L || !sp) return fail(ctx, HK_EINVAL, "lines and species must not be NULL");
+    if (L->n < 0 || L->n > (int64_t)INT32_MAX) return fail(ctx, HK_EINVAL, "line count %lld out of range", (long long)L->n);
+    if (!isfin(sp->T_ref) || !(sp->T_ref > 0.0)) return fail(ctx, HK_EINVAL, "T_ref must be finite and > 0");
+    if (!isfin(sp->mass_amu) || !(sp->mass_amu > 0.0)) return fail(ctx, HK_EINVAL, "mass_amu must be finite and > 0");
+    const int64_t n = L->n;
+    if (n > 0 && (!L->nu || !L->S_ref || !L->E_lower || !L->gamma_air || !L->n_air))
+        return fail(ctx, HK_EINVAL, "nu, S_ref, E_lower, gamma_air and n_air are required");
+    for (int64_t i = 0; i < n; ++i) {
+        if (!isfin(L->nu[i]) || !(L->nu[i] > 0.0)) return fail(ctx, HK_EINVAL, "nu[%lld] = %g must be finite and > 0", (long long)i, L->nu[i]);
+        if (!isfin(L->S_ref[i]) || !(L->S_ref[i] >= 0.0)) return fail(ctx, HK_EINVAL, "S_ref[%lld] = %g must be finite and >= 0", (long long)i, L->S_ref[i]);
+        if (!isfin(L->E_lower[i])) return fail(ctx, HK_EINVAL, "E_lower[%lld] is not finite", (long long)i);
+        if (!isfin(L->gamma_air[i]) || !(L->gamma_air[i] >= 0.0)) return fail(ctx, HK_EINVAL, "gamma_air[%lld] must be finite and >= 0", (long long)i);
+        if (!isfin(L->n_air[i])) return fail(ctx, HK_EINVAL, "n_air[%lld] is not finite", (long long)i);
+        if (L->gamma_self && (!isfin(L->gamma_self[i]) || !(L->gamma_self[i] >= 0.0))) return fail(ctx, HK_EINVAL, "gamma_self[%lld] must be finite and >= 0", (long long)i);
+        if (L->delta && !isfin(L->delta[i])) return fail(ctx, HK_EINVAL, "delta[%lld] is not finite", (long long)i);
+        if (L->A21 && (!isfin(L->A21[i]) || !(L->A21[i] >= 0.0))) return fail(ctx, HK_EINVAL, "A21[%lld] must be finite and >= 0", (long long)i);
+    }
+    if (int rc = check_ctx(ctx)) return rc;
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    // order by ascending (nu, input index): a stable sort of the indices
+    std::vector<int64_t> perm((size_t)n);
+    std::iota(perm.begin(), perm.end(), (int64_t)0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return L->nu[a] < L->nu[b]; });
+    const double* src[8] = {L->nu, L->S_ref, L->E_lower, L->gamma_air, L->n_air,
+                            L->gamma_self ? L->gamma_self : L->gamma_air, L->delta, L->A21};
+    std::vector<double> host((size_t)8 * (size_t)(n > 0 ? n : 1), 0.0);
+    double maxd = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        double* dst = host.data() + (size_t)k * n;
+        if (!src[k]) continue;  // zeros
+        for (int64_t i = 0; i < n; ++i) dst[i] = src[k][perm[(size_t)i]];
+    }
+    if (L->delta)
+        for (int64_t i = 0; i < n; ++i) maxd = std::max(maxd, std::fabs(L->delta[i]));
+    HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    ctx->n_lines = n;
+    ctx->lines_loaded = false;
+    ctx->have_run = false;
+    HK_HIP(ctx, ctx->lines.ensure(host.size() * sizeof(double)), "allocating the line list");
+    if (n > 0)
+        HK_HIP(ctx, hipMemcpy(ctx->lines.p, host.data(), (size_t)8 * n * sizeof(double), hipMemcpyHostToDevice),
+               "copying the line list");
+    ctx->has_self = L->gamma_self != nullptr;
+    ctx->has_delta = L->delta != nullptr;
+    ctx->has_A = L->A21 != nullptr;
+    ctx->max_abs_delta = maxd;
+    ctx->species = *sp;
+    ctx->lines_loaded = true;
+    return HK_OK;
+}
+
+int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precision, void* kappa,
+               void* comp, int accumulate)
+{
+    // arguments first, the context last: the checks run without a device
+    if (int rc = check_state(ctx, st)) return rc;
+    if (int rc = check_grid(ctx, grid)) return rc;
+    if (precision != HK_F64 && precision != HK_F32_KAHAN)
+        return fail(ctx, HK_EINVAL, "unknown precision %d", precision);
+    if (precision == HK_F32_KAHAN)
+        return fail(ctx, HK_EUNSUPPORTED, "HK_F32_KAHAN is not available in this build");
+    if (comp) return fail(ctx, HK_EINVAL, "comp must be NULL for HK_F64");
+    if (grid->n_points > 0 && !kappa) return fail(ctx, HK_EINVAL, "kappa is NULL");
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!ctx->lines_loaded) return fail(ctx, HK_ENOTREADY, "no line list loaded (call hk_load_lines first)");
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    const int64_t n = ctx->n_lines;
+    const int32_t np = (int32_t)grid->n_points;
+
+    PrepParams pp;
+    pp.T = st->T;
+    pp.T_ref = ctx->species.T_ref;
+    pp.P = st->P;
+    pp.P_self = st->P_self;
+    pp.q_ratio = st->q_ratio;
+    pp.dop = std::sqrt(2.0 * kKB * st->T / (ctx->species.mass_amu * kAMU)) / kC;
+    pp.nat = 1.0 / (4.0 * kPi * kC);
+    pp.tscale = st->T / ctx->species.T_ref;
+    pp.nu_min = grid->nu_min;
+    pp.dnu = grid->dnu;
+    pp.cutoff = grid->cutoff;
+    pp.n_points = np;
+
+    const size_t nb = (size_t)std::max<int64_t>(n, 1);
+    HK_HIP(ctx, ctx->wing.ensure(nb * sizeof(WingRec)), "allocating line records");
+    HK_HIP(ctx, ctx->core.ensure(nb * sizeof(CoreRec)), "allocating line records");
+    const int32_t tp = opacity_f64_tile_points();
+    const int64_t n_tiles = ((int64_t)np + tp - 1) / tp;
+    HK_HIP(ctx, ctx->ranges.ensure((size_t)std::max<int64_t>(n_tiles, 1) * 2 * sizeof(int64_t)),
+           "allocating tile ranges");
+
+    LinesDev L;
+    L.nu = lines_field(ctx, 0);
+    L.S_ref = lines_field(ctx, 1);
+    L.E_lower = lines_field(ctx, 2);
+    L.gamma_air = lines_field(ctx, 3);
+    L.n_air = lines_field(ctx, 4);
+    L.gamma_self = lines_field(ctx, 5);
+    L.delta = ctx->has_delta ? lines_field(ctx, 6) : nullptr;
+    L.A21 = ctx->has_A ? lines_field(ctx, 7) : nullptr;
+    L.n = n;
+    WingRec* wing = static_cast<WingRec*>(ctx->wing.p);
+    CoreRec* core = static_cast<CoreRec*>(ctx->core.p);
+    int64_t* ranges = static_cast<int64_t*>(ctx->ranges.p);
+    // a line can reach a tile only if its unshifted centre is within
+    // cutoff + the largest pressure shift (+ two grid steps of slack for the
+    // rounding of the window bounds)
+    const double reach = grid->cutoff + ctx->max_abs_delta * st->P + 2.0 * grid->dnu;
+
+    {
+        StageTimer tm(ctx, HK_STAGE_LINE_PREP);
+        HK_HIP(ctx, launch_line_prep_f64(L, pp, wing, core, ctx->stream), "line_prep_f64");
+        HK_HIP(ctx, launch_tile_ranges(L.nu, n, n_tiles, tp, grid->nu_min, grid->dnu, np, reach, ranges,
+                                       ctx->stream),
+               "tile_ranges");
+        tm.stop();
+    }
+    {
+        StageTimer tm(ctx, HK_STAGE_OPACITY);
+        HK_HIP(ctx, launch_opacity_f64(wing, core, ranges, n_tiles, grid->nu_min, grid->dnu, np,
+                                       static_cast<double*>(kappa), accumulate ? 1 : 0, ctx->stream),
+               "opacity_f64");
+        tm.stop();
+    }
+    ctx->have_run = true;
+    return HK_OK;
+}
+
+int hk_kdist(hk_ctx* ctx, const void* kappa, int precision, int64_t n_points, const hk_bins* bins,
+             double* k_out, void* sorted_out)
+{
+    GValues gv;
+    if (int rc = check_bins(ctx, bins, &gv)) return rc;
+    if (precision != HK_F64 && precision != HK_F32_KAHAN)
+        return fail(ctx, HK_EINVAL, "unknown precision %d", precision);
+    if (n_points < 0 || n_points > HK_MAX_POINTS) return fail(ctx, HK_EINVAL, "n_points out of range");
+    if (n_points > 0 && (!kappa || !k_out)) return fail(ctx, HK_EINVAL, "kappa and k_out must not be NULL");
+    if (int rc = check_ctx(ctx)) return rc;
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    const int eb = precision == HK_F64 ? 8 : 4;
+    const size_t sb = kdist_scratch_bytes(eb, n_points, bins->points_per_bin, ctx->lds_bytes);
+    if (sb) HK_HIP(ctx, ctx->kscratch.ensure(sb), "allocating sort scratch");
+    StageTimer tm(ctx, HK_STAGE_KDIST);
+    HK_HIP(ctx, launch_kdist(kappa, eb, n_points, bins->points_per_bin, gv, k_out, sorted_out,
+                             ctx->kscratch.p, ctx->lds_bytes, ctx->stream),
+           "kdist");
+    tm.stop();
+    return HK_OK;
+}
+
+int hk_stats(hk_ctx* ctx, hk_run_stats* out)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!out) return fail(ctx, HK_EINVAL, "out is NULL");
+    std::memset(out, 0, sizeof *out);
+    out->n_lines = ctx->n_lines;
+    if (!ctx->have_run) return fail(ctx, HK_ENOTREADY, "no hk_opacity call yet");
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    const int32_t nblk = 256;
+    HK_HIP(ctx, ctx->partial.ensure((size_t)nblk * 3 * sizeof(int64_t)), "allocating counters");
+    if (ctx->n_lines > 0) {
+        HK_HIP(ctx, launch_eval_counts(static_cast<WingRec*>(ctx->wing.p), ctx->n_lines,
+                                       static_cast<int64_t*>(ctx->partial.p), nblk, ctx->stream),
+               "eval_counts");
+        std::vector<int64_t> h((size_t)nblk * 3);
+        HK_HIP(ctx, hipMemcpyAsync(h.data(), ctx->partial.p, h.size() * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                   ctx->stream),
+               "copying counters");
+        HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        int64_t e = 0, c = 0, g = 0;
+        for (int b = 0; b < nblk; ++b) {
+            e += h[3 * b];
+            c += h[3 * b + 1];
+            g += h[3 * b + 2];
+        }
+        out->evals = e;
+        out->evals_core = c;
+        out->evals_gh3 = g - c;
+        out->evals_gh1 = e - g;
+    }
+    return HK_OK;
+}
+
+int hk_set_timing(hk_ctx* ctx, int enable)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    for (auto& p : ctx->pending) {
+        ctx->free_events.push_back(p.second.first);
+        ctx->free_events.push_back(p.second.second);
+    }
+    ctx->pending.clear();
+    ctx->tsum = hk_timing{};
+    ctx->timing = enable != 0;
+    return HK_OK;
+}
+
+int hk_get_timing(hk_ctx* ctx, hk_timing* out)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!out) return fail(ctx, HK_EINVAL, "out is NULL");
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    for (auto& p : ctx->pending) {
+        float ms = 0.0f;
+        HK_HIP(ctx, hipEventElapsedTime(&ms, p.second.first, p.second.second), "hipEventElapsedTime");
+        ctx->tsum.ms[p.first] += ms;
+        ctx->tsum.calls[p.first] += 1;
+        ctx->free_events.push_back(p.second.first);
+        ctx->free_events.push_back(p.second.second);
+    }
+    ctx->pending.clear();
+    *out = ctx->tsum;
+    return HK_OK;
+}
+
+// Gauss-Legendre rule on (0, 1).  Each node of P_n on [-1, 1] is refined by
+// Newton's method from the Chebyshev-like start cos(pi (k - 1/4)/(n + 1/2)),
+// with P_n and its derivative from Bonnet's recurrence; weight
+// 2 / ((1 - x^2) P_n'(x)^2).  Mapped to (0, 1): g = (1 + x)/2, w/2.
+int hk_gauss_legendre(int32_t n, double* g, double* w)
+{
+    if (n < 1 || n > 256) return fail(nullptr, HK_EINVAL, "n must be in [1, 256]");
+    if (!g || !w) return fail(nullptr, HK_EINVAL, "g and w must not be NULL");
+    for (int k = 1; k <= n; ++k) {
+        double x = std::cos(kPi * (k - 0.25) / (n + 0.5));
+        double pn = 0.0, dpn = 1.0;
+        for (int it = 0; it < 50; ++it) {
+            double pkm1 = 1.0, pk = x;  // P_0, P_1
+            for (int m = 2; m <= n; ++m) {
+                double pkp1 = ((2 * m - 1) * x * pk - (m - 1) * pkm1) / m;
+                pkm1 = pk;
+                pk = pkp1;
+            }
+            pn = n == 1 ? x : pk;
+            double pnm1 = n == 1 ? 1.0 : pkm1;
+            dpn = n * (pnm1 - x * pn) / (1.0 - x * x);
+            double dx = pn / dpn;
+            x -= dx;
+            if (std::fabs(dx) <= 1e-16 * std::max(1.0, std::fabs(x))) break;
+        }
+        {
+            double pkm1 = 1.0, pk = x;
+            for (int m = 2; m <= n; ++m) {
+                double pkp1 = ((2 * m - 1) * x * pk - (m - 1) * pkm1) / m;
+                pkm1 = pk;
+                pk = pkp1;
+            }
+            pn = n == 1 ? x : pk;
+            double pnm1 = n == 1 ? 1.0 : pkm1;
+            dpn = n * (pnm1 - x * pn) / (1.0 - x * x);
+        }
+        // x is the k-th largest root: store ascending
+        g[n - k] = 0.5 * (1.0 + x);
+        w[n - k] = 1.0 / ((1.0 - x * x) * dpn * dpn);
+    }
+    return HK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// hk_internal.h -- records, constants and launch declarations shared by the
+// HIP kernels and the C-ABI host code of libhk.  Not installed; the public
+// interface is include/hk.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hk {
+
+// Physical constants in CGS (SI 2019 exact values for c, k_B, h; CODATA 2018
+// atomic mass unit).
+constexpr double kC = 2.99792458e10;        // cm s^-1
+constexpr double kKB = 1.380649e-16;        // erg K^-1
+constexpr double kH = 6.62607015e-27;       // erg s
+constexpr double kAMU = 1.66053906660e-24;  // g
+constexpr double kC2 = kH * kC / kKB;       // second radiation constant, cm K
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kInvPi = 0.31830988618379067154;
+constexpr double kInvSqrtPi = 0.56418958354775628695;
+
+// Region radii of the Voigt scheme on a^2 + u^2 (§2.4).
+constexpr double kCoreR2 = 100.0;
+constexpr double kGH1R2 = 1.0e6;
+
+// Per-line record of the binary64 wing evaluation, one per line and state,
+// in line order.  With alpha = Gamma_D / sqrt(ln 2) the Doppler 1/e width,
+// Gamma = Gamma_L and dv = nu_j - nu0:
+//   1-node:  S Phi = Lg / (dv^2 + G2)
+//   3-node:  S Phi = (Lg/3) (2 P + E D0) / (D0 P),
+//            D0 = dv^2 + G2, E = D0 + h, P = E^2 - c6 dv^2,
+// which is the 3-node Gauss-Hermite sum (weights 2/3, 1/6, 1/6 of the
+// Lorentzians at nu0 and nu0 -+ sqrt(3/2) alpha) over one common
+// denominator.  The integer fields are grid-index intervals (closed; empty
+// when lo > hi): the cutoff window and the points whose a^2+u^2 lies below
+// 1e6 and below 100.
+struct alignas(16) WingRec {
+    double nu0;  // pressure-shifted line centre
+    double Lg;   // S(T) Gamma_L / pi
+    double G2;   // Gamma_L^2
+    double h;    // 1.5 alpha^2
+    double c6;   // 6 alpha^2
+    int32_t wlo, whi;
+    int32_t g3lo, g3hi;
+    int32_t clo, chi;
+};
+static_assert(sizeof(WingRec) == 64, "WingRec layout");
+
+// Per-line record of the core-region series, read only for lines whose
+// a^2+u^2 < 100 interval meets a wavefront's points.
+struct alignas(16) CoreRec {
+    double invA;  // 1 / alpha
+    double y;     // Gamma_L / alpha  (the paper's damping parameter a)
+    double y2;    // y * y
+    double ex;    // erfcx(y)
+    double norm;  // S(T) / (alpha sqrt(pi))
+    double T1;    // sum_{n>=1} e^{-n^2/4} / (n^2/4 + y^2)
+    double pad0, pad1;
+};
+static_assert(sizeof(CoreRec) == 64, "CoreRec layout");
+
+// Sorted line list on the device (structure of arrays, ascending nu).
+struct LinesDev {
+    const double* nu;
+    const double* S_ref;
+    const double* E_lower;
+    const double* gamma_air;
+    const double* n_air;
+    const double* gamma_self;
+    const double* delta;
+    const double* A21;
+    int64_t n;
+};
+
+// State-dependent constants of the line preparation, computed on the host.
+struct PrepParams {
+    double T, T_ref, P, P_self, q_ratio;
+    double dop;       // alpha / nu = sqrt(2 k_B T / m) / c
+    double nat;       // 1 / (4 pi c): natural width per unit A21
+    double tscale;    // T / T_ref
+    double nu_min, dnu, cutoff;
+    int32_t n_points;
+};
+
+struct GValues {
+    double g[64];
+    int32_t n;
+};
+
+// ---- launches (stream-ordered, no synchronisation) ----
+hipError_t launch_line_prep_f64(const LinesDev& L, const PrepParams& pp, WingRec* wing,
+                                CoreRec* core, hipStream_t s);
+hipError_t launch_tile_ranges(const double* nu_sorted, int64_t n_lines, int64_t n_tiles,
+                              int32_t tile_points, double nu_min, double dnu, int32_t n_points,
+                              double reach, int64_t* ranges, hipStream_t s);
+int32_t opacity_f64_tile_points();
+hipError_t launch_opacity_f64(const WingRec* wing, const CoreRec* core, const int64_t* ranges,
+                              int64_t n_tiles, double nu_min, double dnu, int32_t n_points,
+                              double* kappa, int accumulate, hipStream_t s);
+hipError_t launch_eval_counts(const WingRec* wing, int64_t n_lines, int64_t* partial,
+                              int32_t n_blocks, hipStream_t s);
+
+// k-distribution.  elem_bytes 8 (binary64 keys) or 4 (binary32 keys).
+int64_t kdist_lds_max_points(int elem_bytes, int64_t lds_bytes);
+hipError_t launch_kdist(const void* kappa, int elem_bytes, int64_t n_points, int64_t ppb,
+                        const GValues& g, double* k_out, void* sorted_out, void* scratch,
+                        int64_t lds_bytes, hipStream_t s);
+size_t kdist_scratch_bytes(int elem_bytes, int64_t n_points, int64_t ppb, int64_t lds_bytes);
+
+}  // namespace hk

@@ -1,0 +1,240 @@
+// kdist.hip -- the "Sort" stage (§2.2, §2.6): per-bin sort of the opacity
+// grid, cumulative coordinate g_i = (i+1)/M, and k(g) at the requested g.
+//
+// The paper sorts the whole grid at once with bin tags (Thrust, §2.6).  Here
+// bins are independent: a bin that fits in LDS is sorted there by one
+// workgroup (bitonic network on the keys' bit patterns: non-negative IEEE
+// values order like their unsigned integer images); larger bins are cut
+// into LDS-sized chunks, each sorted in LDS, then merged pairwise in global
+// memory (each element finds its rank in the partner run by binary search;
+// ties keep left-before-right, so the merge is stable).
+#include "hk_internal.h"
+
+namespace hk {
+namespace {
+
+constexpr int kSortThreads = 1024;
+
+template <typename K>
+struct KeyMax;
+template <>
+struct KeyMax<uint64_t> {
+    static constexpr uint64_t v = ~0ull;
+};
+template <>
+struct KeyMax<uint32_t> {
+    static constexpr uint32_t v = ~0u;
+};
+
+template <typename K>
+__device__ inline double key_value(K k);
+template <>
+__device__ inline double key_value<uint64_t>(uint64_t k)
+{
+    return __longlong_as_double((long long)k);
+}
+template <>
+__device__ inline double key_value<uint32_t>(uint32_t k)
+{
+    return (double)__uint_as_float(k);
+}
+
+// Sort s[0 .. npad) ascending in LDS; npad is a power of two, all threads of
+// the block take part.
+template <typename K>
+__device__ void bitonic_lds(K* s, int npad)
+{
+    for (int k = 2; k <= npad; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < npad; i += blockDim.x) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const K a = s[i], b = s[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) {
+                        s[i] = b;
+                        s[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Rank of the q-th requested g in a bin of m sorted values.
+__device__ inline int64_t g_rank(double g, int64_t m)
+{
+    int64_t r = (int64_t)ceil(g * (double)m) - 1;
+    return r < 0 ? 0 : (r > m - 1 ? m - 1 : r);
+}
+
+// One workgroup per bin (bins <= chunk), or per chunk of a larger bin when
+// `chunk < ppb`: sort in LDS; if `final`, also emit k(g) for the bin.
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void sort_chunk_lds_kernel(
+    const K* __restrict__ src, int64_t n_points, int64_t ppb, int64_t chunk, int npad,
+    int64_t chunks_per_bin, K* __restrict__ dst, GValues g, double* __restrict__ k_out, int final)
+{
+    extern __shared__ unsigned char lds_raw[];
+    K* s = reinterpret_cast<K*>(lds_raw);
+    const int64_t bin = blockIdx.x / chunks_per_bin;
+    const int64_t c = blockIdx.x - bin * chunks_per_bin;
+    const int64_t b0 = bin * ppb;
+    const int64_t m_bin = min(ppb, n_points - b0);
+    const int64_t j0 = b0 + c * chunk;
+    const int64_t m = min(chunk, b0 + m_bin - j0);
+    for (int i = threadIdx.x; i < npad; i += blockDim.x) s[i] = i < m ? src[j0 + i] : KeyMax<K>::v;
+    __syncthreads();
+    bitonic_lds(s, npad);
+    if (dst) {
+        for (int i = threadIdx.x; i < m; i += blockDim.x) dst[j0 + i] = s[i];
+    }
+    if (final && (int)threadIdx.x < g.n) {
+        k_out[bin * g.n + threadIdx.x] = key_value<K>(s[g_rank(g.g[threadIdx.x], m)]);
+    }
+}
+
+// One pass of pairwise merging of sorted runs of length `run` inside each
+// bin.  One thread per element.
+template <typename K>
+__global__ __launch_bounds__(256) void merge_pass_kernel(const K* __restrict__ src,
+                                                         K* __restrict__ dst, int64_t n_points,
+                                                         int64_t ppb, int64_t run)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_points) return;
+    const int64_t bin = e / ppb;
+    const int64_t b0 = bin * ppb;
+    const int64_t m = min(ppb, n_points - b0);
+    const int64_t i = e - b0;
+    const int64_t r = i / run;
+    const int64_t pair0 = (r & ~(int64_t)1) * run;
+    const int64_t own0 = r * run;
+    const K key = src[e];
+    int64_t p0, p1;
+    if ((r & 1) == 0) {
+        p0 = own0 + run;
+        p1 = min(own0 + 2 * run, m);
+    } else {
+        p0 = own0 - run;
+        p1 = own0;
+    }
+    int64_t lo = p0, hi = p1 > p0 ? p1 : p0;
+    if ((r & 1) == 0) {  // left run: count partner keys < key
+        while (lo < hi) {
+            int64_t mid = lo + ((hi - lo) >> 1);
+            if (src[b0 + mid] < key) lo = mid + 1;
+            else hi = mid;
+        }
+    } else {  // right run: count partner keys <= key
+        while (lo < hi) {
+            int64_t mid = lo + ((hi - lo) >> 1);
+            if (src[b0 + mid] <= key) lo = mid + 1;
+            else hi = mid;
+        }
+    }
+    const int64_t partner_rank = lo - p0;
+    dst[b0 + pair0 + (i - own0) + partner_rank] = key;
+}
+
+template <typename K>
+__global__ __launch_bounds__(64) void kdist_pick_kernel(const K* __restrict__ sorted,
+                                                        int64_t n_points, int64_t ppb, GValues g,
+                                                        double* __restrict__ k_out)
+{
+    const int64_t bin = blockIdx.x;
+    const int64_t b0 = bin * ppb;
+    const int64_t m = min(ppb, n_points - b0);
+    if ((int)threadIdx.x < g.n)
+        k_out[bin * g.n + threadIdx.x] = key_value<K>(sorted[b0 + g_rank(g.g[threadIdx.x], m)]);
+}
+
+int pow2_at_least(int64_t m)
+{
+    int p = 1;
+    while (p < m) p <<= 1;
+    return p;
+}
+
+template <typename K>
+hipError_t run_kdist(const K* kappa, int64_t n_points, int64_t ppb, const GValues& g,
+                     double* k_out, K* sorted_out, K* scratch, int64_t lds_bytes, hipStream_t s)
+{
+    const int64_t n_bins = (n_points + ppb - 1) / ppb;
+    const int64_t cap = kdist_lds_max_points(sizeof(K), lds_bytes);
+    if (ppb <= cap) {
+        const int npad = pow2_at_least(ppb);
+        const size_t shm = (size_t)npad * sizeof(K);
+        hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(&sort_chunk_lds_kernel<K>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+        sort_chunk_lds_kernel<K><<<dim3((unsigned)n_bins), dim3(kSortThreads), shm, s>>>(
+            kappa, n_points, ppb, ppb, npad, 1, sorted_out, g, k_out, 1);
+        return hipGetLastError();
+    }
+    // chunked: sort chunks of `cap` points, then merge runs until one run
+    // covers the bin.  Ping-pong between scratch halves; the last pass
+    // lands in sorted_out when given.
+    const int64_t chunk = cap;
+    const int64_t cpb = (ppb + chunk - 1) / chunk;
+    const int npad = pow2_at_least(chunk);
+    const size_t shm = (size_t)npad * sizeof(K);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sort_chunk_lds_kernel<K>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    K* bufA = scratch;
+    K* bufB = scratch + n_points;
+    sort_chunk_lds_kernel<K><<<dim3((unsigned)(n_bins * cpb)), dim3(kSortThreads), shm, s>>>(
+        kappa, n_points, ppb, chunk, npad, cpb, bufA, g, k_out, 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    K* cur = bufA;
+    K* nxt = bufB;
+    int passes = 0;
+    for (int64_t run = chunk; run < ppb; run *= 2) ++passes;
+    int done = 0;
+    for (int64_t run = chunk; run < ppb; run *= 2) {
+        ++done;
+        K* out = (done == passes && sorted_out) ? sorted_out : nxt;
+        const int64_t blocks = (n_points + 255) / 256;
+        merge_pass_kernel<K><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(cur, out, n_points, ppb, run);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        nxt = cur;
+        cur = out;
+    }
+    kdist_pick_kernel<K><<<dim3((unsigned)n_bins), dim3(64), 0, s>>>(cur, n_points, ppb, g, k_out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t kdist_lds_max_points(int elem_bytes, int64_t lds_bytes)
+{
+    // largest power of two whose keys fit in the workgroup's LDS
+    int64_t p = 1;
+    while (p * 2 * elem_bytes <= lds_bytes && p * 2 <= (1 << 16)) p *= 2;
+    return p;
+}
+
+size_t kdist_scratch_bytes(int elem_bytes, int64_t n_points, int64_t ppb, int64_t lds_bytes)
+{
+    if (ppb <= kdist_lds_max_points(elem_bytes, lds_bytes)) return 0;
+    return (size_t)2 * (size_t)n_points * (size_t)elem_bytes;
+}
+
+hipError_t launch_kdist(const void* kappa, int elem_bytes, int64_t n_points, int64_t ppb,
+                        const GValues& g, double* k_out, void* sorted_out, void* scratch,
+                        int64_t lds_bytes, hipStream_t s)
+{
+    if (n_points == 0) return hipSuccess;
+    if (elem_bytes == 8)
+        return run_kdist<uint64_t>(static_cast<const uint64_t*>(kappa), n_points, ppb, g, k_out,
+                                   static_cast<uint64_t*>(sorted_out),
+                                   static_cast<uint64_t*>(scratch), lds_bytes, s);
+    return run_kdist<uint32_t>(static_cast<const uint32_t*>(kappa), n_points, ppb, g, k_out,
+                               static_cast<uint32_t*>(sorted_out), static_cast<uint32_t*>(scratch),
+                               lds_bytes, s);
+}
+
+}  // namespace hk

@@ -1,0 +1,227 @@
+// line_prep.hip -- the per-line stage ("Line" in the paper's Fig. 5):
+// temperature/pressure scaling of every line (§2.3) into the records the
+// opacity kernels read, the line range of each grid tile, and the
+// evaluation counts by region.
+#include "hk_internal.h"
+
+#include <climits>
+
+namespace hk {
+namespace {
+
+// a^2 + u^2 at grid point j for a line (u = (nu_j - nu0) / alpha, a = y).
+__device__ inline double r2_at(int64_t j, double nu_min, double dnu, double nu0, double invA,
+                               double y2)
+{
+    double nuj = fma((double)j, dnu, nu_min);
+    double x = fabs(nuj - nu0) * invA;
+    return fma(x, x, y2);
+}
+
+// Closed interval [lo, hi] of grid indices with a^2+u^2 < R, clipped to the
+// sentinels -1 and n (so "j < lo" / "j > hi" tests stay exact for every grid
+// point).  a^2+u^2 computed as in r2_at is monotone in |nu_j - nu0| (every
+// rounding step is monotone), so the set is an interval; the analytic
+// half-width gives a start within a point or two, and the bounded searches
+// settle the exact edges.  Empty: lo = INT_MAX, hi = INT_MIN.
+__device__ void region_interval(double R, double nu_min, double dnu, int32_t n, double nu0,
+                                double invA, double y2, int32_t* lo_out, int32_t* hi_out)
+{
+    if (!(y2 < R)) {
+        *lo_out = INT_MAX;
+        *hi_out = INT_MIN;
+        return;
+    }
+    double half = sqrt(R - y2) / invA;  // cm^-1
+    double c = (nu0 - nu_min) / dnu;
+    double fhi = floor(c + half / dnu), flo = ceil(c - half / dnu);
+    fhi = fmin(fmax(fhi, -1.0), (double)n);
+    flo = fmin(fmax(flo, -1.0), (double)n);
+    int64_t hi = (int64_t)fhi, lo = (int64_t)flo;
+    for (int it = 0; it < 64 && hi < n && r2_at(hi + 1, nu_min, dnu, nu0, invA, y2) < R; ++it) ++hi;
+    for (int it = 0; it < 64 && hi >= 0 && r2_at(hi, nu_min, dnu, nu0, invA, y2) >= R; ++it) --hi;
+    for (int it = 0; it < 64 && lo > -1 && r2_at(lo - 1, nu_min, dnu, nu0, invA, y2) < R; ++it) --lo;
+    for (int it = 0; it < 64 && lo < n && r2_at(lo, nu_min, dnu, nu0, invA, y2) >= R; ++it) ++lo;
+    if (lo > hi) {
+        *lo_out = INT_MAX;
+        *hi_out = INT_MIN;
+        return;
+    }
+    *lo_out = (int32_t)lo;
+    *hi_out = (int32_t)hi;
+}
+
+__global__ __launch_bounds__(256) void line_prep_f64_kernel(LinesDev L, PrepParams pp,
+                                                            WingRec* __restrict__ wing,
+                                                            CoreRec* __restrict__ core)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.n) return;
+    const double nu = L.nu[i];
+    const double E = L.E_lower[i];
+    const double g_air = L.gamma_air[i];
+    const double g_self = L.gamma_self ? L.gamma_self[i] : g_air;
+    const double delta = L.delta ? L.delta[i] : 0.0;
+    const double A21 = L.A21 ? L.A21[i] : 0.0;
+
+    // eq. (18), with E'' for Delta E and 1 - exp(-z) = -expm1(-z)
+    const double boltz = exp(-kC2 * E / pp.T + kC2 * E / pp.T_ref);
+    const double stim = expm1(-kC2 * nu / pp.T) / expm1(-kC2 * nu / pp.T_ref);
+    const double S = L.S_ref[i] * pp.q_ratio * boltz * stim;
+    // eq. (19): alpha = Gamma_D / sqrt(ln 2) = nu sqrt(2 k_B T / m) / c
+    const double alpha = nu * pp.dop;
+    // eq. (20), P0 = 1 atm
+    const double GL = A21 * pp.nat +
+                      pow(pp.tscale, -L.n_air[i]) * (g_air * (pp.P - pp.P_self) + g_self * pp.P_self);
+    // eq. (21); kept free of contraction so the window bounds below are the
+    // exact binary64 expressions of the definition
+    const double nu0 = __dadd_rn(nu, __dmul_rn(delta, pp.P));
+
+    WingRec w;
+    w.nu0 = nu0;
+    w.Lg = S * GL * kInvPi;
+    w.G2 = GL * GL;
+    w.h = 1.5 * alpha * alpha;
+    w.c6 = 6.0 * alpha * alpha;
+    const int32_t n = pp.n_points;
+    {
+        double flo = ceil((nu0 - pp.cutoff - pp.nu_min) / pp.dnu);
+        double fhi = floor((nu0 + pp.cutoff - pp.nu_min) / pp.dnu);
+        flo = fmax(flo, 0.0);
+        fhi = fmin(fhi, (double)(n - 1));
+        if (!(flo <= fhi)) {
+            w.wlo = 1;
+            w.whi = 0;
+        } else {
+            w.wlo = (int32_t)flo;
+            w.whi = (int32_t)fhi;
+        }
+    }
+    const double invA = 1.0 / alpha;
+    const double y = GL * invA;
+    const double y2 = y * y;
+    region_interval(kGH1R2, pp.nu_min, pp.dnu, n, nu0, invA, y2, &w.g3lo, &w.g3hi);
+    region_interval(kCoreR2, pp.nu_min, pp.dnu, n, nu0, invA, y2, &w.clo, &w.chi);
+    wing[i] = w;
+
+    CoreRec c;
+    c.invA = invA;
+    c.y = y;
+    c.y2 = y2;
+    c.norm = S * invA * kInvSqrtPi;
+    if (w.clo <= w.chi) {
+        c.ex = erfcx(y);
+        double t1 = 0.0;
+        for (int k = 1; k <= 40; ++k) {
+            double hk2 = 0.25 * (double)(k * k);
+            t1 += exp(-hk2) / (hk2 + y2);
+        }
+        c.T1 = t1;
+    } else {
+        c.ex = 0.0;
+        c.T1 = 0.0;
+    }
+    c.pad0 = 0.0;
+    c.pad1 = 0.0;
+    core[i] = c;
+}
+
+// Line index range [first, last) of every grid tile: the lines whose
+// unshifted centre lies within `reach` of the tile's points.  Each line in
+// the range is still tested against its exact window by the opacity kernel.
+__global__ __launch_bounds__(256) void tile_ranges_kernel(const double* __restrict__ nu, int64_t n,
+                                                          int64_t n_tiles, int32_t tile_points,
+                                                          double nu_min, double dnu,
+                                                          int32_t n_points, double reach,
+                                                          int64_t* __restrict__ ranges)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    int64_t j0 = t * tile_points;
+    int64_t j1 = j0 + tile_points;
+    if (j1 > n_points) j1 = n_points;
+    double lo_nu = fma((double)j0, dnu, nu_min) - reach;
+    double hi_nu = fma((double)(j1 - 1), dnu, nu_min) + reach;
+    int64_t a = 0, b = n;  // first nu >= lo_nu
+    while (a < b) {
+        int64_t m = a + ((b - a) >> 1);
+        if (nu[m] < lo_nu) a = m + 1;
+        else b = m;
+    }
+    int64_t first = a;
+    b = n;  // first nu > hi_nu
+    while (a < b) {
+        int64_t m = a + ((b - a) >> 1);
+        if (nu[m] <= hi_nu) a = m + 1;
+        else b = m;
+    }
+    ranges[2 * t] = first;
+    ranges[2 * t + 1] = a;
+}
+
+__device__ inline int64_t overlap(int64_t alo, int64_t ahi, int64_t blo, int64_t bhi)
+{
+    int64_t lo = alo > blo ? alo : blo;
+    int64_t hi = ahi < bhi ? ahi : bhi;
+    return hi >= lo ? hi - lo + 1 : 0;
+}
+
+// Per-block partial sums of (evals, core, below 1e6) over lines.
+__global__ __launch_bounds__(256) void eval_counts_kernel(const WingRec* __restrict__ wing,
+                                                          int64_t n, int64_t* __restrict__ partial)
+{
+    __shared__ int64_t red[3][256];
+    int64_t e = 0, c = 0, g = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        WingRec w = wing[i];
+        if (w.wlo > w.whi) continue;
+        e += w.whi - w.wlo + 1;
+        c += overlap(w.wlo, w.whi, w.clo, w.chi);
+        g += overlap(w.wlo, w.whi, w.g3lo, w.g3hi);
+    }
+    red[0][threadIdx.x] = e;
+    red[1][threadIdx.x] = c;
+    red[2][threadIdx.x] = g;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 3; ++k) partial[3 * blockIdx.x + k] = red[k][0];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_line_prep_f64(const LinesDev& L, const PrepParams& pp, WingRec* wing,
+                                CoreRec* core, hipStream_t s)
+{
+    if (L.n == 0) return hipSuccess;
+    int64_t blocks = (L.n + 255) / 256;
+    line_prep_f64_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(L, pp, wing, core);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_ranges(const double* nu_sorted, int64_t n_lines, int64_t n_tiles,
+                              int32_t tile_points, double nu_min, double dnu, int32_t n_points,
+                              double reach, int64_t* ranges, hipStream_t s)
+{
+    if (n_tiles == 0) return hipSuccess;
+    int64_t blocks = (n_tiles + 255) / 256;
+    tile_ranges_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(
+        nu_sorted, n_lines, n_tiles, tile_points, nu_min, dnu, n_points, reach, ranges);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_counts(const WingRec* wing, int64_t n_lines, int64_t* partial,
+                              int32_t n_blocks, hipStream_t s)
+{
+    eval_counts_kernel<<<dim3(n_blocks), dim3(256), 0, s>>>(wing, n_lines, partial);
+    return hipGetLastError();
+}
+
+}  // namespace hk

@@ -1,0 +1,138 @@
+"""Host-side checks of the C ABI: the library loads and exports every symbol
+include/hk.h declares, argument validation rejects bad input before any
+device work, and the host helpers match their definitions.  No GPU needed."""
+import ctypes as C
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1503_03806_amd as hk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hk.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hk_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert "hk_opacity" in names and "hk_kdist" in names and len(names) >= 11
+    L = C.CDLL(hk.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", hk.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (hk_[a-z0-9_]+)\b", out))
+    assert set(names) <= exported
+
+
+def test_header_compiles_as_c():
+    src = '#include "hk.h"\nint main(void){hk_ctx* c = 0; return hk_sync(c) == HK_EINVAL ? 0 : 1;}\n'
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-I",
+                        os.path.dirname(HEADER), "-x", "c", "-"], input=src, text=True,
+                       capture_output=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_version_and_last_error():
+    assert hk.hk_version() >= 100
+    assert isinstance(hk.hk_last_error(None), str)
+
+
+GOOD_STATE = {"T": 1500.0, "P": 1.0, "P_self": 0.5, "q_ratio": 0.1}
+GOOD_GRID = {"nu_min": 0.0, "dnu": 0.01, "n_points": 1000, "cutoff": 25.0}
+
+
+def _opacity_rc(state, grid, precision=hk.HK_F64, kappa=1, comp=None):
+    st, gr = hk._state(state), hk._grid(grid)
+    return hk.lib().hk_opacity(None, C.byref(st), C.byref(gr), precision, kappa, comp, 0)
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("T", 0.0, "T must"), ("T", float("nan"), "T must"), ("P", -1.0, "P must"),
+    ("P_self", 2.0, "P_self"), ("q_ratio", 0.0, "q_ratio")])
+def test_opacity_rejects_bad_state(field, value, msg):
+    st = dict(GOOD_STATE); st[field] = value
+    assert _opacity_rc(st, GOOD_GRID) == hk.HK_EINVAL
+    assert msg in hk.hk_last_error(None)
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("dnu", 0.0, "dnu"), ("dnu", -0.01, "dnu"), ("n_points", -1, "n_points"),
+    ("n_points", (1 << 30) + 1, "n_points"), ("cutoff", -1.0, "cutoff"),
+    ("nu_min", float("inf"), "nu_min")])
+def test_opacity_rejects_bad_grid(field, value, msg):
+    g = dict(GOOD_GRID); g[field] = value
+    assert _opacity_rc(GOOD_STATE, g) == hk.HK_EINVAL
+    assert msg in hk.hk_last_error(None)
+
+
+def test_opacity_rejects_bad_precision_and_buffers():
+    assert _opacity_rc(GOOD_STATE, GOOD_GRID, precision=7) == hk.HK_EINVAL
+    assert _opacity_rc(GOOD_STATE, GOOD_GRID, kappa=None) == hk.HK_EINVAL
+    assert "kappa" in hk.hk_last_error(None)
+    # valid arguments reach the context check
+    assert _opacity_rc(GOOD_STATE, GOOD_GRID) == hk.HK_EINVAL
+    assert "context" in hk.hk_last_error(None)
+
+
+def test_kdist_rejects_bad_bins():
+    g = np.array([0.1, 0.5])
+
+    def rc(ppb, gv, n_points=100):
+        gg = np.ascontiguousarray(gv, dtype=np.float64)
+        b = hk.hk_bins(ppb, len(gg), gg.ctypes.data_as(C.POINTER(C.c_double)))
+        return hk.lib().hk_kdist(None, 1, hk.HK_F64, n_points, C.byref(b), 1, None)
+    assert rc(0, g) == hk.HK_EINVAL and "points_per_bin" in hk.hk_last_error(None)
+    assert rc(10, [0.0, 0.5]) == hk.HK_EINVAL and "(0, 1)" in hk.hk_last_error(None)
+    assert rc(10, [0.5, 1.0]) == hk.HK_EINVAL
+    assert rc(10, np.full(65, 0.5)) == hk.HK_EINVAL and "n_g" in hk.hk_last_error(None)
+    assert rc(10, g, n_points=-1) == hk.HK_EINVAL
+    assert rc(10, g) == hk.HK_EINVAL and "context" in hk.hk_last_error(None)
+
+
+def test_load_lines_rejects_bad_lists():
+    base = {"nu": np.array([100.0, 200.0]), "S_ref": np.array([1e-20, 1e-21]),
+            "E_lower": np.array([10.0, 20.0]), "gamma_air": np.array([0.05, 0.06]),
+            "n_air": np.array([0.5, 0.6])}
+    for k, v, msg in [("nu", [0.0, 1.0], "nu[0]"), ("nu", [1.0, float("nan")], "nu[1]"),
+                      ("S_ref", [-1.0, 1.0], "S_ref"), ("gamma_air", [0.1, -0.1], "gamma_air"),
+                      ("E_lower", [np.inf, 1.0], "E_lower")]:
+        L = dict(base); L[k] = np.array(v)
+        with pytest.raises(hk.HKError) as e:
+            hk.hk_load_lines(None, L, {"mass_amu": 18.0})
+        assert e.value.code == hk.HK_EINVAL and msg in str(e.value)
+    with pytest.raises(hk.HKError) as e:
+        hk.hk_load_lines(None, base, {"mass_amu": 0.0})
+    assert "mass_amu" in str(e.value)
+    with pytest.raises(hk.HKError) as e:
+        hk.hk_load_lines(None, base, {"mass_amu": 18.0})
+    assert "context" in str(e.value)
+
+
+def test_null_context_calls():
+    for f in ("hk_sync", "hk_set_stream"):
+        fn = getattr(hk.lib(), f)
+        rc = fn(None) if f == "hk_sync" else fn(None, None)
+        assert rc == hk.HK_EINVAL
+    assert hk.lib().hk_destroy(None) == hk.HK_OK
+    s = hk.hk_run_stats()
+    assert hk.lib().hk_stats(None, C.byref(s)) == hk.HK_EINVAL
+
+
+def test_gauss_legendre_helper_matches_numpy():
+    for n in (1, 2, 3, 7, 20, 64):
+        g, w = hk.hk_gauss_legendre(n)
+        x, wr = np.polynomial.legendre.leggauss(n)
+        assert np.max(np.abs(g - 0.5 * (1 + x))) < 2e-15
+        assert np.max(np.abs(w - 0.5 * wr)) < 2e-15
+    with pytest.raises(hk.HKError):
+        hk.hk_gauss_legendre(0)

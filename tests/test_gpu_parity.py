@@ -1,0 +1,246 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerance: 1e-6 relative per grid point and per k(g) entry for the binary64
+path.  Every opacity here is a sum of positive terms, so a per-term relative
+difference bounds the per-point one; the kernel and the oracle differ only in
+rounding (reciprocal-multiply vs division, recurrences vs exp() per series
+term, fma), in summation association, and in which region a point whose
+a^2+u^2 lies within rounding of 100 or 1e6 falls into (the scheme's own error
+there is <= 5.7e-6 of one term, and such ties are ~1e-13 rare).
+Integer outputs (evaluation counts, k(g) of identical inputs) are compared
+exactly.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+hk = pytest.importorskip("paper_1503_03806_amd")
+
+TOL = 1e-6
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = hk.Context(0)
+    yield c
+    c.close()
+
+
+def state_of(cond):
+    return {"T": cond["T"], "P": cond["P"], "P_self": cond["P_self"], "q_ratio": cond["q_ratio"]}
+
+
+def gpu_opacity(ctx, lines, cond, grid, out=None, accumulate=False):
+    ctx.load_lines(lines, cond["mass_amu"], cond["T0"])
+    k = ctx.opacity(state_of(cond), grid, hk.HK_F64, out=out, accumulate=accumulate)
+    torch.cuda.synchronize()
+    return k
+
+
+def assert_close(got, ref, tol=TOL, what=""):
+    got = np.asarray(got); ref = np.asarray(ref)
+    assert got.shape == ref.shape
+    zero = ref == 0
+    assert np.all(got[zero] == 0), (what, "nonzero where the oracle is zero")
+    if (~zero).any():
+        err = np.abs(got[~zero] / ref[~zero] - 1.0)
+        i = int(err.argmax())
+        assert err.max() <= tol, (what, float(err.max()), int(np.flatnonzero(~zero)[i]))
+
+
+# ---- small and edge cases, full grid against the oracle ----
+
+def _one(nu, S=1e-20, E=100.0, g=0.05, n=0.5):
+    return {"nu": np.array([nu], float), "S_ref": np.array([S]), "E_lower": np.array([E]),
+            "gamma_air": np.array([g]), "n_air": np.array([n])}
+
+
+def _cases():
+    L = synth.line_list(500, 60.0, seed=21)
+    hi = synth.line_list(300, 50.0, seed=22); hi["nu"] = hi["nu"] + 29950.0
+    cases = {
+        "ragged_grid": (L, synth.conditions(1500, 1.0),
+                        {"nu_min": 0.0, "dnu": 0.01, "n_points": 6000 + 17, "cutoff": 5.0}),
+        "tiny_grid": (L, synth.conditions(800, 0.3),
+                      {"nu_min": 20.0, "dnu": 0.01, "n_points": 37, "cutoff": 5.0}),
+        "high_nu_cores": (hi, synth.conditions(2500, 0.05),
+                          {"nu_min": 29950.0, "dnu": 0.01, "n_points": 5000, "cutoff": 25.0}),
+        "low_pressure": (hi, synth.conditions(1000, 1e-6),
+                         {"nu_min": 29960.0, "dnu": 0.01, "n_points": 3000, "cutoff": 10.0}),
+        "zero_pressure": (hi, synth.conditions(1000, 0.0),
+                          {"nu_min": 29960.0, "dnu": 0.01, "n_points": 3000, "cutoff": 10.0}),
+        "high_pressure": (L, synth.conditions(300, 100.0),
+                          {"nu_min": 0.0, "dnu": 0.01, "n_points": 6000, "cutoff": 30.0}),
+        "zero_cutoff": (L, synth.conditions(1500, 1.0),
+                        {"nu_min": 0.0, "dnu": 0.0625, "n_points": 960, "cutoff": 0.0}),
+        "offgrid_lines": (L, synth.conditions(1500, 1.0),
+                          {"nu_min": 25.0, "dnu": 0.01, "n_points": 1000, "cutoff": 20.0}),
+        "single_line_on_point": (_one(1000.0), synth.conditions(1500, 1.0),
+                                 {"nu_min": 990.0, "dnu": 0.0078125, "n_points": 2561,
+                                  "cutoff": 10.0}),
+        "empty_list": ({k: np.zeros(0) for k in L}, synth.conditions(1500, 1.0),
+                       {"nu_min": 0.0, "dnu": 0.01, "n_points": 1000, "cutoff": 5.0}),
+    }
+    # optional fields: self broadening, pressure shift, natural width
+    rng = np.random.default_rng(23)
+    L2 = dict(L)
+    L2["gamma_self"] = rng.uniform(0.1, 0.5, 500)
+    L2["delta"] = rng.uniform(-0.02, 0.02, 500)
+    L2["A21"] = 10.0 ** rng.uniform(0, 8, 500)
+    cases["self_shift_natural"] = (L2, synth.conditions(1200, 2.0),
+                                   {"nu_min": 0.0, "dnu": 0.01, "n_points": 6000, "cutoff": 8.0})
+    return cases
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_small_cases_against_oracle(ctx, name):
+    lines, cond, grid = CASES[name]
+    say("case", name, "lines", len(lines["nu"]), "points", grid["n_points"])
+    k = gpu_opacity(ctx, lines, cond, grid).cpu().numpy()
+    ref, n_ref = oracle.opacity(lines, cond, grid)
+    assert_close(k, ref, what=name)
+    st = ctx.stats()
+    assert st["evals"] == n_ref
+    if len(lines["nu"]):
+        tot, core, g3, g1 = oracle.eval_counts(lines, cond, grid)
+        assert tot == st["evals"]
+        for a, b in ((core, st["evals_core"]), (g3, st["evals_gh3"]), (g1, st["evals_gh1"])):
+            assert abs(a - b) <= 2  # region ties at rounding distance only
+
+
+def test_zero_points(ctx):
+    lines, cond, _ = CASES["ragged_grid"]
+    g = {"nu_min": 0.0, "dnu": 0.01, "n_points": 0, "cutoff": 5.0}
+    k = gpu_opacity(ctx, lines, cond, g)
+    assert k.numel() == 0
+
+
+# ---- the CPU-sized FP64 workload, full grid ----
+
+def test_lines1e4_grid3e5_full(ctx):
+    w = synth.WORKLOADS["lines1e4_grid3e5"]
+    lines, cond, grid = w.lines(), w.conditions(), w.grid()
+    say("workload", w.name)
+    kg = gpu_opacity(ctx, lines, cond, grid)
+    k = kg.cpu().numpy()
+    ref, n_ref = oracle.opacity(lines, cond, grid)
+    assert np.all(ref > 0)
+    assert_close(k, ref, what=w.name)
+    st = ctx.stats()
+    tot, core, g3, g1 = oracle.eval_counts(lines, cond, grid)
+    assert st["evals"] == tot == n_ref
+    assert abs(st["evals_core"] - core) <= 2 and abs(st["evals_gh1"] - g1) <= 2
+    # k(g): product nodes on the GPU, the oracle's own nodes on the CPU
+    g_gpu, _ = hk.hk_gauss_legendre(w.n_g)
+    g_ora, _ = oracle.g_nodes(w.n_g)
+    kd = ctx.kdist(kg, w.points_per_bin, g_gpu).cpu().numpy()
+    kd_ref = oracle.kdist(ref, w.points_per_bin, g_ora)
+    assert kd.shape == (3, 20)
+    assert_close(kd, kd_ref, what="k(g)")
+    assert np.all(np.diff(kd, axis=1) >= 0)
+
+
+def test_deterministic_and_accumulate_chunks(ctx):
+    w = synth.WORKLOADS["lines1e4_grid3e5"]
+    lines, cond, grid = w.lines(), w.conditions(), w.grid()
+    a = gpu_opacity(ctx, lines, cond, grid).cpu().numpy()
+    b = gpu_opacity(ctx, lines, cond, grid).cpu().numpy()
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+    # three chunks contiguous in wavenumber, accumulated: each point sums the
+    # same lines in the same order, so the result is bitwise the same
+    order = np.argsort(lines["nu"], kind="stable")
+    out = torch.zeros(grid["n_points"], dtype=torch.float64, device="cuda")
+    for part in np.array_split(order, 3):
+        chunk = {k: v[part] for k, v in lines.items()}
+        gpu_opacity(ctx, chunk, cond, grid, out=out, accumulate=True)
+    c = out.cpu().numpy()
+    assert np.array_equal(a.view(np.uint64), c.view(np.uint64))
+
+
+# ---- k-distribution: LDS and chunked/merge paths, bitwise vs the oracle ----
+
+@pytest.mark.parametrize("n,ppb", [(1, 1), (1000, 7), (100000, 1000), (65536, 16384),
+                                   (50000, 16385), (300000, 100000), (250001, 100000),
+                                   (40000, 40000)])
+def test_kdist_matches_oracle_bitwise(ctx, n, ppb):
+    say("kdist", n, ppb)
+    rng = np.random.default_rng(n + ppb)
+    kap = 10.0 ** rng.uniform(-30, -18, n)
+    kap[rng.integers(0, n, n // 10)] = kap[0]  # ties
+    if n > 10:
+        kap[:5] = 0.0
+    g, _ = oracle.g_nodes(20)
+    kt = torch.from_numpy(kap).cuda()
+    srt = torch.empty_like(kt)
+    kd = ctx.kdist(kt, ppb, g, sorted_out=srt).cpu().numpy()
+    ref = oracle.kdist(kap, ppb, g)
+    assert np.array_equal(kd, ref)
+    s = srt.cpu().numpy()
+    for b0 in range(0, n, ppb):
+        assert np.array_equal(s[b0:b0 + ppb], np.sort(kap[b0:b0 + ppb]))
+
+
+# ---- the mid-scale workload at full size (the benchmark's launch), sampled ----
+
+def test_lines1e6_grid3e6_sampled(ctx):
+    w = synth.WORKLOADS["lines1e6_grid3e6"]
+    lines, cond, grid = w.lines(), w.conditions(), w.grid()
+    say("workload", w.name)
+    kg = gpu_opacity(ctx, lines, cond, grid)
+    k = kg.cpu().numpy()
+    N = grid["n_points"]
+    assert np.all(np.isfinite(k)) and np.all(k > 0)
+    rng = np.random.default_rng(31)
+    for j0 in (0, N // 2 - 1000, N - 2000) + tuple(int(v) for v in rng.integers(0, N - 300, 3)):
+        j1 = min(j0 + 2000, N)
+        ref, _ = oracle.opacity(lines, cond, grid, j0, j1)
+        assert_close(k[j0:j1], ref, what="points %d..%d" % (j0, j1))
+    st = ctx.stats()
+    assert st["evals"] > 1.9e10 and st["evals_core"] > 0
+    g_gpu, _ = hk.hk_gauss_legendre(w.n_g)
+    g_ora, _ = oracle.g_nodes(w.n_g)
+    kd = ctx.kdist(kg, w.points_per_bin, g_gpu).cpu().numpy()
+    assert kd.shape == (300, 20)
+    ppb = w.points_per_bin
+    for b in (0, 137, 299):
+        ref, _ = oracle.opacity(lines, cond, grid, b * ppb, (b + 1) * ppb)
+        kr, _ = oracle.kdist_bin(ref, g_ora)
+        assert_close(kd[b], kr, what="k(g) bin %d" % b)
+
+
+def test_follows_a_non_default_torch_stream(ctx):
+    """Work is ordered on whatever stream the context was given: results read
+    on that stream right after the calls are complete."""
+    w = synth.WORKLOADS["lines1e4_grid3e5"]
+    lines, cond, grid = w.lines(), w.conditions(), w.grid()
+    ref = gpu_opacity(ctx, lines, cond, grid).cpu().numpy()
+    s = torch.cuda.Stream()
+    c2 = hk.Context(0)
+    try:
+        with torch.cuda.stream(s):
+            c2.use_current_stream()
+            c2.load_lines(lines, cond["mass_amu"], cond["T0"])
+            k = c2.opacity(state_of(cond), grid)
+            kd = c2.kdist(k, w.points_per_bin, oracle.g_nodes(20)[0])
+            host = k.to("cpu", non_blocking=False).numpy()
+            kd_host = kd.cpu().numpy()
+        assert np.array_equal(host.view(np.uint64), ref.view(np.uint64))
+        assert np.all(np.diff(kd_host, axis=1) >= 0) and np.all(kd_host > 0)
+    finally:
+        c2.close()
