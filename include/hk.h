@@ -141,9 +141,10 @@ int hk_load_lines(hk_ctx* ctx, const hk_lines* lines, const hk_species* species)
  * the closed index interval [ceil((nu0' - cutoff - nu_min)/dnu),
  * floor((nu0' + cutoff - nu_min)/dnu)].  H_V(a,u) uses the series form of
  * the Faddeeva function for a^2+u^2 < 100 and 3-node / 1-node Gauss-Hermite
- * quadrature for a^2+u^2 < 1e6 / >= 1e6 (§2.4).  Each point sums its lines
- * in ascending (nu, input index) order, with no atomics: results are
- * bitwise reproducible.
+ * quadrature for a^2+u^2 < 1e6 / >= 1e6 (§2.4).  Each point sums its
+ * Gauss-Hermite terms, then its series terms, each in ascending (nu, input
+ * index) order, with no atomics: results are bitwise reproducible and do not
+ * depend on the tuning options.
  *
  * precision HK_F64: kappa is [device] double[n_points]; comp must be NULL.
  * precision HK_F32_KAHAN: kappa is [device] float[n_points] and comp a
@@ -173,6 +174,12 @@ int hk_kdist(hk_ctx* ctx, const void* kappa, int precision, int64_t n_points,
  * nodes ascending, weights summing to 1.  n in 1 .. 256. */
 int hk_gauss_legendre(int32_t n, double* g, double* w);
 
+/* Tuning knobs (results do not depend on them; only speed does):
+ *   "f64_points_per_lane"  2, 4 or 8 grid points per lane in the binary64
+ *                          opacity kernel (default 4).
+ * Unknown names or values: HK_EINVAL. */
+int hk_set_option(hk_ctx* ctx, const char* name, int64_t value);
+
 /* Evaluation counts of the last hk_opacity call (synchronises the stream). */
 int hk_stats(hk_ctx* ctx, hk_run_stats* out);
 
@@ -180,9 +187,10 @@ int hk_stats(hk_ctx* ctx, hk_run_stats* out);
  * stream around each kernel while timing is enabled, summed over calls since
  * the last reset.  Stage indices: */
 #define HK_STAGE_LINE_PREP 0  /* per-line S(T), widths, windows, tile ranges */
-#define HK_STAGE_OPACITY 1    /* Voigt evaluation and accumulation kernel */
+#define HK_STAGE_OPACITY 1    /* Gauss-Hermite (a^2+u^2 >= 100) evaluation kernel */
 #define HK_STAGE_KDIST 2      /* per-bin sort and k(g) */
-#define HK_N_STAGES 3
+#define HK_STAGE_CORE 3       /* series (a^2+u^2 < 100) evaluation kernel */
+#define HK_N_STAGES 4
 typedef struct {
     double ms[HK_N_STAGES];     /* summed milliseconds */
     int64_t calls[HK_N_STAGES]; /* number of timed launches */

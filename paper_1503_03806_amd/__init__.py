@@ -18,7 +18,7 @@ __all__ = ["HK_OK", "HK_EINVAL", "HK_ENOMEM", "HK_EDEVICE", "HK_EUNSUPPORTED", "
            "HK_F64", "HK_F32_KAHAN", "HK_MAX_G", "HKError", "lib", "hk_version", "hk_create",
            "hk_destroy", "hk_set_stream", "hk_sync", "hk_last_error", "hk_load_lines",
            "hk_opacity", "hk_kdist", "hk_gauss_legendre", "hk_stats", "hk_set_timing",
-           "hk_get_timing", "Context", "LIB_PATH"]
+           "hk_get_timing", "hk_set_option", "Context", "LIB_PATH"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhk.so")
 
@@ -58,8 +58,8 @@ class hk_run_stats(C.Structure):
                                          "n_lines")]
 
 
-HK_STAGE_LINE_PREP, HK_STAGE_OPACITY, HK_STAGE_KDIST, HK_N_STAGES = 0, 1, 2, 3
-STAGE_NAMES = ("line_prep", "opacity", "kdist")
+HK_STAGE_LINE_PREP, HK_STAGE_OPACITY, HK_STAGE_KDIST, HK_STAGE_CORE, HK_N_STAGES = 0, 1, 2, 3, 4
+STAGE_NAMES = ("line_prep", "opacity", "kdist", "core")
 
 
 class hk_timing(C.Structure):
@@ -98,6 +98,7 @@ def lib():
         L.hk_gauss_legendre.argtypes = [C.c_int32, _pd, _pd]; L.hk_gauss_legendre.restype = i32
         L.hk_stats.argtypes = [vp, C.POINTER(hk_run_stats)]; L.hk_stats.restype = i32
         L.hk_set_timing.argtypes = [vp, i32]; L.hk_set_timing.restype = i32
+        L.hk_set_option.argtypes = [vp, C.c_char_p, i64]; L.hk_set_option.restype = i32
         L.hk_get_timing.argtypes = [vp, C.POINTER(hk_timing)]; L.hk_get_timing.restype = i32
         _lib = L
     return _lib
@@ -201,6 +202,10 @@ def hk_stats(ctx) -> dict:
     return {f: int(getattr(s, f)) for f, _ in hk_run_stats._fields_}
 
 
+def hk_set_option(ctx, name: str, value: int):
+    _check(lib().hk_set_option(ctx, name.encode(), int(value)), ctx)
+
+
 def hk_set_timing(ctx, enable: bool):
     _check(lib().hk_set_timing(ctx, 1 if enable else 0), ctx)
 
@@ -268,6 +273,9 @@ class Context:
 
     def stats(self) -> dict:
         return hk_stats(self.h)
+
+    def set_option(self, name: str, value: int):
+        hk_set_option(self.h, name, value)
 
     def set_timing(self, enable: bool = True):
         hk_set_timing(self.h, enable)

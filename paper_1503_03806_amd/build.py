@@ -27,7 +27,9 @@ def hipcc() -> str:
 
 
 def common_flags():
-    return ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+    # no implicit contraction: every fused multiply-add is an explicit fma(),
+    # so a value's rounding does not depend on which code path computed it
+    return ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-ffp-contract=off",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-function", "-I" + os.path.join(ROOT, "include")]
 

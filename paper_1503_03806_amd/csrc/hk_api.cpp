@@ -53,13 +53,15 @@ struct hk_ctx {
     bool lines_loaded = false;
     bool has_self = false, has_delta = false, has_A = false;
     double max_abs_delta = 0.0;
+    double nu_max = 0.0;  // largest line centre (bounds the Doppler core widths)
     hk_species species{296.0, 0.0};
     DevBuf lines;  // 8 arrays of n doubles
     // per-state records and tile ranges
-    DevBuf wing, core, ranges;
+    DevBuf wing, core, ranges, ranges_core;
     DevBuf partial;
     DevBuf kscratch;
     bool have_run = false;
+    int f64_points_per_lane = 4;  // tile shape of the binary64 opacity kernel
     // stage timing: events recorded around each timed launch, resolved
     // lazily (pending pairs) so timing adds no host synchronisation
     bool timing = false;
@@ -235,6 +237,7 @@ int hk_destroy(hk_ctx* ctx)
     ctx->wing.release();
     ctx->core.release();
     ctx->ranges.release();
+    ctx->ranges_core.release();
     ctx->partial.release();
     ctx->kscratch.release();
     for (auto& p : ctx->pending) {
@@ -310,6 +313,7 @@ int hk_load_lines(hk_ctx* ctx, const hk_lines* L, const hk_species* sp)
     ctx->has_delta = L->delta != nullptr;
     ctx->has_A = L->A21 != nullptr;
     ctx->max_abs_delta = maxd;
+    ctx->nu_max = n > 0 ? host[(size_t)n - 1] : 0.0;
     ctx->species = *sp;
     ctx->lines_loaded = true;
     return HK_OK;
@@ -350,9 +354,14 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
     const size_t nb = (size_t)std::max<int64_t>(n, 1);
     HK_HIP(ctx, ctx->wing.ensure(nb * sizeof(WingRec)), "allocating line records");
     HK_HIP(ctx, ctx->core.ensure(nb * sizeof(CoreRec)), "allocating line records");
-    const int32_t tp = opacity_f64_tile_points();
+    const int ppl = ctx->f64_points_per_lane;
+    const int32_t tp = opacity_f64_tile_points(ppl);
     const int64_t n_tiles = ((int64_t)np + tp - 1) / tp;
+    const int32_t tpc = core_f64_tile_points();
+    const int64_t n_tiles_c = ((int64_t)np + tpc - 1) / tpc;
     HK_HIP(ctx, ctx->ranges.ensure((size_t)std::max<int64_t>(n_tiles, 1) * 2 * sizeof(int64_t)),
+           "allocating tile ranges");
+    HK_HIP(ctx, ctx->ranges_core.ensure((size_t)std::max<int64_t>(n_tiles_c, 1) * 2 * sizeof(int64_t)),
            "allocating tile ranges");
 
     LinesDev L;
@@ -372,6 +381,11 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
     // cutoff + the largest pressure shift (+ two grid steps of slack for the
     // rounding of the window bounds)
     const double reach = grid->cutoff + ctx->max_abs_delta * st->P + 2.0 * grid->dnu;
+    // the series region a^2+u^2 < 100 lies within 10 alpha of the centre,
+    // and alpha = nu * dop is largest for the largest nu
+    const double reach_core =
+        std::min(10.0 * pp.dop * ctx->nu_max, grid->cutoff) + ctx->max_abs_delta * st->P + 2.0 * grid->dnu;
+    int64_t* ranges_c = static_cast<int64_t*>(ctx->ranges_core.p);
 
     {
         StageTimer tm(ctx, HK_STAGE_LINE_PREP);
@@ -379,13 +393,23 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
         HK_HIP(ctx, launch_tile_ranges(L.nu, n, n_tiles, tp, grid->nu_min, grid->dnu, np, reach, ranges,
                                        ctx->stream),
                "tile_ranges");
+        HK_HIP(ctx, launch_tile_ranges(L.nu, n, n_tiles_c, tpc, grid->nu_min, grid->dnu, np, reach_core,
+                                       ranges_c, ctx->stream),
+               "tile_ranges");
         tm.stop();
     }
     {
         StageTimer tm(ctx, HK_STAGE_OPACITY);
-        HK_HIP(ctx, launch_opacity_f64(wing, core, ranges, n_tiles, grid->nu_min, grid->dnu, np,
-                                       static_cast<double*>(kappa), accumulate ? 1 : 0, ctx->stream),
-               "opacity_f64");
+        HK_HIP(ctx, launch_wing_f64(ppl, wing, ranges, n_tiles, grid->nu_min, grid->dnu, np,
+                                    static_cast<double*>(kappa), accumulate ? 1 : 0, ctx->stream),
+               "wing_f64");
+        tm.stop();
+    }
+    {
+        StageTimer tm(ctx, HK_STAGE_CORE);
+        HK_HIP(ctx, launch_core_f64(wing, core, ranges_c, n_tiles_c, grid->nu_min, grid->dnu, np,
+                                    static_cast<double*>(kappa), ctx->stream),
+               "core_f64");
         tm.stop();
     }
     ctx->have_run = true;
@@ -445,6 +469,19 @@ int hk_stats(hk_ctx* ctx, hk_run_stats* out)
         out->evals_gh1 = e - g;
     }
     return HK_OK;
+}
+
+int hk_set_option(hk_ctx* ctx, const char* name, int64_t value)
+{
+    if (!name) return fail(ctx, HK_EINVAL, "option name is NULL");
+    if (std::strcmp(name, "f64_points_per_lane") == 0) {
+        if (value != 2 && value != 4 && value != 8)
+            return fail(ctx, HK_EINVAL, "f64_points_per_lane must be 2, 4 or 8 (got %lld)", (long long)value);
+        if (int rc = check_ctx(ctx)) return rc;
+        ctx->f64_points_per_lane = (int)value;
+        return HK_OK;
+    }
+    return fail(ctx, HK_EINVAL, "unknown option '%s'", name);
 }
 
 int hk_set_timing(hk_ctx* ctx, int enable)

@@ -93,10 +93,16 @@ hipError_t launch_line_prep_f64(const LinesDev& L, const PrepParams& pp, WingRec
 hipError_t launch_tile_ranges(const double* nu_sorted, int64_t n_lines, int64_t n_tiles,
                               int32_t tile_points, double nu_min, double dnu, int32_t n_points,
                               double reach, int64_t* ranges, hipStream_t s);
-int32_t opacity_f64_tile_points();
-hipError_t launch_opacity_f64(const WingRec* wing, const CoreRec* core, const int64_t* ranges,
-                              int64_t n_tiles, double nu_min, double dnu, int32_t n_points,
-                              double* kappa, int accumulate, hipStream_t s);
+// Binary64 opacity: the wing kernel writes kappa (points_per_lane 2, 4 or
+// 8), the core kernel then adds the series terms.
+int32_t opacity_f64_tile_points(int points_per_lane);
+int32_t core_f64_tile_points();
+hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const int64_t* ranges,
+                           int64_t n_tiles, double nu_min, double dnu, int32_t n_points,
+                           double* kappa, int accumulate, hipStream_t s);
+hipError_t launch_core_f64(const WingRec* wing, const CoreRec* core, const int64_t* ranges,
+                           int64_t n_tiles, double nu_min, double dnu, int32_t n_points,
+                           double* kappa, hipStream_t s);
 hipError_t launch_eval_counts(const WingRec* wing, int64_t n_lines, int64_t* partial,
                               int32_t n_blocks, hipStream_t s);
 

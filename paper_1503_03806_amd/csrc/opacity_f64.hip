@@ -8,77 +8,115 @@
 // lines of its tile in order, so each point sums its lines in ascending
 // (nu, index) order without atomics.
 //
-// Per (wavefront, line) a uniform test against the line's precomputed index
-// intervals picks one of three paths: all points in the 1-node region, all
-// in the 3-node region, or the general path (window edges, region edges,
-// core series).  Only the general path evaluates the series, per lane, for
-// the points with a^2+u^2 < 100.
+// Two kernels per call:
+//  wing: the 3-node and 1-node Gauss-Hermite rules (a^2+u^2 >= 100) for
+//        every line and point; it writes kappa.
+//  core: the series for a^2+u^2 < 100, a few hundred times rarer but ~30
+//        times dearer per point and heavy in registers; it adds its own
+//        ordered sum to kappa.
+// So kappa_j = sum_wing + sum_core, each in line order: reproducible bit for
+// bit, independent of the tile shape.
 #include "hk_internal.h"
 
 namespace hk {
 namespace {
 
-constexpr int kP = 4;       // grid points per lane
-constexpr int kWaves = 4;   // wavefronts per workgroup
-constexpr int kTL = 256;    // line records per LDS tile
-constexpr int kTilePoints = 64 * kP * kWaves;
+constexpr int kWaves = 4;            // wavefronts per workgroup
+constexpr int kTL = 64 * kWaves;     // line records per LDS tile: one per thread
+constexpr int kMaxTerms = 2 * 10 + 14;  // series terms: n = 1 .. 2 ceil(x) + 14, x < 10
 
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous range of tiles so neighbouring tiles, which read mostly the same
-// lines, share that XCD's L2.
-__device__ inline int64_t xcd_tile(int64_t b, int64_t nb)
+// Per-(line, wavefront) path, decided once per LDS tile.
+enum : uint32_t { kSkip = 0, kGH1 = 1, kGH3 = 2, kGeneral = 3 };
+
+// num / den to about 2^-48 relative: the hardware reciprocal (relative
+// error below 2^-24 on gfx950) and one Newton correction of the quotient.
+// Callers discard the result (by select) wherever den may be 0.
+__device__ inline double qdiv(double num, double den)
 {
-    int64_t q = nb >> 3, r = nb & 7;
-    int64_t x = b & 7, k = b >> 3;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+    const double r = __builtin_amdgcn_rcp(den);
+    const double q = num * r;
+    const double e = fma(-den, q, num);
+    return fma(e, r, q);
 }
 
-// H_V(a, u) for a^2 + u^2 < 100 by the series form of the Faddeeva function
-// (Abramowitz & Stegun 7.1.29 applied to w(z) = e^{-z^2} erfc(-iz), step
-// 1/2), the three exponential series summed in one loop (§2.4).  x = |u|,
-// y = a, ex = erfcx(y), T1 = sum_n e^{-n^2/4}/(n^2/4+y^2).  The Gaussians
-// e^{-(n/2 -+ x)^2} come from two geometric-ratio recurrences instead of an
-// exp() per term.
-__device__ double voigt_core(double x, double y, double y2, double ex, double T1)
+// 1 / den to about 2^-48 relative (one Newton step on the reciprocal).
+__device__ inline double qrcp(double den)
 {
-    const double c = 0.77880078307140486825;  // e^{-1/4}
-    const double d = 0.60653065971263342360;  // e^{-1/2}
-    const double E = exp(-x * x);
-    const double up = exp(x);
-    const double dn = 1.0 / up;
-    double g3 = E * up * c;  // e^{-(1/2 - x)^2}
-    double g2 = E * dn * c;  // e^{-(1/2 + x)^2}
-    double r3 = up * (c * d);
-    double r2 = dn * (c * d);
-    const int N = 2 * (int)ceil(x) + 14;
-    double s23 = 0.0;
-    for (int n = 1; n <= N; ++n) {
-        const double den = fma(0.25 * (double)n, (double)n, y2);
-        s23 += (g2 + g3) / den;
-        g3 *= r3;
-        r3 *= d;
-        g2 *= r2;
-        r2 *= d;
-    }
-    double s, co;
-    sincos(x * y, &s, &co);
-    const double cos2 = (co - s) * (co + s);
-    const double sy = (y > 0.0) ? s / y : x;
-    return E * fma(ex, cos2, s * sy * kInvPi) + (y * kInvPi) * fma(-cos2 * E, T1, 0.5 * s23);
+    const double r = __builtin_amdgcn_rcp(den);
+    return fma(r, fma(-den, r, 1.0), r);
 }
 
-__global__ __launch_bounds__(64 * kWaves) void opacity_f64_kernel(
-    const WingRec* __restrict__ wing, const CoreRec* __restrict__ core,
-    const int64_t* __restrict__ ranges, int64_t n_tiles, double nu_min, double dnu, int32_t n,
-    double* __restrict__ kappa, int accumulate)
+// Tiles are dispatched dearest first (high wavenumber: wider Doppler cores,
+// more 3-node points), so the cheap tiles fill the tail of the launch.
+__device__ inline int64_t tile_of(int64_t b, int64_t nb) { return nb - 1 - b; }
+
+// The path of one line for the points [run0, run1] of a wavefront.  The
+// paired reciprocals need the products of two denominators in binary64
+// range: alpha^2 > 1e-40 and Gamma_L^2 < 1e20 cover every physical line
+// (alpha ~ 4e-6 nu at 1500 K); other lines take the general path unpaired.
+__device__ inline bool pair_safe(const WingRec& r) { return r.h > 1.5e-40 && r.G2 < 1e20; }
+
+// run1 is the run's last grid point; a run cut short by the grid end
+// (run1 < run_end) always takes the general path, which evaluates points
+// whose pair partner lies beyond the grid unpaired.
+__device__ inline uint32_t classify(const WingRec& r, int32_t run0, int32_t run1, int32_t run_end)
 {
+    if (run0 > run1 || r.whi < run0 || r.wlo > run1) return kSkip;
+    if (run1 < run_end) return kGeneral;
+    const bool full = r.wlo <= run0 && r.whi >= run1;
+    const bool nocore = run1 < r.clo || run0 > r.chi;
+    if (!(full && nocore && pair_safe(r))) return kGeneral;
+    if (run1 < r.g3lo || run0 > r.g3hi) return kGH1;
+    if (r.g3lo <= run0 && r.g3hi >= run1) return kGH3;
+    return kGeneral;
+}
+
+// S Phi = num / den of one point, dv = nu_j - nu0.
+// 1-node rule: S G/(pi (dv^2 + G^2)).
+__device__ inline void gh1_terms(double dv, double G2, double Lg, double& num, double& den)
+{
+    num = Lg;
+    den = fma(dv, dv, G2);
+}
+// 3-node rule: the three weighted Lorentzians over a common denominator
+// (Lg/3) (2P + E D0) / (D0 P).
+__device__ inline void gh3_terms(double dv, double G2, double h, double c6, double Lg3, double& num,
+                                 double& den)
+{
+    const double q = dv * dv;
+    const double D0 = q + G2;
+    const double E = D0 + h;
+    const double P = fma(E, E, -c6 * q);
+    num = Lg3 * fma(D0, E, P + P);
+    den = D0 * P;
+}
+
+// Two points share one reciprocal: 1/da = db / (da db).  Point j pairs with
+// j + 64 when floor(j / 64) is even (runs start at multiples of 128), so a
+// point's value is the same bits whichever path or tile shape computes it.
+__device__ inline void pair_add(double& acc_a, double& acc_b, double na, double da, double nb,
+                                double db, bool ta, bool tb)
+{
+    const double c = qrcp(da * db);
+    acc_a = fma(ta ? c * db : 0.0, na, acc_a);
+    acc_b = fma(tb ? c * da : 0.0, nb, acc_b);
+}
+
+template <int kP>
+__global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
+    const WingRec* __restrict__ wing, const int64_t* __restrict__ ranges, int64_t n_tiles,
+    double nu_min, double dnu, int32_t n, double* __restrict__ kappa, int accumulate)
+{
+    static_assert(kP % 2 == 0, "points are processed in pairs");
+    constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ WingRec tile[kTL];
-    const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
+    __shared__ uint32_t code[kTL];
+    const int64_t t = tile_of(blockIdx.x, gridDim.x);
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int32_t run0 = (int32_t)(t * kTilePoints) + wave * 64 * kP;
+    const int32_t tile0 = (int32_t)(t * kTilePoints);
+    const int32_t run0 = tile0 + wave * 64 * kP;
     const int32_t run1 = min(run0 + 64 * kP, n) - 1;  // last point of the run (inclusive)
-    const bool active = run0 < n;
 
     double nuj[kP], acc[kP];
 #pragma unroll
@@ -91,91 +129,223 @@ __global__ __launch_bounds__(64 * kWaves) void opacity_f64_kernel(
     const int64_t L0 = ranges[2 * t], L1 = ranges[2 * t + 1];
     for (int64_t base = L0; base < L1; base += kTL) {
         const int cnt = (int)min((int64_t)kTL, L1 - base);
-        {
-            const uint4* src = reinterpret_cast<const uint4*>(wing + base);
-            uint4* dst = reinterpret_cast<uint4*>(tile);
-            for (int k = threadIdx.x; k < cnt * 4; k += 64 * kWaves) dst[k] = src[k];
+        // stage one record per thread and decide its path for each wavefront
+        if ((int)threadIdx.x < cnt) {
+            const WingRec r = wing[base + threadIdx.x];
+            tile[threadIdx.x] = r;
+            uint32_t c = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                const int32_t r0 = tile0 + w * 64 * kP;
+                const int32_t r1 = min(r0 + 64 * kP, n) - 1;
+                c |= classify(r, r0, r1, r0 + 64 * kP - 1) << (8 * w);
+            }
+            code[threadIdx.x] = c;
         }
         __syncthreads();
-        if (active) {
-            for (int k = 0; k < cnt; ++k) {
-                const int32_t wlo = tile[k].wlo, whi = tile[k].whi;
-                if (whi < run0 || wlo > run1) continue;
-                const int32_t g3lo = tile[k].g3lo, g3hi = tile[k].g3hi;
-                const int32_t clo = tile[k].clo, chi = tile[k].chi;
-                const double nu0 = tile[k].nu0, Lg = tile[k].Lg, G2 = tile[k].G2;
-                const bool full = wlo <= run0 && whi >= run1;
-                const bool all1 = run1 < g3lo || run0 > g3hi;
-                const bool nocore = run1 < clo || run0 > chi;
-                if (full && all1) {
+        for (int k = 0; k < cnt; ++k) {
+            const uint32_t path =
+                (uint32_t)__builtin_amdgcn_readfirstlane((int)code[k]) >> (8 * wave) & 0xffu;
+            if (path == kSkip) continue;
+            const double nu0 = tile[k].nu0, Lg = tile[k].Lg, G2 = tile[k].G2;
+            if (path == kGH1) {
 #pragma unroll
-                    for (int p = 0; p < kP; ++p) {
-                        const double dv = nuj[p] - nu0;
-                        acc[p] += Lg / fma(dv, dv, G2);
-                    }
-                    continue;
+                for (int p = 0; p < kP; p += 2) {
+                    double na, da, nb, db;
+                    gh1_terms(nuj[p] - nu0, G2, Lg, na, da);
+                    gh1_terms(nuj[p + 1] - nu0, G2, Lg, nb, db);
+                    pair_add(acc[p], acc[p + 1], na, da, nb, db, true, true);
                 }
-                const double h = tile[k].h, c6 = tile[k].c6;
-                const double Lg3 = Lg * (1.0 / 3.0);
-                if (full && nocore && g3lo <= run0 && g3hi >= run1) {
+                continue;
+            }
+            const double h = tile[k].h, c6 = tile[k].c6;
+            const double Lg3 = Lg * (1.0 / 3.0);
+            if (path == kGH3) {
 #pragma unroll
-                    for (int p = 0; p < kP; ++p) {
-                        const double dv = nuj[p] - nu0;
-                        const double q = dv * dv;
-                        const double D0 = q + G2;
-                        const double E = D0 + h;
-                        const double P = fma(E, E, -c6 * q);
-                        acc[p] += (Lg3 * fma(D0, E, 2.0 * P)) / (D0 * P);
-                    }
-                    continue;
+                for (int p = 0; p < kP; p += 2) {
+                    double na, da, nb, db;
+                    gh3_terms(nuj[p] - nu0, G2, h, c6, Lg3, na, da);
+                    gh3_terms(nuj[p + 1] - nu0, G2, h, c6, Lg3, nb, db);
+                    pair_add(acc[p], acc[p + 1], na, da, nb, db, true, true);
                 }
-                // general path
+                continue;
+            }
+            // general path: window edges, region edges, core points (left to
+            // the core kernel), lines outside the pairing range
+            const int32_t wlo = tile[k].wlo, whi = tile[k].whi;
+            const int32_t g3lo = tile[k].g3lo, g3hi = tile[k].g3hi;
+            const int32_t clo = tile[k].clo, chi = tile[k].chi;
+            const bool safe = pair_safe(tile[k]);
 #pragma unroll
-                for (int p = 0; p < kP; ++p) {
-                    const int32_t j = run0 + lane + 64 * p;
-                    const bool inw = j >= wlo && j <= whi;
+            for (int p = 0; p < kP; p += 2) {
+                double num[2], den[2];
+                bool take[2], core_pt[2];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int32_t j = run0 + lane + 64 * (p + e);
+                    const double dv = nuj[p + e] - nu0;
+                    double n1, d1, n3, d3;
+                    gh1_terms(dv, G2, Lg, n1, d1);
+                    gh3_terms(dv, G2, h, c6, Lg3, n3, d3);
                     const bool one = j < g3lo || j > g3hi;
-                    const double dv = nuj[p] - nu0;
-                    const double q = dv * dv;
-                    const double D0 = q + G2;
-                    const double E = D0 + h;
-                    const double P = fma(E, E, -c6 * q);
-                    const double num = one ? Lg : Lg3 * fma(D0, E, 2.0 * P);
-                    const double den = one ? D0 : D0 * P;
-                    double v = num / den;
-                    if (!nocore) {
-                        if (inw && j >= clo && j <= chi) {
-                            const CoreRec& cr = core[base + k];
-                            const double x = fabs(dv) * cr.invA;
-                            v = cr.norm * voigt_core(x, cr.y, cr.y2, cr.ex, cr.T1);
-                        }
-                    }
-                    acc[p] += inw ? v : 0.0;
+                    core_pt[e] = j >= clo && j <= chi;
+                    take[e] = j >= wlo && j <= whi && !core_pt[e];
+                    num[e] = one ? n1 : n3;
+                    den[e] = one ? d1 : d3;
+                }
+                if (safe && !core_pt[0] && !core_pt[1] && run0 + lane + 64 * (p + 1) < n) {
+                    pair_add(acc[p], acc[p + 1], num[0], den[0], num[1], den[1], take[0], take[1]);
+                } else {
+                    const double va = qdiv(num[0], den[0]), vb = qdiv(num[1], den[1]);
+                    acc[p] += take[0] ? va : 0.0;
+                    acc[p + 1] += take[1] ? vb : 0.0;
                 }
             }
         }
         __syncthreads();
     }
-    if (active) {
 #pragma unroll
-        for (int p = 0; p < kP; ++p) {
-            const int32_t j = run0 + lane + 64 * p;
-            if (j < n) kappa[j] = acc[p];
-        }
+    for (int p = 0; p < kP; ++p) {
+        const int32_t j = run0 + lane + 64 * p;
+        if (j < n) kappa[j] = acc[p];
     }
+}
+
+// H_V(a, u) for a^2 + u^2 < 100 by the series form of the Faddeeva function
+// (Abramowitz & Stegun 7.1.29 applied to w(z) = e^{-z^2} erfc(-iz), step
+// 1/2), the three exponential series summed in one loop (§2.4):
+//   H = e^{-x^2} [erfcx(y) cos 2xy + sin(xy) (sin(xy)/y) / pi]
+//     + (y/pi) [ -cos(2xy) e^{-x^2} T1 + (S2 + S3)/2 ],
+// x = |u|, y = a, T1 = sum_n e^{-n^2/4}/(n^2/4+y^2) (per line), and
+// S2 + S3 = sum_n (e^{-(n/2+x)^2} + e^{-(n/2-x)^2}) / (n^2/4 + y^2).  The
+// Gaussians come from geometric-ratio recurrences instead of an exp() per
+// term; inv[n-1] = 1/(n^2/4 + y^2) is the line's table (same y for all its
+// points), read from LDS.
+__device__ double voigt_core(double x, double y, double ex, double T1, const double* inv)
+{
+    const double c = 0.77880078307140486825;  // e^{-1/4}
+    const double d = 0.60653065971263342360;  // e^{-1/2}
+    const double E = exp(-x * x);
+    const double up = exp(x);
+    const double dn = qrcp(up);
+    double g3 = E * up * c;  // e^{-(1/2 - x)^2}
+    double g2 = E * dn * c;  // e^{-(1/2 + x)^2}
+    double r3 = up * (c * d);
+    double r2 = dn * (c * d);
+    const int N = 2 * (int)ceil(x) + 14;
+    double s23 = 0.0;
+    for (int n = 0; n < N; ++n) {
+        s23 = fma(g2 + g3, inv[n], s23);
+        g3 *= r3;
+        r3 *= d;
+        g2 *= r2;
+        r2 *= d;
+    }
+    double s, co;
+    sincos(x * y, &s, &co);
+    const double cos2 = (co - s) * (co + s);
+    const double sy = (y > 0.0) ? qdiv(s, y) : x;
+    return E * fma(ex, cos2, s * sy * kInvPi) + (y * kInvPi) * fma(-cos2 * E, T1, 0.5 * s23);
+}
+
+// Core-region contributions: each wavefront owns a run of 64*P points as in
+// the wing kernel and walks, in order, the lines whose a^2+u^2 < 100 points
+// meet its run.  Those points form one contiguous interval [a, b]; lanes
+// take them 64 at a time, and each value moves to the lane owning its point
+// (a rotation of the wavefront) to be added there.  kappa_j += the run's sum.
+template <int kP>
+__global__ __launch_bounds__(64 * kWaves) void core_f64_kernel(
+    const WingRec* __restrict__ wing, const CoreRec* __restrict__ core,
+    const int64_t* __restrict__ ranges, int64_t n_tiles, double nu_min, double dnu, int32_t n,
+    double* __restrict__ kappa)
+{
+    constexpr int kTilePoints = 64 * kP * kWaves;
+    __shared__ double inv_tab[kWaves][kMaxTerms];
+    const int64_t t = tile_of(blockIdx.x, gridDim.x);
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int32_t run0 = (int32_t)(t * kTilePoints) + wave * 64 * kP;
+    const int32_t run1 = min(run0 + 64 * kP, n) - 1;
+    if (run0 > run1) return;
+    double* inv = inv_tab[wave];
+    double acc[kP];
+#pragma unroll
+    for (int p = 0; p < kP; ++p) acc[p] = 0.0;
+    bool any = false;
+
+    const int64_t L0 = ranges[2 * t], L1 = ranges[2 * t + 1];
+    for (int64_t i = L0; i < L1; ++i) {
+        const int32_t a = max(max(wing[i].clo, wing[i].wlo), run0);
+        const int32_t b = min(min(wing[i].chi, wing[i].whi), run1);
+        if (a > b) continue;
+        any = true;
+        const double nu0 = wing[i].nu0;
+        const CoreRec cr = core[i];
+        if (lane < kMaxTerms) {
+            const double m = 0.5 * (double)(lane + 1);
+            inv[lane] = qrcp(fma(m, m, cr.y2));
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int32_t c0 = a; c0 <= b; c0 += 64) {
+            const int32_t j = c0 + lane;
+            double v = 0.0;
+            if (j <= b) {
+                const double dv = fma((double)j, dnu, nu_min) - nu0;
+                v = cr.norm * voigt_core(fabs(dv) * cr.invA, cr.y, cr.ex, cr.T1, inv);
+            }
+            // lane L owns point run0 + L + 64 s; its value for this chunk
+            // sits in lane (L - (c0 - run0)) mod 64
+            const int src = (lane - (c0 - run0)) & 63;
+            const double w = __shfl(v, src, 64);
+            const int32_t jo = c0 + src;
+            const int slot = (jo - run0 - lane) >> 6;
+#pragma unroll
+            for (int p = 0; p < kP; ++p) acc[p] += (jo <= b && slot == p) ? w : 0.0;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (!any) return;
+#pragma unroll
+    for (int p = 0; p < kP; ++p) {
+        const int32_t j = run0 + lane + 64 * p;
+        if (j <= run1) kappa[j] += acc[p];
+    }
+}
+
+template <int kP>
+hipError_t launch_wing(const WingRec* wing, const int64_t* ranges, int64_t n_tiles, double nu_min,
+                       double dnu, int32_t n, double* kappa, int accumulate, hipStream_t s)
+{
+    wing_f64_kernel<kP><<<dim3((unsigned)n_tiles), dim3(64 * kWaves), 0, s>>>(
+        wing, ranges, n_tiles, nu_min, dnu, n, kappa, accumulate);
+    return hipGetLastError();
 }
 
 }  // namespace
 
-int32_t opacity_f64_tile_points() { return kTilePoints; }
+int32_t opacity_f64_tile_points(int points_per_lane) { return 64 * points_per_lane * kWaves; }
+int32_t core_f64_tile_points() { return 64 * 4 * kWaves; }
 
-hipError_t launch_opacity_f64(const WingRec* wing, const CoreRec* core, const int64_t* ranges,
-                              int64_t n_tiles, double nu_min, double dnu, int32_t n_points,
-                              double* kappa, int accumulate, hipStream_t s)
+hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const int64_t* ranges,
+                           int64_t n_tiles, double nu_min, double dnu, int32_t n_points,
+                           double* kappa, int accumulate, hipStream_t s)
 {
     if (n_tiles == 0) return hipSuccess;
-    opacity_f64_kernel<<<dim3((unsigned)n_tiles), dim3(64 * kWaves), 0, s>>>(
-        wing, core, ranges, n_tiles, nu_min, dnu, n_points, kappa, accumulate);
+    switch (points_per_lane) {
+    case 2: return launch_wing<2>(wing, ranges, n_tiles, nu_min, dnu, n_points, kappa, accumulate, s);
+    case 4: return launch_wing<4>(wing, ranges, n_tiles, nu_min, dnu, n_points, kappa, accumulate, s);
+    case 8: return launch_wing<8>(wing, ranges, n_tiles, nu_min, dnu, n_points, kappa, accumulate, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_core_f64(const WingRec* wing, const CoreRec* core, const int64_t* ranges,
+                           int64_t n_tiles, double nu_min, double dnu, int32_t n_points,
+                           double* kappa, hipStream_t s)
+{
+    if (n_tiles == 0) return hipSuccess;
+    core_f64_kernel<4><<<dim3((unsigned)n_tiles), dim3(64 * kWaves), 0, s>>>(
+        wing, core, ranges, n_tiles, nu_min, dnu, n_points, kappa);
     return hipGetLastError();
 }
 
