@@ -25,26 +25,34 @@ constexpr double kGH1R2 = 1.0e6;
 
 // Per-line record of the binary64 wing evaluation, one per line and state,
 // in line order.  With alpha = Gamma_D / sqrt(ln 2) the Doppler 1/e width,
-// Gamma = Gamma_L and dv = nu_j - nu0:
-//   1-node:  S Phi = Lg / (dv^2 + G2)
-//   3-node:  S Phi = (Lg/3) (2 P + E D0) / (D0 P),
-//            D0 = dv^2 + G2, E = D0 + h, P = E^2 - c6 dv^2,
-// which is the 3-node Gauss-Hermite sum (weights 2/3, 1/6, 1/6 of the
-// Lorentzians at nu0 and nu0 -+ sqrt(3/2) alpha) over one common
-// denominator.  The integer fields are grid-index intervals (closed; empty
-// when lo > hi): the cutoff window and the points whose a^2+u^2 lies below
-// 1e6 and below 100.
+// G = Gamma_L, dv = nu_j - nu0 and q = dv^2:
+//   1-node:  S Phi = Lg / (q + G2)                       (a Lorentzian)
+//   3-node:  S Phi = (Lg/3) n / (D P),  D = q + G2,
+//            P = q^2 + B q + C,  n = 3 q^2 + Bn q + Cn,
+// the 3-node Gauss-Hermite sum (weights 2/3, 1/6, 1/6 of the Lorentzians at
+// nu0 and nu0 -+ sqrt(3/2) alpha) over one common denominator, expanded in
+// q: with GH = G2 + 1.5 alpha^2, P = (q + GH)^2 - 6 alpha^2 q is the product
+// of the two shifted Lorentzians' denominators and n = 2P + D (q + GH).
+// Coefficients: B = 2 G2 - 3 alpha^2, C = GH^2, Bn = 6 G2 - 4.5 alpha^2,
+// Cn = GH (2 GH + G2).  Where a^2 + u^2 >= 100, q + G2 >= 100 alpha^2, so
+// the negative parts of B and Bn never cancel q's terms.
+// The integer fields are grid-index intervals (closed; empty when lo > hi):
+// the cutoff window, the points whose a^2+u^2 lies below 1e6 and below 100.
 struct alignas(16) WingRec {
     double nu0;  // pressure-shifted line centre
     double Lg;   // S(T) Gamma_L / pi
     double G2;   // Gamma_L^2
-    double h;    // 1.5 alpha^2
-    double c6;   // 6 alpha^2
+    double B, C, Bn, Cn;
     int32_t wlo, whi;
     int32_t g3lo, g3hi;
     int32_t clo, chi;
+    int32_t flags;  // kPairSafe
+    int32_t pad[3];
 };
-static_assert(sizeof(WingRec) == 64, "WingRec layout");
+static_assert(sizeof(WingRec) == 96, "WingRec layout");
+// Products of two denominators stay in binary64 range (alpha^2 > 1e-40,
+// Gamma_L^2 < 1e20: every physical line); otherwise points are not paired.
+constexpr int32_t kPairSafe = 1;
 
 // Per-line record of the core-region series, read only for lines whose
 // a^2+u^2 < 100 interval meets a wavefront's points.

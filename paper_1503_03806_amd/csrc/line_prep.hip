@@ -81,8 +81,16 @@ __global__ __launch_bounds__(256) void line_prep_f64_kernel(LinesDev L, PrepPara
     w.nu0 = nu0;
     w.Lg = S * GL * kInvPi;
     w.G2 = GL * GL;
-    w.h = 1.5 * alpha * alpha;
-    w.c6 = 6.0 * alpha * alpha;
+    {
+        const double a2 = alpha * alpha;
+        const double GH = w.G2 + 1.5 * a2;
+        w.B = 2.0 * w.G2 - 3.0 * a2;
+        w.C = GH * GH;
+        w.Bn = 6.0 * w.G2 - 4.5 * a2;
+        w.Cn = GH * (2.0 * GH + w.G2);
+        w.flags = (a2 > 1e-40 && w.G2 < 1e20) ? kPairSafe : 0;
+        w.pad[0] = w.pad[1] = w.pad[2] = 0;
+    }
     const int32_t n = pp.n_points;
     {
         double flo = ceil((nu0 - pp.cutoff - pp.nu_min) / pp.dnu);

@@ -46,62 +46,59 @@ __device__ inline double qrcp(double den)
     return fma(r, fma(-den, r, 1.0), r);
 }
 
-// Tiles are dispatched dearest first (high wavenumber: wider Doppler cores,
-// more 3-node points), so the cheap tiles fill the tail of the launch.
-__device__ inline int64_t tile_of(int64_t b, int64_t nb) { return nb - 1 - b; }
+// Workgroups go round-robin over the 8 XCDs, each with its own L2.  The
+// rank order r = 0, 1, ... visits tiles dearest first (high wavenumber: wider
+// Doppler cores, more 3-node points), so cheap tiles fill the launch's tail;
+// ranks are dealt to XCDs in chunks of kChunk consecutive tiles, so an XCD's
+// neighbouring tiles, which read mostly the same lines, share its L2, while
+// every XCD gets a mix of dear and cheap chunks.  The grid is padded to a
+// multiple of 8 * kChunk blocks; blocks past the last tile exit at once.
+constexpr int kChunk = 32;
+__device__ inline int64_t tile_of(int64_t b, int64_t n_tiles)
+{
+    const int64_t x = b & 7, k = b >> 3;
+    const int64_t r = ((k / kChunk) * 8 + x) * kChunk + (k % kChunk);
+    return r < n_tiles ? n_tiles - 1 - r : -1;
+}
+int64_t padded_blocks(int64_t n_tiles)
+{
+    const int64_t g = 8 * kChunk;
+    return (n_tiles + g - 1) / g * g;
+}
 
-// The path of one line for the points [run0, run1] of a wavefront.  The
-// paired reciprocals need the products of two denominators in binary64
-// range: alpha^2 > 1e-40 and Gamma_L^2 < 1e20 cover every physical line
-// (alpha ~ 4e-6 nu at 1500 K); other lines take the general path unpaired.
-__device__ inline bool pair_safe(const WingRec& r) { return r.h > 1.5e-40 && r.G2 < 1e20; }
-
-// run1 is the run's last grid point; a run cut short by the grid end
-// (run1 < run_end) always takes the general path, which evaluates points
-// whose pair partner lies beyond the grid unpaired.
+// The path of one line for the points [run0, run1] of a wavefront; run_end
+// is the run's nominal last point.  A run cut short by the grid end takes
+// the general path, which evaluates points whose pair partner lies beyond
+// the grid unpaired.
 __device__ inline uint32_t classify(const WingRec& r, int32_t run0, int32_t run1, int32_t run_end)
 {
     if (run0 > run1 || r.whi < run0 || r.wlo > run1) return kSkip;
     if (run1 < run_end) return kGeneral;
     const bool full = r.wlo <= run0 && r.whi >= run1;
     const bool nocore = run1 < r.clo || run0 > r.chi;
-    if (!(full && nocore && pair_safe(r))) return kGeneral;
+    if (!(full && nocore && (r.flags & kPairSafe))) return kGeneral;
     if (run1 < r.g3lo || run0 > r.g3hi) return kGH1;
     if (r.g3lo <= run0 && r.g3hi >= run1) return kGH3;
     return kGeneral;
 }
 
-// S Phi = num / den of one point, dv = nu_j - nu0.
-// 1-node rule: S G/(pi (dv^2 + G^2)).
-__device__ inline void gh1_terms(double dv, double G2, double Lg, double& num, double& den)
-{
-    num = Lg;
-    den = fma(dv, dv, G2);
-}
-// 3-node rule: the three weighted Lorentzians over a common denominator
-// (Lg/3) (2P + E D0) / (D0 P).
-__device__ inline void gh3_terms(double dv, double G2, double h, double c6, double Lg3, double& num,
-                                 double& den)
+// 3-node rule of one point: S Phi = (Lg/3) n / m with q = dv^2,
+// n = 3q^2 + Bn q + Cn, m = (q + G2)(q^2 + B q + C).
+__device__ inline void gh3_nm(double dv, double G2, double B, double C, double Bn, double Cn,
+                              double& n, double& m)
 {
     const double q = dv * dv;
-    const double D0 = q + G2;
-    const double E = D0 + h;
-    const double P = fma(E, E, -c6 * q);
-    num = Lg3 * fma(D0, E, P + P);
-    den = D0 * P;
+    n = fma(q, fma(3.0, q, Bn), Cn);
+    m = (q + G2) * fma(q, q + B, C);
 }
 
-// Two points share one reciprocal: 1/da = db / (da db).  Point j pairs with
-// j + 64 when floor(j / 64) is even (runs start at multiples of 128), so a
-// point's value is the same bits whichever path or tile shape computes it.
-__device__ inline void pair_add(double& acc_a, double& acc_b, double na, double da, double nb,
-                                double db, bool ta, bool tb)
-{
-    const double c = qrcp(da * db);
-    acc_a = fma(ta ? c * db : 0.0, na, acc_a);
-    acc_b = fma(tb ? c * da : 0.0, nb, acc_b);
-}
-
+// Points pair up to share one reciprocal: 1/da = db / (da db).  Point j
+// pairs with j + 64 when floor(j / 64) is even (runs start at multiples of
+// 128), and each pair type has one fixed sequence of operations, so a
+// point's value has the same bits whichever path or tile shape computes it:
+//   both 1-node:  c = rcp(Da Db) Lg;           acc += c Db
+//   both 3-node:  c = rcp(ma mb) (Lg/3);       acc += (c mb) na
+//   mixed:        c = rcp(den_a den_b);        acc += (c den_b) (L_a num_a)
 template <int kP>
 __global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
     const WingRec* __restrict__ wing, const int64_t* __restrict__ ranges, int64_t n_tiles,
@@ -111,8 +108,9 @@ __global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ WingRec tile[kTL];
     __shared__ uint32_t code[kTL];
-    const int64_t t = tile_of(blockIdx.x, gridDim.x);
-    const int wave = threadIdx.x >> 6;
+    const int64_t t = tile_of(blockIdx.x, n_tiles);
+    if (t < 0) return;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int32_t tile0 = (int32_t)(t * kTilePoints);
     const int32_t run0 = tile0 + wave * 64 * kP;
@@ -144,61 +142,79 @@ __global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
         }
         __syncthreads();
         for (int k = 0; k < cnt; ++k) {
-            const uint32_t path =
-                (uint32_t)__builtin_amdgcn_readfirstlane((int)code[k]) >> (8 * wave) & 0xffu;
+            const uint32_t path = ((uint32_t)__builtin_amdgcn_readfirstlane((int)code[k]) >> (8 * wave)) & 0xffu;
             if (path == kSkip) continue;
             const double nu0 = tile[k].nu0, Lg = tile[k].Lg, G2 = tile[k].G2;
             if (path == kGH1) {
 #pragma unroll
                 for (int p = 0; p < kP; p += 2) {
-                    double na, da, nb, db;
-                    gh1_terms(nuj[p] - nu0, G2, Lg, na, da);
-                    gh1_terms(nuj[p + 1] - nu0, G2, Lg, nb, db);
-                    pair_add(acc[p], acc[p + 1], na, da, nb, db, true, true);
+                    const double da = nuj[p] - nu0, db = nuj[p + 1] - nu0;
+                    const double Da = fma(da, da, G2), Db = fma(db, db, G2);
+                    const double c = qrcp(Da * Db) * Lg;
+                    acc[p] = fma(c, Db, acc[p]);
+                    acc[p + 1] = fma(c, Da, acc[p + 1]);
                 }
                 continue;
             }
-            const double h = tile[k].h, c6 = tile[k].c6;
+            const double B = tile[k].B, C = tile[k].C, Bn = tile[k].Bn, Cn = tile[k].Cn;
             const double Lg3 = Lg * (1.0 / 3.0);
             if (path == kGH3) {
 #pragma unroll
                 for (int p = 0; p < kP; p += 2) {
-                    double na, da, nb, db;
-                    gh3_terms(nuj[p] - nu0, G2, h, c6, Lg3, na, da);
-                    gh3_terms(nuj[p + 1] - nu0, G2, h, c6, Lg3, nb, db);
-                    pair_add(acc[p], acc[p + 1], na, da, nb, db, true, true);
+                    double na, ma, nb, mb;
+                    gh3_nm(nuj[p] - nu0, G2, B, C, Bn, Cn, na, ma);
+                    gh3_nm(nuj[p + 1] - nu0, G2, B, C, Bn, Cn, nb, mb);
+                    const double c = qrcp(ma * mb) * Lg3;
+                    acc[p] = fma(c * mb, na, acc[p]);
+                    acc[p + 1] = fma(c * ma, nb, acc[p + 1]);
                 }
                 continue;
             }
             // general path: window edges, region edges, core points (left to
-            // the core kernel), lines outside the pairing range
+            // the core kernel), the grid end, lines outside the pairing range
             const int32_t wlo = tile[k].wlo, whi = tile[k].whi;
             const int32_t g3lo = tile[k].g3lo, g3hi = tile[k].g3hi;
             const int32_t clo = tile[k].clo, chi = tile[k].chi;
-            const bool safe = pair_safe(tile[k]);
+            const bool safe = (tile[k].flags & kPairSafe) != 0;
 #pragma unroll
             for (int p = 0; p < kP; p += 2) {
                 double num[2], den[2];
-                bool take[2], core_pt[2];
+                bool take[2], one[2], core_pt[2];
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const int32_t j = run0 + lane + 64 * (p + e);
                     const double dv = nuj[p + e] - nu0;
-                    double n1, d1, n3, d3;
-                    gh1_terms(dv, G2, Lg, n1, d1);
-                    gh3_terms(dv, G2, h, c6, Lg3, n3, d3);
-                    const bool one = j < g3lo || j > g3hi;
+                    double n3, m3;
+                    gh3_nm(dv, G2, B, C, Bn, Cn, n3, m3);
+                    one[e] = j < g3lo || j > g3hi;
                     core_pt[e] = j >= clo && j <= chi;
                     take[e] = j >= wlo && j <= whi && !core_pt[e];
-                    num[e] = one ? n1 : n3;
-                    den[e] = one ? d1 : d3;
+                    num[e] = one[e] ? Lg : n3;  // n3 is scaled by Lg/3 below
+                    den[e] = one[e] ? fma(dv, dv, G2) : m3;
                 }
                 if (safe && !core_pt[0] && !core_pt[1] && run0 + lane + 64 * (p + 1) < n) {
-                    pair_add(acc[p], acc[p + 1], num[0], den[0], num[1], den[1], take[0], take[1]);
+                    const double c0 = qrcp(den[0] * den[1]);
+                    double xa, ya, xb, yb;
+                    if (one[0] && one[1]) {
+                        const double c = c0 * Lg;
+                        xa = c; ya = den[1];
+                        xb = c; yb = den[0];
+                    } else if (!one[0] && !one[1]) {
+                        const double c = c0 * Lg3;
+                        xa = c * den[1]; ya = num[0];
+                        xb = c * den[0]; yb = num[1];
+                    } else {
+                        xa = c0 * den[1]; ya = one[0] ? Lg : Lg3 * num[0];
+                        xb = c0 * den[0]; yb = one[1] ? Lg : Lg3 * num[1];
+                    }
+                    acc[p] = fma(take[0] ? xa : 0.0, ya, acc[p]);
+                    acc[p + 1] = fma(take[1] ? xb : 0.0, yb, acc[p + 1]);
                 } else {
-                    const double va = qdiv(num[0], den[0]), vb = qdiv(num[1], den[1]);
-                    acc[p] += take[0] ? va : 0.0;
-                    acc[p + 1] += take[1] ? vb : 0.0;
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const double v = qdiv(one[e] ? Lg : Lg3 * num[e], den[e]);
+                        acc[p + e] += take[e] ? v : 0.0;
+                    }
                 }
             }
         }
@@ -261,7 +277,7 @@ __global__ __launch_bounds__(64 * kWaves) void core_f64_kernel(
 {
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ double inv_tab[kWaves][kMaxTerms];
-    const int64_t t = tile_of(blockIdx.x, gridDim.x);
+    const int64_t t = n_tiles - 1 - (int64_t)blockIdx.x;  // dearest tiles first
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int32_t run0 = (int32_t)(t * kTilePoints) + wave * 64 * kP;
@@ -316,7 +332,7 @@ template <int kP>
 hipError_t launch_wing(const WingRec* wing, const int64_t* ranges, int64_t n_tiles, double nu_min,
                        double dnu, int32_t n, double* kappa, int accumulate, hipStream_t s)
 {
-    wing_f64_kernel<kP><<<dim3((unsigned)n_tiles), dim3(64 * kWaves), 0, s>>>(
+    wing_f64_kernel<kP><<<dim3((unsigned)padded_blocks(n_tiles)), dim3(64 * kWaves), 0, s>>>(
         wing, ranges, n_tiles, nu_min, dnu, n, kappa, accumulate);
     return hipGetLastError();
 }
