@@ -57,7 +57,7 @@ struct hk_ctx {
     hk_species species{296.0, 0.0};
     DevBuf lines;  // 8 arrays of n doubles
     // per-state records and tile ranges
-    DevBuf wing, core, ranges, ranges_core;
+    DevBuf wing, widx, core, ranges, ranges_core;
     DevBuf partial;
     DevBuf kscratch;
     bool have_run = false;
@@ -235,6 +235,7 @@ int hk_destroy(hk_ctx* ctx)
     (void)hipStreamSynchronize(ctx->stream);
     ctx->lines.release();
     ctx->wing.release();
+    ctx->widx.release();
     ctx->core.release();
     ctx->ranges.release();
     ctx->ranges_core.release();
@@ -353,6 +354,7 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
 
     const size_t nb = (size_t)std::max<int64_t>(n, 1);
     HK_HIP(ctx, ctx->wing.ensure(nb * sizeof(WingRec)), "allocating line records");
+    HK_HIP(ctx, ctx->widx.ensure(nb * sizeof(WingIdx)), "allocating line records");
     HK_HIP(ctx, ctx->core.ensure(nb * sizeof(CoreRec)), "allocating line records");
     const int ppl = ctx->f64_points_per_lane;
     const int32_t tp = opacity_f64_tile_points(ppl);
@@ -375,6 +377,7 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
     L.A21 = ctx->has_A ? lines_field(ctx, 7) : nullptr;
     L.n = n;
     WingRec* wing = static_cast<WingRec*>(ctx->wing.p);
+    WingIdx* widx = static_cast<WingIdx*>(ctx->widx.p);
     CoreRec* core = static_cast<CoreRec*>(ctx->core.p);
     int64_t* ranges = static_cast<int64_t*>(ctx->ranges.p);
     // a line can reach a tile only if its unshifted centre is within
@@ -389,7 +392,7 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
 
     {
         StageTimer tm(ctx, HK_STAGE_LINE_PREP);
-        HK_HIP(ctx, launch_line_prep_f64(L, pp, wing, core, ctx->stream), "line_prep_f64");
+        HK_HIP(ctx, launch_line_prep_f64(L, pp, wing, widx, core, ctx->stream), "line_prep_f64");
         HK_HIP(ctx, launch_tile_ranges(L.nu, n, n_tiles, tp, grid->nu_min, grid->dnu, np, reach, ranges,
                                        ctx->stream),
                "tile_ranges");
@@ -400,14 +403,14 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
     }
     {
         StageTimer tm(ctx, HK_STAGE_OPACITY);
-        HK_HIP(ctx, launch_wing_f64(ppl, wing, ranges, n_tiles, grid->nu_min, grid->dnu, np,
+        HK_HIP(ctx, launch_wing_f64(ppl, wing, widx, ranges, n_tiles, grid->nu_min, grid->dnu, np,
                                     static_cast<double*>(kappa), accumulate ? 1 : 0, ctx->stream),
                "wing_f64");
         tm.stop();
     }
     {
         StageTimer tm(ctx, HK_STAGE_CORE);
-        HK_HIP(ctx, launch_core_f64(wing, core, ranges_c, n_tiles_c, grid->nu_min, grid->dnu, np,
+        HK_HIP(ctx, launch_core_f64(wing, widx, core, ranges_c, n_tiles_c, grid->nu_min, grid->dnu, np,
                                     static_cast<double*>(kappa), ctx->stream),
                "core_f64");
         tm.stop();
@@ -449,7 +452,7 @@ int hk_stats(hk_ctx* ctx, hk_run_stats* out)
     const int32_t nblk = 256;
     HK_HIP(ctx, ctx->partial.ensure((size_t)nblk * 3 * sizeof(int64_t)), "allocating counters");
     if (ctx->n_lines > 0) {
-        HK_HIP(ctx, launch_eval_counts(static_cast<WingRec*>(ctx->wing.p), ctx->n_lines,
+        HK_HIP(ctx, launch_eval_counts(static_cast<WingIdx*>(ctx->widx.p), ctx->n_lines,
                                        static_cast<int64_t*>(ctx->partial.p), nblk, ctx->stream),
                "eval_counts");
         std::vector<int64_t> h((size_t)nblk * 3);

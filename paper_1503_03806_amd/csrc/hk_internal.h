@@ -27,29 +27,33 @@ constexpr double kGH1R2 = 1.0e6;
 // in line order.  With alpha = Gamma_D / sqrt(ln 2) the Doppler 1/e width,
 // G = Gamma_L, dv = nu_j - nu0 and q = dv^2:
 //   1-node:  S Phi = Lg / (q + G2)                       (a Lorentzian)
-//   3-node:  S Phi = (Lg/3) n / (D P),  D = q + G2,
-//            P = q^2 + B q + C,  n = 3 q^2 + Bn q + Cn,
+//   3-node:  S Phi = Lg n / (D P),  D = q + G2,
+//            P = q (q + B) + C,  n = q (q + Bn) + Cn,
 // the 3-node Gauss-Hermite sum (weights 2/3, 1/6, 1/6 of the Lorentzians at
 // nu0 and nu0 -+ sqrt(3/2) alpha) over one common denominator, expanded in
 // q: with GH = G2 + 1.5 alpha^2, P = (q + GH)^2 - 6 alpha^2 q is the product
-// of the two shifted Lorentzians' denominators and n = 2P + D (q + GH).
-// Coefficients: B = 2 G2 - 3 alpha^2, C = GH^2, Bn = 6 G2 - 4.5 alpha^2,
-// Cn = GH (2 GH + G2).  Where a^2 + u^2 >= 100, q + G2 >= 100 alpha^2, so
+// of the two shifted Lorentzians' denominators and 3n = 2P + D (q + GH).
+// Coefficients: B = 2 G2 - 3 alpha^2, C = GH^2, Bn = 2 G2 - 1.5 alpha^2,
+// Cn = GH (2 GH + G2) / 3.  Where a^2 + u^2 >= 100, q + G2 >= 100 alpha^2, so
 // the negative parts of B and Bn never cancel q's terms.
-// The integer fields are grid-index intervals (closed; empty when lo > hi):
-// the cutoff window, the points whose a^2+u^2 lies below 1e6 and below 100.
+// The grid-index intervals (closed; empty when lo > hi) sit in WingIdx: the
+// cutoff window and the points whose a^2+u^2 lies below 1e6 and below 100.
 struct alignas(16) WingRec {
     double nu0;  // pressure-shifted line centre
     double Lg;   // S(T) Gamma_L / pi
     double G2;   // Gamma_L^2
     double B, C, Bn, Cn;
+    double pad;
+};
+static_assert(sizeof(WingRec) == 64, "WingRec layout");
+struct alignas(16) WingIdx {
     int32_t wlo, whi;
     int32_t g3lo, g3hi;
     int32_t clo, chi;
     int32_t flags;  // kPairSafe
-    int32_t pad[3];
+    int32_t pad;
 };
-static_assert(sizeof(WingRec) == 96, "WingRec layout");
+static_assert(sizeof(WingIdx) == 32, "WingIdx layout");
 // Products of two denominators stay in binary64 range (alpha^2 > 1e-40,
 // Gamma_L^2 < 1e20: every physical line); otherwise points are not paired.
 constexpr int32_t kPairSafe = 1;
@@ -97,7 +101,7 @@ struct GValues {
 
 // ---- launches (stream-ordered, no synchronisation) ----
 hipError_t launch_line_prep_f64(const LinesDev& L, const PrepParams& pp, WingRec* wing,
-                                CoreRec* core, hipStream_t s);
+                                WingIdx* idx, CoreRec* core, hipStream_t s);
 hipError_t launch_tile_ranges(const double* nu_sorted, int64_t n_lines, int64_t n_tiles,
                               int32_t tile_points, double nu_min, double dnu, int32_t n_points,
                               double reach, int64_t* ranges, hipStream_t s);
@@ -105,13 +109,15 @@ hipError_t launch_tile_ranges(const double* nu_sorted, int64_t n_lines, int64_t 
 // 8), the core kernel then adds the series terms.
 int32_t opacity_f64_tile_points(int points_per_lane);
 int32_t core_f64_tile_points();
-hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const int64_t* ranges,
+hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingIdx* idx,
+                           const int64_t* ranges,
                            int64_t n_tiles, double nu_min, double dnu, int32_t n_points,
                            double* kappa, int accumulate, hipStream_t s);
-hipError_t launch_core_f64(const WingRec* wing, const CoreRec* core, const int64_t* ranges,
+hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRec* core,
+                           const int64_t* ranges,
                            int64_t n_tiles, double nu_min, double dnu, int32_t n_points,
                            double* kappa, hipStream_t s);
-hipError_t launch_eval_counts(const WingRec* wing, int64_t n_lines, int64_t* partial,
+hipError_t launch_eval_counts(const WingIdx* idx, int64_t n_lines, int64_t* partial,
                               int32_t n_blocks, hipStream_t s);
 
 // k-distribution.  elem_bytes 8 (binary64 keys) or 4 (binary32 keys).

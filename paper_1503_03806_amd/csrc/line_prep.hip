@@ -53,6 +53,7 @@ __device__ void region_interval(double R, double nu_min, double dnu, int32_t n, 
 
 __global__ __launch_bounds__(256) void line_prep_f64_kernel(LinesDev L, PrepParams pp,
                                                             WingRec* __restrict__ wing,
+                                                            WingIdx* __restrict__ idx,
                                                             CoreRec* __restrict__ core)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -78,6 +79,7 @@ __global__ __launch_bounds__(256) void line_prep_f64_kernel(LinesDev L, PrepPara
     const double nu0 = __dadd_rn(nu, __dmul_rn(delta, pp.P));
 
     WingRec w;
+    WingIdx x;
     w.nu0 = nu0;
     w.Lg = S * GL * kInvPi;
     w.G2 = GL * GL;
@@ -86,10 +88,11 @@ __global__ __launch_bounds__(256) void line_prep_f64_kernel(LinesDev L, PrepPara
         const double GH = w.G2 + 1.5 * a2;
         w.B = 2.0 * w.G2 - 3.0 * a2;
         w.C = GH * GH;
-        w.Bn = 6.0 * w.G2 - 4.5 * a2;
-        w.Cn = GH * (2.0 * GH + w.G2);
-        w.flags = (a2 > 1e-40 && w.G2 < 1e20) ? kPairSafe : 0;
-        w.pad[0] = w.pad[1] = w.pad[2] = 0;
+        w.Bn = 2.0 * w.G2 - 1.5 * a2;
+        w.Cn = GH * (2.0 * GH + w.G2) * (1.0 / 3.0);
+        w.pad = 0.0;
+        x.flags = (a2 > 1e-40 && w.G2 < 1e20) ? kPairSafe : 0;
+        x.pad = 0;
     }
     const int32_t n = pp.n_points;
     {
@@ -98,26 +101,27 @@ __global__ __launch_bounds__(256) void line_prep_f64_kernel(LinesDev L, PrepPara
         flo = fmax(flo, 0.0);
         fhi = fmin(fhi, (double)(n - 1));
         if (!(flo <= fhi)) {
-            w.wlo = 1;
-            w.whi = 0;
+            x.wlo = 1;
+            x.whi = 0;
         } else {
-            w.wlo = (int32_t)flo;
-            w.whi = (int32_t)fhi;
+            x.wlo = (int32_t)flo;
+            x.whi = (int32_t)fhi;
         }
     }
     const double invA = 1.0 / alpha;
     const double y = GL * invA;
     const double y2 = y * y;
-    region_interval(kGH1R2, pp.nu_min, pp.dnu, n, nu0, invA, y2, &w.g3lo, &w.g3hi);
-    region_interval(kCoreR2, pp.nu_min, pp.dnu, n, nu0, invA, y2, &w.clo, &w.chi);
+    region_interval(kGH1R2, pp.nu_min, pp.dnu, n, nu0, invA, y2, &x.g3lo, &x.g3hi);
+    region_interval(kCoreR2, pp.nu_min, pp.dnu, n, nu0, invA, y2, &x.clo, &x.chi);
     wing[i] = w;
+    idx[i] = x;
 
     CoreRec c;
     c.invA = invA;
     c.y = y;
     c.y2 = y2;
     c.norm = S * invA * kInvSqrtPi;
-    if (w.clo <= w.chi) {
+    if (x.clo <= x.chi) {
         c.ex = erfcx(y);
         double t1 = 0.0;
         for (int k = 1; k <= 40; ++k) {
@@ -175,14 +179,14 @@ __device__ inline int64_t overlap(int64_t alo, int64_t ahi, int64_t blo, int64_t
 }
 
 // Per-block partial sums of (evals, core, below 1e6) over lines.
-__global__ __launch_bounds__(256) void eval_counts_kernel(const WingRec* __restrict__ wing,
+__global__ __launch_bounds__(256) void eval_counts_kernel(const WingIdx* __restrict__ idx,
                                                           int64_t n, int64_t* __restrict__ partial)
 {
     __shared__ int64_t red[3][256];
     int64_t e = 0, c = 0, g = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        WingRec w = wing[i];
+        const WingIdx w = idx[i];
         if (w.wlo > w.whi) continue;
         e += w.whi - w.wlo + 1;
         c += overlap(w.wlo, w.whi, w.clo, w.chi);
@@ -206,11 +210,11 @@ __global__ __launch_bounds__(256) void eval_counts_kernel(const WingRec* __restr
 }  // namespace
 
 hipError_t launch_line_prep_f64(const LinesDev& L, const PrepParams& pp, WingRec* wing,
-                                CoreRec* core, hipStream_t s)
+                                WingIdx* idx, CoreRec* core, hipStream_t s)
 {
     if (L.n == 0) return hipSuccess;
     int64_t blocks = (L.n + 255) / 256;
-    line_prep_f64_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(L, pp, wing, core);
+    line_prep_f64_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(L, pp, wing, idx, core);
     return hipGetLastError();
 }
 
@@ -225,10 +229,10 @@ hipError_t launch_tile_ranges(const double* nu_sorted, int64_t n_lines, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_eval_counts(const WingRec* wing, int64_t n_lines, int64_t* partial,
+hipError_t launch_eval_counts(const WingIdx* idx, int64_t n_lines, int64_t* partial,
                               int32_t n_blocks, hipStream_t s)
 {
-    eval_counts_kernel<<<dim3(n_blocks), dim3(256), 0, s>>>(wing, n_lines, partial);
+    eval_counts_kernel<<<dim3(n_blocks), dim3(256), 0, s>>>(idx, n_lines, partial);
     return hipGetLastError();
 }
 

@@ -70,7 +70,7 @@ int64_t padded_blocks(int64_t n_tiles)
 // is the run's nominal last point.  A run cut short by the grid end takes
 // the general path, which evaluates points whose pair partner lies beyond
 // the grid unpaired.
-__device__ inline uint32_t classify(const WingRec& r, int32_t run0, int32_t run1, int32_t run_end)
+__device__ inline uint32_t classify(const WingIdx& r, int32_t run0, int32_t run1, int32_t run_end)
 {
     if (run0 > run1 || r.whi < run0 || r.wlo > run1) return kSkip;
     if (run1 < run_end) return kGeneral;
@@ -82,13 +82,13 @@ __device__ inline uint32_t classify(const WingRec& r, int32_t run0, int32_t run1
     return kGeneral;
 }
 
-// 3-node rule of one point: S Phi = (Lg/3) n / m with q = dv^2,
-// n = 3q^2 + Bn q + Cn, m = (q + G2)(q^2 + B q + C).
+// 3-node rule of one point: S Phi = Lg n / m with q = dv^2,
+// n = q (q + Bn) + Cn, m = (q + G2)(q (q + B) + C).
 __device__ inline void gh3_nm(double dv, double G2, double B, double C, double Bn, double Cn,
                               double& n, double& m)
 {
     const double q = dv * dv;
-    n = fma(q, fma(3.0, q, Bn), Cn);
+    n = fma(q, q + Bn, Cn);
     m = (q + G2) * fma(q, q + B, C);
 }
 
@@ -97,16 +97,19 @@ __device__ inline void gh3_nm(double dv, double G2, double B, double C, double B
 // 128), and each pair type has one fixed sequence of operations, so a
 // point's value has the same bits whichever path or tile shape computes it:
 //   both 1-node:  c = rcp(Da Db) Lg;           acc += c Db
-//   both 3-node:  c = rcp(ma mb) (Lg/3);       acc += (c mb) na
-//   mixed:        c = rcp(den_a den_b);        acc += (c den_b) (L_a num_a)
+//   both 3-node:  c = rcp(ma mb) Lg;           acc += (c mb) na
+//   mixed:        c = rcp(den_a den_b) Lg;     acc += (c den_b) num_a
+// (num = 1 for a 1-node point).
 template <int kP>
 __global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
-    const WingRec* __restrict__ wing, const int64_t* __restrict__ ranges, int64_t n_tiles,
-    double nu_min, double dnu, int32_t n, double* __restrict__ kappa, int accumulate)
+    const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
+    const int64_t* __restrict__ ranges, int64_t n_tiles, double nu_min, double dnu, int32_t n,
+    double* __restrict__ kappa, int accumulate)
 {
     static_assert(kP % 2 == 0, "points are processed in pairs");
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ WingRec tile[kTL];
+    __shared__ WingIdx tidx[kTL];
     __shared__ uint32_t code[kTL];
     const int64_t t = tile_of(blockIdx.x, n_tiles);
     if (t < 0) return;
@@ -129,8 +132,9 @@ __global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
         const int cnt = (int)min((int64_t)kTL, L1 - base);
         // stage one record per thread and decide its path for each wavefront
         if ((int)threadIdx.x < cnt) {
-            const WingRec r = wing[base + threadIdx.x];
-            tile[threadIdx.x] = r;
+            tile[threadIdx.x] = wing[base + threadIdx.x];
+            const WingIdx r = idx[base + threadIdx.x];
+            tidx[threadIdx.x] = r;
             uint32_t c = 0;
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) {
@@ -157,14 +161,13 @@ __global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
                 continue;
             }
             const double B = tile[k].B, C = tile[k].C, Bn = tile[k].Bn, Cn = tile[k].Cn;
-            const double Lg3 = Lg * (1.0 / 3.0);
             if (path == kGH3) {
 #pragma unroll
                 for (int p = 0; p < kP; p += 2) {
                     double na, ma, nb, mb;
                     gh3_nm(nuj[p] - nu0, G2, B, C, Bn, Cn, na, ma);
                     gh3_nm(nuj[p + 1] - nu0, G2, B, C, Bn, Cn, nb, mb);
-                    const double c = qrcp(ma * mb) * Lg3;
+                    const double c = qrcp(ma * mb) * Lg;
                     acc[p] = fma(c * mb, na, acc[p]);
                     acc[p + 1] = fma(c * ma, nb, acc[p + 1]);
                 }
@@ -172,10 +175,10 @@ __global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
             }
             // general path: window edges, region edges, core points (left to
             // the core kernel), the grid end, lines outside the pairing range
-            const int32_t wlo = tile[k].wlo, whi = tile[k].whi;
-            const int32_t g3lo = tile[k].g3lo, g3hi = tile[k].g3hi;
-            const int32_t clo = tile[k].clo, chi = tile[k].chi;
-            const bool safe = (tile[k].flags & kPairSafe) != 0;
+            const int32_t wlo = tidx[k].wlo, whi = tidx[k].whi;
+            const int32_t g3lo = tidx[k].g3lo, g3hi = tidx[k].g3hi;
+            const int32_t clo = tidx[k].clo, chi = tidx[k].chi;
+            const bool safe = (tidx[k].flags & kPairSafe) != 0;
 #pragma unroll
             for (int p = 0; p < kP; p += 2) {
                 double num[2], den[2];
@@ -189,7 +192,7 @@ __global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
                     one[e] = j < g3lo || j > g3hi;
                     core_pt[e] = j >= clo && j <= chi;
                     take[e] = j >= wlo && j <= whi && !core_pt[e];
-                    num[e] = one[e] ? Lg : n3;  // n3 is scaled by Lg/3 below
+                    num[e] = one[e] ? 1.0 : n3;
                     den[e] = one[e] ? fma(dv, dv, G2) : m3;
                 }
                 if (safe && !core_pt[0] && !core_pt[1] && run0 + lane + 64 * (p + 1) < n) {
@@ -199,20 +202,17 @@ __global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
                         const double c = c0 * Lg;
                         xa = c; ya = den[1];
                         xb = c; yb = den[0];
-                    } else if (!one[0] && !one[1]) {
-                        const double c = c0 * Lg3;
+                    } else {
+                        const double c = c0 * Lg;
                         xa = c * den[1]; ya = num[0];
                         xb = c * den[0]; yb = num[1];
-                    } else {
-                        xa = c0 * den[1]; ya = one[0] ? Lg : Lg3 * num[0];
-                        xb = c0 * den[0]; yb = one[1] ? Lg : Lg3 * num[1];
                     }
                     acc[p] = fma(take[0] ? xa : 0.0, ya, acc[p]);
                     acc[p + 1] = fma(take[1] ? xb : 0.0, yb, acc[p + 1]);
                 } else {
 #pragma unroll
                     for (int e = 0; e < 2; ++e) {
-                        const double v = qdiv(one[e] ? Lg : Lg3 * num[e], den[e]);
+                        const double v = qdiv(Lg * num[e], den[e]);
                         acc[p + e] += take[e] ? v : 0.0;
                     }
                 }
@@ -271,9 +271,9 @@ __device__ double voigt_core(double x, double y, double ex, double T1, const dou
 // (a rotation of the wavefront) to be added there.  kappa_j += the run's sum.
 template <int kP>
 __global__ __launch_bounds__(64 * kWaves) void core_f64_kernel(
-    const WingRec* __restrict__ wing, const CoreRec* __restrict__ core,
-    const int64_t* __restrict__ ranges, int64_t n_tiles, double nu_min, double dnu, int32_t n,
-    double* __restrict__ kappa)
+    const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
+    const CoreRec* __restrict__ core, const int64_t* __restrict__ ranges, int64_t n_tiles,
+    double nu_min, double dnu, int32_t n, double* __restrict__ kappa)
 {
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ double inv_tab[kWaves][kMaxTerms];
@@ -291,8 +291,8 @@ __global__ __launch_bounds__(64 * kWaves) void core_f64_kernel(
 
     const int64_t L0 = ranges[2 * t], L1 = ranges[2 * t + 1];
     for (int64_t i = L0; i < L1; ++i) {
-        const int32_t a = max(max(wing[i].clo, wing[i].wlo), run0);
-        const int32_t b = min(min(wing[i].chi, wing[i].whi), run1);
+        const int32_t a = max(max(idx[i].clo, idx[i].wlo), run0);
+        const int32_t b = min(min(idx[i].chi, idx[i].whi), run1);
         if (a > b) continue;
         any = true;
         const double nu0 = wing[i].nu0;
@@ -329,11 +329,12 @@ __global__ __launch_bounds__(64 * kWaves) void core_f64_kernel(
 }
 
 template <int kP>
-hipError_t launch_wing(const WingRec* wing, const int64_t* ranges, int64_t n_tiles, double nu_min,
-                       double dnu, int32_t n, double* kappa, int accumulate, hipStream_t s)
+hipError_t launch_wing(const WingRec* wing, const WingIdx* idx, const int64_t* ranges,
+                       int64_t n_tiles, double nu_min, double dnu, int32_t n, double* kappa,
+                       int accumulate, hipStream_t s)
 {
     wing_f64_kernel<kP><<<dim3((unsigned)padded_blocks(n_tiles)), dim3(64 * kWaves), 0, s>>>(
-        wing, ranges, n_tiles, nu_min, dnu, n, kappa, accumulate);
+        wing, idx, ranges, n_tiles, nu_min, dnu, n, kappa, accumulate);
     return hipGetLastError();
 }
 
@@ -342,26 +343,26 @@ hipError_t launch_wing(const WingRec* wing, const int64_t* ranges, int64_t n_til
 int32_t opacity_f64_tile_points(int points_per_lane) { return 64 * points_per_lane * kWaves; }
 int32_t core_f64_tile_points() { return 64 * 4 * kWaves; }
 
-hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const int64_t* ranges,
-                           int64_t n_tiles, double nu_min, double dnu, int32_t n_points,
-                           double* kappa, int accumulate, hipStream_t s)
+hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingIdx* idx,
+                           const int64_t* ranges, int64_t n_tiles, double nu_min, double dnu,
+                           int32_t n_points, double* kappa, int accumulate, hipStream_t s)
 {
     if (n_tiles == 0) return hipSuccess;
     switch (points_per_lane) {
-    case 2: return launch_wing<2>(wing, ranges, n_tiles, nu_min, dnu, n_points, kappa, accumulate, s);
-    case 4: return launch_wing<4>(wing, ranges, n_tiles, nu_min, dnu, n_points, kappa, accumulate, s);
-    case 8: return launch_wing<8>(wing, ranges, n_tiles, nu_min, dnu, n_points, kappa, accumulate, s);
+    case 2: return launch_wing<2>(wing, idx, ranges, n_tiles, nu_min, dnu, n_points, kappa, accumulate, s);
+    case 4: return launch_wing<4>(wing, idx, ranges, n_tiles, nu_min, dnu, n_points, kappa, accumulate, s);
+    case 8: return launch_wing<8>(wing, idx, ranges, n_tiles, nu_min, dnu, n_points, kappa, accumulate, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_core_f64(const WingRec* wing, const CoreRec* core, const int64_t* ranges,
-                           int64_t n_tiles, double nu_min, double dnu, int32_t n_points,
-                           double* kappa, hipStream_t s)
+hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRec* core,
+                           const int64_t* ranges, int64_t n_tiles, double nu_min, double dnu,
+                           int32_t n_points, double* kappa, hipStream_t s)
 {
     if (n_tiles == 0) return hipSuccess;
     core_f64_kernel<4><<<dim3((unsigned)n_tiles), dim3(64 * kWaves), 0, s>>>(
-        wing, core, ranges, n_tiles, nu_min, dnu, n_points, kappa);
+        wing, idx, core, ranges, n_tiles, nu_min, dnu, n_points, kappa);
     return hipGetLastError();
 }
 
