@@ -51,7 +51,7 @@ typedef struct hk_ctx hk_ctx;
 typedef enum {
     HK_F64 = 0,        /* everything in binary64 */
     HK_F32_KAHAN = 1   /* binary32 profiles, compensated binary32 sums;
-                          line strengths and g in binary64 */
+                          line strengths, widths and outputs in binary64 */
 } hk_precision;
 
 /* Line list, §2.3 (the HITRAN/HITEMP fields the method uses).  [host]
@@ -146,11 +146,16 @@ int hk_load_lines(hk_ctx* ctx, const hk_lines* lines, const hk_species* species)
  * index) order, with no atomics: results are bitwise reproducible and do not
  * depend on the tuning options.
  *
- * precision HK_F64: kappa is [device] double[n_points]; comp must be NULL.
- * precision HK_F32_KAHAN: kappa is [device] float[n_points] and comp a
- *   [device] float[n_points] compensation term (kappa + comp is the value).
- * accumulate != 0 adds to the values already in kappa (and comp), e.g. to
- * process a line list in chunks; accumulate == 0 overwrites them. */
+ * kappa is [device] double[n_points] for both precisions; comp must be NULL
+ * (reserved).
+ * precision HK_F64: every step in binary64.
+ * precision HK_F32_KAHAN: S(T), widths, windows and region intervals in
+ *   binary64; profiles in binary32 with strengths scaled by a per-state power
+ *   of two; each point's terms summed in binary32 blocks of at most 256 lines
+ *   whose sums are added with Kahan compensation; the compensated sum is
+ *   scaled back and stored in binary64.  Requires cutoff/dnu < 2^23.
+ * accumulate != 0 adds to the values already in kappa, e.g. to process a
+ * line list in chunks; accumulate == 0 overwrites them. */
 int hk_opacity(hk_ctx* ctx, const hk_state* state, const hk_grid* grid,
                int precision, void* kappa, void* comp, int accumulate);
 
@@ -160,8 +165,8 @@ int hk_opacity(hk_ctx* ctx, const hk_state* state, const hk_grid* grid,
  * cumulative coordinate g_i = (i+1)/M of the i-th smallest of the bin's M
  * values (eq. (14) with eq. (15)'s uniform step 1/N_nu), and resample
  * k(g_q) = kappa_sorted[ceil(g_q M) - 1] at the requested g values.
- * kappa: [device] double (HK_F64) or float (HK_F32_KAHAN) [n_points], all
- * values >= 0 (a NaN sorts last).  k_out: [device] double[n_bins][n_g] with
+ * kappa: [device] double (HK_F64) or float (HK_F32_KAHAN: binary32 keys)
+ * [n_points], all values >= 0 (a NaN sorts last).  k_out: [device] double[n_bins][n_g] with
  * n_bins = ceil(n_points / points_per_bin).  sorted_out: NULL, or [device]
  * array of kappa's type [n_points] receiving each bin sorted in place order
  * (the k-distribution function kappa(y) of §2.1.1). */
@@ -177,6 +182,7 @@ int hk_gauss_legendre(int32_t n, double* g, double* w);
 /* Tuning knobs (results do not depend on them; only speed does):
  *   "f64_points_per_lane"  2, 4 or 8 grid points per lane in the binary64
  *                          opacity kernel (default 4).
+ *   "f32_points_per_lane"  the same for the binary32 kernel (default 4).
  * Unknown names or values: HK_EINVAL. */
 int hk_set_option(hk_ctx* ctx, const char* name, int64_t value);
 

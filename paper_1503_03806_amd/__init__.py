@@ -251,13 +251,10 @@ class Context:
                 accumulate: bool = False):
         torch = self._torch
         n = int(grid["n_points"])
-        dt = torch.float64 if precision == HK_F64 else torch.float32
         if out is None:
-            out = torch.empty(max(n, 1), dtype=dt, device="cuda:%d" % self.device)[:n]
-        if precision == HK_F32_KAHAN and comp is None:
-            comp = torch.zeros(max(n, 1), dtype=dt, device="cuda:%d" % self.device)[:n]
+            out = torch.empty(max(n, 1), dtype=torch.float64, device="cuda:%d" % self.device)[:n]
         hk_opacity(self.h, state, grid, precision, out, comp, accumulate)
-        return out if precision == HK_F64 else (out, comp)
+        return out
 
     def kdist(self, kappa, points_per_bin: int, g, precision: int = HK_F64, sorted_out=None):
         torch = self._torch

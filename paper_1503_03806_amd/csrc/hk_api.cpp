@@ -54,14 +54,18 @@ struct hk_ctx {
     bool has_self = false, has_delta = false, has_A = false;
     double max_abs_delta = 0.0;
     double nu_max = 0.0;  // largest line centre (bounds the Doppler core widths)
+    double last_P = 0.0;  // pressure of the state being computed
     hk_species species{296.0, 0.0};
     DevBuf lines;  // 8 arrays of n doubles
     // per-state records and tile ranges
     DevBuf wing, widx, core, ranges, ranges_core;
     DevBuf partial;
     DevBuf kscratch;
+    // binary32 path: records, Kahan pair, scale
+    DevBuf w32, c32, f32sum, f32comp, f32scale, f32partial;
     bool have_run = false;
     int f64_points_per_lane = 4;  // tile shape of the binary64 opacity kernel
+    int f32_points_per_lane = 4;  // tile shape of the binary32 opacity kernel
     // stage timing: events recorded around each timed launch, resolved
     // lazily (pending pairs) so timing adds no host synchronisation
     bool timing = false;
@@ -241,6 +245,8 @@ int hk_destroy(hk_ctx* ctx)
     ctx->ranges_core.release();
     ctx->partial.release();
     ctx->kscratch.release();
+    for (DevBuf* b : {&ctx->w32, &ctx->c32, &ctx->f32sum, &ctx->f32comp, &ctx->f32scale, &ctx->f32partial})
+        b->release();
     for (auto& p : ctx->pending) {
         (void)hipEventDestroy(p.second.first);
         (void)hipEventDestroy(p.second.second);
@@ -320,6 +326,66 @@ int hk_load_lines(hk_ctx* ctx, const hk_lines* L, const hk_species* sp)
     return HK_OK;
 }
 
+// Binary32 profiles with compensated binary32 sums, after the binary64 line
+// preparation: scale, binary32 records, tile ranges, wing and core kernels,
+// then kappa = (sum + comp) 2^-s in binary64.
+static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, WingRec* wing, WingIdx* widx, CoreRec* core,
+                       const int64_t* ranges_c, int64_t n_tiles_c, double* kappa, int accumulate)
+{
+    const int64_t n = ctx->n_lines;
+    const int32_t np = (int32_t)grid->n_points;
+    const size_t nb = (size_t)std::max<int64_t>(n, 1);
+    const int32_t nblk = 256;
+    HK_HIP(ctx, ctx->w32.ensure(nb * sizeof(WingRec32)), "allocating binary32 records");
+    HK_HIP(ctx, ctx->c32.ensure(nb * sizeof(CoreRec32)), "allocating binary32 records");
+    HK_HIP(ctx, ctx->f32sum.ensure((size_t)std::max(np, 1) * sizeof(float)), "allocating binary32 sums");
+    HK_HIP(ctx, ctx->f32comp.ensure((size_t)std::max(np, 1) * sizeof(float)), "allocating binary32 sums");
+    HK_HIP(ctx, ctx->f32scale.ensure(sizeof(int32_t)), "allocating the scale");
+    HK_HIP(ctx, ctx->f32partial.ensure((size_t)nblk * sizeof(double)), "allocating the scale");
+    WingRec32* w32 = static_cast<WingRec32*>(ctx->w32.p);
+    CoreRec32* c32 = static_cast<CoreRec32*>(ctx->c32.p);
+    float* fs = static_cast<float*>(ctx->f32sum.p);
+    float* fc = static_cast<float*>(ctx->f32comp.p);
+    int32_t* scale = static_cast<int32_t*>(ctx->f32scale.p);
+    const int ppl = ctx->f32_points_per_lane;
+    const int32_t tp = opacity_f32_tile_points(ppl);
+    const int64_t n_tiles = ((int64_t)np + tp - 1) / tp;
+    HK_HIP(ctx, ctx->ranges.ensure((size_t)std::max<int64_t>(n_tiles, 1) * 2 * sizeof(int64_t)),
+           "allocating tile ranges");
+    int64_t* ranges = static_cast<int64_t*>(ctx->ranges.p);
+    const double reach = grid->cutoff + ctx->max_abs_delta * ctx->last_P + 2.0 * grid->dnu;
+    {
+        StageTimer tm(ctx, HK_STAGE_LINE_PREP);
+        if (n > 0) {
+            HK_HIP(ctx, launch_f32_scale(wing, core, n, static_cast<double*>(ctx->f32partial.p), nblk, scale,
+                                         ctx->stream),
+                   "f32_scale");
+            HK_HIP(ctx, launch_line_prep_f32(wing, widx, core, n, grid->nu_min, grid->dnu, scale, w32, c32,
+                                             ctx->stream),
+                   "line_prep_f32");
+        } else {
+            HK_HIP(ctx, hipMemsetAsync(scale, 0, sizeof(int32_t), ctx->stream), "hipMemsetAsync");
+        }
+        HK_HIP(ctx, launch_tile_ranges(static_cast<double*>(ctx->lines.p), n, n_tiles, tp, grid->nu_min,
+                                       grid->dnu, np, reach, ranges, ctx->stream),
+               "tile_ranges");
+        tm.stop();
+    }
+    {
+        StageTimer tm(ctx, HK_STAGE_OPACITY);
+        HK_HIP(ctx, launch_wing_f32(ppl, w32, widx, ranges, n_tiles, np, fs, fc, ctx->stream), "wing_f32");
+        tm.stop();
+    }
+    {
+        StageTimer tm(ctx, HK_STAGE_CORE);
+        HK_HIP(ctx, launch_core_f32(widx, c32, ranges_c, n_tiles_c, np, fs, fc, ctx->stream), "core_f32");
+        HK_HIP(ctx, launch_f32_finish(fs, fc, scale, np, kappa, accumulate, ctx->stream), "f32_finish");
+        tm.stop();
+    }
+    ctx->have_run = true;
+    return HK_OK;
+}
+
 int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precision, void* kappa,
                void* comp, int accumulate)
 {
@@ -328,9 +394,9 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
     if (int rc = check_grid(ctx, grid)) return rc;
     if (precision != HK_F64 && precision != HK_F32_KAHAN)
         return fail(ctx, HK_EINVAL, "unknown precision %d", precision);
-    if (precision == HK_F32_KAHAN)
-        return fail(ctx, HK_EUNSUPPORTED, "HK_F32_KAHAN is not available in this build");
-    if (comp) return fail(ctx, HK_EINVAL, "comp must be NULL for HK_F64");
+    if (comp) return fail(ctx, HK_EINVAL, "comp must be NULL (kappa holds the result in binary64)");
+    if (precision == HK_F32_KAHAN && !(grid->cutoff / grid->dnu < 8388608.0))
+        return fail(ctx, HK_EINVAL, "HK_F32_KAHAN needs cutoff/dnu < 2^23 (got %g)", grid->cutoff / grid->dnu);
     if (grid->n_points > 0 && !kappa) return fail(ctx, HK_EINVAL, "kappa is NULL");
     if (int rc = check_ctx(ctx)) return rc;
     if (!ctx->lines_loaded) return fail(ctx, HK_ENOTREADY, "no line list loaded (call hk_load_lines first)");
@@ -351,6 +417,7 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
     pp.dnu = grid->dnu;
     pp.cutoff = grid->cutoff;
     pp.n_points = np;
+    ctx->last_P = st->P;
 
     const size_t nb = (size_t)std::max<int64_t>(n, 1);
     HK_HIP(ctx, ctx->wing.ensure(nb * sizeof(WingRec)), "allocating line records");
@@ -401,6 +468,8 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
                "tile_ranges");
         tm.stop();
     }
+    if (precision == HK_F32_KAHAN) return opacity_f32(ctx, grid, wing, widx, core, ranges_c, n_tiles_c,
+                                                      static_cast<double*>(kappa), accumulate);
     {
         StageTimer tm(ctx, HK_STAGE_OPACITY);
         HK_HIP(ctx, launch_wing_f64(ppl, wing, widx, ranges, n_tiles, grid->nu_min, grid->dnu, np,
@@ -477,11 +546,13 @@ int hk_stats(hk_ctx* ctx, hk_run_stats* out)
 int hk_set_option(hk_ctx* ctx, const char* name, int64_t value)
 {
     if (!name) return fail(ctx, HK_EINVAL, "option name is NULL");
-    if (std::strcmp(name, "f64_points_per_lane") == 0) {
+    const bool f64 = std::strcmp(name, "f64_points_per_lane") == 0;
+    const bool f32 = std::strcmp(name, "f32_points_per_lane") == 0;
+    if (f64 || f32) {
         if (value != 2 && value != 4 && value != 8)
-            return fail(ctx, HK_EINVAL, "f64_points_per_lane must be 2, 4 or 8 (got %lld)", (long long)value);
+            return fail(ctx, HK_EINVAL, "%s must be 2, 4 or 8 (got %lld)", name, (long long)value);
         if (int rc = check_ctx(ctx)) return rc;
-        ctx->f64_points_per_lane = (int)value;
+        (f64 ? ctx->f64_points_per_lane : ctx->f32_points_per_lane) = (int)value;
         return HK_OK;
     }
     return fail(ctx, HK_EINVAL, "unknown option '%s'", name);

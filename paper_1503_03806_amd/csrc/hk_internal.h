@@ -51,7 +51,7 @@ struct alignas(16) WingIdx {
     int32_t g3lo, g3hi;
     int32_t clo, chi;
     int32_t flags;  // kPairSafe
-    int32_t pad;
+    int32_t jc;     // nearest grid index to the centre (binary32 path)
 };
 static_assert(sizeof(WingIdx) == 32, "WingIdx layout");
 // Products of two denominators stay in binary64 range (alpha^2 > 1e-40,
@@ -70,6 +70,26 @@ struct alignas(16) CoreRec {
     double pad0, pad1;
 };
 static_assert(sizeof(CoreRec) == 64, "CoreRec layout");
+
+// Binary32 records of one line and state, derived from the binary64 ones
+// (so both precisions share S(T), widths, windows and region intervals).
+// Lengths are in units of lambda = alpha when the line has 3-node or core
+// points (y^2 < 1e6), else lambda = Gamma_L, which keeps every denominator
+// and product in binary32 range; strengths carry the state's scale 2^s.
+// For point j: dv/lambda = (j - jc) du - fu, with jc the nearest grid point
+// to the centre (WingIdx.jc), du = dnu/lambda, fu = (nu0 - nu_jc)/lambda.
+//   1-node:  Lg / (q + G2),  3-node:  Lg n / ((q + G2) P)  with q = (dv/lambda)^2
+// and the 3-node coefficients of WingRec scaled by lambda^-2 / lambda^-4.
+struct alignas(16) WingRec32 {
+    float du, fu, Lg, G2, B, C, Bn, Cn;
+};
+static_assert(sizeof(WingRec32) == 32, "WingRec32 layout");
+// Core series in x units: x = |(j - jc) dx - fx|, dx = dnu/alpha,
+// fx = (nu0 - nu_jc)/alpha; norm = 2^s S/(alpha sqrt(pi)).
+struct alignas(16) CoreRec32 {
+    float dx, fx, y, y2, ex, norm, T1, pad;
+};
+static_assert(sizeof(CoreRec32) == 32, "CoreRec32 layout");
 
 // Sorted line list on the device (structure of arrays, ascending nu).
 struct LinesDev {
@@ -119,6 +139,24 @@ hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRe
                            double* kappa, hipStream_t s);
 hipError_t launch_eval_counts(const WingIdx* idx, int64_t n_lines, int64_t* partial,
                               int32_t n_blocks, hipStream_t s);
+
+// Binary32 path: the state's scale exponent from the lines' peak heights
+// (two reductions into scale[0]), the record conversion, and the kernels.
+hipError_t launch_f32_scale(const WingRec* wing, const CoreRec* core, int64_t n_lines,
+                            double* partial, int32_t n_blocks, int32_t* scale, hipStream_t s);
+hipError_t launch_line_prep_f32(const WingRec* wing, WingIdx* idx, const CoreRec* core,
+                                int64_t n_lines, double nu_min, double dnu, const int32_t* scale,
+                                WingRec32* w32, CoreRec32* c32, hipStream_t s);
+int32_t opacity_f32_tile_points(int points_per_lane);
+hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const WingIdx* idx,
+                           const int64_t* ranges, int64_t n_tiles, int32_t n_points, float* sum,
+                           float* comp, hipStream_t s);
+hipError_t launch_core_f32(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges,
+                           int64_t n_tiles, int32_t n_points, float* sum, float* comp,
+                           hipStream_t s);
+// kappa (binary64) = (sum + comp) * 2^-s, or += when accumulating.
+hipError_t launch_f32_finish(const float* sum, const float* comp, const int32_t* scale,
+                             int32_t n_points, double* kappa, int accumulate, hipStream_t s);
 
 // k-distribution.  elem_bytes 8 (binary64 keys) or 4 (binary32 keys).
 int64_t kdist_lds_max_points(int elem_bytes, int64_t lds_bytes);

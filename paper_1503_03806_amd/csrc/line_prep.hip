@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void line_prep_f64_kernel(LinesDev L, PrepPara
         w.Cn = GH * (2.0 * GH + w.G2) * (1.0 / 3.0);
         w.pad = 0.0;
         x.flags = (a2 > 1e-40 && w.G2 < 1e20) ? kPairSafe : 0;
-        x.pad = 0;
+        x.jc = 0;
     }
     const int32_t n = pp.n_points;
     {
@@ -207,7 +207,125 @@ __global__ __launch_bounds__(256) void eval_counts_kernel(const WingIdx* __restr
     }
 }
 
+// Peak height of a line's profile times S: S min(1/(alpha sqrt(pi)),
+// 1/(pi Gamma_L)) bounds S Phi everywhere; per-block maxima.
+__global__ __launch_bounds__(256) void f32_peak_kernel(const WingRec* __restrict__ wing,
+                                                       const CoreRec* __restrict__ core, int64_t n,
+                                                       double* __restrict__ partial)
+{
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double doppler = core[i].norm;                     // S / (alpha sqrt(pi))
+        const double lorentz = wing[i].G2 > 0.0 ? wing[i].Lg / wing[i].G2 : doppler;  // S/(pi G)
+        m = fmax(m, fmin(doppler, lorentz));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + k]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// s = 100 - exponent(max peak): peaks land at or below 2^101, so sums of up
+// to 2^26 of them stay below binary32's 2^128.
+__global__ void f32_scale_kernel(const double* __restrict__ partial, int32_t n_blocks,
+                                 int32_t* __restrict__ scale)
+{
+    if (threadIdx.x != 0) return;
+    double m = 0.0;
+    for (int32_t b = 0; b < n_blocks; ++b) m = fmax(m, partial[b]);
+    scale[0] = m > 0.0 ? 100 - ilogb(m) : 0;
+}
+
+__global__ __launch_bounds__(256) void line_prep_f32_kernel(
+    const WingRec* __restrict__ wing, WingIdx* __restrict__ idx, const CoreRec* __restrict__ core,
+    int64_t n, double nu_min, double dnu, const int32_t* __restrict__ scale,
+    WingRec32* __restrict__ w32, CoreRec32* __restrict__ c32)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const WingRec w = wing[i];
+    const CoreRec c = core[i];
+    const int s = scale[0];
+    const double alpha = 1.0 / c.invA;
+    const double G = sqrt(w.G2);
+    const bool use_alpha = c.y2 < kGH1R2;  // the line has 3-node or core points
+    const double lam = use_alpha ? alpha : (G > 0.0 ? G : alpha);
+    const double il = 1.0 / lam;
+    // nearest grid point to the centre, clamped to int32 range
+    double fjc = rint((w.nu0 - nu_min) / dnu);
+    fjc = fmin(fmax(fjc, -1.0e9), 1.0e9);
+    const int32_t jc = (int32_t)fjc;
+    const double f = w.nu0 - fma((double)jc, dnu, nu_min);  // |f| <~ dnu/2
+    WingRec32 r;
+    r.du = (float)(dnu * il);
+    r.fu = (float)(f * il);
+    r.Lg = (float)ldexp(w.Lg * il * il, s);
+    r.G2 = (float)(w.G2 * il * il);
+    r.B = (float)(w.B * il * il);
+    r.C = (float)(w.C * il * il * il * il);
+    r.Bn = (float)(w.Bn * il * il);
+    r.Cn = (float)(w.Cn * il * il * il * il);
+    w32[i] = r;
+    idx[i].jc = jc;
+    CoreRec32 k;
+    k.dx = (float)(dnu * c.invA);
+    k.fx = (float)(f * c.invA);
+    k.y = (float)c.y;
+    k.y2 = (float)c.y2;
+    k.ex = (float)c.ex;
+    k.norm = (float)ldexp(c.norm, s);
+    k.T1 = (float)c.T1;
+    k.pad = 0.0f;
+    c32[i] = k;
+}
+
+__global__ __launch_bounds__(256) void f32_finish_kernel(const float* __restrict__ sum,
+                                                         const float* __restrict__ comp,
+                                                         const int32_t* __restrict__ scale,
+                                                         int32_t n, double* __restrict__ kappa,
+                                                         int accumulate)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double v = ldexp((double)sum[j] + (double)comp[j], -scale[0]);
+    kappa[j] = accumulate ? kappa[j] + v : v;
+}
+
 }  // namespace
+
+hipError_t launch_f32_scale(const WingRec* wing, const CoreRec* core, int64_t n_lines,
+                            double* partial, int32_t n_blocks, int32_t* scale, hipStream_t s)
+{
+    f32_peak_kernel<<<dim3(n_blocks), dim3(256), 0, s>>>(wing, core, n_lines, partial);
+    f32_scale_kernel<<<dim3(1), dim3(64), 0, s>>>(partial, n_blocks, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_line_prep_f32(const WingRec* wing, WingIdx* idx, const CoreRec* core,
+                                int64_t n_lines, double nu_min, double dnu, const int32_t* scale,
+                                WingRec32* w32, CoreRec32* c32, hipStream_t s)
+{
+    if (n_lines == 0) return hipSuccess;
+    const int64_t blocks = (n_lines + 255) / 256;
+    line_prep_f32_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(wing, idx, core, n_lines, nu_min,
+                                                                       dnu, scale, w32, c32);
+    return hipGetLastError();
+}
+
+hipError_t launch_f32_finish(const float* sum, const float* comp, const int32_t* scale,
+                             int32_t n_points, double* kappa, int accumulate, hipStream_t s)
+{
+    if (n_points == 0) return hipSuccess;
+    const int64_t blocks = ((int64_t)n_points + 255) / 256;
+    f32_finish_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(sum, comp, scale, n_points, kappa,
+                                                                    accumulate);
+    return hipGetLastError();
+}
 
 hipError_t launch_line_prep_f64(const LinesDev& L, const PrepParams& pp, WingRec* wing,
                                 WingIdx* idx, CoreRec* core, hipStream_t s)

@@ -1,0 +1,323 @@
+// opacity_f32.hip -- the "kappa(nu)" stage with binary32 profile evaluation
+// and compensated binary32 accumulation (§2.4, §2.5); line strengths, widths
+// and windows come from the binary64 line preparation.
+//
+// Same decomposition as the binary64 kernels (wavefront per run of 64*P
+// points, LDS-staged sorted lines, per-(line, wavefront) path decided once
+// per tile, series in its own kernel).  Differences:
+//  * offsets: dv/lambda = (j - jc) du - fu with an exact small-integer
+//    j - jc, so no large magnitudes cancel in binary32;
+//  * units: per line lambda = alpha or Gamma_L and a per-state power-of-two
+//    scale of the strengths keep every value in binary32 range;
+//  * reciprocals: the hardware v_rcp_f32 (< 2^-23 relative), unpaired;
+//  * accumulation: each point sums the lines of one 256-line block (blocks
+//    aligned to global line indices) in binary32, then adds the block sum to
+//    a Kahan pair (sum, comp).  With at most 256 positive terms per block the
+//    block sum is within 256 * 2^-24 = 1.5e-5 of exact in the worst case,
+//    the Kahan sum of blocks within ~2^-23 -- and the result does not depend
+//    on the tile shape.
+#include "hk_internal.h"
+
+namespace hk {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kTL = 64 * kWaves;  // 256 lines per LDS block, one per thread
+constexpr int kMaxTerms = 2 * 10 + 14;
+enum : uint32_t { kSkip = 0, kGH1 = 1, kGH3 = 2, kGeneral = 3 };
+
+constexpr int kChunk = 32;
+__device__ inline int64_t tile_of(int64_t b, int64_t n_tiles)
+{
+    const int64_t x = b & 7, k = b >> 3;
+    const int64_t r = ((k / kChunk) * 8 + x) * kChunk + (k % kChunk);
+    return r < n_tiles ? n_tiles - 1 - r : -1;
+}
+int64_t padded_blocks(int64_t n_tiles)
+{
+    const int64_t g = 8 * kChunk;
+    return (n_tiles + g - 1) / g * g;
+}
+
+__device__ inline uint32_t classify(const WingIdx& r, int32_t run0, int32_t run1)
+{
+    if (run0 > run1 || r.whi < run0 || r.wlo > run1) return kSkip;
+    const bool full = r.wlo <= run0 && r.whi >= run1;
+    const bool nocore = run1 < r.clo || run0 > r.chi;
+    if (!(full && nocore)) return kGeneral;
+    if (run1 < r.g3lo || run0 > r.g3hi) return kGH1;
+    if (r.g3lo <= run0 && r.g3hi >= run1) return kGH3;
+    return kGeneral;
+}
+
+__device__ inline float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Kahan step: (s, c) += x, with c the running correction (value = s - c).
+__device__ inline void kahan_add(float& s, float& c, float x)
+{
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+template <int kP>
+__global__ __launch_bounds__(64 * kWaves) void wing_f32_kernel(
+    const WingRec32* __restrict__ wing, const WingIdx* __restrict__ idx,
+    const int64_t* __restrict__ ranges, int64_t n_tiles, int32_t n, float* __restrict__ sum_out,
+    float* __restrict__ comp_out)
+{
+    constexpr int kTilePoints = 64 * kP * kWaves;
+    __shared__ WingRec32 tile[kTL];
+    __shared__ WingIdx tidx[kTL];
+    __shared__ uint32_t code[kTL];
+    const int64_t t = tile_of(blockIdx.x, n_tiles);
+    if (t < 0) return;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int32_t tile0 = (int32_t)(t * kTilePoints);
+    const int32_t run0 = tile0 + wave * 64 * kP;
+
+    float fj[kP], s[kP], c[kP], part[kP];
+#pragma unroll
+    for (int p = 0; p < kP; ++p) {
+        fj[p] = (float)(run0 - tile0 + lane + 64 * p);  // exact: < 2^12
+        s[p] = 0.0f;
+        c[p] = 0.0f;
+        part[p] = 0.0f;
+    }
+
+    const int64_t L0 = ranges[2 * t], L1 = ranges[2 * t + 1];
+    for (int64_t base = L0 & ~(int64_t)(kTL - 1); base < L1; base += kTL) {
+        const int cnt = (int)min((int64_t)kTL, L1 - base);
+        if ((int)threadIdx.x < cnt) {
+            tile[threadIdx.x] = wing[base + threadIdx.x];
+            const WingIdx r = idx[base + threadIdx.x];
+            tidx[threadIdx.x] = r;
+            uint32_t cw = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                const int32_t r0 = tile0 + w * 64 * kP;
+                const int32_t r1 = min(r0 + 64 * kP, n) - 1;
+                cw |= classify(r, r0, r1) << (8 * w);
+            }
+            code[threadIdx.x] = cw;
+        }
+        __syncthreads();
+        for (int k = 0; k < cnt; ++k) {
+            const uint32_t path = ((uint32_t)__builtin_amdgcn_readfirstlane((int)code[k]) >> (8 * wave)) & 0xffu;
+            if (path == kSkip) continue;
+            const float fjc = (float)(tidx[k].jc - tile0);  // exact: |.| < 2^24
+            const float du = tile[k].du, fu = tile[k].fu, Lg = tile[k].Lg, G2 = tile[k].G2;
+            if (path == kGH1) {
+#pragma unroll
+                for (int p = 0; p < kP; ++p) {
+                    const float dv = fmaf(fj[p] - fjc, du, -fu);
+                    part[p] = fmaf(Lg, rcpf(fmaf(dv, dv, G2)), part[p]);
+                }
+                continue;
+            }
+            const float B = tile[k].B, C = tile[k].C, Bn = tile[k].Bn, Cn = tile[k].Cn;
+            if (path == kGH3) {
+#pragma unroll
+                for (int p = 0; p < kP; ++p) {
+                    const float dv = fmaf(fj[p] - fjc, du, -fu);
+                    const float q = dv * dv;
+                    const float nn = fmaf(q, q + Bn, Cn);
+                    const float m = (q + G2) * fmaf(q, q + B, C);
+                    part[p] = fmaf(Lg, nn * rcpf(m), part[p]);
+                }
+                continue;
+            }
+            const int32_t wlo = tidx[k].wlo, whi = tidx[k].whi;
+            const int32_t g3lo = tidx[k].g3lo, g3hi = tidx[k].g3hi;
+            const int32_t clo = tidx[k].clo, chi = tidx[k].chi;
+#pragma unroll
+            for (int p = 0; p < kP; ++p) {
+                const int32_t j = run0 + lane + 64 * p;
+                const bool take = j >= wlo && j <= whi && (j < clo || j > chi);
+                const bool one = j < g3lo || j > g3hi;
+                const float dv = fmaf(fj[p] - fjc, du, -fu);
+                const float q = dv * dv;
+                const float v1 = rcpf(fmaf(dv, dv, G2));
+                const float nn = fmaf(q, q + Bn, Cn);
+                const float m = (q + G2) * fmaf(q, q + B, C);
+                const float v3 = nn * rcpf(m);
+                const float acc = fmaf(Lg, one ? v1 : v3, part[p]);
+                part[p] = take ? acc : part[p];
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < kP; ++p) {
+            kahan_add(s[p], c[p], part[p]);
+            part[p] = 0.0f;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int p = 0; p < kP; ++p) {
+        const int32_t j = run0 + lane + 64 * p;
+        if (j < n) {
+            sum_out[j] = s[p];
+            comp_out[j] = -c[p];
+        }
+    }
+}
+
+// The core series in binary32 (see voigt_core in opacity_f64.hip for the
+// formula).  e^{-(n/2 - x)^2} underflows binary32 at n = 1 for x near 10, so
+// its recurrence starts at the largest term n0 = round(2x) and runs both
+// ways; the e^{-(n/2 + x)^2} terms are below e^{-x^2} and run forward from
+// n = 1 (where they underflow they are negligible against the result).
+__device__ float voigt_core_f32(float x, float y, float ex, float T1, const float* inv)
+{
+    const float d = 0.60653065971263342f;  // e^{-1/2}
+    // x < 10 in the core region; the clamp guards the table against the
+    // binary32 rounding of x near 10
+    const int N = min(2 * (int)ceilf(x) + 14, kMaxTerms);
+    const float E = expf(-x * x);
+    int n0 = (int)rintf(2.0f * x);
+    n0 = n0 < 1 ? 1 : (n0 > N ? N : n0);
+    const float h0 = 0.5f * (float)n0 - x;
+    const float g0 = expf(-h0 * h0);
+    float s3 = 0.0f;
+    {  // n = n0, n0-1, ..., 1: g(n-1) = g(n) e^{n/2 - 1/4 - x}
+        float g = g0, q = expf(h0 - 0.25f);
+        for (int n = n0; n >= 1; --n) {
+            s3 = fmaf(g, inv[n - 1], s3);
+            g *= q;
+            q *= d;
+        }
+    }
+    {  // n = n0+1, ..., N: g(n+1) = g(n) e^{x - 1/4 - n/2}
+        float r = expf(-h0 - 0.25f);
+        float g = g0 * r;
+        r *= d;
+        for (int n = n0 + 1; n <= N; ++n) {
+            s3 = fmaf(g, inv[n - 1], s3);
+            g *= r;
+            r *= d;
+        }
+    }
+    float s2 = 0.0f;
+    {  // e^{-(n/2 + x)^2}, n = 1 .. N
+        const float c = 0.77880078307140487f;  // e^{-1/4}
+        const float dn = expf(-x);
+        float g = E * dn * c, r = dn * c * d;
+        for (int n = 1; n <= N; ++n) {
+            s2 = fmaf(g, inv[n - 1], s2);
+            g *= r;
+            r *= d;
+        }
+    }
+    float sn, cs;
+    sincosf(x * y, &sn, &cs);
+    const float cos2 = (cs - sn) * (cs + sn);
+    const float sy = (y > 0.0f) ? sn / y : x;
+    const float inv_pi = 0.31830988618379067f;
+    return E * fmaf(ex, cos2, sn * sy * inv_pi) + (y * inv_pi) * fmaf(-cos2 * E, T1, 0.5f * (s2 + s3));
+}
+
+// Core-region terms: as core_f64_kernel (point ownership, compacted 64-point
+// chunks of the line's core interval, lane rotation); the run's ordered
+// binary32 core sum is added to the Kahan pair written by the wing kernel.
+template <int kP>
+__global__ __launch_bounds__(64 * kWaves) void core_f32_kernel(
+    const WingIdx* __restrict__ idx, const CoreRec32* __restrict__ core,
+    const int64_t* __restrict__ ranges, int64_t n_tiles, int32_t n, float* __restrict__ sum,
+    float* __restrict__ comp)
+{
+    constexpr int kTilePoints = 64 * kP * kWaves;
+    __shared__ float inv_tab[kWaves][kMaxTerms];
+    const int64_t t = n_tiles - 1 - (int64_t)blockIdx.x;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int32_t run0 = (int32_t)(t * kTilePoints) + wave * 64 * kP;
+    const int32_t run1 = min(run0 + 64 * kP, n) - 1;
+    if (run0 > run1) return;
+    float* inv = inv_tab[wave];
+    float acc[kP];
+#pragma unroll
+    for (int p = 0; p < kP; ++p) acc[p] = 0.0f;
+    bool any = false;
+
+    const int64_t L0 = ranges[2 * t], L1 = ranges[2 * t + 1];
+    for (int64_t i = L0; i < L1; ++i) {
+        const int32_t a = max(max(idx[i].clo, idx[i].wlo), run0);
+        const int32_t b = min(min(idx[i].chi, idx[i].whi), run1);
+        if (a > b) continue;
+        any = true;
+        const int32_t jc = idx[i].jc;
+        const CoreRec32 cr = core[i];
+        if (lane < kMaxTerms) {
+            const float m = 0.5f * (float)(lane + 1);
+            inv[lane] = 1.0f / fmaf(m, m, cr.y2);
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int32_t c0 = a; c0 <= b; c0 += 64) {
+            const int32_t j = c0 + lane;
+            float v = 0.0f;
+            if (j <= b) {
+                const float x = fabsf(fmaf((float)(j - jc), cr.dx, -cr.fx));
+                v = cr.norm * voigt_core_f32(x, cr.y, cr.ex, cr.T1, inv);
+            }
+            const int src = (lane - (c0 - run0)) & 63;
+            const float w = __shfl(v, src, 64);
+            const int32_t jo = c0 + src;
+            const int slot = (jo - run0 - lane) >> 6;
+#pragma unroll
+            for (int p = 0; p < kP; ++p) acc[p] += (jo <= b && slot == p) ? w : 0.0f;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (!any) return;
+#pragma unroll
+    for (int p = 0; p < kP; ++p) {
+        const int32_t j = run0 + lane + 64 * p;
+        if (j <= run1) {
+            float sv = sum[j], cv = -comp[j];
+            kahan_add(sv, cv, acc[p]);
+            sum[j] = sv;
+            comp[j] = -cv;
+        }
+    }
+}
+
+template <int kP>
+hipError_t launch_wing(const WingRec32* wing, const WingIdx* idx, const int64_t* ranges,
+                       int64_t n_tiles, int32_t n, float* sum, float* comp, hipStream_t s)
+{
+    wing_f32_kernel<kP><<<dim3((unsigned)padded_blocks(n_tiles)), dim3(64 * kWaves), 0, s>>>(
+        wing, idx, ranges, n_tiles, n, sum, comp);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int32_t opacity_f32_tile_points(int points_per_lane) { return 64 * points_per_lane * kWaves; }
+
+hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const WingIdx* idx,
+                           const int64_t* ranges, int64_t n_tiles, int32_t n_points, float* sum,
+                           float* comp, hipStream_t s)
+{
+    if (n_tiles == 0) return hipSuccess;
+    switch (points_per_lane) {
+    case 2: return launch_wing<2>(wing, idx, ranges, n_tiles, n_points, sum, comp, s);
+    case 4: return launch_wing<4>(wing, idx, ranges, n_tiles, n_points, sum, comp, s);
+    case 8: return launch_wing<8>(wing, idx, ranges, n_tiles, n_points, sum, comp, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_core_f32(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges,
+                           int64_t n_tiles, int32_t n_points, float* sum, float* comp,
+                           hipStream_t s)
+{
+    if (n_tiles == 0) return hipSuccess;
+    core_f32_kernel<4><<<dim3((unsigned)n_tiles), dim3(64 * kWaves), 0, s>>>(idx, core, ranges,
+                                                                               n_tiles, n_points,
+                                                                               sum, comp);
+    return hipGetLastError();
+}
+
+}  // namespace hk

@@ -117,7 +117,6 @@ __global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
     const int lane = threadIdx.x & 63;
     const int32_t tile0 = (int32_t)(t * kTilePoints);
     const int32_t run0 = tile0 + wave * 64 * kP;
-    const int32_t run1 = min(run0 + 64 * kP, n) - 1;  // last point of the run (inclusive)
 
     double nuj[kP], acc[kP];
 #pragma unroll
@@ -248,7 +247,7 @@ __device__ double voigt_core(double x, double y, double ex, double T1, const dou
     double g2 = E * dn * c;  // e^{-(1/2 + x)^2}
     double r3 = up * (c * d);
     double r2 = dn * (c * d);
-    const int N = 2 * (int)ceil(x) + 14;
+    const int N = min(2 * (int)ceil(x) + 14, kMaxTerms);  // x < 10 here
     double s23 = 0.0;
     for (int n = 0; n < N; ++n) {
         s23 = fma(g2 + g3, inv[n], s23);
