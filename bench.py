@@ -86,6 +86,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f32", action="store_true", help="skip the binary32 variant")
     ap.add_argument("--cpu-points", type=int, default=300000,
                     help="grid points in the oracle's timed sample")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -115,23 +116,31 @@ def main(argv=None):
     kappa = torch.empty(N, dtype=torch.float64, device="cuda")
     k_out = torch.empty((n_bins, w.n_g), dtype=torch.float64, device="cuda")
 
-    def step():
-        hk.hk_opacity(ctx.h, state, grid, hk.HK_F64, kappa)
-        hk.hk_kdist(ctx.h, kappa, hk.HK_F64, N, ppb, g, k_out)
+    def timed(precision, steps):
+        def step():
+            hk.hk_opacity(ctx.h, state, grid, precision, kappa)
+            hk.hk_kdist(ctx.h, kappa, hk.HK_F64, N, ppb, g, k_out)
+        for _ in range(a.warmup):
+            step()
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        tm = ctx.timing()
+        ctx.set_timing(False)
+        return elapsed, tm
 
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
+    # the binary32 + compensated-sum variant of the same step, reported beside
+    # the binary64 headline (its result differs from binary64 by ~1e-6)
+    f32_elapsed, f32_tm = (None, None)
+    if not a.no_f32:
+        f32_elapsed, f32_tm = timed(hk.HK_F32_KAHAN, max(1, a.steps // 2))
+    elapsed, tm = timed(hk.HK_F64, a.steps)
     st = ctx.stats()
-    ctx.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(a.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    tm = ctx.timing()
-    ctx.set_timing(False)
     if a.calib_copy_mib:
         n = a.calib_copy_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -166,6 +175,13 @@ def main(argv=None):
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(),
                      "flops_per_launch": flops, "launch_ms": op_ms},
     }
+    if f32_tm is not None:
+        f32_steps = max(1, a.steps // 2)
+        rec["f32_kahan"] = {
+            "value": evals * f32_steps / f32_elapsed, "unit": "evals/s",
+            "ms_per_step": 1e3 * f32_elapsed / f32_steps,
+            "stage_ms": {k: v[0] / max(v[1], 1) for k, v in f32_tm.items()},
+            "speedup_vs_f64": (1e3 * elapsed / a.steps) / (1e3 * f32_elapsed / f32_steps)}
     if not a.no_cpu_baseline:
         log("bench: timing the oracle on a sample")
         rec["cpu_baseline"] = cpu_baseline(w, a.cpu_points)

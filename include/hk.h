@@ -173,20 +173,54 @@ int hk_opacity(hk_ctx* ctx, const hk_state* state, const hk_grid* grid,
 int hk_kdist(hk_ctx* ctx, const void* kappa, int precision, int64_t n_points,
              const hk_bins* bins, double* k_out, void* sorted_out);
 
+/* Opacity tables over many thermodynamic states (§2.5: the k-distribution
+ * is repeated for every combination of temperature and pressure of the
+ * table).  For each states[i] the result equals hk_opacity(states[i], grid,
+ * precision) followed by hk_kdist of that opacity (binary64 keys), written to
+ *   k_out   [device] double [n_states][n_bins][bins->n_g],
+ *           n_bins = ceil(grid->n_points / bins->points_per_bin).
+ * The states are processed in batches: one batch's line records are prepared
+ * per state, then one persistent wing launch and one persistent series launch
+ * cover the (state, grid tile) work items of the whole batch, then the bins
+ * of each state are sorted.  The opacity grids of a batch stay in device
+ * scratch owned by the context (about n_lines * 96 B + n_points * 8 B per
+ * state in binary32, n_lines * 160 B + n_points * 8 B in binary64); the batch
+ * size is "tables_batch" states, or (0, the default) as many as fit in
+ * "tables_mem_mib".  On the first call for a (precision, line count, grid
+ * size, cutoff/dnu) the wing tile shape is chosen by timing 2, 4 and 8
+ * points per lane on up to four states ("tables_autotune", synchronises the
+ * stream once); the shapes give identical results.  precision: HK_F64 or
+ * HK_F32_KAHAN (cutoff/dnu < 2^23).  Errors: HK_EINVAL (argument, with the
+ * index of a bad state), HK_ENOTREADY (no line list), HK_ENOMEM/HK_EDEVICE.
+ * hk_stats afterwards reports the evaluation counts summed over the states. */
+int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_grid* grid,
+              const hk_bins* bins, int precision, double* k_out);
+
 /* ---- helpers -------------------------------------------------------------- */
 
 /* Gauss-Legendre nodes and weights mapped to (0, 1): [host] g[n], w[n],
  * nodes ascending, weights summing to 1.  n in 1 .. 256. */
 int hk_gauss_legendre(int32_t n, double* g, double* w);
 
-/* Tuning knobs (results do not depend on them; only speed does):
+/* Tuning knobs (results do not depend on them; only speed and memory do):
  *   "f64_points_per_lane"  2, 4 or 8 grid points per lane in the binary64
- *                          opacity kernel (default 4).
- *   "f32_points_per_lane"  the same for the binary32 kernel (default 4).
+ *                          opacity kernel (default 2).
+ *   "f32_points_per_lane"  the same for the binary32 kernel (default 2).
+ *   "tables_batch"         states per hk_tables launch, 0 = automatic
+ *                          (default).
+ *   "tables_mem_mib"       device scratch budget of an automatic batch
+ *                          (default 32768).
+ *   "tables_autotune"      1 (default): hk_tables times the tile shapes;
+ *                          0: it uses the *_points_per_lane setting and the
+ *                          cached choices are dropped.
  * Unknown names or values: HK_EINVAL. */
 int hk_set_option(hk_ctx* ctx, const char* name, int64_t value);
+/* Reads a knob into *value; also "tables_points_per_lane", the tile shape
+ * the last hk_tables call used (0 before any). */
+int hk_get_option(hk_ctx* ctx, const char* name, int64_t* value);
 
-/* Evaluation counts of the last hk_opacity call (synchronises the stream). */
+/* Evaluation counts of the last hk_opacity call, or summed over the states
+ * of the last hk_tables call (synchronises the stream). */
 int hk_stats(hk_ctx* ctx, hk_run_stats* out);
 
 /* Per-stage device time, measured with HIP events recorded on the context's

@@ -18,7 +18,7 @@ __all__ = ["HK_OK", "HK_EINVAL", "HK_ENOMEM", "HK_EDEVICE", "HK_EUNSUPPORTED", "
            "HK_F64", "HK_F32_KAHAN", "HK_MAX_G", "HKError", "lib", "hk_version", "hk_create",
            "hk_destroy", "hk_set_stream", "hk_sync", "hk_last_error", "hk_load_lines",
            "hk_opacity", "hk_kdist", "hk_gauss_legendre", "hk_stats", "hk_set_timing",
-           "hk_get_timing", "hk_set_option", "Context", "LIB_PATH"]
+           "hk_get_timing", "hk_set_option", "hk_get_option", "hk_tables", "Context", "LIB_PATH"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhk.so")
 
@@ -99,6 +99,10 @@ def lib():
         L.hk_stats.argtypes = [vp, C.POINTER(hk_run_stats)]; L.hk_stats.restype = i32
         L.hk_set_timing.argtypes = [vp, i32]; L.hk_set_timing.restype = i32
         L.hk_set_option.argtypes = [vp, C.c_char_p, i64]; L.hk_set_option.restype = i32
+        L.hk_get_option.argtypes = [vp, C.c_char_p, C.POINTER(i64)]; L.hk_get_option.restype = i32
+        L.hk_tables.argtypes = [vp, C.POINTER(hk_state), C.c_int32, C.POINTER(hk_grid),
+                                C.POINTER(hk_bins), i32, vp]
+        L.hk_tables.restype = i32
         L.hk_get_timing.argtypes = [vp, C.POINTER(hk_timing)]; L.hk_get_timing.restype = i32
         _lib = L
     return _lib
@@ -190,6 +194,17 @@ def hk_kdist(ctx, kappa, precision: int, n_points: int, points_per_bin: int, g, 
                           _ptr(k_out), _ptr(sorted_out)), ctx)
 
 
+def hk_tables(ctx, states, grid: dict, points_per_bin: int, g, precision: int, k_out):
+    """states: sequence of state dicts; k_out: device tensor
+    [len(states)][n_bins][len(g)] of float64."""
+    arr = (hk_state * max(len(states), 1))(*[_state(s) for s in states])
+    gr = _grid(grid)
+    gg = _f64(g)
+    b = hk_bins(int(points_per_bin), len(gg), gg.ctypes.data_as(_pd))
+    _check(lib().hk_tables(ctx, arr, len(states), C.byref(gr), C.byref(b), int(precision),
+                           _ptr(k_out)), ctx)
+
+
 def hk_gauss_legendre(n: int):
     g = np.empty(n); w = np.empty(n)
     _check(lib().hk_gauss_legendre(int(n), g.ctypes.data_as(_pd), w.ctypes.data_as(_pd)))
@@ -204,6 +219,12 @@ def hk_stats(ctx) -> dict:
 
 def hk_set_option(ctx, name: str, value: int):
     _check(lib().hk_set_option(ctx, name.encode(), int(value)), ctx)
+
+
+def hk_get_option(ctx, name: str) -> int:
+    v = C.c_int64(0)
+    _check(lib().hk_get_option(ctx, name.encode(), C.byref(v)), ctx)
+    return int(v.value)
 
 
 def hk_set_timing(ctx, enable: bool):
@@ -265,6 +286,17 @@ class Context:
         hk_kdist(self.h, kappa, precision, n, points_per_bin, g, k, sorted_out)
         return k
 
+    def tables(self, states, grid: dict, points_per_bin: int, g, precision: int = HK_F32_KAHAN,
+               out=None):
+        torch = self._torch
+        n = int(grid["n_points"])
+        n_bins = -(-n // points_per_bin)
+        if out is None:
+            out = torch.empty((len(states), n_bins, len(g)), dtype=torch.float64,
+                              device="cuda:%d" % self.device)
+        hk_tables(self.h, states, grid, points_per_bin, g, precision, out)
+        return out
+
     def sync(self):
         hk_sync(self.h)
 
@@ -273,6 +305,9 @@ class Context:
 
     def set_option(self, name: str, value: int):
         hk_set_option(self.h, name, value)
+
+    def get_option(self, name: str) -> int:
+        return hk_get_option(self.h, name)
 
     def set_timing(self, enable: bool = True):
         hk_set_timing(self.h, enable)

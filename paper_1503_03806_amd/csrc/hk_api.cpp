@@ -64,8 +64,24 @@ struct hk_ctx {
     // binary32 path: records, Kahan pair, scale
     DevBuf w32, c32, f32sum, f32comp, f32scale, f32partial;
     bool have_run = false;
-    int f64_points_per_lane = 4;  // tile shape of the binary64 opacity kernel
-    int f32_points_per_lane = 4;  // tile shape of the binary32 opacity kernel
+    int f64_points_per_lane = 2;  // tile shape of the binary64 opacity kernel
+    int f32_points_per_lane = 2;  // tile shape of the binary32 opacity kernel
+    // batched tables: per-state records, ranges and sums of one batch, the
+    // per-state evaluation counters of the last call, and the tile shapes
+    // chosen by timing, per (precision, lines, points, cutoff/dnu)
+    DevBuf tb_idx, tb_wing, tb_core, tb_w32, tb_c32, tb_ranges, tb_ranges_c, tb_out, tb_comp, tb_scale, tb_kappa,
+        tb_counts;
+    int64_t tables_batch = 0;  // states per launch; 0 = as many as fit in tables_mem
+    int64_t tables_mem = (int64_t)32 << 30;
+    int tables_autotune = 1;
+    int32_t last_tables_states = 0;  // > 0: hk_stats reports that hk_tables call
+    int tables_ppl_used = 0;          // tile shape of the last hk_tables call
+    struct Tuned {
+        int precision;
+        int64_t n_lines, n_points, cut_steps;
+        int ppl;
+    };
+    std::vector<Tuned> tuned;
     // stage timing: events recorded around each timed launch, resolved
     // lazily (pending pairs) so timing adds no host synchronisation
     bool timing = false;
@@ -193,6 +209,124 @@ struct StageTimer {
 
 double* lines_field(hk_ctx* ctx, int k) { return static_cast<double*>(ctx->lines.p) + (size_t)k * ctx->n_lines; }
 
+LinesDev lines_dev(hk_ctx* ctx)
+{
+    LinesDev L;
+    L.nu = lines_field(ctx, 0);
+    L.S_ref = lines_field(ctx, 1);
+    L.E_lower = lines_field(ctx, 2);
+    L.gamma_air = lines_field(ctx, 3);
+    L.n_air = lines_field(ctx, 4);
+    L.gamma_self = lines_field(ctx, 5);
+    L.delta = ctx->has_delta ? lines_field(ctx, 6) : nullptr;
+    L.A21 = ctx->has_A ? lines_field(ctx, 7) : nullptr;
+    L.n = ctx->n_lines;
+    return L;
+}
+
+// Per-state constants of the line preparation (eq. 18-21 of §2.3, the
+// Doppler factor sqrt(2 k T / m) / c, the natural width factor 1/(4 pi c)).
+PrepParams prep_params(const hk_ctx* ctx, const hk_state* st, const hk_grid* grid)
+{
+    PrepParams pp;
+    pp.T = st->T;
+    pp.T_ref = ctx->species.T_ref;
+    pp.P = st->P;
+    pp.P_self = st->P_self;
+    pp.q_ratio = st->q_ratio;
+    pp.dop = std::sqrt(2.0 * kKB * st->T / (ctx->species.mass_amu * kAMU)) / kC;
+    pp.nat = 1.0 / (4.0 * kPi * kC);
+    pp.tscale = st->T / ctx->species.T_ref;
+    pp.nu_min = grid->nu_min;
+    pp.dnu = grid->dnu;
+    pp.cutoff = grid->cutoff;
+    pp.n_points = (int32_t)grid->n_points;
+    return pp;
+}
+
+// A line can reach a grid tile only if its unshifted centre lies within the
+// cutoff plus the largest pressure shift (+ two grid steps of slack for the
+// rounding of the window bounds).  Its series region a^2+u^2 < 100 lies
+// within 10 alpha of the centre, and alpha = nu * dop is largest for the
+// largest nu.
+double wing_reach(const hk_ctx* ctx, const hk_state* st, const hk_grid* grid)
+{
+    return grid->cutoff + ctx->max_abs_delta * st->P + 2.0 * grid->dnu;
+}
+double core_reach(const hk_ctx* ctx, const hk_state* st, const hk_grid* grid, const PrepParams& pp)
+{
+    return std::min(10.0 * pp.dop * ctx->nu_max, grid->cutoff) + ctx->max_abs_delta * st->P + 2.0 * grid->dnu;
+}
+
+}  // namespace
+
+namespace {
+
+constexpr int32_t kCountBlocks = 256;  // partial sums per evaluation count
+
+// Times the batched wing kernel at 2, 4 and 8 points per lane on the first
+// states of a batch (one untimed launch, then one timed launch each) and
+// returns the fastest shape.  The shapes give identical results, so the
+// choice affects time only.
+int autotune_wing(hk_ctx* ctx, int precision, const hk_state* states, int32_t n_try, const hk_grid* grid,
+                  int* best_out)
+{
+    const int64_t n = ctx->n_lines;
+    const int32_t np = (int32_t)grid->n_points;
+    const double* nu = lines_field(ctx, 0);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HK_HIP(ctx, hipEventCreate(&e0), "hipEventCreate");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(ctx, HK_EDEVICE, "hipEventCreate failed");
+    }
+    int best = 0;
+    float best_ms = 0.0f;
+    hipError_t err = hipSuccess;
+    for (int cand : {2, 4, 8}) {
+        const int32_t tp = precision == HK_F64 ? opacity_f64_tile_points(cand) : opacity_f32_tile_points(cand);
+        const int64_t n_tiles = ((int64_t)np + tp - 1) / tp;
+        err = ctx->tb_ranges.ensure((size_t)std::max<int64_t>(n_tiles * n_try, 1) * 2 * sizeof(int64_t));
+        if (err != hipSuccess) break;
+        int64_t* ranges = static_cast<int64_t*>(ctx->tb_ranges.p);
+        for (int32_t s = 0; s < n_try && err == hipSuccess; ++s)
+            err = launch_tile_ranges(nu, n, n_tiles, tp, grid->nu_min, grid->dnu, np,
+                                     wing_reach(ctx, &states[s], grid), ranges + (int64_t)s * 2 * n_tiles,
+                                     ctx->stream);
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
+            if (rep == 1) err = hipEventRecord(e0, ctx->stream);
+            if (err != hipSuccess) break;
+            if (precision == HK_F64)
+                err = launch_wing_f64_batched(cand, static_cast<WingRec*>(ctx->tb_wing.p),
+                                              static_cast<WingIdx*>(ctx->tb_idx.p), ranges, n, n_tiles,
+                                              grid->nu_min, grid->dnu, np, n_try, static_cast<double*>(ctx->tb_out.p),
+                                              ctx->stream);
+            else
+                err = launch_wing_f32_batched(cand, static_cast<WingRec32*>(ctx->tb_w32.p),
+                                              static_cast<WingIdx*>(ctx->tb_idx.p), ranges, n, n_tiles, np, n_try,
+                                              static_cast<float*>(ctx->tb_out.p), static_cast<float*>(ctx->tb_comp.p),
+                                              ctx->stream);
+            if (err != hipSuccess) break;
+            if (rep == 1) {
+                err = hipEventRecord(e1, ctx->stream);
+                if (err == hipSuccess) err = hipEventSynchronize(e1);
+                if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            }
+        }
+        if (err != hipSuccess) break;
+        if (best == 0 || ms < best_ms) {
+            best = cand;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return hip_fail(ctx, err, "autotuning the opacity tiles");
+    *best_out = best;
+    return HK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -246,6 +380,10 @@ int hk_destroy(hk_ctx* ctx)
     ctx->partial.release();
     ctx->kscratch.release();
     for (DevBuf* b : {&ctx->w32, &ctx->c32, &ctx->f32sum, &ctx->f32comp, &ctx->f32scale, &ctx->f32partial})
+        b->release();
+    for (DevBuf* b : {&ctx->tb_idx, &ctx->tb_wing, &ctx->tb_core, &ctx->tb_w32, &ctx->tb_c32, &ctx->tb_ranges,
+                      &ctx->tb_ranges_c, &ctx->tb_out, &ctx->tb_comp, &ctx->tb_scale, &ctx->tb_kappa,
+                      &ctx->tb_counts})
         b->release();
     for (auto& p : ctx->pending) {
         (void)hipEventDestroy(p.second.first);
@@ -404,20 +542,9 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
     const int64_t n = ctx->n_lines;
     const int32_t np = (int32_t)grid->n_points;
 
-    PrepParams pp;
-    pp.T = st->T;
-    pp.T_ref = ctx->species.T_ref;
-    pp.P = st->P;
-    pp.P_self = st->P_self;
-    pp.q_ratio = st->q_ratio;
-    pp.dop = std::sqrt(2.0 * kKB * st->T / (ctx->species.mass_amu * kAMU)) / kC;
-    pp.nat = 1.0 / (4.0 * kPi * kC);
-    pp.tscale = st->T / ctx->species.T_ref;
-    pp.nu_min = grid->nu_min;
-    pp.dnu = grid->dnu;
-    pp.cutoff = grid->cutoff;
-    pp.n_points = np;
+    const PrepParams pp = prep_params(ctx, st, grid);
     ctx->last_P = st->P;
+    ctx->last_tables_states = 0;
 
     const size_t nb = (size_t)std::max<int64_t>(n, 1);
     HK_HIP(ctx, ctx->wing.ensure(nb * sizeof(WingRec)), "allocating line records");
@@ -433,28 +560,13 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
     HK_HIP(ctx, ctx->ranges_core.ensure((size_t)std::max<int64_t>(n_tiles_c, 1) * 2 * sizeof(int64_t)),
            "allocating tile ranges");
 
-    LinesDev L;
-    L.nu = lines_field(ctx, 0);
-    L.S_ref = lines_field(ctx, 1);
-    L.E_lower = lines_field(ctx, 2);
-    L.gamma_air = lines_field(ctx, 3);
-    L.n_air = lines_field(ctx, 4);
-    L.gamma_self = lines_field(ctx, 5);
-    L.delta = ctx->has_delta ? lines_field(ctx, 6) : nullptr;
-    L.A21 = ctx->has_A ? lines_field(ctx, 7) : nullptr;
-    L.n = n;
+    const LinesDev L = lines_dev(ctx);
     WingRec* wing = static_cast<WingRec*>(ctx->wing.p);
     WingIdx* widx = static_cast<WingIdx*>(ctx->widx.p);
     CoreRec* core = static_cast<CoreRec*>(ctx->core.p);
     int64_t* ranges = static_cast<int64_t*>(ctx->ranges.p);
-    // a line can reach a tile only if its unshifted centre is within
-    // cutoff + the largest pressure shift (+ two grid steps of slack for the
-    // rounding of the window bounds)
-    const double reach = grid->cutoff + ctx->max_abs_delta * st->P + 2.0 * grid->dnu;
-    // the series region a^2+u^2 < 100 lies within 10 alpha of the centre,
-    // and alpha = nu * dop is largest for the largest nu
-    const double reach_core =
-        std::min(10.0 * pp.dop * ctx->nu_max, grid->cutoff) + ctx->max_abs_delta * st->P + 2.0 * grid->dnu;
+    const double reach = wing_reach(ctx, st, grid);
+    const double reach_core = core_reach(ctx, st, grid, pp);
     int64_t* ranges_c = static_cast<int64_t*>(ctx->ranges_core.p);
 
     {
@@ -510,6 +622,203 @@ int hk_kdist(hk_ctx* ctx, const void* kappa, int precision, int64_t n_points, co
     return HK_OK;
 }
 
+int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_grid* grid, const hk_bins* bins,
+              int precision, double* k_out)
+{
+    if (n_states < 0) return fail(ctx, HK_EINVAL, "n_states must be >= 0 (got %d)", n_states);
+    if (n_states > 0 && !states) return fail(ctx, HK_EINVAL, "states is NULL");
+    for (int32_t i = 0; i < n_states; ++i) {
+        if (check_state(ctx, &states[i])) {
+            const std::string m = hk_last_error(ctx);
+            return fail(ctx, HK_EINVAL, "states[%d]: %s", i, m.c_str());
+        }
+    }
+    if (int rc = check_grid(ctx, grid)) return rc;
+    GValues gv;
+    if (int rc = check_bins(ctx, bins, &gv)) return rc;
+    if (precision != HK_F64 && precision != HK_F32_KAHAN)
+        return fail(ctx, HK_EINVAL, "unknown precision %d", precision);
+    if (precision == HK_F32_KAHAN && !(grid->cutoff / grid->dnu < 8388608.0))
+        return fail(ctx, HK_EINVAL, "HK_F32_KAHAN needs cutoff/dnu < 2^23 (got %g)", grid->cutoff / grid->dnu);
+    const int32_t np = (int32_t)grid->n_points;
+    const int64_t n_bins = ((int64_t)np + bins->points_per_bin - 1) / bins->points_per_bin;
+    if (n_states > 0 && np > 0 && !k_out) return fail(ctx, HK_EINVAL, "k_out is NULL");
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!ctx->lines_loaded) return fail(ctx, HK_ENOTREADY, "no line list loaded (call hk_load_lines first)");
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    ctx->last_tables_states = 0;
+    if (n_states == 0 || np == 0) return HK_OK;
+
+    const int64_t n = ctx->n_lines;
+    const bool f64 = precision == HK_F64;
+    const LinesDev L = lines_dev(ctx);
+    const int32_t tpc = f64 ? core_f64_tile_points() : opacity_f32_tile_points(4);
+    const int64_t n_tiles_c = ((int64_t)np + tpc - 1) / tpc;
+    const int64_t n_tiles_max = ((int64_t)np + opacity_f64_tile_points(2) - 1) / opacity_f64_tile_points(2);
+    const int64_t n_tiles_max32 = ((int64_t)np + opacity_f32_tile_points(2) - 1) / opacity_f32_tile_points(2);
+    const int64_t ranges_per_state = 2 * std::max(n_tiles_max, n_tiles_max32);
+
+    // states per launch: the option, or as many as the memory budget holds
+    const int64_t rec_bytes = f64 ? (int64_t)(sizeof(WingRec) + sizeof(WingIdx) + sizeof(CoreRec))
+                                  : (int64_t)(sizeof(WingIdx) + sizeof(WingRec32) + sizeof(CoreRec32));
+    const int64_t per_state = n * rec_bytes + (ranges_per_state + 2 * n_tiles_c) * 8 + (int64_t)np * 8;
+    int64_t B = ctx->tables_batch > 0 ? ctx->tables_batch : std::max<int64_t>(1, ctx->tables_mem / per_state);
+    B = std::min<int64_t>(B, n_states);
+    const int64_t n_batches = (n_states + B - 1) / B;
+    B = (n_states + n_batches - 1) / n_batches;
+
+    const size_t nb = (size_t)std::max<int64_t>(n, 1) * (size_t)B;
+    HK_HIP(ctx, ctx->tb_idx.ensure(nb * sizeof(WingIdx)), "allocating batch records");
+    if (f64) {
+        HK_HIP(ctx, ctx->tb_wing.ensure(nb * sizeof(WingRec)), "allocating batch records");
+        HK_HIP(ctx, ctx->tb_core.ensure(nb * sizeof(CoreRec)), "allocating batch records");
+    } else {
+        const size_t n1 = (size_t)std::max<int64_t>(n, 1);
+        HK_HIP(ctx, ctx->wing.ensure(n1 * sizeof(WingRec)), "allocating line records");
+        HK_HIP(ctx, ctx->core.ensure(n1 * sizeof(CoreRec)), "allocating line records");
+        HK_HIP(ctx, ctx->tb_w32.ensure(nb * sizeof(WingRec32)), "allocating batch records");
+        HK_HIP(ctx, ctx->tb_c32.ensure(nb * sizeof(CoreRec32)), "allocating batch records");
+        HK_HIP(ctx, ctx->tb_comp.ensure((size_t)B * np * sizeof(float)), "allocating batch sums");
+        HK_HIP(ctx, ctx->tb_scale.ensure((size_t)B * sizeof(int32_t)), "allocating batch scales");
+        HK_HIP(ctx, ctx->tb_kappa.ensure((size_t)np * sizeof(double)), "allocating the opacity");
+        HK_HIP(ctx, ctx->f32partial.ensure((size_t)256 * sizeof(double)), "allocating the scale");
+    }
+    HK_HIP(ctx, ctx->tb_out.ensure((size_t)B * np * (f64 ? sizeof(double) : sizeof(float))),
+           "allocating batch opacities");
+    HK_HIP(ctx, ctx->tb_ranges.ensure((size_t)B * ranges_per_state * sizeof(int64_t)), "allocating tile ranges");
+    HK_HIP(ctx, ctx->tb_ranges_c.ensure((size_t)B * 2 * n_tiles_c * sizeof(int64_t)), "allocating tile ranges");
+    HK_HIP(ctx, ctx->tb_counts.ensure((size_t)n_states * kCountBlocks * 3 * sizeof(int64_t)),
+           "allocating counters");
+    const size_t sb = kdist_scratch_bytes(8, np, bins->points_per_bin, ctx->lds_bytes);
+    if (sb) HK_HIP(ctx, ctx->kscratch.ensure(sb), "allocating sort scratch");
+
+    WingIdx* tidx = static_cast<WingIdx*>(ctx->tb_idx.p);
+    int64_t* rc_all = static_cast<int64_t*>(ctx->tb_ranges_c.p);
+    int64_t* counts = static_cast<int64_t*>(ctx->tb_counts.p);
+
+    // tile shape: cached, or timed on the first batch
+    const int64_t cut_steps = (int64_t)std::llround(grid->cutoff / grid->dnu);
+    int ppl = f64 ? ctx->f64_points_per_lane : ctx->f32_points_per_lane;
+    bool tune = false;
+    if (ctx->tables_autotune) {
+        tune = true;
+        for (const auto& t : ctx->tuned)
+            if (t.precision == precision && t.n_lines == n && t.n_points == np && t.cut_steps == cut_steps) {
+                ppl = t.ppl;
+                tune = false;
+            }
+    }
+
+    for (int64_t b0 = 0; b0 < n_states; b0 += B) {
+        const int32_t nbat = (int32_t)std::min<int64_t>(B, n_states - b0);
+        {
+            StageTimer tm(ctx, HK_STAGE_LINE_PREP);
+            for (int32_t s = 0; s < nbat; ++s) {
+                const hk_state* st = &states[b0 + s];
+                const PrepParams pp = prep_params(ctx, st, grid);
+                WingIdx* ix = tidx + (int64_t)s * n;
+                if (f64) {
+                    HK_HIP(ctx, launch_line_prep_f64(L, pp, static_cast<WingRec*>(ctx->tb_wing.p) + (int64_t)s * n, ix,
+                                                     static_cast<CoreRec*>(ctx->tb_core.p) + (int64_t)s * n,
+                                                     ctx->stream),
+                           "line_prep_f64");
+                } else {
+                    WingRec* w = static_cast<WingRec*>(ctx->wing.p);
+                    CoreRec* c = static_cast<CoreRec*>(ctx->core.p);
+                    int32_t* scale = static_cast<int32_t*>(ctx->tb_scale.p) + s;
+                    HK_HIP(ctx, launch_line_prep_f64(L, pp, w, ix, c, ctx->stream), "line_prep_f64");
+                    if (n > 0) {
+                        HK_HIP(ctx, launch_f32_scale(w, c, n, static_cast<double*>(ctx->f32partial.p), 256, scale,
+                                                     ctx->stream),
+                               "f32_scale");
+                        HK_HIP(ctx, launch_line_prep_f32(w, ix, c, n, grid->nu_min, grid->dnu, scale,
+                                                         static_cast<WingRec32*>(ctx->tb_w32.p) + (int64_t)s * n,
+                                                         static_cast<CoreRec32*>(ctx->tb_c32.p) + (int64_t)s * n,
+                                                         ctx->stream),
+                               "line_prep_f32");
+                    } else {
+                        HK_HIP(ctx, hipMemsetAsync(scale, 0, sizeof(int32_t), ctx->stream), "hipMemsetAsync");
+                    }
+                }
+                HK_HIP(ctx, launch_eval_counts(ix, n, counts + (b0 + s) * kCountBlocks * 3, kCountBlocks, ctx->stream),
+                       "eval_counts");
+                HK_HIP(ctx, launch_tile_ranges(L.nu, n, n_tiles_c, tpc, grid->nu_min, grid->dnu, np,
+                                               core_reach(ctx, st, grid, pp), rc_all + (int64_t)s * 2 * n_tiles_c,
+                                               ctx->stream),
+                       "tile_ranges");
+            }
+            tm.stop();
+        }
+        if (tune) {
+            const int32_t n_try = std::min<int32_t>(nbat, 4);
+            if (int rc = autotune_wing(ctx, precision, &states[b0], n_try, grid, &ppl)) return rc;
+            ctx->tuned.push_back({precision, n, np, cut_steps, ppl});
+            tune = false;
+        }
+        const int32_t tp = f64 ? opacity_f64_tile_points(ppl) : opacity_f32_tile_points(ppl);
+        const int64_t n_tiles = ((int64_t)np + tp - 1) / tp;
+        int64_t* rw = static_cast<int64_t*>(ctx->tb_ranges.p);
+        {
+            StageTimer tm(ctx, HK_STAGE_OPACITY);
+            for (int32_t s = 0; s < nbat; ++s)
+                HK_HIP(ctx, launch_tile_ranges(L.nu, n, n_tiles, tp, grid->nu_min, grid->dnu, np,
+                                               wing_reach(ctx, &states[b0 + s], grid), rw + (int64_t)s * 2 * n_tiles,
+                                               ctx->stream),
+                       "tile_ranges");
+            if (f64)
+                HK_HIP(ctx, launch_wing_f64_batched(ppl, static_cast<WingRec*>(ctx->tb_wing.p), tidx, rw, n, n_tiles,
+                                                    grid->nu_min, grid->dnu, np, nbat,
+                                                    static_cast<double*>(ctx->tb_out.p), ctx->stream),
+                       "wing_f64_batched");
+            else
+                HK_HIP(ctx, launch_wing_f32_batched(ppl, static_cast<WingRec32*>(ctx->tb_w32.p), tidx, rw, n, n_tiles,
+                                                    np, nbat, static_cast<float*>(ctx->tb_out.p),
+                                                    static_cast<float*>(ctx->tb_comp.p), ctx->stream),
+                       "wing_f32_batched");
+            tm.stop();
+        }
+        {
+            StageTimer tm(ctx, HK_STAGE_CORE);
+            if (f64)
+                HK_HIP(ctx, launch_core_f64_batched(static_cast<WingRec*>(ctx->tb_wing.p), tidx,
+                                                    static_cast<CoreRec*>(ctx->tb_core.p), rc_all, n, n_tiles_c,
+                                                    grid->nu_min, grid->dnu, np, nbat,
+                                                    static_cast<double*>(ctx->tb_out.p), ctx->stream),
+                       "core_f64_batched");
+            else
+                HK_HIP(ctx, launch_core_f32_batched(tidx, static_cast<CoreRec32*>(ctx->tb_c32.p), rc_all, n, n_tiles_c,
+                                                    np, nbat, static_cast<float*>(ctx->tb_out.p),
+                                                    static_cast<float*>(ctx->tb_comp.p), ctx->stream),
+                       "core_f32_batched");
+            tm.stop();
+        }
+        {
+            StageTimer tm(ctx, HK_STAGE_KDIST);
+            for (int32_t s = 0; s < nbat; ++s) {
+                const double* kap;
+                if (f64) {
+                    kap = static_cast<double*>(ctx->tb_out.p) + (int64_t)s * np;
+                } else {
+                    double* kk = static_cast<double*>(ctx->tb_kappa.p);
+                    HK_HIP(ctx, launch_f32_finish(static_cast<float*>(ctx->tb_out.p) + (int64_t)s * np,
+                                                  static_cast<float*>(ctx->tb_comp.p) + (int64_t)s * np,
+                                                  static_cast<int32_t*>(ctx->tb_scale.p) + s, np, kk, 0, ctx->stream),
+                           "f32_finish");
+                    kap = kk;
+                }
+                HK_HIP(ctx, launch_kdist(kap, 8, np, bins->points_per_bin, gv, k_out + (b0 + s) * n_bins * gv.n,
+                                         nullptr, ctx->kscratch.p, ctx->lds_bytes, ctx->stream),
+                       "kdist");
+            }
+            tm.stop();
+        }
+    }
+    ctx->last_tables_states = n_states;
+    ctx->tables_ppl_used = ppl;
+    ctx->have_run = true;
+    return HK_OK;
+}
+
 int hk_stats(hk_ctx* ctx, hk_run_stats* out)
 {
     if (int rc = check_ctx(ctx)) return rc;
@@ -518,19 +827,23 @@ int hk_stats(hk_ctx* ctx, hk_run_stats* out)
     out->n_lines = ctx->n_lines;
     if (!ctx->have_run) return fail(ctx, HK_ENOTREADY, "no hk_opacity call yet");
     HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
-    const int32_t nblk = 256;
-    HK_HIP(ctx, ctx->partial.ensure((size_t)nblk * 3 * sizeof(int64_t)), "allocating counters");
+    // hk_opacity: count from the state's records now; hk_tables: the
+    // per-state counters it left
+    const bool tables = ctx->last_tables_states > 0;
+    const int64_t nblk = tables ? (int64_t)kCountBlocks * ctx->last_tables_states : kCountBlocks;
+    HK_HIP(ctx, ctx->partial.ensure((size_t)kCountBlocks * 3 * sizeof(int64_t)), "allocating counters");
     if (ctx->n_lines > 0) {
-        HK_HIP(ctx, launch_eval_counts(static_cast<WingIdx*>(ctx->widx.p), ctx->n_lines,
-                                       static_cast<int64_t*>(ctx->partial.p), nblk, ctx->stream),
-               "eval_counts");
+        if (!tables)
+            HK_HIP(ctx, launch_eval_counts(static_cast<WingIdx*>(ctx->widx.p), ctx->n_lines,
+                                           static_cast<int64_t*>(ctx->partial.p), kCountBlocks, ctx->stream),
+                   "eval_counts");
         std::vector<int64_t> h((size_t)nblk * 3);
-        HK_HIP(ctx, hipMemcpyAsync(h.data(), ctx->partial.p, h.size() * sizeof(int64_t), hipMemcpyDeviceToHost,
-                                   ctx->stream),
+        HK_HIP(ctx, hipMemcpyAsync(h.data(), tables ? ctx->tb_counts.p : ctx->partial.p, h.size() * sizeof(int64_t),
+                                   hipMemcpyDeviceToHost, ctx->stream),
                "copying counters");
         HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
         int64_t e = 0, c = 0, g = 0;
-        for (int b = 0; b < nblk; ++b) {
+        for (int64_t b = 0; b < nblk; ++b) {
             e += h[3 * b];
             c += h[3 * b + 1];
             g += h[3 * b + 2];
@@ -555,7 +868,40 @@ int hk_set_option(hk_ctx* ctx, const char* name, int64_t value)
         (f64 ? ctx->f64_points_per_lane : ctx->f32_points_per_lane) = (int)value;
         return HK_OK;
     }
+    if (std::strcmp(name, "tables_batch") == 0) {
+        if (value < 0 || value > INT32_MAX) return fail(ctx, HK_EINVAL, "tables_batch must be >= 0");
+        if (int rc = check_ctx(ctx)) return rc;
+        ctx->tables_batch = value;
+        return HK_OK;
+    }
+    if (std::strcmp(name, "tables_mem_mib") == 0) {
+        if (value < 1 || value > ((int64_t)1 << 30)) return fail(ctx, HK_EINVAL, "tables_mem_mib must be >= 1");
+        if (int rc = check_ctx(ctx)) return rc;
+        ctx->tables_mem = value << 20;
+        return HK_OK;
+    }
+    if (std::strcmp(name, "tables_autotune") == 0) {
+        if (value != 0 && value != 1) return fail(ctx, HK_EINVAL, "tables_autotune must be 0 or 1");
+        if (int rc = check_ctx(ctx)) return rc;
+        ctx->tables_autotune = (int)value;
+        if (!value) ctx->tuned.clear();
+        return HK_OK;
+    }
     return fail(ctx, HK_EINVAL, "unknown option '%s'", name);
+}
+
+int hk_get_option(hk_ctx* ctx, const char* name, int64_t* value)
+{
+    if (!name || !value) return fail(ctx, HK_EINVAL, "name and value must not be NULL");
+    if (int rc = check_ctx(ctx)) return rc;
+    if (std::strcmp(name, "f64_points_per_lane") == 0) *value = ctx->f64_points_per_lane;
+    else if (std::strcmp(name, "f32_points_per_lane") == 0) *value = ctx->f32_points_per_lane;
+    else if (std::strcmp(name, "tables_batch") == 0) *value = ctx->tables_batch;
+    else if (std::strcmp(name, "tables_mem_mib") == 0) *value = ctx->tables_mem >> 20;
+    else if (std::strcmp(name, "tables_autotune") == 0) *value = ctx->tables_autotune;
+    else if (std::strcmp(name, "tables_points_per_lane") == 0) *value = ctx->tables_ppl_used;
+    else return fail(ctx, HK_EINVAL, "unknown option '%s'", name);
+    return HK_OK;
 }
 
 int hk_set_timing(hk_ctx* ctx, int enable)

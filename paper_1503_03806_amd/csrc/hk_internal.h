@@ -137,6 +137,17 @@ hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRe
                            const int64_t* ranges,
                            int64_t n_tiles, double nu_min, double dnu, int32_t n_points,
                            double* kappa, hipStream_t s);
+// Batched forms: one persistent launch over n_states states whose records
+// lie n_lines apart, tile ranges 2 n_tiles apart, outputs n_points apart
+// (results identical to the single-state kernels, without accumulation).
+hipError_t launch_wing_f64_batched(int points_per_lane, const WingRec* wing, const WingIdx* idx,
+                                   const int64_t* ranges, int64_t n_lines, int64_t n_tiles, double nu_min,
+                                   double dnu, int32_t n_points, int32_t n_states, double* kappa,
+                                   hipStream_t s);
+hipError_t launch_core_f64_batched(const WingRec* wing, const WingIdx* idx, const CoreRec* core,
+                                   const int64_t* ranges, int64_t n_lines, int64_t n_tiles, double nu_min,
+                                   double dnu, int32_t n_points, int32_t n_states, double* kappa,
+                                   hipStream_t s);
 hipError_t launch_eval_counts(const WingIdx* idx, int64_t n_lines, int64_t* partial,
                               int32_t n_blocks, hipStream_t s);
 
@@ -154,6 +165,13 @@ hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const Win
 hipError_t launch_core_f32(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges,
                            int64_t n_tiles, int32_t n_points, float* sum, float* comp,
                            hipStream_t s);
+hipError_t launch_wing_f32_batched(int points_per_lane, const WingRec32* wing, const WingIdx* idx,
+                                   const int64_t* ranges, int64_t n_lines, int64_t n_tiles,
+                                   int32_t n_points, int32_t n_states, float* sum, float* comp,
+                                   hipStream_t s);
+hipError_t launch_core_f32_batched(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges,
+                                   int64_t n_lines, int64_t n_tiles, int32_t n_points,
+                                   int32_t n_states, float* sum, float* comp, hipStream_t s);
 // kappa (binary64) = (sum + comp) * 2^-s, or += when accumulating.
 hipError_t launch_f32_finish(const float* sum, const float* comp, const int32_t* scale,
                              int32_t n_points, double* kappa, int accumulate, hipStream_t s);

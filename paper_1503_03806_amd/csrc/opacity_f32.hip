@@ -16,6 +16,8 @@
 //    block sum is within 256 * 2^-24 = 1.5e-5 of exact in the worst case,
 //    the Kahan sum of blocks within ~2^-23 -- and the result does not depend
 //    on the tile shape.
+#include <algorithm>
+
 #include "hk_internal.h"
 
 namespace hk {
@@ -61,18 +63,16 @@ __device__ inline void kahan_add(float& s, float& c, float x)
     s = t;
 }
 
+// One grid tile t of one state (pointers already offset to the state).
 template <int kP>
-__global__ __launch_bounds__(64 * kWaves) void wing_f32_kernel(
-    const WingRec32* __restrict__ wing, const WingIdx* __restrict__ idx,
-    const int64_t* __restrict__ ranges, int64_t n_tiles, int32_t n, float* __restrict__ sum_out,
-    float* __restrict__ comp_out)
+__device__ void wing_f32_tile(int64_t t, const WingRec32* __restrict__ wing,
+                              const WingIdx* __restrict__ idx, const int64_t* __restrict__ ranges,
+                              int32_t n, float* __restrict__ sum_out, float* __restrict__ comp_out)
 {
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ WingRec32 tile[kTL];
     __shared__ WingIdx tidx[kTL];
     __shared__ uint32_t code[kTL];
-    const int64_t t = tile_of(blockIdx.x, n_tiles);
-    if (t < 0) return;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int32_t tile0 = (int32_t)(t * kTilePoints);
@@ -164,6 +164,34 @@ __global__ __launch_bounds__(64 * kWaves) void wing_f32_kernel(
     }
 }
 
+template <int kP>
+__global__ __launch_bounds__(64 * kWaves) void wing_f32_kernel(
+    const WingRec32* __restrict__ wing, const WingIdx* __restrict__ idx,
+    const int64_t* __restrict__ ranges, int64_t n_tiles, int32_t n, float* __restrict__ sum_out,
+    float* __restrict__ comp_out)
+{
+    const int64_t t = tile_of(blockIdx.x, n_tiles);
+    if (t < 0) return;
+    wing_f32_tile<kP>(t, wing, idx, ranges, n, sum_out, comp_out);
+}
+
+// Persistent launch over the (state, tile) items of a batch of states, in
+// the order of the binary64 one.
+template <int kP>
+__global__ __launch_bounds__(64 * kWaves) void wing_f32_batched_kernel(
+    const WingRec32* __restrict__ wing, const WingIdx* __restrict__ idx,
+    const int64_t* __restrict__ ranges, int64_t n_lines, int64_t n_tiles, int32_t n,
+    int32_t n_states, float* __restrict__ sum, float* __restrict__ comp)
+{
+    const int64_t n_items = n_tiles * n_states;
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int64_t st = item % n_states;
+        const int64_t t = n_tiles - 1 - item / n_states;
+        wing_f32_tile<kP>(t, wing + st * n_lines, idx + st * n_lines, ranges + st * 2 * n_tiles, n,
+                          sum + st * (int64_t)n, comp + st * (int64_t)n);
+    }
+}
+
 // The core series in binary32 (see voigt_core in opacity_f64.hip for the
 // formula).  e^{-(n/2 - x)^2} underflows binary32 at n = 1 for x near 10, so
 // its recurrence starts at the largest term n0 = round(2x) and runs both
@@ -222,14 +250,12 @@ __device__ float voigt_core_f32(float x, float y, float ex, float T1, const floa
 // chunks of the line's core interval, lane rotation); the run's ordered
 // binary32 core sum is added to the Kahan pair written by the wing kernel.
 template <int kP>
-__global__ __launch_bounds__(64 * kWaves) void core_f32_kernel(
-    const WingIdx* __restrict__ idx, const CoreRec32* __restrict__ core,
-    const int64_t* __restrict__ ranges, int64_t n_tiles, int32_t n, float* __restrict__ sum,
-    float* __restrict__ comp)
+__device__ void core_f32_tile(int64_t t, const WingIdx* __restrict__ idx,
+                              const CoreRec32* __restrict__ core, const int64_t* __restrict__ ranges,
+                              int32_t n, float* __restrict__ sum, float* __restrict__ comp)
 {
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ float inv_tab[kWaves][kMaxTerms];
-    const int64_t t = n_tiles - 1 - (int64_t)blockIdx.x;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int32_t run0 = (int32_t)(t * kTilePoints) + wave * 64 * kP;
@@ -284,11 +310,59 @@ __global__ __launch_bounds__(64 * kWaves) void core_f32_kernel(
 }
 
 template <int kP>
+__global__ __launch_bounds__(64 * kWaves) void core_f32_kernel(
+    const WingIdx* __restrict__ idx, const CoreRec32* __restrict__ core,
+    const int64_t* __restrict__ ranges, int64_t n_tiles, int32_t n, float* __restrict__ sum,
+    float* __restrict__ comp)
+{
+    core_f32_tile<kP>(n_tiles - 1 - (int64_t)blockIdx.x, idx, core, ranges, n, sum, comp);
+}
+
+template <int kP>
+__global__ __launch_bounds__(64 * kWaves) void core_f32_batched_kernel(
+    const WingIdx* __restrict__ idx, const CoreRec32* __restrict__ core,
+    const int64_t* __restrict__ ranges, int64_t n_lines, int64_t n_tiles, int32_t n,
+    int32_t n_states, float* __restrict__ sum, float* __restrict__ comp)
+{
+    const int64_t n_items = n_tiles * n_states;
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int64_t st = item % n_states;
+        const int64_t t = n_tiles - 1 - item / n_states;
+        core_f32_tile<kP>(t, idx + st * n_lines, core + st * n_lines, ranges + st * 2 * n_tiles, n,
+                          sum + st * (int64_t)n, comp + st * (int64_t)n);
+    }
+}
+
+template <int kP>
 hipError_t launch_wing(const WingRec32* wing, const WingIdx* idx, const int64_t* ranges,
                        int64_t n_tiles, int32_t n, float* sum, float* comp, hipStream_t s)
 {
     wing_f32_kernel<kP><<<dim3((unsigned)padded_blocks(n_tiles)), dim3(64 * kWaves), 0, s>>>(
         wing, idx, ranges, n_tiles, n, sum, comp);
+    return hipGetLastError();
+}
+
+// Workgroups of a persistent launch: as many as the device keeps resident.
+template <typename K>
+int persistent_blocks(K kernel, int64_t n_items)
+{
+    int dev = 0, cus = 256, per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * kWaves, 0);
+    }
+    const int64_t b = (int64_t)std::max(cus, 1) * std::max(per_cu, 1);
+    return (int)std::max<int64_t>(1, std::min(n_items, b));
+}
+
+template <int kP>
+hipError_t launch_wing_batched(const WingRec32* wing, const WingIdx* idx, const int64_t* ranges,
+                               int64_t n_lines, int64_t n_tiles, int32_t n, int32_t n_states,
+                               float* sum, float* comp, hipStream_t s)
+{
+    const int nb = persistent_blocks(wing_f32_batched_kernel<kP>, n_tiles * n_states);
+    wing_f32_batched_kernel<kP><<<dim3(nb), dim3(64 * kWaves), 0, s>>>(wing, idx, ranges, n_lines, n_tiles,
+                                                                      n, n_states, sum, comp);
     return hipGetLastError();
 }
 
@@ -321,3 +395,33 @@ hipError_t launch_core_f32(const WingIdx* idx, const CoreRec32* core, const int6
 }
 
 }  // namespace hk
+
+namespace hk {
+
+hipError_t launch_wing_f32_batched(int points_per_lane, const WingRec32* wing, const WingIdx* idx,
+                                   const int64_t* ranges, int64_t n_lines, int64_t n_tiles,
+                                   int32_t n_points, int32_t n_states, float* sum, float* comp,
+                                   hipStream_t s)
+{
+    if (n_tiles == 0 || n_states == 0) return hipSuccess;
+    switch (points_per_lane) {
+    case 2: return launch_wing_batched<2>(wing, idx, ranges, n_lines, n_tiles, n_points, n_states, sum, comp, s);
+    case 4: return launch_wing_batched<4>(wing, idx, ranges, n_lines, n_tiles, n_points, n_states, sum, comp, s);
+    case 8: return launch_wing_batched<8>(wing, idx, ranges, n_lines, n_tiles, n_points, n_states, sum, comp, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_core_f32_batched(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges,
+                                   int64_t n_lines, int64_t n_tiles, int32_t n_points,
+                                   int32_t n_states, float* sum, float* comp, hipStream_t s)
+{
+    if (n_tiles == 0 || n_states == 0) return hipSuccess;
+    const int nb = persistent_blocks(core_f32_batched_kernel<4>, n_tiles * n_states);
+    core_f32_batched_kernel<4><<<dim3(nb), dim3(64 * kWaves), 0, s>>>(idx, core, ranges, n_lines, n_tiles,
+                                                                     n_points, n_states, sum, comp);
+    return hipGetLastError();
+}
+
+}  // namespace hk
+

@@ -16,6 +16,8 @@
 //        ordered sum to kappa.
 // So kappa_j = sum_wing + sum_core, each in line order: reproducible bit for
 // bit, independent of the tile shape.
+#include <algorithm>
+
 #include "hk_internal.h"
 
 namespace hk {
@@ -100,19 +102,17 @@ __device__ inline void gh3_nm(double dv, double G2, double B, double C, double B
 //   both 3-node:  c = rcp(ma mb) Lg;           acc += (c mb) na
 //   mixed:        c = rcp(den_a den_b) Lg;     acc += (c den_b) num_a
 // (num = 1 for a 1-node point).
+// One grid tile t of one state (pointers already offset to the state).
 template <int kP>
-__global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
-    const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
-    const int64_t* __restrict__ ranges, int64_t n_tiles, double nu_min, double dnu, int32_t n,
-    double* __restrict__ kappa, int accumulate)
+__device__ void wing_f64_tile(int64_t t, const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
+                              const int64_t* __restrict__ ranges, double nu_min, double dnu, int32_t n,
+                              double* __restrict__ kappa, int accumulate)
 {
     static_assert(kP % 2 == 0, "points are processed in pairs");
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ WingRec tile[kTL];
     __shared__ WingIdx tidx[kTL];
     __shared__ uint32_t code[kTL];
-    const int64_t t = tile_of(blockIdx.x, n_tiles);
-    if (t < 0) return;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int32_t tile0 = (int32_t)(t * kTilePoints);
@@ -226,6 +226,37 @@ __global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
     }
 }
 
+template <int kP>
+__global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
+    const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
+    const int64_t* __restrict__ ranges, int64_t n_tiles, double nu_min, double dnu, int32_t n,
+    double* __restrict__ kappa, int accumulate)
+{
+    const int64_t t = tile_of(blockIdx.x, n_tiles);
+    if (t < 0) return;
+    wing_f64_tile<kP>(t, wing, idx, ranges, nu_min, dnu, n, kappa, accumulate);
+}
+
+// Persistent launch over the (state, tile) items of a batch of states: item
+// r is the (r / n_states)-th dearest tile of state r % n_states, so the
+// states progress together and the cheap tiles of all of them come last;
+// workgroups stride over the items.  Per-state arrays lie n_lines records,
+// 2 n_tiles ranges and n points apart.
+template <int kP>
+__global__ __launch_bounds__(64 * kWaves) void wing_f64_batched_kernel(
+    const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
+    const int64_t* __restrict__ ranges, int64_t n_lines, int64_t n_tiles, double nu_min, double dnu,
+    int32_t n, int32_t n_states, double* __restrict__ kappa)
+{
+    const int64_t n_items = n_tiles * n_states;
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int64_t st = item % n_states;
+        const int64_t t = n_tiles - 1 - item / n_states;
+        wing_f64_tile<kP>(t, wing + st * n_lines, idx + st * n_lines, ranges + st * 2 * n_tiles, nu_min,
+                          dnu, n, kappa + st * (int64_t)n, 0);
+    }
+}
+
 // H_V(a, u) for a^2 + u^2 < 100 by the series form of the Faddeeva function
 // (Abramowitz & Stegun 7.1.29 applied to w(z) = e^{-z^2} erfc(-iz), step
 // 1/2), the three exponential series summed in one loop (§2.4):
@@ -269,14 +300,12 @@ __device__ double voigt_core(double x, double y, double ex, double T1, const dou
 // take them 64 at a time, and each value moves to the lane owning its point
 // (a rotation of the wavefront) to be added there.  kappa_j += the run's sum.
 template <int kP>
-__global__ __launch_bounds__(64 * kWaves) void core_f64_kernel(
-    const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
-    const CoreRec* __restrict__ core, const int64_t* __restrict__ ranges, int64_t n_tiles,
-    double nu_min, double dnu, int32_t n, double* __restrict__ kappa)
+__device__ void core_f64_tile(int64_t t, const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
+                              const CoreRec* __restrict__ core, const int64_t* __restrict__ ranges,
+                              double nu_min, double dnu, int32_t n, double* __restrict__ kappa)
 {
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ double inv_tab[kWaves][kMaxTerms];
-    const int64_t t = n_tiles - 1 - (int64_t)blockIdx.x;  // dearest tiles first
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int32_t run0 = (int32_t)(t * kTilePoints) + wave * 64 * kP;
@@ -328,12 +357,62 @@ __global__ __launch_bounds__(64 * kWaves) void core_f64_kernel(
 }
 
 template <int kP>
+__global__ __launch_bounds__(64 * kWaves) void core_f64_kernel(
+    const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
+    const CoreRec* __restrict__ core, const int64_t* __restrict__ ranges, int64_t n_tiles,
+    double nu_min, double dnu, int32_t n, double* __restrict__ kappa)
+{
+    // dearest tiles first
+    core_f64_tile<kP>(n_tiles - 1 - (int64_t)blockIdx.x, wing, idx, core, ranges, nu_min, dnu, n, kappa);
+}
+
+template <int kP>
+__global__ __launch_bounds__(64 * kWaves) void core_f64_batched_kernel(
+    const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
+    const CoreRec* __restrict__ core, const int64_t* __restrict__ ranges, int64_t n_lines,
+    int64_t n_tiles, double nu_min, double dnu, int32_t n, int32_t n_states, double* __restrict__ kappa)
+{
+    const int64_t n_items = n_tiles * n_states;
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int64_t st = item % n_states;
+        const int64_t t = n_tiles - 1 - item / n_states;
+        const int64_t o = st * n_lines;
+        core_f64_tile<kP>(t, wing + o, idx + o, core + o, ranges + st * 2 * n_tiles, nu_min, dnu, n,
+                          kappa + st * (int64_t)n);
+    }
+}
+
+template <int kP>
 hipError_t launch_wing(const WingRec* wing, const WingIdx* idx, const int64_t* ranges,
                        int64_t n_tiles, double nu_min, double dnu, int32_t n, double* kappa,
                        int accumulate, hipStream_t s)
 {
     wing_f64_kernel<kP><<<dim3((unsigned)padded_blocks(n_tiles)), dim3(64 * kWaves), 0, s>>>(
         wing, idx, ranges, n_tiles, nu_min, dnu, n, kappa, accumulate);
+    return hipGetLastError();
+}
+
+// Workgroups of a persistent launch: as many as the device keeps resident.
+template <typename K>
+int persistent_blocks(K kernel, int64_t n_items)
+{
+    int dev = 0, cus = 256, per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * kWaves, 0);
+    }
+    const int64_t b = (int64_t)std::max(cus, 1) * std::max(per_cu, 1);
+    return (int)std::max<int64_t>(1, std::min(n_items, b));
+}
+
+template <int kP>
+hipError_t launch_wing_batched(const WingRec* wing, const WingIdx* idx, const int64_t* ranges,
+                               int64_t n_lines, int64_t n_tiles, double nu_min, double dnu, int32_t n,
+                               int32_t n_states, double* kappa, hipStream_t s)
+{
+    const int nb = persistent_blocks(wing_f64_batched_kernel<kP>, n_tiles * n_states);
+    wing_f64_batched_kernel<kP><<<dim3(nb), dim3(64 * kWaves), 0, s>>>(wing, idx, ranges, n_lines, n_tiles,
+                                                                      nu_min, dnu, n, n_states, kappa);
     return hipGetLastError();
 }
 
@@ -362,6 +441,32 @@ hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRe
     if (n_tiles == 0) return hipSuccess;
     core_f64_kernel<4><<<dim3((unsigned)n_tiles), dim3(64 * kWaves), 0, s>>>(
         wing, idx, core, ranges, n_tiles, nu_min, dnu, n_points, kappa);
+    return hipGetLastError();
+}
+
+hipError_t launch_wing_f64_batched(int points_per_lane, const WingRec* wing, const WingIdx* idx,
+                                   const int64_t* ranges, int64_t n_lines, int64_t n_tiles, double nu_min,
+                                   double dnu, int32_t n_points, int32_t n_states, double* kappa,
+                                   hipStream_t s)
+{
+    if (n_tiles == 0 || n_states == 0) return hipSuccess;
+    switch (points_per_lane) {
+    case 2: return launch_wing_batched<2>(wing, idx, ranges, n_lines, n_tiles, nu_min, dnu, n_points, n_states, kappa, s);
+    case 4: return launch_wing_batched<4>(wing, idx, ranges, n_lines, n_tiles, nu_min, dnu, n_points, n_states, kappa, s);
+    case 8: return launch_wing_batched<8>(wing, idx, ranges, n_lines, n_tiles, nu_min, dnu, n_points, n_states, kappa, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_core_f64_batched(const WingRec* wing, const WingIdx* idx, const CoreRec* core,
+                                   const int64_t* ranges, int64_t n_lines, int64_t n_tiles, double nu_min,
+                                   double dnu, int32_t n_points, int32_t n_states, double* kappa,
+                                   hipStream_t s)
+{
+    if (n_tiles == 0 || n_states == 0) return hipSuccess;
+    const int nb = persistent_blocks(core_f64_batched_kernel<4>, n_tiles * n_states);
+    core_f64_batched_kernel<4><<<dim3(nb), dim3(64 * kWaves), 0, s>>>(wing, idx, core, ranges, n_lines, n_tiles,
+                                                                     nu_min, dnu, n_points, n_states, kappa);
     return hipGetLastError();
 }
 

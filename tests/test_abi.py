@@ -136,3 +136,37 @@ def test_gauss_legendre_helper_matches_numpy():
         assert np.max(np.abs(w - 0.5 * wr)) < 2e-15
     with pytest.raises(hk.HKError):
         hk.hk_gauss_legendre(0)
+
+
+def _tables_rc(states, n_states=None, grid=GOOD_GRID, ppb=100, g=(0.25, 0.75),
+               precision=hk.HK_F32_KAHAN, k_out=1):
+    arr = (hk.hk_state * max(len(states), 1))(*[hk._state(s) for s in states])
+    gg = np.ascontiguousarray(g, dtype=np.float64)
+    b = hk.hk_bins(ppb, len(gg), gg.ctypes.data_as(C.POINTER(C.c_double)))
+    gr = hk._grid(grid)
+    n = len(states) if n_states is None else n_states
+    return hk.lib().hk_tables(None, arr, n, C.byref(gr), C.byref(b), precision, k_out)
+
+
+def test_tables_rejects_bad_arguments():
+    bad = dict(GOOD_STATE, T=-5.0)
+    assert _tables_rc([GOOD_STATE], n_states=-1) == hk.HK_EINVAL
+    assert "n_states" in hk.hk_last_error(None)
+    assert _tables_rc([GOOD_STATE, GOOD_STATE, bad]) == hk.HK_EINVAL
+    assert "states[2]" in hk.hk_last_error(None) and "T must" in hk.hk_last_error(None)
+    assert _tables_rc([GOOD_STATE], ppb=0) == hk.HK_EINVAL
+    assert _tables_rc([GOOD_STATE], precision=5) == hk.HK_EINVAL
+    assert _tables_rc([GOOD_STATE], grid=dict(GOOD_GRID, dnu=1e-7, cutoff=1.0)) == hk.HK_EINVAL
+    assert "2^23" in hk.hk_last_error(None)
+    assert _tables_rc([GOOD_STATE], k_out=None) == hk.HK_EINVAL
+    assert "k_out" in hk.hk_last_error(None)
+    # valid arguments reach the context check
+    assert _tables_rc([GOOD_STATE]) == hk.HK_EINVAL and "context" in hk.hk_last_error(None)
+
+
+def test_options_need_a_context_and_valid_values():
+    v = C.c_int64(0)
+    assert hk.lib().hk_get_option(None, b"tables_batch", C.byref(v)) == hk.HK_EINVAL
+    assert hk.lib().hk_set_option(None, b"tables_autotune", 2) == hk.HK_EINVAL
+    assert hk.lib().hk_set_option(None, b"tables_batch", -1) == hk.HK_EINVAL
+    assert hk.lib().hk_set_option(None, b"no_such_option", 1) == hk.HK_EINVAL
