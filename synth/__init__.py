@@ -122,3 +122,36 @@ WORKLOADS = {
     "lines1e8_surrogate": Workload("lines1e8_surrogate", 100_000_000, 30000.0, 0.01, 25.0,
                                    1500.0, 1.0, 300),
 }
+
+
+# ---- learned surrogate: random draws only (the method's arithmetic lives in
+# the library and the oracle) ------------------------------------------------
+
+MLP_SHAPES = [(64, 2), (64,), (64, 64), (64,), (64, 64), (64,), (64, 64), (64,), (64,), (1,)]
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """Initial parameters of the 2-64-64-64-64-1 network as one flat float32
+    vector in the library's order (W1 b1 W2 b2 W3 b3 W4 b4 w5 b5, row-major
+    W[out][in]): weights uniform on +-sqrt(6 / fan_in) (He et al. 2015),
+    biases zero."""
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    parts = []
+    for k, shape in enumerate(MLP_SHAPES):
+        is_weight = k in (0, 2, 4, 6, 8)
+        if is_weight:
+            fan_in = shape[1] if len(shape) == 2 else shape[0]
+            b = np.sqrt(6.0 / fan_in)
+            parts.append(rng.uniform(-b, b, size=shape).ravel())
+        else:
+            parts.append(np.zeros(int(np.prod(shape))))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def surrogate_samples(n: int, seed: int = 0):
+    """Training inputs: x uniform on [0, 50], y log-uniform on [1e-4, 1e2]
+    (float32 arrays)."""
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    x = rng.uniform(0.0, 50.0, n)
+    y = 10.0 ** rng.uniform(-4.0, 2.0, n)
+    return x.astype(np.float32), y.astype(np.float32)
