@@ -28,7 +28,9 @@ series remains the fallback and the judge of its error.  Definitions:
   so that K = G3 exp(tau sinh(z)).  z = 0 wherever the plain method itself
   uses the 3-node rule; the asinh compresses the series region's large
   corrections and keeps small ones resolvable.
-* Loss: mean squared error of z over the batch.  Update: Adam (Kingma & Ba
+* Loss: mean of w(z) (z_hat - z)^2 over the batch, w(z) = 1/(1 + (z/s)^2)
+  (s = 0: w = 1), which spends less of the network on the core where
+  |z| is large and no certification is possible anyway.  Update: Adam (Kingma & Ba
   2015, Algorithm 1) with bias-corrected moments.
 """
 from __future__ import annotations
@@ -110,16 +112,20 @@ def forward(theta, x, y, emulate_bf16: bool = True):
     return out, {"zs": zs, "ins": ins, "p": p, "rnd": rnd}
 
 
-def loss_and_grad(theta, x, y, target, emulate_bf16: bool = True):
-    """Mean squared error of the output against ``target`` and its gradient
-    with respect to the flat parameter vector (the roundings of the forward
-    pass are treated as identities, as the GPU's backward pass does)."""
+def loss_and_grad(theta, x, y, target, emulate_bf16: bool = True, wscale: float = 0.0):
+    """Weighted mean squared error of the output against ``target`` --
+    mean of w (z_hat - z)^2 with w = 1/(1 + (z/wscale)^2), or w = 1 for
+    wscale = 0 -- and its gradient with respect to the flat parameter vector
+    (the roundings of the forward pass are treated as identities, as the
+    GPU's backward pass does)."""
     out, c = forward(theta, x, y, emulate_bf16)
     p, rnd, zs, ins = c["p"], c["rnd"], c["zs"], c["ins"]
     n = len(out)
-    r = out - np.asarray(target, dtype=np.float64)
-    loss = float(np.mean(r * r))
-    d_out = 2.0 * r / n
+    t = np.asarray(target, dtype=np.float64)
+    w = 1.0 / (1.0 + (t / wscale) ** 2) if wscale > 0 else np.ones_like(t)
+    r = out - t
+    loss = float(np.mean(w * r * r))
+    d_out = 2.0 * w * r / n
     g = {"w5": ins[4].T @ d_out, "b5": np.array([d_out.sum()])}
     dh = np.outer(d_out, rnd(p["w5"]))
     for k in (4, 3, 2):

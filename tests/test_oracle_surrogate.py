@@ -41,11 +41,12 @@ def small_batch(n=48, seed=5):
     return x, y
 
 
-def test_gradient_matches_finite_differences():
+@pytest.mark.parametrize("wscale", [0.0, 1.5])
+def test_gradient_matches_finite_differences(wscale):
     theta = synth.mlp_init(11).astype(np.float64)
     x, y = small_batch()
-    t = np.random.default_rng(6).normal(size=len(x))
-    _, g = S.loss_and_grad(theta, x, y, t, emulate_bf16=False)
+    t = np.random.default_rng(6).normal(size=len(x)) * 3
+    _, g = S.loss_and_grad(theta, x, y, t, emulate_bf16=False, wscale=wscale)
     rng = np.random.default_rng(7)
     # parameters from every block, biases and the output included
     offs = np.cumsum([0] + [int(np.prod(s)) for _, s in S.SHAPES])
@@ -54,8 +55,8 @@ def test_gradient_matches_finite_differences():
         h = 1e-5 * max(1.0, abs(theta[i]))
         tp = theta.copy(); tp[i] += h
         tm = theta.copy(); tm[i] -= h
-        fp, _ = S.loss_and_grad(tp, x, y, t, emulate_bf16=False)
-        fm, _ = S.loss_and_grad(tm, x, y, t, emulate_bf16=False)
+        fp, _ = S.loss_and_grad(tp, x, y, t, emulate_bf16=False, wscale=wscale)
+        fm, _ = S.loss_and_grad(tm, x, y, t, emulate_bf16=False, wscale=wscale)
         fd = (fp - fm) / (2 * h)
         assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g[i])) + 1e-9, (i, fd, g[i])
 
@@ -120,3 +121,14 @@ def test_target_is_zero_where_the_method_uses_the_three_node_rule():
     # t = 0 is a narrow Lorentzian): z < 0; a little off centre it misses the
     # Gaussian core: z > 0
     assert S.target(0.0, 1e-4)[0] < 0 and S.target(1.0, 1e-4)[0] > 0
+
+
+def test_weighted_loss_is_the_weighted_mean():
+    # with every weight computed by hand: w = 1/(1 + (z/s)^2)
+    theta = synth.mlp_init(13).astype(np.float64)
+    x, y = small_batch(6, 14)
+    t = np.array([0.0, 1.0, -2.0, 4.0, 8.0, -16.0])
+    out, _ = S.forward(theta, x, y, emulate_bf16=False)
+    w = np.array([1.0, 1 / 1.25, 1 / 2.0, 1 / 5.0, 1 / 17.0, 1 / 65.0])
+    loss, _ = S.loss_and_grad(theta, x, y, t, emulate_bf16=False, wscale=2.0)
+    assert abs(loss - np.mean(w * (out - t) ** 2)) <= 1e-14 * loss
