@@ -104,7 +104,7 @@ __device__ inline void gh3_nm(double dv, double G2, double B, double C, double B
 // (num = 1 for a 1-node point).
 // One grid tile t of one state (pointers already offset to the state).
 template <int kP>
-__device__ void wing_f64_tile(int64_t t, const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
+__device__ __forceinline__ void wing_f64_tile(int64_t t, const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
                               const int64_t* __restrict__ ranges, double nu_min, double dnu, int32_t n,
                               double* __restrict__ kappa, int accumulate)
 {
@@ -144,34 +144,52 @@ __device__ void wing_f64_tile(int64_t t, const WingRec* __restrict__ wing, const
             code[threadIdx.x] = c;
         }
         __syncthreads();
-        for (int k = 0; k < cnt; ++k) {
-            const uint32_t path = ((uint32_t)__builtin_amdgcn_readfirstlane((int)code[k]) >> (8 * wave)) & 0xffu;
-            if (path == kSkip) continue;
-            const double nu0 = tile[k].nu0, Lg = tile[k].Lg, G2 = tile[k].G2;
+        // runs of consecutive lines on the same path are looped over
+        // without leaving the path (keeps the accumulators in place)
+        auto path_of = [&](int kk) -> uint32_t {
+            return ((uint32_t)__builtin_amdgcn_readfirstlane((int)code[kk]) >> (8 * wave)) & 0xffu;
+        };
+        int k = 0;
+        while (k < cnt) {
+            const uint32_t path = path_of(k);
+            if (path == kSkip) {
+                ++k;
+                continue;
+            }
             if (path == kGH1) {
+                do {
+                    const double nu0 = tile[k].nu0, Lg = tile[k].Lg, G2 = tile[k].G2;
 #pragma unroll
-                for (int p = 0; p < kP; p += 2) {
-                    const double da = nuj[p] - nu0, db = nuj[p + 1] - nu0;
-                    const double Da = fma(da, da, G2), Db = fma(db, db, G2);
-                    const double c = qrcp(Da * Db) * Lg;
-                    acc[p] = fma(c, Db, acc[p]);
-                    acc[p + 1] = fma(c, Da, acc[p + 1]);
-                }
+                    for (int p = 0; p < kP; p += 2) {
+                        const double da = nuj[p] - nu0, db = nuj[p + 1] - nu0;
+                        const double Da = fma(da, da, G2), Db = fma(db, db, G2);
+                        const double c = qrcp(Da * Db) * Lg;
+                        acc[p] = fma(c, Db, acc[p]);
+                        acc[p + 1] = fma(c, Da, acc[p + 1]);
+                    }
+                    ++k;
+                } while (k < cnt && path_of(k) == kGH1);
                 continue;
             }
-            const double B = tile[k].B, C = tile[k].C, Bn = tile[k].Bn, Cn = tile[k].Cn;
             if (path == kGH3) {
+                do {
+                    const double nu0 = tile[k].nu0, Lg = tile[k].Lg, G2 = tile[k].G2;
+                    const double B = tile[k].B, C = tile[k].C, Bn = tile[k].Bn, Cn = tile[k].Cn;
 #pragma unroll
-                for (int p = 0; p < kP; p += 2) {
-                    double na, ma, nb, mb;
-                    gh3_nm(nuj[p] - nu0, G2, B, C, Bn, Cn, na, ma);
-                    gh3_nm(nuj[p + 1] - nu0, G2, B, C, Bn, Cn, nb, mb);
-                    const double c = qrcp(ma * mb) * Lg;
-                    acc[p] = fma(c * mb, na, acc[p]);
-                    acc[p + 1] = fma(c * ma, nb, acc[p + 1]);
-                }
+                    for (int p = 0; p < kP; p += 2) {
+                        double na, ma, nb, mb;
+                        gh3_nm(nuj[p] - nu0, G2, B, C, Bn, Cn, na, ma);
+                        gh3_nm(nuj[p + 1] - nu0, G2, B, C, Bn, Cn, nb, mb);
+                        const double c = qrcp(ma * mb) * Lg;
+                        acc[p] = fma(c * mb, na, acc[p]);
+                        acc[p + 1] = fma(c * ma, nb, acc[p + 1]);
+                    }
+                    ++k;
+                } while (k < cnt && path_of(k) == kGH3);
                 continue;
             }
+            const double nu0 = tile[k].nu0, Lg = tile[k].Lg, G2 = tile[k].G2;
+            const double B = tile[k].B, C = tile[k].C, Bn = tile[k].Bn, Cn = tile[k].Cn;
             // general path: window edges, region edges, core points (left to
             // the core kernel), the grid end, lines outside the pairing range
             const int32_t wlo = tidx[k].wlo, whi = tidx[k].whi;
@@ -216,6 +234,7 @@ __device__ void wing_f64_tile(int64_t t, const WingRec* __restrict__ wing, const
                     }
                 }
             }
+            ++k;
         }
         __syncthreads();
     }
@@ -300,7 +319,7 @@ __device__ double voigt_core(double x, double y, double ex, double T1, const dou
 // take them 64 at a time, and each value moves to the lane owning its point
 // (a rotation of the wavefront) to be added there.  kappa_j += the run's sum.
 template <int kP>
-__device__ void core_f64_tile(int64_t t, const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
+__device__ __forceinline__ void core_f64_tile(int64_t t, const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
                               const CoreRec* __restrict__ core, const int64_t* __restrict__ ranges,
                               double nu_min, double dnu, int32_t n, double* __restrict__ kappa)
 {
