@@ -5,9 +5,13 @@ A step is one pass of the whole path over the mid-scale binary64 workload
 100 cm^-1 cutoff, T = 1500 K, P = 1 atm, 300 bins x 20 Gauss-Legendre g):
 per-line scaling and windows, the Voigt evaluation and accumulation kernel,
 and the per-bin sort and k(g).  The line list is resident on the device
-before timing starts.  Prints one JSON line.
+before timing starts.  Beside the headline the line reports the binary32
+variant of the same step, the batched tables (the same lines over 200
+(T, P) states) and the learned surrogate (1e8 lines, 25 cm^-1 cutoff,
+against the binary64 path).  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-f32]
+                    [--no-tables] [--no-surrogate]
 """
 from __future__ import annotations
 
@@ -31,6 +35,9 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X binary64 vector peak
 # with its average of 24 terms at 10 flops each plus 18 of set-up: 258.
 FLOPS_PER_EVAL = {"gh1": 5, "gh3": 16, "core": 258}
 DOMINANT_KERNEL = "wing_f64_kernel"
+# surrogate training recipe: (Adam steps, learning rate) phases, batch 4096
+SURROGATE_SCHEDULE = ((20000, 5e-3), (20000, 1e-3), (20000, 2e-4))
+SURROGATE_WSCALE = 5.0  # loss weight 1/(1 + (z/5)^2)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "wing_f64_lines1e6_grid3e6_traffic.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1503_03806_amd", "csrc", "opacity_f64.hip")
 
@@ -80,6 +87,93 @@ def cpu_baseline(w, points: int):
                                                     w.name, len(lines["nu"]), evals, dt)}
 
 
+def bench_tables(hk, torch, ctx, g):
+    """The batched tables: the same 1e6 lines over 20 x 10 (T, P) states,
+    binary32 profiles, k(g) for 300 bins x 20 g per state; one untimed call
+    (it times the tile shapes once), then one timed call."""
+    import synth
+    w = synth.WORKLOADS["lines1e6_tables200"]
+    grid = w.grid()
+    states = [{k: c[k] for k in ("T", "P", "P_self", "q_ratio")}
+              for c in (synth.conditions(T, P) for T, P in w.states)]
+    log("bench: tables, %d states" % len(states))
+    out = torch.empty((len(states), w.n_bins, w.n_g), dtype=torch.float64, device="cuda")
+    ctx.tables(states, grid, w.points_per_bin, g, hk.HK_F32_KAHAN, out=out)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    ctx.tables(states, grid, w.points_per_bin, g, hk.HK_F32_KAHAN, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tm = ctx.timing()
+    ctx.set_timing(False)
+    evals = ctx.stats()["evals"]
+    return {"workload": w.name, "states": len(states), "precision": "f32_kahan",
+            "value": evals / dt, "unit": "evals/s", "ms_per_call": 1e3 * dt, "evals": evals,
+            "points_per_lane": ctx.get_option("tables_points_per_lane"),
+            "stage_ms": {k: v[0] for k, v in tm.items()}}
+
+
+def bench_surrogate(hk, torch, ctx):
+    """The learned surrogate: trained on 1e7 samples (x in [0, 50], y in
+    [1e-4, 1e2], targets from the plain method), certified at a 2e-5
+    per-evaluation budget, then the opacity of 1e8 lines (0.01 cm^-1 grid of
+    3e6 points, 25 cm^-1 cutoff, 1500 K, 1 atm) with the surrogate, with the
+    binary32 path and with the binary64 path; error against binary64."""
+    import synth
+    w = synth.WORKLOADS["lines1e8_surrogate"]
+    log("bench: surrogate training")
+    x, y = synth.surrogate_samples(10_000_000, seed=7)
+    xd = torch.tensor(x, device="cuda")
+    yd = torch.tensor(y, device="cuda")
+    zd = ctx.surrogate_labels(xd, yd)
+    ctx.surrogate_set_params(synth.mlp_init(7))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = []
+    for steps, lr in SURROGATE_SCHEDULE:
+        hist.append(ctx.surrogate_train(xd, yd, zd, batch=4096, steps=steps, lr=lr,
+                                        wscale=SURROGATE_WSCALE))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    hist = torch.cat(hist).cpu()
+    err, count = ctx.surrogate_certify(2e-5)
+    del xd, yd, zd
+    log("bench: surrogate workload, generating %d lines" % w.n_lines)
+    lines, cond = w.lines(), w.conditions()
+    grid = w.grid()
+    ctx.load_lines(lines, cond["mass_amu"], cond["T0"])
+    del lines
+    st = {k: cond[k] for k in ("T", "P", "P_self", "q_ratio")}
+    res = {}
+    for name, prec in (("f64", hk.HK_F64), ("f32_kahan", hk.HK_F32_KAHAN),
+                       ("f32_surrogate", hk.HK_F32_SURROGATE)):
+        k = ctx.opacity(st, grid, prec)
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(2):
+            ctx.opacity(st, grid, prec, out=k)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 2
+        tm = ctx.timing()
+        ctx.set_timing(False)
+        res[name] = (k, dt, {kk: v[0] / max(v[1], 1) for kk, v in tm.items()})
+    evals = ctx.stats()["evals"]
+    ref = res["f64"][0]
+    out = {"workload": w.name, "n_lines": w.n_lines, "evals": evals,
+           "train_samples": 10_000_000, "train_steps": int(len(hist)), "train_s": train_s,
+           "loss_first": float(hist[0]), "loss_last100": float(hist[-100:].mean()),
+           "certified_cells": count, "cells": int(err.size), "budget": 2e-5}
+    for name, (k, dt, stage) in res.items():
+        pos = ref > 0
+        out[name] = {"ms": 1e3 * dt, "evals_per_s": evals / dt, "stage_ms": stage,
+                     "max_rel_err_vs_f64": float(((k[pos] - ref[pos]).abs() / ref[pos]).max())}
+    out["speedup_surrogate_vs_f64"] = res["f64"][1] / res["f32_surrogate"][1]
+    out["speedup_surrogate_vs_f32"] = res["f32_kahan"][1] / res["f32_surrogate"][1]
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +181,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true", help="skip the binary32 variant")
+    ap.add_argument("--no-tables", action="store_true", help="skip the batched tables")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate workload")
     ap.add_argument("--cpu-points", type=int, default=300000,
                     help="grid points in the oracle's timed sample")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -182,9 +278,13 @@ def main(argv=None):
             "ms_per_step": 1e3 * f32_elapsed / f32_steps,
             "stage_ms": {k: v[0] / max(v[1], 1) for k, v in f32_tm.items()},
             "speedup_vs_f64": (1e3 * elapsed / a.steps) / (1e3 * f32_elapsed / f32_steps)}
+    if not a.no_tables:
+        rec["tables"] = bench_tables(hk, torch, ctx, g)
     if not a.no_cpu_baseline:
         log("bench: timing the oracle on a sample")
         rec["cpu_baseline"] = cpu_baseline(w, a.cpu_points)
+    if not a.no_surrogate:
+        rec["surrogate"] = bench_surrogate(hk, torch, ctx)
     ctx.close()
     print(json.dumps(rec), flush=True)
     return 0

@@ -49,9 +49,11 @@ typedef struct hk_ctx hk_ctx;
 
 /* Arithmetic of the profile evaluation and accumulation. */
 typedef enum {
-    HK_F64 = 0,        /* everything in binary64 */
-    HK_F32_KAHAN = 1   /* binary32 profiles, compensated binary32 sums;
-                          line strengths, widths and outputs in binary64 */
+    HK_F64 = 0,          /* everything in binary64 */
+    HK_F32_KAHAN = 1,    /* binary32 profiles, compensated binary32 sums;
+                            line strengths, widths and outputs in binary64 */
+    HK_F32_SURROGATE = 2 /* HK_F32_KAHAN, with the learned surrogate in place
+                            of the series wherever it is certified */
 } hk_precision;
 
 /* Line list, §2.3 (the HITRAN/HITEMP fields the method uses).  [host]
@@ -154,6 +156,10 @@ int hk_load_lines(hk_ctx* ctx, const hk_lines* lines, const hk_species* species)
  *   of two; each point's terms summed in binary32 blocks of at most 256 lines
  *   whose sums are added with Kahan compensation; the compensated sum is
  *   scaled back and stored in binary64.  Requires cutoff/dnu < 2^23.
+ * precision HK_F32_SURROGATE: as HK_F32_KAHAN, except that series-region
+ *   points (a^2+u^2 < 100) whose (u, a) cell the last hk_surrogate_certify
+ *   call certified take the learned surrogate instead of the series;
+ *   HK_ENOTREADY without a certification.
  * accumulate != 0 adds to the values already in kappa, e.g. to process a
  * line list in chunks; accumulate == 0 overwrites them. */
 int hk_opacity(hk_ctx* ctx, const hk_state* state, const hk_grid* grid,
@@ -195,6 +201,65 @@ int hk_kdist(hk_ctx* ctx, const void* kappa, int precision, int64_t n_points,
  * hk_stats afterwards reports the evaluation counts summed over the states. */
 int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_grid* grid,
               const hk_bins* bins, int precision, double* k_out);
+
+/* ---- learned surrogate of K(x, y) = H_V(a = y, u = x) ---------------------
+ * Not part of the paper's method: a network that stands in for the series
+ * (§2.4) where a certification against the series allows it; the series
+ * stays the fallback.  Features f1 = x/25 - 1, f2 = (log10 y + 1)/3; four
+ * hidden layers of 64 SiLU units (SiLU(z) = z/(1+e^-z)); one linear output
+ * z_hat; K_hat = G3(x, y) exp(tau sinh(z_hat)), tau = 1e-5, G3 the 3-node
+ * Gauss-Hermite value.  Parameters: one binary32 vector, row-major
+ * W[out][in]: W1[64][2] b1[64] W2[64][64] b2[64] W3[64][64] b3[64]
+ * W4[64][64] b4[64] w5[64] b5[1].  Weights are used as bfloat16 (round to
+ * nearest even), as are the hidden activations and layer gradients entering
+ * the 64-wide products (matrix cores, binary32 sums); biases and features
+ * stay binary32.  Training minimises the mean squared error of z_hat against
+ * z = asinh(ln(K/G3)/tau), optionally weighted against large |z| where the
+ * surrogate cannot be certified anyway, with Adam (Kingma & Ba 2015); every step's
+ * gradient is summed in a fixed order (no atomics).  x, y, z, K below are
+ * [device] float arrays of n values (x >= 0 is used as |x|, y > 0). */
+#define HK_SURR_N_PARAMS 12737
+#define HK_SURR_MAX_BATCH 65536
+#define HK_SURR_CELLS_X 80   /* certification cells: x in [0, 10) ... */
+#define HK_SURR_CELLS_Y 40   /* ... times log10 y in [-4, 1), 0.125 wide */
+typedef struct {
+    int32_t batch;   /* samples per step, 1 .. HK_SURR_MAX_BATCH */
+    int32_t steps;   /* Adam steps */
+    double lr, beta1, beta2, eps;
+    double wscale;   /* loss weight 1/(1 + (z/wscale)^2); 0: unweighted */
+} hk_train_cfg;
+
+/* Training targets z = asinh(ln(K/G3)/tau) with K from the plain method in
+ * binary64 (series for x^2+y^2 < 100, 3-node rule below 1e6, 1-node rule
+ * beyond, §2.4). */
+int hk_surrogate_labels(hk_ctx* ctx, const float* x, const float* y, int64_t n, float* z);
+/* [host] theta[HK_SURR_N_PARAMS]: set the parameters (copied; synchronises),
+ * reset Adam's moments, step count and sample cursor, drop the
+ * certification. */
+int hk_surrogate_set_params(hk_ctx* ctx, const float* theta);
+/* [host] theta[HK_SURR_N_PARAMS] <- the current parameters (synchronises). */
+int hk_surrogate_get_params(hk_ctx* ctx, float* theta);
+/* Loss over n (1 .. HK_SURR_MAX_BATCH) samples -- the mean of
+ * w(z) (z_hat - z)^2, w(z) = 1/(1 + (z/wscale)^2) (w = 1 for wscale = 0) --
+ * and its gradient: grad [device] float[HK_SURR_N_PARAMS], loss [device]
+ * float[1] or NULL.  The parameters are not changed. */
+int hk_surrogate_grad(hk_ctx* ctx, const float* x, const float* y, const float* z, int64_t n,
+                      double wscale, float* grad, float* loss);
+/* cfg->steps Adam steps on batches of cfg->batch consecutive samples of the
+ * n given (cyclically, continuing where the previous call stopped);
+ * loss_hist [device] float[steps] (the loss of each step's batch before its
+ * update) or NULL.  Drops the certification. */
+int hk_surrogate_train(hk_ctx* ctx, const float* x, const float* y, const float* z, int64_t n,
+                       const hk_train_cfg* cfg, float* loss_hist);
+/* z_hat and (K != NULL) K_hat at n points. */
+int hk_surrogate_eval(hk_ctx* ctx, const float* x, const float* y, int64_t n, float* z, float* K);
+/* Certification: for each cell (ix, iy) -- x in [ix, ix+1) * 0.125,
+ * log10 y in -4 + [iy, iy+1) * 0.125 -- the largest relative error of K_hat
+ * against the binary64 series over the cell's 8x8 lattice of points (edges
+ * included); cells with error <= budget are certified for HK_F32_SURROGATE.
+ * err: [host] double[HK_SURR_CELLS_Y][HK_SURR_CELLS_X] or NULL;
+ * n_certified: [host] or NULL.  Synchronises. */
+int hk_surrogate_certify(hk_ctx* ctx, double budget, double* err, int32_t* n_certified);
 
 /* ---- helpers -------------------------------------------------------------- */
 

@@ -18,12 +18,18 @@ __all__ = ["HK_OK", "HK_EINVAL", "HK_ENOMEM", "HK_EDEVICE", "HK_EUNSUPPORTED", "
            "HK_F64", "HK_F32_KAHAN", "HK_MAX_G", "HKError", "lib", "hk_version", "hk_create",
            "hk_destroy", "hk_set_stream", "hk_sync", "hk_last_error", "hk_load_lines",
            "hk_opacity", "hk_kdist", "hk_gauss_legendre", "hk_stats", "hk_set_timing",
-           "hk_get_timing", "hk_set_option", "hk_get_option", "hk_tables", "Context", "LIB_PATH"]
+           "hk_get_timing", "hk_set_option", "hk_get_option", "hk_tables", "HK_F32_SURROGATE",
+           "HK_SURR_N_PARAMS", "HK_SURR_CELLS_X", "HK_SURR_CELLS_Y", "hk_train_cfg",
+           "hk_surrogate_labels", "hk_surrogate_set_params", "hk_surrogate_get_params",
+           "hk_surrogate_grad", "hk_surrogate_train", "hk_surrogate_eval", "hk_surrogate_certify",
+           "Context", "LIB_PATH"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhk.so")
 
 HK_OK, HK_EINVAL, HK_ENOMEM, HK_EDEVICE, HK_EUNSUPPORTED, HK_ENOTREADY = 0, -1, -2, -3, -4, -5
-HK_F64, HK_F32_KAHAN = 0, 1
+HK_F64, HK_F32_KAHAN, HK_F32_SURROGATE = 0, 1, 2
+HK_SURR_N_PARAMS, HK_SURR_MAX_BATCH = 12737, 65536
+HK_SURR_CELLS_X, HK_SURR_CELLS_Y = 80, 40
 HK_MAX_G = 64
 HK_MAX_POINTS = 1 << 30
 
@@ -103,6 +109,15 @@ def lib():
         L.hk_tables.argtypes = [vp, C.POINTER(hk_state), C.c_int32, C.POINTER(hk_grid),
                                 C.POINTER(hk_bins), i32, vp]
         L.hk_tables.restype = i32
+        L.hk_surrogate_labels.argtypes = [vp, vp, vp, i64, vp]
+        L.hk_surrogate_set_params.argtypes = [vp, vp]
+        L.hk_surrogate_get_params.argtypes = [vp, vp]
+        L.hk_surrogate_grad.argtypes = [vp, vp, vp, vp, i64, C.c_double, vp, vp]
+        L.hk_surrogate_train.argtypes = [vp, vp, vp, vp, i64, C.POINTER(hk_train_cfg), vp]
+        L.hk_surrogate_eval.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.hk_surrogate_certify.argtypes = [vp, C.c_double, vp, C.POINTER(C.c_int32)]
+        for f in ("labels", "set_params", "get_params", "grad", "train", "eval", "certify"):
+            getattr(L, "hk_surrogate_" + f).restype = i32
         L.hk_get_timing.argtypes = [vp, C.POINTER(hk_timing)]; L.hk_get_timing.restype = i32
         _lib = L
     return _lib
@@ -205,6 +220,63 @@ def hk_tables(ctx, states, grid: dict, points_per_bin: int, g, precision: int, k
                            _ptr(k_out)), ctx)
 
 
+class hk_train_cfg(C.Structure):
+    _fields_ = [("batch", C.c_int32), ("steps", C.c_int32), ("lr", C.c_double),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("wscale", C.c_double)]
+
+
+def hk_surrogate_labels(ctx, x, y, z):
+    _check(lib().hk_surrogate_labels(ctx, _ptr(x), _ptr(y), _numel(x, y), _ptr(z)), ctx)
+
+
+def hk_surrogate_set_params(ctx, theta):
+    t = np.ascontiguousarray(theta, dtype=np.float32)
+    if t.shape != (HK_SURR_N_PARAMS,):
+        raise ValueError("theta must hold %d values" % HK_SURR_N_PARAMS)
+    _check(lib().hk_surrogate_set_params(ctx, t.ctypes.data), ctx)
+
+
+def hk_surrogate_get_params(ctx) -> np.ndarray:
+    t = np.empty(HK_SURR_N_PARAMS, dtype=np.float32)
+    _check(lib().hk_surrogate_get_params(ctx, t.ctypes.data), ctx)
+    return t
+
+
+def hk_surrogate_grad(ctx, x, y, z, grad, loss=None, wscale: float = 0.0):
+    _check(lib().hk_surrogate_grad(ctx, _ptr(x), _ptr(y), _ptr(z), _numel(x, y, z), float(wscale),
+                                   _ptr(grad), _ptr(loss)), ctx)
+
+
+def hk_surrogate_train(ctx, x, y, z, batch: int, steps: int, lr: float, beta1: float = 0.9,
+                       beta2: float = 0.999, eps: float = 1e-8, wscale: float = 0.0, loss_hist=None):
+    cfg = hk_train_cfg(int(batch), int(steps), float(lr), float(beta1), float(beta2), float(eps),
+                       float(wscale))
+    _check(lib().hk_surrogate_train(ctx, _ptr(x), _ptr(y), _ptr(z), _numel(x, y, z), C.byref(cfg),
+                                    _ptr(loss_hist)), ctx)
+
+
+def hk_surrogate_eval(ctx, x, y, z, K=None):
+    _check(lib().hk_surrogate_eval(ctx, _ptr(x), _ptr(y), _numel(x, y), _ptr(z), _ptr(K)), ctx)
+
+
+def hk_surrogate_certify(ctx, budget: float):
+    err = np.empty((HK_SURR_CELLS_Y, HK_SURR_CELLS_X))
+    cnt = C.c_int32(0)
+    _check(lib().hk_surrogate_certify(ctx, float(budget), err.ctypes.data, C.byref(cnt)), ctx)
+    return err, int(cnt.value)
+
+
+def _numel(*arrays) -> int:
+    n = {int(a.numel() if hasattr(a, "numel") else len(a)) for a in arrays}
+    if len(n) != 1:
+        raise ValueError("arrays differ in length: %s" % sorted(n))
+    for a in arrays:
+        if hasattr(a, "dtype") and str(a.dtype) not in ("torch.float32", "float32"):
+            raise ValueError("surrogate arrays are float32 (got %s)" % a.dtype)
+    return n.pop()
+
+
 def hk_gauss_legendre(n: int):
     g = np.empty(n); w = np.empty(n)
     _check(lib().hk_gauss_legendre(int(n), g.ctypes.data_as(_pd), w.ctypes.data_as(_pd)))
@@ -296,6 +368,40 @@ class Context:
                               device="cuda:%d" % self.device)
         hk_tables(self.h, states, grid, points_per_bin, g, precision, out)
         return out
+
+    # -- learned surrogate (float32 device tensors) --
+    def surrogate_labels(self, x, y):
+        z = self._torch.empty_like(x)
+        hk_surrogate_labels(self.h, x, y, z)
+        return z
+
+    def surrogate_set_params(self, theta):
+        hk_surrogate_set_params(self.h, theta)
+
+    def surrogate_params(self):
+        return hk_surrogate_get_params(self.h)
+
+    def surrogate_grad(self, x, y, z, wscale: float = 0.0):
+        torch = self._torch
+        g = torch.empty(HK_SURR_N_PARAMS, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        hk_surrogate_grad(self.h, x, y, z, g, loss, wscale)
+        return g, loss
+
+    def surrogate_train(self, x, y, z, batch: int, steps: int, lr: float, **kw):
+        torch = self._torch
+        hist = torch.empty(max(steps, 1), dtype=torch.float32, device=x.device)
+        hk_surrogate_train(self.h, x, y, z, batch, steps, lr, loss_hist=hist, **kw)
+        return hist[:steps]
+
+    def surrogate_eval(self, x, y):
+        z = self._torch.empty_like(x)
+        K = self._torch.empty_like(x)
+        hk_surrogate_eval(self.h, x, y, z, K)
+        return z, K
+
+    def surrogate_certify(self, budget: float):
+        return hk_surrogate_certify(self.h, budget)
 
     def sync(self):
         hk_sync(self.h)

@@ -82,6 +82,12 @@ struct hk_ctx {
         int ppl;
     };
     std::vector<Tuned> tuned;
+    // learned surrogate: binary32 parameters, Adam moments, the bfloat16
+    // compute copy, training partials, certification errors and mask
+    DevBuf sg_theta, sg_m, sg_v, sg_copy, sg_part, sg_ploss, sg_err, sg_mask;
+    bool sg_loaded = false, sg_certified = false;
+    int64_t sg_step = 0;  // Adam steps taken
+    int64_t sg_cursor = 0;  // next training sample
     // stage timing: events recorded around each timed launch, resolved
     // lazily (pending pairs) so timing adds no host synchronisation
     bool timing = false;
@@ -342,6 +348,8 @@ const char* hk_last_error(const hk_ctx* ctx)
 int hk_create(int device, hk_ctx** out)
 {
     if (!out) return fail(nullptr, HK_EINVAL, "out is NULL");
+    if (surrogate_n_params() != HK_SURR_N_PARAMS || surrogate_cells() != HK_SURR_CELLS_X * HK_SURR_CELLS_Y)
+        return fail(nullptr, HK_EUNSUPPORTED, "surrogate layout differs from hk.h");
     *out = nullptr;
     int n = 0;
     hipError_t e = hipGetDeviceCount(&n);
@@ -384,6 +392,9 @@ int hk_destroy(hk_ctx* ctx)
     for (DevBuf* b : {&ctx->tb_idx, &ctx->tb_wing, &ctx->tb_core, &ctx->tb_w32, &ctx->tb_c32, &ctx->tb_ranges,
                       &ctx->tb_ranges_c, &ctx->tb_out, &ctx->tb_comp, &ctx->tb_scale, &ctx->tb_kappa,
                       &ctx->tb_counts})
+        b->release();
+    for (DevBuf* b : {&ctx->sg_theta, &ctx->sg_m, &ctx->sg_v, &ctx->sg_copy, &ctx->sg_part, &ctx->sg_ploss,
+                      &ctx->sg_err, &ctx->sg_mask})
         b->release();
     for (auto& p : ctx->pending) {
         (void)hipEventDestroy(p.second.first);
@@ -468,7 +479,7 @@ int hk_load_lines(hk_ctx* ctx, const hk_lines* L, const hk_species* sp)
 // preparation: scale, binary32 records, tile ranges, wing and core kernels,
 // then kappa = (sum + comp) 2^-s in binary64.
 static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, WingRec* wing, WingIdx* widx, CoreRec* core,
-                       const int64_t* ranges_c, int64_t n_tiles_c, double* kappa, int accumulate)
+                       const int64_t* ranges_c, int64_t n_tiles_c, double* kappa, int accumulate, bool surrogate)
 {
     const int64_t n = ctx->n_lines;
     const int32_t np = (int32_t)grid->n_points;
@@ -516,7 +527,12 @@ static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, WingRec* wing, WingIdx*
     }
     {
         StageTimer tm(ctx, HK_STAGE_CORE);
-        HK_HIP(ctx, launch_core_f32(widx, c32, ranges_c, n_tiles_c, np, fs, fc, ctx->stream), "core_f32");
+        if (surrogate)
+            HK_HIP(ctx, launch_core_f32_surrogate(widx, c32, ranges_c, n_tiles_c, np, fs, fc, ctx->sg_copy.p,
+                                                  static_cast<const uint8_t*>(ctx->sg_mask.p), ctx->stream),
+                   "core_f32_surrogate");
+        else
+            HK_HIP(ctx, launch_core_f32(widx, c32, ranges_c, n_tiles_c, np, fs, fc, ctx->stream), "core_f32");
         HK_HIP(ctx, launch_f32_finish(fs, fc, scale, np, kappa, accumulate, ctx->stream), "f32_finish");
         tm.stop();
     }
@@ -530,14 +546,16 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
     // arguments first, the context last: the checks run without a device
     if (int rc = check_state(ctx, st)) return rc;
     if (int rc = check_grid(ctx, grid)) return rc;
-    if (precision != HK_F64 && precision != HK_F32_KAHAN)
+    if (precision != HK_F64 && precision != HK_F32_KAHAN && precision != HK_F32_SURROGATE)
         return fail(ctx, HK_EINVAL, "unknown precision %d", precision);
     if (comp) return fail(ctx, HK_EINVAL, "comp must be NULL (kappa holds the result in binary64)");
-    if (precision == HK_F32_KAHAN && !(grid->cutoff / grid->dnu < 8388608.0))
-        return fail(ctx, HK_EINVAL, "HK_F32_KAHAN needs cutoff/dnu < 2^23 (got %g)", grid->cutoff / grid->dnu);
+    if (precision != HK_F64 && !(grid->cutoff / grid->dnu < 8388608.0))
+        return fail(ctx, HK_EINVAL, "binary32 profiles need cutoff/dnu < 2^23 (got %g)", grid->cutoff / grid->dnu);
     if (grid->n_points > 0 && !kappa) return fail(ctx, HK_EINVAL, "kappa is NULL");
     if (int rc = check_ctx(ctx)) return rc;
     if (!ctx->lines_loaded) return fail(ctx, HK_ENOTREADY, "no line list loaded (call hk_load_lines first)");
+    if (precision == HK_F32_SURROGATE && !ctx->sg_certified)
+        return fail(ctx, HK_ENOTREADY, "HK_F32_SURROGATE needs a certified surrogate (hk_surrogate_certify)");
     HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     const int64_t n = ctx->n_lines;
     const int32_t np = (int32_t)grid->n_points;
@@ -580,8 +598,9 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
                "tile_ranges");
         tm.stop();
     }
-    if (precision == HK_F32_KAHAN) return opacity_f32(ctx, grid, wing, widx, core, ranges_c, n_tiles_c,
-                                                      static_cast<double*>(kappa), accumulate);
+    if (precision != HK_F64)
+        return opacity_f32(ctx, grid, wing, widx, core, ranges_c, n_tiles_c, static_cast<double*>(kappa), accumulate,
+                           precision == HK_F32_SURROGATE);
     {
         StageTimer tm(ctx, HK_STAGE_OPACITY);
         HK_HIP(ctx, launch_wing_f64(ppl, wing, widx, ranges, n_tiles, grid->nu_min, grid->dnu, np,
@@ -636,6 +655,8 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
     if (int rc = check_grid(ctx, grid)) return rc;
     GValues gv;
     if (int rc = check_bins(ctx, bins, &gv)) return rc;
+    if (precision == HK_F32_SURROGATE)
+        return fail(ctx, HK_EUNSUPPORTED, "hk_tables supports HK_F64 and HK_F32_KAHAN");
     if (precision != HK_F64 && precision != HK_F32_KAHAN)
         return fail(ctx, HK_EINVAL, "unknown precision %d", precision);
     if (precision == HK_F32_KAHAN && !(grid->cutoff / grid->dnu < 8388608.0))
@@ -816,6 +837,173 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
     ctx->last_tables_states = n_states;
     ctx->tables_ppl_used = ppl;
     ctx->have_run = true;
+    return HK_OK;
+}
+
+static int sg_ready(hk_ctx* ctx)
+{
+    if (!ctx->sg_loaded) return fail(ctx, HK_ENOTREADY, "no surrogate parameters (hk_surrogate_set_params)");
+    return HK_OK;
+}
+
+static int check_samples(hk_ctx* ctx, const float* x, const float* y, int64_t n)
+{
+    if (n < 0 || n > HK_MAX_POINTS) return fail(ctx, HK_EINVAL, "sample count %lld out of range", (long long)n);
+    if (n > 0 && (!x || !y)) return fail(ctx, HK_EINVAL, "x and y must not be NULL");
+    return HK_OK;
+}
+
+int hk_surrogate_labels(hk_ctx* ctx, const float* x, const float* y, int64_t n, float* z)
+{
+    if (int rc = check_samples(ctx, x, y, n)) return rc;
+    if (n > 0 && !z) return fail(ctx, HK_EINVAL, "z is NULL");
+    if (int rc = check_ctx(ctx)) return rc;
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    HK_HIP(ctx, launch_surrogate_labels(x, y, n, z, ctx->stream), "surrogate_labels");
+    return HK_OK;
+}
+
+int hk_surrogate_set_params(hk_ctx* ctx, const float* theta)
+{
+    if (!theta) return fail(ctx, HK_EINVAL, "theta is NULL");
+    for (int i = 0; i < HK_SURR_N_PARAMS; ++i)
+        if (!std::isfinite(theta[i])) return fail(ctx, HK_EINVAL, "theta[%d] is not finite", i);
+    if (int rc = check_ctx(ctx)) return rc;
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    const size_t nb = (size_t)HK_SURR_N_PARAMS * sizeof(float);
+    HK_HIP(ctx, ctx->sg_theta.ensure(nb), "allocating parameters");
+    HK_HIP(ctx, ctx->sg_m.ensure(nb), "allocating parameters");
+    HK_HIP(ctx, ctx->sg_v.ensure(nb), "allocating parameters");
+    HK_HIP(ctx, ctx->sg_copy.ensure(surrogate_params_bytes()), "allocating parameters");
+    HK_HIP(ctx, hipMemcpyAsync(ctx->sg_theta.p, theta, nb, hipMemcpyHostToDevice, ctx->stream), "copying parameters");
+    HK_HIP(ctx, hipMemsetAsync(ctx->sg_m.p, 0, nb, ctx->stream), "hipMemsetAsync");
+    HK_HIP(ctx, hipMemsetAsync(ctx->sg_v.p, 0, nb, ctx->stream), "hipMemsetAsync");
+    HK_HIP(ctx, launch_surrogate_pack(static_cast<float*>(ctx->sg_theta.p), ctx->sg_copy.p, ctx->stream),
+           "surrogate_pack");
+    HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    ctx->sg_loaded = true;
+    ctx->sg_certified = false;
+    ctx->sg_step = 0;
+    ctx->sg_cursor = 0;
+    return HK_OK;
+}
+
+int hk_surrogate_get_params(hk_ctx* ctx, float* theta)
+{
+    if (!theta) return fail(ctx, HK_EINVAL, "theta is NULL");
+    if (int rc = check_ctx(ctx)) return rc;
+    if (int rc = sg_ready(ctx)) return rc;
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    HK_HIP(ctx, hipMemcpyAsync(theta, ctx->sg_theta.p, (size_t)HK_SURR_N_PARAMS * sizeof(float),
+                               hipMemcpyDeviceToHost, ctx->stream),
+           "copying parameters");
+    HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    return HK_OK;
+}
+
+static int sg_partials(hk_ctx* ctx, int32_t batch)
+{
+    const int64_t n_wg = (batch + 63) / 64;
+    HK_HIP(ctx, ctx->sg_part.ensure((size_t)n_wg * HK_SURR_N_PARAMS * sizeof(float)), "allocating gradients");
+    HK_HIP(ctx, ctx->sg_ploss.ensure((size_t)n_wg * sizeof(float)), "allocating gradients");
+    return HK_OK;
+}
+
+int hk_surrogate_grad(hk_ctx* ctx, const float* x, const float* y, const float* z, int64_t n, double wscale,
+                      float* grad, float* loss)
+{
+    if (!(wscale >= 0.0) || !std::isfinite(wscale)) return fail(ctx, HK_EINVAL, "wscale must be finite and >= 0");
+    if (int rc = check_samples(ctx, x, y, n)) return rc;
+    if (n < 1 || n > HK_SURR_MAX_BATCH)
+        return fail(ctx, HK_EINVAL, "n must be in [1, %d] (got %lld)", HK_SURR_MAX_BATCH, (long long)n);
+    if (!z || !grad) return fail(ctx, HK_EINVAL, "z and grad must not be NULL");
+    if (int rc = check_ctx(ctx)) return rc;
+    if (int rc = sg_ready(ctx)) return rc;
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (int rc = sg_partials(ctx, (int32_t)n)) return rc;
+    float* part = static_cast<float*>(ctx->sg_part.p);
+    float* pl = static_cast<float*>(ctx->sg_ploss.p);
+    HK_HIP(ctx, launch_surrogate_train_step(ctx->sg_copy.p, x, y, z, n, 0, (int32_t)n, (float)wscale, part, pl,
+                                            ctx->stream),
+           "surrogate_train_step");
+    HK_HIP(ctx, launch_surrogate_reduce(part, (int32_t)n, grad, pl, loss, ctx->stream), "surrogate_reduce");
+    return HK_OK;
+}
+
+int hk_surrogate_train(hk_ctx* ctx, const float* x, const float* y, const float* z, int64_t n,
+                       const hk_train_cfg* cfg, float* loss_hist)
+{
+    if (int rc = check_samples(ctx, x, y, n)) return rc;
+    if (n < 1 || !z) return fail(ctx, HK_EINVAL, "need n >= 1 samples with targets z");
+    if (!cfg) return fail(ctx, HK_EINVAL, "cfg is NULL");
+    if (cfg->batch < 1 || cfg->batch > HK_SURR_MAX_BATCH)
+        return fail(ctx, HK_EINVAL, "batch must be in [1, %d]", HK_SURR_MAX_BATCH);
+    if (cfg->steps < 0) return fail(ctx, HK_EINVAL, "steps must be >= 0");
+    if (!(cfg->lr > 0.0) || !(cfg->beta1 >= 0.0 && cfg->beta1 < 1.0) || !(cfg->beta2 >= 0.0 && cfg->beta2 < 1.0) ||
+        !(cfg->eps > 0.0) || !(cfg->wscale >= 0.0) || !std::isfinite(cfg->wscale))
+        return fail(ctx, HK_EINVAL, "need lr > 0, 0 <= beta1, beta2 < 1, eps > 0, wscale >= 0");
+    if (int rc = check_ctx(ctx)) return rc;
+    if (int rc = sg_ready(ctx)) return rc;
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (int rc = sg_partials(ctx, cfg->batch)) return rc;
+    float* part = static_cast<float*>(ctx->sg_part.p);
+    float* pl = static_cast<float*>(ctx->sg_ploss.p);
+    for (int32_t s = 0; s < cfg->steps; ++s) {
+        const int64_t t = ctx->sg_step + 1;
+        const float c1 = (float)(1.0 / (1.0 - std::pow(cfg->beta1, (double)t)));
+        const float c2 = (float)(1.0 / (1.0 - std::pow(cfg->beta2, (double)t)));
+        HK_HIP(ctx, launch_surrogate_train_step(ctx->sg_copy.p, x, y, z, n, ctx->sg_cursor, cfg->batch,
+                                                (float)cfg->wscale, part, pl, ctx->stream),
+               "surrogate_train_step");
+        HK_HIP(ctx, launch_surrogate_adam(static_cast<float*>(ctx->sg_theta.p), static_cast<float*>(ctx->sg_m.p),
+                                          static_cast<float*>(ctx->sg_v.p), part, cfg->batch, (float)cfg->lr,
+                                          (float)cfg->beta1, (float)cfg->beta2, (float)cfg->eps, c1, c2,
+                                          ctx->sg_copy.p, pl, loss_hist ? loss_hist + s : nullptr, ctx->stream),
+               "surrogate_adam");
+        ctx->sg_step = t;
+        ctx->sg_cursor = (ctx->sg_cursor + cfg->batch) % n;
+    }
+    ctx->sg_certified = false;
+    return HK_OK;
+}
+
+int hk_surrogate_eval(hk_ctx* ctx, const float* x, const float* y, int64_t n, float* z, float* K)
+{
+    if (int rc = check_samples(ctx, x, y, n)) return rc;
+    if (n > 0 && !z) return fail(ctx, HK_EINVAL, "z is NULL");
+    if (int rc = check_ctx(ctx)) return rc;
+    if (int rc = sg_ready(ctx)) return rc;
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    HK_HIP(ctx, launch_surrogate_eval(ctx->sg_copy.p, x, y, n, z, K, ctx->stream), "surrogate_eval");
+    return HK_OK;
+}
+
+int hk_surrogate_certify(hk_ctx* ctx, double budget, double* err, int32_t* n_certified)
+{
+    if (!(budget > 0.0) || !std::isfinite(budget)) return fail(ctx, HK_EINVAL, "budget must be finite and > 0");
+    if (int rc = check_ctx(ctx)) return rc;
+    if (int rc = sg_ready(ctx)) return rc;
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    const int nc = surrogate_cells();
+    HK_HIP(ctx, ctx->sg_err.ensure((size_t)nc * sizeof(double)), "allocating certification");
+    HK_HIP(ctx, ctx->sg_mask.ensure((size_t)nc), "allocating certification");
+    HK_HIP(ctx, launch_surrogate_certify(ctx->sg_copy.p, static_cast<double*>(ctx->sg_err.p), ctx->stream),
+           "surrogate_certify");
+    std::vector<double> e((size_t)nc);
+    HK_HIP(ctx, hipMemcpyAsync(e.data(), ctx->sg_err.p, e.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream),
+           "copying certification");
+    HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    std::vector<uint8_t> mask((size_t)nc);
+    int32_t cnt = 0;
+    for (int c = 0; c < nc; ++c) {
+        mask[(size_t)c] = e[(size_t)c] <= budget ? 1 : 0;
+        cnt += mask[(size_t)c];
+    }
+    HK_HIP(ctx, hipMemcpy(ctx->sg_mask.p, mask.data(), mask.size(), hipMemcpyHostToDevice), "copying the mask");
+    if (err) std::memcpy(err, e.data(), e.size() * sizeof(double));
+    if (n_certified) *n_certified = cnt;
+    ctx->sg_certified = true;
     return HK_OK;
 }
 

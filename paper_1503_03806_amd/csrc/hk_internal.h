@@ -172,6 +172,11 @@ hipError_t launch_wing_f32_batched(int points_per_lane, const WingRec32* wing, c
 hipError_t launch_core_f32_batched(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges,
                                    int64_t n_lines, int64_t n_tiles, int32_t n_points,
                                    int32_t n_states, float* sum, float* comp, hipStream_t s);
+// The same series kernel with the learned surrogate in certified cells
+// (surrogate: the bfloat16 parameter copy; mask: certified cells).
+hipError_t launch_core_f32_surrogate(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges,
+                                     int64_t n_tiles, int32_t n_points, float* sum, float* comp,
+                                     const void* surrogate, const uint8_t* mask, hipStream_t s);
 // kappa (binary64) = (sum + comp) * 2^-s, or += when accumulating.
 hipError_t launch_f32_finish(const float* sum, const float* comp, const int32_t* scale,
                              int32_t n_points, double* kappa, int accumulate, hipStream_t s);
@@ -182,5 +187,25 @@ hipError_t launch_kdist(const void* kappa, int elem_bytes, int64_t n_points, int
                         const GValues& g, double* k_out, void* sorted_out, void* scratch,
                         int64_t lds_bytes, hipStream_t s);
 size_t kdist_scratch_bytes(int elem_bytes, int64_t n_points, int64_t ppb, int64_t lds_bytes);
+
+// Learned K(x, y) surrogate (surrogate.hip): sizes, labels, the compute
+// copy of the parameters, one training step and its Adam update, a plain
+// gradient, evaluation and per-cell certification errors.
+size_t surrogate_params_bytes();
+int32_t surrogate_n_params();
+int32_t surrogate_cells();
+hipError_t launch_surrogate_labels(const float* x, const float* y, int64_t n, float* z, hipStream_t s);
+hipError_t launch_surrogate_pack(const float* theta, void* P, hipStream_t s);
+hipError_t launch_surrogate_train_step(const void* P, const float* x, const float* y, const float* z, int64_t n,
+                                       int64_t base, int32_t batch, float wscale, float* part_grad,
+                                       float* part_loss, hipStream_t s);
+hipError_t launch_surrogate_adam(float* theta, float* m, float* v, const float* part_grad, int32_t batch,
+                                 float lr, float beta1, float beta2, float eps, float c1, float c2, void* P,
+                                 const float* part_loss, float* loss_out, hipStream_t s);
+hipError_t launch_surrogate_reduce(const float* part_grad, int32_t batch, float* grad, const float* part_loss,
+                                   float* loss_out, hipStream_t s);
+hipError_t launch_surrogate_eval(const void* P, const float* x, const float* y, int64_t n, float* z, float* K,
+                                 hipStream_t s);
+hipError_t launch_surrogate_certify(const void* P, double* err, hipStream_t s);
 
 }  // namespace hk

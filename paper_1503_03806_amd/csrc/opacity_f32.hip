@@ -19,6 +19,7 @@
 #include <algorithm>
 
 #include "hk_internal.h"
+#include "surrogate_dev.h"
 
 namespace hk {
 namespace {
@@ -65,7 +66,7 @@ __device__ inline void kahan_add(float& s, float& c, float x)
 
 // One grid tile t of one state (pointers already offset to the state).
 template <int kP>
-__device__ void wing_f32_tile(int64_t t, const WingRec32* __restrict__ wing,
+__device__ __forceinline__ void wing_f32_tile(int64_t t, const WingRec32* __restrict__ wing,
                               const WingIdx* __restrict__ idx, const int64_t* __restrict__ ranges,
                               int32_t n, float* __restrict__ sum_out, float* __restrict__ comp_out)
 {
@@ -73,6 +74,7 @@ __device__ void wing_f32_tile(int64_t t, const WingRec32* __restrict__ wing,
     __shared__ WingRec32 tile[kTL];
     __shared__ WingIdx tidx[kTL];
     __shared__ uint32_t code[kTL];
+    __shared__ float fjct[kTL];  // line centre index relative to the tile, exact
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int32_t tile0 = (int32_t)(t * kTilePoints);
@@ -94,6 +96,7 @@ __device__ void wing_f32_tile(int64_t t, const WingRec32* __restrict__ wing,
             tile[threadIdx.x] = wing[base + threadIdx.x];
             const WingIdx r = idx[base + threadIdx.x];
             tidx[threadIdx.x] = r;
+            fjct[threadIdx.x] = (float)(r.jc - tile0);  // exact: |.| < 2^24
             uint32_t cw = 0;
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) {
@@ -104,31 +107,51 @@ __device__ void wing_f32_tile(int64_t t, const WingRec32* __restrict__ wing,
             code[threadIdx.x] = cw;
         }
         __syncthreads();
-        for (int k = 0; k < cnt; ++k) {
-            const uint32_t path = ((uint32_t)__builtin_amdgcn_readfirstlane((int)code[k]) >> (8 * wave)) & 0xffu;
-            if (path == kSkip) continue;
-            const float fjc = (float)(tidx[k].jc - tile0);  // exact: |.| < 2^24
-            const float du = tile[k].du, fu = tile[k].fu, Lg = tile[k].Lg, G2 = tile[k].G2;
+        // runs of consecutive lines on the same path are looped over
+        // without leaving the path (keeps the partial sums in place)
+        auto path_of = [&](int kk) -> uint32_t {
+            return ((uint32_t)__builtin_amdgcn_readfirstlane((int)code[kk]) >> (8 * wave)) & 0xffu;
+        };
+        int k = 0;
+        while (k < cnt) {
+            const uint32_t path = path_of(k);
+            if (path == kSkip) {
+                ++k;
+                continue;
+            }
             if (path == kGH1) {
+                do {
+                    const float fjc = fjct[k];
+                    const float du = tile[k].du, fu = tile[k].fu, Lg = tile[k].Lg, G2 = tile[k].G2;
 #pragma unroll
-                for (int p = 0; p < kP; ++p) {
-                    const float dv = fmaf(fj[p] - fjc, du, -fu);
-                    part[p] = fmaf(Lg, rcpf(fmaf(dv, dv, G2)), part[p]);
-                }
+                    for (int p = 0; p < kP; ++p) {
+                        const float dv = fmaf(fj[p] - fjc, du, -fu);
+                        part[p] = fmaf(Lg, rcpf(fmaf(dv, dv, G2)), part[p]);
+                    }
+                    ++k;
+                } while (k < cnt && path_of(k) == kGH1);
                 continue;
             }
-            const float B = tile[k].B, C = tile[k].C, Bn = tile[k].Bn, Cn = tile[k].Cn;
             if (path == kGH3) {
+                do {
+                    const float fjc = fjct[k];
+                    const float du = tile[k].du, fu = tile[k].fu, Lg = tile[k].Lg, G2 = tile[k].G2;
+                    const float B = tile[k].B, C = tile[k].C, Bn = tile[k].Bn, Cn = tile[k].Cn;
 #pragma unroll
-                for (int p = 0; p < kP; ++p) {
-                    const float dv = fmaf(fj[p] - fjc, du, -fu);
-                    const float q = dv * dv;
-                    const float nn = fmaf(q, q + Bn, Cn);
-                    const float m = (q + G2) * fmaf(q, q + B, C);
-                    part[p] = fmaf(Lg, nn * rcpf(m), part[p]);
-                }
+                    for (int p = 0; p < kP; ++p) {
+                        const float dv = fmaf(fj[p] - fjc, du, -fu);
+                        const float q = dv * dv;
+                        const float nn = fmaf(q, q + Bn, Cn);
+                        const float m = (q + G2) * fmaf(q, q + B, C);
+                        part[p] = fmaf(Lg, nn * rcpf(m), part[p]);
+                    }
+                    ++k;
+                } while (k < cnt && path_of(k) == kGH3);
                 continue;
             }
+            const float fjc = fjct[k];
+            const float du = tile[k].du, fu = tile[k].fu, Lg = tile[k].Lg, G2 = tile[k].G2;
+            const float B = tile[k].B, C = tile[k].C, Bn = tile[k].Bn, Cn = tile[k].Cn;
             const int32_t wlo = tidx[k].wlo, whi = tidx[k].whi;
             const int32_t g3lo = tidx[k].g3lo, g3hi = tidx[k].g3hi;
             const int32_t clo = tidx[k].clo, chi = tidx[k].chi;
@@ -146,6 +169,7 @@ __device__ void wing_f32_tile(int64_t t, const WingRec32* __restrict__ wing,
                 const float acc = fmaf(Lg, one ? v1 : v3, part[p]);
                 part[p] = take ? acc : part[p];
             }
+            ++k;
         }
 #pragma unroll
         for (int p = 0; p < kP; ++p) {
@@ -249,13 +273,18 @@ __device__ float voigt_core_f32(float x, float y, float ex, float T1, const floa
 // Core-region terms: as core_f64_kernel (point ownership, compacted 64-point
 // chunks of the line's core interval, lane rotation); the run's ordered
 // binary32 core sum is added to the Kahan pair written by the wing kernel.
-template <int kP>
-__device__ void core_f32_tile(int64_t t, const WingIdx* __restrict__ idx,
+// With kSurr, points of certified (x, y) cells take the learned surrogate
+// instead of the series (the wavefront runs the network when any of its
+// lanes needs it, the series when any needs that).
+template <int kP, bool kSurr = false>
+__device__ __forceinline__ void core_f32_tile(int64_t t, const WingIdx* __restrict__ idx,
                               const CoreRec32* __restrict__ core, const int64_t* __restrict__ ranges,
-                              int32_t n, float* __restrict__ sum, float* __restrict__ comp)
+                              int32_t n, float* __restrict__ sum, float* __restrict__ comp,
+                              const surr::MlpBf16* __restrict__ P = nullptr, const uint8_t* __restrict__ mask = nullptr)
 {
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ float inv_tab[kWaves][kMaxTerms];
+    __shared__ __align__(16) uint16_t act_tab[kSurr ? kWaves : 1][kSurr ? 64 * surr::kLd : 1];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int32_t run0 = (int32_t)(t * kTilePoints) + wave * 64 * kP;
@@ -283,7 +312,19 @@ __device__ void core_f32_tile(int64_t t, const WingIdx* __restrict__ idx,
         for (int32_t c0 = a; c0 <= b; c0 += 64) {
             const int32_t j = c0 + lane;
             float v = 0.0f;
-            if (j <= b) {
+            if constexpr (kSurr) {
+                const bool valid = j <= b;
+                const float x = valid ? fabsf(fmaf((float)(j - jc), cr.dx, -cr.fx)) : 0.0f;
+                const bool use = valid && surr::certified(mask, x, cr.y);
+                if (__ballot(valid && !use)) {
+                    if (valid && !use) v = cr.norm * voigt_core_f32(x, cr.y, cr.ex, cr.T1, inv);
+                }
+                if (__ballot(use)) {
+                    const float z = surr::mlp_forward<false>(P, act_tab[wave], surr::feature_x(x),
+                                                             surr::feature_y(use ? cr.y : 1.0f));
+                    if (use) v = cr.norm * surr::surrogate_K(x, cr.y, z);
+                }
+            } else if (j <= b) {
                 const float x = fabsf(fmaf((float)(j - jc), cr.dx, -cr.fx));
                 v = cr.norm * voigt_core_f32(x, cr.y, cr.ex, cr.T1, inv);
             }
@@ -316,6 +357,14 @@ __global__ __launch_bounds__(64 * kWaves) void core_f32_kernel(
     float* __restrict__ comp)
 {
     core_f32_tile<kP>(n_tiles - 1 - (int64_t)blockIdx.x, idx, core, ranges, n, sum, comp);
+}
+
+__global__ __launch_bounds__(64 * kWaves) void core_f32_surrogate_kernel(
+    const WingIdx* __restrict__ idx, const CoreRec32* __restrict__ core,
+    const int64_t* __restrict__ ranges, int64_t n_tiles, int32_t n, float* __restrict__ sum,
+    float* __restrict__ comp, const surr::MlpBf16* __restrict__ P, const uint8_t* __restrict__ mask)
+{
+    core_f32_tile<4, true>(n_tiles - 1 - (int64_t)blockIdx.x, idx, core, ranges, n, sum, comp, P, mask);
 }
 
 template <int kP>
@@ -425,3 +474,16 @@ hipError_t launch_core_f32_batched(const WingIdx* idx, const CoreRec32* core, co
 
 }  // namespace hk
 
+namespace hk {
+
+hipError_t launch_core_f32_surrogate(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges,
+                                     int64_t n_tiles, int32_t n_points, float* sum, float* comp,
+                                     const void* surrogate, const uint8_t* mask, hipStream_t s)
+{
+    if (n_tiles == 0) return hipSuccess;
+    core_f32_surrogate_kernel<<<dim3((unsigned)n_tiles), dim3(64 * kWaves), 0, s>>>(
+        idx, core, ranges, n_tiles, n_points, sum, comp, static_cast<const surr::MlpBf16*>(surrogate), mask);
+    return hipGetLastError();
+}
+
+}  // namespace hk

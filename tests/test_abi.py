@@ -170,3 +170,24 @@ def test_options_need_a_context_and_valid_values():
     assert hk.lib().hk_set_option(None, b"tables_autotune", 2) == hk.HK_EINVAL
     assert hk.lib().hk_set_option(None, b"tables_batch", -1) == hk.HK_EINVAL
     assert hk.lib().hk_set_option(None, b"no_such_option", 1) == hk.HK_EINVAL
+
+
+def test_surrogate_calls_validate_arguments():
+    L = hk.lib()
+    assert L.hk_surrogate_labels(None, None, None, 5, None) == hk.HK_EINVAL
+    assert "x and y" in hk.hk_last_error(None)
+    assert L.hk_surrogate_labels(None, 1, 1, -1, 1) == hk.HK_EINVAL
+    theta = np.zeros(hk.HK_SURR_N_PARAMS, dtype=np.float32)
+    theta[17] = np.nan
+    assert L.hk_surrogate_set_params(None, theta.ctypes.data) == hk.HK_EINVAL
+    assert "theta[17]" in hk.hk_last_error(None)
+    assert L.hk_surrogate_grad(None, 1, 1, 1, 0, 1, None) == hk.HK_EINVAL
+    assert L.hk_surrogate_grad(None, 1, 1, 1, hk.HK_SURR_MAX_BATCH + 1, 1, None) == hk.HK_EINVAL
+    cfg = hk.hk_train_cfg(0, 10, 1e-3, 0.9, 0.999, 1e-8)
+    assert L.hk_surrogate_train(None, 1, 1, 1, 100, C.byref(cfg), None) == hk.HK_EINVAL
+    assert "batch" in hk.hk_last_error(None)
+    cfg = hk.hk_train_cfg(64, 10, 1e-3, 1.0, 0.999, 1e-8)
+    assert L.hk_surrogate_train(None, 1, 1, 1, 100, C.byref(cfg), None) == hk.HK_EINVAL
+    assert L.hk_surrogate_certify(None, 0.0, None, None) == hk.HK_EINVAL
+    assert L.hk_surrogate_certify(None, 1e-5, None, None) == hk.HK_EINVAL
+    assert "context" in hk.hk_last_error(None)
