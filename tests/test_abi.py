@@ -181,12 +181,14 @@ def test_surrogate_calls_validate_arguments():
     theta[17] = np.nan
     assert L.hk_surrogate_set_params(None, theta.ctypes.data) == hk.HK_EINVAL
     assert "theta[17]" in hk.hk_last_error(None)
-    assert L.hk_surrogate_grad(None, 1, 1, 1, 0, 1, None) == hk.HK_EINVAL
-    assert L.hk_surrogate_grad(None, 1, 1, 1, hk.HK_SURR_MAX_BATCH + 1, 1, None) == hk.HK_EINVAL
-    cfg = hk.hk_train_cfg(0, 10, 1e-3, 0.9, 0.999, 1e-8)
+    assert L.hk_surrogate_grad(None, 1, 1, 1, 0, 0.0, 1, None) == hk.HK_EINVAL
+    assert L.hk_surrogate_grad(None, 1, 1, 1, hk.HK_SURR_MAX_BATCH + 1, 0.0, 1, None) == hk.HK_EINVAL
+    assert L.hk_surrogate_grad(None, 1, 1, 1, 64, -1.0, 1, None) == hk.HK_EINVAL
+    assert "wscale" in hk.hk_last_error(None)
+    cfg = hk.hk_train_cfg(0, 10, 1e-3, 0.9, 0.999, 1e-8, 0.0)
     assert L.hk_surrogate_train(None, 1, 1, 1, 100, C.byref(cfg), None) == hk.HK_EINVAL
     assert "batch" in hk.hk_last_error(None)
-    cfg = hk.hk_train_cfg(64, 10, 1e-3, 1.0, 0.999, 1e-8)
+    cfg = hk.hk_train_cfg(64, 10, 1e-3, 1.0, 0.999, 1e-8, 0.0)
     assert L.hk_surrogate_train(None, 1, 1, 1, 100, C.byref(cfg), None) == hk.HK_EINVAL
     assert L.hk_surrogate_certify(None, 0.0, None, None) == hk.HK_EINVAL
     assert L.hk_surrogate_certify(None, 1e-5, None, None) == hk.HK_EINVAL
