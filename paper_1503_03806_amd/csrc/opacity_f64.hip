@@ -111,7 +111,6 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, const WingRec* __restri
     static_assert(kP % 2 == 0, "points are processed in pairs");
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ WingRec tile[kTL];
-    __shared__ WingIdx tidx[kTL];
     __shared__ uint32_t code[kTL];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -133,7 +132,6 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, const WingRec* __restri
         if ((int)threadIdx.x < cnt) {
             tile[threadIdx.x] = wing[base + threadIdx.x];
             const WingIdx r = idx[base + threadIdx.x];
-            tidx[threadIdx.x] = r;
             uint32_t c = 0;
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) {
@@ -192,10 +190,12 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, const WingRec* __restri
             const double B = tile[k].B, C = tile[k].C, Bn = tile[k].Bn, Cn = tile[k].Cn;
             // general path: window edges, region edges, core points (left to
             // the core kernel), the grid end, lines outside the pairing range
-            const int32_t wlo = tidx[k].wlo, whi = tidx[k].whi;
-            const int32_t g3lo = tidx[k].g3lo, g3hi = tidx[k].g3hi;
-            const int32_t clo = tidx[k].clo, chi = tidx[k].chi;
-            const bool safe = (tidx[k].flags & kPairSafe) != 0;
+            // (rare: the index record is read from memory, not staged)
+            const WingIdx ri = idx[base + k];
+            const int32_t wlo = ri.wlo, whi = ri.whi;
+            const int32_t g3lo = ri.g3lo, g3hi = ri.g3hi;
+            const int32_t clo = ri.clo, chi = ri.chi;
+            const bool safe = (ri.flags & kPairSafe) != 0;
 #pragma unroll
             for (int p = 0; p < kP; p += 2) {
                 double num[2], den[2];
@@ -282,35 +282,71 @@ __global__ __launch_bounds__(64 * kWaves) void wing_f64_batched_kernel(
 //   H = e^{-x^2} [erfcx(y) cos 2xy + sin(xy) (sin(xy)/y) / pi]
 //     + (y/pi) [ -cos(2xy) e^{-x^2} T1 + (S2 + S3)/2 ],
 // x = |u|, y = a, T1 = sum_n e^{-n^2/4}/(n^2/4+y^2) (per line), and
-// S2 + S3 = sum_n (e^{-(n/2+x)^2} + e^{-(n/2-x)^2}) / (n^2/4 + y^2).  The
-// Gaussians come from geometric-ratio recurrences instead of an exp() per
-// term; inv[n-1] = 1/(n^2/4 + y^2) is the line's table (same y for all its
-// points), read from LDS.
-__device__ double voigt_core(double x, double y, double ex, double T1, const double* inv)
+// S2 + S3 = sum_n (e^{-(n/2+x)^2} + e^{-(n/2-x)^2}) / (n^2/4 + y^2)
+//         = 2 e^{-x^2} sum_n w_n cosh(n x),  w_n = e^{-n^2/4} / (n^2/4 + y^2),
+// so that H = e^{-x^2} [erfcx(y) cos 2xy + sin^2(xy)/(pi y)
+//                        + (y/pi) (sum_n w_n cosh(nx) - cos(2xy) T1)].
+// cosh(nx) comes from the powers e^{+-nx} by recurrence (at most e^{340},
+// x < 10, n <= 34); w[n-1] is the line's table (same y for all its points),
+// read from LDS.
+// e^{-n^2/4}, n = 1 .. kMaxTerms
+__constant__ double kGauss[kMaxTerms] = {
+    0.77880078307140488,
+    0.36787944117144233,
+    0.10539922456186433,
+    0.018315638888734179,
+    0.0019304541362277093,
+    0.00012340980408667956,
+    4.7851173921290088e-06,
+    1.1253517471925912e-07,
+    1.6052280551856116e-09,
+    1.3887943864964021e-11,
+    7.2877240958196922e-14,
+    2.3195228302435696e-16,
+    4.4777324417183015e-19,
+    5.2428856633634639e-22,
+    3.7233631217505106e-25,
+    1.6038108905486379e-28,
+    4.1900931944943974e-32,
+    6.6396771995807348e-36,
+    6.3815034480607908e-40,
+    3.7200759760208361e-44,
+    1.3153258948574645e-48,
+    2.8207700884601352e-53,
+    3.6690596154291634e-58,
+    2.8946403116483003e-63,
+    1.3851193699226017e-68,
+    4.0200602157433552e-74,
+    7.0766981754295491e-80,
+    7.5558190197119609e-86,
+    4.8931122620973616e-92,
+    1.9219477278238491e-98,
+    4.5787899692915775e-105,
+    6.6162610567094853e-112,
+    5.7986554185640377e-119,
+    3.0824406969490981e-126,
+};
+
+__device__ double voigt_core(double x, double y, double ex, double T1, const double* w)
 {
-    const double c = 0.77880078307140486825;  // e^{-1/4}
-    const double d = 0.60653065971263342360;  // e^{-1/2}
     const double E = exp(-x * x);
     const double up = exp(x);
     const double dn = qrcp(up);
-    double g3 = E * up * c;  // e^{-(1/2 - x)^2}
-    double g2 = E * dn * c;  // e^{-(1/2 + x)^2}
-    double r3 = up * (c * d);
-    double r2 = dn * (c * d);
-    const int N = min(2 * (int)ceil(x) + 14, kMaxTerms);  // x < 10 here
-    double s23 = 0.0;
-    for (int n = 0; n < N; ++n) {
-        s23 = fma(g2 + g3, inv[n], s23);
-        g3 *= r3;
-        r3 *= d;
-        g2 *= r2;
-        r2 *= d;
+    // all kMaxTerms terms for every point (x < 10, so at least the
+    // 2 ceil(x) + 14 terms the series needs; the rest are below 1e-20 of the
+    // sum): a fixed trip count, the same for every lane
+    double p = up, q = dn, sc = 0.0;
+#pragma unroll 2
+    for (int n = 0; n < kMaxTerms; ++n) {
+        sc = fma(w[n], p + q, sc);
+        p *= up;
+        q *= dn;
     }
     double s, co;
     sincos(x * y, &s, &co);
     const double cos2 = (co - s) * (co + s);
     const double sy = (y > 0.0) ? qdiv(s, y) : x;
-    return E * fma(ex, cos2, s * sy * kInvPi) + (y * kInvPi) * fma(-cos2 * E, T1, 0.5 * s23);
+    return E * (fma(ex, cos2, s * sy * kInvPi) + (y * kInvPi) * fma(-cos2, T1, 0.5 * sc));
 }
 
 // Core-region contributions: each wavefront owns a run of 64*P points as in
@@ -346,7 +382,7 @@ __device__ __forceinline__ void core_f64_tile(int64_t t, const WingRec* __restri
         const CoreRec cr = core[i];
         if (lane < kMaxTerms) {
             const double m = 0.5 * (double)(lane + 1);
-            inv[lane] = qrcp(fma(m, m, cr.y2));
+            inv[lane] = kGauss[lane] * qrcp(fma(m, m, cr.y2));
         }
         __builtin_amdgcn_wave_barrier();
         for (int32_t c0 = a; c0 <= b; c0 += 64) {
