@@ -216,47 +216,39 @@ __global__ __launch_bounds__(64 * kWaves) void wing_f32_batched_kernel(
     }
 }
 
-// The core series in binary32 (see voigt_core in opacity_f64.hip for the
-// formula).  e^{-(n/2 - x)^2} underflows binary32 at n = 1 for x near 10, so
-// its recurrence starts at the largest term n0 = round(2x) and runs both
-// ways; the e^{-(n/2 + x)^2} terms are below e^{-x^2} and run forward from
-// n = 1 (where they underflow they are negligible against the result).
+// The core series in binary32 (the formula of voigt_core in
+// opacity_f64.hip).  Binary32 cannot hold e^{+-nx} (x up to 10, n up to
+// 34), so the Gaussians are summed directly, each over a fixed window of
+// terms that holds everything above 2e-9 of its largest term:
+//   e^{-(n/2 - x)^2}: 19 terms from n = max(1, round(2x) - 9), by the ratio
+//     recurrence g(n+1) = g(n) e^{x - n/2 - 1/4}, started at its largest
+//     term so that nothing underflows before it matters;
+//   e^{-(n/2 + x)^2}: n = 1 .. 9 (below e^{-20} of e^{-x^2} beyond).
+// The trip counts are the same for every lane.
 __device__ float voigt_core_f32(float x, float y, float ex, float T1, const float* inv)
 {
     const float d = 0.60653065971263342f;  // e^{-1/2}
-    // x < 10 in the core region; the clamp guards the table against the
-    // binary32 rounding of x near 10
-    const int N = min(2 * (int)ceilf(x) + 14, kMaxTerms);
     const float E = expf(-x * x);
-    int n0 = (int)rintf(2.0f * x);
-    n0 = n0 < 1 ? 1 : (n0 > N ? N : n0);
-    const float h0 = 0.5f * (float)n0 - x;
-    const float g0 = expf(-h0 * h0);
+    const int st = max(1, (int)rintf(2.0f * x) - 9);
     float s3 = 0.0f;
-    {  // n = n0, n0-1, ..., 1: g(n-1) = g(n) e^{n/2 - 1/4 - x}
-        float g = g0, q = expf(h0 - 0.25f);
-        for (int n = n0; n >= 1; --n) {
-            s3 = fmaf(g, inv[n - 1], s3);
-            g *= q;
-            q *= d;
-        }
-    }
-    {  // n = n0+1, ..., N: g(n+1) = g(n) e^{x - 1/4 - n/2}
-        float r = expf(-h0 - 0.25f);
-        float g = g0 * r;
-        r *= d;
-        for (int n = n0 + 1; n <= N; ++n) {
-            s3 = fmaf(g, inv[n - 1], s3);
+    {
+        const float h = 0.5f * (float)st - x;
+        float g = expf(-h * h);
+        float r = expf(-h - 0.25f);  // e^{x - st/2 - 1/4}
+#pragma unroll
+        for (int k = 0; k < 19; ++k) {
+            s3 = fmaf(g, inv[st - 1 + k], s3);
             g *= r;
             r *= d;
         }
     }
     float s2 = 0.0f;
-    {  // e^{-(n/2 + x)^2}, n = 1 .. N
+    {  // e^{-(n/2 + x)^2}, n = 1 .. 9
         const float c = 0.77880078307140487f;  // e^{-1/4}
         const float dn = expf(-x);
         float g = E * dn * c, r = dn * c * d;
-        for (int n = 1; n <= N; ++n) {
+#pragma unroll
+        for (int n = 1; n <= 9; ++n) {
             s2 = fmaf(g, inv[n - 1], s2);
             g *= r;
             r *= d;
