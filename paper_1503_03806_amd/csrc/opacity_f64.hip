@@ -111,7 +111,7 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, const WingRec* __restri
     static_assert(kP % 2 == 0, "points are processed in pairs");
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ WingRec tile[kTL];
-    __shared__ uint32_t code[kTL];
+    __shared__ uint8_t code[kWaves][kTL];  // path of each staged line, per wavefront
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int32_t tile0 = (int32_t)(t * kTilePoints);
@@ -132,20 +132,26 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, const WingRec* __restri
         if ((int)threadIdx.x < cnt) {
             tile[threadIdx.x] = wing[base + threadIdx.x];
             const WingIdx r = idx[base + threadIdx.x];
-            uint32_t c = 0;
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) {
                 const int32_t r0 = tile0 + w * 64 * kP;
                 const int32_t r1 = min(r0 + 64 * kP, n) - 1;
-                c |= classify(r, r0, r1, r0 + 64 * kP - 1) << (8 * w);
+                code[w][threadIdx.x] = (uint8_t)classify(r, r0, r1, r0 + 64 * kP - 1);
             }
-            code[threadIdx.x] = c;
         }
         __syncthreads();
         // runs of consecutive lines on the same path are looped over
         // without leaving the path (keeps the accumulators in place)
+        // (the codes of four consecutive lines are read at once)
+        const uint32_t* codes = reinterpret_cast<const uint32_t*>(code[wave]);
+        uint32_t cword = 0;
+        int cbase = -4;
         auto path_of = [&](int kk) -> uint32_t {
-            return ((uint32_t)__builtin_amdgcn_readfirstlane((int)code[kk]) >> (8 * wave)) & 0xffu;
+            if ((kk & ~3) != cbase) {
+                cbase = kk & ~3;
+                cword = (uint32_t)__builtin_amdgcn_readfirstlane((int)codes[kk >> 2]);
+            }
+            return (cword >> (8 * (kk & 3))) & 0xffu;
         };
         int k = 0;
         while (k < cnt) {
