@@ -114,7 +114,7 @@ def bench_tables(hk, torch, ctx, g):
             "stage_ms": {k: v[0] for k, v in tm.items()}}
 
 
-def bench_surrogate(hk, torch, ctx):
+def bench_surrogate(hk, torch, ctx, n_lines: int = 0, train_steps: int = 0):
     """The learned surrogate: trained on 1e7 samples (x in [0, 50], y in
     [1e-4, 1e2], targets from the plain method), certified at a 2e-5
     per-evaluation budget, then the opacity of 1e8 lines (0.01 cm^-1 grid of
@@ -122,6 +122,13 @@ def bench_surrogate(hk, torch, ctx):
     binary32 path and with the binary64 path; error against binary64."""
     import synth
     w = synth.WORKLOADS["lines1e8_surrogate"]
+    if n_lines:
+        import dataclasses
+        w = dataclasses.replace(w, n_lines=n_lines)
+    schedule = SURROGATE_SCHEDULE
+    if train_steps:
+        total = sum(s for s, _ in schedule)
+        schedule = tuple((max(1, s * train_steps // total), lr) for s, lr in schedule)
     log("bench: surrogate training")
     x, y = synth.surrogate_samples(10_000_000, seed=7)
     xd = torch.tensor(x, device="cuda")
@@ -131,7 +138,7 @@ def bench_surrogate(hk, torch, ctx):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hist = []
-    for steps, lr in SURROGATE_SCHEDULE:
+    for steps, lr in schedule:
         hist.append(ctx.surrogate_train(xd, yd, zd, batch=4096, steps=steps, lr=lr,
                                         wscale=SURROGATE_WSCALE))
     torch.cuda.synchronize()
@@ -161,7 +168,8 @@ def bench_surrogate(hk, torch, ctx):
         res[name] = (k, dt, {kk: v[0] / max(v[1], 1) for kk, v in tm.items()})
     evals = ctx.stats()["evals"]
     ref = res["f64"][0]
-    out = {"workload": w.name, "n_lines": w.n_lines, "evals": evals,
+    out = {"workload": w.name if not n_lines else "%s (%d lines)" % (w.name, n_lines),
+           "n_lines": w.n_lines, "evals": evals,
            "train_samples": 10_000_000, "train_steps": int(len(hist)), "train_s": train_s,
            "loss_first": float(hist[0]), "loss_last100": float(hist[-100:].mean()),
            "certified_cells": count, "cells": int(err.size), "budget": 2e-5}
@@ -183,6 +191,10 @@ def main(argv=None):
     ap.add_argument("--no-f32", action="store_true", help="skip the binary32 variant")
     ap.add_argument("--no-tables", action="store_true", help="skip the batched tables")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate workload")
+    ap.add_argument("--surrogate-lines", type=int, default=0,
+                    help="lines of the surrogate leg (default: the workload's 1e8; fewer for profiling)")
+    ap.add_argument("--surrogate-train-steps", type=int, default=0,
+                    help="Adam steps of the surrogate training (default: the full recipe)")
     ap.add_argument("--cpu-points", type=int, default=300000,
                     help="grid points in the oracle's timed sample")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -284,7 +296,7 @@ def main(argv=None):
         log("bench: timing the oracle on a sample")
         rec["cpu_baseline"] = cpu_baseline(w, a.cpu_points)
     if not a.no_surrogate:
-        rec["surrogate"] = bench_surrogate(hk, torch, ctx)
+        rec["surrogate"] = bench_surrogate(hk, torch, ctx, a.surrogate_lines, a.surrogate_train_steps)
     ctx.close()
     print(json.dumps(rec), flush=True)
     return 0
