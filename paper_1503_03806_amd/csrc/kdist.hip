@@ -41,20 +41,22 @@ __device__ inline double key_value<uint32_t>(uint32_t k)
 
 // Sort s[0 .. npad) ascending in LDS; npad is a power of two, all threads of
 // the block take part.
+// Each stage has npad/2 compare-exchange pairs (i, i + j), i with bit j
+// clear; thread t takes pairs t, t + blockDim, ... so that every lane works.
 template <typename K>
 __device__ void bitonic_lds(K* s, int npad)
 {
+    const int half = npad >> 1;
     for (int k = 2; k <= npad; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < npad; i += blockDim.x) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const K a = s[i], b = s[ixj];
-                    const bool up = (i & k) == 0;
-                    if ((a > b) == up) {
-                        s[i] = b;
-                        s[ixj] = a;
-                    }
+            for (int q = threadIdx.x; q < half; q += blockDim.x) {
+                const int i = ((q & ~(j - 1)) << 1) | (q & (j - 1));
+                const int ixj = i + j;
+                const K a = s[i], b = s[ixj];
+                const bool up = (i & k) == 0;
+                if ((a > b) == up) {
+                    s[i] = b;
+                    s[ixj] = a;
                 }
             }
             __syncthreads();
