@@ -202,6 +202,38 @@ int hk_kdist(hk_ctx* ctx, const void* kappa, int precision, int64_t n_points,
 int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_grid* grid,
               const hk_bins* bins, int precision, double* k_out);
 
+/* ---- §2.6, eq. (5): resampling and transmission ---------------------------- */
+
+#define HK_MAX_COEF 32             /* most Chebyshev coefficients per bin */
+#define HK_MAX_COLUMNS (1 << 20)   /* most column masses per call */
+#define HK_TRANSMISSION_NODES 100  /* Gauss-Legendre nodes of hk_transmission */
+
+/* Least-squares Chebyshev fit of ln kappa(y) per bin (§2.6), solved by the
+ * QR decomposition of the design matrix A[i][c] = T_c(t_i),
+ * t_i = 2 y_i - 1, y_i = (i + 1/2)/M for the i-th smallest of the bin's M
+ * values (one thin Householder QR per bin size, computed on the host and
+ * cached; per bin the kernel forms Q^T d and solves R C = Q^T d).
+ *   sorted   [device] the bins sorted ascending, as hk_kdist's sorted_out
+ *            (double for HK_F64, float for HK_F32_KAHAN keys)
+ *   coef_out [device] double [n_bins][n_coef]
+ * Values <= 0 are clamped to the smallest positive normal double before
+ * the logarithm.  Every bin needs at least n_coef points (HK_EINVAL). */
+int hk_resample(hk_ctx* ctx, const void* sorted, int precision, int64_t n_points,
+                int64_t points_per_bin, int32_t n_coef, double* coef_out);
+
+/* Transmission function T(m) = int_0^1 exp(-kappa(y) m) dy (eq. 5) from
+ * the fitted coefficients, by the HK_TRANSMISSION_NODES-node
+ * Gauss-Legendre rule on [0, 1]:
+ *   coef  [device] double [n_bins][n_coef];  m_col [device] double [n_m]
+ *   T_out [device] double [n_bins][n_m] */
+int hk_transmission(hk_ctx* ctx, const double* coef, int64_t n_bins, int32_t n_coef,
+                    const double* m_col, int32_t n_m, double* T_out);
+
+/* The same from the sorted values themselves: T(m) = (1/M) sum_i
+ * exp(-kappa_i m) per bin (the reference for the resampling error). */
+int hk_transmission_direct(hk_ctx* ctx, const void* sorted, int precision, int64_t n_points,
+                           int64_t points_per_bin, const double* m_col, int32_t n_m, double* T_out);
+
 /* ---- learned surrogate of K(x, y) = H_V(a = y, u = x) ---------------------
  * Not part of the paper's method: a network that stands in for the series
  * (§2.4) where a certification against the series allows it; the series

@@ -22,7 +22,8 @@ __all__ = ["HK_OK", "HK_EINVAL", "HK_ENOMEM", "HK_EDEVICE", "HK_EUNSUPPORTED", "
            "HK_SURR_N_PARAMS", "HK_SURR_CELLS_X", "HK_SURR_CELLS_Y", "hk_train_cfg",
            "hk_surrogate_labels", "hk_surrogate_set_params", "hk_surrogate_get_params",
            "hk_surrogate_grad", "hk_surrogate_train", "hk_surrogate_eval", "hk_surrogate_certify",
-           "Context", "LIB_PATH"]
+           "hk_resample", "hk_transmission", "hk_transmission_direct", "HK_MAX_COEF",
+           "HK_TRANSMISSION_NODES", "Context", "LIB_PATH"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhk.so")
 
@@ -30,6 +31,7 @@ HK_OK, HK_EINVAL, HK_ENOMEM, HK_EDEVICE, HK_EUNSUPPORTED, HK_ENOTREADY = 0, -1, 
 HK_F64, HK_F32_KAHAN, HK_F32_SURROGATE = 0, 1, 2
 HK_SURR_N_PARAMS, HK_SURR_MAX_BATCH = 12737, 65536
 HK_SURR_CELLS_X, HK_SURR_CELLS_Y = 80, 40
+HK_MAX_COEF, HK_MAX_COLUMNS, HK_TRANSMISSION_NODES = 32, 1 << 20, 100
 HK_MAX_G = 64
 HK_MAX_POINTS = 1 << 30
 
@@ -116,6 +118,11 @@ def lib():
         L.hk_surrogate_train.argtypes = [vp, vp, vp, vp, i64, C.POINTER(hk_train_cfg), vp]
         L.hk_surrogate_eval.argtypes = [vp, vp, vp, i64, vp, vp]
         L.hk_surrogate_certify.argtypes = [vp, C.c_double, vp, C.POINTER(C.c_int32)]
+        L.hk_resample.argtypes = [vp, vp, i32, i64, i64, C.c_int32, vp]
+        L.hk_transmission.argtypes = [vp, vp, i64, C.c_int32, vp, C.c_int32, vp]
+        L.hk_transmission_direct.argtypes = [vp, vp, i32, i64, i64, vp, C.c_int32, vp]
+        for f in ("hk_resample", "hk_transmission", "hk_transmission_direct"):
+            getattr(L, f).restype = i32
         for f in ("labels", "set_params", "get_params", "grad", "train", "eval", "certify"):
             getattr(L, "hk_surrogate_" + f).restype = i32
         L.hk_get_timing.argtypes = [vp, C.POINTER(hk_timing)]; L.hk_get_timing.restype = i32
@@ -267,6 +274,10 @@ def hk_surrogate_certify(ctx, budget: float):
     return err, int(cnt.value)
 
 
+def _count(a) -> int:
+    return int(a.numel() if hasattr(a, "numel") else len(a))
+
+
 def _numel(*arrays) -> int:
     n = {int(a.numel() if hasattr(a, "numel") else len(a)) for a in arrays}
     if len(n) != 1:
@@ -275,6 +286,24 @@ def _numel(*arrays) -> int:
         if hasattr(a, "dtype") and str(a.dtype) not in ("torch.float32", "float32"):
             raise ValueError("surrogate arrays are float32 (got %s)" % a.dtype)
     return n.pop()
+
+
+def hk_resample(ctx, sorted_kappa, precision: int, n_points: int, points_per_bin: int, n_coef: int,
+                coef_out):
+    _check(lib().hk_resample(ctx, _ptr(sorted_kappa), int(precision), int(n_points),
+                             int(points_per_bin), int(n_coef), _ptr(coef_out)), ctx)
+
+
+def hk_transmission(ctx, coef, n_bins: int, n_coef: int, m_col, T_out):
+    _check(lib().hk_transmission(ctx, _ptr(coef), int(n_bins), int(n_coef), _ptr(m_col),
+                                 _count(m_col), _ptr(T_out)), ctx)
+
+
+def hk_transmission_direct(ctx, sorted_kappa, precision: int, n_points: int, points_per_bin: int,
+                           m_col, T_out):
+    _check(lib().hk_transmission_direct(ctx, _ptr(sorted_kappa), int(precision), int(n_points),
+                                        int(points_per_bin), _ptr(m_col), _count(m_col),
+                                        _ptr(T_out)), ctx)
 
 
 def hk_gauss_legendre(n: int):
@@ -368,6 +397,29 @@ class Context:
                               device="cuda:%d" % self.device)
         hk_tables(self.h, states, grid, points_per_bin, g, precision, out)
         return out
+
+    # -- resampling and transmission (float64 device tensors) --
+    def resample(self, sorted_kappa, points_per_bin: int, n_coef: int = 20, precision: int = HK_F64):
+        torch = self._torch
+        n = sorted_kappa.numel()
+        n_bins = -(-n // points_per_bin)
+        coef = torch.empty((n_bins, n_coef), dtype=torch.float64, device=sorted_kappa.device)
+        hk_resample(self.h, sorted_kappa, precision, n, points_per_bin, n_coef, coef)
+        return coef
+
+    def transmission(self, coef, m_col):
+        torch = self._torch
+        T = torch.empty((coef.shape[0], m_col.numel()), dtype=torch.float64, device=coef.device)
+        hk_transmission(self.h, coef, coef.shape[0], coef.shape[1], m_col, T)
+        return T
+
+    def transmission_direct(self, sorted_kappa, points_per_bin: int, m_col, precision: int = HK_F64):
+        torch = self._torch
+        n = sorted_kappa.numel()
+        T = torch.empty((-(-n // points_per_bin), m_col.numel()), dtype=torch.float64,
+                        device=sorted_kappa.device)
+        hk_transmission_direct(self.h, sorted_kappa, precision, n, points_per_bin, m_col, T)
+        return T
 
     # -- learned surrogate (float32 device tensors) --
     def surrogate_labels(self, x, y):

@@ -86,6 +86,12 @@ struct hk_ctx {
     // compute copy, training partials, certification errors and mask
     DevBuf sg_theta, sg_m, sg_v, sg_copy, sg_part, sg_ploss, sg_err, sg_mask;
     bool sg_loaded = false, sg_certified = false;
+    // resampling: QR factors of the Chebyshev design matrix for the bin
+    // sizes of the last call (main and ragged last bin), and the quadrature
+    DevBuf rs_Q, rs_R, rs_Ql, rs_Rl, rs_quad;
+    int64_t rs_m = -1, rs_ml = -1;
+    int rs_nc = 0;
+    bool rs_quad_ready = false;
     int64_t sg_step = 0;  // Adam steps taken
     int64_t sg_cursor = 0;  // next training sample
     // stage timing: events recorded around each timed launch, resolved
@@ -335,6 +341,80 @@ int autotune_wing(hk_ctx* ctx, int precision, const hk_state* states, int32_t n_
 
 }  // namespace
 
+namespace {
+
+// Thin QR of the m x nc Chebyshev design matrix A[i][c] = T_c(t_i),
+// t_i = 2 (i + 1/2)/m - 1, by Householder reflections (Golub & Van Loan,
+// Alg. 5.2.1): Q row-major [m][nc], R row-major [nc][nc] upper triangular.
+void chebyshev_qr(int64_t m, int nc, std::vector<double>& Q, std::vector<double>& R)
+{
+    std::vector<double> A((size_t)m * nc);
+    for (int64_t i = 0; i < m; ++i) {
+        const double t = 2.0 * ((double)i + 0.5) / (double)m - 1.0;
+        double tm = 1.0, tc = t;
+        A[(size_t)i * nc] = 1.0;
+        if (nc > 1) A[(size_t)i * nc + 1] = t;
+        for (int c = 2; c < nc; ++c) {
+            const double tn = 2.0 * t * tc - tm;
+            tm = tc;
+            tc = tn;
+            A[(size_t)i * nc + c] = tn;
+        }
+    }
+    std::vector<std::vector<double>> V(nc);  // reflector k acts on rows k..m-1
+    for (int k = 0; k < nc; ++k) {
+        double nrm = 0.0;
+        for (int64_t i = k; i < m; ++i) nrm += A[(size_t)i * nc + k] * A[(size_t)i * nc + k];
+        nrm = std::sqrt(nrm);
+        std::vector<double> v((size_t)(m - k));
+        for (int64_t i = k; i < m; ++i) v[(size_t)(i - k)] = A[(size_t)i * nc + k];
+        const double alpha = v[0] >= 0.0 ? -nrm : nrm;
+        v[0] -= alpha;
+        double vn = 0.0;
+        for (double x : v) vn += x * x;
+        if (vn > 0.0) {
+            for (int c = k; c < nc; ++c) {
+                double dot = 0.0;
+                for (int64_t i = k; i < m; ++i) dot += v[(size_t)(i - k)] * A[(size_t)i * nc + c];
+                const double f = 2.0 * dot / vn;
+                for (int64_t i = k; i < m; ++i) A[(size_t)i * nc + c] -= f * v[(size_t)(i - k)];
+            }
+        }
+        V[k] = std::move(v);
+    }
+    R.assign((size_t)nc * nc, 0.0);
+    for (int r = 0; r < nc; ++r)
+        for (int c = r; c < nc; ++c) R[(size_t)r * nc + c] = A[(size_t)r * nc + c];
+    // Q = H_0 ... H_{nc-1} applied to the first nc columns of the identity
+    Q.assign((size_t)m * nc, 0.0);
+    for (int c = 0; c < nc; ++c) Q[(size_t)c * nc + c] = 1.0;
+    for (int k = nc - 1; k >= 0; --k) {
+        const std::vector<double>& v = V[k];
+        double vn = 0.0;
+        for (double x : v) vn += x * x;
+        if (vn == 0.0) continue;
+        for (int c = 0; c < nc; ++c) {
+            double dot = 0.0;
+            for (int64_t i = k; i < m; ++i) dot += v[(size_t)(i - k)] * Q[(size_t)i * nc + c];
+            const double f = 2.0 * dot / vn;
+            for (int64_t i = k; i < m; ++i) Q[(size_t)i * nc + c] -= f * v[(size_t)(i - k)];
+        }
+    }
+}
+
+int upload_qr(hk_ctx* ctx, int64_t m, int nc, DevBuf& dQ, DevBuf& dR)
+{
+    std::vector<double> Q, R;
+    chebyshev_qr(m, nc, Q, R);
+    HK_HIP(ctx, dQ.ensure(Q.size() * sizeof(double)), "allocating QR factors");
+    HK_HIP(ctx, dR.ensure(R.size() * sizeof(double)), "allocating QR factors");
+    HK_HIP(ctx, hipMemcpy(dQ.p, Q.data(), Q.size() * sizeof(double), hipMemcpyHostToDevice), "copying QR factors");
+    HK_HIP(ctx, hipMemcpy(dR.p, R.data(), R.size() * sizeof(double), hipMemcpyHostToDevice), "copying QR factors");
+    return HK_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int hk_version(void) { return 100; }
@@ -394,7 +474,7 @@ int hk_destroy(hk_ctx* ctx)
                       &ctx->tb_counts})
         b->release();
     for (DevBuf* b : {&ctx->sg_theta, &ctx->sg_m, &ctx->sg_v, &ctx->sg_copy, &ctx->sg_part, &ctx->sg_ploss,
-                      &ctx->sg_err, &ctx->sg_mask})
+                      &ctx->sg_err, &ctx->sg_mask, &ctx->rs_Q, &ctx->rs_R, &ctx->rs_Ql, &ctx->rs_Rl, &ctx->rs_quad})
         b->release();
     for (auto& p : ctx->pending) {
         (void)hipEventDestroy(p.second.first);
@@ -1004,6 +1084,92 @@ int hk_surrogate_certify(hk_ctx* ctx, double budget, double* err, int32_t* n_cer
     if (err) std::memcpy(err, e.data(), e.size() * sizeof(double));
     if (n_certified) *n_certified = cnt;
     ctx->sg_certified = true;
+    return HK_OK;
+}
+
+static_assert(HK_MAX_COEF == kMaxCoef, "coefficient bound");
+static_assert(HK_TRANSMISSION_NODES <= kMaxQuad, "quadrature bound");
+
+int hk_resample(hk_ctx* ctx, const void* sorted, int precision, int64_t n_points, int64_t points_per_bin,
+                int32_t n_coef, double* coef_out)
+{
+    if (precision != HK_F64 && precision != HK_F32_KAHAN)
+        return fail(ctx, HK_EINVAL, "unknown precision %d", precision);
+    if (n_points < 0 || n_points > HK_MAX_POINTS) return fail(ctx, HK_EINVAL, "n_points out of range");
+    if (points_per_bin < 1) return fail(ctx, HK_EINVAL, "points_per_bin must be >= 1");
+    if (n_coef < 1 || n_coef > HK_MAX_COEF) return fail(ctx, HK_EINVAL, "n_coef must be in [1, %d]", HK_MAX_COEF);
+    const int64_t ml = n_points % points_per_bin;
+    if ((n_points >= points_per_bin && points_per_bin < n_coef) || (ml > 0 && ml < n_coef))
+        return fail(ctx, HK_EINVAL, "every bin needs at least n_coef = %d points", n_coef);
+    if (n_points > 0 && (!sorted || !coef_out)) return fail(ctx, HK_EINVAL, "sorted and coef_out must not be NULL");
+    if (int rc = check_ctx(ctx)) return rc;
+    if (n_points == 0) return HK_OK;
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    const int64_t m = std::min(points_per_bin, n_points);
+    if (ctx->rs_m != m || ctx->rs_nc != n_coef) {
+        HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        if (int rc = upload_qr(ctx, m, n_coef, ctx->rs_Q, ctx->rs_R)) return rc;
+        ctx->rs_m = m;
+        ctx->rs_ml = -1;
+        ctx->rs_nc = n_coef;
+    }
+    const bool ragged = n_points > points_per_bin && ml > 0;
+    if (ragged && ctx->rs_ml != ml) {
+        HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        if (int rc = upload_qr(ctx, ml, n_coef, ctx->rs_Ql, ctx->rs_Rl)) return rc;
+        ctx->rs_ml = ml;
+    }
+    const double* Ql = ragged ? static_cast<const double*>(ctx->rs_Ql.p) : static_cast<const double*>(ctx->rs_Q.p);
+    const double* Rl = ragged ? static_cast<const double*>(ctx->rs_Rl.p) : static_cast<const double*>(ctx->rs_R.p);
+    HK_HIP(ctx, launch_resample(sorted, precision == HK_F64 ? 8 : 4, n_points, points_per_bin, n_coef,
+                                static_cast<const double*>(ctx->rs_Q.p), static_cast<const double*>(ctx->rs_R.p), Ql,
+                                Rl, coef_out, ctx->stream),
+           "resample");
+    return HK_OK;
+}
+
+int hk_transmission(hk_ctx* ctx, const double* coef, int64_t n_bins, int32_t n_coef, const double* m_col,
+                    int32_t n_m, double* T_out)
+{
+    if (n_bins < 0 || n_bins > HK_MAX_POINTS) return fail(ctx, HK_EINVAL, "n_bins out of range");
+    if (n_coef < 1 || n_coef > HK_MAX_COEF) return fail(ctx, HK_EINVAL, "n_coef must be in [1, %d]", HK_MAX_COEF);
+    if (n_m < 0 || n_m > HK_MAX_COLUMNS) return fail(ctx, HK_EINVAL, "n_m must be in [0, %d]", HK_MAX_COLUMNS);
+    if (n_bins > 0 && n_m > 0 && (!coef || !m_col || !T_out))
+        return fail(ctx, HK_EINVAL, "coef, m and T_out must not be NULL");
+    if (int rc = check_ctx(ctx)) return rc;
+    if (n_bins == 0 || n_m == 0) return HK_OK;
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (!ctx->rs_quad_ready) {
+        std::vector<double> q(2 * HK_TRANSMISSION_NODES);
+        if (int rc = hk_gauss_legendre(HK_TRANSMISSION_NODES, q.data(), q.data() + HK_TRANSMISSION_NODES)) return rc;
+        HK_HIP(ctx, ctx->rs_quad.ensure(q.size() * sizeof(double)), "allocating the quadrature");
+        HK_HIP(ctx, hipMemcpy(ctx->rs_quad.p, q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice),
+               "copying the quadrature");
+        ctx->rs_quad_ready = true;
+    }
+    const double* yq = static_cast<const double*>(ctx->rs_quad.p);
+    HK_HIP(ctx, launch_transmission_fit(coef, n_bins, n_coef, yq, yq + HK_TRANSMISSION_NODES, HK_TRANSMISSION_NODES,
+                                        m_col, n_m, T_out, ctx->stream),
+           "transmission");
+    return HK_OK;
+}
+
+int hk_transmission_direct(hk_ctx* ctx, const void* sorted, int precision, int64_t n_points, int64_t points_per_bin,
+                           const double* m_col, int32_t n_m, double* T_out)
+{
+    if (precision != HK_F64 && precision != HK_F32_KAHAN)
+        return fail(ctx, HK_EINVAL, "unknown precision %d", precision);
+    if (n_points < 0 || n_points > HK_MAX_POINTS) return fail(ctx, HK_EINVAL, "n_points out of range");
+    if (points_per_bin < 1) return fail(ctx, HK_EINVAL, "points_per_bin must be >= 1");
+    if (n_m < 0 || n_m > HK_MAX_COLUMNS) return fail(ctx, HK_EINVAL, "n_m must be in [0, %d]", HK_MAX_COLUMNS);
+    if (n_points > 0 && n_m > 0 && (!sorted || !m_col || !T_out))
+        return fail(ctx, HK_EINVAL, "sorted, m and T_out must not be NULL");
+    if (int rc = check_ctx(ctx)) return rc;
+    if (n_points == 0 || n_m == 0) return HK_OK;
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    HK_HIP(ctx, launch_transmission_direct(sorted, precision == HK_F64 ? 8 : 4, n_points, points_per_bin, m_col, n_m,
+                                           T_out, ctx->stream),
+           "transmission_direct");
     return HK_OK;
 }
 

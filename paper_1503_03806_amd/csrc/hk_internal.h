@@ -208,4 +208,15 @@ hipError_t launch_surrogate_eval(const void* P, const float* x, const float* y, 
                                  hipStream_t s);
 hipError_t launch_surrogate_certify(const void* P, double* err, hipStream_t s);
 
+// Resampling and transmission (resample.hip).
+constexpr int kMaxCoef = 32;   // Chebyshev coefficients per bin
+constexpr int kMaxQuad = 128;  // quadrature nodes of the fitted transmission
+hipError_t launch_resample(const void* sorted, int key_bytes, int64_t n_points, int64_t ppb, int nc,
+                           const double* Q, const double* R, const double* Ql, const double* Rl, double* coef,
+                           hipStream_t s);
+hipError_t launch_transmission_fit(const double* coef, int64_t n_bins, int nc, const double* yq, const double* wq,
+                                   int nq, const double* m, int n_m, double* T, hipStream_t s);
+hipError_t launch_transmission_direct(const void* sorted, int key_bytes, int64_t n_points, int64_t ppb,
+                                      const double* m, int n_m, double* T, hipStream_t s);
+
 }  // namespace hk

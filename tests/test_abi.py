@@ -193,3 +193,16 @@ def test_surrogate_calls_validate_arguments():
     assert L.hk_surrogate_certify(None, 0.0, None, None) == hk.HK_EINVAL
     assert L.hk_surrogate_certify(None, 1e-5, None, None) == hk.HK_EINVAL
     assert "context" in hk.hk_last_error(None)
+
+
+def test_resample_and_transmission_validate_arguments():
+    L = hk.lib()
+    assert L.hk_resample(None, 1, 0, 100, 10, 20, 1) == hk.HK_EINVAL  # bins of 10 < 20 coefficients
+    assert "n_coef" in hk.hk_last_error(None)
+    assert L.hk_resample(None, 1, 0, 105, 100, 20, 1) == hk.HK_EINVAL  # ragged bin of 5
+    assert L.hk_resample(None, 1, 0, 100, 100, 33, 1) == hk.HK_EINVAL
+    assert L.hk_resample(None, 1, 7, 100, 100, 20, 1) == hk.HK_EINVAL
+    assert L.hk_resample(None, 1, 0, 100, 100, 20, 1) == hk.HK_EINVAL and "context" in hk.hk_last_error(None)
+    assert L.hk_transmission(None, 1, 3, 20, 1, -1, 1) == hk.HK_EINVAL
+    assert L.hk_transmission(None, None, 3, 20, 1, 5, 1) == hk.HK_EINVAL
+    assert L.hk_transmission_direct(None, 1, 0, 100, 0, 1, 5, 1) == hk.HK_EINVAL
