@@ -6,12 +6,13 @@ A step is one pass of the whole path over the mid-scale binary64 workload
 per-line scaling and windows, the Voigt evaluation and accumulation kernel,
 and the per-bin sort and k(g).  The line list is resident on the device
 before timing starts.  Beside the headline the line reports the binary32
-variant of the same step, the batched tables (the same lines over 200
-(T, P) states) and the learned surrogate (1e8 lines, 25 cm^-1 cutoff,
-against the binary64 path).  Prints one JSON line.
+variant of the same step, the Chebyshev resampling and transmission of the
+same bins, the batched tables (the same lines over 200 (T, P) states) and
+the learned surrogate (1e8 lines, 25 cm^-1 cutoff, against the binary64
+path).  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-f32]
-                    [--no-tables] [--no-surrogate]
+                    [--no-resample] [--no-tables] [--no-surrogate]
 """
 from __future__ import annotations
 
@@ -85,6 +86,37 @@ def cpu_baseline(w, points: int):
             "sample": "grid points %d..%d (%d of %d bins) of %s, all %d lines: %d evals "
                       "in %.2f s, opacity + k(g)" % (j0, j1, (j1 - j0) // ppb, N // ppb,
                                                     w.name, len(lines["nu"]), evals, dt)}
+
+
+def bench_resample(hk, torch, ctx, kappa, N, ppb, g):
+    """Steps after k(g) on the headline grid (last binary64 opacity): sort
+    with the sorted bins kept, 20 Chebyshev coefficients per bin, and the
+    transmission for 1000 column masses per bin."""
+    import numpy as np
+    sorted_k = torch.empty_like(kappa)
+    m_col = torch.tensor(np.logspace(-18.0, 30.0, 1000), device="cuda")
+    def once():
+        ctx.kdist(kappa, ppb, g, sorted_out=sorted_k)
+        coef = ctx.resample(sorted_k, ppb, 20)
+        return ctx.transmission(coef, m_col)
+    once()
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        once()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    t1 = time.perf_counter()
+    coef = ctx.resample(sorted_k, ppb, 20)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    ctx.transmission(coef, m_col)
+    torch.cuda.synchronize()
+    t_tr = time.perf_counter() - t1
+    return {"bins": int(-(-N // ppb)), "n_coef": 20, "n_m": 1000,
+            "ms_sort_fit_transmission": 1e3 * dt, "ms_fit": 1e3 * t_fit, "ms_transmission": 1e3 * t_tr}
 
 
 def bench_tables(hk, torch, ctx, g):
@@ -190,6 +222,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true", help="skip the binary32 variant")
     ap.add_argument("--no-tables", action="store_true", help="skip the batched tables")
+    ap.add_argument("--no-resample", action="store_true",
+                    help="skip the Chebyshev resampling + transmission leg")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate workload")
     ap.add_argument("--surrogate-lines", type=int, default=0,
                     help="lines of the surrogate leg (default: the workload's 1e8; fewer for profiling)")
@@ -290,6 +324,8 @@ def main(argv=None):
             "ms_per_step": 1e3 * f32_elapsed / f32_steps,
             "stage_ms": {k: v[0] / max(v[1], 1) for k, v in f32_tm.items()},
             "speedup_vs_f64": (1e3 * elapsed / a.steps) / (1e3 * f32_elapsed / f32_steps)}
+    if not a.no_resample:
+        rec["resample"] = bench_resample(hk, torch, ctx, kappa, N, ppb, g)
     if not a.no_tables:
         rec["tables"] = bench_tables(hk, torch, ctx, g)
     if not a.no_cpu_baseline:
