@@ -45,7 +45,7 @@ class _Cond(C.Structure):
 
 class _Grid(C.Structure):
     _fields_ = [("nu_min", C.c_double), ("dnu", C.c_double),
-                ("n_points", C.c_int64), ("cutoff", C.c_double)]
+                ("n_points", C.c_int64), ("cutoff", C.c_double), ("cutoff_lorentz", C.c_double)]
 
 
 def lib():
@@ -169,7 +169,8 @@ def _structs(lines, cond, grid):
                                        "gamma_self", "delta", "A21")])
     cs = _Cond(cond.get("T0", 296.0), cond["mass_amu"], cond["T"], cond["P"],
                cond.get("P_self", 0.5 * cond["P"]), cond.get("q_ratio", 1.0))
-    gs = _Grid(grid["nu_min"], grid["dnu"], int(grid["n_points"]), grid["cutoff"])
+    gs = _Grid(grid["nu_min"], grid["dnu"], int(grid["n_points"]), grid["cutoff"],
+               float(grid.get("cutoff_lorentz", 0.0)))
     return Ls, cs, gs, keep
 
 

@@ -230,6 +230,7 @@ typedef struct {
     int64_t* wlo;
     int64_t* whi;
     double max_shift;
+    double max_cut;  /* largest cutoff over the lines */
 } prepped_t;
 
 static void free_prepped(prepped_t* p)
@@ -251,6 +252,7 @@ static int check_inputs(const ora_lines* L, const ora_conditions* c,
         !(c->q_ratio > 0.0))
         return -1;
     if (!(g->dnu > 0.0) || g->n_points < 0 || !(g->cutoff >= 0.0)) return -1;
+    if (!(g->cutoff_lorentz >= 0.0) || !isfinite(g->cutoff_lorentz)) return -1;
     for (int64_t i = 0; i < L->n; ++i)
         if (!(L->nu[i] > 0.0)) return -1;
     return 0;
@@ -285,6 +287,7 @@ static int prep_lines(const ora_lines* L, const ora_conditions* c,
     }
     qsort(keys, (size_t)n, sizeof(key_t_), cmp_key);
     p->max_shift = 0.0;
+    p->max_cut = 0.0;
     for (int64_t k = 0; k < n; ++k) {
         int64_t i = keys[k].idx;
         double nu = L->nu[i];
@@ -301,7 +304,10 @@ static int prep_lines(const ora_lines* L, const ora_conditions* c,
         p->nu0p[k] = nu + dl * c->P / P0_ATM;
         double shift = fabs(p->nu0p[k] - nu);
         if (shift > p->max_shift) p->max_shift = shift;
-        ora_window(p->nu0p[k], g->cutoff, g->nu_min, g->dnu, g->n_points,
+        /* the cutoff: absolute, or a multiple of the line's Lorentz HWHM */
+        double cut = g->cutoff_lorentz > 0.0 ? g->cutoff_lorentz * p->GL[k] : g->cutoff;
+        if (cut > p->max_cut) p->max_cut = cut;
+        ora_window(p->nu0p[k], cut, g->nu_min, g->dnu, g->n_points,
                    &p->wlo[k], &p->whi[k]);
     }
     free(keys);
@@ -336,7 +342,7 @@ int64_t ora_opacity(const ora_lines* L, const ora_conditions* c,
      * cutoff + max shift of nu_j; one grid step of slack covers the
      * rounding of the window bounds.  Each candidate is then tested against
      * its exact window. */
-    const double reach = g->cutoff + p.max_shift + g->dnu;
+    const double reach = p.max_cut + p.max_shift + g->dnu;
     int64_t total = 0;
 
 #pragma omp parallel for schedule(static) reduction(+ : total)

@@ -88,7 +88,8 @@ typedef struct {
     double nu_min;
     double dnu;
     int64_t n_points;
-    double cutoff;
+    double cutoff;          /* cm^-1, used when cutoff_lorentz == 0 */
+    double cutoff_lorentz;  /* > 0: each line's cutoff is this many Gamma_L (§2.4, §3.4) */
 } ora_grid;
 
 /* Opacity kappa_j for the grid points j in [j_begin, j_end), written to

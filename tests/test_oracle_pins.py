@@ -410,3 +410,32 @@ def test_p13_bin_mean_transmission_invariant_under_sorting():
             t_x = np.mean(np.exp(-seg * m_col))
             t_y = np.mean(np.exp(-srt * m_col))
             assert abs(t_x - t_y) <= 1e-14 * max(t_x, 1e-300) + 1e-300
+
+
+def test_lorentz_width_cutoff_is_the_absolute_cutoff_of_each_line():
+    """A cutoff of k Gamma_L per line (§2.4, §3.4) equals, line by line, the
+    absolute cutoff k Gamma_L; a no-cutoff grid (cutoff beyond the span)
+    takes every line at every point."""
+    lines = synth.line_list(6, 300.0, seed=21)
+    lines["nu"] = lines["nu"] + 1000.0
+    cond = synth.conditions(1200.0, 3.0)
+    grid = {"nu_min": 1000.0, "dnu": 0.02, "n_points": 15000, "cutoff": 0.0, "cutoff_lorentz": 40.0}
+    kap, n = oracle.opacity(lines, cond, grid)
+    total = np.zeros_like(kap)
+    n_sum = 0
+    for i in range(6):
+        one = {k: v[i:i + 1] for k, v in lines.items()}
+        GL = oracle.lorentz_hwhm(0.0, one["n_air"][0], one["gamma_air"][0], one["gamma_air"][0],
+                                 cond["T"], cond["T0"], cond["P"], cond["P_self"])
+        g1 = dict(grid, cutoff=40.0 * GL, cutoff_lorentz=0.0)
+        k1, n1 = oracle.opacity(one, cond, g1)
+        total += k1
+        n_sum += n1
+        lo, hi = oracle.window(one["nu"][0], 40.0 * GL, grid["nu_min"], grid["dnu"], grid["n_points"])[:2]
+        assert n1 == hi - lo + 1
+    assert n == n_sum
+    assert np.allclose(kap, total, rtol=1e-14, atol=0)
+    # no cutoff: every line at every point
+    big = dict(grid, cutoff=1e9, cutoff_lorentz=0.0)
+    _, nb = oracle.opacity(lines, cond, big)
+    assert nb == 6 * grid["n_points"]
