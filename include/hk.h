@@ -88,6 +88,10 @@ typedef struct {
     double dnu;        /* spacing, > 0 */
     int64_t n_points;  /* 0 <= n_points <= HK_MAX_POINTS */
     double cutoff;     /* absolute line-wing cutoff, >= 0 (§2.4, §3.4) */
+    double cutoff_lorentz; /* > 0: each line's cutoff is this many of its own
+                              Lorentz HWHM Gamma_L instead (§2.4: 500 Gamma_L);
+                              0: the absolute cutoff.  A cutoff beyond the grid's
+                              span is no cutoff (every line at every point). */
 } hk_grid;
 #define HK_MAX_POINTS ((int64_t)1 << 30)
 
@@ -155,7 +159,8 @@ int hk_load_lines(hk_ctx* ctx, const hk_lines* lines, const hk_species* species)
  *   binary64; profiles in binary32 with strengths scaled by a per-state power
  *   of two; each point's terms summed in binary32 blocks of at most 256 lines
  *   whose sums are added with Kahan compensation; the compensated sum is
- *   scaled back and stored in binary64.  Requires cutoff/dnu < 2^23.
+ *   scaled back and stored in binary64.  Requires cutoff/dnu < 2^23 (for a
+ *   Lorentz-width cutoff: cutoff_lorentz * max Gamma_L / dnu < 2^23).
  * precision HK_F32_SURROGATE: as HK_F32_KAHAN, except that series-region
  *   points (a^2+u^2 < 100) whose (u, a) cell the last hk_surrogate_certify
  *   call certified take the learned surrogate instead of the series;

@@ -54,7 +54,7 @@ class hk_state(C.Structure):
 
 class hk_grid(C.Structure):
     _fields_ = [("nu_min", C.c_double), ("dnu", C.c_double), ("n_points", C.c_int64),
-                ("cutoff", C.c_double)]
+                ("cutoff", C.c_double), ("cutoff_lorentz", C.c_double)]
 
 
 class hk_bins(C.Structure):
@@ -198,7 +198,8 @@ def _state(st: dict) -> hk_state:
 
 
 def _grid(g: dict) -> hk_grid:
-    return hk_grid(float(g["nu_min"]), float(g["dnu"]), int(g["n_points"]), float(g["cutoff"]))
+    return hk_grid(float(g["nu_min"]), float(g["dnu"]), int(g["n_points"]), float(g["cutoff"]),
+                   float(g.get("cutoff_lorentz", 0.0)))
 
 
 def hk_opacity(ctx, state: dict, grid: dict, precision: int, kappa, comp=None,

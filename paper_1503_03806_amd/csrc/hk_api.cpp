@@ -53,6 +53,8 @@ struct hk_ctx {
     bool lines_loaded = false;
     bool has_self = false, has_delta = false, has_A = false;
     double max_abs_delta = 0.0;
+    // bounds of the width parameters, for the reach of Lorentz-width cutoffs
+    double max_gamma_air = 0.0, max_gamma_self = 0.0, max_A21 = 0.0, min_n_air = 0.0, max_n_air = 0.0;
     double nu_max = 0.0;  // largest line centre (bounds the Doppler core widths)
     double last_P = 0.0;  // pressure of the state being computed
     hk_species species{296.0, 0.0};
@@ -160,6 +162,8 @@ int check_grid(hk_ctx* ctx, const hk_grid* g)
                     (long long)g->n_points);
     if (!isfin(g->cutoff) || !(g->cutoff >= 0.0))
         return fail(ctx, HK_EINVAL, "cutoff must be finite and >= 0 (got %g)", g->cutoff);
+    if (!isfin(g->cutoff_lorentz) || !(g->cutoff_lorentz >= 0.0))
+        return fail(ctx, HK_EINVAL, "cutoff_lorentz must be finite and >= 0 (got %g)", g->cutoff_lorentz);
     double last = g->nu_min + (double)(g->n_points > 0 ? g->n_points - 1 : 0) * g->dnu;
     if (!isfin(last)) return fail(ctx, HK_EINVAL, "grid end is not finite");
     return HK_OK;
@@ -252,6 +256,7 @@ PrepParams prep_params(const hk_ctx* ctx, const hk_state* st, const hk_grid* gri
     pp.nu_min = grid->nu_min;
     pp.dnu = grid->dnu;
     pp.cutoff = grid->cutoff;
+    pp.cutoff_lorentz = grid->cutoff_lorentz;
     pp.n_points = (int32_t)grid->n_points;
     return pp;
 }
@@ -261,13 +266,26 @@ PrepParams prep_params(const hk_ctx* ctx, const hk_state* st, const hk_grid* gri
 // rounding of the window bounds).  Its series region a^2+u^2 < 100 lies
 // within 10 alpha of the centre, and alpha = nu * dop is largest for the
 // largest nu.
+// The largest cutoff of any line: the absolute cutoff, or cutoff_lorentz
+// times an upper bound of Gamma_L (eq. 20 with each parameter at its
+// extreme over the loaded lines; (T/T_ref)^-n is monotone in n).
+double max_cutoff(const hk_ctx* ctx, const hk_state* st, const hk_grid* grid)
+{
+    if (!(grid->cutoff_lorentz > 0.0)) return grid->cutoff;
+    const double ts = st->T / ctx->species.T_ref;
+    const double f = std::max(std::pow(ts, -ctx->min_n_air), std::pow(ts, -ctx->max_n_air));
+    const double gl = ctx->max_A21 / (4.0 * kPi * kC) +
+                      f * (ctx->max_gamma_air * (st->P - st->P_self) + ctx->max_gamma_self * st->P_self);
+    return grid->cutoff_lorentz * gl * (1.0 + 1e-9);
+}
 double wing_reach(const hk_ctx* ctx, const hk_state* st, const hk_grid* grid)
 {
-    return grid->cutoff + ctx->max_abs_delta * st->P + 2.0 * grid->dnu;
+    return max_cutoff(ctx, st, grid) + ctx->max_abs_delta * st->P + 2.0 * grid->dnu;
 }
 double core_reach(const hk_ctx* ctx, const hk_state* st, const hk_grid* grid, const PrepParams& pp)
 {
-    return std::min(10.0 * pp.dop * ctx->nu_max, grid->cutoff) + ctx->max_abs_delta * st->P + 2.0 * grid->dnu;
+    return std::min(10.0 * pp.dop * ctx->nu_max, max_cutoff(ctx, st, grid)) + ctx->max_abs_delta * st->P +
+           2.0 * grid->dnu;
 }
 
 }  // namespace
@@ -537,6 +555,14 @@ int hk_load_lines(hk_ctx* ctx, const hk_lines* L, const hk_species* sp)
     }
     if (L->delta)
         for (int64_t i = 0; i < n; ++i) maxd = std::max(maxd, std::fabs(L->delta[i]));
+    double mga = 0.0, mgs = 0.0, mA = 0.0, nlo = 0.0, nhi = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        mga = std::max(mga, L->gamma_air[i]);
+        mgs = std::max(mgs, L->gamma_self ? L->gamma_self[i] : L->gamma_air[i]);
+        if (L->A21) mA = std::max(mA, L->A21[i]);
+        nlo = i == 0 ? L->n_air[i] : std::min(nlo, L->n_air[i]);
+        nhi = i == 0 ? L->n_air[i] : std::max(nhi, L->n_air[i]);
+    }
     HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     ctx->n_lines = n;
     ctx->lines_loaded = false;
@@ -549,6 +575,11 @@ int hk_load_lines(hk_ctx* ctx, const hk_lines* L, const hk_species* sp)
     ctx->has_delta = L->delta != nullptr;
     ctx->has_A = L->A21 != nullptr;
     ctx->max_abs_delta = maxd;
+    ctx->max_gamma_air = mga;
+    ctx->max_gamma_self = mgs;
+    ctx->max_A21 = mA;
+    ctx->min_n_air = nlo;
+    ctx->max_n_air = nhi;
     ctx->nu_max = n > 0 ? host[(size_t)n - 1] : 0.0;
     ctx->species = *sp;
     ctx->lines_loaded = true;
@@ -558,7 +589,7 @@ int hk_load_lines(hk_ctx* ctx, const hk_lines* L, const hk_species* sp)
 // Binary32 profiles with compensated binary32 sums, after the binary64 line
 // preparation: scale, binary32 records, tile ranges, wing and core kernels,
 // then kappa = (sum + comp) 2^-s in binary64.
-static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, WingRec* wing, WingIdx* widx, CoreRec* core,
+static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, double reach, WingRec* wing, WingIdx* widx, CoreRec* core,
                        const int64_t* ranges_c, int64_t n_tiles_c, double* kappa, int accumulate, bool surrogate)
 {
     const int64_t n = ctx->n_lines;
@@ -582,7 +613,6 @@ static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, WingRec* wing, WingIdx*
     HK_HIP(ctx, ctx->ranges.ensure((size_t)std::max<int64_t>(n_tiles, 1) * 2 * sizeof(int64_t)),
            "allocating tile ranges");
     int64_t* ranges = static_cast<int64_t*>(ctx->ranges.p);
-    const double reach = grid->cutoff + ctx->max_abs_delta * ctx->last_P + 2.0 * grid->dnu;
     {
         StageTimer tm(ctx, HK_STAGE_LINE_PREP);
         if (n > 0) {
@@ -629,13 +659,16 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
     if (precision != HK_F64 && precision != HK_F32_KAHAN && precision != HK_F32_SURROGATE)
         return fail(ctx, HK_EINVAL, "unknown precision %d", precision);
     if (comp) return fail(ctx, HK_EINVAL, "comp must be NULL (kappa holds the result in binary64)");
-    if (precision != HK_F64 && !(grid->cutoff / grid->dnu < 8388608.0))
+    if (precision != HK_F64 && !(grid->cutoff_lorentz > 0.0) && !(grid->cutoff / grid->dnu < 8388608.0))
         return fail(ctx, HK_EINVAL, "binary32 profiles need cutoff/dnu < 2^23 (got %g)", grid->cutoff / grid->dnu);
     if (grid->n_points > 0 && !kappa) return fail(ctx, HK_EINVAL, "kappa is NULL");
     if (int rc = check_ctx(ctx)) return rc;
     if (!ctx->lines_loaded) return fail(ctx, HK_ENOTREADY, "no line list loaded (call hk_load_lines first)");
     if (precision == HK_F32_SURROGATE && !ctx->sg_certified)
         return fail(ctx, HK_ENOTREADY, "HK_F32_SURROGATE needs a certified surrogate (hk_surrogate_certify)");
+    if (precision != HK_F64 && !(max_cutoff(ctx, st, grid) / grid->dnu < 8388608.0))
+        return fail(ctx, HK_EINVAL, "binary32 profiles need (largest cutoff)/dnu < 2^23 (got %g)",
+                    max_cutoff(ctx, st, grid) / grid->dnu);
     HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     const int64_t n = ctx->n_lines;
     const int32_t np = (int32_t)grid->n_points;
@@ -679,8 +712,8 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
         tm.stop();
     }
     if (precision != HK_F64)
-        return opacity_f32(ctx, grid, wing, widx, core, ranges_c, n_tiles_c, static_cast<double*>(kappa), accumulate,
-                           precision == HK_F32_SURROGATE);
+        return opacity_f32(ctx, grid, reach, wing, widx, core, ranges_c, n_tiles_c, static_cast<double*>(kappa),
+                           accumulate, precision == HK_F32_SURROGATE);
     {
         StageTimer tm(ctx, HK_STAGE_OPACITY);
         HK_HIP(ctx, launch_wing_f64(ppl, wing, widx, ranges, n_tiles, grid->nu_min, grid->dnu, np,
@@ -739,13 +772,17 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
         return fail(ctx, HK_EUNSUPPORTED, "hk_tables supports HK_F64 and HK_F32_KAHAN");
     if (precision != HK_F64 && precision != HK_F32_KAHAN)
         return fail(ctx, HK_EINVAL, "unknown precision %d", precision);
-    if (precision == HK_F32_KAHAN && !(grid->cutoff / grid->dnu < 8388608.0))
+    if (precision == HK_F32_KAHAN && !(grid->cutoff_lorentz > 0.0) && !(grid->cutoff / grid->dnu < 8388608.0))
         return fail(ctx, HK_EINVAL, "HK_F32_KAHAN needs cutoff/dnu < 2^23 (got %g)", grid->cutoff / grid->dnu);
     const int32_t np = (int32_t)grid->n_points;
     const int64_t n_bins = ((int64_t)np + bins->points_per_bin - 1) / bins->points_per_bin;
     if (n_states > 0 && np > 0 && !k_out) return fail(ctx, HK_EINVAL, "k_out is NULL");
     if (int rc = check_ctx(ctx)) return rc;
     if (!ctx->lines_loaded) return fail(ctx, HK_ENOTREADY, "no line list loaded (call hk_load_lines first)");
+    if (precision == HK_F32_KAHAN)
+        for (int32_t i = 0; i < n_states; ++i)
+            if (!(max_cutoff(ctx, &states[i], grid) / grid->dnu < 8388608.0))
+                return fail(ctx, HK_EINVAL, "states[%d]: binary32 profiles need (largest cutoff)/dnu < 2^23", i);
     HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     ctx->last_tables_states = 0;
     if (n_states == 0 || np == 0) return HK_OK;
@@ -798,7 +835,8 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
     int64_t* counts = static_cast<int64_t*>(ctx->tb_counts.p);
 
     // tile shape: cached, or timed on the first batch
-    const int64_t cut_steps = (int64_t)std::llround(grid->cutoff / grid->dnu);
+    const int64_t cut_steps = grid->cutoff_lorentz > 0.0 ? -(int64_t)std::llround(grid->cutoff_lorentz * 1e3)
+                                                         : (int64_t)std::llround(grid->cutoff / grid->dnu);
     int ppl = f64 ? ctx->f64_points_per_lane : ctx->f32_points_per_lane;
     bool tune = false;
     if (ctx->tables_autotune) {

@@ -111,6 +111,7 @@ struct PrepParams {
     double nat;       // 1 / (4 pi c): natural width per unit A21
     double tscale;    // T / T_ref
     double nu_min, dnu, cutoff;
+    double cutoff_lorentz;  // > 0: each line's cutoff is this many Gamma_L
     int32_t n_points;
 };
 

@@ -96,8 +96,10 @@ __global__ __launch_bounds__(256) void line_prep_f64_kernel(LinesDev L, PrepPara
     }
     const int32_t n = pp.n_points;
     {
-        double flo = ceil((nu0 - pp.cutoff - pp.nu_min) / pp.dnu);
-        double fhi = floor((nu0 + pp.cutoff - pp.nu_min) / pp.dnu);
+        // the cutoff: absolute, or a multiple of the line's Lorentz HWHM
+        const double cut = pp.cutoff_lorentz > 0.0 ? pp.cutoff_lorentz * GL : pp.cutoff;
+        double flo = ceil((nu0 - cut - pp.nu_min) / pp.dnu);
+        double fhi = floor((nu0 + cut - pp.nu_min) / pp.dnu);
         flo = fmax(flo, 0.0);
         fhi = fmin(fhi, (double)(n - 1));
         if (!(flo <= fhi)) {
