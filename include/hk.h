@@ -81,6 +81,10 @@ typedef struct {
     double P;        /* total pressure, atm, >= 0 */
     double P_self;   /* self-broadening partial pressure, 0 <= P_self <= P */
     double q_ratio;  /* partition-function ratio Q(T_ref)/Q(T), > 0 */
+    double abundance; /* weight X_s >= 0 of this species in a mixture: the
+                         opacity is X_s kappa_s, so that a mixture's is
+                         sum_s X_s kappa_s (§2.1; hk_opacity with accumulate
+                         over the species' line lists); 1 for one species */
 } hk_state;
 
 typedef struct {

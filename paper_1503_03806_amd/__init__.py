@@ -49,7 +49,7 @@ class hk_species(C.Structure):
 
 class hk_state(C.Structure):
     _fields_ = [("T", C.c_double), ("P", C.c_double), ("P_self", C.c_double),
-                ("q_ratio", C.c_double)]
+                ("q_ratio", C.c_double), ("abundance", C.c_double)]
 
 
 class hk_grid(C.Structure):
@@ -194,7 +194,7 @@ def hk_load_lines(ctx, lines: dict, species: dict):
 def _state(st: dict) -> hk_state:
     P = float(st["P"])
     return hk_state(float(st["T"]), P, float(st.get("P_self", 0.5 * P)),
-                    float(st.get("q_ratio", 1.0)))
+                    float(st.get("q_ratio", 1.0)), float(st.get("abundance", 1.0)))
 
 
 def _grid(g: dict) -> hk_grid:

@@ -149,6 +149,8 @@ int check_state(hk_ctx* ctx, const hk_state* st)
         return fail(ctx, HK_EINVAL, "P_self must satisfy 0 <= P_self <= P (got %g, P = %g)", st->P_self, st->P);
     if (!isfin(st->q_ratio) || !(st->q_ratio > 0.0))
         return fail(ctx, HK_EINVAL, "q_ratio must be finite and > 0 (got %g)", st->q_ratio);
+    if (!isfin(st->abundance) || !(st->abundance >= 0.0))
+        return fail(ctx, HK_EINVAL, "abundance must be finite and >= 0 (got %g)", st->abundance);
     return HK_OK;
 }
 
@@ -249,7 +251,7 @@ PrepParams prep_params(const hk_ctx* ctx, const hk_state* st, const hk_grid* gri
     pp.T_ref = ctx->species.T_ref;
     pp.P = st->P;
     pp.P_self = st->P_self;
-    pp.q_ratio = st->q_ratio;
+    pp.q_ratio = st->q_ratio * st->abundance;  // S scales with the species' weight
     pp.dop = std::sqrt(2.0 * kKB * st->T / (ctx->species.mass_amu * kAMU)) / kC;
     pp.nat = 1.0 / (4.0 * kPi * kC);
     pp.tscale = st->T / ctx->species.T_ref;

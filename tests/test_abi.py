@@ -58,7 +58,8 @@ def _opacity_rc(state, grid, precision=hk.HK_F64, kappa=1, comp=None):
 
 @pytest.mark.parametrize("field,value,msg", [
     ("T", 0.0, "T must"), ("T", float("nan"), "T must"), ("P", -1.0, "P must"),
-    ("P_self", 2.0, "P_self"), ("q_ratio", 0.0, "q_ratio")])
+    ("P_self", 2.0, "P_self"), ("q_ratio", 0.0, "q_ratio"), ("abundance", -0.5, "abundance"),
+    ("abundance", float("inf"), "abundance")])
 def test_opacity_rejects_bad_state(field, value, msg):
     st = dict(GOOD_STATE); st[field] = value
     assert _opacity_rc(st, GOOD_GRID) == hk.HK_EINVAL
