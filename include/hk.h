@@ -142,6 +142,33 @@ const char* hk_last_error(const hk_ctx* ctx);
  * Synchronous with respect to the host arrays: they may be freed on return. */
 int hk_load_lines(hk_ctx* ctx, const hk_lines* lines, const hk_species* species);
 
+/* ---- Input (§2.3, §3.5): HITRAN / HITEMP line records -------------------- */
+
+/* Writable line arrays of `capacity` values each (the reader's output);
+ * every pointer is required. */
+typedef struct {
+    int64_t capacity;
+    double *nu, *S_ref, *E_lower, *gamma_air, *n_air, *gamma_self, *delta, *A21;
+} hk_lines_out;
+
+/* Read line records in the HITRAN fixed-width format (Rothman et al. 2005
+ * layout, the one HITRAN and HITEMP files share: 160 characters per record,
+ * each ended by LF or CR LF) from the file at `path`, starting at record
+ * `first` (0-based), into out's arrays.  The fields read, by 1-based
+ * column: molecule number 1-2, line centre nu 4-15, S_ref (at 296 K) 16-25,
+ * Einstein A 26-35, gamma_air 36-40, gamma_self 41-45, E'' 46-55, n_air
+ * 56-59, pressure shift delta 60-67; the rest of the record is not read.
+ * molecule > 0 keeps only records of that molecule number; 0 keeps all.
+ * Reading stops at the end of the file or when out->capacity records are
+ * stored.  *n_read: records stored; *next: the index of the first record
+ * not consumed (records skipped by the molecule filter are consumed), so a
+ * list is read in chunks by calling again with first = *next until
+ * *n_read == 0.  HK_EINVAL for a file that is not in this format (record
+ * length, line ends), a truncated last record or an unparsable field,
+ * naming the record and the field.  Host only: no device is used. */
+int hk_read_par(const char* path, int64_t first, int32_t molecule, const hk_lines_out* out,
+                int64_t* n_read, int64_t* next);
+
 /* ---- §2.3-§2.5: opacity function ---------------------------------------- */
 
 /* Opacity kappa(nu_j) on the grid for one state.  For every line: S(T) by
@@ -173,6 +200,30 @@ int hk_load_lines(hk_ctx* ctx, const hk_lines* lines, const hk_species* species)
  * line list in chunks; accumulate == 0 overwrites them. */
 int hk_opacity(hk_ctx* ctx, const hk_state* state, const hk_grid* grid,
                int precision, void* kappa, void* comp, int accumulate);
+
+#define HK_MAX_CHUNKS 65536
+
+/* The opacity of a line list given in chunks (§3.5: a list shipped as many
+ * files whose opacities are added), with the host work and the copy to the
+ * device of chunk c+1 overlapping the kernels of chunk c.  The result is
+ * bitwise that of calling, for c = 0 .. n_chunks-1, hk_load_lines(&chunks[c],
+ * species) and then hk_opacity(state, grid, precision, kappa, NULL,
+ * accumulate || c > 0); only two chunks are on the device at a time.
+ *   chunks: [host] n_chunks (0 .. HK_MAX_CHUNKS) line lists, each under the
+ *     rules of hk_load_lines.  All are checked before any work is enqueued
+ *     (HK_EINVAL names the chunk); chunks in non-decreasing nu are copied
+ *     as they are, others are ordered first.
+ *   kappa: [device] double[n_points], as in hk_opacity; with n_chunks == 0
+ *     it is zeroed (accumulate == 0) or left as it is.
+ * The host arrays are copied into pinned staging buffers of the context
+ * during the call and may be freed on return; the device work is
+ * asynchronous, as for hk_opacity.  Copies run on a second non-blocking
+ * stream of the context, ordered against ctx's stream by events.
+ * Afterwards the loaded list is the last chunk, and hk_stats counts the
+ * whole stream. */
+int hk_opacity_stream(hk_ctx* ctx, const hk_lines* chunks, int32_t n_chunks, const hk_species* species,
+                      const hk_state* state, const hk_grid* grid, int precision, double* kappa,
+                      int accumulate);
 
 /* ---- §2.2, §2.6: k-distribution ------------------------------------------ */
 

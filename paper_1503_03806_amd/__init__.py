@@ -23,7 +23,8 @@ __all__ = ["HK_OK", "HK_EINVAL", "HK_ENOMEM", "HK_EDEVICE", "HK_EUNSUPPORTED", "
            "hk_surrogate_labels", "hk_surrogate_set_params", "hk_surrogate_get_params",
            "hk_surrogate_grad", "hk_surrogate_train", "hk_surrogate_eval", "hk_surrogate_certify",
            "hk_resample", "hk_transmission", "hk_transmission_direct", "HK_MAX_COEF",
-           "HK_TRANSMISSION_NODES", "Context", "LIB_PATH"]
+           "HK_TRANSMISSION_NODES", "hk_opacity_stream", "hk_read_par", "HK_MAX_CHUNKS", "Context",
+           "LIB_PATH"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhk.so")
 
@@ -34,13 +35,20 @@ HK_SURR_CELLS_X, HK_SURR_CELLS_Y = 80, 40
 HK_MAX_COEF, HK_MAX_COLUMNS, HK_TRANSMISSION_NODES = 32, 1 << 20, 100
 HK_MAX_G = 64
 HK_MAX_POINTS = 1 << 30
+HK_MAX_CHUNKS = 65536
 
 _pd = C.POINTER(C.c_double)
 
 
+LINE_FIELDS = ("nu", "S_ref", "E_lower", "gamma_air", "n_air", "gamma_self", "delta", "A21")
+
+
 class hk_lines(C.Structure):
-    _fields_ = [("n", C.c_int64)] + [(f, _pd) for f in (
-        "nu", "S_ref", "E_lower", "gamma_air", "n_air", "gamma_self", "delta", "A21")]
+    _fields_ = [("n", C.c_int64)] + [(f, _pd) for f in LINE_FIELDS]
+
+
+class hk_lines_out(C.Structure):
+    _fields_ = [("capacity", C.c_int64)] + [(f, _pd) for f in LINE_FIELDS]
 
 
 class hk_species(C.Structure):
@@ -101,6 +109,12 @@ def lib():
         L.hk_load_lines.restype = i32
         L.hk_opacity.argtypes = [vp, C.POINTER(hk_state), C.POINTER(hk_grid), i32, vp, vp, i32]
         L.hk_opacity.restype = i32
+        L.hk_opacity_stream.argtypes = [vp, C.POINTER(hk_lines), C.c_int32, C.POINTER(hk_species),
+                                        C.POINTER(hk_state), C.POINTER(hk_grid), i32, vp, i32]
+        L.hk_opacity_stream.restype = i32
+        L.hk_read_par.argtypes = [C.c_char_p, i64, C.c_int32, C.POINTER(hk_lines_out),
+                                  C.POINTER(i64), C.POINTER(i64)]
+        L.hk_read_par.restype = i32
         L.hk_kdist.argtypes = [vp, vp, i32, i64, C.POINTER(hk_bins), vp, vp]
         L.hk_kdist.restype = i32
         L.hk_gauss_legendre.argtypes = [C.c_int32, _pd, _pd]; L.hk_gauss_legendre.restype = i32
@@ -176,19 +190,50 @@ def _f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
 
 
-def hk_load_lines(ctx, lines: dict, species: dict):
-    """lines: dict of host arrays (nu, S_ref, E_lower, gamma_air, n_air and
-    optional gamma_self, delta, A21); species: {T_ref, mass_amu}."""
-    keep = {k: _f64(lines.get(k)) for k in ("nu", "S_ref", "E_lower", "gamma_air", "n_air",
-                                            "gamma_self", "delta", "A21")}
+def _lines(lines: dict):
+    """(hk_lines, the arrays it points into: keep them alive)."""
+    keep = {k: _f64(lines.get(k)) for k in LINE_FIELDS}
     n = len(keep["nu"])
     for k, v in keep.items():
         if v is not None and len(v) != n:
             raise ValueError("line field %s has %d values, expected %d" % (k, len(v), n))
     fld = [None if v is None else v.ctypes.data_as(_pd) for v in keep.values()]
-    s = hk_lines(n, *fld)
-    sp = hk_species(float(species.get("T_ref", 296.0)), float(species["mass_amu"]))
+    return hk_lines(n, *fld), keep
+
+
+def _species(species: dict) -> hk_species:
+    return hk_species(float(species.get("T_ref", 296.0)), float(species["mass_amu"]))
+
+
+def hk_load_lines(ctx, lines: dict, species: dict):
+    """lines: dict of host arrays (nu, S_ref, E_lower, gamma_air, n_air and
+    optional gamma_self, delta, A21); species: {T_ref, mass_amu}."""
+    s, keep = _lines(lines)
+    sp = _species(species)
     _check(lib().hk_load_lines(ctx, C.byref(s), C.byref(sp)), ctx)
+
+
+def hk_opacity_stream(ctx, chunks, species: dict, state: dict, grid: dict, precision: int, kappa,
+                      accumulate: bool = False):
+    """chunks: a sequence of line dicts (as hk_load_lines takes)."""
+    made = [_lines(c) for c in chunks]
+    arr = (hk_lines * max(len(made), 1))(*[m[0] for m in made])
+    sp, st, gr = _species(species), _state(state), _grid(grid)
+    _check(lib().hk_opacity_stream(ctx, arr if made else None, len(made), C.byref(sp), C.byref(st),
+                                   C.byref(gr), int(precision), _ptr(kappa), 1 if accumulate else 0),
+           ctx)
+
+
+def hk_read_par(path: str, first: int = 0, capacity: int = 1 << 20, molecule: int = 0):
+    """Read up to `capacity` HITRAN-format records from record `first`:
+    (dict of float64 arrays, n_read, next)."""
+    arrays = {k: np.empty(max(int(capacity), 1)) for k in LINE_FIELDS}
+    out = hk_lines_out(int(capacity), *[arrays[k].ctypes.data_as(_pd) for k in LINE_FIELDS])
+    n_read, nxt = C.c_int64(0), C.c_int64(0)
+    _check(lib().hk_read_par(os.fsencode(path), int(first), int(molecule), C.byref(out),
+                             C.byref(n_read), C.byref(nxt)))
+    n = n_read.value
+    return {k: v[:n].copy() for k, v in arrays.items()}, n, nxt.value
 
 
 def _state(st: dict) -> hk_state:
@@ -369,6 +414,17 @@ class Context:
 
     def load_lines(self, lines: dict, mass_amu: float, T_ref: float = 296.0):
         hk_load_lines(self.h, lines, {"T_ref": T_ref, "mass_amu": mass_amu})
+
+    def opacity_stream(self, chunks, mass_amu: float, state: dict, grid: dict,
+                       precision: int = HK_F64, out=None, accumulate: bool = False,
+                       T_ref: float = 296.0):
+        torch = self._torch
+        n = int(grid["n_points"])
+        if out is None:
+            out = torch.empty(max(n, 1), dtype=torch.float64, device="cuda:%d" % self.device)[:n]
+        hk_opacity_stream(self.h, chunks, {"T_ref": T_ref, "mass_amu": mass_amu}, state, grid,
+                          precision, out, accumulate)
+        return out
 
     def opacity(self, state: dict, grid: dict, precision: int = HK_F64, out=None, comp=None,
                 accumulate: bool = False):

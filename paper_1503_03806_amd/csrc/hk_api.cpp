@@ -13,6 +13,7 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "hk_internal.h"
@@ -42,6 +43,16 @@ struct DevBuf {
     }
 };
 
+// What the launches need to know of a line list besides its values: which
+// optional fields it has, and bounds that size the tile ranges.
+struct ListInfo {
+    bool has_self = false, has_delta = false, has_A = false;
+    double max_abs_delta = 0.0;
+    // bounds of the width parameters, for the reach of Lorentz-width cutoffs
+    double max_gamma_air = 0.0, max_gamma_self = 0.0, max_A21 = 0.0, min_n_air = 0.0, max_n_air = 0.0;
+    double nu_max = 0.0;  // largest line centre (bounds the Doppler core widths)
+};
+
 struct hk_ctx {
     int device = 0;
     hipStream_t own = nullptr;     // created with the context
@@ -51,14 +62,21 @@ struct hk_ctx {
     // line list, ascending (nu, index)
     int64_t n_lines = 0;
     bool lines_loaded = false;
-    bool has_self = false, has_delta = false, has_A = false;
-    double max_abs_delta = 0.0;
-    // bounds of the width parameters, for the reach of Lorentz-width cutoffs
-    double max_gamma_air = 0.0, max_gamma_self = 0.0, max_A21 = 0.0, min_n_air = 0.0, max_n_air = 0.0;
-    double nu_max = 0.0;  // largest line centre (bounds the Doppler core widths)
+    ListInfo li;
     double last_P = 0.0;  // pressure of the state being computed
     hk_species species{296.0, 0.0};
     DevBuf lines;  // 8 arrays of n doubles
+    // streamed lists: the second device line buffer, pinned host staging
+    // (two buffers of pin_cap doubles), a copy stream and its events, and
+    // the per-chunk evaluation counters of the last hk_opacity_stream call
+    DevBuf lines_alt;
+    double* pin[2] = {nullptr, nullptr};
+    size_t pin_cap = 0;
+    hipStream_t copy = nullptr;
+    hipEvent_t ev_copied[2] = {nullptr, nullptr}, ev_used[2] = {nullptr, nullptr};
+    DevBuf st_counts;
+    int32_t last_stream_chunks = 0;  // > 0: hk_stats reports that call
+    int64_t stream_lines = 0;
     // per-state records and tile ranges
     DevBuf wing, widx, core, ranges, ranges_core;
     DevBuf partial;
@@ -236,8 +254,8 @@ LinesDev lines_dev(hk_ctx* ctx)
     L.gamma_air = lines_field(ctx, 3);
     L.n_air = lines_field(ctx, 4);
     L.gamma_self = lines_field(ctx, 5);
-    L.delta = ctx->has_delta ? lines_field(ctx, 6) : nullptr;
-    L.A21 = ctx->has_A ? lines_field(ctx, 7) : nullptr;
+    L.delta = ctx->li.has_delta ? lines_field(ctx, 6) : nullptr;
+    L.A21 = ctx->li.has_A ? lines_field(ctx, 7) : nullptr;
     L.n = ctx->n_lines;
     return L;
 }
@@ -271,23 +289,180 @@ PrepParams prep_params(const hk_ctx* ctx, const hk_state* st, const hk_grid* gri
 // The largest cutoff of any line: the absolute cutoff, or cutoff_lorentz
 // times an upper bound of Gamma_L (eq. 20 with each parameter at its
 // extreme over the loaded lines; (T/T_ref)^-n is monotone in n).
-double max_cutoff(const hk_ctx* ctx, const hk_state* st, const hk_grid* grid)
+double max_cutoff(const ListInfo& li, double T_ref, const hk_state* st, const hk_grid* grid)
 {
     if (!(grid->cutoff_lorentz > 0.0)) return grid->cutoff;
-    const double ts = st->T / ctx->species.T_ref;
-    const double f = std::max(std::pow(ts, -ctx->min_n_air), std::pow(ts, -ctx->max_n_air));
-    const double gl = ctx->max_A21 / (4.0 * kPi * kC) +
-                      f * (ctx->max_gamma_air * (st->P - st->P_self) + ctx->max_gamma_self * st->P_self);
+    const double ts = st->T / T_ref;
+    const double f = std::max(std::pow(ts, -li.min_n_air), std::pow(ts, -li.max_n_air));
+    const double gl = li.max_A21 / (4.0 * kPi * kC) +
+                      f * (li.max_gamma_air * (st->P - st->P_self) + li.max_gamma_self * st->P_self);
     return grid->cutoff_lorentz * gl * (1.0 + 1e-9);
+}
+double max_cutoff(const hk_ctx* ctx, const hk_state* st, const hk_grid* grid)
+{
+    return max_cutoff(ctx->li, ctx->species.T_ref, st, grid);
 }
 double wing_reach(const hk_ctx* ctx, const hk_state* st, const hk_grid* grid)
 {
-    return max_cutoff(ctx, st, grid) + ctx->max_abs_delta * st->P + 2.0 * grid->dnu;
+    return max_cutoff(ctx, st, grid) + ctx->li.max_abs_delta * st->P + 2.0 * grid->dnu;
 }
 double core_reach(const hk_ctx* ctx, const hk_state* st, const hk_grid* grid, const PrepParams& pp)
 {
-    return std::min(10.0 * pp.dop * ctx->nu_max, max_cutoff(ctx, st, grid)) + ctx->max_abs_delta * st->P +
+    return std::min(10.0 * pp.dop * ctx->li.nu_max, max_cutoff(ctx, st, grid)) + ctx->li.max_abs_delta * st->P +
            2.0 * grid->dnu;
+}
+
+// Runs fn(i0, i1, t) over [0, n) split into contiguous ranges, on up to 8
+// host threads when the range is large (the host side of loading a list).
+template <typename F>
+void host_ranges(int64_t n, int n_max_threads, F fn)
+{
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int t = n < ((int64_t)1 << 20) ? 1 : (int)std::min<unsigned>((unsigned)n_max_threads, hw);
+    if (t <= 1) {
+        fn((int64_t)0, n, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve((size_t)t);
+    for (int k = 0; k < t; ++k) th.emplace_back(fn, n * k / t, n * (k + 1) / t, k);
+    for (auto& x : th) x.join();
+}
+
+int check_species(hk_ctx* ctx, const hk_species* sp)
+{
+    if (!sp) return fail(ctx, HK_EINVAL, "species must not be NULL");
+    if (!isfin(sp->T_ref) || !(sp->T_ref > 0.0)) return fail(ctx, HK_EINVAL, "T_ref must be finite and > 0");
+    if (!isfin(sp->mass_amu) || !(sp->mass_amu > 0.0)) return fail(ctx, HK_EINVAL, "mass_amu must be finite and > 0");
+    return HK_OK;
+}
+
+// The value rules of a line list (hk_load_lines); chunk >= 0 names the
+// chunk of a streamed list in the message.  The first offending line, in
+// input order, is reported.
+int check_lines(hk_ctx* ctx, const hk_lines* L, int64_t chunk)
+{
+    char pre[40] = "";
+    if (chunk >= 0) snprintf(pre, sizeof pre, "chunk %lld: ", (long long)chunk);
+    if (!L) return fail(ctx, HK_EINVAL, "%slines must not be NULL", pre);
+    if (L->n < 0 || L->n > (int64_t)INT32_MAX)
+        return fail(ctx, HK_EINVAL, "%sline count %lld out of range", pre, (long long)L->n);
+    const int64_t n = L->n;
+    if (n > 0 && (!L->nu || !L->S_ref || !L->E_lower || !L->gamma_air || !L->n_air))
+        return fail(ctx, HK_EINVAL, "%snu, S_ref, E_lower, gamma_air and n_air are required", pre);
+    auto bad = [L](int64_t i) {
+        return !isfin(L->nu[i]) || !(L->nu[i] > 0.0) || !isfin(L->S_ref[i]) || !(L->S_ref[i] >= 0.0) ||
+               !isfin(L->E_lower[i]) || !isfin(L->gamma_air[i]) || !(L->gamma_air[i] >= 0.0) ||
+               !isfin(L->n_air[i]) ||
+               (L->gamma_self && (!isfin(L->gamma_self[i]) || !(L->gamma_self[i] >= 0.0))) ||
+               (L->delta && !isfin(L->delta[i])) || (L->A21 && (!isfin(L->A21[i]) || !(L->A21[i] >= 0.0)));
+    };
+    std::vector<int64_t> first(8, n);
+    host_ranges(n, 8, [&](int64_t i0, int64_t i1, int t) {
+        for (int64_t i = i0; i < i1; ++i)
+            if (bad(i)) {
+                first[(size_t)t] = i;
+                return;
+            }
+    });
+    const int64_t i = *std::min_element(first.begin(), first.end());
+    if (i == n) return HK_OK;
+    const long long li = (long long)i;
+    if (!isfin(L->nu[i]) || !(L->nu[i] > 0.0))
+        return fail(ctx, HK_EINVAL, "%snu[%lld] = %g must be finite and > 0", pre, li, L->nu[i]);
+    if (!isfin(L->S_ref[i]) || !(L->S_ref[i] >= 0.0))
+        return fail(ctx, HK_EINVAL, "%sS_ref[%lld] = %g must be finite and >= 0", pre, li, L->S_ref[i]);
+    if (!isfin(L->E_lower[i])) return fail(ctx, HK_EINVAL, "%sE_lower[%lld] is not finite", pre, li);
+    if (!isfin(L->gamma_air[i]) || !(L->gamma_air[i] >= 0.0))
+        return fail(ctx, HK_EINVAL, "%sgamma_air[%lld] must be finite and >= 0", pre, li);
+    if (!isfin(L->n_air[i])) return fail(ctx, HK_EINVAL, "%sn_air[%lld] is not finite", pre, li);
+    if (L->gamma_self && (!isfin(L->gamma_self[i]) || !(L->gamma_self[i] >= 0.0)))
+        return fail(ctx, HK_EINVAL, "%sgamma_self[%lld] must be finite and >= 0", pre, li);
+    if (L->delta && !isfin(L->delta[i])) return fail(ctx, HK_EINVAL, "%sdelta[%lld] is not finite", pre, li);
+    return fail(ctx, HK_EINVAL, "%sA21[%lld] must be finite and >= 0", pre, li);
+}
+
+// Flags and bounds of a validated list.
+ListInfo list_info(const hk_lines* L)
+{
+    ListInfo li;
+    li.has_self = L->gamma_self != nullptr;
+    li.has_delta = L->delta != nullptr;
+    li.has_A = L->A21 != nullptr;
+    const int64_t n = L->n;
+    if (n == 0) return li;
+    std::vector<ListInfo> part(8);
+    host_ranges(n, 8, [&](int64_t i0, int64_t i1, int t) {
+        ListInfo b;
+        b.min_n_air = L->n_air[i0];
+        b.max_n_air = L->n_air[i0];
+        for (int64_t i = i0; i < i1; ++i) {
+            if (L->delta) b.max_abs_delta = std::max(b.max_abs_delta, std::fabs(L->delta[i]));
+            b.max_gamma_air = std::max(b.max_gamma_air, L->gamma_air[i]);
+            b.max_gamma_self = std::max(b.max_gamma_self, L->gamma_self ? L->gamma_self[i] : L->gamma_air[i]);
+            if (L->A21) b.max_A21 = std::max(b.max_A21, L->A21[i]);
+            b.min_n_air = std::min(b.min_n_air, L->n_air[i]);
+            b.max_n_air = std::max(b.max_n_air, L->n_air[i]);
+            b.nu_max = std::max(b.nu_max, L->nu[i]);
+        }
+        part[(size_t)t] = b;
+    });
+    bool first = true;
+    for (unsigned k = 0; k < part.size(); ++k) {
+        const ListInfo& b = part[k];
+        if (!(b.nu_max > 0.0)) continue;  // no range of that thread (nu > 0 on every line)
+        li.max_abs_delta = std::max(li.max_abs_delta, b.max_abs_delta);
+        li.max_gamma_air = std::max(li.max_gamma_air, b.max_gamma_air);
+        li.max_gamma_self = std::max(li.max_gamma_self, b.max_gamma_self);
+        li.max_A21 = std::max(li.max_A21, b.max_A21);
+        li.min_n_air = first ? b.min_n_air : std::min(li.min_n_air, b.min_n_air);
+        li.max_n_air = first ? b.max_n_air : std::max(li.max_n_air, b.max_n_air);
+        li.nu_max = std::max(li.nu_max, b.nu_max);
+        first = false;
+    }
+    return li;
+}
+
+// Writes a validated list as 8 field arrays of n values (dst[k n + i]) in
+// ascending (nu, input index) order, optional fields defaulted (gamma_self
+// = gamma_air, delta = A21 = 0).  A list already in non-decreasing nu is
+// copied as it is (a stable sort would not move it).
+void order_lines(const hk_lines* L, double* dst)
+{
+    const int64_t n = L->n;
+    if (n == 0) return;
+    const double* src[8] = {L->nu, L->S_ref, L->E_lower, L->gamma_air, L->n_air,
+                            L->gamma_self ? L->gamma_self : L->gamma_air, L->delta, L->A21};
+    bool sorted = true;
+    {
+        std::vector<char> ok(8, 1);
+        host_ranges(n, 8, [&](int64_t i0, int64_t i1, int t) {
+            const int64_t a = std::max<int64_t>(i0, 1);
+            for (int64_t i = a; i < i1; ++i)
+                if (L->nu[i] < L->nu[i - 1]) {
+                    ok[(size_t)t] = 0;
+                    return;
+                }
+        });
+        for (char c : ok) sorted = sorted && c;
+    }
+    std::vector<int64_t> perm;
+    if (!sorted) {
+        perm.resize((size_t)n);
+        std::iota(perm.begin(), perm.end(), (int64_t)0);
+        std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return L->nu[a] < L->nu[b]; });
+    }
+    host_ranges(n, 8, [&](int64_t i0, int64_t i1, int) {
+        for (int k = 0; k < 8; ++k) {
+            double* d = dst + (size_t)k * n;
+            if (!src[k])
+                std::fill(d + i0, d + i1, 0.0);
+            else if (sorted)
+                std::memcpy(d + i0, src[k] + i0, (size_t)(i1 - i0) * sizeof(double));
+            else
+                for (int64_t i = i0; i < i1; ++i) d[i] = src[k][perm[(size_t)i]];
+        }
+    });
 }
 
 }  // namespace
@@ -435,6 +610,8 @@ int upload_qr(hk_ctx* ctx, int64_t m, int nc, DevBuf& dQ, DevBuf& dR)
 
 }  // namespace
 
+void hk::set_thread_error(const char* msg) { t_err = msg; }
+
 extern "C" {
 
 int hk_version(void) { return 100; }
@@ -479,7 +656,16 @@ int hk_destroy(hk_ctx* ctx)
     if (!ctx) return HK_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->copy) (void)hipStreamSynchronize(ctx->copy);
     ctx->lines.release();
+    ctx->lines_alt.release();
+    ctx->st_counts.release();
+    for (int x = 0; x < 2; ++x) {
+        if (ctx->pin[x]) (void)hipHostFree(ctx->pin[x]);
+        if (ctx->ev_copied[x]) (void)hipEventDestroy(ctx->ev_copied[x]);
+        if (ctx->ev_used[x]) (void)hipEventDestroy(ctx->ev_used[x]);
+    }
+    if (ctx->copy) (void)hipStreamDestroy(ctx->copy);
     ctx->wing.release();
     ctx->widx.release();
     ctx->core.release();
@@ -525,64 +711,24 @@ int hk_load_lines(hk_ctx* ctx, const hk_lines* L, const hk_species* sp)
 {
     if (!L || !sp) return fail(ctx, HK_EINVAL, "lines and species must not be NULL");
     if (L->n < 0 || L->n > (int64_t)INT32_MAX) return fail(ctx, HK_EINVAL, "line count %lld out of range", (long long)L->n);
-    if (!isfin(sp->T_ref) || !(sp->T_ref > 0.0)) return fail(ctx, HK_EINVAL, "T_ref must be finite and > 0");
-    if (!isfin(sp->mass_amu) || !(sp->mass_amu > 0.0)) return fail(ctx, HK_EINVAL, "mass_amu must be finite and > 0");
-    const int64_t n = L->n;
-    if (n > 0 && (!L->nu || !L->S_ref || !L->E_lower || !L->gamma_air || !L->n_air))
-        return fail(ctx, HK_EINVAL, "nu, S_ref, E_lower, gamma_air and n_air are required");
-    for (int64_t i = 0; i < n; ++i) {
-        if (!isfin(L->nu[i]) || !(L->nu[i] > 0.0)) return fail(ctx, HK_EINVAL, "nu[%lld] = %g must be finite and > 0", (long long)i, L->nu[i]);
-        if (!isfin(L->S_ref[i]) || !(L->S_ref[i] >= 0.0)) return fail(ctx, HK_EINVAL, "S_ref[%lld] = %g must be finite and >= 0", (long long)i, L->S_ref[i]);
-        if (!isfin(L->E_lower[i])) return fail(ctx, HK_EINVAL, "E_lower[%lld] is not finite", (long long)i);
-        if (!isfin(L->gamma_air[i]) || !(L->gamma_air[i] >= 0.0)) return fail(ctx, HK_EINVAL, "gamma_air[%lld] must be finite and >= 0", (long long)i);
-        if (!isfin(L->n_air[i])) return fail(ctx, HK_EINVAL, "n_air[%lld] is not finite", (long long)i);
-        if (L->gamma_self && (!isfin(L->gamma_self[i]) || !(L->gamma_self[i] >= 0.0))) return fail(ctx, HK_EINVAL, "gamma_self[%lld] must be finite and >= 0", (long long)i);
-        if (L->delta && !isfin(L->delta[i])) return fail(ctx, HK_EINVAL, "delta[%lld] is not finite", (long long)i);
-        if (L->A21 && (!isfin(L->A21[i]) || !(L->A21[i] >= 0.0))) return fail(ctx, HK_EINVAL, "A21[%lld] must be finite and >= 0", (long long)i);
-    }
+    if (int rc = check_species(ctx, sp)) return rc;
+    if (int rc = check_lines(ctx, L, -1)) return rc;
     if (int rc = check_ctx(ctx)) return rc;
     HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
-    // order by ascending (nu, input index): a stable sort of the indices
-    std::vector<int64_t> perm((size_t)n);
-    std::iota(perm.begin(), perm.end(), (int64_t)0);
-    std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return L->nu[a] < L->nu[b]; });
-    const double* src[8] = {L->nu, L->S_ref, L->E_lower, L->gamma_air, L->n_air,
-                            L->gamma_self ? L->gamma_self : L->gamma_air, L->delta, L->A21};
+    const int64_t n = L->n;
     std::vector<double> host((size_t)8 * (size_t)(n > 0 ? n : 1), 0.0);
-    double maxd = 0.0;
-    for (int k = 0; k < 8; ++k) {
-        double* dst = host.data() + (size_t)k * n;
-        if (!src[k]) continue;  // zeros
-        for (int64_t i = 0; i < n; ++i) dst[i] = src[k][perm[(size_t)i]];
-    }
-    if (L->delta)
-        for (int64_t i = 0; i < n; ++i) maxd = std::max(maxd, std::fabs(L->delta[i]));
-    double mga = 0.0, mgs = 0.0, mA = 0.0, nlo = 0.0, nhi = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        mga = std::max(mga, L->gamma_air[i]);
-        mgs = std::max(mgs, L->gamma_self ? L->gamma_self[i] : L->gamma_air[i]);
-        if (L->A21) mA = std::max(mA, L->A21[i]);
-        nlo = i == 0 ? L->n_air[i] : std::min(nlo, L->n_air[i]);
-        nhi = i == 0 ? L->n_air[i] : std::max(nhi, L->n_air[i]);
-    }
+    order_lines(L, host.data());
+    const ListInfo li = list_info(L);
     HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     ctx->n_lines = n;
     ctx->lines_loaded = false;
     ctx->have_run = false;
+    ctx->last_stream_chunks = 0;
     HK_HIP(ctx, ctx->lines.ensure(host.size() * sizeof(double)), "allocating the line list");
     if (n > 0)
         HK_HIP(ctx, hipMemcpy(ctx->lines.p, host.data(), (size_t)8 * n * sizeof(double), hipMemcpyHostToDevice),
                "copying the line list");
-    ctx->has_self = L->gamma_self != nullptr;
-    ctx->has_delta = L->delta != nullptr;
-    ctx->has_A = L->A21 != nullptr;
-    ctx->max_abs_delta = maxd;
-    ctx->max_gamma_air = mga;
-    ctx->max_gamma_self = mgs;
-    ctx->max_A21 = mA;
-    ctx->min_n_air = nlo;
-    ctx->max_n_air = nhi;
-    ctx->nu_max = n > 0 ? host[(size_t)n - 1] : 0.0;
+    ctx->li = li;
     ctx->species = *sp;
     ctx->lines_loaded = true;
     return HK_OK;
@@ -652,32 +798,29 @@ static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, double reach, WingRec* 
     return HK_OK;
 }
 
-int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precision, void* kappa,
-               void* comp, int accumulate)
+// The argument rules of hk_opacity and hk_opacity_stream (no device).
+static int check_opacity_args(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precision, void* kappa)
 {
-    // arguments first, the context last: the checks run without a device
     if (int rc = check_state(ctx, st)) return rc;
     if (int rc = check_grid(ctx, grid)) return rc;
     if (precision != HK_F64 && precision != HK_F32_KAHAN && precision != HK_F32_SURROGATE)
         return fail(ctx, HK_EINVAL, "unknown precision %d", precision);
-    if (comp) return fail(ctx, HK_EINVAL, "comp must be NULL (kappa holds the result in binary64)");
     if (precision != HK_F64 && !(grid->cutoff_lorentz > 0.0) && !(grid->cutoff / grid->dnu < 8388608.0))
         return fail(ctx, HK_EINVAL, "binary32 profiles need cutoff/dnu < 2^23 (got %g)", grid->cutoff / grid->dnu);
     if (grid->n_points > 0 && !kappa) return fail(ctx, HK_EINVAL, "kappa is NULL");
-    if (int rc = check_ctx(ctx)) return rc;
-    if (!ctx->lines_loaded) return fail(ctx, HK_ENOTREADY, "no line list loaded (call hk_load_lines first)");
-    if (precision == HK_F32_SURROGATE && !ctx->sg_certified)
-        return fail(ctx, HK_ENOTREADY, "HK_F32_SURROGATE needs a certified surrogate (hk_surrogate_certify)");
-    if (precision != HK_F64 && !(max_cutoff(ctx, st, grid) / grid->dnu < 8388608.0))
-        return fail(ctx, HK_EINVAL, "binary32 profiles need (largest cutoff)/dnu < 2^23 (got %g)",
-                    max_cutoff(ctx, st, grid) / grid->dnu);
-    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    return HK_OK;
+}
+
+// The launch sequence of one state over the loaded list (line preparation,
+// tile ranges, wing and core kernels), on ctx->stream.
+static int opacity_run(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precision, double* kappa,
+                       int accumulate)
+{
     const int64_t n = ctx->n_lines;
     const int32_t np = (int32_t)grid->n_points;
 
     const PrepParams pp = prep_params(ctx, st, grid);
     ctx->last_P = st->P;
-    ctx->last_tables_states = 0;
 
     const size_t nb = (size_t)std::max<int64_t>(n, 1);
     HK_HIP(ctx, ctx->wing.ensure(nb * sizeof(WingRec)), "allocating line records");
@@ -714,23 +857,156 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
         tm.stop();
     }
     if (precision != HK_F64)
-        return opacity_f32(ctx, grid, reach, wing, widx, core, ranges_c, n_tiles_c, static_cast<double*>(kappa),
-                           accumulate, precision == HK_F32_SURROGATE);
+        return opacity_f32(ctx, grid, reach, wing, widx, core, ranges_c, n_tiles_c, kappa, accumulate,
+                           precision == HK_F32_SURROGATE);
     {
         StageTimer tm(ctx, HK_STAGE_OPACITY);
-        HK_HIP(ctx, launch_wing_f64(ppl, wing, widx, ranges, n_tiles, grid->nu_min, grid->dnu, np,
-                                    static_cast<double*>(kappa), accumulate ? 1 : 0, ctx->stream),
+        HK_HIP(ctx, launch_wing_f64(ppl, wing, widx, ranges, n_tiles, grid->nu_min, grid->dnu, np, kappa,
+                                    accumulate ? 1 : 0, ctx->stream),
                "wing_f64");
         tm.stop();
     }
     {
         StageTimer tm(ctx, HK_STAGE_CORE);
-        HK_HIP(ctx, launch_core_f64(wing, widx, core, ranges_c, n_tiles_c, grid->nu_min, grid->dnu, np,
-                                    static_cast<double*>(kappa), ctx->stream),
+        HK_HIP(ctx, launch_core_f64(wing, widx, core, ranges_c, n_tiles_c, grid->nu_min, grid->dnu, np, kappa,
+                                    ctx->stream),
                "core_f64");
         tm.stop();
     }
     ctx->have_run = true;
+    return HK_OK;
+}
+
+int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precision, void* kappa,
+               void* comp, int accumulate)
+{
+    // arguments first, the context last: the checks run without a device
+    if (int rc = check_opacity_args(ctx, st, grid, precision, kappa)) return rc;
+    if (comp) return fail(ctx, HK_EINVAL, "comp must be NULL (kappa holds the result in binary64)");
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!ctx->lines_loaded) return fail(ctx, HK_ENOTREADY, "no line list loaded (call hk_load_lines first)");
+    if (precision == HK_F32_SURROGATE && !ctx->sg_certified)
+        return fail(ctx, HK_ENOTREADY, "HK_F32_SURROGATE needs a certified surrogate (hk_surrogate_certify)");
+    if (precision != HK_F64 && !(max_cutoff(ctx, st, grid) / grid->dnu < 8388608.0))
+        return fail(ctx, HK_EINVAL, "binary32 profiles need (largest cutoff)/dnu < 2^23 (got %g)",
+                    max_cutoff(ctx, st, grid) / grid->dnu);
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    ctx->last_tables_states = 0;
+    ctx->last_stream_chunks = 0;
+    return opacity_run(ctx, st, grid, precision, static_cast<double*>(kappa), accumulate);
+}
+
+// Sizes every per-line buffer of opacity_run for lists of up to n lines, so
+// that a stream of chunks never reallocates (and so never synchronises) in
+// its loop.
+static int reserve_line_buffers(hk_ctx* ctx, int64_t n, int precision)
+{
+    const size_t nb = (size_t)std::max<int64_t>(n, 1);
+    HK_HIP(ctx, ctx->wing.ensure(nb * sizeof(WingRec)), "allocating line records");
+    HK_HIP(ctx, ctx->widx.ensure(nb * sizeof(WingIdx)), "allocating line records");
+    HK_HIP(ctx, ctx->core.ensure(nb * sizeof(CoreRec)), "allocating line records");
+    if (precision != HK_F64) {
+        HK_HIP(ctx, ctx->w32.ensure(nb * sizeof(WingRec32)), "allocating binary32 records");
+        HK_HIP(ctx, ctx->c32.ensure(nb * sizeof(CoreRec32)), "allocating binary32 records");
+    }
+    HK_HIP(ctx, ctx->lines.ensure((size_t)8 * nb * sizeof(double)), "allocating the line list");
+    HK_HIP(ctx, ctx->lines_alt.ensure((size_t)8 * nb * sizeof(double)), "allocating the line list");
+    return HK_OK;
+}
+
+static int stream_resources(hk_ctx* ctx, size_t pin_doubles)
+{
+    if (!ctx->copy) HK_HIP(ctx, hipStreamCreateWithFlags(&ctx->copy, hipStreamNonBlocking), "hipStreamCreate");
+    for (int x = 0; x < 2; ++x) {
+        if (!ctx->ev_copied[x])
+            HK_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_copied[x], hipEventDisableTiming), "hipEventCreate");
+        if (!ctx->ev_used[x])
+            HK_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_used[x], hipEventDisableTiming), "hipEventCreate");
+    }
+    // copies of an earlier call read the staging buffers: let them finish
+    HK_HIP(ctx, hipStreamSynchronize(ctx->copy), "hipStreamSynchronize");
+    if (pin_doubles > ctx->pin_cap) {
+        for (int x = 0; x < 2; ++x) {
+            if (ctx->pin[x]) (void)hipHostFree(ctx->pin[x]);
+            ctx->pin[x] = nullptr;
+        }
+        ctx->pin_cap = 0;
+        for (int x = 0; x < 2; ++x)
+            HK_HIP(ctx, hipHostMalloc((void**)&ctx->pin[x], pin_doubles * sizeof(double), hipHostMallocDefault),
+                   "allocating pinned staging");
+        ctx->pin_cap = pin_doubles;
+    }
+    return HK_OK;
+}
+
+int hk_opacity_stream(hk_ctx* ctx, const hk_lines* chunks, int32_t n_chunks, const hk_species* sp,
+                      const hk_state* st, const hk_grid* grid, int precision, double* kappa, int accumulate)
+{
+    if (int rc = check_opacity_args(ctx, st, grid, precision, kappa)) return rc;
+    if (n_chunks < 0 || n_chunks > HK_MAX_CHUNKS)
+        return fail(ctx, HK_EINVAL, "n_chunks = %d out of [0, %d]", n_chunks, HK_MAX_CHUNKS);
+    if (n_chunks > 0 && !chunks) return fail(ctx, HK_EINVAL, "chunks is NULL");
+    if (int rc = check_species(ctx, sp)) return rc;
+    // every chunk is checked before any work is enqueued
+    std::vector<ListInfo> info((size_t)n_chunks);
+    int64_t n_max = 0, n_total = 0;
+    for (int32_t c = 0; c < n_chunks; ++c) {
+        if (int rc = check_lines(ctx, &chunks[c], c)) return rc;
+        info[(size_t)c] = list_info(&chunks[c]);
+        if (precision != HK_F64 && !(max_cutoff(info[(size_t)c], sp->T_ref, st, grid) / grid->dnu < 8388608.0))
+            return fail(ctx, HK_EINVAL, "chunk %d: binary32 profiles need (largest cutoff)/dnu < 2^23 (got %g)", c,
+                        max_cutoff(info[(size_t)c], sp->T_ref, st, grid) / grid->dnu);
+        n_max = std::max(n_max, chunks[c].n);
+        n_total += chunks[c].n;
+    }
+    if (int rc = check_ctx(ctx)) return rc;
+    if (precision == HK_F32_SURROGATE && !ctx->sg_certified)
+        return fail(ctx, HK_ENOTREADY, "HK_F32_SURROGATE needs a certified surrogate (hk_surrogate_certify)");
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    const int64_t np = grid->n_points;
+    if (n_chunks == 0) {  // the opacity of no lines
+        if (!accumulate && np > 0)
+            HK_HIP(ctx, hipMemsetAsync(kappa, 0, (size_t)np * sizeof(double), ctx->stream), "hipMemsetAsync");
+        return HK_OK;
+    }
+    // the loaded list is replaced: from here on it is the chunk being computed
+    ctx->lines_loaded = false;
+    ctx->have_run = false;
+    ctx->last_tables_states = 0;
+    ctx->last_stream_chunks = 0;
+    HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    if (int rc = reserve_line_buffers(ctx, n_max, precision)) return rc;
+    if (int rc = stream_resources(ctx, (size_t)8 * (size_t)std::max<int64_t>(n_max, 1))) return rc;
+    HK_HIP(ctx, ctx->st_counts.ensure((size_t)kCountBlocks * 3 * (size_t)n_chunks * sizeof(int64_t)),
+           "allocating counters");
+    ctx->species = *sp;
+    for (int32_t c = 0; c < n_chunks; ++c) {
+        const int x = c & 1;
+        const int64_t n = chunks[c].n;
+        // staging x last held chunk c-2: its copy must be done before it is rewritten
+        if (c >= 2) HK_HIP(ctx, hipEventSynchronize(ctx->ev_copied[x]), "hipEventSynchronize");
+        order_lines(&chunks[c], ctx->pin[x]);
+        if (c > 0) std::swap(ctx->lines, ctx->lines_alt);  // device buffer x holds chunk c
+        // device buffer x last held chunk c-2: wait until its kernels are done
+        if (c >= 2) HK_HIP(ctx, hipStreamWaitEvent(ctx->copy, ctx->ev_used[x], 0), "hipStreamWaitEvent");
+        if (n > 0)
+            HK_HIP(ctx, hipMemcpyAsync(ctx->lines.p, ctx->pin[x], (size_t)8 * n * sizeof(double),
+                                       hipMemcpyHostToDevice, ctx->copy),
+                   "copying a chunk");
+        HK_HIP(ctx, hipEventRecord(ctx->ev_copied[x], ctx->copy), "hipEventRecord");
+        HK_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_copied[x], 0), "hipStreamWaitEvent");
+        ctx->n_lines = n;
+        ctx->li = info[(size_t)c];
+        ctx->lines_loaded = true;
+        if (int rc = opacity_run(ctx, st, grid, precision, kappa, (accumulate || c > 0) ? 1 : 0)) return rc;
+        HK_HIP(ctx, launch_eval_counts(static_cast<WingIdx*>(ctx->widx.p), n,
+                                       static_cast<int64_t*>(ctx->st_counts.p) + (size_t)kCountBlocks * 3 * c,
+                                       kCountBlocks, ctx->stream),
+               "eval_counts");
+        HK_HIP(ctx, hipEventRecord(ctx->ev_used[x], ctx->stream), "hipEventRecord");
+    }
+    ctx->last_stream_chunks = n_chunks;
+    ctx->stream_lines = n_total;
     return HK_OK;
 }
 
@@ -787,6 +1063,7 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
                 return fail(ctx, HK_EINVAL, "states[%d]: binary32 profiles need (largest cutoff)/dnu < 2^23", i);
     HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     ctx->last_tables_states = 0;
+    ctx->last_stream_chunks = 0;
     if (n_states == 0 || np == 0) return HK_OK;
 
     const int64_t n = ctx->n_lines;
@@ -1218,21 +1495,25 @@ int hk_stats(hk_ctx* ctx, hk_run_stats* out)
     if (int rc = check_ctx(ctx)) return rc;
     if (!out) return fail(ctx, HK_EINVAL, "out is NULL");
     std::memset(out, 0, sizeof *out);
-    out->n_lines = ctx->n_lines;
+    const bool streamed = ctx->last_stream_chunks > 0;
+    out->n_lines = streamed ? ctx->stream_lines : ctx->n_lines;
     if (!ctx->have_run) return fail(ctx, HK_ENOTREADY, "no hk_opacity call yet");
     HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
-    // hk_opacity: count from the state's records now; hk_tables: the
-    // per-state counters it left
+    // hk_opacity: count from the state's records now; hk_tables and
+    // hk_opacity_stream: the per-state or per-chunk counters they left
     const bool tables = ctx->last_tables_states > 0;
-    const int64_t nblk = tables ? (int64_t)kCountBlocks * ctx->last_tables_states : kCountBlocks;
+    const int64_t nblk = tables     ? (int64_t)kCountBlocks * ctx->last_tables_states
+                         : streamed ? (int64_t)kCountBlocks * ctx->last_stream_chunks
+                                    : kCountBlocks;
     HK_HIP(ctx, ctx->partial.ensure((size_t)kCountBlocks * 3 * sizeof(int64_t)), "allocating counters");
-    if (ctx->n_lines > 0) {
-        if (!tables)
+    if (out->n_lines > 0) {
+        if (!tables && !streamed)
             HK_HIP(ctx, launch_eval_counts(static_cast<WingIdx*>(ctx->widx.p), ctx->n_lines,
                                            static_cast<int64_t*>(ctx->partial.p), kCountBlocks, ctx->stream),
                    "eval_counts");
         std::vector<int64_t> h((size_t)nblk * 3);
-        HK_HIP(ctx, hipMemcpyAsync(h.data(), tables ? ctx->tb_counts.p : ctx->partial.p, h.size() * sizeof(int64_t),
+        const void* src = tables ? ctx->tb_counts.p : streamed ? ctx->st_counts.p : ctx->partial.p;
+        HK_HIP(ctx, hipMemcpyAsync(h.data(), src, h.size() * sizeof(int64_t),
                                    hipMemcpyDeviceToHost, ctx->stream),
                "copying counters");
         HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");

@@ -220,4 +220,8 @@ hipError_t launch_transmission_fit(const double* coef, int64_t n_bins, int nc, c
 hipError_t launch_transmission_direct(const void* sorted, int key_bytes, int64_t n_points, int64_t ppb,
                                       const double* m, int n_m, double* T, hipStream_t s);
 
+// Sets the message hk_last_error(NULL) returns on this thread (host code
+// outside hk_api.cpp that fails without a context).
+void set_thread_error(const char* msg);
+
 }  // namespace hk

@@ -207,3 +207,40 @@ def test_resample_and_transmission_validate_arguments():
     assert L.hk_transmission(None, 1, 3, 20, 1, -1, 1) == hk.HK_EINVAL
     assert L.hk_transmission(None, None, 3, 20, 1, 5, 1) == hk.HK_EINVAL
     assert L.hk_transmission_direct(None, 1, 0, 100, 0, 1, 5, 1) == hk.HK_EINVAL
+
+
+def _stream_rc(chunks, n_chunks=None, species=(296.0, 18.0), state=GOOD_STATE, grid=GOOD_GRID,
+               precision=hk.HK_F64):
+    made = [hk._lines(c) for c in chunks]
+    arr = (hk.hk_lines * max(len(made), 1))(*[m[0] for m in made])
+    sp = hk.hk_species(*species)
+    st, gr = hk._state(state), hk._grid(grid)
+    n = len(made) if n_chunks is None else n_chunks
+    return hk.lib().hk_opacity_stream(None, arr if made else None, n, C.byref(sp), C.byref(st),
+                                      C.byref(gr), precision, 1, 0)
+
+
+def _chunk(n, seed):
+    import synth
+    return synth.line_list(n, 10.0, seed=seed)
+
+
+def test_opacity_stream_rejects_bad_input():
+    good = [_chunk(5, 0), _chunk(7, 1)]
+    assert _stream_rc(good, n_chunks=-1) == hk.HK_EINVAL and "n_chunks" in hk.hk_last_error(None)
+    assert _stream_rc([], n_chunks=2) == hk.HK_EINVAL and "chunks is NULL" in hk.hk_last_error(None)
+    assert _stream_rc(good, species=(296.0, 0.0)) == hk.HK_EINVAL
+    assert "mass_amu" in hk.hk_last_error(None)
+    bad = _chunk(7, 1)
+    bad["S_ref"][2] = -1.0
+    assert _stream_rc([good[0], bad]) == hk.HK_EINVAL
+    assert hk.hk_last_error(None).startswith("chunk 1: S_ref[2]")
+    assert _stream_rc(good, precision=7) == hk.HK_EINVAL and "precision" in hk.hk_last_error(None)
+    wide = dict(GOOD_GRID, dnu=1e-9, cutoff=1.0)
+    assert _stream_rc(good, grid=wide, precision=hk.HK_F32_KAHAN) == hk.HK_EINVAL
+    assert "2^23" in hk.hk_last_error(None)
+    lor = dict(GOOD_GRID, dnu=1e-7, cutoff_lorentz=1e6)
+    assert _stream_rc(good, grid=lor, precision=hk.HK_F32_KAHAN) == hk.HK_EINVAL
+    assert hk.hk_last_error(None).startswith("chunk 0: binary32")
+    # valid arguments reach the context check (NULL context)
+    assert _stream_rc(good) == hk.HK_EINVAL and "context" in hk.hk_last_error(None)
