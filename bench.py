@@ -9,10 +9,11 @@ before timing starts.  Beside the headline the line reports the binary32
 variant of the same step, the Chebyshev resampling and transmission of the
 same bins, the batched tables (the same lines over 200 (T, P) states) and
 the learned surrogate (1e8 lines, 25 cm^-1 cutoff, against the binary64
-path).  Prints one JSON line.
+path) and a 1e7-line list streamed from host memory in 34 pieces.  Prints
+one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-f32]
-                    [--no-resample] [--no-tables] [--no-surrogate]
+                    [--no-resample] [--no-tables] [--no-surrogate] [--no-stream]
 """
 from __future__ import annotations
 
@@ -117,6 +118,54 @@ def bench_resample(hk, torch, ctx, kappa, N, ppb, g):
     t_tr = time.perf_counter() - t1
     return {"bins": int(-(-N // ppb)), "n_coef": 20, "n_m": 1000,
             "ms_sort_fit_transmission": 1e3 * dt, "ms_fit": 1e3 * t_fit, "ms_transmission": 1e3 * t_tr}
+
+
+def bench_stream(hk, torch, ctx, n_chunks: int = 34):
+    """A list streamed from host memory: the 1e7-line binary32 workload cut
+    into 34 wavenumber-ordered pieces (the paper's largest list came in 34
+    files), timed wall-clock from host arrays to the finished grid, against
+    the same opacity call on the list already resident on the device and
+    against loading and accumulating the pieces one call at a time."""
+    import numpy as np
+    import synth
+    w = synth.WORKLOADS["lines1e7_fp32"]
+    lines, cond, grid = w.lines(), w.conditions(), w.grid()
+    st = {k: cond[k] for k in ("T", "P", "P_self", "q_ratio")}
+    log("bench: stream, %d lines in %d chunks" % (len(lines["nu"]), n_chunks))
+    order = np.argsort(lines["nu"], kind="stable")
+    ordered = {k: np.ascontiguousarray(v[order]) for k, v in lines.items()}
+    cuts = np.linspace(0, len(order), n_chunks + 1).astype(int)
+    chunks = [{k: v[a:b] for k, v in ordered.items()} for a, b in zip(cuts[:-1], cuts[1:])]
+    prec = hk.HK_F32_KAHAN
+    out = torch.empty(grid["n_points"], dtype=torch.float64, device="cuda")
+
+    def wall(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / reps
+
+    ms_stream = wall(lambda: ctx.opacity_stream(chunks, cond["mass_amu"], st, grid, prec, out=out,
+                                                T_ref=cond["T0"]), 3)
+    evals = ctx.stats()["evals"]
+
+    def sequential():
+        for i, c in enumerate(chunks):
+            ctx.load_lines(c, cond["mass_amu"], cond["T0"])
+            ctx.opacity(st, grid, prec, out=out, accumulate=i > 0)
+    ms_seq = wall(sequential, 1)
+    t0 = time.perf_counter()
+    ctx.load_lines(ordered, cond["mass_amu"], cond["T0"])
+    ms_load = 1e3 * (time.perf_counter() - t0)
+    ms_res = wall(lambda: ctx.opacity(st, grid, prec, out=out), 3)
+    return {"workload": w.name, "chunks": n_chunks, "precision": "f32_kahan", "evals": evals,
+            "ms_streamed": ms_stream, "ms_resident_opacity": ms_res,
+            "ms_load_whole_list": ms_load, "ms_load_and_opacity_per_chunk": ms_seq,
+            "host_bytes": 8 * 5 * len(order),
+            "streamed_over_resident": ms_stream / ms_res}
 
 
 def bench_tables(hk, torch, ctx, g):
@@ -225,6 +274,7 @@ def main(argv=None):
     ap.add_argument("--no-resample", action="store_true",
                     help="skip the Chebyshev resampling + transmission leg")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate workload")
+    ap.add_argument("--no-stream", action="store_true", help="skip the streamed line list")
     ap.add_argument("--surrogate-lines", type=int, default=0,
                     help="lines of the surrogate leg (default: the workload's 1e8; fewer for profiling)")
     ap.add_argument("--surrogate-train-steps", type=int, default=0,
@@ -328,6 +378,8 @@ def main(argv=None):
         rec["resample"] = bench_resample(hk, torch, ctx, kappa, N, ppb, g)
     if not a.no_tables:
         rec["tables"] = bench_tables(hk, torch, ctx, g)
+    if not a.no_stream:
+        rec["stream"] = bench_stream(hk, torch, ctx)
     if not a.no_cpu_baseline:
         log("bench: timing the oracle on a sample")
         rec["cpu_baseline"] = cpu_baseline(w, a.cpu_points)

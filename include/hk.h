@@ -180,8 +180,11 @@ int hk_read_par(const char* path, int64_t first, int32_t molecule, const hk_line
  * the Faddeeva function for a^2+u^2 < 100 and 3-node / 1-node Gauss-Hermite
  * quadrature for a^2+u^2 < 1e6 / >= 1e6 (§2.4).  Each point sums its
  * Gauss-Hermite terms, then its series terms, each in ascending (nu, input
- * index) order, with no atomics: results are bitwise reproducible and do not
- * depend on the tuning options.
+ * index) order, with no atomics; where the lines crowd into few grid tiles
+ * (a wavenumber-ordered piece of a list, a dense band) the Gauss-Hermite sum
+ * is split at fixed line-index segments whose ordered sums are then added in
+ * segment order.  Results are bitwise reproducible, do not depend on the
+ * tuning options, and agree bit for bit with hk_tables.
  *
  * kappa is [device] double[n_points] for both precisions; comp must be NULL
  * (reserved).
@@ -372,8 +375,12 @@ int hk_gauss_legendre(int32_t n, double* g, double* w);
  *                          cached choices are dropped.
  * Unknown names or values: HK_EINVAL. */
 int hk_set_option(hk_ctx* ctx, const char* name, int64_t value);
-/* Reads a knob into *value; also "tables_points_per_lane", the tile shape
- * the last hk_tables call used (0 before any). */
+/* Reads a knob into *value; also, read-only: "tables_points_per_lane", the
+ * tile shape the last hk_tables call used (0 before any); "wing_items", the
+ * work items of the last wing launch (one per grid tile and state unless
+ * tiles were split into line segments); "wing_segment_lines", the segment
+ * length of that launch's first state (0: not split).  The last two wait
+ * for the stream. */
 int hk_get_option(hk_ctx* ctx, const char* name, int64_t* value);
 
 /* Evaluation counts of the last hk_opacity call, or summed over the states

@@ -81,6 +81,9 @@ struct hk_ctx {
     DevBuf wing, widx, core, ranges, ranges_core;
     DevBuf partial;
     DevBuf kscratch;
+    // work plan of the wing kernels: reference tile ranges, segment lengths,
+    // per-pair first item and partial slot, block sums, totals, partial sums
+    DevBuf wp_ref, wp_seg, wp_first, wp_slot, wp_bsum, wp_total, wp_partial;
     // binary32 path: records, Kahan pair, scale
     DevBuf w32, c32, f32sum, f32comp, f32scale, f32partial;
     bool have_run = false;
@@ -471,6 +474,69 @@ namespace {
 
 constexpr int32_t kCountBlocks = 256;  // partial sums per evaluation count
 
+// The wing stage of n_states states whose records lie n_lines apart: the
+// states' reference tile ranges, segment lengths and work plan, then the
+// wing items and the reduction of cut tiles (work_plan.hip).  ranges: tile
+// ranges for tiles of `ppl` points per lane, 2 n_tiles per state; reach[s]:
+// state s's wing reach; out: kappa (binary64) or the Kahan sums (binary32,
+// with comp), n_points per state.  exact: read the plan's totals back (one
+// host synchronisation) to size the launch and the partial sums; else their
+// bounds.
+int wing_stage(hk_ctx* ctx, int precision, int ppl, const void* recs, const WingIdx* idx, const int64_t* ranges,
+               int64_t n_tiles, int32_t n_states, const double* reach, const hk_grid* grid, void* out, float* comp,
+               int accumulate, bool exact)
+{
+    const int64_t n = ctx->n_lines;
+    const int32_t np = (int32_t)grid->n_points;
+    const bool f64 = precision == HK_F64;
+    const int32_t tp = f64 ? opacity_f64_tile_points(ppl) : opacity_f32_tile_points(ppl);
+    const int64_t n_ref = ((int64_t)np + kRefTilePoints - 1) / kRefTilePoints;
+    const int64_t P = n_tiles * n_states;
+    HK_HIP(ctx, ctx->wp_ref.ensure((size_t)std::max<int64_t>(n_ref * n_states, 1) * 2 * sizeof(int64_t)),
+           "allocating the work plan");
+    HK_HIP(ctx, ctx->wp_seg.ensure((size_t)std::max(n_states, 1) * sizeof(int64_t)), "allocating the work plan");
+    HK_HIP(ctx, ctx->wp_first.ensure((size_t)std::max<int64_t>(P, 1) * sizeof(int64_t)), "allocating the work plan");
+    HK_HIP(ctx, ctx->wp_slot.ensure((size_t)std::max<int64_t>(P, 1) * sizeof(int64_t)), "allocating the work plan");
+    HK_HIP(ctx, ctx->wp_bsum.ensure((size_t)plan_scratch_count(P) * sizeof(int64_t)), "allocating the work plan");
+    HK_HIP(ctx, ctx->wp_total.ensure(2 * sizeof(int64_t)), "allocating the work plan");
+    int64_t* ref = static_cast<int64_t*>(ctx->wp_ref.p);
+    int64_t* seg = static_cast<int64_t*>(ctx->wp_seg.p);
+    int64_t* first = static_cast<int64_t*>(ctx->wp_first.p);
+    int64_t* slot = static_cast<int64_t*>(ctx->wp_slot.p);
+    int64_t* total = static_cast<int64_t*>(ctx->wp_total.p);
+    const double* nu = lines_field(ctx, 0);
+    for (int32_t s = 0; s < n_states; ++s)
+        HK_HIP(ctx, launch_tile_ranges(nu, n, n_ref, kRefTilePoints, grid->nu_min, grid->dnu, np, reach[s],
+                                       ref + (int64_t)s * 2 * n_ref, ctx->stream),
+               "tile_ranges");
+    HK_HIP(ctx, launch_seg_length(ref, n_ref, n_states, np, n, seg, ctx->stream), "seg_length");
+    HK_HIP(ctx, launch_work_plan(ranges, n_tiles, n_states, seg, first, slot, static_cast<int64_t*>(ctx->wp_bsum.p),
+                                 total, ctx->stream),
+           "work_plan");
+    int64_t items = n_states * plan_items_bound(n_tiles);
+    int64_t points = n_states * plan_partial_points_bound(np, tp);
+    if (exact) {
+        int64_t h[2] = {0, 0};
+        HK_HIP(ctx, hipMemcpyAsync(h, total, sizeof h, hipMemcpyDeviceToHost, ctx->stream), "reading the work plan");
+        HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        items = h[0];
+        points = h[1] * tp;
+    }
+    HK_HIP(ctx, ctx->wp_partial.ensure((size_t)std::max<int64_t>(points, 1) * 8), "allocating partial sums");
+    const WorkPlan wp{seg, first, slot, total, P};
+    if (f64)
+        HK_HIP(ctx, launch_wing_f64(ppl, static_cast<const WingRec*>(recs), idx, ranges, n, n_tiles, n_states, wp, items,
+                                    grid->nu_min, grid->dnu, np, static_cast<double*>(out),
+                                    static_cast<double*>(ctx->wp_partial.p), accumulate, ctx->stream),
+               "wing_f64");
+    else
+        HK_HIP(ctx, launch_wing_f32(ppl, static_cast<const WingRec32*>(recs), idx, ranges, n, n_tiles, n_states, wp,
+                                    items, np, static_cast<float*>(out), comp, static_cast<float2*>(ctx->wp_partial.p),
+                                    ctx->stream),
+               "wing_f32");
+    return HK_OK;
+}
+
 // Times the batched wing kernel at 2, 4 and 8 points per lane on the first
 // states of a batch (one untimed launch, then one timed launch each) and
 // returns the fastest shape.  The shapes give identical results, so the
@@ -490,6 +556,8 @@ int autotune_wing(hk_ctx* ctx, int precision, const hk_state* states, int32_t n_
     int best = 0;
     float best_ms = 0.0f;
     hipError_t err = hipSuccess;
+    std::vector<double> reach((size_t)n_try);
+    for (int32_t s = 0; s < n_try; ++s) reach[(size_t)s] = wing_reach(ctx, &states[s], grid);
     for (int cand : {2, 4, 8}) {
         const int32_t tp = precision == HK_F64 ? opacity_f64_tile_points(cand) : opacity_f32_tile_points(cand);
         const int64_t n_tiles = ((int64_t)np + tp - 1) / tp;
@@ -504,17 +572,14 @@ int autotune_wing(hk_ctx* ctx, int precision, const hk_state* states, int32_t n_
         for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
             if (rep == 1) err = hipEventRecord(e0, ctx->stream);
             if (err != hipSuccess) break;
-            if (precision == HK_F64)
-                err = launch_wing_f64_batched(cand, static_cast<WingRec*>(ctx->tb_wing.p),
-                                              static_cast<WingIdx*>(ctx->tb_idx.p), ranges, n, n_tiles,
-                                              grid->nu_min, grid->dnu, np, n_try, static_cast<double*>(ctx->tb_out.p),
-                                              ctx->stream);
-            else
-                err = launch_wing_f32_batched(cand, static_cast<WingRec32*>(ctx->tb_w32.p),
-                                              static_cast<WingIdx*>(ctx->tb_idx.p), ranges, n, n_tiles, np, n_try,
-                                              static_cast<float*>(ctx->tb_out.p), static_cast<float*>(ctx->tb_comp.p),
-                                              ctx->stream);
-            if (err != hipSuccess) break;
+            const void* recs = precision == HK_F64 ? ctx->tb_wing.p : ctx->tb_w32.p;
+            if (int rc = wing_stage(ctx, precision, cand, recs, static_cast<WingIdx*>(ctx->tb_idx.p), ranges, n_tiles,
+                                    n_try, reach.data(), grid, ctx->tb_out.p, static_cast<float*>(ctx->tb_comp.p), 0,
+                                    false)) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return rc;
+            }
             if (rep == 1) {
                 err = hipEventRecord(e1, ctx->stream);
                 if (err == hipSuccess) err = hipEventSynchronize(e1);
@@ -673,6 +738,9 @@ int hk_destroy(hk_ctx* ctx)
     ctx->ranges_core.release();
     ctx->partial.release();
     ctx->kscratch.release();
+    for (DevBuf* b : {&ctx->wp_ref, &ctx->wp_seg, &ctx->wp_first, &ctx->wp_slot, &ctx->wp_bsum, &ctx->wp_total,
+                      &ctx->wp_partial})
+        b->release();
     for (DevBuf* b : {&ctx->w32, &ctx->c32, &ctx->f32sum, &ctx->f32comp, &ctx->f32scale, &ctx->f32partial})
         b->release();
     for (DevBuf* b : {&ctx->tb_idx, &ctx->tb_wing, &ctx->tb_core, &ctx->tb_w32, &ctx->tb_c32, &ctx->tb_ranges,
@@ -780,7 +848,8 @@ static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, double reach, WingRec* 
     }
     {
         StageTimer tm(ctx, HK_STAGE_OPACITY);
-        HK_HIP(ctx, launch_wing_f32(ppl, w32, widx, ranges, n_tiles, np, fs, fc, ctx->stream), "wing_f32");
+        if (int rc = wing_stage(ctx, HK_F32_KAHAN, ppl, w32, widx, ranges, n_tiles, 1, &reach, grid, fs, fc, 0, false))
+            return rc;
         tm.stop();
     }
     {
@@ -861,9 +930,9 @@ static int opacity_run(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int
                            precision == HK_F32_SURROGATE);
     {
         StageTimer tm(ctx, HK_STAGE_OPACITY);
-        HK_HIP(ctx, launch_wing_f64(ppl, wing, widx, ranges, n_tiles, grid->nu_min, grid->dnu, np, kappa,
-                                    accumulate ? 1 : 0, ctx->stream),
-               "wing_f64");
+        if (int rc = wing_stage(ctx, HK_F64, ppl, wing, widx, ranges, n_tiles, 1, &reach, grid, kappa, nullptr,
+                                accumulate ? 1 : 0, false))
+            return rc;
         tm.stop();
     }
     {
@@ -1183,16 +1252,11 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
                                                wing_reach(ctx, &states[b0 + s], grid), rw + (int64_t)s * 2 * n_tiles,
                                                ctx->stream),
                        "tile_ranges");
-            if (f64)
-                HK_HIP(ctx, launch_wing_f64_batched(ppl, static_cast<WingRec*>(ctx->tb_wing.p), tidx, rw, n, n_tiles,
-                                                    grid->nu_min, grid->dnu, np, nbat,
-                                                    static_cast<double*>(ctx->tb_out.p), ctx->stream),
-                       "wing_f64_batched");
-            else
-                HK_HIP(ctx, launch_wing_f32_batched(ppl, static_cast<WingRec32*>(ctx->tb_w32.p), tidx, rw, n, n_tiles,
-                                                    np, nbat, static_cast<float*>(ctx->tb_out.p),
-                                                    static_cast<float*>(ctx->tb_comp.p), ctx->stream),
-                       "wing_f32_batched");
+            std::vector<double> reach((size_t)nbat);
+            for (int32_t s = 0; s < nbat; ++s) reach[(size_t)s] = wing_reach(ctx, &states[b0 + s], grid);
+            if (int rc = wing_stage(ctx, precision, ppl, f64 ? ctx->tb_wing.p : ctx->tb_w32.p, tidx, rw, n_tiles, nbat,
+                                    reach.data(), grid, ctx->tb_out.p, static_cast<float*>(ctx->tb_comp.p), 0, true))
+                return rc;
             tm.stop();
         }
         {
@@ -1575,7 +1639,19 @@ int hk_get_option(hk_ctx* ctx, const char* name, int64_t* value)
     else if (std::strcmp(name, "tables_mem_mib") == 0) *value = ctx->tables_mem >> 20;
     else if (std::strcmp(name, "tables_autotune") == 0) *value = ctx->tables_autotune;
     else if (std::strcmp(name, "tables_points_per_lane") == 0) *value = ctx->tables_ppl_used;
-    else return fail(ctx, HK_EINVAL, "unknown option '%s'", name);
+    else if (std::strcmp(name, "wing_items") == 0 || std::strcmp(name, "wing_segment_lines") == 0) {
+        // the last wing stage's plan (for its first state), read back
+        *value = 0;
+        if (!ctx->wp_total.p) return HK_OK;
+        HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+        const bool items = name[5] == 'i';
+        HK_HIP(ctx, hipMemcpyAsync(value, items ? ctx->wp_total.p : ctx->wp_seg.p, sizeof *value,
+                                   hipMemcpyDeviceToHost, ctx->stream),
+               "reading the work plan");
+        HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        if (!items && *value == kNoSplit) *value = 0;
+    } else
+        return fail(ctx, HK_EINVAL, "unknown option '%s'", name);
     return HK_OK;
 }
 

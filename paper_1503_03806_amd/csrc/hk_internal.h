@@ -120,6 +120,107 @@ struct GValues {
     int32_t n;
 };
 
+// ---- work items of the wing kernels (work_plan.hip) ----
+// A tile's lines are summed by one workgroup, unless the lines crowd into
+// few tiles or unevenly (a wavenumber-ordered piece of a list, a dense band):
+// then every tile's line range is cut where it crosses a multiple of a
+// segment length Lseg (a power of two >= 256, per state, from statistics of
+// 512-point reference tiles, so the same for every tile shape), and each
+// piece is an item of its own that writes partial sums; a reduction adds a
+// cut tile's partials in segment order.  A point's value is then the ordered
+// sum over segments of the ordered sum of its lines in each segment -- the
+// same for every tile shape, since a tile is cut exactly where the lines
+// reaching its points span segments (other segments add exact zeros).
+// Items: every (state, tile) pair in chunks of kPlanChunk tiles (dearest
+// first), each chunk holding every state's run of those tiles, a pair's
+// segments consecutive; workgroups take items in XCD-dealt chunks.
+constexpr int32_t kRefTilePoints = 512;
+constexpr int64_t kNoSplit = (int64_t)1 << 62;
+constexpr int32_t kPlanChunk = 32;
+struct WorkPlan {
+    const int64_t* seg;    // [n_states] segment length (kNoSplit: not cut)
+    const int64_t* first;  // [n_pairs] first item of each pair, in pair order
+    const int64_t* slot;   // [n_pairs] first partial slot of each cut pair
+    const int64_t* total;  // [2] items, partial slots
+    int64_t n_pairs;
+};
+// Upper bounds per state, for sizing without reading the plan back: items
+// <= 4 n_tiles + 2, partial points <= 4 n_points + 2 tile_points.
+inline int64_t plan_items_bound(int64_t n_tiles) { return 4 * n_tiles + 2; }
+inline int64_t plan_partial_points_bound(int64_t n_points, int32_t tile_points)
+{
+    return 4 * n_points + 2 * (int64_t)tile_points;
+}
+int64_t plan_scratch_count(int64_t n_pairs);  // int64 values of the plan's block sums
+// seg[s] from the reference ranges (tiles of kRefTilePoints points, 2 n_ref
+// values per state) of n_states states.
+hipError_t launch_seg_length(const int64_t* ref_ranges, int64_t n_ref, int32_t n_states, int64_t n_points,
+                             int64_t n_lines, int64_t* seg, hipStream_t s);
+// first, slot and total from the tile ranges (2 n_tiles per state) and seg.
+hipError_t launch_work_plan(const int64_t* ranges, int64_t n_tiles, int32_t n_states, const int64_t* seg,
+                            int64_t* first, int64_t* slot, int64_t* block_sums, int64_t* total, hipStream_t s);
+// Workgroups for `items` items: padded to whole XCD chunks.
+inline int64_t plan_blocks(int64_t items) { return (items + 8 * kPlanChunk - 1) / (8 * kPlanChunk) * (8 * kPlanChunk); }
+
+// Rank of workgroup b: XCD b % 8 takes chunks of kPlanChunk consecutive
+// ranks, so neighbouring tiles, which read mostly the same lines, share an
+// L2 (a bijection on every multiple of 8 kPlanChunk).
+__device__ inline int64_t xcd_rank(int64_t b)
+{
+    const int64_t x = b & 7, k = b >> 3;
+    return ((k / kPlanChunk) * 8 + x) * kPlanChunk + (k % kPlanChunk);
+}
+// (state, tile rank) of pair p.
+__device__ inline void pair_decode(int64_t p, int64_t n_tiles, int32_t n_states, int64_t& st, int64_t& k)
+{
+    const int64_t per_chunk = (int64_t)kPlanChunk * n_states;
+    const int64_t c = p / per_chunk;
+    const int64_t sz = min((int64_t)kPlanChunk, n_tiles - c * kPlanChunk);
+    const int64_t rem = p - c * per_chunk;
+    st = rem / sz;
+    k = c * kPlanChunk + rem % sz;
+}
+struct WorkItem {
+    int64_t st, tile;  // state, grid tile
+    int64_t lo, hi;    // lines [lo, hi)
+    int64_t slot;      // partial slot, or -1: the item writes the output
+};
+// Item r of the plan (false past the last item).  Every thread of a
+// workgroup calls it with the same r.
+__device__ inline bool work_item(int64_t r, const WorkPlan& wp, const int64_t* ranges, int64_t n_tiles,
+                                 int32_t n_states, WorkItem& it)
+{
+    const int64_t total = wp.total[0];
+    if (r >= total) return false;
+    int64_t p = r;  // nothing cut: item r is pair r
+    if (total != wp.n_pairs) {
+        int64_t a = 0, b = wp.n_pairs;  // last pair whose first item <= r
+        while (b - a > 1) {
+            const int64_t m = a + ((b - a) >> 1);
+            if (wp.first[m] <= r) a = m;
+            else b = m;
+        }
+        p = a;
+    }
+    const int64_t nseg = (p + 1 < wp.n_pairs ? wp.first[p + 1] : total) - wp.first[p];
+    int64_t k;
+    pair_decode(p, n_tiles, n_states, it.st, k);
+    it.tile = n_tiles - 1 - k;
+    const int64_t* rg = ranges + it.st * 2 * n_tiles;
+    it.lo = rg[2 * it.tile];
+    it.hi = rg[2 * it.tile + 1];
+    it.slot = -1;
+    if (nseg > 1) {
+        const int64_t L = wp.seg[it.st];
+        const int64_t s = r - wp.first[p];
+        const int64_t g = it.lo / L + s;
+        it.lo = max(it.lo, g * L);
+        it.hi = min(it.hi, (g + 1) * L);
+        it.slot = wp.slot[p] + s;
+    }
+    return true;
+}
+
 // ---- launches (stream-ordered, no synchronisation) ----
 hipError_t launch_line_prep_f64(const LinesDev& L, const PrepParams& pp, WingRec* wing,
                                 WingIdx* idx, CoreRec* core, hipStream_t s);
@@ -130,21 +231,22 @@ hipError_t launch_tile_ranges(const double* nu_sorted, int64_t n_lines, int64_t 
 // 8), the core kernel then adds the series terms.
 int32_t opacity_f64_tile_points(int points_per_lane);
 int32_t core_f64_tile_points();
-hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingIdx* idx,
-                           const int64_t* ranges,
-                           int64_t n_tiles, double nu_min, double dnu, int32_t n_points,
-                           double* kappa, int accumulate, hipStream_t s);
+// The wing items of n_states states (records n_lines apart, ranges 2 n_tiles
+// apart, kappa n_points apart); items cut by the plan write partial (binary64,
+// tile_points per slot), which the reduction then adds into kappa.  With
+// accumulate, kappa += the wing sum (single state).  items_bound: workgroups
+// needed (the plan's item count or its bound).
+hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingIdx* idx, const int64_t* ranges,
+                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp,
+                           int64_t items_bound, double nu_min, double dnu, int32_t n_points, double* kappa,
+                           double* partial, int accumulate, hipStream_t s);
 hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRec* core,
                            const int64_t* ranges,
                            int64_t n_tiles, double nu_min, double dnu, int32_t n_points,
                            double* kappa, hipStream_t s);
-// Batched forms: one persistent launch over n_states states whose records
+// Batched series: one persistent launch over n_states states whose records
 // lie n_lines apart, tile ranges 2 n_tiles apart, outputs n_points apart
-// (results identical to the single-state kernels, without accumulation).
-hipError_t launch_wing_f64_batched(int points_per_lane, const WingRec* wing, const WingIdx* idx,
-                                   const int64_t* ranges, int64_t n_lines, int64_t n_tiles, double nu_min,
-                                   double dnu, int32_t n_points, int32_t n_states, double* kappa,
-                                   hipStream_t s);
+// (results identical to the single-state kernel).
 hipError_t launch_core_f64_batched(const WingRec* wing, const WingIdx* idx, const CoreRec* core,
                                    const int64_t* ranges, int64_t n_lines, int64_t n_tiles, double nu_min,
                                    double dnu, int32_t n_points, int32_t n_states, double* kappa,
@@ -160,16 +262,15 @@ hipError_t launch_line_prep_f32(const WingRec* wing, WingIdx* idx, const CoreRec
                                 int64_t n_lines, double nu_min, double dnu, const int32_t* scale,
                                 WingRec32* w32, CoreRec32* c32, hipStream_t s);
 int32_t opacity_f32_tile_points(int points_per_lane);
-hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const WingIdx* idx,
-                           const int64_t* ranges, int64_t n_tiles, int32_t n_points, float* sum,
-                           float* comp, hipStream_t s);
+// As launch_wing_f64: the Kahan pairs (sum, comp) of n_states states; cut
+// items write (sum, comp) pairs to partial (tile_points float2 per slot).
+hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const WingIdx* idx, const int64_t* ranges,
+                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp,
+                           int64_t items_bound, int32_t n_points, float* sum, float* comp, float2* partial,
+                           hipStream_t s);
 hipError_t launch_core_f32(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges,
                            int64_t n_tiles, int32_t n_points, float* sum, float* comp,
                            hipStream_t s);
-hipError_t launch_wing_f32_batched(int points_per_lane, const WingRec32* wing, const WingIdx* idx,
-                                   const int64_t* ranges, int64_t n_lines, int64_t n_tiles,
-                                   int32_t n_points, int32_t n_states, float* sum, float* comp,
-                                   hipStream_t s);
 hipError_t launch_core_f32_batched(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges,
                                    int64_t n_lines, int64_t n_tiles, int32_t n_points,
                                    int32_t n_states, float* sum, float* comp, hipStream_t s);

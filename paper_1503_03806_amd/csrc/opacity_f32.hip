@@ -29,19 +29,6 @@ constexpr int kTL = 64 * kWaves;  // 256 lines per LDS block, one per thread
 constexpr int kMaxTerms = 2 * 10 + 14;
 enum : uint32_t { kSkip = 0, kGH1 = 1, kGH3 = 2, kGeneral = 3 };
 
-constexpr int kChunk = 32;
-__device__ inline int64_t tile_of(int64_t b, int64_t n_tiles)
-{
-    const int64_t x = b & 7, k = b >> 3;
-    const int64_t r = ((k / kChunk) * 8 + x) * kChunk + (k % kChunk);
-    return r < n_tiles ? n_tiles - 1 - r : -1;
-}
-int64_t padded_blocks(int64_t n_tiles)
-{
-    const int64_t g = 8 * kChunk;
-    return (n_tiles + g - 1) / g * g;
-}
-
 __device__ inline uint32_t classify(const WingIdx& r, int32_t run0, int32_t run1)
 {
     if (run0 > run1 || r.whi < run0 || r.wlo > run1) return kSkip;
@@ -64,11 +51,16 @@ __device__ inline void kahan_add(float& s, float& c, float x)
     s = t;
 }
 
-// One grid tile t of one state (pointers already offset to the state).
+// Lines [L0, L1) at the points of grid tile t of one state (record
+// pointers already offset to the state).  direct: the Kahan pair of each
+// point, normalised through binary64 (sum = its value rounded to binary32,
+// comp = the rest), to sum_out / comp_out; else the raw pair (sum, comp) to
+// partial[j - obase].
 template <int kP>
-__device__ __forceinline__ void wing_f32_tile(int64_t t, const WingRec32* __restrict__ wing,
-                              const WingIdx* __restrict__ idx, const int64_t* __restrict__ ranges,
-                              int32_t n, float* __restrict__ sum_out, float* __restrict__ comp_out)
+__device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1, const WingRec32* __restrict__ wing,
+                                              const WingIdx* __restrict__ idx, int32_t n, float* __restrict__ sum_out,
+                                              float* __restrict__ comp_out, float2* __restrict__ partial,
+                                              int64_t obase, bool direct)
 {
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ WingRec32 tile[kTL];
@@ -89,7 +81,6 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, const WingRec32* __rest
         part[p] = 0.0f;
     }
 
-    const int64_t L0 = ranges[2 * t], L1 = ranges[2 * t + 1];
     for (int64_t base = L0 & ~(int64_t)(kTL - 1); base < L1; base += kTL) {
         const int cnt = (int)min((int64_t)kTL, L1 - base);
         if ((int)threadIdx.x < cnt) {
@@ -182,37 +173,62 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, const WingRec32* __rest
     for (int p = 0; p < kP; ++p) {
         const int32_t j = run0 + lane + 64 * p;
         if (j < n) {
-            sum_out[j] = s[p];
-            comp_out[j] = -c[p];
+            if (direct) {
+                const double v = (double)s[p] - (double)c[p];
+                const float hi = (float)v;
+                sum_out[j] = hi;
+                comp_out[j] = (float)(v - (double)hi);
+            } else {
+                partial[j - obase] = make_float2(s[p], -c[p]);
+            }
         }
     }
 }
 
+// One workgroup per work item (a grid tile of a state, or its lines in one
+// segment); the layout of the binary64 kernel.
 template <int kP>
 __global__ __launch_bounds__(64 * kWaves) void wing_f32_kernel(
-    const WingRec32* __restrict__ wing, const WingIdx* __restrict__ idx,
-    const int64_t* __restrict__ ranges, int64_t n_tiles, int32_t n, float* __restrict__ sum_out,
-    float* __restrict__ comp_out)
+    const WingRec32* __restrict__ wing, const WingIdx* __restrict__ idx, const int64_t* __restrict__ ranges,
+    int64_t n_lines, int64_t n_tiles, int32_t n_states, WorkPlan wp, int32_t n, float* __restrict__ sum,
+    float* __restrict__ comp, float2* __restrict__ partial)
 {
-    const int64_t t = tile_of(blockIdx.x, n_tiles);
-    if (t < 0) return;
-    wing_f32_tile<kP>(t, wing, idx, ranges, n, sum_out, comp_out);
+    constexpr int64_t kTilePoints = 64 * kP * kWaves;
+    WorkItem it;
+    if (!work_item(xcd_rank(blockIdx.x), wp, ranges, n_tiles, n_states, it)) return;
+    const int64_t o = it.st * n_lines, so = it.st * (int64_t)n;
+    const bool direct = it.slot < 0;
+    wing_f32_tile<kP>(it.tile, it.lo, it.hi, wing + o, idx + o, n, sum + so, comp + so,
+                      partial + (direct ? 0 : it.slot * kTilePoints), it.tile * kTilePoints, direct);
 }
 
-// Persistent launch over the (state, tile) items of a batch of states, in
-// the order of the binary64 one.
-template <int kP>
-__global__ __launch_bounds__(64 * kWaves) void wing_f32_batched_kernel(
-    const WingRec32* __restrict__ wing, const WingIdx* __restrict__ idx,
-    const int64_t* __restrict__ ranges, int64_t n_lines, int64_t n_tiles, int32_t n,
-    int32_t n_states, float* __restrict__ sum, float* __restrict__ comp)
+// The cut tiles: each point's value is the binary64 sum of its partial
+// pairs in segment order, stored normalised as by a direct item.
+__global__ __launch_bounds__(256) void wing_f32_reduce_kernel(WorkPlan wp, int64_t n_tiles, int32_t n_states,
+                                                             int32_t tp, int32_t n, const float2* __restrict__ partial,
+                                                             float* __restrict__ sum, float* __restrict__ comp)
 {
-    const int64_t n_items = n_tiles * n_states;
-    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const int64_t st = item % n_states;
-        const int64_t t = n_tiles - 1 - item / n_states;
-        wing_f32_tile<kP>(t, wing + st * n_lines, idx + st * n_lines, ranges + st * 2 * n_tiles, n,
-                          sum + st * (int64_t)n, comp + st * (int64_t)n);
+    const int64_t total = wp.total[0];
+    if (total == wp.n_pairs) return;  // nothing cut
+    for (int64_t p = blockIdx.x; p < wp.n_pairs; p += gridDim.x) {
+        const int64_t nseg = (p + 1 < wp.n_pairs ? wp.first[p + 1] : total) - wp.first[p];
+        if (nseg < 2) continue;
+        int64_t st, k;
+        pair_decode(p, n_tiles, n_states, st, k);
+        const int64_t j0 = (n_tiles - 1 - k) * tp;
+        const float2* src = partial + wp.slot[p] * tp;
+        for (int q = threadIdx.x; q < tp; q += blockDim.x) {
+            const int64_t j = j0 + q;
+            if (j >= n) break;
+            double v = 0.0;
+            for (int64_t sg = 0; sg < nseg; ++sg) {
+                const float2 e = src[sg * tp + q];
+                v += (double)e.x + (double)e.y;
+            }
+            const float hi = (float)v;
+            sum[st * (int64_t)n + j] = hi;
+            comp[st * (int64_t)n + j] = (float)(v - (double)hi);
+        }
     }
 }
 
@@ -375,11 +391,17 @@ __global__ __launch_bounds__(64 * kWaves) void core_f32_batched_kernel(
 }
 
 template <int kP>
-hipError_t launch_wing(const WingRec32* wing, const WingIdx* idx, const int64_t* ranges,
-                       int64_t n_tiles, int32_t n, float* sum, float* comp, hipStream_t s)
+hipError_t launch_wing(const WingRec32* wing, const WingIdx* idx, const int64_t* ranges, int64_t n_lines,
+                       int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int64_t items_bound, int32_t n,
+                       float* sum, float* comp, float2* partial, hipStream_t s)
 {
-    wing_f32_kernel<kP><<<dim3((unsigned)padded_blocks(n_tiles)), dim3(64 * kWaves), 0, s>>>(
-        wing, idx, ranges, n_tiles, n, sum, comp);
+    const int64_t nb = plan_blocks(items_bound);
+    if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+    wing_f32_kernel<kP><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(wing, idx, ranges, n_lines, n_tiles,
+                                                                        n_states, wp, n, sum, comp, partial);
+    const int64_t nr = std::min<int64_t>(wp.n_pairs, 8192);
+    wing_f32_reduce_kernel<<<dim3((unsigned)nr), dim3(256), 0, s>>>(wp, n_tiles, n_states, 64 * kP * kWaves, n,
+                                                                    partial, sum, comp);
     return hipGetLastError();
 }
 
@@ -396,30 +418,23 @@ int persistent_blocks(K kernel, int64_t n_items)
     return (int)std::max<int64_t>(1, std::min(n_items, b));
 }
 
-template <int kP>
-hipError_t launch_wing_batched(const WingRec32* wing, const WingIdx* idx, const int64_t* ranges,
-                               int64_t n_lines, int64_t n_tiles, int32_t n, int32_t n_states,
-                               float* sum, float* comp, hipStream_t s)
-{
-    const int nb = persistent_blocks(wing_f32_batched_kernel<kP>, n_tiles * n_states);
-    wing_f32_batched_kernel<kP><<<dim3(nb), dim3(64 * kWaves), 0, s>>>(wing, idx, ranges, n_lines, n_tiles,
-                                                                      n, n_states, sum, comp);
-    return hipGetLastError();
-}
-
 }  // namespace
 
 int32_t opacity_f32_tile_points(int points_per_lane) { return 64 * points_per_lane * kWaves; }
 
-hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const WingIdx* idx,
-                           const int64_t* ranges, int64_t n_tiles, int32_t n_points, float* sum,
-                           float* comp, hipStream_t s)
+hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const WingIdx* idx, const int64_t* ranges,
+                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp,
+                           int64_t items_bound, int32_t n_points, float* sum, float* comp, float2* partial,
+                           hipStream_t s)
 {
-    if (n_tiles == 0) return hipSuccess;
+    if (n_tiles == 0 || n_states == 0) return hipSuccess;
     switch (points_per_lane) {
-    case 2: return launch_wing<2>(wing, idx, ranges, n_tiles, n_points, sum, comp, s);
-    case 4: return launch_wing<4>(wing, idx, ranges, n_tiles, n_points, sum, comp, s);
-    case 8: return launch_wing<8>(wing, idx, ranges, n_tiles, n_points, sum, comp, s);
+    case 2: return launch_wing<2>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, items_bound, n_points, sum,
+                                  comp, partial, s);
+    case 4: return launch_wing<4>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, items_bound, n_points, sum,
+                                  comp, partial, s);
+    case 8: return launch_wing<8>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, items_bound, n_points, sum,
+                                  comp, partial, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -438,20 +453,6 @@ hipError_t launch_core_f32(const WingIdx* idx, const CoreRec32* core, const int6
 }  // namespace hk
 
 namespace hk {
-
-hipError_t launch_wing_f32_batched(int points_per_lane, const WingRec32* wing, const WingIdx* idx,
-                                   const int64_t* ranges, int64_t n_lines, int64_t n_tiles,
-                                   int32_t n_points, int32_t n_states, float* sum, float* comp,
-                                   hipStream_t s)
-{
-    if (n_tiles == 0 || n_states == 0) return hipSuccess;
-    switch (points_per_lane) {
-    case 2: return launch_wing_batched<2>(wing, idx, ranges, n_lines, n_tiles, n_points, n_states, sum, comp, s);
-    case 4: return launch_wing_batched<4>(wing, idx, ranges, n_lines, n_tiles, n_points, n_states, sum, comp, s);
-    case 8: return launch_wing_batched<8>(wing, idx, ranges, n_lines, n_tiles, n_points, n_states, sum, comp, s);
-    default: return hipErrorInvalidValue;
-    }
-}
 
 hipError_t launch_core_f32_batched(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges,
                                    int64_t n_lines, int64_t n_tiles, int32_t n_points,

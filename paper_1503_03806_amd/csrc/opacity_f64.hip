@@ -10,7 +10,9 @@
 //
 // Two kernels per call:
 //  wing: the 3-node and 1-node Gauss-Hermite rules (a^2+u^2 >= 100) for
-//        every line and point; it writes kappa.
+//        every line and point; it writes kappa (over the work items of
+//        work_plan.hip: a tile, or the part of its lines in one segment,
+//        whose partial sums a reduction adds in segment order).
 //  core: the series for a^2+u^2 < 100, a few hundred times rarer but ~30
 //        times dearer per point and heavy in registers; it adds its own
 //        ordered sum to kappa.
@@ -48,25 +50,11 @@ __device__ inline double qrcp(double den)
     return fma(r, fma(-den, r, 1.0), r);
 }
 
-// Workgroups go round-robin over the 8 XCDs, each with its own L2.  The
-// rank order r = 0, 1, ... visits tiles dearest first (high wavenumber: wider
-// Doppler cores, more 3-node points), so cheap tiles fill the launch's tail;
-// ranks are dealt to XCDs in chunks of kChunk consecutive tiles, so an XCD's
-// neighbouring tiles, which read mostly the same lines, share its L2, while
-// every XCD gets a mix of dear and cheap chunks.  The grid is padded to a
-// multiple of 8 * kChunk blocks; blocks past the last tile exit at once.
-constexpr int kChunk = 32;
-__device__ inline int64_t tile_of(int64_t b, int64_t n_tiles)
-{
-    const int64_t x = b & 7, k = b >> 3;
-    const int64_t r = ((k / kChunk) * 8 + x) * kChunk + (k % kChunk);
-    return r < n_tiles ? n_tiles - 1 - r : -1;
-}
-int64_t padded_blocks(int64_t n_tiles)
-{
-    const int64_t g = 8 * kChunk;
-    return (n_tiles + g - 1) / g * g;
-}
+// Work items run dearest tile first (high wavenumber: wider Doppler cores,
+// more 3-node points), so cheap tiles fill the launch's tail, and are dealt
+// to the 8 XCDs (each with its own L2) in chunks of consecutive tiles
+// (xcd_rank), so an XCD's neighbouring tiles, which read mostly the same
+// lines, share its L2 while every XCD gets a mix of dear and cheap chunks.
 
 // The path of one line for the points [run0, run1] of a wavefront; run_end
 // is the run's nominal last point.  A run cut short by the grid end takes
@@ -102,11 +90,13 @@ __device__ inline void gh3_nm(double dv, double G2, double B, double C, double B
 //   both 3-node:  c = rcp(ma mb) Lg;           acc += (c mb) na
 //   mixed:        c = rcp(den_a den_b) Lg;     acc += (c den_b) num_a
 // (num = 1 for a 1-node point).
-// One grid tile t of one state (pointers already offset to the state).
+// Lines [L0, L1) at the points of grid tile t of one state (record
+// pointers already offset to the state): out[j - obase] = the ordered sum,
+// or += it with accumulate.
 template <int kP>
-__device__ __forceinline__ void wing_f64_tile(int64_t t, const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
-                              const int64_t* __restrict__ ranges, double nu_min, double dnu, int32_t n,
-                              double* __restrict__ kappa, int accumulate)
+__device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1, const WingRec* __restrict__ wing,
+                                              const WingIdx* __restrict__ idx, double nu_min, double dnu, int32_t n,
+                                              double* __restrict__ out, int64_t obase, int accumulate)
 {
     static_assert(kP % 2 == 0, "points are processed in pairs");
     constexpr int kTilePoints = 64 * kP * kWaves;
@@ -122,10 +112,9 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, const WingRec* __restri
     for (int p = 0; p < kP; ++p) {
         const int32_t j = run0 + lane + 64 * p;
         nuj[p] = fma((double)j, dnu, nu_min);
-        acc[p] = (accumulate && j < n) ? kappa[j] : 0.0;
+        acc[p] = 0.0;
     }
 
-    const int64_t L0 = ranges[2 * t], L1 = ranges[2 * t + 1];
     for (int64_t base = L0; base < L1; base += kTL) {
         const int cnt = (int)min((int64_t)kTL, L1 - base);
         // stage one record per thread and decide its path for each wavefront
@@ -247,38 +236,52 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, const WingRec* __restri
 #pragma unroll
     for (int p = 0; p < kP; ++p) {
         const int32_t j = run0 + lane + 64 * p;
-        if (j < n) kappa[j] = acc[p];
+        if (j < n) out[j - obase] = accumulate ? out[j - obase] + acc[p] : acc[p];
     }
 }
 
+// One workgroup per work item (a grid tile of a state, or its lines in one
+// segment).  Per-state arrays lie n_lines records, 2 n_tiles ranges and n
+// points apart; a cut item writes its slot of partial (kTilePoints values).
 template <int kP>
 __global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
-    const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
-    const int64_t* __restrict__ ranges, int64_t n_tiles, double nu_min, double dnu, int32_t n,
-    double* __restrict__ kappa, int accumulate)
+    const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx, const int64_t* __restrict__ ranges,
+    int64_t n_lines, int64_t n_tiles, int32_t n_states, WorkPlan wp, double nu_min, double dnu, int32_t n,
+    double* __restrict__ kappa, double* __restrict__ partial, int accumulate)
 {
-    const int64_t t = tile_of(blockIdx.x, n_tiles);
-    if (t < 0) return;
-    wing_f64_tile<kP>(t, wing, idx, ranges, nu_min, dnu, n, kappa, accumulate);
+    constexpr int64_t kTilePoints = 64 * kP * kWaves;
+    WorkItem it;
+    if (!work_item(xcd_rank(blockIdx.x), wp, ranges, n_tiles, n_states, it)) return;
+    const int64_t o = it.st * n_lines;
+    const bool direct = it.slot < 0;
+    double* out = direct ? kappa + it.st * (int64_t)n : partial + it.slot * kTilePoints;
+    wing_f64_tile<kP>(it.tile, it.lo, it.hi, wing + o, idx + o, nu_min, dnu, n, out,
+                      direct ? 0 : it.tile * kTilePoints, direct ? accumulate : 0);
 }
 
-// Persistent launch over the (state, tile) items of a batch of states: item
-// r is the (r / n_states)-th dearest tile of state r % n_states, so the
-// states progress together and the cheap tiles of all of them come last;
-// workgroups stride over the items.  Per-state arrays lie n_lines records,
-// 2 n_tiles ranges and n points apart.
-template <int kP>
-__global__ __launch_bounds__(64 * kWaves) void wing_f64_batched_kernel(
-    const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
-    const int64_t* __restrict__ ranges, int64_t n_lines, int64_t n_tiles, double nu_min, double dnu,
-    int32_t n, int32_t n_states, double* __restrict__ kappa)
+// The cut tiles: kappa_j (+)= the ordered sum of the tile's partials,
+// segment by segment.  Workgroups stride over the (state, tile) pairs.
+__global__ __launch_bounds__(256) void wing_f64_reduce_kernel(WorkPlan wp, int64_t n_tiles, int32_t n_states,
+                                                             int32_t tp, int32_t n, const double* __restrict__ partial,
+                                                             double* __restrict__ kappa, int accumulate)
 {
-    const int64_t n_items = n_tiles * n_states;
-    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const int64_t st = item % n_states;
-        const int64_t t = n_tiles - 1 - item / n_states;
-        wing_f64_tile<kP>(t, wing + st * n_lines, idx + st * n_lines, ranges + st * 2 * n_tiles, nu_min,
-                          dnu, n, kappa + st * (int64_t)n, 0);
+    const int64_t total = wp.total[0];
+    if (total == wp.n_pairs) return;  // nothing cut
+    for (int64_t p = blockIdx.x; p < wp.n_pairs; p += gridDim.x) {
+        const int64_t nseg = (p + 1 < wp.n_pairs ? wp.first[p + 1] : total) - wp.first[p];
+        if (nseg < 2) continue;
+        int64_t st, k;
+        pair_decode(p, n_tiles, n_states, st, k);
+        const int64_t j0 = (n_tiles - 1 - k) * tp;
+        const double* src = partial + wp.slot[p] * tp;
+        double* dst = kappa + st * (int64_t)n;
+        for (int q = threadIdx.x; q < tp; q += blockDim.x) {
+            const int64_t j = j0 + q;
+            if (j >= n) break;
+            double v = 0.0;
+            for (int64_t sg = 0; sg < nseg; ++sg) v += src[sg * tp + q];
+            dst[j] = accumulate ? dst[j] + v : v;
+        }
     }
 }
 
@@ -444,12 +447,17 @@ __global__ __launch_bounds__(64 * kWaves) void core_f64_batched_kernel(
 }
 
 template <int kP>
-hipError_t launch_wing(const WingRec* wing, const WingIdx* idx, const int64_t* ranges,
-                       int64_t n_tiles, double nu_min, double dnu, int32_t n, double* kappa,
-                       int accumulate, hipStream_t s)
+hipError_t launch_wing(const WingRec* wing, const WingIdx* idx, const int64_t* ranges, int64_t n_lines,
+                       int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int64_t items_bound, double nu_min,
+                       double dnu, int32_t n, double* kappa, double* partial, int accumulate, hipStream_t s)
 {
-    wing_f64_kernel<kP><<<dim3((unsigned)padded_blocks(n_tiles)), dim3(64 * kWaves), 0, s>>>(
-        wing, idx, ranges, n_tiles, nu_min, dnu, n, kappa, accumulate);
+    const int64_t nb = plan_blocks(items_bound);
+    if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+    wing_f64_kernel<kP><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(
+        wing, idx, ranges, n_lines, n_tiles, n_states, wp, nu_min, dnu, n, kappa, partial, accumulate);
+    const int64_t nr = std::min<int64_t>(wp.n_pairs, 8192);
+    wing_f64_reduce_kernel<<<dim3((unsigned)nr), dim3(256), 0, s>>>(wp, n_tiles, n_states, 64 * kP * kWaves, n,
+                                                                    partial, kappa, accumulate);
     return hipGetLastError();
 }
 
@@ -466,31 +474,24 @@ int persistent_blocks(K kernel, int64_t n_items)
     return (int)std::max<int64_t>(1, std::min(n_items, b));
 }
 
-template <int kP>
-hipError_t launch_wing_batched(const WingRec* wing, const WingIdx* idx, const int64_t* ranges,
-                               int64_t n_lines, int64_t n_tiles, double nu_min, double dnu, int32_t n,
-                               int32_t n_states, double* kappa, hipStream_t s)
-{
-    const int nb = persistent_blocks(wing_f64_batched_kernel<kP>, n_tiles * n_states);
-    wing_f64_batched_kernel<kP><<<dim3(nb), dim3(64 * kWaves), 0, s>>>(wing, idx, ranges, n_lines, n_tiles,
-                                                                      nu_min, dnu, n, n_states, kappa);
-    return hipGetLastError();
-}
-
 }  // namespace
 
 int32_t opacity_f64_tile_points(int points_per_lane) { return 64 * points_per_lane * kWaves; }
 int32_t core_f64_tile_points() { return 64 * 4 * kWaves; }
 
-hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingIdx* idx,
-                           const int64_t* ranges, int64_t n_tiles, double nu_min, double dnu,
-                           int32_t n_points, double* kappa, int accumulate, hipStream_t s)
+hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingIdx* idx, const int64_t* ranges,
+                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp,
+                           int64_t items_bound, double nu_min, double dnu, int32_t n_points, double* kappa,
+                           double* partial, int accumulate, hipStream_t s)
 {
-    if (n_tiles == 0) return hipSuccess;
+    if (n_tiles == 0 || n_states == 0) return hipSuccess;
     switch (points_per_lane) {
-    case 2: return launch_wing<2>(wing, idx, ranges, n_tiles, nu_min, dnu, n_points, kappa, accumulate, s);
-    case 4: return launch_wing<4>(wing, idx, ranges, n_tiles, nu_min, dnu, n_points, kappa, accumulate, s);
-    case 8: return launch_wing<8>(wing, idx, ranges, n_tiles, nu_min, dnu, n_points, kappa, accumulate, s);
+    case 2: return launch_wing<2>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, items_bound, nu_min, dnu,
+                                  n_points, kappa, partial, accumulate, s);
+    case 4: return launch_wing<4>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, items_bound, nu_min, dnu,
+                                  n_points, kappa, partial, accumulate, s);
+    case 8: return launch_wing<8>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, items_bound, nu_min, dnu,
+                                  n_points, kappa, partial, accumulate, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -503,20 +504,6 @@ hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRe
     core_f64_kernel<4><<<dim3((unsigned)n_tiles), dim3(64 * kWaves), 0, s>>>(
         wing, idx, core, ranges, n_tiles, nu_min, dnu, n_points, kappa);
     return hipGetLastError();
-}
-
-hipError_t launch_wing_f64_batched(int points_per_lane, const WingRec* wing, const WingIdx* idx,
-                                   const int64_t* ranges, int64_t n_lines, int64_t n_tiles, double nu_min,
-                                   double dnu, int32_t n_points, int32_t n_states, double* kappa,
-                                   hipStream_t s)
-{
-    if (n_tiles == 0 || n_states == 0) return hipSuccess;
-    switch (points_per_lane) {
-    case 2: return launch_wing_batched<2>(wing, idx, ranges, n_lines, n_tiles, nu_min, dnu, n_points, n_states, kappa, s);
-    case 4: return launch_wing_batched<4>(wing, idx, ranges, n_lines, n_tiles, nu_min, dnu, n_points, n_states, kappa, s);
-    case 8: return launch_wing_batched<8>(wing, idx, ranges, n_lines, n_tiles, nu_min, dnu, n_points, n_states, kappa, s);
-    default: return hipErrorInvalidValue;
-    }
 }
 
 hipError_t launch_core_f64_batched(const WingRec* wing, const WingIdx* idx, const CoreRec* core,
