@@ -53,6 +53,15 @@ struct ListInfo {
     double nu_max = 0.0;  // largest line centre (bounds the Doppler core widths)
 };
 
+// Device buffers of one work plan (work_plan.hip) and its partial sums.
+struct PlanBufs {
+    DevBuf ref, seg, first, slot, bsum, total, partial;
+    void release()
+    {
+        for (DevBuf* b : {&ref, &seg, &first, &slot, &bsum, &total, &partial}) b->release();
+    }
+};
+
 struct hk_ctx {
     int device = 0;
     hipStream_t own = nullptr;     // created with the context
@@ -81,9 +90,8 @@ struct hk_ctx {
     DevBuf wing, widx, core, ranges, ranges_core;
     DevBuf partial;
     DevBuf kscratch;
-    // work plan of the wing kernels: reference tile ranges, segment lengths,
-    // per-pair first item and partial slot, block sums, totals, partial sums
-    DevBuf wp_ref, wp_seg, wp_first, wp_slot, wp_bsum, wp_total, wp_partial;
+    // work plans of the wing and the series kernels
+    PlanBufs wplan, cplan;
     // binary32 path: records, Kahan pair, scale
     DevBuf w32, c32, f32sum, f32comp, f32scale, f32partial;
     bool have_run = false;
@@ -474,66 +482,107 @@ namespace {
 
 constexpr int32_t kCountBlocks = 256;  // partial sums per evaluation count
 
-// The wing stage of n_states states whose records lie n_lines apart: the
-// states' reference tile ranges, segment lengths and work plan, then the
-// wing items and the reduction of cut tiles (work_plan.hip).  ranges: tile
-// ranges for tiles of `ppl` points per lane, 2 n_tiles per state; reach[s]:
-// state s's wing reach; out: kappa (binary64) or the Kahan sums (binary32,
-// with comp), n_points per state.  exact: read the plan's totals back (one
-// host synchronisation) to size the launch and the partial sums; else their
-// bounds.
-int wing_stage(hk_ctx* ctx, int precision, int ppl, const void* recs, const WingIdx* idx, const int64_t* ranges,
-               int64_t n_tiles, int32_t n_states, const double* reach, const hk_grid* grid, void* out, float* comp,
-               int accumulate, bool exact)
+// The work plan of n_states states (work_plan.hip): reference tile ranges
+// for reach[s], segment lengths, then the items of the tiles whose ranges
+// (2 n_tiles per state) are given, into pb.  exact: read the totals back (one
+// host synchronisation) for *items and the partial sums; else their bounds.
+int make_plan(hk_ctx* ctx, PlanBufs& pb, const int64_t* ranges, int64_t n_tiles, int32_t n_states,
+              const double* reach, int32_t tp, const hk_grid* grid, bool exact, WorkPlan* wp, int64_t* items)
 {
     const int64_t n = ctx->n_lines;
     const int32_t np = (int32_t)grid->n_points;
-    const bool f64 = precision == HK_F64;
-    const int32_t tp = f64 ? opacity_f64_tile_points(ppl) : opacity_f32_tile_points(ppl);
     const int64_t n_ref = ((int64_t)np + kRefTilePoints - 1) / kRefTilePoints;
     const int64_t P = n_tiles * n_states;
-    HK_HIP(ctx, ctx->wp_ref.ensure((size_t)std::max<int64_t>(n_ref * n_states, 1) * 2 * sizeof(int64_t)),
+    HK_HIP(ctx, pb.ref.ensure((size_t)std::max<int64_t>(n_ref * n_states, 1) * 2 * sizeof(int64_t)),
            "allocating the work plan");
-    HK_HIP(ctx, ctx->wp_seg.ensure((size_t)std::max(n_states, 1) * sizeof(int64_t)), "allocating the work plan");
-    HK_HIP(ctx, ctx->wp_first.ensure((size_t)std::max<int64_t>(P, 1) * sizeof(int64_t)), "allocating the work plan");
-    HK_HIP(ctx, ctx->wp_slot.ensure((size_t)std::max<int64_t>(P, 1) * sizeof(int64_t)), "allocating the work plan");
-    HK_HIP(ctx, ctx->wp_bsum.ensure((size_t)plan_scratch_count(P) * sizeof(int64_t)), "allocating the work plan");
-    HK_HIP(ctx, ctx->wp_total.ensure(2 * sizeof(int64_t)), "allocating the work plan");
-    int64_t* ref = static_cast<int64_t*>(ctx->wp_ref.p);
-    int64_t* seg = static_cast<int64_t*>(ctx->wp_seg.p);
-    int64_t* first = static_cast<int64_t*>(ctx->wp_first.p);
-    int64_t* slot = static_cast<int64_t*>(ctx->wp_slot.p);
-    int64_t* total = static_cast<int64_t*>(ctx->wp_total.p);
+    HK_HIP(ctx, pb.seg.ensure((size_t)std::max(n_states, 1) * sizeof(int64_t)), "allocating the work plan");
+    HK_HIP(ctx, pb.first.ensure((size_t)std::max<int64_t>(P, 1) * sizeof(int64_t)), "allocating the work plan");
+    HK_HIP(ctx, pb.slot.ensure((size_t)std::max<int64_t>(P, 1) * sizeof(int64_t)), "allocating the work plan");
+    HK_HIP(ctx, pb.bsum.ensure((size_t)plan_scratch_count(P) * sizeof(int64_t)), "allocating the work plan");
+    HK_HIP(ctx, pb.total.ensure(2 * sizeof(int64_t)), "allocating the work plan");
+    int64_t* ref = static_cast<int64_t*>(pb.ref.p);
+    int64_t* seg = static_cast<int64_t*>(pb.seg.p);
+    int64_t* first = static_cast<int64_t*>(pb.first.p);
+    int64_t* slot = static_cast<int64_t*>(pb.slot.p);
+    int64_t* total = static_cast<int64_t*>(pb.total.p);
     const double* nu = lines_field(ctx, 0);
     for (int32_t s = 0; s < n_states; ++s)
         HK_HIP(ctx, launch_tile_ranges(nu, n, n_ref, kRefTilePoints, grid->nu_min, grid->dnu, np, reach[s],
                                        ref + (int64_t)s * 2 * n_ref, ctx->stream),
                "tile_ranges");
     HK_HIP(ctx, launch_seg_length(ref, n_ref, n_states, np, n, seg, ctx->stream), "seg_length");
-    HK_HIP(ctx, launch_work_plan(ranges, n_tiles, n_states, seg, first, slot, static_cast<int64_t*>(ctx->wp_bsum.p),
-                                 total, ctx->stream),
+    HK_HIP(ctx, launch_work_plan(ranges, n_tiles, n_states, seg, first, slot, static_cast<int64_t*>(pb.bsum.p), total,
+                                 ctx->stream),
            "work_plan");
-    int64_t items = n_states * plan_items_bound(n_tiles);
+    int64_t it = n_states * plan_items_bound(n_tiles);
     int64_t points = n_states * plan_partial_points_bound(np, tp);
     if (exact) {
         int64_t h[2] = {0, 0};
         HK_HIP(ctx, hipMemcpyAsync(h, total, sizeof h, hipMemcpyDeviceToHost, ctx->stream), "reading the work plan");
         HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-        items = h[0];
+        it = h[0];
         points = h[1] * tp;
     }
-    HK_HIP(ctx, ctx->wp_partial.ensure((size_t)std::max<int64_t>(points, 1) * 8), "allocating partial sums");
-    const WorkPlan wp{seg, first, slot, total, P};
+    HK_HIP(ctx, pb.partial.ensure((size_t)std::max<int64_t>(points, 1) * 8), "allocating partial sums");
+    *wp = WorkPlan{seg, first, slot, total, P};
+    *items = it;
+    return HK_OK;
+}
+
+// The wing stage of n_states states whose records lie n_lines apart: the
+// plan, then the wing items and the reduction of cut tiles.  ranges: tile
+// ranges for tiles of `ppl` points per lane; reach[s]: state s's wing reach;
+// out: kappa (binary64) or the Kahan sums (binary32, with comp), n_points
+// per state.
+int wing_stage(hk_ctx* ctx, int precision, int ppl, const void* recs, const WingIdx* idx, const int64_t* ranges,
+               int64_t n_tiles, int32_t n_states, const double* reach, const hk_grid* grid, void* out, float* comp,
+               int accumulate, bool exact)
+{
+    const bool f64 = precision == HK_F64;
+    const int32_t tp = f64 ? opacity_f64_tile_points(ppl) : opacity_f32_tile_points(ppl);
+    WorkPlan wp;
+    int64_t items = 0;
+    if (int rc = make_plan(ctx, ctx->wplan, ranges, n_tiles, n_states, reach, tp, grid, exact, &wp, &items))
+        return rc;
+    const int64_t n = ctx->n_lines;
+    const int32_t np = (int32_t)grid->n_points;
     if (f64)
         HK_HIP(ctx, launch_wing_f64(ppl, static_cast<const WingRec*>(recs), idx, ranges, n, n_tiles, n_states, wp, items,
                                     grid->nu_min, grid->dnu, np, static_cast<double*>(out),
-                                    static_cast<double*>(ctx->wp_partial.p), accumulate, ctx->stream),
+                                    static_cast<double*>(ctx->wplan.partial.p), accumulate, ctx->stream),
                "wing_f64");
     else
         HK_HIP(ctx, launch_wing_f32(ppl, static_cast<const WingRec32*>(recs), idx, ranges, n, n_tiles, n_states, wp,
-                                    items, np, static_cast<float*>(out), comp, static_cast<float2*>(ctx->wp_partial.p),
-                                    ctx->stream),
+                                    items, np, static_cast<float*>(out), comp,
+                                    static_cast<float2*>(ctx->wplan.partial.p), ctx->stream),
                "wing_f32");
+    return HK_OK;
+}
+
+// The series stage, the same way over the series tiles (ranges for the
+// series reach[s]); binary32 with surrogate/mask: the learned surrogate.
+int core_stage(hk_ctx* ctx, int precision, const void* wing, const WingIdx* idx, const void* core,
+               const int64_t* ranges, int64_t n_tiles, int32_t n_states, const double* reach, const hk_grid* grid,
+               void* out, float* comp, const void* surrogate, const uint8_t* mask, bool exact)
+{
+    const bool f64 = precision == HK_F64;
+    const int32_t tp = f64 ? core_f64_tile_points() : opacity_f32_tile_points(4);
+    WorkPlan wp;
+    int64_t items = 0;
+    if (int rc = make_plan(ctx, ctx->cplan, ranges, n_tiles, n_states, reach, tp, grid, exact, &wp, &items))
+        return rc;
+    const int64_t n = ctx->n_lines;
+    const int32_t np = (int32_t)grid->n_points;
+    if (f64)
+        HK_HIP(ctx, launch_core_f64(static_cast<const WingRec*>(wing), idx, static_cast<const CoreRec*>(core), ranges, n,
+                                    n_tiles, n_states, wp, items, grid->nu_min, grid->dnu, np, static_cast<double*>(out),
+                                    static_cast<double*>(ctx->cplan.partial.p), ctx->stream),
+               "core_f64");
+    else
+        HK_HIP(ctx, launch_core_f32(idx, static_cast<const CoreRec32*>(core), ranges, n, n_tiles, n_states, wp, items,
+                                    np, static_cast<float*>(out), comp, static_cast<float*>(ctx->cplan.partial.p),
+                                    surrogate, mask, ctx->stream),
+               "core_f32");
     return HK_OK;
 }
 
@@ -738,9 +787,8 @@ int hk_destroy(hk_ctx* ctx)
     ctx->ranges_core.release();
     ctx->partial.release();
     ctx->kscratch.release();
-    for (DevBuf* b : {&ctx->wp_ref, &ctx->wp_seg, &ctx->wp_first, &ctx->wp_slot, &ctx->wp_bsum, &ctx->wp_total,
-                      &ctx->wp_partial})
-        b->release();
+    ctx->wplan.release();
+    ctx->cplan.release();
     for (DevBuf* b : {&ctx->w32, &ctx->c32, &ctx->f32sum, &ctx->f32comp, &ctx->f32scale, &ctx->f32partial})
         b->release();
     for (DevBuf* b : {&ctx->tb_idx, &ctx->tb_wing, &ctx->tb_core, &ctx->tb_w32, &ctx->tb_c32, &ctx->tb_ranges,
@@ -805,7 +853,8 @@ int hk_load_lines(hk_ctx* ctx, const hk_lines* L, const hk_species* sp)
 // Binary32 profiles with compensated binary32 sums, after the binary64 line
 // preparation: scale, binary32 records, tile ranges, wing and core kernels,
 // then kappa = (sum + comp) 2^-s in binary64.
-static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, double reach, WingRec* wing, WingIdx* widx, CoreRec* core,
+static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, double reach, double reach_core, WingRec* wing,
+                       WingIdx* widx, CoreRec* core,
                        const int64_t* ranges_c, int64_t n_tiles_c, double* kappa, int accumulate, bool surrogate)
 {
     const int64_t n = ctx->n_lines;
@@ -854,12 +903,10 @@ static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, double reach, WingRec* 
     }
     {
         StageTimer tm(ctx, HK_STAGE_CORE);
-        if (surrogate)
-            HK_HIP(ctx, launch_core_f32_surrogate(widx, c32, ranges_c, n_tiles_c, np, fs, fc, ctx->sg_copy.p,
-                                                  static_cast<const uint8_t*>(ctx->sg_mask.p), ctx->stream),
-                   "core_f32_surrogate");
-        else
-            HK_HIP(ctx, launch_core_f32(widx, c32, ranges_c, n_tiles_c, np, fs, fc, ctx->stream), "core_f32");
+        if (int rc = core_stage(ctx, HK_F32_KAHAN, nullptr, widx, c32, ranges_c, n_tiles_c, 1, &reach_core, grid, fs,
+                                fc, surrogate ? ctx->sg_copy.p : nullptr,
+                                surrogate ? static_cast<const uint8_t*>(ctx->sg_mask.p) : nullptr, false))
+            return rc;
         HK_HIP(ctx, launch_f32_finish(fs, fc, scale, np, kappa, accumulate, ctx->stream), "f32_finish");
         tm.stop();
     }
@@ -926,7 +973,7 @@ static int opacity_run(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int
         tm.stop();
     }
     if (precision != HK_F64)
-        return opacity_f32(ctx, grid, reach, wing, widx, core, ranges_c, n_tiles_c, kappa, accumulate,
+        return opacity_f32(ctx, grid, reach, reach_core, wing, widx, core, ranges_c, n_tiles_c, kappa, accumulate,
                            precision == HK_F32_SURROGATE);
     {
         StageTimer tm(ctx, HK_STAGE_OPACITY);
@@ -937,9 +984,9 @@ static int opacity_run(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int
     }
     {
         StageTimer tm(ctx, HK_STAGE_CORE);
-        HK_HIP(ctx, launch_core_f64(wing, widx, core, ranges_c, n_tiles_c, grid->nu_min, grid->dnu, np, kappa,
-                                    ctx->stream),
-               "core_f64");
+        if (int rc = core_stage(ctx, HK_F64, wing, widx, core, ranges_c, n_tiles_c, 1, &reach_core, grid, kappa, nullptr,
+                                nullptr, nullptr, false))
+            return rc;
         tm.stop();
     }
     ctx->have_run = true;
@@ -1198,6 +1245,7 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
 
     for (int64_t b0 = 0; b0 < n_states; b0 += B) {
         const int32_t nbat = (int32_t)std::min<int64_t>(B, n_states - b0);
+        std::vector<double> reach_c((size_t)nbat);
         {
             StageTimer tm(ctx, HK_STAGE_LINE_PREP);
             for (int32_t s = 0; s < nbat; ++s) {
@@ -1229,9 +1277,9 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
                 }
                 HK_HIP(ctx, launch_eval_counts(ix, n, counts + (b0 + s) * kCountBlocks * 3, kCountBlocks, ctx->stream),
                        "eval_counts");
-                HK_HIP(ctx, launch_tile_ranges(L.nu, n, n_tiles_c, tpc, grid->nu_min, grid->dnu, np,
-                                               core_reach(ctx, st, grid, pp), rc_all + (int64_t)s * 2 * n_tiles_c,
-                                               ctx->stream),
+                reach_c[(size_t)s] = core_reach(ctx, st, grid, pp);
+                HK_HIP(ctx, launch_tile_ranges(L.nu, n, n_tiles_c, tpc, grid->nu_min, grid->dnu, np, reach_c[(size_t)s],
+                                               rc_all + (int64_t)s * 2 * n_tiles_c, ctx->stream),
                        "tile_ranges");
             }
             tm.stop();
@@ -1261,17 +1309,10 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
         }
         {
             StageTimer tm(ctx, HK_STAGE_CORE);
-            if (f64)
-                HK_HIP(ctx, launch_core_f64_batched(static_cast<WingRec*>(ctx->tb_wing.p), tidx,
-                                                    static_cast<CoreRec*>(ctx->tb_core.p), rc_all, n, n_tiles_c,
-                                                    grid->nu_min, grid->dnu, np, nbat,
-                                                    static_cast<double*>(ctx->tb_out.p), ctx->stream),
-                       "core_f64_batched");
-            else
-                HK_HIP(ctx, launch_core_f32_batched(tidx, static_cast<CoreRec32*>(ctx->tb_c32.p), rc_all, n, n_tiles_c,
-                                                    np, nbat, static_cast<float*>(ctx->tb_out.p),
-                                                    static_cast<float*>(ctx->tb_comp.p), ctx->stream),
-                       "core_f32_batched");
+            if (int rc = core_stage(ctx, precision, ctx->tb_wing.p, tidx, f64 ? ctx->tb_core.p : ctx->tb_c32.p, rc_all,
+                                    n_tiles_c, nbat, reach_c.data(), grid, ctx->tb_out.p,
+                                    static_cast<float*>(ctx->tb_comp.p), nullptr, nullptr, true))
+                return rc;
             tm.stop();
         }
         {
@@ -1642,10 +1683,10 @@ int hk_get_option(hk_ctx* ctx, const char* name, int64_t* value)
     else if (std::strcmp(name, "wing_items") == 0 || std::strcmp(name, "wing_segment_lines") == 0) {
         // the last wing stage's plan (for its first state), read back
         *value = 0;
-        if (!ctx->wp_total.p) return HK_OK;
+        if (!ctx->wplan.total.p) return HK_OK;
         HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
         const bool items = name[5] == 'i';
-        HK_HIP(ctx, hipMemcpyAsync(value, items ? ctx->wp_total.p : ctx->wp_seg.p, sizeof *value,
+        HK_HIP(ctx, hipMemcpyAsync(value, items ? ctx->wplan.total.p : ctx->wplan.seg.p, sizeof *value,
                                    hipMemcpyDeviceToHost, ctx->stream),
                "reading the work plan");
         HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");

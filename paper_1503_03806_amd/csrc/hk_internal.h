@@ -240,17 +240,12 @@ hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingI
                            int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp,
                            int64_t items_bound, double nu_min, double dnu, int32_t n_points, double* kappa,
                            double* partial, int accumulate, hipStream_t s);
-hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRec* core,
-                           const int64_t* ranges,
-                           int64_t n_tiles, double nu_min, double dnu, int32_t n_points,
-                           double* kappa, hipStream_t s);
-// Batched series: one persistent launch over n_states states whose records
-// lie n_lines apart, tile ranges 2 n_tiles apart, outputs n_points apart
-// (results identical to the single-state kernel).
-hipError_t launch_core_f64_batched(const WingRec* wing, const WingIdx* idx, const CoreRec* core,
-                                   const int64_t* ranges, int64_t n_lines, int64_t n_tiles, double nu_min,
-                                   double dnu, int32_t n_points, int32_t n_states, double* kappa,
-                                   hipStream_t s);
+// The series items of n_states states (tiles of core_f64_tile_points(),
+// their own plan): kappa += the series sums; cut items write partial.
+hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRec* core, const int64_t* ranges,
+                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp,
+                           int64_t items_bound, double nu_min, double dnu, int32_t n_points, double* kappa,
+                           double* partial, hipStream_t s);
 hipError_t launch_eval_counts(const WingIdx* idx, int64_t n_lines, int64_t* partial,
                               int32_t n_blocks, hipStream_t s);
 
@@ -268,17 +263,15 @@ hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const Win
                            int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp,
                            int64_t items_bound, int32_t n_points, float* sum, float* comp, float2* partial,
                            hipStream_t s);
-hipError_t launch_core_f32(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges,
-                           int64_t n_tiles, int32_t n_points, float* sum, float* comp,
-                           hipStream_t s);
-hipError_t launch_core_f32_batched(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges,
-                                   int64_t n_lines, int64_t n_tiles, int32_t n_points,
-                                   int32_t n_states, float* sum, float* comp, hipStream_t s);
-// The same series kernel with the learned surrogate in certified cells
-// (surrogate: the bfloat16 parameter copy; mask: certified cells).
-hipError_t launch_core_f32_surrogate(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges,
-                                     int64_t n_tiles, int32_t n_points, float* sum, float* comp,
-                                     const void* surrogate, const uint8_t* mask, hipStream_t s);
+// The series items (tiles of opacity_f32_tile_points(4)): the Kahan pairs
+// += the series sums; surrogate (the bfloat16 parameter copy, single state):
+// the learned surrogate in the cells `mask` certifies.
+hipError_t launch_core_f32(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges, int64_t n_lines,
+                           int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int64_t items_bound,
+                           int32_t n_points, float* sum, float* comp, float* partial, const void* surrogate,
+                           const uint8_t* mask, hipStream_t s);
+
+
 // kappa (binary64) = (sum + comp) * 2^-s, or += when accumulating.
 hipError_t launch_f32_finish(const float* sum, const float* comp, const int32_t* scale,
                              int32_t n_points, double* kappa, int accumulate, hipStream_t s);

@@ -283,12 +283,15 @@ __device__ float voigt_core_f32(float x, float y, float ex, float T1, const floa
 // binary32 core sum is added to the Kahan pair written by the wing kernel.
 // With kSurr, points of certified (x, y) cells take the learned surrogate
 // instead of the series (the wavefront runs the network when any of its
-// lanes needs it, the series when any needs that).
+// lanes needs it, the series when any needs that).  Lines [L0, L1) of tile
+// t; direct: the Kahan pair update; else every point's binary32 sum to
+// partial[j - obase].
 template <int kP, bool kSurr = false>
-__device__ __forceinline__ void core_f32_tile(int64_t t, const WingIdx* __restrict__ idx,
-                              const CoreRec32* __restrict__ core, const int64_t* __restrict__ ranges,
-                              int32_t n, float* __restrict__ sum, float* __restrict__ comp,
-                              const surr::MlpBf16* __restrict__ P = nullptr, const uint8_t* __restrict__ mask = nullptr)
+__device__ __forceinline__ void core_f32_tile(int64_t t, int64_t L0, int64_t L1, const WingIdx* __restrict__ idx,
+                                              const CoreRec32* __restrict__ core, int32_t n, float* __restrict__ sum,
+                                              float* __restrict__ comp, float* __restrict__ partial, int64_t obase,
+                                              bool direct, const surr::MlpBf16* __restrict__ P,
+                                              const uint8_t* __restrict__ mask)
 {
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ float inv_tab[kWaves][kMaxTerms];
@@ -304,7 +307,6 @@ __device__ __forceinline__ void core_f32_tile(int64_t t, const WingIdx* __restri
     for (int p = 0; p < kP; ++p) acc[p] = 0.0f;
     bool any = false;
 
-    const int64_t L0 = ranges[2 * t], L1 = ranges[2 * t + 1];
     for (int64_t i = L0; i < L1; ++i) {
         const int32_t a = max(max(idx[i].clo, idx[i].wlo), run0);
         const int32_t b = min(min(idx[i].chi, idx[i].whi), run1);
@@ -345,6 +347,14 @@ __device__ __forceinline__ void core_f32_tile(int64_t t, const WingIdx* __restri
         }
         __builtin_amdgcn_wave_barrier();
     }
+    if (!direct) {
+#pragma unroll
+        for (int p = 0; p < kP; ++p) {
+            const int32_t j = run0 + lane + 64 * p;
+            if (j <= run1) partial[j - obase] = acc[p];
+        }
+        return;
+    }
     if (!any) return;
 #pragma unroll
     for (int p = 0; p < kP; ++p) {
@@ -358,35 +368,52 @@ __device__ __forceinline__ void core_f32_tile(int64_t t, const WingIdx* __restri
     }
 }
 
-template <int kP>
+// One workgroup per work item of the series (the layout of wing_f32_kernel),
+// in plan order as in the binary64 series kernel;
+// kSurr: the learned surrogate where certified (single state).
+template <int kP, bool kSurr>
 __global__ __launch_bounds__(64 * kWaves) void core_f32_kernel(
-    const WingIdx* __restrict__ idx, const CoreRec32* __restrict__ core,
-    const int64_t* __restrict__ ranges, int64_t n_tiles, int32_t n, float* __restrict__ sum,
-    float* __restrict__ comp)
+    const WingIdx* __restrict__ idx, const CoreRec32* __restrict__ core, const int64_t* __restrict__ ranges,
+    int64_t n_lines, int64_t n_tiles, int32_t n_states, WorkPlan wp, int32_t n, float* __restrict__ sum,
+    float* __restrict__ comp, float* __restrict__ partial, const surr::MlpBf16* __restrict__ P,
+    const uint8_t* __restrict__ mask)
 {
-    core_f32_tile<kP>(n_tiles - 1 - (int64_t)blockIdx.x, idx, core, ranges, n, sum, comp);
+    constexpr int64_t kTilePoints = 64 * kP * kWaves;
+    WorkItem it;
+    if (!work_item((int64_t)blockIdx.x, wp, ranges, n_tiles, n_states, it)) return;
+    const int64_t o = it.st * n_lines, so = it.st * (int64_t)n;
+    const bool direct = it.slot < 0;
+    core_f32_tile<kP, kSurr>(it.tile, it.lo, it.hi, idx + o, core + o, n, sum + so, comp + so,
+                             partial + (direct ? 0 : it.slot * kTilePoints), it.tile * kTilePoints, direct, P, mask);
 }
 
-__global__ __launch_bounds__(64 * kWaves) void core_f32_surrogate_kernel(
-    const WingIdx* __restrict__ idx, const CoreRec32* __restrict__ core,
-    const int64_t* __restrict__ ranges, int64_t n_tiles, int32_t n, float* __restrict__ sum,
-    float* __restrict__ comp, const surr::MlpBf16* __restrict__ P, const uint8_t* __restrict__ mask)
+// Cut series tiles: each point's partials summed in segment order in
+// binary32, then added to its Kahan pair (a zero sum is not added).
+__global__ __launch_bounds__(256) void core_f32_reduce_kernel(WorkPlan wp, int64_t n_tiles, int32_t n_states,
+                                                             int32_t tp, int32_t n, const float* __restrict__ partial,
+                                                             float* __restrict__ sum, float* __restrict__ comp)
 {
-    core_f32_tile<4, true>(n_tiles - 1 - (int64_t)blockIdx.x, idx, core, ranges, n, sum, comp, P, mask);
-}
-
-template <int kP>
-__global__ __launch_bounds__(64 * kWaves) void core_f32_batched_kernel(
-    const WingIdx* __restrict__ idx, const CoreRec32* __restrict__ core,
-    const int64_t* __restrict__ ranges, int64_t n_lines, int64_t n_tiles, int32_t n,
-    int32_t n_states, float* __restrict__ sum, float* __restrict__ comp)
-{
-    const int64_t n_items = n_tiles * n_states;
-    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const int64_t st = item % n_states;
-        const int64_t t = n_tiles - 1 - item / n_states;
-        core_f32_tile<kP>(t, idx + st * n_lines, core + st * n_lines, ranges + st * 2 * n_tiles, n,
-                          sum + st * (int64_t)n, comp + st * (int64_t)n);
+    const int64_t total = wp.total[0];
+    if (total == wp.n_pairs) return;  // nothing cut
+    for (int64_t p = blockIdx.x; p < wp.n_pairs; p += gridDim.x) {
+        const int64_t nseg = (p + 1 < wp.n_pairs ? wp.first[p + 1] : total) - wp.first[p];
+        if (nseg < 2) continue;
+        int64_t st, k;
+        pair_decode(p, n_tiles, n_states, st, k);
+        const int64_t j0 = (n_tiles - 1 - k) * tp;
+        const float* src = partial + wp.slot[p] * tp;
+        for (int q = threadIdx.x; q < tp; q += blockDim.x) {
+            const int64_t j = j0 + q;
+            if (j >= n) break;
+            float v = 0.0f;
+            for (int64_t sg = 0; sg < nseg; ++sg) v += src[sg * tp + q];
+            if (v == 0.0f) continue;
+            const int64_t o = st * (int64_t)n + j;
+            float sv = sum[o], cv = -comp[o];
+            kahan_add(sv, cv, v);
+            sum[o] = sv;
+            comp[o] = -cv;
+        }
     }
 }
 
@@ -403,19 +430,6 @@ hipError_t launch_wing(const WingRec32* wing, const WingIdx* idx, const int64_t*
     wing_f32_reduce_kernel<<<dim3((unsigned)nr), dim3(256), 0, s>>>(wp, n_tiles, n_states, 64 * kP * kWaves, n,
                                                                     partial, sum, comp);
     return hipGetLastError();
-}
-
-// Workgroups of a persistent launch: as many as the device keeps resident.
-template <typename K>
-int persistent_blocks(K kernel, int64_t n_items)
-{
-    int dev = 0, cus = 256, per_cu = 1;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * kWaves, 0);
-    }
-    const int64_t b = (int64_t)std::max(cus, 1) * std::max(per_cu, 1);
-    return (int)std::max<int64_t>(1, std::min(n_items, b));
 }
 
 }  // namespace
@@ -439,43 +453,25 @@ hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const Win
     }
 }
 
-hipError_t launch_core_f32(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges,
-                           int64_t n_tiles, int32_t n_points, float* sum, float* comp,
-                           hipStream_t s)
-{
-    if (n_tiles == 0) return hipSuccess;
-    core_f32_kernel<4><<<dim3((unsigned)n_tiles), dim3(64 * kWaves), 0, s>>>(idx, core, ranges,
-                                                                               n_tiles, n_points,
-                                                                               sum, comp);
-    return hipGetLastError();
-}
-
-}  // namespace hk
-
-namespace hk {
-
-hipError_t launch_core_f32_batched(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges,
-                                   int64_t n_lines, int64_t n_tiles, int32_t n_points,
-                                   int32_t n_states, float* sum, float* comp, hipStream_t s)
+hipError_t launch_core_f32(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges, int64_t n_lines,
+                           int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int64_t items_bound,
+                           int32_t n_points, float* sum, float* comp, float* partial, const void* surrogate,
+                           const uint8_t* mask, hipStream_t s)
 {
     if (n_tiles == 0 || n_states == 0) return hipSuccess;
-    const int nb = persistent_blocks(core_f32_batched_kernel<4>, n_tiles * n_states);
-    core_f32_batched_kernel<4><<<dim3(nb), dim3(64 * kWaves), 0, s>>>(idx, core, ranges, n_lines, n_tiles,
-                                                                     n_points, n_states, sum, comp);
-    return hipGetLastError();
-}
-
-}  // namespace hk
-
-namespace hk {
-
-hipError_t launch_core_f32_surrogate(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges,
-                                     int64_t n_tiles, int32_t n_points, float* sum, float* comp,
-                                     const void* surrogate, const uint8_t* mask, hipStream_t s)
-{
-    if (n_tiles == 0) return hipSuccess;
-    core_f32_surrogate_kernel<<<dim3((unsigned)n_tiles), dim3(64 * kWaves), 0, s>>>(
-        idx, core, ranges, n_tiles, n_points, sum, comp, static_cast<const surr::MlpBf16*>(surrogate), mask);
+    if (surrogate && n_states != 1) return hipErrorInvalidValue;
+    const int64_t nb = plan_blocks(items_bound);
+    if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+    const auto* P = static_cast<const surr::MlpBf16*>(surrogate);
+    if (surrogate)
+        core_f32_kernel<4, true><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(
+            idx, core, ranges, n_lines, n_tiles, n_states, wp, n_points, sum, comp, partial, P, mask);
+    else
+        core_f32_kernel<4, false><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(
+            idx, core, ranges, n_lines, n_tiles, n_states, wp, n_points, sum, comp, partial, nullptr, nullptr);
+    const int64_t nr = std::min<int64_t>(wp.n_pairs, 8192);
+    core_f32_reduce_kernel<<<dim3((unsigned)nr), dim3(256), 0, s>>>(wp, n_tiles, n_states, 64 * 4 * kWaves,
+                                                                    n_points, partial, sum, comp);
     return hipGetLastError();
 }
 

@@ -362,11 +362,14 @@ __device__ double voigt_core(double x, double y, double ex, double T1, const dou
 // the wing kernel and walks, in order, the lines whose a^2+u^2 < 100 points
 // meet its run.  Those points form one contiguous interval [a, b]; lanes
 // take them 64 at a time, and each value moves to the lane owning its point
-// (a rotation of the wavefront) to be added there.  kappa_j += the run's sum.
+// (a rotation of the wavefront) to be added there.  Lines [L0, L1) of tile t;
+// direct: kappa_j += the run's sum (points some line reaches); else every
+// point's sum to partial[j - obase].
 template <int kP>
-__device__ __forceinline__ void core_f64_tile(int64_t t, const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
-                              const CoreRec* __restrict__ core, const int64_t* __restrict__ ranges,
-                              double nu_min, double dnu, int32_t n, double* __restrict__ kappa)
+__device__ __forceinline__ void core_f64_tile(int64_t t, int64_t L0, int64_t L1, const WingRec* __restrict__ wing,
+                                              const WingIdx* __restrict__ idx, const CoreRec* __restrict__ core,
+                                              double nu_min, double dnu, int32_t n, double* __restrict__ kappa,
+                                              double* __restrict__ partial, int64_t obase, bool direct)
 {
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ double inv_tab[kWaves][kMaxTerms];
@@ -381,7 +384,6 @@ __device__ __forceinline__ void core_f64_tile(int64_t t, const WingRec* __restri
     for (int p = 0; p < kP; ++p) acc[p] = 0.0;
     bool any = false;
 
-    const int64_t L0 = ranges[2 * t], L1 = ranges[2 * t + 1];
     for (int64_t i = L0; i < L1; ++i) {
         const int32_t a = max(max(idx[i].clo, idx[i].wlo), run0);
         const int32_t b = min(min(idx[i].chi, idx[i].whi), run1);
@@ -412,37 +414,62 @@ __device__ __forceinline__ void core_f64_tile(int64_t t, const WingRec* __restri
         }
         __builtin_amdgcn_wave_barrier();
     }
-    if (!any) return;
+    if (direct) {
+        if (!any) return;
 #pragma unroll
-    for (int p = 0; p < kP; ++p) {
-        const int32_t j = run0 + lane + 64 * p;
-        if (j <= run1) kappa[j] += acc[p];
+        for (int p = 0; p < kP; ++p) {
+            const int32_t j = run0 + lane + 64 * p;
+            if (j <= run1) kappa[j] += acc[p];
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < kP; ++p) {
+            const int32_t j = run0 + lane + 64 * p;
+            if (j <= run1) partial[j - obase] = acc[p];
+        }
     }
 }
 
+// One workgroup per work item of the series (the layout of wing_f64_kernel),
+// taken in plan order: a series tile reads few lines, so dealing neighbouring
+// tiles to one XCD does not pay here (measured: it costs ~5%).
 template <int kP>
 __global__ __launch_bounds__(64 * kWaves) void core_f64_kernel(
-    const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
-    const CoreRec* __restrict__ core, const int64_t* __restrict__ ranges, int64_t n_tiles,
-    double nu_min, double dnu, int32_t n, double* __restrict__ kappa)
+    const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx, const CoreRec* __restrict__ core,
+    const int64_t* __restrict__ ranges, int64_t n_lines, int64_t n_tiles, int32_t n_states, WorkPlan wp,
+    double nu_min, double dnu, int32_t n, double* __restrict__ kappa, double* __restrict__ partial)
 {
-    // dearest tiles first
-    core_f64_tile<kP>(n_tiles - 1 - (int64_t)blockIdx.x, wing, idx, core, ranges, nu_min, dnu, n, kappa);
+    constexpr int64_t kTilePoints = 64 * kP * kWaves;
+    WorkItem it;
+    if (!work_item((int64_t)blockIdx.x, wp, ranges, n_tiles, n_states, it)) return;
+    const int64_t o = it.st * n_lines;
+    const bool direct = it.slot < 0;
+    core_f64_tile<kP>(it.tile, it.lo, it.hi, wing + o, idx + o, core + o, nu_min, dnu, n, kappa + it.st * (int64_t)n,
+                      partial + (direct ? 0 : it.slot * kTilePoints), it.tile * kTilePoints, direct);
 }
 
-template <int kP>
-__global__ __launch_bounds__(64 * kWaves) void core_f64_batched_kernel(
-    const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx,
-    const CoreRec* __restrict__ core, const int64_t* __restrict__ ranges, int64_t n_lines,
-    int64_t n_tiles, double nu_min, double dnu, int32_t n, int32_t n_states, double* __restrict__ kappa)
+// Cut series tiles: kappa_j += the ordered sum of the tile's partials.
+__global__ __launch_bounds__(256) void core_f64_reduce_kernel(WorkPlan wp, int64_t n_tiles, int32_t n_states,
+                                                             int32_t tp, int32_t n, const double* __restrict__ partial,
+                                                             double* __restrict__ kappa)
 {
-    const int64_t n_items = n_tiles * n_states;
-    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const int64_t st = item % n_states;
-        const int64_t t = n_tiles - 1 - item / n_states;
-        const int64_t o = st * n_lines;
-        core_f64_tile<kP>(t, wing + o, idx + o, core + o, ranges + st * 2 * n_tiles, nu_min, dnu, n,
-                          kappa + st * (int64_t)n);
+    const int64_t total = wp.total[0];
+    if (total == wp.n_pairs) return;  // nothing cut
+    for (int64_t p = blockIdx.x; p < wp.n_pairs; p += gridDim.x) {
+        const int64_t nseg = (p + 1 < wp.n_pairs ? wp.first[p + 1] : total) - wp.first[p];
+        if (nseg < 2) continue;
+        int64_t st, k;
+        pair_decode(p, n_tiles, n_states, st, k);
+        const int64_t j0 = (n_tiles - 1 - k) * tp;
+        const double* src = partial + wp.slot[p] * tp;
+        double* dst = kappa + st * (int64_t)n;
+        for (int q = threadIdx.x; q < tp; q += blockDim.x) {
+            const int64_t j = j0 + q;
+            if (j >= n) break;
+            double v = 0.0;
+            for (int64_t sg = 0; sg < nseg; ++sg) v += src[sg * tp + q];
+            dst[j] += v;
+        }
     }
 }
 
@@ -461,18 +488,7 @@ hipError_t launch_wing(const WingRec* wing, const WingIdx* idx, const int64_t* r
     return hipGetLastError();
 }
 
-// Workgroups of a persistent launch: as many as the device keeps resident.
-template <typename K>
-int persistent_blocks(K kernel, int64_t n_items)
-{
-    int dev = 0, cus = 256, per_cu = 1;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * kWaves, 0);
-    }
-    const int64_t b = (int64_t)std::max(cus, 1) * std::max(per_cu, 1);
-    return (int)std::max<int64_t>(1, std::min(n_items, b));
-}
+
 
 }  // namespace
 
@@ -496,25 +512,20 @@ hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingI
     }
 }
 
-hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRec* core,
-                           const int64_t* ranges, int64_t n_tiles, double nu_min, double dnu,
-                           int32_t n_points, double* kappa, hipStream_t s)
-{
-    if (n_tiles == 0) return hipSuccess;
-    core_f64_kernel<4><<<dim3((unsigned)n_tiles), dim3(64 * kWaves), 0, s>>>(
-        wing, idx, core, ranges, n_tiles, nu_min, dnu, n_points, kappa);
-    return hipGetLastError();
-}
-
-hipError_t launch_core_f64_batched(const WingRec* wing, const WingIdx* idx, const CoreRec* core,
-                                   const int64_t* ranges, int64_t n_lines, int64_t n_tiles, double nu_min,
-                                   double dnu, int32_t n_points, int32_t n_states, double* kappa,
-                                   hipStream_t s)
+hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRec* core, const int64_t* ranges,
+                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp,
+                           int64_t items_bound, double nu_min, double dnu, int32_t n_points, double* kappa,
+                           double* partial, hipStream_t s)
 {
     if (n_tiles == 0 || n_states == 0) return hipSuccess;
-    const int nb = persistent_blocks(core_f64_batched_kernel<4>, n_tiles * n_states);
-    core_f64_batched_kernel<4><<<dim3(nb), dim3(64 * kWaves), 0, s>>>(wing, idx, core, ranges, n_lines, n_tiles,
-                                                                     nu_min, dnu, n_points, n_states, kappa);
+    const int64_t nb = plan_blocks(items_bound);
+    if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+    core_f64_kernel<4><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(wing, idx, core, ranges, n_lines, n_tiles,
+                                                                       n_states, wp, nu_min, dnu, n_points, kappa,
+                                                                       partial);
+    const int64_t nr = std::min<int64_t>(wp.n_pairs, 8192);
+    core_f64_reduce_kernel<<<dim3((unsigned)nr), dim3(256), 0, s>>>(wp, n_tiles, n_states, core_f64_tile_points(),
+                                                                    n_points, partial, kappa);
     return hipGetLastError();
 }
 
