@@ -75,7 +75,7 @@ def cpu_baseline(w, points: int):
     lines, cond, grid = w.lines(), w.conditions(), w.grid()
     N = grid["n_points"]
     ppb = w.points_per_bin
-    j0 = (N // 2 // ppb) * ppb
+    j0 = (max(N - points, 0) // 2 // ppb) * ppb  # centred, whole bins
     j1 = min(j0 + points, N)
     g, _ = oracle.g_nodes(w.n_g)
     t0 = time.perf_counter()
@@ -279,7 +279,7 @@ def main(argv=None):
                     help="lines of the surrogate leg (default: the workload's 1e8; fewer for profiling)")
     ap.add_argument("--surrogate-train-steps", type=int, default=0,
                     help="Adam steps of the surrogate training (default: the full recipe)")
-    ap.add_argument("--cpu-points", type=int, default=300000,
+    ap.add_argument("--cpu-points", type=int, default=3000000,
                     help="grid points in the oracle's timed sample")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (counter "

@@ -329,7 +329,7 @@ template <typename F>
 void host_ranges(int64_t n, int n_max_threads, F fn)
 {
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const int t = n < ((int64_t)1 << 20) ? 1 : (int)std::min<unsigned>((unsigned)n_max_threads, hw);
+    const int t = n < ((int64_t)1 << 16) ? 1 : (int)std::min<unsigned>((unsigned)n_max_threads, hw);
     if (t <= 1) {
         fn((int64_t)0, n, 0);
         return;
