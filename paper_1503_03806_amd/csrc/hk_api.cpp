@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <numeric>
 #include <string>
@@ -264,7 +265,7 @@ LinesDev lines_dev(hk_ctx* ctx)
     L.E_lower = lines_field(ctx, 2);
     L.gamma_air = lines_field(ctx, 3);
     L.n_air = lines_field(ctx, 4);
-    L.gamma_self = lines_field(ctx, 5);
+    L.gamma_self = ctx->li.has_self ? lines_field(ctx, 5) : L.gamma_air;
     L.delta = ctx->li.has_delta ? lines_field(ctx, 6) : nullptr;
     L.A21 = ctx->li.has_A ? lines_field(ctx, 7) : nullptr;
     L.n = ctx->n_lines;
@@ -434,16 +435,57 @@ ListInfo list_info(const hk_lines* L)
     return li;
 }
 
-// Writes a validated list as 8 field arrays of n values (dst[k n + i]) in
-// ascending (nu, input index) order, optional fields defaulted (gamma_self
-// = gamma_air, delta = A21 = 0).  A list already in non-decreasing nu is
-// copied as it is (a stable sort would not move it).
+// The indices of an unordered list sorted by (nu, index) -- the order a
+// stable sort by nu gives -- on up to 8 host threads: each sorts a
+// contiguous part of (nu, index) pairs, then the parts are merged pairwise.
+std::vector<int64_t> line_order(const double* nu, int64_t n)
+{
+    struct Key {
+        double nu;
+        int64_t i;
+    };
+    const auto less = [](const Key& x, const Key& y) { return x.nu < y.nu || (x.nu == y.nu && x.i < y.i); };
+    std::vector<Key> a((size_t)n), b((size_t)n);
+    host_ranges(n, 8, [&](int64_t i0, int64_t i1, int) {
+        for (int64_t i = i0; i < i1; ++i) a[(size_t)i] = Key{nu[i], i};
+    });
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    int parts = 1;
+    while (parts * 2 <= (int)std::min(8u, hw) && n >= ((int64_t)1 << 16)) parts *= 2;
+    std::vector<int64_t> bound((size_t)parts + 1);
+    for (int k = 0; k <= parts; ++k) bound[(size_t)k] = n * k / parts;
+    auto on_threads = [](int count, auto fn) {
+        std::vector<std::thread> th;
+        for (int k = 0; k < count; ++k) th.emplace_back(fn, k);
+        for (auto& x : th) x.join();
+    };
+    on_threads(parts, [&](int k) { std::sort(a.begin() + bound[(size_t)k], a.begin() + bound[(size_t)k + 1], less); });
+    for (int w = 1; w < parts; w *= 2) {
+        on_threads(parts / (2 * w), [&](int m) {
+            const size_t lo = (size_t)bound[(size_t)(2 * w * m)], mid = (size_t)bound[(size_t)(2 * w * m + w)];
+            const size_t hi = (size_t)bound[(size_t)(2 * w * m + 2 * w)];
+            std::merge(a.begin() + lo, a.begin() + mid, a.begin() + mid, a.begin() + hi, b.begin() + lo, less);
+        });
+        a.swap(b);
+    }
+    std::vector<int64_t> perm((size_t)n);
+    host_ranges(n, 8, [&](int64_t i0, int64_t i1, int) {
+        for (int64_t i = i0; i < i1; ++i) perm[(size_t)i] = a[(size_t)i].i;
+    });
+    return perm;
+}
+
+// Writes a validated list as field arrays of n values (dst[k n + i], k = 0
+// .. 7: nu, S_ref, E_lower, gamma_air, n_air, gamma_self, delta, A21) in
+// ascending (nu, input index) order; absent optional fields are not written
+// (the launches use gamma_air for gamma_self and read no delta or A21).  A
+// list already in non-decreasing nu is copied as it is (a stable sort would
+// not move it).
 void order_lines(const hk_lines* L, double* dst)
 {
     const int64_t n = L->n;
     if (n == 0) return;
-    const double* src[8] = {L->nu, L->S_ref, L->E_lower, L->gamma_air, L->n_air,
-                            L->gamma_self ? L->gamma_self : L->gamma_air, L->delta, L->A21};
+    const double* src[8] = {L->nu, L->S_ref, L->E_lower, L->gamma_air, L->n_air, L->gamma_self, L->delta, L->A21};
     bool sorted = true;
     {
         std::vector<char> ok(8, 1);
@@ -458,22 +500,31 @@ void order_lines(const hk_lines* L, double* dst)
         for (char c : ok) sorted = sorted && c;
     }
     std::vector<int64_t> perm;
-    if (!sorted) {
-        perm.resize((size_t)n);
-        std::iota(perm.begin(), perm.end(), (int64_t)0);
-        std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return L->nu[a] < L->nu[b]; });
-    }
+    if (!sorted) perm = line_order(L->nu, n);
     host_ranges(n, 8, [&](int64_t i0, int64_t i1, int) {
         for (int k = 0; k < 8; ++k) {
             double* d = dst + (size_t)k * n;
             if (!src[k])
-                std::fill(d + i0, d + i1, 0.0);
+                continue;
             else if (sorted)
                 std::memcpy(d + i0, src[k] + i0, (size_t)(i1 - i0) * sizeof(double));
             else
                 for (int64_t i = i0; i < i1; ++i) d[i] = src[k][perm[(size_t)i]];
         }
     });
+}
+
+// Runs (first field, field count) of the fields order_lines writes, for the
+// copies to the device (none for an empty list).
+std::vector<std::pair<size_t, size_t>> present_fields(const hk_lines* L)
+{
+    std::vector<std::pair<size_t, size_t>> f;
+    if (L->n == 0) return f;
+    f.push_back({0, 5});
+    if (L->gamma_self) f.push_back({5, 1});
+    if (L->delta) f.push_back({6, 1});
+    if (L->A21) f.push_back({7, 1});
+    return f;
 }
 
 }  // namespace
@@ -832,17 +883,20 @@ int hk_load_lines(hk_ctx* ctx, const hk_lines* L, const hk_species* sp)
     if (int rc = check_ctx(ctx)) return rc;
     HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     const int64_t n = L->n;
-    std::vector<double> host((size_t)8 * (size_t)(n > 0 ? n : 1), 0.0);
-    order_lines(L, host.data());
+    const size_t cap = (size_t)8 * (size_t)(n > 0 ? n : 1);
+    std::unique_ptr<double[]> host(new (std::nothrow) double[cap]);
+    if (!host) return fail(ctx, HK_ENOMEM, "out of host memory for %lld lines", (long long)n);
+    order_lines(L, host.get());
     const ListInfo li = list_info(L);
     HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     ctx->n_lines = n;
     ctx->lines_loaded = false;
     ctx->have_run = false;
     ctx->last_stream_chunks = 0;
-    HK_HIP(ctx, ctx->lines.ensure(host.size() * sizeof(double)), "allocating the line list");
-    if (n > 0)
-        HK_HIP(ctx, hipMemcpy(ctx->lines.p, host.data(), (size_t)8 * n * sizeof(double), hipMemcpyHostToDevice),
+    HK_HIP(ctx, ctx->lines.ensure(cap * sizeof(double)), "allocating the line list");
+    for (const auto& f : present_fields(L))  // the fields order_lines wrote
+        HK_HIP(ctx, hipMemcpy(static_cast<double*>(ctx->lines.p) + f.first * n, host.get() + f.first * n,
+                              (size_t)f.second * n * sizeof(double), hipMemcpyHostToDevice),
                "copying the line list");
     ctx->li = li;
     ctx->species = *sp;
@@ -1105,9 +1159,9 @@ int hk_opacity_stream(hk_ctx* ctx, const hk_lines* chunks, int32_t n_chunks, con
         if (c > 0) std::swap(ctx->lines, ctx->lines_alt);  // device buffer x holds chunk c
         // device buffer x last held chunk c-2: wait until its kernels are done
         if (c >= 2) HK_HIP(ctx, hipStreamWaitEvent(ctx->copy, ctx->ev_used[x], 0), "hipStreamWaitEvent");
-        if (n > 0)
-            HK_HIP(ctx, hipMemcpyAsync(ctx->lines.p, ctx->pin[x], (size_t)8 * n * sizeof(double),
-                                       hipMemcpyHostToDevice, ctx->copy),
+        for (const auto& f : present_fields(&chunks[c]))
+            HK_HIP(ctx, hipMemcpyAsync(static_cast<double*>(ctx->lines.p) + f.first * n, ctx->pin[x] + f.first * n,
+                                       (size_t)f.second * n * sizeof(double), hipMemcpyHostToDevice, ctx->copy),
                    "copying a chunk");
         HK_HIP(ctx, hipEventRecord(ctx->ev_copied[x], ctx->copy), "hipEventRecord");
         HK_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_copied[x], 0), "hipStreamWaitEvent");
