@@ -249,16 +249,19 @@ int hk_kdist(hk_ctx* ctx, const void* kappa, int precision, int64_t n_points,
  *   k_out   [device] double [n_states][n_bins][bins->n_g],
  *           n_bins = ceil(grid->n_points / bins->points_per_bin).
  * The states are processed in batches: one batch's line records are prepared
- * per state, then one persistent wing launch and one persistent series launch
- * cover the (state, grid tile) work items of the whole batch, then the bins
- * of each state are sorted.  The opacity grids of a batch stay in device
- * scratch owned by the context (about n_lines * 96 B + n_points * 8 B per
- * state in binary32, n_lines * 160 B + n_points * 8 B in binary64); the batch
- * size is "tables_batch" states, or (0, the default) as many as fit in
- * "tables_mem_mib".  On the first call for a (precision, line count, grid
- * size, cutoff/dnu) the wing tile shape is chosen by timing 2, 4 and 8
- * points per lane on up to four states ("tables_autotune", synchronises the
- * stream once); the shapes give identical results.  precision: HK_F64 or
+ * per state, then one wing launch and one series launch cover the work items
+ * (grid tiles, or a tile's lines in one segment where lines crowd) of every
+ * state of the batch, then the bins of each state are sorted.  The opacity
+ * grids of a batch stay in device scratch owned by the context (about
+ * n_lines * 96 B + n_points * 8 B per state in binary32, n_lines * 160 B +
+ * n_points * 8 B in binary64, plus up to 4 n_points * 8 B of partial sums per
+ * state whose tiles are split); the batch size is "tables_batch" states, or
+ * (0, the default) as many as fit in "tables_mem_mib".  Each batch's work
+ * plan is read back once to size its launches (one stream synchronisation
+ * per batch).  On the first call for a (precision, line count, grid size,
+ * cutoff/dnu) the wing tile shape is chosen by timing 2, 4 and 8 points per
+ * lane on up to four states ("tables_autotune", synchronises the stream
+ * once); the shapes give identical results.  precision: HK_F64 or
  * HK_F32_KAHAN (cutoff/dnu < 2^23).  Errors: HK_EINVAL (argument, with the
  * index of a bad state), HK_ENOTREADY (no line list), HK_ENOMEM/HK_EDEVICE.
  * hk_stats afterwards reports the evaluation counts summed over the states. */
