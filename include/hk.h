@@ -200,7 +200,9 @@ int hk_read_par(const char* path, int64_t first, int32_t molecule, const hk_line
  *   call certified take the learned surrogate instead of the series;
  *   HK_ENOTREADY without a certification.
  * accumulate != 0 adds to the values already in kappa, e.g. to process a
- * line list in chunks; accumulate == 0 overwrites them. */
+ * line list in chunks; accumulate == 0 overwrites them.  Asynchronous, except
+ * on grids above ~3e7 points, where each stage's work plan is read back once
+ * (two stream synchronisations) to size its scratch. */
 int hk_opacity(hk_ctx* ctx, const hk_state* state, const hk_grid* grid,
                int precision, void* kappa, void* comp, int accumulate);
 

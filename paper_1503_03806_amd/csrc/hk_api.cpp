@@ -533,10 +533,15 @@ namespace {
 
 constexpr int32_t kCountBlocks = 256;  // partial sums per evaluation count
 
+// Partial sums sized by their bound up to this many bytes; beyond it (grids
+// above ~3e7 points) the plan is read back instead.
+constexpr int64_t kPlanBoundBytes = (int64_t)1 << 30;
+
 // The work plan of n_states states (work_plan.hip): reference tile ranges
 // for reach[s], segment lengths, then the items of the tiles whose ranges
-// (2 n_tiles per state) are given, into pb.  exact: read the totals back (one
-// host synchronisation) for *items and the partial sums; else their bounds.
+// (2 n_tiles per state) are given, into pb.  exact, or a bound above
+// kPlanBoundBytes: read the totals back (one host synchronisation) for
+// *items and the partial sums; else their bounds.
 int make_plan(hk_ctx* ctx, PlanBufs& pb, const int64_t* ranges, int64_t n_tiles, int32_t n_states,
               const double* reach, int32_t tp, const hk_grid* grid, bool exact, WorkPlan* wp, int64_t* items)
 {
@@ -567,7 +572,7 @@ int make_plan(hk_ctx* ctx, PlanBufs& pb, const int64_t* ranges, int64_t n_tiles,
            "work_plan");
     int64_t it = n_states * plan_items_bound(n_tiles);
     int64_t points = n_states * plan_partial_points_bound(np, tp);
-    if (exact) {
+    if (exact || points * 8 > kPlanBoundBytes) {
         int64_t h[2] = {0, 0};
         HK_HIP(ctx, hipMemcpyAsync(h, total, sizeof h, hipMemcpyDeviceToHost, ctx->stream), "reading the work plan");
         HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");

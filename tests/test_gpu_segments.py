@@ -114,3 +114,22 @@ def test_even_list_is_not_split(ctx):
         ref, _ = oracle.opacity(lines, COND, grid, int(a), int(a) + 1)
         v = k[int(a)].item()
         assert (ref[0] == 0 and v == 0) or abs(v / ref[0] - 1) <= 1e-6
+
+
+def test_large_grid_reads_the_plan_back(ctx):
+    """A grid of 4e7 points (its plans' partial-sum bound passes 1 GiB, so
+    the plans are read back): sampled points against the oracle, binary64
+    and binary32, with a crowded list so that tiles are split."""
+    L = synth.line_list(20_000, 40.0, seed=25)
+    L["nu"] = L["nu"] + 20000.0
+    grid = {"nu_min": 0.0, "dnu": 0.001, "n_points": 40_000_000, "cutoff": 5.0}
+    ctx.load_lines(L, COND["mass_amu"], COND["T0"])
+    j = np.concatenate([np.random.default_rng(7).integers(19_990_000, 20_050_000, 24), [0, 39_999_999]])
+    for prec, bar in ((hk.HK_F64, 1e-6), (hk.HK_F32_KAHAN, 1e-4)):
+        k = ctx.opacity(STATE, grid, prec)
+        assert ctx.get_option("wing_segment_lines") > 0
+        for a in j:
+            ref, _ = oracle.opacity(L, COND, grid, int(a), int(a) + 1)
+            v = k[int(a)].item()
+            assert (ref[0] == 0 and v == 0) or abs(v / ref[0] - 1) <= bar, (prec, int(a))
+        del k
