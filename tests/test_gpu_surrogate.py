@@ -220,3 +220,30 @@ def test_surrogate_gain_is_reported(ctx, trained):
         % (out[hk.HK_F32_KAHAN][1], out[hk.HK_F32_SURROGATE][1], out[hk.HK_F32_KAHAN][2],
            out[hk.HK_F32_SURROGATE][2], trained["count"], e))
     assert e <= 1e-4
+
+
+def test_surrogate_workload_full_size_sampled(ctx, trained):
+    """The surrogate configuration at its full size (1e8 lines over
+    0-30000 cm^-1, 3e6 points, 25 cm^-1 cutoff, 1500 K, 1 atm), in the launch
+    configuration the benchmark times: four windows of 8 points against the
+    oracle.  The oracle is given the lines within the cutoff (+1 cm^-1) of
+    each window -- every other line adds exactly nothing there -- so that it
+    does not sort and prepare all 1e8 lines per window."""
+    w = synth.WORKLOADS["lines1e8_surrogate"]
+    lines, cond, grid = w.lines(), w.conditions(), w.grid()
+    say("full size: %d lines, %d points" % (len(lines["nu"]), grid["n_points"]))
+    ctx.load_lines(lines, cond["mass_amu"], cond["T0"])
+    st = {k: cond[k] for k in ("T", "P", "P_self", "q_ratio")}
+    k = ctx.opacity(st, grid, hk.HK_F32_SURROGATE)
+    worst = 0.0
+    for j0 in (1000, 1_000_003, 2_000_017, 2_999_990):
+        got = k[j0:j0 + 8].cpu().numpy()
+        lo = grid["nu_min"] + j0 * grid["dnu"] - grid["cutoff"] - 1.0
+        hi = grid["nu_min"] + (j0 + 7) * grid["dnu"] + grid["cutoff"] + 1.0
+        near = (lines["nu"] >= lo) & (lines["nu"] <= hi)
+        ref, _ = oracle.opacity({f: v[near] for f, v in lines.items()}, cond, grid, j0, j0 + 8)
+        worst = max(worst, float(np.abs(got / ref - 1).max()))
+    say("  max rel err vs oracle %.2e over 32 sampled points" % worst)
+    assert worst <= 1e-4
+    del k
+    ctx.load_lines(synth.line_list(10, 10.0), cond["mass_amu"], cond["T0"])  # release the list's device memory
