@@ -201,7 +201,7 @@ int hk_read_par(const char* path, int64_t first, int32_t molecule, const hk_line
  *   HK_ENOTREADY without a certification.
  * accumulate != 0 adds to the values already in kappa, e.g. to process a
  * line list in chunks; accumulate == 0 overwrites them.  Asynchronous, except
- * on grids above ~3e7 points, where each stage's work plan is read back once
+ * on grids above ~2e7 points, where each stage's work plan is read back once
  * (two stream synchronisations) to size its scratch. */
 int hk_opacity(hk_ctx* ctx, const hk_state* state, const hk_grid* grid,
                int precision, void* kappa, void* comp, int accumulate);
@@ -256,7 +256,7 @@ int hk_kdist(hk_ctx* ctx, const void* kappa, int precision, int64_t n_points,
  * state of the batch, then the bins of each state are sorted.  The opacity
  * grids of a batch stay in device scratch owned by the context (about
  * n_lines * 96 B + n_points * 8 B per state in binary32, n_lines * 160 B +
- * n_points * 8 B in binary64, plus up to 4 n_points * 8 B of partial sums per
+ * n_points * 8 B in binary64, plus up to 6 n_points * 8 B of partial sums per
  * state whose tiles are split); the batch size is "tables_batch" states, or
  * (0, the default) as many as fit in "tables_mem_mib".  Each batch's work
  * plan is read back once to size its launches (one stream synchronisation

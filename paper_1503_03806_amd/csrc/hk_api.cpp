@@ -534,7 +534,7 @@ namespace {
 constexpr int32_t kCountBlocks = 256;  // partial sums per evaluation count
 
 // Partial sums sized by their bound up to this many bytes; beyond it (grids
-// above ~3e7 points) the plan is read back instead.
+// above ~2e7 points) the plan is read back instead.
 constexpr int64_t kPlanBoundBytes = (int64_t)1 << 30;
 
 // The work plan of n_states states (work_plan.hip): reference tile ranges
@@ -543,7 +543,7 @@ constexpr int64_t kPlanBoundBytes = (int64_t)1 << 30;
 // kPlanBoundBytes: read the totals back (one host synchronisation) for
 // *items and the partial sums; else their bounds.
 int make_plan(hk_ctx* ctx, PlanBufs& pb, const int64_t* ranges, int64_t n_tiles, int32_t n_states,
-              const double* reach, int32_t tp, const hk_grid* grid, bool exact, WorkPlan* wp, int64_t* items)
+              const double* reach, int32_t tp, int64_t min_seg, const hk_grid* grid, bool exact, WorkPlan* wp)
 {
     const int64_t n = ctx->n_lines;
     const int32_t np = (int32_t)grid->n_points;
@@ -566,22 +566,21 @@ int make_plan(hk_ctx* ctx, PlanBufs& pb, const int64_t* ranges, int64_t n_tiles,
         HK_HIP(ctx, launch_tile_ranges(nu, n, n_ref, kRefTilePoints, grid->nu_min, grid->dnu, np, reach[s],
                                        ref + (int64_t)s * 2 * n_ref, ctx->stream),
                "tile_ranges");
-    HK_HIP(ctx, launch_seg_length(ref, n_ref, n_states, np, n, seg, ctx->stream), "seg_length");
+    HK_HIP(ctx, launch_seg_length(ref, n_ref, n_states, np, n, min_seg, seg, ctx->stream), "seg_length");
     HK_HIP(ctx, launch_work_plan(ranges, n_tiles, n_states, seg, first, slot, static_cast<int64_t*>(pb.bsum.p), total,
                                  ctx->stream),
            "work_plan");
-    int64_t it = n_states * plan_items_bound(n_tiles);
+    int64_t items = plan_items_bound(P, n_states);
     int64_t points = n_states * plan_partial_points_bound(np, tp);
     if (exact || points * 8 > kPlanBoundBytes) {
         int64_t h[2] = {0, 0};
         HK_HIP(ctx, hipMemcpyAsync(h, total, sizeof h, hipMemcpyDeviceToHost, ctx->stream), "reading the work plan");
         HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-        it = h[0];
+        items = h[0];
         points = h[1] * tp;
     }
     HK_HIP(ctx, pb.partial.ensure((size_t)std::max<int64_t>(points, 1) * 8), "allocating partial sums");
-    *wp = WorkPlan{seg, first, slot, total, P};
-    *items = it;
+    *wp = WorkPlan{seg, first, slot, total, P, items};
     return HK_OK;
 }
 
@@ -597,19 +596,19 @@ int wing_stage(hk_ctx* ctx, int precision, int ppl, const void* recs, const Wing
     const bool f64 = precision == HK_F64;
     const int32_t tp = f64 ? opacity_f64_tile_points(ppl) : opacity_f32_tile_points(ppl);
     WorkPlan wp;
-    int64_t items = 0;
-    if (int rc = make_plan(ctx, ctx->wplan, ranges, n_tiles, n_states, reach, tp, grid, exact, &wp, &items))
+    // binary32: segments of whole 256-line compensation blocks
+    if (int rc = make_plan(ctx, ctx->wplan, ranges, n_tiles, n_states, reach, tp, f64 ? 64 : 256, grid, exact, &wp))
         return rc;
     const int64_t n = ctx->n_lines;
     const int32_t np = (int32_t)grid->n_points;
     if (f64)
-        HK_HIP(ctx, launch_wing_f64(ppl, static_cast<const WingRec*>(recs), idx, ranges, n, n_tiles, n_states, wp, items,
+        HK_HIP(ctx, launch_wing_f64(ppl, static_cast<const WingRec*>(recs), idx, ranges, n, n_tiles, n_states, wp,
                                     grid->nu_min, grid->dnu, np, static_cast<double*>(out),
                                     static_cast<double*>(ctx->wplan.partial.p), accumulate, ctx->stream),
                "wing_f64");
     else
         HK_HIP(ctx, launch_wing_f32(ppl, static_cast<const WingRec32*>(recs), idx, ranges, n, n_tiles, n_states, wp,
-                                    items, np, static_cast<float*>(out), comp,
+                                    np, static_cast<float*>(out), comp,
                                     static_cast<float2*>(ctx->wplan.partial.p), ctx->stream),
                "wing_f32");
     return HK_OK;
@@ -624,18 +623,17 @@ int core_stage(hk_ctx* ctx, int precision, const void* wing, const WingIdx* idx,
     const bool f64 = precision == HK_F64;
     const int32_t tp = f64 ? core_f64_tile_points() : opacity_f32_tile_points(4);
     WorkPlan wp;
-    int64_t items = 0;
-    if (int rc = make_plan(ctx, ctx->cplan, ranges, n_tiles, n_states, reach, tp, grid, exact, &wp, &items))
+    if (int rc = make_plan(ctx, ctx->cplan, ranges, n_tiles, n_states, reach, tp, 64, grid, exact, &wp))
         return rc;
     const int64_t n = ctx->n_lines;
     const int32_t np = (int32_t)grid->n_points;
     if (f64)
         HK_HIP(ctx, launch_core_f64(static_cast<const WingRec*>(wing), idx, static_cast<const CoreRec*>(core), ranges, n,
-                                    n_tiles, n_states, wp, items, grid->nu_min, grid->dnu, np, static_cast<double*>(out),
+                                    n_tiles, n_states, wp, grid->nu_min, grid->dnu, np, static_cast<double*>(out),
                                     static_cast<double*>(ctx->cplan.partial.p), ctx->stream),
                "core_f64");
     else
-        HK_HIP(ctx, launch_core_f32(idx, static_cast<const CoreRec32*>(core), ranges, n, n_tiles, n_states, wp, items,
+        HK_HIP(ctx, launch_core_f32(idx, static_cast<const CoreRec32*>(core), ranges, n, n_tiles, n_states, wp,
                                     np, static_cast<float*>(out), comp, static_cast<float*>(ctx->cplan.partial.p),
                                     surrogate, mask, ctx->stream),
                "core_f32");

@@ -124,8 +124,8 @@ struct GValues {
 // A tile's lines are summed by one workgroup, unless the lines crowd into
 // few tiles or unevenly (a wavenumber-ordered piece of a list, a dense band):
 // then every tile's line range is cut where it crosses a multiple of a
-// segment length Lseg (a power of two >= 256, per state, from statistics of
-// 512-point reference tiles, so the same for every tile shape), and each
+// segment length Lseg (a power of two, per state, from statistics of 512-point
+// reference tiles, so the same for every tile shape), and each
 // piece is an item of its own that writes partial sums; a reduction adds a
 // cut tile's partials in segment order.  A point's value is then the ordered
 // sum over segments of the ordered sum of its lines in each segment -- the
@@ -143,23 +143,28 @@ struct WorkPlan {
     const int64_t* slot;   // [n_pairs] first partial slot of each cut pair
     const int64_t* total;  // [2] items, partial slots
     int64_t n_pairs;
+    int64_t launch_items;  // host: workgroups to launch (the item count, or its bound)
 };
-// Upper bounds per state, for sizing without reading the plan back: items
-// <= 4 n_tiles + 2, partial points <= 4 n_points + 2 tile_points.
-inline int64_t plan_items_bound(int64_t n_tiles) { return 4 * n_tiles + 2; }
+// Upper bounds, for sizing without reading the plan back: items <= 6 n_tiles
+// + 2 per state (launches of n_pairs = n_tiles n_states pairs), partial
+// points <= 6 n_points + 2 tile_points per state.
+inline int64_t plan_items_bound(int64_t n_pairs, int32_t n_states) { return 6 * n_pairs + 2 * (int64_t)n_states; }
 inline int64_t plan_partial_points_bound(int64_t n_points, int32_t tile_points)
 {
-    return 4 * n_points + 2 * (int64_t)tile_points;
+    return 6 * n_points + 2 * (int64_t)tile_points;
 }
 int64_t plan_scratch_count(int64_t n_pairs);  // int64 values of the plan's block sums
 // seg[s] from the reference ranges (tiles of kRefTilePoints points, 2 n_ref
-// values per state) of n_states states.
+// values per state) of n_states states; min_seg: the shortest segment, a
+// power of two (256 for the binary32 wing, whose compensated sums run over
+// 256-line blocks aligned to global line indices).
 hipError_t launch_seg_length(const int64_t* ref_ranges, int64_t n_ref, int32_t n_states, int64_t n_points,
-                             int64_t n_lines, int64_t* seg, hipStream_t s);
+                             int64_t n_lines, int64_t min_seg, int64_t* seg, hipStream_t s);
 // first, slot and total from the tile ranges (2 n_tiles per state) and seg.
 hipError_t launch_work_plan(const int64_t* ranges, int64_t n_tiles, int32_t n_states, const int64_t* seg,
                             int64_t* first, int64_t* slot, int64_t* block_sums, int64_t* total, hipStream_t s);
-// Workgroups for `items` items: padded to whole XCD chunks.
+// Workgroups for `items` items: padded to whole XCD chunks (xcd_rank is a
+// bijection on each multiple of 8 kPlanChunk).
 inline int64_t plan_blocks(int64_t items) { return (items + 8 * kPlanChunk - 1) / (8 * kPlanChunk) * (8 * kPlanChunk); }
 
 // Rank of workgroup b: XCD b % 8 takes chunks of kPlanChunk consecutive
@@ -234,18 +239,17 @@ int32_t core_f64_tile_points();
 // The wing items of n_states states (records n_lines apart, ranges 2 n_tiles
 // apart, kappa n_points apart); items cut by the plan write partial (binary64,
 // tile_points per slot), which the reduction then adds into kappa.  With
-// accumulate, kappa += the wing sum (single state).  items_bound: workgroups
-// needed (the plan's item count or its bound).
+// accumulate, kappa += the wing sum (single state).  One workgroup per item
+// (wp.launch_items workgroups).
 hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingIdx* idx, const int64_t* ranges,
-                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp,
-                           int64_t items_bound, double nu_min, double dnu, int32_t n_points, double* kappa,
-                           double* partial, int accumulate, hipStream_t s);
+                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, double nu_min,
+                           double dnu, int32_t n_points, double* kappa, double* partial, int accumulate,
+                           hipStream_t s);
 // The series items of n_states states (tiles of core_f64_tile_points(),
 // their own plan): kappa += the series sums; cut items write partial.
 hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRec* core, const int64_t* ranges,
-                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp,
-                           int64_t items_bound, double nu_min, double dnu, int32_t n_points, double* kappa,
-                           double* partial, hipStream_t s);
+                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, double nu_min,
+                           double dnu, int32_t n_points, double* kappa, double* partial, hipStream_t s);
 hipError_t launch_eval_counts(const WingIdx* idx, int64_t n_lines, int64_t* partial,
                               int32_t n_blocks, hipStream_t s);
 
@@ -260,16 +264,14 @@ int32_t opacity_f32_tile_points(int points_per_lane);
 // As launch_wing_f64: the Kahan pairs (sum, comp) of n_states states; cut
 // items write (sum, comp) pairs to partial (tile_points float2 per slot).
 hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const WingIdx* idx, const int64_t* ranges,
-                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp,
-                           int64_t items_bound, int32_t n_points, float* sum, float* comp, float2* partial,
-                           hipStream_t s);
+                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int32_t n_points,
+                           float* sum, float* comp, float2* partial, hipStream_t s);
 // The series items (tiles of opacity_f32_tile_points(4)): the Kahan pairs
 // += the series sums; surrogate (the bfloat16 parameter copy, single state):
 // the learned surrogate in the cells `mask` certifies.
 hipError_t launch_core_f32(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges, int64_t n_lines,
-                           int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int64_t items_bound,
-                           int32_t n_points, float* sum, float* comp, float* partial, const void* surrogate,
-                           const uint8_t* mask, hipStream_t s);
+                           int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int32_t n_points, float* sum,
+                           float* comp, float* partial, const void* surrogate, const uint8_t* mask, hipStream_t s);
 
 
 // kappa (binary64) = (sum + comp) * 2^-s, or += when accumulating.

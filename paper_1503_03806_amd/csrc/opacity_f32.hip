@@ -195,11 +195,12 @@ __global__ __launch_bounds__(64 * kWaves) void wing_f32_kernel(
 {
     constexpr int64_t kTilePoints = 64 * kP * kWaves;
     WorkItem it;
-    if (!work_item(xcd_rank(blockIdx.x), wp, ranges, n_tiles, n_states, it)) return;
-    const int64_t o = it.st * n_lines, so = it.st * (int64_t)n;
-    const bool direct = it.slot < 0;
-    wing_f32_tile<kP>(it.tile, it.lo, it.hi, wing + o, idx + o, n, sum + so, comp + so,
-                      partial + (direct ? 0 : it.slot * kTilePoints), it.tile * kTilePoints, direct);
+    if (work_item(xcd_rank(blockIdx.x), wp, ranges, n_tiles, n_states, it)) {
+        const int64_t o = it.st * n_lines, so = it.st * (int64_t)n;
+        const bool direct = it.slot < 0;
+        wing_f32_tile<kP>(it.tile, it.lo, it.hi, wing + o, idx + o, n, sum + so, comp + so,
+                          partial + (direct ? 0 : it.slot * kTilePoints), it.tile * kTilePoints, direct);
+    }
 }
 
 // The cut tiles: each point's value is the binary64 sum of its partial
@@ -380,11 +381,13 @@ __global__ __launch_bounds__(64 * kWaves) void core_f32_kernel(
 {
     constexpr int64_t kTilePoints = 64 * kP * kWaves;
     WorkItem it;
-    if (!work_item((int64_t)blockIdx.x, wp, ranges, n_tiles, n_states, it)) return;
-    const int64_t o = it.st * n_lines, so = it.st * (int64_t)n;
-    const bool direct = it.slot < 0;
-    core_f32_tile<kP, kSurr>(it.tile, it.lo, it.hi, idx + o, core + o, n, sum + so, comp + so,
-                             partial + (direct ? 0 : it.slot * kTilePoints), it.tile * kTilePoints, direct, P, mask);
+    if (work_item(blockIdx.x, wp, ranges, n_tiles, n_states, it)) {
+        const int64_t o = it.st * n_lines, so = it.st * (int64_t)n;
+        const bool direct = it.slot < 0;
+        core_f32_tile<kP, kSurr>(it.tile, it.lo, it.hi, idx + o, core + o, n, sum + so, comp + so,
+                                 partial + (direct ? 0 : it.slot * kTilePoints), it.tile * kTilePoints, direct, P,
+                                 mask);
+    }
 }
 
 // Cut series tiles: each point's partials summed in segment order in
@@ -419,10 +422,10 @@ __global__ __launch_bounds__(256) void core_f32_reduce_kernel(WorkPlan wp, int64
 
 template <int kP>
 hipError_t launch_wing(const WingRec32* wing, const WingIdx* idx, const int64_t* ranges, int64_t n_lines,
-                       int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int64_t items_bound, int32_t n,
-                       float* sum, float* comp, float2* partial, hipStream_t s)
+                       int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int32_t n, float* sum, float* comp,
+                       float2* partial, hipStream_t s)
 {
-    const int64_t nb = plan_blocks(items_bound);
+    const int64_t nb = plan_blocks(wp.launch_items);
     if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
     wing_f32_kernel<kP><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(wing, idx, ranges, n_lines, n_tiles,
                                                                         n_states, wp, n, sum, comp, partial);
@@ -437,30 +440,25 @@ hipError_t launch_wing(const WingRec32* wing, const WingIdx* idx, const int64_t*
 int32_t opacity_f32_tile_points(int points_per_lane) { return 64 * points_per_lane * kWaves; }
 
 hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const WingIdx* idx, const int64_t* ranges,
-                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp,
-                           int64_t items_bound, int32_t n_points, float* sum, float* comp, float2* partial,
-                           hipStream_t s)
+                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int32_t n_points,
+                           float* sum, float* comp, float2* partial, hipStream_t s)
 {
     if (n_tiles == 0 || n_states == 0) return hipSuccess;
     switch (points_per_lane) {
-    case 2: return launch_wing<2>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, items_bound, n_points, sum,
-                                  comp, partial, s);
-    case 4: return launch_wing<4>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, items_bound, n_points, sum,
-                                  comp, partial, s);
-    case 8: return launch_wing<8>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, items_bound, n_points, sum,
-                                  comp, partial, s);
+    case 2: return launch_wing<2>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, n_points, sum, comp, partial, s);
+    case 4: return launch_wing<4>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, n_points, sum, comp, partial, s);
+    case 8: return launch_wing<8>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, n_points, sum, comp, partial, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_core_f32(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges, int64_t n_lines,
-                           int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int64_t items_bound,
-                           int32_t n_points, float* sum, float* comp, float* partial, const void* surrogate,
-                           const uint8_t* mask, hipStream_t s)
+                           int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int32_t n_points, float* sum,
+                           float* comp, float* partial, const void* surrogate, const uint8_t* mask, hipStream_t s)
 {
     if (n_tiles == 0 || n_states == 0) return hipSuccess;
     if (surrogate && n_states != 1) return hipErrorInvalidValue;
-    const int64_t nb = plan_blocks(items_bound);
+    const int64_t nb = plan_blocks(wp.launch_items);
     if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
     const auto* P = static_cast<const surr::MlpBf16*>(surrogate);
     if (surrogate)

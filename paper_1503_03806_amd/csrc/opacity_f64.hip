@@ -241,8 +241,11 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
 }
 
 // One workgroup per work item (a grid tile of a state, or its lines in one
-// segment).  Per-state arrays lie n_lines records, 2 n_tiles ranges and n
-// points apart; a cut item writes its slot of partial (kTilePoints values).
+// segment), wp.launch_items of them (the plan's item count or its bound:
+// workgroups past the last item exit at once; a loop over several items per
+// workgroup measured slower, it costs registers).  Per-state arrays lie n_lines records, 2 n_tiles ranges
+// and n points apart; a cut item writes its slot of partial (kTilePoints
+// values).
 template <int kP>
 __global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
     const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx, const int64_t* __restrict__ ranges,
@@ -251,12 +254,13 @@ __global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
 {
     constexpr int64_t kTilePoints = 64 * kP * kWaves;
     WorkItem it;
-    if (!work_item(xcd_rank(blockIdx.x), wp, ranges, n_tiles, n_states, it)) return;
-    const int64_t o = it.st * n_lines;
-    const bool direct = it.slot < 0;
-    double* out = direct ? kappa + it.st * (int64_t)n : partial + it.slot * kTilePoints;
-    wing_f64_tile<kP>(it.tile, it.lo, it.hi, wing + o, idx + o, nu_min, dnu, n, out,
-                      direct ? 0 : it.tile * kTilePoints, direct ? accumulate : 0);
+    if (work_item(xcd_rank(blockIdx.x), wp, ranges, n_tiles, n_states, it)) {
+        const int64_t o = it.st * n_lines;
+        const bool direct = it.slot < 0;
+        double* out = direct ? kappa + it.st * (int64_t)n : partial + it.slot * kTilePoints;
+        wing_f64_tile<kP>(it.tile, it.lo, it.hi, wing + o, idx + o, nu_min, dnu, n, out,
+                          direct ? 0 : it.tile * kTilePoints, direct ? accumulate : 0);
+    }
 }
 
 // The cut tiles: kappa_j (+)= the ordered sum of the tile's partials,
@@ -441,11 +445,13 @@ __global__ __launch_bounds__(64 * kWaves) void core_f64_kernel(
 {
     constexpr int64_t kTilePoints = 64 * kP * kWaves;
     WorkItem it;
-    if (!work_item((int64_t)blockIdx.x, wp, ranges, n_tiles, n_states, it)) return;
-    const int64_t o = it.st * n_lines;
-    const bool direct = it.slot < 0;
-    core_f64_tile<kP>(it.tile, it.lo, it.hi, wing + o, idx + o, core + o, nu_min, dnu, n, kappa + it.st * (int64_t)n,
-                      partial + (direct ? 0 : it.slot * kTilePoints), it.tile * kTilePoints, direct);
+    if (work_item(blockIdx.x, wp, ranges, n_tiles, n_states, it)) {
+        const int64_t o = it.st * n_lines;
+        const bool direct = it.slot < 0;
+        core_f64_tile<kP>(it.tile, it.lo, it.hi, wing + o, idx + o, core + o, nu_min, dnu, n,
+                          kappa + it.st * (int64_t)n, partial + (direct ? 0 : it.slot * kTilePoints),
+                          it.tile * kTilePoints, direct);
+    }
 }
 
 // Cut series tiles: kappa_j += the ordered sum of the tile's partials.
@@ -475,10 +481,10 @@ __global__ __launch_bounds__(256) void core_f64_reduce_kernel(WorkPlan wp, int64
 
 template <int kP>
 hipError_t launch_wing(const WingRec* wing, const WingIdx* idx, const int64_t* ranges, int64_t n_lines,
-                       int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int64_t items_bound, double nu_min,
-                       double dnu, int32_t n, double* kappa, double* partial, int accumulate, hipStream_t s)
+                       int64_t n_tiles, int32_t n_states, const WorkPlan& wp, double nu_min, double dnu, int32_t n,
+                       double* kappa, double* partial, int accumulate, hipStream_t s)
 {
-    const int64_t nb = plan_blocks(items_bound);
+    const int64_t nb = plan_blocks(wp.launch_items);
     if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
     wing_f64_kernel<kP><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(
         wing, idx, ranges, n_lines, n_tiles, n_states, wp, nu_min, dnu, n, kappa, partial, accumulate);
@@ -496,29 +502,27 @@ int32_t opacity_f64_tile_points(int points_per_lane) { return 64 * points_per_la
 int32_t core_f64_tile_points() { return 64 * 4 * kWaves; }
 
 hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingIdx* idx, const int64_t* ranges,
-                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp,
-                           int64_t items_bound, double nu_min, double dnu, int32_t n_points, double* kappa,
-                           double* partial, int accumulate, hipStream_t s)
+                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, double nu_min,
+                           double dnu, int32_t n_points, double* kappa, double* partial, int accumulate, hipStream_t s)
 {
     if (n_tiles == 0 || n_states == 0) return hipSuccess;
     switch (points_per_lane) {
-    case 2: return launch_wing<2>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, items_bound, nu_min, dnu,
-                                  n_points, kappa, partial, accumulate, s);
-    case 4: return launch_wing<4>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, items_bound, nu_min, dnu,
-                                  n_points, kappa, partial, accumulate, s);
-    case 8: return launch_wing<8>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, items_bound, nu_min, dnu,
-                                  n_points, kappa, partial, accumulate, s);
+    case 2: return launch_wing<2>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, nu_min, dnu, n_points, kappa,
+                                  partial, accumulate, s);
+    case 4: return launch_wing<4>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, nu_min, dnu, n_points, kappa,
+                                  partial, accumulate, s);
+    case 8: return launch_wing<8>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, nu_min, dnu, n_points, kappa,
+                                  partial, accumulate, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRec* core, const int64_t* ranges,
-                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp,
-                           int64_t items_bound, double nu_min, double dnu, int32_t n_points, double* kappa,
-                           double* partial, hipStream_t s)
+                           int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, double nu_min,
+                           double dnu, int32_t n_points, double* kappa, double* partial, hipStream_t s)
 {
     if (n_tiles == 0 || n_states == 0) return hipSuccess;
-    const int64_t nb = plan_blocks(items_bound);
+    const int64_t nb = plan_blocks(wp.launch_items);
     if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
     core_f64_kernel<4><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(wing, idx, core, ranges, n_lines, n_tiles,
                                                                        n_states, wp, nu_min, dnu, n_points, kappa,

@@ -18,13 +18,15 @@ constexpr int64_t kPerBlock = (int64_t)kThreads * kPerThread;
 constexpr int64_t kBusyMin = 4096;
 constexpr int64_t kUneven = 3;
 
-// One workgroup per state.  Segment length: the smallest power of two >= 256
-// and >= W / (2 n_points), W = 512 sum_t c_t + 8192 n_lines (c_t: lines of
-// reference tile t).  W bounds sum over any tiles of <= 2048 points of
-// (lines in the tile's range) x (tile points), which keeps the items at
-// <= 4 n_tiles + 2 and the partial points at <= 4 n_points + 2 tile_points.
+// One workgroup per state.  Segment length: the smallest power of two >=
+// min_seg and >= W / (4 n_points), W = 512 sum_t c_t + 4096 n_lines (c_t:
+// lines of reference tile t).  W bounds the sum over any tiles of <= 2048
+// points of (lines in the tile's range) x (tile points): a line's reach
+// covers |A| grid points, which lie in >= |A| / 512 reference tiles and meet
+// <= |A| / tp + 2 tiles of tp points.  So the items stay <= sum_t (c_t / L
+// + 2) <= 6 n_tiles and the partial points <= 6 n_points + 2 tile points.
 __global__ __launch_bounds__(kThreads) void seg_length_kernel(const int64_t* __restrict__ ref, int64_t n_ref,
-                                                              int64_t n_points, int64_t n_lines,
+                                                              int64_t n_points, int64_t n_lines, int64_t min_seg,
                                                               int64_t* __restrict__ seg)
 {
     __shared__ int64_t red[3][kThreads];
@@ -54,9 +56,9 @@ __global__ __launch_bounds__(kThreads) void seg_length_kernel(const int64_t* __r
         sum = red[2][0];
         int64_t L = kNoSplit;
         if (sum > 0 && (busy < kBusyMin || mx * busy > kUneven * sum)) {
-            const double W = 512.0 * (double)sum + 8192.0 * (double)n_lines;
-            const double need = W / (2.0 * (double)n_points);
-            L = 256;
+            const double W = 512.0 * (double)sum + 4096.0 * (double)n_lines;
+            const double need = W / (4.0 * (double)n_points);
+            L = min_seg;
             while ((double)L < need && L < kNoSplit) L <<= 1;  // kNoSplit: not cut after all
         }
         seg[blockIdx.x] = L;
@@ -179,10 +181,12 @@ __global__ __launch_bounds__(kThreads) void plan_offset_kernel(int64_t n_pairs, 
 int64_t plan_scratch_count(int64_t n_pairs) { return 2 * std::max<int64_t>(1, (n_pairs + kPerBlock - 1) / kPerBlock); }
 
 hipError_t launch_seg_length(const int64_t* ref_ranges, int64_t n_ref, int32_t n_states, int64_t n_points,
-                             int64_t n_lines, int64_t* seg, hipStream_t s)
+                             int64_t n_lines, int64_t min_seg, int64_t* seg, hipStream_t s)
 {
     if (n_states <= 0) return hipSuccess;
-    seg_length_kernel<<<dim3((unsigned)n_states), dim3(kThreads), 0, s>>>(ref_ranges, n_ref, n_points, n_lines, seg);
+    if (min_seg < 1 || (min_seg & (min_seg - 1)) != 0) return hipErrorInvalidValue;
+    seg_length_kernel<<<dim3((unsigned)n_states), dim3(kThreads), 0, s>>>(ref_ranges, n_ref, n_points, n_lines,
+                                                                         min_seg, seg);
     return hipGetLastError();
 }
 

@@ -71,7 +71,7 @@ def test_split_lists_match_the_oracle(ctx, which):
         items, seg = ctx.get_option("wing_items"), ctx.get_option("wing_segment_lines")
         e = rel(k, ref)
         say("%s, precision %d: %d items, segments of %d lines, max rel err %.2e" % (which, prec, items, seg, e))
-        assert seg >= 256 and items > 586
+        assert seg >= 64 and items > 586
         assert e <= bar
     assert ctx.stats()["evals"] == n_evals
 
