@@ -365,7 +365,9 @@ def main(argv=None):
         "roofline": {"bound": "alu", "kernel": DOMINANT_KERNEL,
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(),
-                     "flops_per_launch": flops, "launch_ms": op_ms},
+                     "flops_per_launch": flops, "launch_ms": op_ms,
+                     "concurrent_with": "core_f64_kernel on a second stream (launch_ms includes "
+                                        "the time the two share the device)"},
     }
     if f32_tm is not None:
         f32_steps = max(1, a.steps // 2)

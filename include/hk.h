@@ -200,7 +200,12 @@ int hk_read_par(const char* path, int64_t first, int32_t molecule, const hk_line
  *   call certified take the learned surrogate instead of the series;
  *   HK_ENOTREADY without a certification.
  * accumulate != 0 adds to the values already in kappa, e.g. to process a
- * line list in chunks; accumulate == 0 overwrites them.  Asynchronous, except
+ * line list in chunks; accumulate == 0 overwrites them.  In binary64 the
+ * series terms are computed on a second non-blocking stream of the context,
+ * concurrently with the Gauss-Hermite terms, into a grid of its own that is
+ * then added to kappa on ctx's stream (fork and join by events, so the call
+ * stays ordered on ctx's stream and its results are those of adding in
+ * place).  Asynchronous, except
  * on grids above ~2e7 points, where each stage's work plan is read back once
  * (two stream synchronisations) to size its scratch. */
 int hk_opacity(hk_ctx* ctx, const hk_state* state, const hk_grid* grid,
@@ -392,9 +397,11 @@ int hk_get_option(hk_ctx* ctx, const char* name, int64_t* value);
  * of the last hk_tables call (synchronises the stream). */
 int hk_stats(hk_ctx* ctx, hk_run_stats* out);
 
-/* Per-stage device time, measured with HIP events recorded on the context's
- * stream around each kernel while timing is enabled, summed over calls since
- * the last reset.  Stage indices: */
+/* Per-stage device time, measured with HIP events recorded around each
+ * stage's kernels on the stream they run on while timing is enabled, summed
+ * over calls since the last reset.  In binary64 the series stage runs on a
+ * second stream, concurrently with the Gauss-Hermite stage, so the two
+ * overlap (each includes the time it shares the device).  Stage indices: */
 #define HK_STAGE_LINE_PREP 0  /* per-line S(T), widths, windows, tile ranges */
 #define HK_STAGE_OPACITY 1    /* Gauss-Hermite (a^2+u^2 >= 100) evaluation kernel */
 #define HK_STAGE_KDIST 2      /* per-bin sort and k(g) */

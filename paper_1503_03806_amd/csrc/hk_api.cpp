@@ -93,6 +93,11 @@ struct hk_ctx {
     DevBuf kscratch;
     // work plans of the wing and the series kernels
     PlanBufs wplan, cplan;
+    // binary64 series on a second stream, concurrent with the wing: its grid,
+    // the stream and the fork / join events
+    DevBuf kc;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // binary32 path: records, Kahan pair, scale
     DevBuf w32, c32, f32sum, f32comp, f32scale, f32partial;
     bool have_run = false;
@@ -233,18 +238,20 @@ hipEvent_t take_event(hk_ctx* ctx)
 struct StageTimer {
     hk_ctx* ctx;
     int stage;
+    hipStream_t strm;
     hipEvent_t a = nullptr, b = nullptr;
-    StageTimer(hk_ctx* c, int s) : ctx(c), stage(s)
+    StageTimer(hk_ctx* c, int s) : StageTimer(c, s, c->stream) {}
+    StageTimer(hk_ctx* c, int s, hipStream_t st) : ctx(c), stage(s), strm(st)
     {
         if (!ctx->timing) return;
         a = take_event(ctx);
         b = take_event(ctx);
-        if (a && b) (void)hipEventRecord(a, ctx->stream);
+        if (a && b) (void)hipEventRecord(a, strm);
     }
     void stop()
     {
         if (!a || !b) return;
-        (void)hipEventRecord(b, ctx->stream);
+        (void)hipEventRecord(b, strm);
         ctx->pending.push_back({stage, {a, b}});
         a = b = nullptr;
     }
@@ -543,7 +550,8 @@ constexpr int64_t kPlanBoundBytes = (int64_t)1 << 30;
 // kPlanBoundBytes: read the totals back (one host synchronisation) for
 // *items and the partial sums; else their bounds.
 int make_plan(hk_ctx* ctx, PlanBufs& pb, const int64_t* ranges, int64_t n_tiles, int32_t n_states,
-              const double* reach, int32_t tp, int64_t min_seg, const hk_grid* grid, bool exact, WorkPlan* wp)
+              const double* reach, int32_t tp, int64_t min_seg, const hk_grid* grid, bool exact, WorkPlan* wp,
+              hipStream_t strm)
 {
     const int64_t n = ctx->n_lines;
     const int32_t np = (int32_t)grid->n_points;
@@ -564,18 +572,18 @@ int make_plan(hk_ctx* ctx, PlanBufs& pb, const int64_t* ranges, int64_t n_tiles,
     const double* nu = lines_field(ctx, 0);
     for (int32_t s = 0; s < n_states; ++s)
         HK_HIP(ctx, launch_tile_ranges(nu, n, n_ref, kRefTilePoints, grid->nu_min, grid->dnu, np, reach[s],
-                                       ref + (int64_t)s * 2 * n_ref, ctx->stream),
+                                       ref + (int64_t)s * 2 * n_ref, strm),
                "tile_ranges");
-    HK_HIP(ctx, launch_seg_length(ref, n_ref, n_states, np, n, min_seg, seg, ctx->stream), "seg_length");
+    HK_HIP(ctx, launch_seg_length(ref, n_ref, n_states, np, n, min_seg, seg, strm), "seg_length");
     HK_HIP(ctx, launch_work_plan(ranges, n_tiles, n_states, seg, first, slot, static_cast<int64_t*>(pb.bsum.p), total,
-                                 ctx->stream),
+                                 strm),
            "work_plan");
     int64_t items = plan_items_bound(P, n_states);
     int64_t points = n_states * plan_partial_points_bound(np, tp);
     if (exact || points * 8 > kPlanBoundBytes) {
         int64_t h[2] = {0, 0};
-        HK_HIP(ctx, hipMemcpyAsync(h, total, sizeof h, hipMemcpyDeviceToHost, ctx->stream), "reading the work plan");
-        HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        HK_HIP(ctx, hipMemcpyAsync(h, total, sizeof h, hipMemcpyDeviceToHost, strm), "reading the work plan");
+        HK_HIP(ctx, hipStreamSynchronize(strm), "hipStreamSynchronize");
         items = h[0];
         points = h[1] * tp;
     }
@@ -597,7 +605,8 @@ int wing_stage(hk_ctx* ctx, int precision, int ppl, const void* recs, const Wing
     const int32_t tp = f64 ? opacity_f64_tile_points(ppl) : opacity_f32_tile_points(ppl);
     WorkPlan wp;
     // binary32: segments of whole 256-line compensation blocks
-    if (int rc = make_plan(ctx, ctx->wplan, ranges, n_tiles, n_states, reach, tp, f64 ? 64 : 256, grid, exact, &wp))
+    if (int rc = make_plan(ctx, ctx->wplan, ranges, n_tiles, n_states, reach, tp, f64 ? 64 : 256, grid, exact, &wp,
+                           ctx->stream))
         return rc;
     const int64_t n = ctx->n_lines;
     const int32_t np = (int32_t)grid->n_points;
@@ -615,27 +624,29 @@ int wing_stage(hk_ctx* ctx, int precision, int ppl, const void* recs, const Wing
 }
 
 // The series stage, the same way over the series tiles (ranges for the
-// series reach[s]); binary32 with surrogate/mask: the learned surrogate.
+// series reach[s]), on stream st; binary64 with store: out = the series sums
+// (a grid of its own); binary32 with surrogate/mask: the learned surrogate.
 int core_stage(hk_ctx* ctx, int precision, const void* wing, const WingIdx* idx, const void* core,
                const int64_t* ranges, int64_t n_tiles, int32_t n_states, const double* reach, const hk_grid* grid,
-               void* out, float* comp, const void* surrogate, const uint8_t* mask, bool exact)
+               void* out, float* comp, const void* surrogate, const uint8_t* mask, bool exact, int store,
+               hipStream_t st)
 {
     const bool f64 = precision == HK_F64;
     const int32_t tp = f64 ? core_f64_tile_points() : opacity_f32_tile_points(4);
     WorkPlan wp;
-    if (int rc = make_plan(ctx, ctx->cplan, ranges, n_tiles, n_states, reach, tp, 64, grid, exact, &wp))
+    if (int rc = make_plan(ctx, ctx->cplan, ranges, n_tiles, n_states, reach, tp, 64, grid, exact, &wp, st))
         return rc;
     const int64_t n = ctx->n_lines;
     const int32_t np = (int32_t)grid->n_points;
     if (f64)
         HK_HIP(ctx, launch_core_f64(static_cast<const WingRec*>(wing), idx, static_cast<const CoreRec*>(core), ranges, n,
                                     n_tiles, n_states, wp, grid->nu_min, grid->dnu, np, static_cast<double*>(out),
-                                    static_cast<double*>(ctx->cplan.partial.p), ctx->stream),
+                                    static_cast<double*>(ctx->cplan.partial.p), store, st),
                "core_f64");
     else
         HK_HIP(ctx, launch_core_f32(idx, static_cast<const CoreRec32*>(core), ranges, n, n_tiles, n_states, wp,
                                     np, static_cast<float*>(out), comp, static_cast<float*>(ctx->cplan.partial.p),
-                                    surrogate, mask, ctx->stream),
+                                    surrogate, mask, st),
                "core_f32");
     return HK_OK;
 }
@@ -843,6 +854,11 @@ int hk_destroy(hk_ctx* ctx)
     ctx->kscratch.release();
     ctx->wplan.release();
     ctx->cplan.release();
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+    ctx->kc.release();
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     for (DevBuf* b : {&ctx->w32, &ctx->c32, &ctx->f32sum, &ctx->f32comp, &ctx->f32scale, &ctx->f32partial})
         b->release();
     for (DevBuf* b : {&ctx->tb_idx, &ctx->tb_wing, &ctx->tb_core, &ctx->tb_w32, &ctx->tb_c32, &ctx->tb_ranges,
@@ -962,7 +978,8 @@ static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, double reach, double re
         StageTimer tm(ctx, HK_STAGE_CORE);
         if (int rc = core_stage(ctx, HK_F32_KAHAN, nullptr, widx, c32, ranges_c, n_tiles_c, 1, &reach_core, grid, fs,
                                 fc, surrogate ? ctx->sg_copy.p : nullptr,
-                                surrogate ? static_cast<const uint8_t*>(ctx->sg_mask.p) : nullptr, false))
+                                surrogate ? static_cast<const uint8_t*>(ctx->sg_mask.p) : nullptr, false, 0,
+                                ctx->stream))
             return rc;
         HK_HIP(ctx, launch_f32_finish(fs, fc, scale, np, kappa, accumulate, ctx->stream), "f32_finish");
         tm.stop();
@@ -1032,20 +1049,48 @@ static int opacity_run(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int
     if (precision != HK_F64)
         return opacity_f32(ctx, grid, reach, reach_core, wing, widx, core, ranges_c, n_tiles_c, kappa, accumulate,
                            precision == HK_F32_SURROGATE);
+    // The series runs on a second stream, concurrent with the wing (each
+    // leaves the VALU idle ~20% of the time, which the other fills), into a
+    // grid of its own; the join adds it to the wing's: kappa_j = wing_j +
+    // series_j, the same single addition as adding in place.  Both work plans
+    // are made first, on ctx's stream, so that only the two big kernels run
+    // side by side (small kernels queued behind a running one wait for CUs).
+    if (!ctx->side) {
+        HK_HIP(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking), "hipStreamCreate");
+        HK_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming), "hipEventCreate");
+        HK_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming), "hipEventCreate");
+    }
+    HK_HIP(ctx, ctx->kc.ensure((size_t)std::max(np, 1) * sizeof(double)), "allocating the series grid");
+    WorkPlan wwp, cwp;
+    {
+        StageTimer tm(ctx, HK_STAGE_LINE_PREP);
+        if (int rc = make_plan(ctx, ctx->wplan, ranges, n_tiles, 1, &reach, tp, 64, grid, false, &wwp, ctx->stream))
+            return rc;
+        if (int rc = make_plan(ctx, ctx->cplan, ranges_c, n_tiles_c, 1, &reach_core, tpc, 64, grid, false, &cwp,
+                               ctx->stream))
+            return rc;
+        tm.stop();
+    }
+    HK_HIP(ctx, hipEventRecord(ctx->ev_fork, ctx->stream), "hipEventRecord");
+    HK_HIP(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0), "hipStreamWaitEvent");
+    {
+        StageTimer tm(ctx, HK_STAGE_CORE, ctx->side);
+        HK_HIP(ctx, launch_core_f64(wing, widx, core, ranges_c, n, n_tiles_c, 1, cwp, grid->nu_min, grid->dnu, np,
+                                    static_cast<double*>(ctx->kc.p), static_cast<double*>(ctx->cplan.partial.p), 1,
+                                    ctx->side),
+               "core_f64");
+        tm.stop();
+    }
+    HK_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->side), "hipEventRecord");
     {
         StageTimer tm(ctx, HK_STAGE_OPACITY);
-        if (int rc = wing_stage(ctx, HK_F64, ppl, wing, widx, ranges, n_tiles, 1, &reach, grid, kappa, nullptr,
-                                accumulate ? 1 : 0, false))
-            return rc;
+        HK_HIP(ctx, launch_wing_f64(ppl, wing, widx, ranges, n, n_tiles, 1, wwp, grid->nu_min, grid->dnu, np, kappa,
+                                    static_cast<double*>(ctx->wplan.partial.p), accumulate ? 1 : 0, ctx->stream),
+               "wing_f64");
         tm.stop();
     }
-    {
-        StageTimer tm(ctx, HK_STAGE_CORE);
-        if (int rc = core_stage(ctx, HK_F64, wing, widx, core, ranges_c, n_tiles_c, 1, &reach_core, grid, kappa, nullptr,
-                                nullptr, nullptr, false))
-            return rc;
-        tm.stop();
-    }
+    HK_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "hipStreamWaitEvent");
+    HK_HIP(ctx, launch_add_f64(kappa, static_cast<const double*>(ctx->kc.p), np, ctx->stream), "add_f64");
     ctx->have_run = true;
     return HK_OK;
 }
@@ -1368,7 +1413,7 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
             StageTimer tm(ctx, HK_STAGE_CORE);
             if (int rc = core_stage(ctx, precision, ctx->tb_wing.p, tidx, f64 ? ctx->tb_core.p : ctx->tb_c32.p, rc_all,
                                     n_tiles_c, nbat, reach_c.data(), grid, ctx->tb_out.p,
-                                    static_cast<float*>(ctx->tb_comp.p), nullptr, nullptr, true))
+                                    static_cast<float*>(ctx->tb_comp.p), nullptr, nullptr, true, 0, ctx->stream))
                 return rc;
             tm.stop();
         }

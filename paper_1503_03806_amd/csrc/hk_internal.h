@@ -246,10 +246,14 @@ hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingI
                            double dnu, int32_t n_points, double* kappa, double* partial, int accumulate,
                            hipStream_t s);
 // The series items of n_states states (tiles of core_f64_tile_points(),
-// their own plan): kappa += the series sums; cut items write partial.
+// their own plan): kappa += the series sums, or with store kappa = them
+// (every point written; a grid of its own, added to the wing's afterwards);
+// cut items write partial.
 hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRec* core, const int64_t* ranges,
                            int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, double nu_min,
-                           double dnu, int32_t n_points, double* kappa, double* partial, hipStream_t s);
+                           double dnu, int32_t n_points, double* kappa, double* partial, int store, hipStream_t s);
+// a[j] += b[j], j < n.
+hipError_t launch_add_f64(double* a, const double* b, int32_t n, hipStream_t s);
 hipError_t launch_eval_counts(const WingIdx* idx, int64_t n_lines, int64_t* partial,
                               int32_t n_blocks, hipStream_t s);
 

@@ -367,13 +367,14 @@ __device__ double voigt_core(double x, double y, double ex, double T1, const dou
 // meet its run.  Those points form one contiguous interval [a, b]; lanes
 // take them 64 at a time, and each value moves to the lane owning its point
 // (a rotation of the wavefront) to be added there.  Lines [L0, L1) of tile t;
-// direct: kappa_j += the run's sum (points some line reaches); else every
+// direct: kappa_j += the run's sum (points some line reaches), or with store
+// kappa_j = the run's sum (every point, 0 where no line reaches); else every
 // point's sum to partial[j - obase].
 template <int kP>
 __device__ __forceinline__ void core_f64_tile(int64_t t, int64_t L0, int64_t L1, const WingRec* __restrict__ wing,
                                               const WingIdx* __restrict__ idx, const CoreRec* __restrict__ core,
                                               double nu_min, double dnu, int32_t n, double* __restrict__ kappa,
-                                              double* __restrict__ partial, int64_t obase, bool direct)
+                                              double* __restrict__ partial, int64_t obase, bool direct, bool store)
 {
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ double inv_tab[kWaves][kMaxTerms];
@@ -418,7 +419,13 @@ __device__ __forceinline__ void core_f64_tile(int64_t t, int64_t L0, int64_t L1,
         }
         __builtin_amdgcn_wave_barrier();
     }
-    if (direct) {
+    if (direct && store) {
+#pragma unroll
+        for (int p = 0; p < kP; ++p) {
+            const int32_t j = run0 + lane + 64 * p;
+            if (j <= run1) kappa[j] = acc[p];
+        }
+    } else if (direct) {
         if (!any) return;
 #pragma unroll
         for (int p = 0; p < kP; ++p) {
@@ -441,7 +448,7 @@ template <int kP>
 __global__ __launch_bounds__(64 * kWaves) void core_f64_kernel(
     const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx, const CoreRec* __restrict__ core,
     const int64_t* __restrict__ ranges, int64_t n_lines, int64_t n_tiles, int32_t n_states, WorkPlan wp,
-    double nu_min, double dnu, int32_t n, double* __restrict__ kappa, double* __restrict__ partial)
+    double nu_min, double dnu, int32_t n, double* __restrict__ kappa, double* __restrict__ partial, int store)
 {
     constexpr int64_t kTilePoints = 64 * kP * kWaves;
     WorkItem it;
@@ -450,14 +457,15 @@ __global__ __launch_bounds__(64 * kWaves) void core_f64_kernel(
         const bool direct = it.slot < 0;
         core_f64_tile<kP>(it.tile, it.lo, it.hi, wing + o, idx + o, core + o, nu_min, dnu, n,
                           kappa + it.st * (int64_t)n, partial + (direct ? 0 : it.slot * kTilePoints),
-                          it.tile * kTilePoints, direct);
+                          it.tile * kTilePoints, direct, store != 0);
     }
 }
 
-// Cut series tiles: kappa_j += the ordered sum of the tile's partials.
+// Cut series tiles: kappa_j += (store: =) the ordered sum of the tile's
+// partials.
 __global__ __launch_bounds__(256) void core_f64_reduce_kernel(WorkPlan wp, int64_t n_tiles, int32_t n_states,
                                                              int32_t tp, int32_t n, const double* __restrict__ partial,
-                                                             double* __restrict__ kappa)
+                                                             double* __restrict__ kappa, int store)
 {
     const int64_t total = wp.total[0];
     if (total == wp.n_pairs) return;  // nothing cut
@@ -474,7 +482,7 @@ __global__ __launch_bounds__(256) void core_f64_reduce_kernel(WorkPlan wp, int64
             if (j >= n) break;
             double v = 0.0;
             for (int64_t sg = 0; sg < nseg; ++sg) v += src[sg * tp + q];
-            dst[j] += v;
+            dst[j] = store ? v : dst[j] + v;
         }
     }
 }
@@ -519,17 +527,34 @@ hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingI
 
 hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRec* core, const int64_t* ranges,
                            int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, double nu_min,
-                           double dnu, int32_t n_points, double* kappa, double* partial, hipStream_t s)
+                           double dnu, int32_t n_points, double* kappa, double* partial, int store, hipStream_t s)
 {
     if (n_tiles == 0 || n_states == 0) return hipSuccess;
     const int64_t nb = plan_blocks(wp.launch_items);
     if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
     core_f64_kernel<4><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(wing, idx, core, ranges, n_lines, n_tiles,
                                                                        n_states, wp, nu_min, dnu, n_points, kappa,
-                                                                       partial);
+                                                                       partial, store);
     const int64_t nr = std::min<int64_t>(wp.n_pairs, 8192);
     core_f64_reduce_kernel<<<dim3((unsigned)nr), dim3(256), 0, s>>>(wp, n_tiles, n_states, core_f64_tile_points(),
-                                                                    n_points, partial, kappa);
+                                                                    n_points, partial, kappa, store);
+    return hipGetLastError();
+}
+
+namespace {
+
+__global__ __launch_bounds__(256) void add_f64_kernel(double* __restrict__ a, const double* __restrict__ b, int32_t n)
+{
+    const int32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j < n) a[j] += b[j];
+}
+
+}  // namespace
+
+hipError_t launch_add_f64(double* a, const double* b, int32_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    add_f64_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(a, b, n);
     return hipGetLastError();
 }
 
