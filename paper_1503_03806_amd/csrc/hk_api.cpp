@@ -107,7 +107,7 @@ struct hk_ctx {
     // per-state evaluation counters of the last call, and the tile shapes
     // chosen by timing, per (precision, lines, points, cutoff/dnu)
     DevBuf tb_idx, tb_wing, tb_core, tb_w32, tb_c32, tb_ranges, tb_ranges_c, tb_out, tb_comp, tb_scale, tb_kappa,
-        tb_counts;
+        tb_counts, tb_series;
     int64_t tables_batch = 0;  // states per launch; 0 = as many as fit in tables_mem
     int64_t tables_mem = (int64_t)32 << 30;
     int tables_autotune = 1;
@@ -623,31 +623,13 @@ int wing_stage(hk_ctx* ctx, int precision, int ppl, const void* recs, const Wing
     return HK_OK;
 }
 
-// The series stage, the same way over the series tiles (ranges for the
-// series reach[s]), on stream st; binary64 with store: out = the series sums
-// (a grid of its own); binary32 with surrogate/mask: the learned surrogate.
-int core_stage(hk_ctx* ctx, int precision, const void* wing, const WingIdx* idx, const void* core,
-               const int64_t* ranges, int64_t n_tiles, int32_t n_states, const double* reach, const hk_grid* grid,
-               void* out, float* comp, const void* surrogate, const uint8_t* mask, bool exact, int store,
-               hipStream_t st)
+// The second stream and its fork / join events, made on first use.
+int ensure_side(hk_ctx* ctx)
 {
-    const bool f64 = precision == HK_F64;
-    const int32_t tp = f64 ? core_f64_tile_points() : opacity_f32_tile_points(4);
-    WorkPlan wp;
-    if (int rc = make_plan(ctx, ctx->cplan, ranges, n_tiles, n_states, reach, tp, 64, grid, exact, &wp, st))
-        return rc;
-    const int64_t n = ctx->n_lines;
-    const int32_t np = (int32_t)grid->n_points;
-    if (f64)
-        HK_HIP(ctx, launch_core_f64(static_cast<const WingRec*>(wing), idx, static_cast<const CoreRec*>(core), ranges, n,
-                                    n_tiles, n_states, wp, grid->nu_min, grid->dnu, np, static_cast<double*>(out),
-                                    static_cast<double*>(ctx->cplan.partial.p), store, st),
-               "core_f64");
-    else
-        HK_HIP(ctx, launch_core_f32(idx, static_cast<const CoreRec32*>(core), ranges, n, n_tiles, n_states, wp,
-                                    np, static_cast<float*>(out), comp, static_cast<float*>(ctx->cplan.partial.p),
-                                    surrogate, mask, st),
-               "core_f32");
+    if (ctx->side) return HK_OK;
+    HK_HIP(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking), "hipStreamCreate");
+    HK_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming), "hipEventCreate");
+    HK_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming), "hipEventCreate");
     return HK_OK;
 }
 
@@ -863,7 +845,7 @@ int hk_destroy(hk_ctx* ctx)
         b->release();
     for (DevBuf* b : {&ctx->tb_idx, &ctx->tb_wing, &ctx->tb_core, &ctx->tb_w32, &ctx->tb_c32, &ctx->tb_ranges,
                       &ctx->tb_ranges_c, &ctx->tb_out, &ctx->tb_comp, &ctx->tb_scale, &ctx->tb_kappa,
-                      &ctx->tb_counts})
+                      &ctx->tb_counts, &ctx->tb_series})
         b->release();
     for (DevBuf* b : {&ctx->sg_theta, &ctx->sg_m, &ctx->sg_v, &ctx->sg_copy, &ctx->sg_part, &ctx->sg_ploss,
                       &ctx->sg_err, &ctx->sg_mask, &ctx->rs_Q, &ctx->rs_R, &ctx->rs_Ql, &ctx->rs_Rl, &ctx->rs_quad})
@@ -968,22 +950,42 @@ static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, double reach, double re
                "tile_ranges");
         tm.stop();
     }
+    // as in binary64: both plans, then the series on the second stream into
+    // its own grid while the wing runs; the finish adds it
+    if (int rc = ensure_side(ctx)) return rc;
+    HK_HIP(ctx, ctx->kc.ensure((size_t)std::max(np, 1) * sizeof(double)), "allocating the series grid");
+    float* series = static_cast<float*>(ctx->kc.p);
+    WorkPlan wwp, cwp;
+    {
+        StageTimer tm(ctx, HK_STAGE_LINE_PREP);
+        // segments of whole 256-line compensation blocks for the wing
+        if (int rc = make_plan(ctx, ctx->wplan, ranges, n_tiles, 1, &reach, tp, 256, grid, false, &wwp, ctx->stream))
+            return rc;
+        if (int rc = make_plan(ctx, ctx->cplan, ranges_c, n_tiles_c, 1, &reach_core, opacity_f32_tile_points(4), 64,
+                               grid, false, &cwp, ctx->stream))
+            return rc;
+        tm.stop();
+    }
+    HK_HIP(ctx, hipEventRecord(ctx->ev_fork, ctx->stream), "hipEventRecord");
+    HK_HIP(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0), "hipStreamWaitEvent");
+    {
+        StageTimer tm(ctx, HK_STAGE_CORE, ctx->side);
+        HK_HIP(ctx, launch_core_f32(widx, c32, ranges_c, n, n_tiles_c, 1, cwp, np, series,
+                                    static_cast<float*>(ctx->cplan.partial.p), surrogate ? ctx->sg_copy.p : nullptr,
+                                    surrogate ? static_cast<const uint8_t*>(ctx->sg_mask.p) : nullptr, ctx->side),
+               "core_f32");
+        tm.stop();
+    }
+    HK_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->side), "hipEventRecord");
     {
         StageTimer tm(ctx, HK_STAGE_OPACITY);
-        if (int rc = wing_stage(ctx, HK_F32_KAHAN, ppl, w32, widx, ranges, n_tiles, 1, &reach, grid, fs, fc, 0, false))
-            return rc;
+        HK_HIP(ctx, launch_wing_f32(ppl, w32, widx, ranges, n, n_tiles, 1, wwp, np, fs, fc,
+                                    static_cast<float2*>(ctx->wplan.partial.p), ctx->stream),
+               "wing_f32");
         tm.stop();
     }
-    {
-        StageTimer tm(ctx, HK_STAGE_CORE);
-        if (int rc = core_stage(ctx, HK_F32_KAHAN, nullptr, widx, c32, ranges_c, n_tiles_c, 1, &reach_core, grid, fs,
-                                fc, surrogate ? ctx->sg_copy.p : nullptr,
-                                surrogate ? static_cast<const uint8_t*>(ctx->sg_mask.p) : nullptr, false, 0,
-                                ctx->stream))
-            return rc;
-        HK_HIP(ctx, launch_f32_finish(fs, fc, scale, np, kappa, accumulate, ctx->stream), "f32_finish");
-        tm.stop();
-    }
+    HK_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "hipStreamWaitEvent");
+    HK_HIP(ctx, launch_f32_finish(fs, fc, series, scale, np, kappa, accumulate, ctx->stream), "f32_finish");
     ctx->have_run = true;
     return HK_OK;
 }
@@ -1055,11 +1057,7 @@ static int opacity_run(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int
     // series_j, the same single addition as adding in place.  Both work plans
     // are made first, on ctx's stream, so that only the two big kernels run
     // side by side (small kernels queued behind a running one wait for CUs).
-    if (!ctx->side) {
-        HK_HIP(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking), "hipStreamCreate");
-        HK_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming), "hipEventCreate");
-        HK_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming), "hipEventCreate");
-    }
+    if (int rc = ensure_side(ctx)) return rc;
     HK_HIP(ctx, ctx->kc.ensure((size_t)std::max(np, 1) * sizeof(double)), "allocating the series grid");
     WorkPlan wwp, cwp;
     {
@@ -1076,7 +1074,7 @@ static int opacity_run(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int
     {
         StageTimer tm(ctx, HK_STAGE_CORE, ctx->side);
         HK_HIP(ctx, launch_core_f64(wing, widx, core, ranges_c, n, n_tiles_c, 1, cwp, grid->nu_min, grid->dnu, np,
-                                    static_cast<double*>(ctx->kc.p), static_cast<double*>(ctx->cplan.partial.p), 1,
+                                    static_cast<double*>(ctx->kc.p), static_cast<double*>(ctx->cplan.partial.p),
                                     ctx->side),
                "core_f64");
         tm.stop();
@@ -1296,7 +1294,9 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
     // states per launch: the option, or as many as the memory budget holds
     const int64_t rec_bytes = f64 ? (int64_t)(sizeof(WingRec) + sizeof(WingIdx) + sizeof(CoreRec))
                                   : (int64_t)(sizeof(WingIdx) + sizeof(WingRec32) + sizeof(CoreRec32));
-    const int64_t per_state = n * rec_bytes + (ranges_per_state + 2 * n_tiles_c) * 8 + (int64_t)np * 8;
+    // records, tile ranges, the opacity grid and the series grid (binary32:
+    // sums, compensations and series in binary32)
+    const int64_t per_state = n * rec_bytes + (ranges_per_state + 2 * n_tiles_c) * 8 + (int64_t)np * (f64 ? 16 : 12);
     int64_t B = ctx->tables_batch > 0 ? ctx->tables_batch : std::max<int64_t>(1, ctx->tables_mem / per_state);
     B = std::min<int64_t>(B, n_states);
     const int64_t n_batches = (n_states + B - 1) / B;
@@ -1320,6 +1320,8 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
     }
     HK_HIP(ctx, ctx->tb_out.ensure((size_t)B * np * (f64 ? sizeof(double) : sizeof(float))),
            "allocating batch opacities");
+    HK_HIP(ctx, ctx->tb_series.ensure((size_t)B * np * (f64 ? sizeof(double) : sizeof(float))),
+           "allocating batch series grids");
     HK_HIP(ctx, ctx->tb_ranges.ensure((size_t)B * ranges_per_state * sizeof(int64_t)), "allocating tile ranges");
     HK_HIP(ctx, ctx->tb_ranges_c.ensure((size_t)B * 2 * n_tiles_c * sizeof(int64_t)), "allocating tile ranges");
     HK_HIP(ctx, ctx->tb_counts.ensure((size_t)n_states * kCountBlocks * 3 * sizeof(int64_t)),
@@ -1395,28 +1397,65 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
         const int32_t tp = f64 ? opacity_f64_tile_points(ppl) : opacity_f32_tile_points(ppl);
         const int64_t n_tiles = ((int64_t)np + tp - 1) / tp;
         int64_t* rw = static_cast<int64_t*>(ctx->tb_ranges.p);
+        std::vector<double> reach((size_t)nbat);
+        for (int32_t s = 0; s < nbat; ++s) reach[(size_t)s] = wing_reach(ctx, &states[b0 + s], grid);
+        WorkPlan wwp, cwp;
+        {
+            StageTimer tm(ctx, HK_STAGE_LINE_PREP);
+            for (int32_t s = 0; s < nbat; ++s)
+                HK_HIP(ctx, launch_tile_ranges(L.nu, n, n_tiles, tp, grid->nu_min, grid->dnu, np, reach[(size_t)s],
+                                               rw + (int64_t)s * 2 * n_tiles, ctx->stream),
+                       "tile_ranges");
+            // the plans of the whole batch, read back to size the launches
+            if (int rc = make_plan(ctx, ctx->wplan, rw, n_tiles, nbat, reach.data(), tp, f64 ? 64 : 256, grid, true,
+                                   &wwp, ctx->stream))
+                return rc;
+            if (int rc = make_plan(ctx, ctx->cplan, rc_all, n_tiles_c, nbat, reach_c.data(), tpc, 64, grid, true, &cwp,
+                                   ctx->stream))
+                return rc;
+            tm.stop();
+        }
+        // the series of the batch on the second stream, into its own grids,
+        // while the wing runs
+        if (int rc = ensure_side(ctx)) return rc;
+        HK_HIP(ctx, hipEventRecord(ctx->ev_fork, ctx->stream), "hipEventRecord");
+        HK_HIP(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0), "hipStreamWaitEvent");
+        {
+            StageTimer tm(ctx, HK_STAGE_CORE, ctx->side);
+            if (f64)
+                HK_HIP(ctx, launch_core_f64(static_cast<WingRec*>(ctx->tb_wing.p), tidx,
+                                            static_cast<CoreRec*>(ctx->tb_core.p), rc_all, n, n_tiles_c, nbat, cwp,
+                                            grid->nu_min, grid->dnu, np, static_cast<double*>(ctx->tb_series.p),
+                                            static_cast<double*>(ctx->cplan.partial.p), ctx->side),
+                       "core_f64");
+            else
+                HK_HIP(ctx, launch_core_f32(tidx, static_cast<CoreRec32*>(ctx->tb_c32.p), rc_all, n, n_tiles_c, nbat,
+                                            cwp, np, static_cast<float*>(ctx->tb_series.p),
+                                            static_cast<float*>(ctx->cplan.partial.p), nullptr, nullptr, ctx->side),
+                       "core_f32");
+            tm.stop();
+        }
+        HK_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->side), "hipEventRecord");
         {
             StageTimer tm(ctx, HK_STAGE_OPACITY);
-            for (int32_t s = 0; s < nbat; ++s)
-                HK_HIP(ctx, launch_tile_ranges(L.nu, n, n_tiles, tp, grid->nu_min, grid->dnu, np,
-                                               wing_reach(ctx, &states[b0 + s], grid), rw + (int64_t)s * 2 * n_tiles,
-                                               ctx->stream),
-                       "tile_ranges");
-            std::vector<double> reach((size_t)nbat);
-            for (int32_t s = 0; s < nbat; ++s) reach[(size_t)s] = wing_reach(ctx, &states[b0 + s], grid);
-            if (int rc = wing_stage(ctx, precision, ppl, f64 ? ctx->tb_wing.p : ctx->tb_w32.p, tidx, rw, n_tiles, nbat,
-                                    reach.data(), grid, ctx->tb_out.p, static_cast<float*>(ctx->tb_comp.p), 0, true))
-                return rc;
+            if (f64)
+                HK_HIP(ctx, launch_wing_f64(ppl, static_cast<WingRec*>(ctx->tb_wing.p), tidx, rw, n, n_tiles, nbat, wwp,
+                                            grid->nu_min, grid->dnu, np, static_cast<double*>(ctx->tb_out.p),
+                                            static_cast<double*>(ctx->wplan.partial.p), 0, ctx->stream),
+                       "wing_f64");
+            else
+                HK_HIP(ctx, launch_wing_f32(ppl, static_cast<WingRec32*>(ctx->tb_w32.p), tidx, rw, n, n_tiles, nbat,
+                                            wwp, np, static_cast<float*>(ctx->tb_out.p),
+                                            static_cast<float*>(ctx->tb_comp.p),
+                                            static_cast<float2*>(ctx->wplan.partial.p), ctx->stream),
+                       "wing_f32");
             tm.stop();
         }
-        {
-            StageTimer tm(ctx, HK_STAGE_CORE);
-            if (int rc = core_stage(ctx, precision, ctx->tb_wing.p, tidx, f64 ? ctx->tb_core.p : ctx->tb_c32.p, rc_all,
-                                    n_tiles_c, nbat, reach_c.data(), grid, ctx->tb_out.p,
-                                    static_cast<float*>(ctx->tb_comp.p), nullptr, nullptr, true, 0, ctx->stream))
-                return rc;
-            tm.stop();
-        }
+        HK_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "hipStreamWaitEvent");
+        if (f64)
+            HK_HIP(ctx, launch_add_f64(static_cast<double*>(ctx->tb_out.p), static_cast<double*>(ctx->tb_series.p),
+                                       (int64_t)nbat * np, ctx->stream),
+                   "add_f64");
         {
             StageTimer tm(ctx, HK_STAGE_KDIST);
             for (int32_t s = 0; s < nbat; ++s) {
@@ -1427,6 +1466,7 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
                     double* kk = static_cast<double*>(ctx->tb_kappa.p);
                     HK_HIP(ctx, launch_f32_finish(static_cast<float*>(ctx->tb_out.p) + (int64_t)s * np,
                                                   static_cast<float*>(ctx->tb_comp.p) + (int64_t)s * np,
+                                                  static_cast<float*>(ctx->tb_series.p) + (int64_t)s * np,
                                                   static_cast<int32_t*>(ctx->tb_scale.p) + s, np, kk, 0, ctx->stream),
                            "f32_finish");
                     kap = kk;

@@ -246,14 +246,14 @@ hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingI
                            double dnu, int32_t n_points, double* kappa, double* partial, int accumulate,
                            hipStream_t s);
 // The series items of n_states states (tiles of core_f64_tile_points(),
-// their own plan): kappa += the series sums, or with store kappa = them
-// (every point written; a grid of its own, added to the wing's afterwards);
-// cut items write partial.
+// their own plan): series = the series sums, every point written (a grid of
+// its own, n_points per state, added to the wing's afterwards, so that the
+// two kernels can run at the same time); cut items write partial.
 hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRec* core, const int64_t* ranges,
                            int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, double nu_min,
-                           double dnu, int32_t n_points, double* kappa, double* partial, int store, hipStream_t s);
+                           double dnu, int32_t n_points, double* series, double* partial, hipStream_t s);
 // a[j] += b[j], j < n.
-hipError_t launch_add_f64(double* a, const double* b, int32_t n, hipStream_t s);
+hipError_t launch_add_f64(double* a, const double* b, int64_t n, hipStream_t s);
 hipError_t launch_eval_counts(const WingIdx* idx, int64_t n_lines, int64_t* partial,
                               int32_t n_blocks, hipStream_t s);
 
@@ -270,16 +270,18 @@ int32_t opacity_f32_tile_points(int points_per_lane);
 hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const WingIdx* idx, const int64_t* ranges,
                            int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int32_t n_points,
                            float* sum, float* comp, float2* partial, hipStream_t s);
-// The series items (tiles of opacity_f32_tile_points(4)): the Kahan pairs
-// += the series sums; surrogate (the bfloat16 parameter copy, single state):
-// the learned surrogate in the cells `mask` certifies.
+// The series items (tiles of opacity_f32_tile_points(4)): series = the
+// binary32 series sums, every point written (added to the wing's Kahan pairs
+// by launch_f32_finish); surrogate (the bfloat16 parameter copy, single
+// state): the learned surrogate in the cells `mask` certifies.
 hipError_t launch_core_f32(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges, int64_t n_lines,
-                           int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int32_t n_points, float* sum,
-                           float* comp, float* partial, const void* surrogate, const uint8_t* mask, hipStream_t s);
+                           int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int32_t n_points, float* series,
+                           float* partial, const void* surrogate, const uint8_t* mask, hipStream_t s);
 
 
-// kappa (binary64) = (sum + comp) * 2^-s, or += when accumulating.
-hipError_t launch_f32_finish(const float* sum, const float* comp, const int32_t* scale,
+// kappa (binary64) = (the Kahan pair (sum, comp) with the series sum, when
+// not zero, Kahan-added) * 2^-s, or += when accumulating; series may be NULL.
+hipError_t launch_f32_finish(const float* sum, const float* comp, const float* series, const int32_t* scale,
                              int32_t n_points, double* kappa, int accumulate, hipStream_t s);
 
 // k-distribution.  elem_bytes 8 (binary64 keys) or 4 (binary32 keys).

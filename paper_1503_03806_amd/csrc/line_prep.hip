@@ -286,15 +286,27 @@ __global__ __launch_bounds__(256) void line_prep_f32_kernel(
     c32[i] = k;
 }
 
+// The wing's Kahan pair (sum, comp) of each point; the series sum, when not
+// zero, Kahan-added to it (value = s - c, c the running correction); then
+// scaled back into binary64.
 __global__ __launch_bounds__(256) void f32_finish_kernel(const float* __restrict__ sum,
                                                          const float* __restrict__ comp,
+                                                         const float* __restrict__ series,
                                                          const int32_t* __restrict__ scale,
                                                          int32_t n, double* __restrict__ kappa,
                                                          int accumulate)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const double v = ldexp((double)sum[j] + (double)comp[j], -scale[0]);
+    float s = sum[j], c = -comp[j];
+    const float x = series ? series[j] : 0.0f;
+    if (x != 0.0f) {
+        const float y = x - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    const double v = ldexp((double)s - (double)c, -scale[0]);
     kappa[j] = accumulate ? kappa[j] + v : v;
 }
 
@@ -319,12 +331,12 @@ hipError_t launch_line_prep_f32(const WingRec* wing, WingIdx* idx, const CoreRec
     return hipGetLastError();
 }
 
-hipError_t launch_f32_finish(const float* sum, const float* comp, const int32_t* scale,
+hipError_t launch_f32_finish(const float* sum, const float* comp, const float* series, const int32_t* scale,
                              int32_t n_points, double* kappa, int accumulate, hipStream_t s)
 {
     if (n_points == 0) return hipSuccess;
     const int64_t blocks = ((int64_t)n_points + 255) / 256;
-    f32_finish_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(sum, comp, scale, n_points, kappa,
+    f32_finish_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(sum, comp, series, scale, n_points, kappa,
                                                                     accumulate);
     return hipGetLastError();
 }

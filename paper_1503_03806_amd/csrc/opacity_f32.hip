@@ -281,16 +281,17 @@ __device__ float voigt_core_f32(float x, float y, float ex, float T1, const floa
 
 // Core-region terms: as core_f64_kernel (point ownership, compacted 64-point
 // chunks of the line's core interval, lane rotation); the run's ordered
-// binary32 core sum is added to the Kahan pair written by the wing kernel.
+// binary32 series sums go to a grid of their own, which the finish adds to
+// the wing's Kahan pairs (so the two kernels can run at the same time).
 // With kSurr, points of certified (x, y) cells take the learned surrogate
 // instead of the series (the wavefront runs the network when any of its
 // lanes needs it, the series when any needs that).  Lines [L0, L1) of tile
-// t; direct: the Kahan pair update; else every point's binary32 sum to
-// partial[j - obase].
+// t; direct: series_j = the run's sum (every point, 0 where no line
+// reaches); else every point's sum to partial[j - obase].
 template <int kP, bool kSurr = false>
 __device__ __forceinline__ void core_f32_tile(int64_t t, int64_t L0, int64_t L1, const WingIdx* __restrict__ idx,
-                                              const CoreRec32* __restrict__ core, int32_t n, float* __restrict__ sum,
-                                              float* __restrict__ comp, float* __restrict__ partial, int64_t obase,
+                                              const CoreRec32* __restrict__ core, int32_t n,
+                                              float* __restrict__ series, float* __restrict__ partial, int64_t obase,
                                               bool direct, const surr::MlpBf16* __restrict__ P,
                                               const uint8_t* __restrict__ mask)
 {
@@ -306,13 +307,11 @@ __device__ __forceinline__ void core_f32_tile(int64_t t, int64_t L0, int64_t L1,
     float acc[kP];
 #pragma unroll
     for (int p = 0; p < kP; ++p) acc[p] = 0.0f;
-    bool any = false;
 
     for (int64_t i = L0; i < L1; ++i) {
         const int32_t a = max(max(idx[i].clo, idx[i].wlo), run0);
         const int32_t b = min(min(idx[i].chi, idx[i].whi), run1);
         if (a > b) continue;
-        any = true;
         const int32_t jc = idx[i].jc;
         const CoreRec32 cr = core[i];
         if (lane < kMaxTerms) {
@@ -348,23 +347,14 @@ __device__ __forceinline__ void core_f32_tile(int64_t t, int64_t L0, int64_t L1,
         }
         __builtin_amdgcn_wave_barrier();
     }
-    if (!direct) {
-#pragma unroll
-        for (int p = 0; p < kP; ++p) {
-            const int32_t j = run0 + lane + 64 * p;
-            if (j <= run1) partial[j - obase] = acc[p];
-        }
-        return;
-    }
-    if (!any) return;
 #pragma unroll
     for (int p = 0; p < kP; ++p) {
         const int32_t j = run0 + lane + 64 * p;
         if (j <= run1) {
-            float sv = sum[j], cv = -comp[j];
-            kahan_add(sv, cv, acc[p]);
-            sum[j] = sv;
-            comp[j] = -cv;
+            if (direct)
+                series[j] = acc[p];
+            else
+                partial[j - obase] = acc[p];
         }
     }
 }
@@ -375,26 +365,25 @@ __device__ __forceinline__ void core_f32_tile(int64_t t, int64_t L0, int64_t L1,
 template <int kP, bool kSurr>
 __global__ __launch_bounds__(64 * kWaves) void core_f32_kernel(
     const WingIdx* __restrict__ idx, const CoreRec32* __restrict__ core, const int64_t* __restrict__ ranges,
-    int64_t n_lines, int64_t n_tiles, int32_t n_states, WorkPlan wp, int32_t n, float* __restrict__ sum,
-    float* __restrict__ comp, float* __restrict__ partial, const surr::MlpBf16* __restrict__ P,
-    const uint8_t* __restrict__ mask)
+    int64_t n_lines, int64_t n_tiles, int32_t n_states, WorkPlan wp, int32_t n, float* __restrict__ series,
+    float* __restrict__ partial, const surr::MlpBf16* __restrict__ P, const uint8_t* __restrict__ mask)
 {
     constexpr int64_t kTilePoints = 64 * kP * kWaves;
     WorkItem it;
     if (work_item(blockIdx.x, wp, ranges, n_tiles, n_states, it)) {
         const int64_t o = it.st * n_lines, so = it.st * (int64_t)n;
         const bool direct = it.slot < 0;
-        core_f32_tile<kP, kSurr>(it.tile, it.lo, it.hi, idx + o, core + o, n, sum + so, comp + so,
+        core_f32_tile<kP, kSurr>(it.tile, it.lo, it.hi, idx + o, core + o, n, series + so,
                                  partial + (direct ? 0 : it.slot * kTilePoints), it.tile * kTilePoints, direct, P,
                                  mask);
     }
 }
 
-// Cut series tiles: each point's partials summed in segment order in
-// binary32, then added to its Kahan pair (a zero sum is not added).
+// Cut series tiles: series_j = the partials summed in segment order in
+// binary32.
 __global__ __launch_bounds__(256) void core_f32_reduce_kernel(WorkPlan wp, int64_t n_tiles, int32_t n_states,
                                                              int32_t tp, int32_t n, const float* __restrict__ partial,
-                                                             float* __restrict__ sum, float* __restrict__ comp)
+                                                             float* __restrict__ series)
 {
     const int64_t total = wp.total[0];
     if (total == wp.n_pairs) return;  // nothing cut
@@ -410,12 +399,7 @@ __global__ __launch_bounds__(256) void core_f32_reduce_kernel(WorkPlan wp, int64
             if (j >= n) break;
             float v = 0.0f;
             for (int64_t sg = 0; sg < nseg; ++sg) v += src[sg * tp + q];
-            if (v == 0.0f) continue;
-            const int64_t o = st * (int64_t)n + j;
-            float sv = sum[o], cv = -comp[o];
-            kahan_add(sv, cv, v);
-            sum[o] = sv;
-            comp[o] = -cv;
+            series[st * (int64_t)n + j] = v;
         }
     }
 }
@@ -453,8 +437,8 @@ hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const Win
 }
 
 hipError_t launch_core_f32(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges, int64_t n_lines,
-                           int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int32_t n_points, float* sum,
-                           float* comp, float* partial, const void* surrogate, const uint8_t* mask, hipStream_t s)
+                           int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int32_t n_points, float* series,
+                           float* partial, const void* surrogate, const uint8_t* mask, hipStream_t s)
 {
     if (n_tiles == 0 || n_states == 0) return hipSuccess;
     if (surrogate && n_states != 1) return hipErrorInvalidValue;
@@ -463,13 +447,13 @@ hipError_t launch_core_f32(const WingIdx* idx, const CoreRec32* core, const int6
     const auto* P = static_cast<const surr::MlpBf16*>(surrogate);
     if (surrogate)
         core_f32_kernel<4, true><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(
-            idx, core, ranges, n_lines, n_tiles, n_states, wp, n_points, sum, comp, partial, P, mask);
+            idx, core, ranges, n_lines, n_tiles, n_states, wp, n_points, series, partial, P, mask);
     else
         core_f32_kernel<4, false><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(
-            idx, core, ranges, n_lines, n_tiles, n_states, wp, n_points, sum, comp, partial, nullptr, nullptr);
+            idx, core, ranges, n_lines, n_tiles, n_states, wp, n_points, series, partial, nullptr, nullptr);
     const int64_t nr = std::min<int64_t>(wp.n_pairs, 8192);
     core_f32_reduce_kernel<<<dim3((unsigned)nr), dim3(256), 0, s>>>(wp, n_tiles, n_states, 64 * 4 * kWaves,
-                                                                    n_points, partial, sum, comp);
+                                                                    n_points, partial, series);
     return hipGetLastError();
 }
 

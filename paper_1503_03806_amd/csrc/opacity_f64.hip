@@ -367,14 +367,15 @@ __device__ double voigt_core(double x, double y, double ex, double T1, const dou
 // meet its run.  Those points form one contiguous interval [a, b]; lanes
 // take them 64 at a time, and each value moves to the lane owning its point
 // (a rotation of the wavefront) to be added there.  Lines [L0, L1) of tile t;
-// direct: kappa_j += the run's sum (points some line reaches), or with store
-// kappa_j = the run's sum (every point, 0 where no line reaches); else every
-// point's sum to partial[j - obase].
+// direct: series_j = the run's sum (every point, 0 where no line reaches);
+// else every point's sum to partial[j - obase].  The series has a grid of
+// its own, added to the wing's afterwards (the two kernels can then run at
+// the same time).
 template <int kP>
 __device__ __forceinline__ void core_f64_tile(int64_t t, int64_t L0, int64_t L1, const WingRec* __restrict__ wing,
                                               const WingIdx* __restrict__ idx, const CoreRec* __restrict__ core,
-                                              double nu_min, double dnu, int32_t n, double* __restrict__ kappa,
-                                              double* __restrict__ partial, int64_t obase, bool direct, bool store)
+                                              double nu_min, double dnu, int32_t n, double* __restrict__ series,
+                                              double* __restrict__ partial, int64_t obase, bool direct)
 {
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ double inv_tab[kWaves][kMaxTerms];
@@ -387,13 +388,11 @@ __device__ __forceinline__ void core_f64_tile(int64_t t, int64_t L0, int64_t L1,
     double acc[kP];
 #pragma unroll
     for (int p = 0; p < kP; ++p) acc[p] = 0.0;
-    bool any = false;
 
     for (int64_t i = L0; i < L1; ++i) {
         const int32_t a = max(max(idx[i].clo, idx[i].wlo), run0);
         const int32_t b = min(min(idx[i].chi, idx[i].whi), run1);
         if (a > b) continue;
-        any = true;
         const double nu0 = wing[i].nu0;
         const CoreRec cr = core[i];
         if (lane < kMaxTerms) {
@@ -419,18 +418,11 @@ __device__ __forceinline__ void core_f64_tile(int64_t t, int64_t L0, int64_t L1,
         }
         __builtin_amdgcn_wave_barrier();
     }
-    if (direct && store) {
+    if (direct) {
 #pragma unroll
         for (int p = 0; p < kP; ++p) {
             const int32_t j = run0 + lane + 64 * p;
-            if (j <= run1) kappa[j] = acc[p];
-        }
-    } else if (direct) {
-        if (!any) return;
-#pragma unroll
-        for (int p = 0; p < kP; ++p) {
-            const int32_t j = run0 + lane + 64 * p;
-            if (j <= run1) kappa[j] += acc[p];
+            if (j <= run1) series[j] = acc[p];
         }
     } else {
 #pragma unroll
@@ -448,7 +440,7 @@ template <int kP>
 __global__ __launch_bounds__(64 * kWaves) void core_f64_kernel(
     const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx, const CoreRec* __restrict__ core,
     const int64_t* __restrict__ ranges, int64_t n_lines, int64_t n_tiles, int32_t n_states, WorkPlan wp,
-    double nu_min, double dnu, int32_t n, double* __restrict__ kappa, double* __restrict__ partial, int store)
+    double nu_min, double dnu, int32_t n, double* __restrict__ series, double* __restrict__ partial)
 {
     constexpr int64_t kTilePoints = 64 * kP * kWaves;
     WorkItem it;
@@ -456,16 +448,15 @@ __global__ __launch_bounds__(64 * kWaves) void core_f64_kernel(
         const int64_t o = it.st * n_lines;
         const bool direct = it.slot < 0;
         core_f64_tile<kP>(it.tile, it.lo, it.hi, wing + o, idx + o, core + o, nu_min, dnu, n,
-                          kappa + it.st * (int64_t)n, partial + (direct ? 0 : it.slot * kTilePoints),
-                          it.tile * kTilePoints, direct, store != 0);
+                          series + it.st * (int64_t)n, partial + (direct ? 0 : it.slot * kTilePoints),
+                          it.tile * kTilePoints, direct);
     }
 }
 
-// Cut series tiles: kappa_j += (store: =) the ordered sum of the tile's
-// partials.
+// Cut series tiles: series_j = the ordered sum of the tile's partials.
 __global__ __launch_bounds__(256) void core_f64_reduce_kernel(WorkPlan wp, int64_t n_tiles, int32_t n_states,
                                                              int32_t tp, int32_t n, const double* __restrict__ partial,
-                                                             double* __restrict__ kappa, int store)
+                                                             double* __restrict__ series)
 {
     const int64_t total = wp.total[0];
     if (total == wp.n_pairs) return;  // nothing cut
@@ -476,13 +467,13 @@ __global__ __launch_bounds__(256) void core_f64_reduce_kernel(WorkPlan wp, int64
         pair_decode(p, n_tiles, n_states, st, k);
         const int64_t j0 = (n_tiles - 1 - k) * tp;
         const double* src = partial + wp.slot[p] * tp;
-        double* dst = kappa + st * (int64_t)n;
+        double* dst = series + st * (int64_t)n;
         for (int q = threadIdx.x; q < tp; q += blockDim.x) {
             const int64_t j = j0 + q;
             if (j >= n) break;
             double v = 0.0;
             for (int64_t sg = 0; sg < nseg; ++sg) v += src[sg * tp + q];
-            dst[j] = store ? v : dst[j] + v;
+            dst[j] = v;
         }
     }
 }
@@ -527,33 +518,34 @@ hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingI
 
 hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRec* core, const int64_t* ranges,
                            int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, double nu_min,
-                           double dnu, int32_t n_points, double* kappa, double* partial, int store, hipStream_t s)
+                           double dnu, int32_t n_points, double* series, double* partial, hipStream_t s)
 {
     if (n_tiles == 0 || n_states == 0) return hipSuccess;
     const int64_t nb = plan_blocks(wp.launch_items);
     if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
     core_f64_kernel<4><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(wing, idx, core, ranges, n_lines, n_tiles,
-                                                                       n_states, wp, nu_min, dnu, n_points, kappa,
-                                                                       partial, store);
+                                                                       n_states, wp, nu_min, dnu, n_points, series,
+                                                                       partial);
     const int64_t nr = std::min<int64_t>(wp.n_pairs, 8192);
     core_f64_reduce_kernel<<<dim3((unsigned)nr), dim3(256), 0, s>>>(wp, n_tiles, n_states, core_f64_tile_points(),
-                                                                    n_points, partial, kappa, store);
+                                                                    n_points, partial, series);
     return hipGetLastError();
 }
 
 namespace {
 
-__global__ __launch_bounds__(256) void add_f64_kernel(double* __restrict__ a, const double* __restrict__ b, int32_t n)
+__global__ __launch_bounds__(256) void add_f64_kernel(double* __restrict__ a, const double* __restrict__ b, int64_t n)
 {
-    const int32_t j = blockIdx.x * 256 + threadIdx.x;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j < n) a[j] += b[j];
 }
 
 }  // namespace
 
-hipError_t launch_add_f64(double* a, const double* b, int32_t n, hipStream_t s)
+hipError_t launch_add_f64(double* a, const double* b, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
+    if ((n + 255) / 256 > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
     add_f64_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(a, b, n);
     return hipGetLastError();
 }
