@@ -191,8 +191,9 @@ int hk_read_par(const char* path, int64_t first, int32_t molecule, const hk_line
  * precision HK_F64: every step in binary64.
  * precision HK_F32_KAHAN: S(T), widths, windows and region intervals in
  *   binary64; profiles in binary32 with strengths scaled by a per-state power
- *   of two; each point's terms summed in binary32 blocks of at most 256 lines
- *   whose sums are added with Kahan compensation; the compensated sum is
+ *   of two; each point's Gauss-Hermite terms summed in binary32 blocks of at
+ *   most 256 lines whose sums are added with Kahan compensation, its series
+ *   terms summed in binary32 and then Kahan-added; the compensated sum is
  *   scaled back and stored in binary64.  Requires cutoff/dnu < 2^23 (for a
  *   Lorentz-width cutoff: cutoff_lorentz * max Gamma_L / dnu < 2^23).
  * precision HK_F32_SURROGATE: as HK_F32_KAHAN, except that series-region
@@ -200,12 +201,11 @@ int hk_read_par(const char* path, int64_t first, int32_t molecule, const hk_line
  *   call certified take the learned surrogate instead of the series;
  *   HK_ENOTREADY without a certification.
  * accumulate != 0 adds to the values already in kappa, e.g. to process a
- * line list in chunks; accumulate == 0 overwrites them.  In binary64 the
- * series terms are computed on a second non-blocking stream of the context,
- * concurrently with the Gauss-Hermite terms, into a grid of its own that is
- * then added to kappa on ctx's stream (fork and join by events, so the call
- * stays ordered on ctx's stream and its results are those of adding in
- * place).  Asynchronous, except
+ * line list in chunks; accumulate == 0 overwrites them.  The series terms
+ * are computed on a second non-blocking stream of the context, concurrently
+ * with the Gauss-Hermite terms, into a grid of their own that is then added
+ * on ctx's stream (fork and join by events, so the call stays ordered on
+ * ctx's stream; hk_tables does the same per batch).  Asynchronous, except
  * on grids above ~2e7 points, where each stage's work plan is read back once
  * (two stream synchronisations) to size its scratch. */
 int hk_opacity(hk_ctx* ctx, const hk_state* state, const hk_grid* grid,
@@ -399,9 +399,10 @@ int hk_stats(hk_ctx* ctx, hk_run_stats* out);
 
 /* Per-stage device time, measured with HIP events recorded around each
  * stage's kernels on the stream they run on while timing is enabled, summed
- * over calls since the last reset.  In binary64 the series stage runs on a
- * second stream, concurrently with the Gauss-Hermite stage, so the two
- * overlap (each includes the time it shares the device).  Stage indices: */
+ * over calls since the last reset.  The series stage runs on a second
+ * stream, concurrently with the Gauss-Hermite stage, so the two overlap
+ * (each includes the time it shares the device); the line-preparation stage
+ * includes the tile ranges and work plans.  Stage indices: */
 #define HK_STAGE_LINE_PREP 0  /* per-line S(T), widths, windows, tile ranges */
 #define HK_STAGE_OPACITY 1    /* Gauss-Hermite (a^2+u^2 >= 100) evaluation kernel */
 #define HK_STAGE_KDIST 2      /* per-bin sort and k(g) */
