@@ -362,6 +362,8 @@ def main(argv=None):
                    "evals_per_step": evals, "evals_core": st["evals_core"],
                    "evals_gh3": st["evals_gh3"], "evals_gh1": st["evals_gh1"]},
         "stage_ms": {k: v[0] / max(v[1], 1) for k, v in tm.items()},
+        "stage_note": "event-timed mean per timed launch; 'opacity' (wing) and 'core' (series) run concurrently "
+                      "on two streams and overlap; 'line_prep' includes tile ranges and work plans",
         "roofline": {"bound": "alu", "kernel": DOMINANT_KERNEL,
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(),

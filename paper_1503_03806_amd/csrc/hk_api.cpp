@@ -943,7 +943,7 @@ static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, double reach, double re
                                              ctx->stream),
                    "line_prep_f32");
         } else {
-            HK_HIP(ctx, hipMemsetAsync(scale, 0, sizeof(int32_t), ctx->stream), "hipMemsetAsync");
+            HK_HIP(ctx, launch_zero(scale, sizeof(int32_t), ctx->stream), "zero");
         }
         HK_HIP(ctx, launch_tile_ranges(static_cast<double*>(ctx->lines.p), n, n_tiles, tp, grid->nu_min,
                                        grid->dnu, np, reach, ranges, ctx->stream),
@@ -1182,7 +1182,7 @@ int hk_opacity_stream(hk_ctx* ctx, const hk_lines* chunks, int32_t n_chunks, con
     const int64_t np = grid->n_points;
     if (n_chunks == 0) {  // the opacity of no lines
         if (!accumulate && np > 0)
-            HK_HIP(ctx, hipMemsetAsync(kappa, 0, (size_t)np * sizeof(double), ctx->stream), "hipMemsetAsync");
+            HK_HIP(ctx, launch_zero(kappa, (size_t)np * sizeof(double), ctx->stream), "zero");
         return HK_OK;
     }
     // the loaded list is replaced: from here on it is the chunk being computed
@@ -1376,7 +1376,7 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
                                                          ctx->stream),
                                "line_prep_f32");
                     } else {
-                        HK_HIP(ctx, hipMemsetAsync(scale, 0, sizeof(int32_t), ctx->stream), "hipMemsetAsync");
+                        HK_HIP(ctx, launch_zero(scale, sizeof(int32_t), ctx->stream), "zero");
                     }
                 }
                 HK_HIP(ctx, launch_eval_counts(ix, n, counts + (b0 + s) * kCountBlocks * 3, kCountBlocks, ctx->stream),
@@ -1520,8 +1520,8 @@ int hk_surrogate_set_params(hk_ctx* ctx, const float* theta)
     HK_HIP(ctx, ctx->sg_v.ensure(nb), "allocating parameters");
     HK_HIP(ctx, ctx->sg_copy.ensure(surrogate_params_bytes()), "allocating parameters");
     HK_HIP(ctx, hipMemcpyAsync(ctx->sg_theta.p, theta, nb, hipMemcpyHostToDevice, ctx->stream), "copying parameters");
-    HK_HIP(ctx, hipMemsetAsync(ctx->sg_m.p, 0, nb, ctx->stream), "hipMemsetAsync");
-    HK_HIP(ctx, hipMemsetAsync(ctx->sg_v.p, 0, nb, ctx->stream), "hipMemsetAsync");
+    HK_HIP(ctx, launch_zero(ctx->sg_m.p, nb, ctx->stream), "zero");
+    HK_HIP(ctx, launch_zero(ctx->sg_v.p, nb, ctx->stream), "zero");
     HK_HIP(ctx, launch_surrogate_pack(static_cast<float*>(ctx->sg_theta.p), ctx->sg_copy.p, ctx->stream),
            "surrogate_pack");
     HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");

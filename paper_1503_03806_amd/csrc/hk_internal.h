@@ -252,6 +252,9 @@ hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingI
 hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRec* core, const int64_t* ranges,
                            int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, double nu_min,
                            double dnu, int32_t n_points, double* series, double* partial, hipStream_t s);
+// Zero `bytes` (a multiple of 4) at p with a kernel (unlike hipMemsetAsync,
+// safe to record into a captured graph).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // a[j] += b[j], j < n.
 hipError_t launch_add_f64(double* a, const double* b, int64_t n, hipStream_t s);
 hipError_t launch_eval_counts(const WingIdx* idx, int64_t n_lines, int64_t* partial,

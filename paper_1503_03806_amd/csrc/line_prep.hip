@@ -2,6 +2,8 @@
 // temperature/pressure scaling of every line (§2.3) into the records the
 // opacity kernels read, the line range of each grid tile, and the
 // evaluation counts by region.
+#include <algorithm>
+
 #include "hk_internal.h"
 
 #include <climits>
@@ -365,6 +367,25 @@ hipError_t launch_eval_counts(const WingIdx* idx, int64_t n_lines, int64_t* part
                               int32_t n_blocks, hipStream_t s)
 {
     eval_counts_kernel<<<dim3(n_blocks), dim3(256), 0, s>>>(idx, n_lines, partial);
+    return hipGetLastError();
+}
+
+namespace {
+
+__global__ __launch_bounds__(256) void zero_words_kernel(uint32_t* __restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0u;
+}
+
+}  // namespace
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return hipSuccess;
+    if (bytes % 4 != 0) return hipErrorInvalidValue;
+    const int64_t n = (int64_t)(bytes / 4);
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    zero_words_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(static_cast<uint32_t*>(p), n);
     return hipGetLastError();
 }
 
