@@ -14,8 +14,9 @@
 //        work_plan.hip: a tile, or the part of its lines in one segment,
 //        whose partial sums a reduction adds in segment order).
 //  core: the series for a^2+u^2 < 100, a few hundred times rarer but ~30
-//        times dearer per point and heavy in registers; it adds its own
-//        ordered sum to kappa.
+//        times dearer per point and heavy in registers; it writes its own
+//        ordered sums into a grid of their own (so the two kernels can run
+//        at the same time, on two streams), added to kappa afterwards.
 // So kappa_j = sum_wing + sum_core, each in line order: reproducible bit for
 // bit, independent of the tile shape.
 #include <algorithm>
