@@ -99,13 +99,25 @@ typedef struct {
 } hk_grid;
 #define HK_MAX_POINTS ((int64_t)1 << 30)
 
-/* Bins of consecutive grid points and the g values at which k(g) is
- * reported.  The last bin may hold fewer than points_per_bin points. */
+/* Bins of consecutive grid points, the g values at which k(g) is reported
+ * and the rule that reads k(g) off a sorted bin.  The last bin may hold
+ * fewer than points_per_bin points. */
 typedef struct {
     int64_t points_per_bin;  /* >= 1 */
     int32_t n_g;             /* 1 .. HK_MAX_G */
     const double* g;         /* [host] n_g values, each in (0, 1) */
+    int32_t rule;            /* HK_RULE_STEP or HK_RULE_LINEAR */
 } hk_bins;
+/* k(g) from a bin's M values sorted ascending, s_0 <= ... <= s_{M-1}:
+ *   HK_RULE_STEP:   s_r, r = ceil(g M) - 1, the smallest rank whose
+ *                   cumulative coordinate g_r = (r+1)/M reaches g (§2.2);
+ *   HK_RULE_LINEAR: s_i placed at y_i = (i + 1/2)/M (the abscissae of the
+ *                   Chebyshev fit, §2.6), straight lines between neighbours,
+ *                   s_0 below y_0 and s_{M-1} above y_{M-1}; with
+ *                   u = g M - 1/2, i = floor(u), k = s_i + (u - i)(s_{i+1} - s_i),
+ *                   evaluated in binary64 without contraction. */
+#define HK_RULE_STEP 0
+#define HK_RULE_LINEAR 1
 
 /* Counts of line-point evaluations of the last hk_opacity call. */
 typedef struct {
@@ -240,7 +252,9 @@ int hk_opacity_stream(hk_ctx* ctx, const hk_lines* chunks, int32_t n_chunks, con
 /* For each bin of consecutive points: sort the opacities ascending, form the
  * cumulative coordinate g_i = (i+1)/M of the i-th smallest of the bin's M
  * values (eq. (14) with eq. (15)'s uniform step 1/N_nu), and resample
- * k(g_q) = kappa_sorted[ceil(g_q M) - 1] at the requested g values.
+ * k(g_q) at the requested g values by bins->rule (the step rule
+ * k(g_q) = kappa_sorted[ceil(g_q M) - 1], or the midpoint-linear rule;
+ * see hk_bins).
  * kappa: [device] double (HK_F64) or float (HK_F32_KAHAN: binary32 keys)
  * [n_points], all values >= 0 (a NaN sorts last).  k_out: [device] double[n_bins][n_g] with
  * n_bins = ceil(n_points / points_per_bin).  sorted_out: NULL, or [device]

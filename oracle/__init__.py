@@ -51,8 +51,7 @@ class _Grid(C.Structure):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO):
-            build()
+        build()  # rebuilds when oracle.c is newer than the library
         L = C.CDLL(_SO)
         d, i64, i32 = C.c_double, C.c_int64, C.c_int
         pd = C.POINTER(C.c_double)
@@ -72,8 +71,8 @@ def lib():
         L.ora_eval_counts.argtypes = [C.POINTER(_Lines), C.POINTER(_Cond), C.POINTER(_Grid), pi64]
         L.ora_eval_counts.restype = i32
         L.ora_gauss_legendre.argtypes = [i32, pd, pd]; L.ora_gauss_legendre.restype = i32
-        L.ora_kdist_bin.argtypes = [pd, i64, i32, pd, pd, pd]; L.ora_kdist_bin.restype = i32
-        L.ora_kdist.argtypes = [pd, i64, i64, i32, pd, pd]; L.ora_kdist.restype = i32
+        L.ora_kdist_bin.argtypes = [pd, i64, i32, pd, i32, pd, pd]; L.ora_kdist_bin.restype = i32
+        L.ora_kdist.argtypes = [pd, i64, i64, i32, pd, i32, pd]; L.ora_kdist.restype = i32
         L.ora_num_threads.argtypes = []; L.ora_num_threads.restype = i32
         _lib = L
     return _lib
@@ -210,20 +209,21 @@ def g_nodes(n: int = 20):
     return 0.5 * (1.0 + x), 0.5 * w
 
 
-def kdist_bin(kappa, g):
+def kdist_bin(kappa, g, rule: int = 0):
+    """k(g) of one bin: rule 0 step, rule 1 midpoint-linear (oracle.h)."""
     kappa = _f64(kappa); g = _f64(g)
     out = np.empty(len(g)); srt = np.empty(len(kappa))
-    rc = lib().ora_kdist_bin(_p(kappa), kappa.size, len(g), _p(g), _p(out), _p(srt))
+    rc = lib().ora_kdist_bin(_p(kappa), kappa.size, len(g), _p(g), int(rule), _p(out), _p(srt))
     if rc != 0:
         raise ValueError("ora_kdist_bin rejected its input")
     return out, srt
 
 
-def kdist(kappa, points_per_bin: int, g):
+def kdist(kappa, points_per_bin: int, g, rule: int = 0):
     kappa = _f64(kappa); g = _f64(g)
     n_bins = -(-kappa.size // points_per_bin)
     out = np.empty((n_bins, len(g)))
-    rc = lib().ora_kdist(_p(kappa), kappa.size, points_per_bin, len(g), _p(g), _p(out))
+    rc = lib().ora_kdist(_p(kappa), kappa.size, points_per_bin, len(g), _p(g), int(rule), _p(out))
     if rc != 0:
         raise ValueError("ora_kdist rejected its input")
     return out

@@ -28,7 +28,9 @@
  *  - The unshifted centre enters Gamma_D and S(T); the shifted one the
  *    profile.  Grid points are nu_j = nu_min + j * dnu (point sampling).
  *  - k(g) step rule: g_i = (i+1)/M for the i-th smallest of M values,
- *    k(g) = kappa_(ceil(g M) - 1).
+ *    k(g) = kappa_(ceil(g M) - 1).  The midpoint-linear rule places the
+ *    i-th smallest at (i + 1/2)/M (the Chebyshev fit's abscissae, §2.6) and
+ *    joins neighbours by straight lines, holding the end values.
  */
 #include "oracle.h"
 
@@ -441,9 +443,10 @@ static int cmp_double(const void* pa, const void* pb)
 }
 
 int ora_kdist_bin(const double* kappa, int64_t m, int n_g, const double* g,
-                  double* k_out, double* sorted_out)
+                  int rule, double* k_out, double* sorted_out)
 {
     if (m < 1 || n_g < 0 || !kappa || (n_g > 0 && (!g || !k_out))) return -1;
+    if (rule != 0 && rule != 1) return -1;
     double* s = (double*)malloc((size_t)m * sizeof(double));
     if (!s) return -2;
     memcpy(s, kappa, (size_t)m * sizeof(double));
@@ -453,11 +456,28 @@ int ora_kdist_bin(const double* kappa, int64_t m, int n_g, const double* g,
             free(s);
             return -1;
         }
-        /* smallest rank i with g_i = (i+1)/m >= g_q */
-        int64_t r = (int64_t)ceil(g[q] * (double)m) - 1;
-        if (r < 0) r = 0;
-        if (r > m - 1) r = m - 1;
-        k_out[q] = s[r];
+        if (rule == 0) {
+            /* smallest rank i with g_i = (i+1)/m >= g_q */
+            int64_t r = (int64_t)ceil(g[q] * (double)m) - 1;
+            if (r < 0) r = 0;
+            if (r > m - 1) r = m - 1;
+            k_out[q] = s[r];
+        } else {
+            /* the i-th smallest value sits at y_i = (i + 1/2)/m; straight
+             * line between neighbours, the end values held beyond y_0 and
+             * y_{m-1}.  u = g m - 1/2 is g in units of the spacing from y_0. */
+            double u = g[q] * (double)m - 0.5;
+            double fl = floor(u);
+            if (u <= 0.0) {
+                k_out[q] = s[0];
+            } else if (fl >= (double)(m - 1)) {
+                k_out[q] = s[m - 1];
+            } else {
+                int64_t i = (int64_t)fl;
+                double f = u - fl;
+                k_out[q] = s[i] + f * (s[i + 1] - s[i]);
+            }
+        }
     }
     if (sorted_out) memcpy(sorted_out, s, (size_t)m * sizeof(double));
     free(s);
@@ -465,7 +485,7 @@ int ora_kdist_bin(const double* kappa, int64_t m, int n_g, const double* g,
 }
 
 int ora_kdist(const double* kappa, int64_t n_points, int64_t points_per_bin,
-              int n_g, const double* g, double* k_out)
+              int n_g, const double* g, int rule, double* k_out)
 {
     if (n_points < 1 || points_per_bin < 1) return -1;
     int64_t n_bins = (n_points + points_per_bin - 1) / points_per_bin;
@@ -475,7 +495,7 @@ int ora_kdist(const double* kappa, int64_t n_points, int64_t points_per_bin,
         int64_t j0 = b * points_per_bin;
         int64_t m = n_points - j0 < points_per_bin ? n_points - j0
                                                    : points_per_bin;
-        rc |= ora_kdist_bin(kappa + j0, m, n_g, g, k_out + b * n_g, NULL);
+        rc |= ora_kdist_bin(kappa + j0, m, n_g, g, rule, k_out + b * n_g, NULL);
     }
     return rc ? -1 : 0;
 }

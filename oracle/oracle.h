@@ -111,16 +111,20 @@ int ora_gauss_legendre(int n, double* x, double* w);
 
 /* k-distribution of §2.2 for one bin of m opacity values: sort ascending,
  * cumulative coordinate g_i = (i+1)/m (eq. (14) with delta y = 1/N_nu,
- * eq. (15)), and k(g_q) = kappa_sorted[ceil(g_q m) - 1] for the n_g given
- * g values in (0, 1).  sorted_out may be NULL. */
+ * eq. (15)), and, for the n_g given g values in (0, 1):
+ *   rule 0 (step):  k(g_q) = kappa_sorted[ceil(g_q m) - 1];
+ *   rule 1 (midpoint-linear): the i-th smallest sits at y_i = (i + 1/2)/m,
+ *     k(g_q) interpolates linearly between neighbouring y_i and holds
+ *     kappa_sorted[0] below y_0 and kappa_sorted[m-1] above y_{m-1}.
+ * sorted_out may be NULL. */
 int ora_kdist_bin(const double* kappa, int64_t m, int n_g, const double* g,
-                  double* k_out, double* sorted_out);
+                  int rule, double* k_out, double* sorted_out);
 
 /* k-distribution of a whole grid cut into consecutive bins of
  * points_per_bin points (the last bin may be shorter).  k_out is
  * [n_bins][n_g]. */
 int ora_kdist(const double* kappa, int64_t n_points, int64_t points_per_bin,
-              int n_g, const double* g, double* k_out);
+              int n_g, const double* g, int rule, double* k_out);
 
 int ora_num_threads(void);
 

@@ -15,7 +15,8 @@ import os
 import numpy as np
 
 __all__ = ["HK_OK", "HK_EINVAL", "HK_ENOMEM", "HK_EDEVICE", "HK_EUNSUPPORTED", "HK_ENOTREADY",
-           "HK_F64", "HK_F32_KAHAN", "HK_MAX_G", "HKError", "lib", "hk_version", "hk_create",
+           "HK_F64", "HK_F32_KAHAN", "HK_MAX_G", "HK_RULE_STEP", "HK_RULE_LINEAR", "HKError", "lib",
+           "hk_version", "hk_create",
            "hk_destroy", "hk_set_stream", "hk_sync", "hk_last_error", "hk_load_lines",
            "hk_opacity", "hk_kdist", "hk_gauss_legendre", "hk_stats", "hk_set_timing",
            "hk_get_timing", "hk_set_option", "hk_get_option", "hk_tables", "HK_F32_SURROGATE",
@@ -34,6 +35,7 @@ HK_SURR_N_PARAMS, HK_SURR_MAX_BATCH = 12737, 65536
 HK_SURR_CELLS_X, HK_SURR_CELLS_Y = 80, 40
 HK_MAX_COEF, HK_MAX_COLUMNS, HK_TRANSMISSION_NODES = 32, 1 << 20, 100
 HK_MAX_G = 64
+HK_RULE_STEP, HK_RULE_LINEAR = 0, 1
 HK_MAX_POINTS = 1 << 30
 HK_MAX_CHUNKS = 65536
 
@@ -66,7 +68,7 @@ class hk_grid(C.Structure):
 
 
 class hk_bins(C.Structure):
-    _fields_ = [("points_per_bin", C.c_int64), ("n_g", C.c_int32), ("g", _pd)]
+    _fields_ = [("points_per_bin", C.c_int64), ("n_g", C.c_int32), ("g", _pd), ("rule", C.c_int32)]
 
 
 class hk_run_stats(C.Structure):
@@ -255,20 +257,21 @@ def hk_opacity(ctx, state: dict, grid: dict, precision: int, kappa, comp=None,
 
 
 def hk_kdist(ctx, kappa, precision: int, n_points: int, points_per_bin: int, g, k_out,
-             sorted_out=None):
+             sorted_out=None, rule: int = 0):
     gg = _f64(g)
-    b = hk_bins(int(points_per_bin), len(gg), gg.ctypes.data_as(_pd))
+    b = hk_bins(int(points_per_bin), len(gg), gg.ctypes.data_as(_pd), int(rule))
     _check(lib().hk_kdist(ctx, _ptr(kappa), int(precision), int(n_points), C.byref(b),
                           _ptr(k_out), _ptr(sorted_out)), ctx)
 
 
-def hk_tables(ctx, states, grid: dict, points_per_bin: int, g, precision: int, k_out):
+def hk_tables(ctx, states, grid: dict, points_per_bin: int, g, precision: int, k_out,
+              rule: int = 0):
     """states: sequence of state dicts; k_out: device tensor
     [len(states)][n_bins][len(g)] of float64."""
     arr = (hk_state * max(len(states), 1))(*[_state(s) for s in states])
     gr = _grid(grid)
     gg = _f64(g)
-    b = hk_bins(int(points_per_bin), len(gg), gg.ctypes.data_as(_pd))
+    b = hk_bins(int(points_per_bin), len(gg), gg.ctypes.data_as(_pd), int(rule))
     _check(lib().hk_tables(ctx, arr, len(states), C.byref(gr), C.byref(b), int(precision),
                            _ptr(k_out)), ctx)
 
@@ -435,24 +438,25 @@ class Context:
         hk_opacity(self.h, state, grid, precision, out, comp, accumulate)
         return out
 
-    def kdist(self, kappa, points_per_bin: int, g, precision: int = HK_F64, sorted_out=None):
+    def kdist(self, kappa, points_per_bin: int, g, precision: int = HK_F64, sorted_out=None,
+              rule: int = 0):
         torch = self._torch
         n = kappa.numel()
         n_bins = -(-n // points_per_bin)
         k = torch.empty((max(n_bins, 1), len(g)), dtype=torch.float64,
                         device="cuda:%d" % self.device)[:n_bins]
-        hk_kdist(self.h, kappa, precision, n, points_per_bin, g, k, sorted_out)
+        hk_kdist(self.h, kappa, precision, n, points_per_bin, g, k, sorted_out, rule)
         return k
 
     def tables(self, states, grid: dict, points_per_bin: int, g, precision: int = HK_F32_KAHAN,
-               out=None):
+               out=None, rule: int = 0):
         torch = self._torch
         n = int(grid["n_points"])
         n_bins = -(-n // points_per_bin)
         if out is None:
             out = torch.empty((len(states), n_bins, len(g)), dtype=torch.float64,
                               device="cuda:%d" % self.device)
-        hk_tables(self.h, states, grid, points_per_bin, g, precision, out)
+        hk_tables(self.h, states, grid, points_per_bin, g, precision, out, rule)
         return out
 
     # -- resampling and transmission (float64 device tensors) --

@@ -212,7 +212,10 @@ int check_bins(hk_ctx* ctx, const hk_bins* b, GValues* gv)
     if (b->points_per_bin < 1) return fail(ctx, HK_EINVAL, "points_per_bin must be >= 1");
     if (b->n_g < 1 || b->n_g > HK_MAX_G) return fail(ctx, HK_EINVAL, "n_g must be in [1, %d]", HK_MAX_G);
     if (!b->g) return fail(ctx, HK_EINVAL, "g is NULL");
+    if (b->rule != HK_RULE_STEP && b->rule != HK_RULE_LINEAR)
+        return fail(ctx, HK_EINVAL, "rule %d is neither HK_RULE_STEP nor HK_RULE_LINEAR", b->rule);
     gv->n = b->n_g;
+    gv->rule = b->rule;
     for (int q = 0; q < b->n_g; ++q) {
         if (!isfin(b->g[q]) || !(b->g[q] > 0.0) || !(b->g[q] < 1.0))
             return fail(ctx, HK_EINVAL, "g[%d] = %g is not in (0, 1)", q, b->g[q]);
@@ -1652,6 +1655,7 @@ int hk_surrogate_certify(hk_ctx* ctx, double budget, double* err, int32_t* n_cer
 }
 
 static_assert(HK_MAX_COEF == kMaxCoef, "coefficient bound");
+static_assert(HK_RULE_STEP == kRuleStep && HK_RULE_LINEAR == kRuleLinear, "k(g) rules");
 static_assert(HK_TRANSMISSION_NODES <= kMaxQuad, "quadrature bound");
 
 int hk_resample(hk_ctx* ctx, const void* sorted, int precision, int64_t n_points, int64_t points_per_bin,

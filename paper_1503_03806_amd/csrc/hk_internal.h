@@ -115,9 +115,14 @@ struct PrepParams {
     int32_t n_points;
 };
 
+// Rules that read k(g) off a sorted bin: step, midpoint-linear.
+constexpr int32_t kRuleStep = 0;
+constexpr int32_t kRuleLinear = 1;
+
 struct GValues {
     double g[64];
     int32_t n;
+    int32_t rule;  // kRuleStep or kRuleLinear
 };
 
 // ---- work items of the wing kernels (work_plan.hip) ----

@@ -1,5 +1,6 @@
 // kdist.hip -- the "Sort" stage (§2.2, §2.6): per-bin sort of the opacity
-// grid, cumulative coordinate g_i = (i+1)/M, and k(g) at the requested g.
+// grid, cumulative coordinate g_i = (i+1)/M, and k(g) at the requested g by
+// the step or the midpoint-linear rule.
 //
 // The paper sorts the whole grid at once with bin tags (Thrust, §2.6).  Here
 // bins are independent: a bin that fits in LDS is sorted there by one
@@ -64,11 +65,26 @@ __device__ void bitonic_lds(K* s, int npad)
     }
 }
 
-// Rank of the q-th requested g in a bin of m sorted values.
-__device__ inline int64_t g_rank(double g, int64_t m)
+// k(g) read off a bin's m sorted keys s[0 .. m).  Step rule: the smallest
+// rank r whose g_r = (r+1)/m reaches g.  Midpoint-linear rule: key i sits at
+// (i + 1/2)/m, straight lines between neighbours, the end keys held outside;
+// no contraction, so the binary64 result is that of the expression as written.
+template <typename K>
+__device__ inline double k_of_g(const K* s, int64_t m, double g, int rule)
 {
-    int64_t r = (int64_t)ceil(g * (double)m) - 1;
-    return r < 0 ? 0 : (r > m - 1 ? m - 1 : r);
+#pragma clang fp contract(off)
+    if (rule == kRuleStep) {
+        int64_t r = (int64_t)ceil(g * (double)m) - 1;
+        r = r < 0 ? 0 : (r > m - 1 ? m - 1 : r);
+        return key_value<K>(s[r]);
+    }
+    const double u = g * (double)m - 0.5;
+    const double fl = floor(u);
+    if (u <= 0.0) return key_value<K>(s[0]);
+    if (fl >= (double)(m - 1)) return key_value<K>(s[m - 1]);
+    const int64_t i = (int64_t)fl;  // 0 <= i <= m - 2
+    const double a = key_value<K>(s[i]), b = key_value<K>(s[i + 1]);
+    return a + (u - fl) * (b - a);
 }
 
 // One workgroup per bin (bins <= chunk), or per chunk of a larger bin when
@@ -93,7 +109,7 @@ __global__ __launch_bounds__(kSortThreads) void sort_chunk_lds_kernel(
         for (int i = threadIdx.x; i < m; i += blockDim.x) dst[j0 + i] = s[i];
     }
     if (final && (int)threadIdx.x < g.n) {
-        k_out[bin * g.n + threadIdx.x] = key_value<K>(s[g_rank(g.g[threadIdx.x], m)]);
+        k_out[bin * g.n + threadIdx.x] = k_of_g<K>(s, m, g.g[threadIdx.x], g.rule);
     }
 }
 
@@ -149,7 +165,7 @@ __global__ __launch_bounds__(64) void kdist_pick_kernel(const K* __restrict__ so
     const int64_t b0 = bin * ppb;
     const int64_t m = min(ppb, n_points - b0);
     if ((int)threadIdx.x < g.n)
-        k_out[bin * g.n + threadIdx.x] = key_value<K>(sorted[b0 + g_rank(g.g[threadIdx.x], m)]);
+        k_out[bin * g.n + threadIdx.x] = k_of_g<K>(sorted + b0, m, g.g[threadIdx.x], g.rule);
 }
 
 int pow2_at_least(int64_t m)

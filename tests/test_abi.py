@@ -88,16 +88,19 @@ def test_opacity_rejects_bad_precision_and_buffers():
 def test_kdist_rejects_bad_bins():
     g = np.array([0.1, 0.5])
 
-    def rc(ppb, gv, n_points=100):
+    def rc(ppb, gv, n_points=100, rule=hk.HK_RULE_STEP):
         gg = np.ascontiguousarray(gv, dtype=np.float64)
-        b = hk.hk_bins(ppb, len(gg), gg.ctypes.data_as(C.POINTER(C.c_double)))
+        b = hk.hk_bins(ppb, len(gg), gg.ctypes.data_as(C.POINTER(C.c_double)), rule)
         return hk.lib().hk_kdist(None, 1, hk.HK_F64, n_points, C.byref(b), 1, None)
     assert rc(0, g) == hk.HK_EINVAL and "points_per_bin" in hk.hk_last_error(None)
     assert rc(10, [0.0, 0.5]) == hk.HK_EINVAL and "(0, 1)" in hk.hk_last_error(None)
     assert rc(10, [0.5, 1.0]) == hk.HK_EINVAL
     assert rc(10, np.full(65, 0.5)) == hk.HK_EINVAL and "n_g" in hk.hk_last_error(None)
     assert rc(10, g, n_points=-1) == hk.HK_EINVAL
+    assert rc(10, g, rule=2) == hk.HK_EINVAL and "rule 2" in hk.hk_last_error(None)
+    assert rc(10, g, rule=-1) == hk.HK_EINVAL and "rule -1" in hk.hk_last_error(None)
     assert rc(10, g) == hk.HK_EINVAL and "context" in hk.hk_last_error(None)
+    assert rc(10, g, rule=hk.HK_RULE_LINEAR) == hk.HK_EINVAL and "context" in hk.hk_last_error(None)
 
 
 def test_load_lines_rejects_bad_lists():
@@ -140,10 +143,10 @@ def test_gauss_legendre_helper_matches_numpy():
 
 
 def _tables_rc(states, n_states=None, grid=GOOD_GRID, ppb=100, g=(0.25, 0.75),
-               precision=hk.HK_F32_KAHAN, k_out=1):
+               precision=hk.HK_F32_KAHAN, k_out=1, rule=hk.HK_RULE_STEP):
     arr = (hk.hk_state * max(len(states), 1))(*[hk._state(s) for s in states])
     gg = np.ascontiguousarray(g, dtype=np.float64)
-    b = hk.hk_bins(ppb, len(gg), gg.ctypes.data_as(C.POINTER(C.c_double)))
+    b = hk.hk_bins(ppb, len(gg), gg.ctypes.data_as(C.POINTER(C.c_double)), rule)
     gr = hk._grid(grid)
     n = len(states) if n_states is None else n_states
     return hk.lib().hk_tables(None, arr, n, C.byref(gr), C.byref(b), precision, k_out)
@@ -157,6 +160,7 @@ def test_tables_rejects_bad_arguments():
     assert "states[2]" in hk.hk_last_error(None) and "T must" in hk.hk_last_error(None)
     assert _tables_rc([GOOD_STATE], ppb=0) == hk.HK_EINVAL
     assert _tables_rc([GOOD_STATE], precision=5) == hk.HK_EINVAL
+    assert _tables_rc([GOOD_STATE], rule=7) == hk.HK_EINVAL and "rule 7" in hk.hk_last_error(None)
     assert _tables_rc([GOOD_STATE], grid=dict(GOOD_GRID, dnu=1e-7, cutoff=1.0)) == hk.HK_EINVAL
     assert "2^23" in hk.hk_last_error(None)
     assert _tables_rc([GOOD_STATE], k_out=None) == hk.HK_EINVAL

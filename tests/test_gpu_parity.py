@@ -203,6 +203,33 @@ def test_kdist_matches_oracle_bitwise(ctx, n, ppb):
         assert np.array_equal(s[b0:b0 + ppb], np.sort(kap[b0:b0 + ppb]))
 
 
+# The midpoint-linear rule: the same binary64 expression on both sides,
+# evaluated without contraction, so the results agree bit for bit; binary32
+# keys enter as their exact binary64 values.
+@pytest.mark.parametrize("n,ppb", [(1, 1), (3, 2), (1000, 7), (100000, 1000), (50000, 16385),
+                                   (250001, 100000)])
+@pytest.mark.parametrize("precision", [hk.HK_F64, hk.HK_F32_KAHAN])
+def test_kdist_linear_rule_matches_oracle_bitwise(ctx, n, ppb, precision):
+    say("kdist linear", n, ppb, precision)
+    rng = np.random.default_rng(7 * n + ppb)
+    kap = 10.0 ** rng.uniform(-30, -18, n)
+    kap[rng.integers(0, n, n // 10)] = kap[0]  # ties
+    if n > 10:
+        kap[:5] = 0.0
+    g = np.concatenate([oracle.g_nodes(20)[0], [1e-9, 0.5, 0.75, 1 - 1e-12]])
+    if precision == hk.HK_F32_KAHAN:
+        kap = kap.astype(np.float32).astype(np.float64)
+        kt = torch.from_numpy(kap.astype(np.float32)).cuda()
+    else:
+        kt = torch.from_numpy(kap).cuda()
+    kd = ctx.kdist(kt, ppb, g, precision=precision, rule=hk.HK_RULE_LINEAR).cpu().numpy()
+    ref = oracle.kdist(kap, ppb, g, rule=1)
+    assert np.array_equal(kd.view(np.uint64), ref.view(np.uint64))
+    # and the step rule of the same call still gives the step rule's values
+    kd0 = ctx.kdist(kt, ppb, g, precision=precision).cpu().numpy()
+    assert np.array_equal(kd0, oracle.kdist(kap, ppb, g))
+
+
 # ---- the mid-scale workload at full size (the benchmark's launch), sampled ----
 
 def test_lines1e6_grid3e6_sampled(ctx):

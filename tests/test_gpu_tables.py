@@ -83,6 +83,26 @@ def test_tables_match_single_state_path_and_oracle(ctx, precision):
     assert st["evals"] == total
 
 
+@pytest.mark.parametrize("precision", [hk.HK_F64, hk.HK_F32_KAHAN])
+def test_tables_linear_rule_matches_single_state_path(ctx, precision):
+    w, lines, grid, conds = small_setup()
+    ppb = 10_000
+    g, _ = oracle.g_nodes(w.n_g)
+    ctx.load_lines(lines, conds[0]["mass_amu"], conds[0]["T0"])
+    say("tables linear rule, precision", precision)
+    tab = ctx.tables([state_of(c) for c in conds[:3]], grid, ppb, g, precision,
+                     rule=hk.HK_RULE_LINEAR).cpu().numpy()
+    for s, cond in enumerate(conds[:3]):
+        k = ctx.opacity(state_of(cond), grid, precision)
+        ref = ctx.kdist(k, ppb, g, rule=hk.HK_RULE_LINEAR).cpu().numpy()
+        assert np.array_equal(tab[s].view(np.uint64), ref.view(np.uint64)), s
+        # against the oracle's own opacity and linear rule
+        ora, _ = oracle.opacity(lines, cond, grid)
+        e = np.abs(tab[s] / oracle.kdist(ora, ppb, g, rule=1) - 1).max()
+        say("  state %d: linear-rule k(g) max rel err vs oracle %.2e" % (s, e))
+        assert e <= TOL[precision]
+
+
 def test_tables_batches_and_shapes_are_bitwise_identical(ctx):
     w, lines, grid, conds = small_setup()
     ppb = 10_000

@@ -439,3 +439,46 @@ def test_lorentz_width_cutoff_is_the_absolute_cutoff_of_each_line():
     big = dict(grid, cutoff=1e9, cutoff_lorentz=0.0)
     _, nb = oracle.opacity(lines, cond, big)
     assert nb == 6 * grid["n_points"]
+
+
+def test_p12b_midpoint_linear_rule_pins():
+    """Rule 1: the i-th smallest at y_i = (i + 1/2)/M, straight lines between
+    neighbours, end values held.  Pinned by numpy.interp (a library's
+    piecewise-linear interpolation), exact dyadic nodes, a closed form on
+    evenly spaced values and the one-value bin."""
+    rng = np.random.default_rng(41)
+    g = np.concatenate([oracle.g_nodes(20)[0], [1e-9, 0.3e-3, 0.5, 0.9995, 1 - 1e-12]])
+    for m in (1, 2, 3, 1000, 4097):
+        kap = 10.0 ** rng.uniform(-28, -18, m)
+        kap[: m // 3] = kap[0]  # ties
+        k, srt = oracle.kdist_bin(kap, g, rule=1)
+        srt_ref = np.sort(kap)
+        ref = np.interp(g, (np.arange(m) + 0.5) / m, srt_ref)
+        # numpy rounds in the abscissa (x - x_j), which the slope amplifies:
+        # allow (M + 1) eps of the larger neighbour, a few times over
+        i = np.clip(np.floor(g * m - 0.5).astype(np.int64), 0, m - 1)
+        nb = np.maximum(srt_ref[i], srt_ref[np.minimum(i + 1, m - 1)])
+        assert np.all(np.abs(k - ref) <= 8 * (m + 1) * np.finfo(float).eps * nb), m
+        assert np.all(np.diff(k[np.argsort(g)]) >= 0)
+        assert np.array_equal(srt, np.sort(kap))
+    # dyadic: g = (i + 1/2)/1024 is exact, so k is the i-th smallest exactly
+    m = 1024
+    kap = rng.permutation(10.0 ** rng.uniform(-25, -20, m))
+    i = np.array([0, 1, 17, 511, 1022, 1023])
+    k, srt = oracle.kdist_bin(kap, (i + 0.5) / m, rule=1)
+    assert np.array_equal(k, srt[i])
+    # evenly spaced values a + b i: k(g) = a + b (g M - 1/2), clamped to the ends
+    a, b, m = 2.0, 0.25, 64
+    kap = rng.permutation(a + b * np.arange(m))
+    gg = np.linspace(0.001, 0.999, 97)
+    ref = a + b * np.clip(gg * m - 0.5, 0, m - 1)
+    assert np.allclose(oracle.kdist_bin(kap, gg, rule=1)[0], ref, rtol=0, atol=1e-14)
+    # the step rule and the linear rule agree on a constant bin and on M = 1
+    assert np.all(oracle.kdist(np.full(500, 3.5e-22), 100, g, rule=1) == 3.5e-22)
+    assert np.all(oracle.kdist_bin([7.0], g, rule=1)[0] == 7.0)
+    # whole grid with a ragged last bin = per-bin calls
+    kap = 10.0 ** rng.uniform(-28, -18, 3 * 1000 + 17)
+    k = oracle.kdist(kap, 1000, g, rule=1)
+    assert np.array_equal(k[3], oracle.kdist_bin(kap[3000:], g, rule=1)[0])
+    with pytest.raises(ValueError):
+        oracle.kdist_bin(kap, g, rule=2)
