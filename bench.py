@@ -37,6 +37,10 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X binary64 vector peak
 # with its average of 24 terms at 10 flops each plus 18 of set-up: 258.
 FLOPS_PER_EVAL = {"gh1": 5, "gh3": 16, "core": 258}
 DOMINANT_KERNEL = "wing_f64_kernel"
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+# LDS read rate assumed for the sort: 32 banks x 4 B per clock per CU, 256 CUs,
+# 2.4 GHz
+PEAK_LDS_GBS = 256 * 128 * 2.4
 # surrogate training recipe: (Adam steps, learning rate) phases, batch 4096
 SURROGATE_SCHEDULE = ((20000, 5e-3), (20000, 1e-3), (20000, 2e-4))
 SURROGATE_WSCALE = 5.0  # loss weight 1/(1 + (z/5)^2)
@@ -118,6 +122,25 @@ def bench_resample(hk, torch, ctx, kappa, N, ppb, g):
     t_tr = time.perf_counter() - t1
     return {"bins": int(-(-N // ppb)), "n_coef": 20, "n_m": 1000,
             "ms_sort_fit_transmission": 1e3 * dt, "ms_fit": 1e3 * t_fit, "ms_transmission": 1e3 * t_tr}
+
+
+def kdist_stage(ms, N, ppb, n_g, key_bytes=8, lds_keys=16384):
+    """The Sort + k(g) stage against HBM and LDS: its algorithmic bytes (each
+    opacity read once, k(g) written once) and, for bins sorted in LDS, the
+    keys the bitonic network reads there (each of its log2(n)(log2(n)+1)/2
+    stages reads every padded key once)."""
+    n_bins = -(-N // ppb)
+    hbm = key_bytes * N + 8 * n_bins * n_g
+    out = {"ms": ms, "hbm_bytes": hbm, "GB_s": hbm / (ms * 1e-3) / 1e9,
+           "frac_of_hbm_peak": hbm / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    if ppb <= lds_keys:
+        npad = 1 << (ppb - 1).bit_length()
+        lg = npad.bit_length() - 1
+        lds = n_bins * (lg * (lg + 1) // 2) * npad * key_bytes
+        out.update({"bound": "lds", "lds_read_bytes": lds,
+                    "lds_read_GB_s": lds / (ms * 1e-3) / 1e9,
+                    "frac_of_lds_read_peak": lds / (ms * 1e-3) / 1e9 / PEAK_LDS_GBS})
+    return out
 
 
 def bench_stream(hk, torch, ctx, n_chunks: int = 34):
@@ -362,6 +385,7 @@ def main(argv=None):
                    "evals_per_step": evals, "evals_core": st["evals_core"],
                    "evals_gh3": st["evals_gh3"], "evals_gh1": st["evals_gh1"]},
         "stage_ms": {k: v[0] / max(v[1], 1) for k, v in tm.items()},
+        "kdist": kdist_stage(tm["kdist"][0] / max(tm["kdist"][1], 1), N, ppb, w.n_g),
         "stage_note": "event-timed mean per timed launch; 'opacity' (wing) and 'core' (series) run concurrently "
                       "on two streams and overlap; 'line_prep' includes tile ranges and work plans",
         "roofline": {"bound": "alu", "kernel": DOMINANT_KERNEL,
