@@ -34,16 +34,19 @@ constexpr double kGH1R2 = 1.0e6;
 // q: with GH = G2 + 1.5 alpha^2, P = (q + GH)^2 - 6 alpha^2 q is the product
 // of the two shifted Lorentzians' denominators and 3n = 2P + D (q + GH).
 // Coefficients: B = 2 G2 - 3 alpha^2, C = GH^2, Bn = 2 G2 - 1.5 alpha^2,
-// Cn = GH (2 GH + G2) / 3.  Where a^2 + u^2 >= 100, q + G2 >= 100 alpha^2, so
-// the negative parts of B and Bn never cancel q's terms.
+// Cn = GH (2 GH + G2) / 3.  The record holds the denominator as one cubic,
+// D P = ((q + M2) q + M1) q + M0 with M2 = G2 + B = 3 (G2 - alpha^2),
+// M1 = C + G2 B = 3 G2^2 + 2.25 alpha^4 (no cancellation) and M0 = G2 C.
+// Where a^2 + u^2 >= 100, q + G2 >= 100 alpha^2, so the negative parts of
+// M2 and Bn never cancel q's terms.
 // The grid-index intervals (closed; empty when lo > hi) sit in WingIdx: the
 // cutoff window and the points whose a^2+u^2 lies below 1e6 and below 100.
 struct alignas(16) WingRec {
     double nu0;  // pressure-shifted line centre
     double Lg;   // S(T) Gamma_L / pi
     double G2;   // Gamma_L^2
-    double B, C, Bn, Cn;
-    double pad;
+    double M2, M1, M0;  // the 3-node denominator's cubic
+    double Bn, Cn;      // the 3-node numerator's quadratic
 };
 static_assert(sizeof(WingRec) == 64, "WingRec layout");
 struct alignas(16) WingIdx {
@@ -79,7 +82,7 @@ static_assert(sizeof(CoreRec) == 64, "CoreRec layout");
 // For point j: dv/lambda = (j - jc) du - fu, with jc the nearest grid point
 // to the centre (WingIdx.jc), du = dnu/lambda, fu = (nu0 - nu_jc)/lambda.
 //   1-node:  Lg / (q + G2),  3-node:  Lg n / ((q + G2) P)  with q = (dv/lambda)^2
-// and the 3-node coefficients of WingRec scaled by lambda^-2 / lambda^-4.
+// and the 3-node coefficients B, C, Bn, Cn scaled by lambda^-2 / lambda^-4.
 struct alignas(16) WingRec32 {
     float du, fu, Lg, G2, B, C, Bn, Cn;
 };

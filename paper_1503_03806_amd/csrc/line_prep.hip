@@ -88,11 +88,11 @@ __global__ __launch_bounds__(256) void line_prep_f64_kernel(LinesDev L, PrepPara
     {
         const double a2 = alpha * alpha;
         const double GH = w.G2 + 1.5 * a2;
-        w.B = 2.0 * w.G2 - 3.0 * a2;
-        w.C = GH * GH;
+        w.M2 = 3.0 * (w.G2 - a2);
+        w.M1 = 3.0 * (w.G2 * w.G2) + 2.25 * (a2 * a2);
+        w.M0 = w.G2 * (GH * GH);
         w.Bn = 2.0 * w.G2 - 1.5 * a2;
         w.Cn = GH * (2.0 * GH + w.G2) * (1.0 / 3.0);
-        w.pad = 0.0;
         x.flags = (a2 > 1e-40 && w.G2 < 1e20) ? kPairSafe : 0;
         x.jc = 0;
     }
@@ -270,8 +270,10 @@ __global__ __launch_bounds__(256) void line_prep_f32_kernel(
     r.fu = (float)(f * il);
     r.Lg = (float)ldexp(w.Lg * il * il, s);
     r.G2 = (float)(w.G2 * il * il);
-    r.B = (float)(w.B * il * il);
-    r.C = (float)(w.C * il * il * il * il);
+    const double a2 = alpha * alpha;
+    const double GH = w.G2 + 1.5 * a2;
+    r.B = (float)((2.0 * w.G2 - 3.0 * a2) * il * il);
+    r.C = (float)(GH * GH * il * il * il * il);
     r.Bn = (float)(w.Bn * il * il);
     r.Cn = (float)(w.Cn * il * il * il * il);
     w32[i] = r;

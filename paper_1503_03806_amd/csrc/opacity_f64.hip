@@ -74,13 +74,13 @@ __device__ inline uint32_t classify(const WingIdx& r, int32_t run0, int32_t run1
 }
 
 // 3-node rule of one point: S Phi = Lg n / m with q = dv^2,
-// n = q (q + Bn) + Cn, m = (q + G2)(q (q + B) + C).
-__device__ inline void gh3_nm(double dv, double G2, double B, double C, double Bn, double Cn,
+// n = q (q + Bn) + Cn, m = (q + G2)(q (q + B) + C) = ((q + M2) q + M1) q + M0.
+__device__ inline void gh3_nm(double dv, double M2, double M1, double M0, double Bn, double Cn,
                               double& n, double& m)
 {
     const double q = dv * dv;
     n = fma(q, q + Bn, Cn);
-    m = (q + G2) * fma(q, q + B, C);
+    m = fma(fma(q + M2, q, M1), q, M0);
 }
 
 // Points pair up to share one reciprocal: 1/da = db / (da db).  Point j
@@ -167,13 +167,13 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
             }
             if (path == kGH3) {
                 do {
-                    const double nu0 = tile[k].nu0, Lg = tile[k].Lg, G2 = tile[k].G2;
-                    const double B = tile[k].B, C = tile[k].C, Bn = tile[k].Bn, Cn = tile[k].Cn;
+                    const double nu0 = tile[k].nu0, Lg = tile[k].Lg;
+                    const double M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Bn = tile[k].Bn, Cn = tile[k].Cn;
 #pragma unroll
                     for (int p = 0; p < kP; p += 2) {
                         double na, ma, nb, mb;
-                        gh3_nm(nuj[p] - nu0, G2, B, C, Bn, Cn, na, ma);
-                        gh3_nm(nuj[p + 1] - nu0, G2, B, C, Bn, Cn, nb, mb);
+                        gh3_nm(nuj[p] - nu0, M2, M1, M0, Bn, Cn, na, ma);
+                        gh3_nm(nuj[p + 1] - nu0, M2, M1, M0, Bn, Cn, nb, mb);
                         const double c = qrcp(ma * mb) * Lg;
                         acc[p] = fma(c * mb, na, acc[p]);
                         acc[p + 1] = fma(c * ma, nb, acc[p + 1]);
@@ -183,7 +183,7 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                 continue;
             }
             const double nu0 = tile[k].nu0, Lg = tile[k].Lg, G2 = tile[k].G2;
-            const double B = tile[k].B, C = tile[k].C, Bn = tile[k].Bn, Cn = tile[k].Cn;
+            const double M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Bn = tile[k].Bn, Cn = tile[k].Cn;
             // general path: window edges, region edges, core points (left to
             // the core kernel), the grid end, lines outside the pairing range
             // (rare: the index record is read from memory, not staged)
@@ -201,7 +201,7 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                     const int32_t j = run0 + lane + 64 * (p + e);
                     const double dv = nuj[p + e] - nu0;
                     double n3, m3;
-                    gh3_nm(dv, G2, B, C, Bn, Cn, n3, m3);
+                    gh3_nm(dv, M2, M1, M0, Bn, Cn, n3, m3);
                     one[e] = j < g3lo || j > g3hi;
                     core_pt[e] = j >= clo && j <= chi;
                     take[e] = j >= wlo && j <= whi && !core_pt[e];
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(256) void wing_f64_reduce_kernel(WorkPlan wp, int64
 //         = 2 e^{-x^2} sum_n w_n cosh(n x),  w_n = e^{-n^2/4} / (n^2/4 + y^2),
 // so that H = e^{-x^2} [erfcx(y) cos 2xy + sin^2(xy)/(pi y)
 //                        + (y/pi) (sum_n w_n cosh(nx) - cos(2xy) T1)].
-// cosh(nx) comes from the powers e^{+-nx} by recurrence (at most e^{340},
+// cosh(nx) comes from a three-term recurrence in n (at most e^{340}/2,
 // x < 10, n <= 34); w[n-1] is the line's table (same y for all its points),
 // read from LDS.
 // e^{-n^2/4}, n = 1 .. kMaxTerms
@@ -345,16 +345,19 @@ __device__ double voigt_core(double x, double y, double ex, double T1, const dou
 {
     const double E = exp(-x * x);
     const double up = exp(x);
-    const double dn = qrcp(up);
+    const double c1 = up + qrcp(up);  // 2 cosh x
     // all kMaxTerms terms for every point (x < 10, so at least the
     // 2 ceil(x) + 14 terms the series needs; the rest are below 1e-20 of the
-    // sum): a fixed trip count, the same for every lane
-    double p = up, q = dn, sc = 0.0;
+    // sum): a fixed trip count, the same for every lane.  2 cosh(n x) by the
+    // three-term recurrence c_{n+1} = c_1 c_n - c_{n-1}, c_0 = 2, which
+    // follows the growing solution e^{nx} stably (relative error ~n eps).
+    double cm = 2.0, cc = c1, sc = 0.0;
 #pragma unroll 2
     for (int n = 0; n < kMaxTerms; ++n) {
-        sc = fma(w[n], p + q, sc);
-        p *= up;
-        q *= dn;
+        sc = fma(w[n], cc, sc);
+        const double cn = fma(c1, cc, -cm);
+        cm = cc;
+        cc = cn;
     }
     double s, co;
     sincos(x * y, &s, &co);
