@@ -101,7 +101,7 @@ struct hk_ctx {
     // binary32 path: records, Kahan pair, scale
     DevBuf w32, c32, f32sum, f32comp, f32scale, f32partial;
     bool have_run = false;
-    int f64_points_per_lane = 2;  // tile shape of the binary64 opacity kernel
+    int f64_points_per_lane = 4;  // tile shape of the binary64 opacity kernel (4 or 8)
     int f32_points_per_lane = 2;  // tile shape of the binary32 opacity kernel
     // batched tables: per-state records, ranges and sums of one batch, the
     // per-state evaluation counters of the last call, and the tile shapes
@@ -658,6 +658,7 @@ int autotune_wing(hk_ctx* ctx, int precision, const hk_state* states, int32_t n_
     std::vector<double> reach((size_t)n_try);
     for (int32_t s = 0; s < n_try; ++s) reach[(size_t)s] = wing_reach(ctx, &states[s], grid);
     for (int cand : {2, 4, 8}) {
+        if (precision == HK_F64 && cand == 2) continue;  // binary64 groups points by four
         const int32_t tp = precision == HK_F64 ? opacity_f64_tile_points(cand) : opacity_f32_tile_points(cand);
         const int64_t n_tiles = ((int64_t)np + tp - 1) / tp;
         err = ctx->tb_ranges.ensure((size_t)std::max<int64_t>(n_tiles * n_try, 1) * 2 * sizeof(int64_t));
@@ -1788,6 +1789,9 @@ int hk_set_option(hk_ctx* ctx, const char* name, int64_t value)
     const bool f64 = std::strcmp(name, "f64_points_per_lane") == 0;
     const bool f32 = std::strcmp(name, "f32_points_per_lane") == 0;
     if (f64 || f32) {
+        // binary64 points form groups of four within a lane
+        if (f64 && value != 4 && value != 8)
+            return fail(ctx, HK_EINVAL, "%s must be 4 or 8 (got %lld)", name, (long long)value);
         if (value != 2 && value != 4 && value != 8)
             return fail(ctx, HK_EINVAL, "%s must be 2, 4 or 8 (got %lld)", name, (long long)value);
         if (int rc = check_ctx(ctx)) return rc;

@@ -53,13 +53,15 @@ struct alignas(16) WingIdx {
     int32_t wlo, whi;
     int32_t g3lo, g3hi;
     int32_t clo, chi;
-    int32_t flags;  // kPairSafe
+    int32_t flags;  // kGroupSafe
     int32_t jc;     // nearest grid index to the centre (binary32 path)
 };
 static_assert(sizeof(WingIdx) == 32, "WingIdx layout");
-// Products of two denominators stay in binary64 range (alpha^2 > 1e-40,
-// Gamma_L^2 < 1e20: every physical line); otherwise points are not paired.
-constexpr int32_t kPairSafe = 1;
+// Products of four denominators stay in binary64 range: alpha^2 >= 1e-22 and
+// dv^2 + Gamma_L^2 <= 1e20 at every grid point (every physical line and
+// grid) put each 3-node denominator m = D P within about 1e-60 .. 1e60 (D >=
+// 100 alpha^2 outside the core region).  Otherwise points are not grouped.
+constexpr int32_t kGroupSafe = 1;
 
 // Per-line record of the core-region series, read only for lines whose
 // a^2+u^2 < 100 interval meets a wavefront's points.

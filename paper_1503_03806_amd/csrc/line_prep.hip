@@ -93,10 +93,13 @@ __global__ __launch_bounds__(256) void line_prep_f64_kernel(LinesDev L, PrepPara
         w.M0 = w.G2 * (GH * GH);
         w.Bn = 2.0 * w.G2 - 1.5 * a2;
         w.Cn = GH * (2.0 * GH + w.G2) * (1.0 / 3.0);
-        x.flags = (a2 > 1e-40 && w.G2 < 1e20) ? kPairSafe : 0;
         x.jc = 0;
     }
     const int32_t n = pp.n_points;
+    {
+        const double span = fmax(fabs(nu0 - pp.nu_min), fabs(fma((double)(n - 1), pp.dnu, pp.nu_min) - nu0));
+        x.flags = (alpha * alpha >= 1e-22 && fma(span, span, w.G2) <= 1e20) ? kGroupSafe : 0;
+    }
     {
         // the cutoff: absolute, or a multiple of the line's Lorentz HWHM
         const double cut = pp.cutoff_lorentz > 0.0 ? pp.cutoff_lorentz * GL : pp.cutoff;

@@ -59,15 +59,15 @@ __device__ inline double qrcp(double den)
 
 // The path of one line for the points [run0, run1] of a wavefront; run_end
 // is the run's nominal last point.  A run cut short by the grid end takes
-// the general path, which evaluates points whose pair partner lies beyond
-// the grid unpaired.
+// the general path, which evaluates points whose group reaches beyond the
+// grid one by one.
 __device__ inline uint32_t classify(const WingIdx& r, int32_t run0, int32_t run1, int32_t run_end)
 {
     if (run0 > run1 || r.whi < run0 || r.wlo > run1) return kSkip;
     if (run1 < run_end) return kGeneral;
     const bool full = r.wlo <= run0 && r.whi >= run1;
     const bool nocore = run1 < r.clo || run0 > r.chi;
-    if (!(full && nocore && (r.flags & kPairSafe))) return kGeneral;
+    if (!(full && nocore && (r.flags & kGroupSafe))) return kGeneral;
     if (run1 < r.g3lo || run0 > r.g3hi) return kGH1;
     if (r.g3lo <= run0 && r.g3hi >= run1) return kGH3;
     return kGeneral;
@@ -83,14 +83,16 @@ __device__ inline void gh3_nm(double dv, double M2, double M1, double M0, double
     m = fma(fma(q + M2, q, M1), q, M0);
 }
 
-// Points pair up to share one reciprocal: 1/da = db / (da db).  Point j
-// pairs with j + 64 when floor(j / 64) is even (runs start at multiples of
-// 128), and each pair type has one fixed sequence of operations, so a
+// Points form groups of four that share one reciprocal (the binary64
+// reciprocal issues at a quarter of the FMA rate): with d_0 .. d_3 the
+// group's denominators, P01 = d_0 d_1, P23 = d_2 d_3, c = rcp(P01 P23) Lg,
+// 1/d_0 = (c P23) d_1 / Lg and so on.  Point j groups with j + 64, j + 128
+// and j + 192 when floor(j / 64) is a multiple of 4 (runs start at multiples
+// of 256), and each group type has one fixed sequence of operations, so a
 // point's value has the same bits whichever path or tile shape computes it:
-//   both 1-node:  c = rcp(Da Db) Lg;           acc += c Db
-//   both 3-node:  c = rcp(ma mb) Lg;           acc += (c mb) na
-//   mixed:        c = rcp(den_a den_b) Lg;     acc += (c den_b) num_a
-// (num = 1 for a 1-node point).
+//   all 1-node:  acc_0 += (c P23) * d_1   (one fma; likewise for the others)
+//   otherwise:   acc_0 += ((c P23) d_1) * num_0
+// (num = 1 for a 1-node point, n of the 3-node rule otherwise).
 // Lines [L0, L1) at the points of grid tile t of one state (record
 // pointers already offset to the state): out[j - obase] = the ordered sum,
 // or += it with accumulate.
@@ -99,7 +101,7 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                                               const WingIdx* __restrict__ idx, double nu_min, double dnu, int32_t n,
                                               double* __restrict__ out, int64_t obase, int accumulate)
 {
-    static_assert(kP % 2 == 0, "points are processed in pairs");
+    static_assert(kP % 4 == 0, "points are processed in groups of four");
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ WingRec tile[kTL];
     __shared__ uint8_t code[kWaves][kTL];  // path of each staged line, per wavefront
@@ -154,12 +156,20 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                 do {
                     const double nu0 = tile[k].nu0, Lg = tile[k].Lg, G2 = tile[k].G2;
 #pragma unroll
-                    for (int p = 0; p < kP; p += 2) {
-                        const double da = nuj[p] - nu0, db = nuj[p + 1] - nu0;
-                        const double Da = fma(da, da, G2), Db = fma(db, db, G2);
-                        const double c = qrcp(Da * Db) * Lg;
-                        acc[p] = fma(c, Db, acc[p]);
-                        acc[p + 1] = fma(c, Da, acc[p + 1]);
+                    for (int p = 0; p < kP; p += 4) {
+                        double D[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const double dv = nuj[p + e] - nu0;
+                            D[e] = fma(dv, dv, G2);
+                        }
+                        const double P01 = D[0] * D[1], P23 = D[2] * D[3];
+                        const double c = qrcp(P01 * P23) * Lg;
+                        const double c01 = c * P23, c23 = c * P01;
+                        acc[p] = fma(c01, D[1], acc[p]);
+                        acc[p + 1] = fma(c01, D[0], acc[p + 1]);
+                        acc[p + 2] = fma(c23, D[3], acc[p + 2]);
+                        acc[p + 3] = fma(c23, D[2], acc[p + 3]);
                     }
                     ++k;
                 } while (k < cnt && path_of(k) == kGH1);
@@ -170,13 +180,17 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                     const double nu0 = tile[k].nu0, Lg = tile[k].Lg;
                     const double M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Bn = tile[k].Bn, Cn = tile[k].Cn;
 #pragma unroll
-                    for (int p = 0; p < kP; p += 2) {
-                        double na, ma, nb, mb;
-                        gh3_nm(nuj[p] - nu0, M2, M1, M0, Bn, Cn, na, ma);
-                        gh3_nm(nuj[p + 1] - nu0, M2, M1, M0, Bn, Cn, nb, mb);
-                        const double c = qrcp(ma * mb) * Lg;
-                        acc[p] = fma(c * mb, na, acc[p]);
-                        acc[p + 1] = fma(c * ma, nb, acc[p + 1]);
+                    for (int p = 0; p < kP; p += 4) {
+                        double nn[4], mm[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) gh3_nm(nuj[p + e] - nu0, M2, M1, M0, Bn, Cn, nn[e], mm[e]);
+                        const double P01 = mm[0] * mm[1], P23 = mm[2] * mm[3];
+                        const double c = qrcp(P01 * P23) * Lg;
+                        const double c01 = c * P23, c23 = c * P01;
+                        acc[p] = fma(c01 * mm[1], nn[0], acc[p]);
+                        acc[p + 1] = fma(c01 * mm[0], nn[1], acc[p + 1]);
+                        acc[p + 2] = fma(c23 * mm[3], nn[2], acc[p + 2]);
+                        acc[p + 3] = fma(c23 * mm[2], nn[3], acc[p + 3]);
                     }
                     ++k;
                 } while (k < cnt && path_of(k) == kGH3);
@@ -185,19 +199,19 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
             const double nu0 = tile[k].nu0, Lg = tile[k].Lg, G2 = tile[k].G2;
             const double M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Bn = tile[k].Bn, Cn = tile[k].Cn;
             // general path: window edges, region edges, core points (left to
-            // the core kernel), the grid end, lines outside the pairing range
+            // the core kernel), the grid end, lines outside the grouping range
             // (rare: the index record is read from memory, not staged)
             const WingIdx ri = idx[base + k];
             const int32_t wlo = ri.wlo, whi = ri.whi;
             const int32_t g3lo = ri.g3lo, g3hi = ri.g3hi;
             const int32_t clo = ri.clo, chi = ri.chi;
-            const bool safe = (ri.flags & kPairSafe) != 0;
+            const bool safe = (ri.flags & kGroupSafe) != 0;
 #pragma unroll
-            for (int p = 0; p < kP; p += 2) {
-                double num[2], den[2];
-                bool take[2], one[2], core_pt[2];
+            for (int p = 0; p < kP; p += 4) {
+                double num[4], den[4];
+                bool take[4], one[4], core_pt[4];
 #pragma unroll
-                for (int e = 0; e < 2; ++e) {
+                for (int e = 0; e < 4; ++e) {
                     const int32_t j = run0 + lane + 64 * (p + e);
                     const double dv = nuj[p + e] - nu0;
                     double n3, m3;
@@ -208,23 +222,28 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                     num[e] = one[e] ? 1.0 : n3;
                     den[e] = one[e] ? fma(dv, dv, G2) : m3;
                 }
-                if (safe && !core_pt[0] && !core_pt[1] && run0 + lane + 64 * (p + 1) < n) {
-                    const double c0 = qrcp(den[0] * den[1]);
-                    double xa, ya, xb, yb;
-                    if (one[0] && one[1]) {
-                        const double c = c0 * Lg;
-                        xa = c; ya = den[1];
-                        xb = c; yb = den[0];
+                if (safe && !core_pt[0] && !core_pt[1] && !core_pt[2] && !core_pt[3] &&
+                    run0 + lane + 64 * (p + 3) < n) {
+                    const double P01 = den[0] * den[1], P23 = den[2] * den[3];
+                    const double c = qrcp(P01 * P23) * Lg;
+                    const double c01 = c * P23, c23 = c * P01;
+                    double xs[4], ys[4];
+                    if (one[0] && one[1] && one[2] && one[3]) {
+                        xs[0] = c01; ys[0] = den[1];
+                        xs[1] = c01; ys[1] = den[0];
+                        xs[2] = c23; ys[2] = den[3];
+                        xs[3] = c23; ys[3] = den[2];
                     } else {
-                        const double c = c0 * Lg;
-                        xa = c * den[1]; ya = num[0];
-                        xb = c * den[0]; yb = num[1];
+                        xs[0] = c01 * den[1]; ys[0] = num[0];
+                        xs[1] = c01 * den[0]; ys[1] = num[1];
+                        xs[2] = c23 * den[3]; ys[2] = num[2];
+                        xs[3] = c23 * den[2]; ys[3] = num[3];
                     }
-                    acc[p] = fma(take[0] ? xa : 0.0, ya, acc[p]);
-                    acc[p + 1] = fma(take[1] ? xb : 0.0, yb, acc[p + 1]);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc[p + e] = fma(take[e] ? xs[e] : 0.0, ys[e], acc[p + e]);
                 } else {
 #pragma unroll
-                    for (int e = 0; e < 2; ++e) {
+                    for (int e = 0; e < 4; ++e) {
                         const double v = qdiv(Lg * num[e], den[e]);
                         acc[p + e] += take[e] ? v : 0.0;
                     }
@@ -510,8 +529,6 @@ hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingI
 {
     if (n_tiles == 0 || n_states == 0) return hipSuccess;
     switch (points_per_lane) {
-    case 2: return launch_wing<2>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, nu_min, dnu, n_points, kappa,
-                                  partial, accumulate, s);
     case 4: return launch_wing<4>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, nu_min, dnu, n_points, kappa,
                                   partial, accumulate, s);
     case 8: return launch_wing<8>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, nu_min, dnu, n_points, kappa,

@@ -175,6 +175,12 @@ def test_options_need_a_context_and_valid_values():
     assert hk.lib().hk_set_option(None, b"tables_autotune", 2) == hk.HK_EINVAL
     assert hk.lib().hk_set_option(None, b"tables_batch", -1) == hk.HK_EINVAL
     assert hk.lib().hk_set_option(None, b"no_such_option", 1) == hk.HK_EINVAL
+    # binary64 points form groups of four within a lane
+    assert hk.lib().hk_set_option(None, b"f64_points_per_lane", 2) == hk.HK_EINVAL
+    assert "4 or 8" in hk.hk_last_error(None)
+    assert hk.lib().hk_set_option(None, b"f32_points_per_lane", 3) == hk.HK_EINVAL
+    assert hk.lib().hk_set_option(None, b"f64_points_per_lane", 8) == hk.HK_EINVAL
+    assert "context" in hk.hk_last_error(None)
 
 
 def test_surrogate_calls_validate_arguments():

@@ -26,7 +26,7 @@ def say(*a):
 def ctx():
     c = hk.Context(0)
     yield c
-    c.set_option("f64_points_per_lane", 2)
+    c.set_option("f64_points_per_lane", 4)
     c.set_option("f32_points_per_lane", 2)
     c.close()
 
@@ -80,13 +80,14 @@ def test_split_lists_match_the_oracle(ctx, which):
 def test_split_results_do_not_depend_on_the_tile_shape(ctx, prec):
     ctx.load_lines(crowded(), COND["mass_amu"], COND["T0"])
     name = "f64_points_per_lane" if prec == hk.HK_F64 else "f32_points_per_lane"
+    shapes = (4, 8) if prec == hk.HK_F64 else (2, 4, 8)
     outs = []
-    for ppl in (2, 4, 8):
+    for ppl in shapes:
         ctx.set_option(name, ppl)
         outs.append(bits(ctx.opacity(STATE, GRID, prec)))
         say("points per lane %d: %d items" % (ppl, ctx.get_option("wing_items")))
-    ctx.set_option(name, 2)
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    ctx.set_option(name, shapes[0])
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
 
 
 @pytest.mark.parametrize("prec", [hk.HK_F64, hk.HK_F32_KAHAN])
@@ -107,7 +108,8 @@ def test_even_list_is_not_split(ctx):
     grid = {"nu_min": 0.0, "dnu": 0.01, "n_points": 3_000_000, "cutoff": 25.0}
     ctx.load_lines(lines, COND["mass_amu"], COND["T0"])
     k = ctx.opacity(STATE, grid, hk.HK_F64)
-    n_tiles = -(-grid["n_points"] // 512)
+    tile_points = 64 * 4 * ctx.get_option("f64_points_per_lane")  # four wavefronts per tile
+    n_tiles = -(-grid["n_points"] // tile_points)
     assert ctx.get_option("wing_segment_lines") == 0 and ctx.get_option("wing_items") == n_tiles
     j = np.random.default_rng(3).choice(grid["n_points"], 16, replace=False)
     for a in j:

@@ -70,7 +70,8 @@ def test_tables_match_single_state_path_and_oracle(ctx, precision):
     st = ctx.stats()
     total = 0
     for s, cond in enumerate(conds):
-        ctx.set_option("f64_points_per_lane" if precision == hk.HK_F64 else "f32_points_per_lane", 2)
+        ctx.set_option("f64_points_per_lane" if precision == hk.HK_F64 else "f32_points_per_lane",
+                       4 if precision == hk.HK_F64 else 2)
         ref_k, kap = single_state(ctx, lines, cond, grid, ppb, g, precision)
         total += ctx.stats()["evals"]
         assert np.array_equal(tab[s].view(np.uint64), ref_k.view(np.uint64)), s
