@@ -143,10 +143,12 @@ struct GValues {
 // reaching its points span segments (other segments add exact zeros).
 // Items: every (state, tile) pair in chunks of kPlanChunk tiles (dearest
 // first), each chunk holding every state's run of those tiles, a pair's
-// segments consecutive; workgroups take items in XCD-dealt chunks.
+// segments consecutive; workgroups take items in XCD-dealt chunks.  16
+// tiles of 1024 binary64 points keep the lines of the tiles an XCD runs at
+// once closer to its 4 MB L2 than 32 (measured 4% faster; 8 is no better).
 constexpr int32_t kRefTilePoints = 512;
 constexpr int64_t kNoSplit = (int64_t)1 << 62;
-constexpr int32_t kPlanChunk = 32;
+constexpr int32_t kPlanChunk = 16;
 struct WorkPlan {
     const int64_t* seg;    // [n_states] segment length (kNoSplit: not cut)
     const int64_t* first;  // [n_pairs] first item of each pair, in pair order
