@@ -83,10 +83,13 @@ static_assert(sizeof(CoreRec) == 64, "CoreRec layout");
 // and product in binary32 range; strengths carry the state's scale 2^s.
 // For point j: dv/lambda = (j - jc) du - fu, with jc the nearest grid point
 // to the centre (WingIdx.jc), du = dnu/lambda, fu = (nu0 - nu_jc)/lambda.
-//   1-node:  Lg / (q + G2),  3-node:  Lg n / ((q + G2) P)  with q = (dv/lambda)^2
-// and the 3-node coefficients B, C, Bn, Cn scaled by lambda^-2 / lambda^-4.
+//   1-node:  Lg / (q + G2),  3-node:  Lg n / m  with q = (dv/lambda)^2,
+// m = ((q + M2) q + M1) q + M0 and n = q (q + Bn) + Cn, the coefficients of
+// WingRec scaled by powers of 1/lambda.  A line with 3-node points has
+// lambda = alpha, where Bn = 2 G2 - 1.5 exactly: it is formed in the kernel
+// (lines with lambda = Gamma_L never use the 3-node rule).
 struct alignas(16) WingRec32 {
-    float du, fu, Lg, G2, B, C, Bn, Cn;
+    float du, fu, Lg, G2, M2, M1, M0, Cn;
 };
 static_assert(sizeof(WingRec32) == 32, "WingRec32 layout");
 // Core series in x units: x = |(j - jc) dx - fx|, dx = dnu/alpha,

@@ -273,12 +273,11 @@ __global__ __launch_bounds__(256) void line_prep_f32_kernel(
     r.fu = (float)(f * il);
     r.Lg = (float)ldexp(w.Lg * il * il, s);
     r.G2 = (float)(w.G2 * il * il);
-    const double a2 = alpha * alpha;
-    const double GH = w.G2 + 1.5 * a2;
-    r.B = (float)((2.0 * w.G2 - 3.0 * a2) * il * il);
-    r.C = (float)(GH * GH * il * il * il * il);
-    r.Bn = (float)(w.Bn * il * il);
-    r.Cn = (float)(w.Cn * il * il * il * il);
+    const double il2 = il * il;
+    r.M2 = (float)(w.M2 * il2);
+    r.M1 = (float)(w.M1 * il2 * il2);
+    r.M0 = (float)(w.M0 * il2 * il2 * il2);
+    r.Cn = (float)(w.Cn * il2 * il2);
     w32[i] = r;
     idx[i].jc = jc;
     CoreRec32 k;

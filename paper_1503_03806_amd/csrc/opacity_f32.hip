@@ -9,7 +9,10 @@
 //    j - jc, so no large magnitudes cancel in binary32;
 //  * units: per line lambda = alpha or Gamma_L and a per-state power-of-two
 //    scale of the strengths keep every value in binary32 range;
-//  * reciprocals: the hardware v_rcp_f32 (< 2^-23 relative), unpaired;
+//  * reciprocals: the hardware v_rcp_f32 (< 2^-23 relative); two 3-node
+//    points j and j + 64 (floor(j / 64) even) share one, 1/m_a = m_b/(m_a m_b)
+//    (3-node denominators lie within 1e5 .. 1e18 in alpha units, so their
+//    products stay in binary32 range), 1-node points take their own;
 //  * accumulation: each point sums the lines of one 256-line block (blocks
 //    aligned to global line indices) in binary32, then adds the block sum to
 //    a Kahan pair (sum, comp).  With at most 256 positive terms per block the
@@ -62,6 +65,7 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
                                               float* __restrict__ comp_out, float2* __restrict__ partial,
                                               int64_t obase, bool direct)
 {
+    static_assert(kP % 2 == 0, "3-node points pair up within a lane");
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ WingRec32 tile[kTL];
     __shared__ WingIdx tidx[kTL];
@@ -126,15 +130,22 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
             if (path == kGH3) {
                 do {
                     const float fjc = fjct[k];
-                    const float du = tile[k].du, fu = tile[k].fu, Lg = tile[k].Lg, G2 = tile[k].G2;
-                    const float B = tile[k].B, C = tile[k].C, Bn = tile[k].Bn, Cn = tile[k].Cn;
+                    const float du = tile[k].du, fu = tile[k].fu, Lg = tile[k].Lg;
+                    const float M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Cn = tile[k].Cn;
+                    const float Bn = fmaf(2.0f, tile[k].G2, -1.5f);
 #pragma unroll
-                    for (int p = 0; p < kP; ++p) {
-                        const float dv = fmaf(fj[p] - fjc, du, -fu);
-                        const float q = dv * dv;
-                        const float nn = fmaf(q, q + Bn, Cn);
-                        const float m = (q + G2) * fmaf(q, q + B, C);
-                        part[p] = fmaf(Lg, nn * rcpf(m), part[p]);
+                    for (int p = 0; p < kP; p += 2) {
+                        float nn[2], mm[2];
+#pragma unroll
+                        for (int e = 0; e < 2; ++e) {
+                            const float dv = fmaf(fj[p + e] - fjc, du, -fu);
+                            const float q = dv * dv;
+                            nn[e] = fmaf(q, q + Bn, Cn);
+                            mm[e] = fmaf(fmaf(q + M2, q, M1), q, M0);
+                        }
+                        const float cp = rcpf(mm[0] * mm[1]) * Lg;
+                        part[p] = fmaf(cp * mm[1], nn[0], part[p]);
+                        part[p + 1] = fmaf(cp * mm[0], nn[1], part[p + 1]);
                     }
                     ++k;
                 } while (k < cnt && path_of(k) == kGH3);
@@ -142,23 +153,38 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
             }
             const float fjc = fjct[k];
             const float du = tile[k].du, fu = tile[k].fu, Lg = tile[k].Lg, G2 = tile[k].G2;
-            const float B = tile[k].B, C = tile[k].C, Bn = tile[k].Bn, Cn = tile[k].Cn;
+            const float M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Cn = tile[k].Cn;
+            const float Bn = fmaf(2.0f, G2, -1.5f);
             const int32_t wlo = tidx[k].wlo, whi = tidx[k].whi;
             const int32_t g3lo = tidx[k].g3lo, g3hi = tidx[k].g3hi;
             const int32_t clo = tidx[k].clo, chi = tidx[k].chi;
 #pragma unroll
-            for (int p = 0; p < kP; ++p) {
-                const int32_t j = run0 + lane + 64 * p;
-                const bool take = j >= wlo && j <= whi && (j < clo || j > chi);
-                const bool one = j < g3lo || j > g3hi;
-                const float dv = fmaf(fj[p] - fjc, du, -fu);
-                const float q = dv * dv;
-                const float v1 = rcpf(fmaf(dv, dv, G2));
-                const float nn = fmaf(q, q + Bn, Cn);
-                const float m = (q + G2) * fmaf(q, q + B, C);
-                const float v3 = nn * rcpf(m);
-                const float acc = fmaf(Lg, one ? v1 : v3, part[p]);
-                part[p] = take ? acc : part[p];
+            for (int p = 0; p < kP; p += 2) {
+                float nn[2], mm[2], v1[2];
+                bool take[2], one[2], core_pt[2];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int32_t j = run0 + lane + 64 * (p + e);
+                    core_pt[e] = j >= clo && j <= chi;
+                    take[e] = j >= wlo && j <= whi && !core_pt[e];
+                    one[e] = j < g3lo || j > g3hi;
+                    const float dv = fmaf(fj[p + e] - fjc, du, -fu);
+                    const float q = dv * dv;
+                    v1[e] = rcpf(fmaf(dv, dv, G2));
+                    nn[e] = fmaf(q, q + Bn, Cn);
+                    mm[e] = fmaf(fmaf(q + M2, q, M1), q, M0);
+                }
+                // two 3-node points outside the core, both on the grid: the
+                // sequence of the 3-node path above
+                const bool paired = !one[0] && !one[1] && !core_pt[0] && !core_pt[1] &&
+                                    run0 + lane + 64 * (p + 1) < n;
+                const float cp = rcpf(mm[0] * mm[1]) * Lg;
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const float acc = paired ? fmaf(cp * mm[1 - e], nn[e], part[p + e])
+                                             : fmaf(Lg, one[e] ? v1[e] : nn[e] * rcpf(mm[e]), part[p + e]);
+                    part[p + e] = take[e] ? acc : part[p + e];
+                }
             }
             ++k;
         }
