@@ -45,7 +45,10 @@ PEAK_LDS_GBS = 256 * 128 * 2.4
 SURROGATE_SCHEDULE = ((20000, 5e-3), (20000, 1e-3), (20000, 2e-4))
 SURROGATE_WSCALE = 5.0  # loss weight 1/(1 + (z/5)^2)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "wing_f64_lines1e6_grid3e6_traffic.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1503_03806_amd", "csrc", "opacity_f64.hip")
+# what the dominant kernel's traffic depends on: its code, its line records
+# and the order of its work items
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1503_03806_amd", "csrc", f)
+                  for f in ("opacity_f64.hip", "hk_internal.h", "work_plan.hip", "line_prep.hip")]
 
 
 def log(*a):
@@ -53,20 +56,23 @@ def log(*a):
 
 
 def kernel_digest() -> str:
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
     """HBM bytes per launch of the dominant kernel (fetch + write) from the
-    committed counter summary, or None if the kernel source changed since the
-    counters were taken."""
+    committed counter summary, or None if the kernel's sources changed since
+    the counters were taken."""
     try:
         kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE)
                   if ":" in line and not line.startswith("#"))
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
-    if kv.get("kernel_source_sha256_16") != kernel_digest():
+    if kv.get("kernel_sources_sha256_16") != kernel_digest():
         return None
     try:
         return int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"])
