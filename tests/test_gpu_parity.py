@@ -102,6 +102,12 @@ def _cases():
     L2["A21"] = 10.0 ** rng.uniform(0, 8, 500)
     cases["self_shift_natural"] = (L2, synth.conditions(1200, 2.0),
                                    {"nu_min": 0.0, "dnu": 0.01, "n_points": 6000, "cutoff": 8.0})
+    # lines within 1e-5 cm^-1 of zero: Doppler widths below 1e-11, so their
+    # points are not grouped for a shared reciprocal (each takes its own)
+    L3 = synth.line_list(300, 3.0, seed=26)
+    L3["nu"][:100] = 10.0 ** rng.uniform(-7, -5, 100)
+    cases["near_zero_lines"] = (L3, synth.conditions(1500, 1.0),
+                                {"nu_min": 0.0, "dnu": 0.001, "n_points": 4000, "cutoff": 2.0})
     return cases
 
 
@@ -122,6 +128,15 @@ def test_small_cases_against_oracle(ctx, name):
         assert tot == st["evals"]
         for a, b in ((core, st["evals_core"]), (g3, st["evals_gh3"]), (g1, st["evals_gh1"])):
             assert abs(a - b) <= 2  # region ties at rounding distance only
+
+
+def test_ungrouped_lines_do_not_depend_on_the_tile_shape(ctx):
+    lines, cond, grid = CASES["near_zero_lines"]
+    outs = []
+    for ppl in (8, 4):
+        ctx.set_option("f64_points_per_lane", ppl)
+        outs.append(gpu_opacity(ctx, lines, cond, grid).cpu().numpy().view(np.uint64))
+    assert np.array_equal(outs[0], outs[1])
 
 
 def test_zero_points(ctx):
