@@ -7,6 +7,7 @@ slip in the oracle (a dropped term, a wrong sign or factor, a transposed
 operand, an off-by-one window) fails at least one of them.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -482,3 +483,50 @@ def test_p12b_midpoint_linear_rule_pins():
     assert np.array_equal(k[3], oracle.kdist_bin(kap[3000:], g, rule=1)[0])
     with pytest.raises(ValueError):
         oracle.kdist_bin(kap, g, rule=2)
+
+
+def _scheme_constants():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "scheme_constants.txt")
+    out = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            name, value, section = line.split()[:3]
+            assert section.startswith("§"), line
+            out[name] = float(value)
+    return out
+
+
+def test_golden_scheme_constants():
+    """The oracle against the numbers the paper prints (tests/golden)."""
+    c = _scheme_constants()
+    # region thresholds: H_V is the series just below a^2 + u^2 = 100, the
+    # 3-node rule from there, the 1-node rule from 1e6 on (exact branches)
+    for a in (0.0, 0.3, 4.0):
+        for r2, below, above in ((c["core_region_r2"], oracle.voigt_series, oracle.voigt_gh3),
+                                 (c["gh1_region_r2"], oracle.voigt_gh3, oracle.voigt_gh1)):
+            u = math.sqrt(r2 - a * a)
+            lo, hi = u * (1 - 1e-9), u * (1 + 1e-9)
+            assert a * a + lo * lo < r2 <= a * a + hi * hi
+            assert oracle.voigt_H(a, lo)[0] == below(a, lo)[0]
+            assert oracle.voigt_H(a, hi)[0] == above(a, hi)[0]
+    # reference conditions: S(T0) = S0 and, at T0 and P0 with no self
+    # broadening or natural width, Gamma_L is the tabulated coefficient
+    T0, P0 = c["reference_temperature_K"], c["reference_pressure_atm"]
+    assert synth.conditions(1500.0, 1.0)["T0"] == T0
+    assert oracle.line_strength(3.7e-21, 1234.5, 2500.0, T0, T0)[()] == 3.7e-21
+    g = oracle.lorentz_hwhm(0.0, 0.6, 0.0731, 0.31, T0, T0, P0, 0.0)[()]
+    assert abs(g - 0.0731) <= 1e-16
+    # the Lorentz-width cutoff: 500 widths is the absolute cutoff 500 Gamma_L
+    L = {"nu": np.array([1000.0]), "S_ref": np.array([1e-20]), "E_lower": np.array([300.0]),
+         "gamma_air": np.array([0.05]), "n_air": np.array([0.5])}
+    cond = synth.conditions(1500.0, 0.01)
+    GL = oracle.lorentz_hwhm(0.0, 0.5, 0.05, 0.05, cond["T"], cond["T0"], cond["P"], cond["P_self"])[()]
+    n_w = c["lorentz_cutoff_widths"]
+    grid = {"nu_min": 990.0, "dnu": 1e-4, "n_points": 200001, "cutoff": 0.0, "cutoff_lorentz": n_w}
+    k1, e1 = oracle.opacity(L, cond, grid)
+    k2, e2 = oracle.opacity(L, cond, dict(grid, cutoff=n_w * GL, cutoff_lorentz=0.0))
+    assert e1 == e2 and np.array_equal(k1, k2) and 0 < e1 < grid["n_points"]
+    # the resampling's coefficient count
+    from oracle import resample
+    assert len(resample.fit_bin(np.sort(10.0 ** np.random.default_rng(5).uniform(-25, -20, 500)))) == \
+        int(c["chebyshev_coefficients"])
