@@ -32,9 +32,15 @@ constexpr int kTL = 64 * kWaves;  // 256 lines per LDS block, one per thread
 constexpr int kMaxTerms = 2 * 10 + 14;
 enum : uint32_t { kSkip = 0, kGH1 = 1, kGH3 = 2, kGeneral = 3 };
 
-__device__ inline uint32_t classify(const WingIdx& r, int32_t run0, int32_t run1)
+// The path of one line for the points [run0, run1] of a wavefront; run_end
+// is the run's nominal last point.  A run cut short by the grid end takes
+// the general path, which leaves 3-node points whose pair partner lies
+// beyond the grid unpaired (so a point's bits do not depend on the tile
+// shape).
+__device__ inline uint32_t classify(const WingIdx& r, int32_t run0, int32_t run1, int32_t run_end)
 {
     if (run0 > run1 || r.whi < run0 || r.wlo > run1) return kSkip;
+    if (run1 < run_end) return kGeneral;
     const bool full = r.wlo <= run0 && r.whi >= run1;
     const bool nocore = run1 < r.clo || run0 > r.chi;
     if (!(full && nocore)) return kGeneral;
@@ -97,7 +103,7 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
             for (int w = 0; w < kWaves; ++w) {
                 const int32_t r0 = tile0 + w * 64 * kP;
                 const int32_t r1 = min(r0 + 64 * kP, n) - 1;
-                cw |= classify(r, r0, r1) << (8 * w);
+                cw |= classify(r, r0, r1, r0 + 64 * kP - 1) << (8 * w);
             }
             code[threadIdx.x] = cw;
         }

@@ -7,6 +7,7 @@ hardware reciprocal (a few ulps, ~5e-7), binary32 block sums of <= 256
 positive terms (<= 1.5e-5 worst case), Kahan sum of blocks (~1e-7), the
 series in binary32 (~2e-6), and the region ties of the binary64 path.
 """
+import math
 import sys
 
 import numpy as np
@@ -89,6 +90,31 @@ def test_f32_lines1e4_grid3e5_full_and_tile_shapes(ctx):
         k2 = run(ctx, lines, cond, grid).cpu().numpy()
         assert np.array_equal(kk.view(np.uint64), k2.view(np.uint64)), ppl
     ctx.set_option("f32_points_per_lane", 2)
+
+
+def test_f32_ragged_grid_end_does_not_depend_on_the_tile_shape(ctx):
+    """One line whose 3-node interval starts inside the last, cut-short run
+    of a ragged grid at 8 points per lane but covers that run whole at 2 and
+    4: the points there whose pair partner lies beyond the grid are evaluated
+    alone in every tile shape (the line's terms are the whole sum there, so
+    any difference in rounding would show)."""
+    cond = synth.conditions(1500.0, 0.01)
+    grid = {"nu_min": 1900.0, "dnu": 0.01, "n_points": 10_000 + 37, "cutoff": 25.0}
+    # the 3-node interval's lower edge (a^2 + u^2 = 1e6, a ~ 0) at point 9850:
+    # nu0 - 1000 alpha(nu0) = nu_9850, alpha proportional to nu0
+    c_alpha = oracle.doppler_hwhm(1.0, cond["T"], cond["mass_amu"])[()] / math.sqrt(math.log(2.0))
+    nu0 = (grid["nu_min"] + 9850 * grid["dnu"]) / (1.0 - 1000.0 * c_alpha)
+    lines = {"nu": np.array([nu0]), "S_ref": np.array([1e-20]), "E_lower": np.array([500.0]),
+             "gamma_air": np.array([0.05]), "n_air": np.array([0.5])}
+    outs = []
+    for ppl in (2, 4, 8):
+        ctx.set_option("f32_points_per_lane", ppl)
+        outs.append(run(ctx, lines, cond, grid).cpu().numpy())
+    ctx.set_option("f32_points_per_lane", 2)
+    for o in outs[1:]:
+        assert np.array_equal(outs[0].view(np.uint64), o.view(np.uint64))
+    ref, _ = oracle.opacity(lines, cond, grid)
+    assert rel_err(outs[0], ref).max() <= TOL
 
 
 def test_f32_accumulate_chunks(ctx):
