@@ -139,6 +139,25 @@ def test_ungrouped_lines_do_not_depend_on_the_tile_shape(ctx):
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_ragged_grid_end_does_not_depend_on_the_tile_shape(ctx):
+    """One line whose 3-node interval starts inside the last, cut-short run
+    at 8 points per lane and covers it whole at 4: points whose group
+    reaches beyond the grid are evaluated alone in both shapes."""
+    cond = synth.conditions(1500.0, 0.01)
+    grid = {"nu_min": 1900.0, "dnu": 0.01, "n_points": 10_000 + 37, "cutoff": 25.0}
+    c_alpha = oracle.doppler_hwhm(1.0, cond["T"], cond["mass_amu"])[()] / math.sqrt(math.log(2.0))
+    nu0 = (grid["nu_min"] + 9850 * grid["dnu"]) / (1.0 - 1000.0 * c_alpha)
+    lines = {"nu": np.array([nu0]), "S_ref": np.array([1e-20]), "E_lower": np.array([500.0]),
+             "gamma_air": np.array([0.05]), "n_air": np.array([0.5])}
+    outs = []
+    for ppl in (8, 4):
+        ctx.set_option("f64_points_per_lane", ppl)
+        outs.append(gpu_opacity(ctx, lines, cond, grid).cpu().numpy())
+    assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
+    ref, _ = oracle.opacity(lines, cond, grid)
+    assert_close(outs[1], ref, what="ragged end")
+
+
 def test_zero_points(ctx):
     lines, cond, _ = CASES["ragged_grid"]
     g = {"nu_min": 0.0, "dnu": 0.01, "n_points": 0, "cutoff": 5.0}
