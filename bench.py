@@ -130,22 +130,26 @@ def bench_resample(hk, torch, ctx, kappa, N, ppb, g):
             "ms_sort_fit_transmission": 1e3 * dt, "ms_fit": 1e3 * t_fit, "ms_transmission": 1e3 * t_tr}
 
 
-def kdist_stage(ms, N, ppb, n_g, key_bytes=8, lds_keys=16384):
+def kdist_stage(ms, N, ppb, n_g, key_bytes=8, sort_lds_bytes=65536):
     """The Sort + k(g) stage against HBM and LDS: its algorithmic bytes (each
-    opacity read once, k(g) written once) and, for bins sorted in LDS, the
-    keys the bitonic network reads there (each of its log2(n)(log2(n)+1)/2
-    stages reads every padded key once)."""
+    opacity read once, k(g) written once) and the keys the bitonic networks
+    read in LDS (each of log2(n)(log2(n)+1)/2 stages reads every padded key
+    once; bins above the 64 KB a sort workgroup uses are sorted in chunks of
+    that size, then merged through global memory, one pass per doubling)."""
     n_bins = -(-N // ppb)
     hbm = key_bytes * N + 8 * n_bins * n_g
     out = {"ms": ms, "hbm_bytes": hbm, "GB_s": hbm / (ms * 1e-3) / 1e9,
            "frac_of_hbm_peak": hbm / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
-    if ppb <= lds_keys:
-        npad = 1 << (ppb - 1).bit_length()
-        lg = npad.bit_length() - 1
-        lds = n_bins * (lg * (lg + 1) // 2) * npad * key_bytes
-        out.update({"bound": "lds", "lds_read_bytes": lds,
-                    "lds_read_GB_s": lds / (ms * 1e-3) / 1e9,
-                    "frac_of_lds_read_peak": lds / (ms * 1e-3) / 1e9 / PEAK_LDS_GBS})
+    cap = sort_lds_bytes // key_bytes
+    chunk = min(1 << (ppb - 1).bit_length(), cap)
+    per_bin = -(-ppb // chunk)
+    lg = chunk.bit_length() - 1
+    lds = n_bins * per_bin * (lg * (lg + 1) // 2) * chunk * key_bytes
+    merges = max(0, (per_bin - 1).bit_length())
+    out.update({"bound": "lds", "sort_chunk_keys": chunk, "chunks_per_bin": per_bin, "merge_passes": merges,
+                "merge_bytes": merges * 2 * key_bytes * N, "lds_read_bytes": lds,
+                "lds_read_GB_s": lds / (ms * 1e-3) / 1e9,
+                "frac_of_lds_read_peak": lds / (ms * 1e-3) / 1e9 / PEAK_LDS_GBS})
     return out
 
 

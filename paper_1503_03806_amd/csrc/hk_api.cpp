@@ -67,7 +67,7 @@ struct hk_ctx {
     int device = 0;
     hipStream_t own = nullptr;     // created with the context
     hipStream_t stream = nullptr;  // where work is enqueued (may be the null stream)
-    int64_t lds_bytes = 65536;
+    int64_t lds_bytes = kSortLdsBytes;  // LDS a sort workgroup may use
     std::string err;
     // line list, ascending (nu, index)
     int64_t n_lines = 0;
@@ -811,7 +811,7 @@ int hk_create(int device, hk_ctx** out)
     ctx->stream = ctx->own;
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
-        ctx->lds_bytes = lds;
+        ctx->lds_bytes = std::min<int64_t>(lds, kSortLdsBytes);
     *out = ctx;
     return HK_OK;
 }
