@@ -130,11 +130,11 @@ def bench_resample(hk, torch, ctx, kappa, N, ppb, g):
             "ms_sort_fit_transmission": 1e3 * dt, "ms_fit": 1e3 * t_fit, "ms_transmission": 1e3 * t_tr}
 
 
-def kdist_stage(ms, N, ppb, n_g, key_bytes=8, sort_lds_bytes=65536):
+def kdist_stage(ms, N, ppb, n_g, key_bytes=8, sort_lds_bytes=32768):
     """The Sort + k(g) stage against HBM and LDS: its algorithmic bytes (each
     opacity read once, k(g) written once) and the keys the bitonic networks
     read in LDS (each of log2(n)(log2(n)+1)/2 stages reads every padded key
-    once; bins above the 64 KB a sort workgroup uses are sorted in chunks of
+    once; bins above the 32 KB a sort workgroup uses are sorted in chunks of
     that size, then merged through global memory, one pass per doubling)."""
     n_bins = -(-N // ppb)
     hbm = key_bytes * N + 8 * n_bins * n_g

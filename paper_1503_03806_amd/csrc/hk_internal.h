@@ -304,11 +304,12 @@ hipError_t launch_f32_finish(const float* sum, const float* comp, const float* s
 
 // k-distribution.  elem_bytes 8 (binary64 keys) or 4 (binary32 keys).
 int64_t kdist_lds_max_points(int elem_bytes, int64_t lds_bytes);
-// LDS per sort workgroup: 64 KB lets two sort a CU's bins at once (8192
-// binary64 or 16384 binary32 keys each); larger bins are sorted in chunks of
-// that size and merged.  Measured: 300 bins of 1e4 binary64 keys take 0.22 ms
-// in two 64 KB chunks each against 0.30 ms in one 128 KB sort each.
-constexpr int64_t kSortLdsBytes = 65536;
+// LDS per sort workgroup: 32 KB (4096 binary64 or 8192 binary32 keys);
+// larger bins are sorted in chunks of that size and merged.  Measured: 300
+// bins of 1e4 binary64 keys take 0.18 ms in 32 KB chunks, 0.19 in 16 KB,
+// 0.22 in 64 KB and 0.30 ms in one 128 KB sort each (more, smaller sorts
+// share the CUs; the merges are cheap).
+constexpr int64_t kSortLdsBytes = 32768;
 hipError_t launch_kdist(const void* kappa, int elem_bytes, int64_t n_points, int64_t ppb,
                         const GValues& g, double* k_out, void* sorted_out, void* scratch,
                         int64_t lds_bytes, hipStream_t s);

@@ -215,7 +215,8 @@ def test_deterministic_and_accumulate_chunks(ctx):
 
 # ---- k-distribution: LDS and chunked/merge paths, bitwise vs the oracle ----
 
-@pytest.mark.parametrize("n,ppb", [(1, 1), (1000, 7), (100000, 1000), (16384, 8192), (20000, 8193),
+@pytest.mark.parametrize("n,ppb", [(1, 1), (1000, 7), (100000, 1000), (8192, 4096), (12000, 4097),
+                                   (16384, 8192), (20000, 8193),
                                    (30017, 10000), (65536, 16384),
                                    (50000, 16385), (300000, 100000), (250001, 100000),
                                    (40000, 40000)])
@@ -240,7 +241,8 @@ def test_kdist_matches_oracle_bitwise(ctx, n, ppb):
 # The midpoint-linear rule: the same binary64 expression on both sides,
 # evaluated without contraction, so the results agree bit for bit; binary32
 # keys enter as their exact binary64 values.
-@pytest.mark.parametrize("n,ppb", [(1, 1), (3, 2), (1000, 7), (100000, 1000), (20000, 8193), (50000, 16385),
+@pytest.mark.parametrize("n,ppb", [(1, 1), (3, 2), (1000, 7), (100000, 1000), (12000, 4097), (20000, 8193),
+                                   (50000, 16385),
                                    (250001, 100000)])
 @pytest.mark.parametrize("precision", [hk.HK_F64, hk.HK_F32_KAHAN])
 def test_kdist_linear_rule_matches_oracle_bitwise(ctx, n, ppb, precision):
