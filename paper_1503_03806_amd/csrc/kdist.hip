@@ -14,7 +14,9 @@
 namespace hk {
 namespace {
 
-constexpr int kSortThreads = 1024;
+// threads per sort workgroup (300 bins of 1e4 binary64 keys: 0.177 ms, against
+// 0.185 ms with 1024 threads and 0.188 ms with 256)
+constexpr int kSortThreads = 512;
 
 template <typename K>
 struct KeyMax;
