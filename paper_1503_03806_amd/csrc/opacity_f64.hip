@@ -31,7 +31,9 @@ constexpr int kTL = 64 * kWaves;     // line records per LDS tile: one per threa
 constexpr int kMaxTerms = 2 * 10 + 14;  // series terms: n = 1 .. 2 ceil(x) + 14, x < 10
 
 // Per-(line, wavefront) path, decided once per LDS tile.
-enum : uint32_t { kSkip = 0, kGH1 = 1, kGH3 = 2, kGeneral = 3 };
+// (kGH1Edge, kGH3Edge: a run wholly in one rule's region that the line's
+// window covers in part)
+enum : uint32_t { kSkip = 0, kGH1 = 1, kGH3 = 2, kGeneral = 3, kGH1Edge = 4, kGH3Edge = 5 };
 
 // num / den to about 2^-48 relative: the hardware reciprocal (relative
 // error below 2^-24 on gfx950) and one Newton correction of the quotient.
@@ -67,9 +69,9 @@ __device__ inline uint32_t classify(const WingIdx& r, int32_t run0, int32_t run1
     if (run1 < run_end) return kGeneral;
     const bool full = r.wlo <= run0 && r.whi >= run1;
     const bool nocore = run1 < r.clo || run0 > r.chi;
-    if (!(full && nocore && (r.flags & kGroupSafe))) return kGeneral;
-    if (run1 < r.g3lo || run0 > r.g3hi) return kGH1;
-    if (r.g3lo <= run0 && r.g3hi >= run1) return kGH3;
+    if (!(nocore && (r.flags & kGroupSafe))) return kGeneral;
+    if (run1 < r.g3lo || run0 > r.g3hi) return full ? kGH1 : kGH1Edge;
+    if (r.g3lo <= run0 && r.g3hi >= run1) return full ? kGH3 : kGH3Edge;
     return kGeneral;
 }
 
@@ -194,6 +196,57 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                     }
                     ++k;
                 } while (k < cnt && path_of(k) == kGH3);
+                continue;
+            }
+            if (path == kGH1Edge || path == kGH3Edge) {
+                // the rule's own sequence, points outside the window adding
+                // zero: the general path's sequence for these groups, bit
+                // for bit, without evaluating the other rule
+                const WingIdx ri = idx[base + k];
+                const double nu0 = tile[k].nu0, Lg = tile[k].Lg;
+                bool take[kP];
+#pragma unroll
+                for (int p = 0; p < kP; ++p) {
+                    const int32_t j = run0 + lane + 64 * p;
+                    take[p] = j >= ri.wlo && j <= ri.whi;
+                }
+                if (path == kGH1Edge) {
+                    const double G2 = tile[k].G2;
+#pragma unroll
+                    for (int p = 0; p < kP; p += 4) {
+                        double D[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const double dv = nuj[p + e] - nu0;
+                            D[e] = fma(dv, dv, G2);
+                        }
+                        const double P01 = D[0] * D[1], P23 = D[2] * D[3];
+                        const double c = qrcp(P01 * P23) * Lg;
+                        const double c01 = c * P23, c23 = c * P01;
+                        acc[p] = fma(take[p] ? c01 : 0.0, D[1], acc[p]);
+                        acc[p + 1] = fma(take[p + 1] ? c01 : 0.0, D[0], acc[p + 1]);
+                        acc[p + 2] = fma(take[p + 2] ? c23 : 0.0, D[3], acc[p + 2]);
+                        acc[p + 3] = fma(take[p + 3] ? c23 : 0.0, D[2], acc[p + 3]);
+                    }
+                } else {
+                    const double M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Bn = tile[k].Bn,
+                                 Cn = tile[k].Cn;
+#pragma unroll
+                    for (int p = 0; p < kP; p += 4) {
+                        double nn[4], mm[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) gh3_nm(nuj[p + e] - nu0, M2, M1, M0, Bn, Cn, nn[e], mm[e]);
+                        const double P01 = mm[0] * mm[1], P23 = mm[2] * mm[3];
+                        const double c = qrcp(P01 * P23) * Lg;
+                        const double c01 = c * P23, c23 = c * P01;
+                        const double x0 = c01 * mm[1], x1 = c01 * mm[0], x2 = c23 * mm[3], x3 = c23 * mm[2];
+                        acc[p] = fma(take[p] ? x0 : 0.0, nn[0], acc[p]);
+                        acc[p + 1] = fma(take[p + 1] ? x1 : 0.0, nn[1], acc[p + 1]);
+                        acc[p + 2] = fma(take[p + 2] ? x2 : 0.0, nn[2], acc[p + 2]);
+                        acc[p + 3] = fma(take[p + 3] ? x3 : 0.0, nn[3], acc[p + 3]);
+                    }
+                }
+                ++k;
                 continue;
             }
             const double nu0 = tile[k].nu0, Lg = tile[k].Lg, G2 = tile[k].G2;
