@@ -30,7 +30,9 @@ namespace {
 constexpr int kWaves = 4;
 constexpr int kTL = 64 * kWaves;  // 256 lines per LDS block, one per thread
 constexpr int kMaxTerms = 2 * 10 + 14;
-enum : uint32_t { kSkip = 0, kGH1 = 1, kGH3 = 2, kGeneral = 3 };
+// (kGH1Edge, kGH3Edge: a run wholly in one rule's region that the line's
+// window covers in part)
+enum : uint32_t { kSkip = 0, kGH1 = 1, kGH3 = 2, kGeneral = 3, kGH1Edge = 4, kGH3Edge = 5 };
 
 // The path of one line for the points [run0, run1] of a wavefront; run_end
 // is the run's nominal last point.  A run cut short by the grid end takes
@@ -43,9 +45,9 @@ __device__ inline uint32_t classify(const WingIdx& r, int32_t run0, int32_t run1
     if (run1 < run_end) return kGeneral;
     const bool full = r.wlo <= run0 && r.whi >= run1;
     const bool nocore = run1 < r.clo || run0 > r.chi;
-    if (!(full && nocore)) return kGeneral;
-    if (run1 < r.g3lo || run0 > r.g3hi) return kGH1;
-    if (r.g3lo <= run0 && r.g3hi >= run1) return kGH3;
+    if (!nocore) return kGeneral;
+    if (run1 < r.g3lo || run0 > r.g3hi) return full ? kGH1 : kGH1Edge;
+    if (r.g3lo <= run0 && r.g3hi >= run1) return full ? kGH3 : kGH3Edge;
     return kGeneral;
 }
 
@@ -155,6 +157,46 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
                     }
                     ++k;
                 } while (k < cnt && path_of(k) == kGH3);
+                continue;
+            }
+            if (path == kGH1Edge || path == kGH3Edge) {
+                // the rule's own sequence, points outside the window left as
+                // they are: the general path's sequence for these points, bit
+                // for bit, without evaluating the other rule
+                const float fjc = fjct[k];
+                const float du = tile[k].du, fu = tile[k].fu, Lg = tile[k].Lg, G2 = tile[k].G2;
+                const int32_t wlo = tidx[k].wlo, whi = tidx[k].whi;
+                if (path == kGH1Edge) {
+#pragma unroll
+                    for (int p = 0; p < kP; ++p) {
+                        const int32_t j = run0 + lane + 64 * p;
+                        const float dv = fmaf(fj[p] - fjc, du, -fu);
+                        const float acc = fmaf(Lg, rcpf(fmaf(dv, dv, G2)), part[p]);
+                        part[p] = (j >= wlo && j <= whi) ? acc : part[p];
+                    }
+                } else {
+                    const float M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Cn = tile[k].Cn;
+                    const float Bn = fmaf(2.0f, G2, -1.5f);
+#pragma unroll
+                    for (int p = 0; p < kP; p += 2) {
+                        float nn[2], mm[2];
+#pragma unroll
+                        for (int e = 0; e < 2; ++e) {
+                            const float dv = fmaf(fj[p + e] - fjc, du, -fu);
+                            const float q = dv * dv;
+                            nn[e] = fmaf(q, q + Bn, Cn);
+                            mm[e] = fmaf(fmaf(q + M2, q, M1), q, M0);
+                        }
+                        const float cp = rcpf(mm[0] * mm[1]) * Lg;
+#pragma unroll
+                        for (int e = 0; e < 2; ++e) {
+                            const int32_t j = run0 + lane + 64 * (p + e);
+                            const float acc = fmaf(cp * mm[1 - e], nn[e], part[p + e]);
+                            part[p + e] = (j >= wlo && j <= whi) ? acc : part[p + e];
+                        }
+                    }
+                }
+                ++k;
                 continue;
             }
             const float fjc = fjct[k];
