@@ -30,12 +30,14 @@ if ROOT not in sys.path:
 
 WORKLOAD = "lines1e6_grid3e6"
 PEAK_FP64_TFLOPS = 78.6  # MI355X binary64 vector peak
-# Algorithmic flops per line-point evaluation, by region, counted from the
-# formulas as written (+, -, *, / and each exp/sin/cos/erfcx as one flop, an
-# fma as two): 1-node rule S G/(pi (dv^2 + G^2)) plus the offset dv and the
-# accumulation: 5; 3-node rule, three weighted Lorentzians: 16; core series
-# with its average of 24 terms at 10 flops each plus 18 of set-up: 258.
-FLOPS_PER_EVAL = {"gh1": 5, "gh3": 16, "core": 258}
+# Algorithmic work per line-point evaluation, by region, in the scope
+# table's count: 7 operations common to every evaluation (offset, scaling,
+# square, radius, region compare, line strength, accumulation), then for the
+# 1-node rule one reciprocal (8); for the 3-node rule ~9 operations and 3
+# reciprocals (19); for the series (2 ceil(x) + 14) terms of ~10 operations
+# and a reciprocal each -- 24 terms on average over the series region -- plus
+# erfcx, sin/cos and the two exponentials of the set-up (7 + 24 * 11 + 6 = 277).
+FLOPS_PER_EVAL = {"gh1": 8, "gh3": 19, "core": 277}
 DOMINANT_KERNEL = "wing_f64_kernel"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 # LDS read rate assumed for the sort: 32 banks x 4 B per clock per CU, 256 CUs,
@@ -80,23 +82,64 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(w, points: int):
+def cpu_baseline(w, points: int, one_thread_bins: int, kappa_gpu=None, k_gpu=None):
+    """The oracle, built -O3 -march=native on this host, timed on all host
+    threads over `points` grid points (whole bins, centred; the whole grid
+    by default) and on one thread over `one_thread_bins` bins, opacity +
+    k(g) each.  With the GPU's binary64 grid and k(g) table (host arrays),
+    also their error against the oracle's: max and p99.9 per bin for kappa,
+    max per bin for k(g)."""
+    import tempfile
+
+    import numpy as np
+
     import oracle
+    tmpdir = tempfile.mkdtemp(prefix="oracle_native")
+    oracle.use_native(os.path.join(tmpdir, "liboracle_native.so"))
     lines, cond, grid = w.lines(), w.conditions(), w.grid()
     N = grid["n_points"]
     ppb = w.points_per_bin
-    j0 = (max(N - points, 0) // 2 // ppb) * ppb  # centred, whole bins
-    j1 = min(j0 + points, N)
     g, _ = oracle.g_nodes(w.n_g)
-    t0 = time.perf_counter()
-    kap, evals = oracle.opacity(lines, cond, grid, j0, j1)
-    oracle.kdist(kap, ppb, g)
-    dt = time.perf_counter() - t0
-    return {"value": evals / dt, "unit": "evals/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "grid points %d..%d (%d of %d bins) of %s, all %d lines: %d evals "
-                      "in %.2f s, opacity + k(g)" % (j0, j1, (j1 - j0) // ppb, N // ppb,
-                                                    w.name, len(lines["nu"]), evals, dt)}
+
+    def run(n_pts):
+        j0 = (max(N - n_pts, 0) // 2 // ppb) * ppb  # centred, whole bins
+        j1 = min(j0 + n_pts, N)
+        t0 = time.perf_counter()
+        kap, evals = oracle.opacity(lines, cond, grid, j0, j1)
+        kd = oracle.kdist(kap, ppb, g)
+        return j0, j1, kap, kd, evals, time.perf_counter() - t0
+
+    cores = oracle.num_threads()
+    j0, j1, kap, kd, evals, dt = run(points)
+    rec = {"value": evals / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
+           "build": "gcc -O3 -march=native -ffp-contract=off, OpenMP static schedule",
+           "sample": "grid points %d..%d (%d of %d bins) of %s, all %d lines: %d evals "
+                     "in %.2f s, opacity + k(g)" % (j0, j1, (j1 - j0) // ppb, N // ppb,
+                                                   w.name, len(lines["nu"]), evals, dt)}
+    if kappa_gpu is not None and j0 == 0 and j1 == N:
+        pos = kap > 0
+        assert np.array_equal(pos, kappa_gpu > 0)
+        e = np.zeros(N)
+        e[pos] = np.abs(kappa_gpu[pos] / kap[pos] - 1.0)
+        eb = e.reshape(-1, ppb)
+        ek = np.abs(k_gpu / kd - 1.0).max(axis=1)
+
+        def r3(a):
+            return [float("%.3g" % v) for v in a]
+        rec["error_vs_oracle"] = {
+            "what": "relative error of the GPU binary64 step's results against the oracle's, per bin",
+            "kappa_max": float(eb.max()), "kappa_p999_worst_bin": float(np.quantile(eb, 0.999, axis=1).max()),
+            "kg_max": float(ek.max()), "bins": int(eb.shape[0]),
+            "kappa_max_per_bin": r3(eb.max(axis=1)),
+            "kappa_p999_per_bin": r3(np.quantile(eb, 0.999, axis=1)),
+            "kg_max_per_bin": r3(ek)}
+    oracle.set_num_threads(1)
+    j0, j1, _, _, evals1, dt1 = run(one_thread_bins * ppb)
+    oracle.set_num_threads(cores)
+    rec["one_thread"] = {"value": evals1 / dt1, "unit": "evals/s", "cores": 1,
+                         "sample": "grid points %d..%d (%d bins): %d evals in %.2f s, opacity + k(g)"
+                                   % (j0, j1, (j1 - j0) // ppb, evals1, dt1)}
+    return rec
 
 
 def bench_resample(hk, torch, ctx, kappa, N, ppb, g):
@@ -279,7 +322,7 @@ def bench_surrogate(hk, torch, ctx, n_lines: int = 0, train_steps: int = 0):
         dt = (time.perf_counter() - t0) / 2
         tm = ctx.timing()
         ctx.set_timing(False)
-        res[name] = (k, dt, {kk: v[0] / max(v[1], 1) for kk, v in tm.items()})
+        res[name] = (k, dt, {kk: v[0] / max(v[1], 1) for kk, v in tm.items()}, ctx.stats())
     evals = ctx.stats()["evals"]
     ref = res["f64"][0]
     out = {"workload": w.name if not n_lines else "%s (%d lines)" % (w.name, n_lines),
@@ -287,10 +330,15 @@ def bench_surrogate(hk, torch, ctx, n_lines: int = 0, train_steps: int = 0):
            "train_samples": 10_000_000, "train_steps": int(len(hist)), "train_s": train_s,
            "loss_first": float(hist[0]), "loss_last100": float(hist[-100:].mean()),
            "certified_cells": count, "cells": int(err.size), "budget": 2e-5}
-    for name, (k, dt, stage) in res.items():
+    for name, (k, dt, stage, stt) in res.items():
         pos = ref > 0
         out[name] = {"ms": 1e3 * dt, "evals_per_s": evals / dt, "stage_ms": stage,
                      "max_rel_err_vs_f64": float(((k[pos] - ref[pos]).abs() / ref[pos]).max())}
+        if name == "f32_surrogate":
+            out[name]["evals_surrogate"] = stt["evals_surrogate"]
+            out[name]["network_share_of_series_region"] = stt["evals_surrogate"] / max(stt["evals_core"], 1)
+    out["series_kernel_ms"] = {"f32_kahan": res["f32_kahan"][2]["core"],
+                               "f32_surrogate": res["f32_surrogate"][2]["core"]}
     out["speedup_surrogate_vs_f64"] = res["f64"][1] / res["f32_surrogate"][1]
     out["speedup_surrogate_vs_f32"] = res["f32_kahan"][1] / res["f32_surrogate"][1]
     return out
@@ -313,7 +361,9 @@ def main(argv=None):
     ap.add_argument("--surrogate-train-steps", type=int, default=0,
                     help="Adam steps of the surrogate training (default: the full recipe)")
     ap.add_argument("--cpu-points", type=int, default=3000000,
-                    help="grid points in the oracle's timed sample")
+                    help="grid points in the oracle's timed sample (all threads)")
+    ap.add_argument("--cpu-one-thread-bins", type=int, default=8,
+                    help="bins in the oracle's one-thread timed sample")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (counter "
                          "calibration)")
@@ -366,6 +416,7 @@ def main(argv=None):
         f32_elapsed, f32_tm = timed(hk.HK_F32_KAHAN, max(1, a.steps // 2))
     elapsed, tm = timed(hk.HK_F64, a.steps)
     st = ctx.stats()
+    kappa_host, k_host = kappa.cpu().numpy(), k_out.cpu().numpy()  # for the error against the oracle
     if a.calib_copy_mib:
         n = a.calib_copy_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -381,6 +432,11 @@ def main(argv=None):
     op_ms = tm["opacity"][0] / max(tm["opacity"][1], 1)
     flops = FLOPS_PER_EVAL["gh1"] * st["evals_gh1"] + FLOPS_PER_EVAL["gh3"] * st["evals_gh3"]
     achieved = flops / (op_ms * 1e-3) / 1e12
+    step_flops = flops + FLOPS_PER_EVAL["core"] * st["evals_core"]
+    # the wing's algorithmic bytes: each line record (64 B) read once, each
+    # grid value (8 B) written once
+    alg_bytes = 64 * len(lines["nu"]) + 8 * N
+    traffic = measured_traffic()
     rec = {
         "metric": "Voigt line-point evals/s (opacity + k(g) wall time per step in ms_per_step)",
         "value": evals * a.steps / elapsed,
@@ -400,10 +456,16 @@ def main(argv=None):
                       "on two streams and overlap; 'line_prep' includes tile ranges and work plans",
         "roofline": {"bound": "alu", "kernel": DOMINANT_KERNEL,
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(),
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "flops_per_launch": flops, "launch_ms": op_ms,
+                     "flops_per_eval": FLOPS_PER_EVAL,
+                     "algorithmic_bytes": alg_bytes,
+                     "traffic_over_algorithmic": (traffic / alg_bytes) if traffic else None,
                      "concurrent_with": "core_f64_kernel on a second stream (launch_ms includes "
-                                        "the time the two share the device)"},
+                                        "the time the two share the device)",
+                     "step": {"flops": step_flops, "achieved": step_flops / (ms_step * 1e-3) / 1e12,
+                              "frac": step_flops / (ms_step * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                              "what": "wing + series algorithmic work over the whole step's wall time"}},
     }
     if f32_tm is not None:
         f32_steps = max(1, a.steps // 2)
@@ -420,7 +482,9 @@ def main(argv=None):
         rec["stream"] = bench_stream(hk, torch, ctx)
     if not a.no_cpu_baseline:
         log("bench: timing the oracle on a sample")
-        rec["cpu_baseline"] = cpu_baseline(w, a.cpu_points)
+        rec["cpu_baseline"] = cpu_baseline(w, a.cpu_points, a.cpu_one_thread_bins, kappa_host, k_host)
+        if "error_vs_oracle" in rec["cpu_baseline"]:
+            rec["error_vs_oracle"] = rec["cpu_baseline"].pop("error_vs_oracle")
     if not a.no_surrogate:
         rec["surrogate"] = bench_surrogate(hk, torch, ctx, a.surrogate_lines, a.surrogate_train_steps)
     ctx.close()

@@ -126,6 +126,10 @@ typedef struct {
     int64_t evals_gh3;   /* 100 <= a^2 + u^2 < 1e6: 3-node Gauss-Hermite */
     int64_t evals_gh1;   /* a^2 + u^2 >= 1e6: 1-node Gauss-Hermite */
     int64_t n_lines;     /* lines in the context */
+    int64_t evals_surrogate; /* of evals_core, the points the learned
+                                surrogate evaluated (HK_F32_SURROGATE; the
+                                rest took the series); 0 for other precisions
+                                and after hk_tables */
 } hk_run_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -148,11 +152,20 @@ int hk_sync(hk_ctx* ctx);
  * this thread).  Never NULL; valid until the next call. */
 const char* hk_last_error(const hk_ctx* ctx);
 
-/* Copy a line list to the device, ordered by ascending (nu, input index),
- * replacing any earlier one.  Inputs are validated (finite values, nu > 0,
- * S_ref, gamma >= 0); rejected lists leave the context unchanged.
- * Synchronous with respect to the host arrays: they may be freed on return. */
-int hk_load_lines(hk_ctx* ctx, const hk_lines* lines, const hk_species* species);
+/* Copy a line list (§2.3: the database fields the method uses) into the
+ * context, ordered by ascending (nu, input index) -- the order in which the
+ * opacity kernels walk the lines (§2.5) -- replacing any earlier one.
+ *   lines_on_device == 0: lines' arrays are [host] memory;
+ *   lines_on_device != 0: they are [device] memory of the context's device
+ *     (e.g. torch tensors), read but not modified.
+ * Inputs are validated (finite values, nu > 0, S_ref, gamma, A21 >= 0; on
+ * the host for host arrays, by a kernel for device arrays); HK_EINVAL names
+ * the first offending line, and a rejected list leaves the context
+ * unchanged.  A list not already in non-decreasing nu is ordered on the
+ * device by a stable radix sort of nu's bit patterns (temporary device
+ * memory of ~24 B per line, released on return; a host list is first copied
+ * as it is).  Synchronous: the arrays may be freed or rewritten on return. */
+int hk_load_lines(hk_ctx* ctx, const hk_lines* lines, const hk_species* species, int lines_on_device);
 
 /* ---- Input (§2.3, §3.5): HITRAN / HITEMP line records -------------------- */
 
@@ -198,8 +211,13 @@ int hk_read_par(const char* path, int64_t first, int32_t molecule, const hk_line
  * segment order.  Results are bitwise reproducible, do not depend on the
  * tuning options, and agree bit for bit with hk_tables.
  *
- * kappa is [device] double[n_points] for both precisions; comp must be NULL
- * (reserved).
+ * kappa is [device] double[n_points] for both precisions.  comp must be
+ * NULL: it is reserved for a caller-held binary32 compensation term, which
+ * this library does not need -- the binary32 path keeps its Kahan pair
+ * (sum, compensation) in the context's scratch and folds it into kappa in
+ * binary64 at the end of the call, so kappa carries the compensated sum to
+ * binary64 rounding, and accumulate adds each call's result to kappa in
+ * binary64 (chunks of a list, species of a mixture).
  * precision HK_F64: every step in binary64.
  * precision HK_F32_KAHAN: S(T), widths, windows and region intervals in
  *   binary64; profiles in binary32 with strengths scaled by a per-state power
@@ -379,6 +397,23 @@ int hk_surrogate_eval(hk_ctx* ctx, const float* x, const float* y, int64_t n, fl
  * err: [host] double[HK_SURR_CELLS_Y][HK_SURR_CELLS_X] or NULL;
  * n_certified: [host] or NULL.  Synchronises. */
 int hk_surrogate_certify(hk_ctx* ctx, double budget, double* err, int32_t* n_certified);
+
+/* The trained surrogate as one self-contained byte string, to be kept and
+ * loaded into another context (or process) without training again:
+ * a 32-byte header ("HKSURR01", int32 parameter count, int32 cell count,
+ * int32 certified flag, int32 0, binary64 budget), the binary32 parameters
+ * (the layout above) and, when certified, the binary64 error of every cell
+ * (cell (ix, iy) at iy * HK_SURR_CELLS_X + ix); little-endian.
+ * hk_surrogate_save: with blob NULL only *size is set (the bytes needed);
+ * else blob [host] of `capacity` bytes receives them (synchronises).
+ * HK_ENOTREADY without parameters. */
+int hk_surrogate_save(hk_ctx* ctx, void* blob, size_t capacity, size_t* size);
+/* hk_surrogate_load: blob [host] of `size` bytes from hk_surrogate_save.
+ * Sets the parameters as hk_surrogate_set_params does (Adam's state reset)
+ * and, if the blob holds a certification, restores it with its budget, so
+ * HK_F32_SURROGATE runs at once.  HK_EINVAL for a blob of another layout,
+ * size or with non-finite values; the context is then unchanged. */
+int hk_surrogate_load(hk_ctx* ctx, const void* blob, size_t size);
 
 /* ---- helpers -------------------------------------------------------------- */
 

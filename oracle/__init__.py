@@ -20,18 +20,34 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
+# -O3 without fast-math and without floating-point contraction: every
+# expression is evaluated as written, in the order written, so the results
+# are the same bits whatever the instruction set.  The in-tree library
+# targets x86-64-v2 (it may run on another host than the one that built it);
+# the timed baseline builds a -march=native copy on the host it runs on.
+_FLAGS = ["-std=gnu11", "-O3", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math"]
 
-def build(force: bool = False) -> str:
-    """Compile ``liboracle.so`` with gcc: -O2, OpenMP, no fast-math and no
-    floating-point contraction (each expression evaluated as written)."""
+
+def build(force: bool = False, native: bool = False, path: str | None = None) -> str:
+    """Compile the oracle with gcc (see _FLAGS): ``liboracle.so`` for
+    x86-64-v2, or with native=True a copy for this host's own CPU at `path`."""
     src = os.path.join(_HERE, "oracle.c")
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
-        tmp = _SO + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-std=gnu11", "-O2", "-fPIC", "-shared", "-fopenmp",
-               "-ffp-contract=off", "-fno-fast-math", "-o", tmp, src, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _SO)
-    return _SO
+    so = path or _SO
+    if native or force or not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(src):
+        tmp = so + ".tmp%d" % os.getpid()
+        arch = "-march=native" if native else "-march=x86-64-v2"
+        subprocess.run(["gcc"] + _FLAGS + [arch, "-o", tmp, src, "-lm"], check=True)
+        os.replace(tmp, so)
+    return so
+
+
+def use_native(path: str) -> None:
+    """Build a -march=native copy of the oracle at `path` and use it for
+    every later call of this module (the timed CPU baseline)."""
+    global _lib, _SO
+    build(native=True, path=path)
+    _SO = path
+    _lib = None
 
 
 class _Lines(C.Structure):
@@ -74,6 +90,7 @@ def lib():
         L.ora_kdist_bin.argtypes = [pd, i64, i32, pd, i32, pd, pd]; L.ora_kdist_bin.restype = i32
         L.ora_kdist.argtypes = [pd, i64, i64, i32, pd, i32, pd]; L.ora_kdist.restype = i32
         L.ora_num_threads.argtypes = []; L.ora_num_threads.restype = i32
+        L.ora_set_num_threads.argtypes = [i32]; L.ora_set_num_threads.restype = i32
         _lib = L
     return _lib
 
@@ -92,6 +109,11 @@ def const(name: str) -> float:
 
 def num_threads() -> int:
     return lib().ora_num_threads()
+
+
+def set_num_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops from now on; returns the count."""
+    return lib().ora_set_num_threads(int(n))
 
 
 # ---- §2.3 ------------------------------------------------------------------

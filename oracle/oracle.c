@@ -69,6 +69,19 @@ int ora_num_threads(void)
 #endif
 }
 
+/* Threads of the parallel loops from now on (n >= 1); returns the count in
+ * effect afterwards.  Results do not depend on it: every point and bin is
+ * computed by one thread in the same order. */
+int ora_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+    return ora_num_threads();
+}
+
 /* ---------------------------------------------------------------- §2.3 -- */
 
 /* eq. (18): S/S0 = (Q0/Q) exp(-dE/kT + dE/kT0) [1-exp(-hc nu/kT)] /

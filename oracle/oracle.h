@@ -127,6 +127,7 @@ int ora_kdist(const double* kappa, int64_t n_points, int64_t points_per_bin,
               int n_g, const double* g, int rule, double* k_out);
 
 int ora_num_threads(void);
+int ora_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

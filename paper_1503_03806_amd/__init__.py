@@ -23,6 +23,7 @@ __all__ = ["HK_OK", "HK_EINVAL", "HK_ENOMEM", "HK_EDEVICE", "HK_EUNSUPPORTED", "
            "HK_SURR_N_PARAMS", "HK_SURR_CELLS_X", "HK_SURR_CELLS_Y", "hk_train_cfg",
            "hk_surrogate_labels", "hk_surrogate_set_params", "hk_surrogate_get_params",
            "hk_surrogate_grad", "hk_surrogate_train", "hk_surrogate_eval", "hk_surrogate_certify",
+           "hk_surrogate_save", "hk_surrogate_load",
            "hk_resample", "hk_transmission", "hk_transmission_direct", "HK_MAX_COEF",
            "HK_TRANSMISSION_NODES", "hk_opacity_stream", "hk_read_par", "HK_MAX_CHUNKS", "Context",
            "LIB_PATH"]
@@ -73,7 +74,7 @@ class hk_bins(C.Structure):
 
 class hk_run_stats(C.Structure):
     _fields_ = [(f, C.c_int64) for f in ("evals", "evals_core", "evals_gh3", "evals_gh1",
-                                         "n_lines")]
+                                         "n_lines", "evals_surrogate")]
 
 
 HK_STAGE_LINE_PREP, HK_STAGE_OPACITY, HK_STAGE_KDIST, HK_STAGE_CORE, HK_N_STAGES = 0, 1, 2, 3, 4
@@ -107,7 +108,7 @@ def lib():
         L.hk_set_stream.argtypes = [vp, vp]; L.hk_set_stream.restype = i32
         L.hk_sync.argtypes = [vp]; L.hk_sync.restype = i32
         L.hk_last_error.argtypes = [vp]; L.hk_last_error.restype = C.c_char_p
-        L.hk_load_lines.argtypes = [vp, C.POINTER(hk_lines), C.POINTER(hk_species)]
+        L.hk_load_lines.argtypes = [vp, C.POINTER(hk_lines), C.POINTER(hk_species), i32]
         L.hk_load_lines.restype = i32
         L.hk_opacity.argtypes = [vp, C.POINTER(hk_state), C.POINTER(hk_grid), i32, vp, vp, i32]
         L.hk_opacity.restype = i32
@@ -134,12 +135,14 @@ def lib():
         L.hk_surrogate_train.argtypes = [vp, vp, vp, vp, i64, C.POINTER(hk_train_cfg), vp]
         L.hk_surrogate_eval.argtypes = [vp, vp, vp, i64, vp, vp]
         L.hk_surrogate_certify.argtypes = [vp, C.c_double, vp, C.POINTER(C.c_int32)]
+        L.hk_surrogate_save.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
+        L.hk_surrogate_load.argtypes = [vp, vp, C.c_size_t]
         L.hk_resample.argtypes = [vp, vp, i32, i64, i64, C.c_int32, vp]
         L.hk_transmission.argtypes = [vp, vp, i64, C.c_int32, vp, C.c_int32, vp]
         L.hk_transmission_direct.argtypes = [vp, vp, i32, i64, i64, vp, C.c_int32, vp]
         for f in ("hk_resample", "hk_transmission", "hk_transmission_direct"):
             getattr(L, f).restype = i32
-        for f in ("labels", "set_params", "get_params", "grad", "train", "eval", "certify"):
+        for f in ("labels", "set_params", "get_params", "grad", "train", "eval", "certify", "save", "load"):
             getattr(L, "hk_surrogate_" + f).restype = i32
         L.hk_get_timing.argtypes = [vp, C.POINTER(hk_timing)]; L.hk_get_timing.restype = i32
         _lib = L
@@ -207,12 +210,40 @@ def _species(species: dict) -> hk_species:
     return hk_species(float(species.get("T_ref", 296.0)), float(species["mass_amu"]))
 
 
+def _lines_device(lines: dict):
+    """hk_lines over device tensors (contiguous float64, one length)."""
+    ptrs, n = [], None
+    for k in LINE_FIELDS:
+        v = lines.get(k)
+        if v is None:
+            ptrs.append(None)
+            continue
+        if str(v.dtype) != "torch.float64" or not v.is_contiguous() or v.dim() != 1:
+            raise ValueError("device line field %s must be a contiguous 1-D float64 tensor" % k)
+        if n is None:
+            n = v.numel()
+        elif v.numel() != n:
+            raise ValueError("line field %s has %d values, expected %d" % (k, v.numel(), n))
+        ptrs.append(C.cast(C.c_void_p(v.data_ptr()), _pd))
+    return hk_lines(n or 0, *ptrs)
+
+
+def _on_device(lines: dict) -> bool:
+    v = lines.get("nu")
+    return hasattr(v, "is_cuda") and bool(v.is_cuda)
+
+
 def hk_load_lines(ctx, lines: dict, species: dict):
-    """lines: dict of host arrays (nu, S_ref, E_lower, gamma_air, n_air and
-    optional gamma_self, delta, A21); species: {T_ref, mass_amu}."""
-    s, keep = _lines(lines)
+    """lines: dict of arrays (nu, S_ref, E_lower, gamma_air, n_air and
+    optional gamma_self, delta, A21), all host arrays or all device tensors
+    (float64; then lines_on_device = 1); species: {T_ref, mass_amu}."""
     sp = _species(species)
-    _check(lib().hk_load_lines(ctx, C.byref(s), C.byref(sp)), ctx)
+    if _on_device(lines):
+        s = _lines_device(lines)
+        _check(lib().hk_load_lines(ctx, C.byref(s), C.byref(sp), 1), ctx)
+    else:
+        s, keep = _lines(lines)
+        _check(lib().hk_load_lines(ctx, C.byref(s), C.byref(sp), 0), ctx)
 
 
 def hk_opacity_stream(ctx, chunks, species: dict, state: dict, grid: dict, precision: int, kappa,
@@ -321,6 +352,20 @@ def hk_surrogate_certify(ctx, budget: float):
     cnt = C.c_int32(0)
     _check(lib().hk_surrogate_certify(ctx, float(budget), err.ctypes.data, C.byref(cnt)), ctx)
     return err, int(cnt.value)
+
+
+def hk_surrogate_save(ctx) -> bytes:
+    """The trained (and, if done, certified) surrogate as a byte string."""
+    n = C.c_size_t(0)
+    _check(lib().hk_surrogate_save(ctx, None, 0, C.byref(n)), ctx)
+    buf = C.create_string_buffer(n.value)
+    _check(lib().hk_surrogate_save(ctx, buf, n.value, C.byref(n)), ctx)
+    return buf.raw[:n.value]
+
+
+def hk_surrogate_load(ctx, blob: bytes):
+    b = bytes(blob)
+    _check(lib().hk_surrogate_load(ctx, C.c_char_p(b), len(b)), ctx)
 
 
 def _count(a) -> int:
@@ -512,6 +557,12 @@ class Context:
         K = self._torch.empty_like(x)
         hk_surrogate_eval(self.h, x, y, z, K)
         return z, K
+
+    def surrogate_save(self) -> bytes:
+        return hk_surrogate_save(self.h)
+
+    def surrogate_load(self, blob: bytes):
+        hk_surrogate_load(self.h, blob)
 
     def surrogate_certify(self, budget: float):
         return hk_surrogate_certify(self.h, budget)

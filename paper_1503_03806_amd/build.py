@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhk.so")
-SOURCES = ["hk_api.cpp", "line_prep.hip", "opacity_f64.hip", "opacity_f32.hip", "kdist.hip", "surrogate.hip", "resample.hip", "work_plan.hip", "line_io.cpp"]
+SOURCES = ["hk_api.cpp", "line_prep.hip", "opacity_f64.hip", "opacity_f32.hip", "kdist.hip", "surrogate.hip", "resample.hip", "work_plan.hip", "line_sort.hip", "line_io.cpp"]
 ARCH = "gfx950"
 
 

@@ -68,6 +68,7 @@ struct hk_ctx {
     hipStream_t own = nullptr;     // created with the context
     hipStream_t stream = nullptr;  // where work is enqueued (may be the null stream)
     int64_t lds_bytes = kSortLdsBytes;  // LDS a sort workgroup may use
+    int64_t lds_max = 65536;            // the device's LDS per workgroup (the radix sorts)
     std::string err;
     // line list, ascending (nu, index)
     int64_t n_lines = 0;
@@ -107,7 +108,7 @@ struct hk_ctx {
     // per-state evaluation counters of the last call, and the tile shapes
     // chosen by timing, per (precision, lines, points, cutoff/dnu)
     DevBuf tb_idx, tb_wing, tb_core, tb_w32, tb_c32, tb_ranges, tb_ranges_c, tb_out, tb_comp, tb_scale, tb_kappa,
-        tb_counts, tb_series;
+        tb_counts, tb_series, tb_prep;
     int64_t tables_batch = 0;  // states per launch; 0 = as many as fit in tables_mem
     int64_t tables_mem = (int64_t)32 << 30;
     int tables_autotune = 1;
@@ -123,6 +124,11 @@ struct hk_ctx {
     // compute copy, training partials, certification errors and mask
     DevBuf sg_theta, sg_m, sg_v, sg_copy, sg_part, sg_ploss, sg_err, sg_mask;
     bool sg_loaded = false, sg_certified = false;
+    // per-workgroup counts of the points the network evaluated in a
+    // HK_F32_SURROGATE series launch, and their running total (element 0 of
+    // sg_used_total) over the calls of one hk_opacity / hk_opacity_stream
+    DevBuf sg_used, sg_used_total;
+    double sg_budget = 0.0;  // of the current certification
     // resampling: QR factors of the Chebyshev design matrix for the bin
     // sizes of the last call (main and ragged last bin), and the quadrature
     DevBuf rs_Q, rs_R, rs_Ql, rs_Rl, rs_quad;
@@ -542,6 +548,7 @@ std::vector<std::pair<size_t, size_t>> present_fields(const hk_lines* L)
 namespace {
 
 constexpr int32_t kCountBlocks = 256;  // partial sums per evaluation count
+constexpr int64_t kTablesSub = 16;      // binary32 tables: states per binary64 record pass
 
 // Partial sums sized by their bound up to this many bytes; beyond it (grids
 // above ~2e7 points) the plan is read back instead.
@@ -554,7 +561,7 @@ constexpr int64_t kPlanBoundBytes = (int64_t)1 << 30;
 // *items and the partial sums; else their bounds.
 int make_plan(hk_ctx* ctx, PlanBufs& pb, const int64_t* ranges, int64_t n_tiles, int32_t n_states,
               const double* reach, int32_t tp, int64_t min_seg, const hk_grid* grid, bool exact, WorkPlan* wp,
-              hipStream_t strm)
+              hipStream_t strm, const double* reach_dev = nullptr)
 {
     const int64_t n = ctx->n_lines;
     const int32_t np = (int32_t)grid->n_points;
@@ -573,10 +580,15 @@ int make_plan(hk_ctx* ctx, PlanBufs& pb, const int64_t* ranges, int64_t n_tiles,
     int64_t* slot = static_cast<int64_t*>(pb.slot.p);
     int64_t* total = static_cast<int64_t*>(pb.total.p);
     const double* nu = lines_field(ctx, 0);
-    for (int32_t s = 0; s < n_states; ++s)
-        HK_HIP(ctx, launch_tile_ranges(nu, n, n_ref, kRefTilePoints, grid->nu_min, grid->dnu, np, reach[s],
-                                       ref + (int64_t)s * 2 * n_ref, strm),
+    if (reach_dev)  // reach_dev: the same reaches on the device, every state in one launch
+        HK_HIP(ctx, launch_tile_ranges(nu, n, n_ref, kRefTilePoints, grid->nu_min, grid->dnu, np, 0.0, ref, strm,
+                                       reach_dev, n_states),
                "tile_ranges");
+    else
+        for (int32_t s = 0; s < n_states; ++s)
+            HK_HIP(ctx, launch_tile_ranges(nu, n, n_ref, kRefTilePoints, grid->nu_min, grid->dnu, np, reach[s],
+                                           ref + (int64_t)s * 2 * n_ref, strm),
+                   "tile_ranges");
     HK_HIP(ctx, launch_seg_length(ref, n_ref, n_states, np, n, min_seg, seg, strm), "seg_length");
     HK_HIP(ctx, launch_work_plan(ranges, n_tiles, n_states, seg, first, slot, static_cast<int64_t*>(pb.bsum.p), total,
                                  strm),
@@ -633,6 +645,15 @@ int ensure_side(hk_ctx* ctx)
     HK_HIP(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking), "hipStreamCreate");
     HK_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming), "hipEventCreate");
     HK_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming), "hipEventCreate");
+    return HK_OK;
+}
+
+// Clears the running count of surrogate evaluations (stream-ordered, by a
+// fill kernel), at the start of each hk_opacity / hk_opacity_stream call.
+int reset_surrogate_count(hk_ctx* ctx)
+{
+    HK_HIP(ctx, ctx->sg_used_total.ensure(sizeof(int64_t)), "allocating surrogate counters");
+    HK_HIP(ctx, launch_zero(ctx->sg_used_total.p, sizeof(int64_t), ctx->stream), "zero");
     return HK_OK;
 }
 
@@ -810,8 +831,10 @@ int hk_create(int device, hk_ctx** out)
     }
     ctx->stream = ctx->own;
     int lds = 0;
-    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0) {
         ctx->lds_bytes = std::min<int64_t>(lds, kSortLdsBytes);
+        ctx->lds_max = lds;
+    }
     *out = ctx;
     return HK_OK;
 }
@@ -849,10 +872,10 @@ int hk_destroy(hk_ctx* ctx)
         b->release();
     for (DevBuf* b : {&ctx->tb_idx, &ctx->tb_wing, &ctx->tb_core, &ctx->tb_w32, &ctx->tb_c32, &ctx->tb_ranges,
                       &ctx->tb_ranges_c, &ctx->tb_out, &ctx->tb_comp, &ctx->tb_scale, &ctx->tb_kappa,
-                      &ctx->tb_counts, &ctx->tb_series})
+                      &ctx->tb_counts, &ctx->tb_series, &ctx->tb_prep})
         b->release();
     for (DevBuf* b : {&ctx->sg_theta, &ctx->sg_m, &ctx->sg_v, &ctx->sg_copy, &ctx->sg_part, &ctx->sg_ploss,
-                      &ctx->sg_err, &ctx->sg_mask, &ctx->rs_Q, &ctx->rs_R, &ctx->rs_Ql, &ctx->rs_Rl, &ctx->rs_quad})
+                      &ctx->sg_err, &ctx->sg_mask, &ctx->sg_used, &ctx->sg_used_total, &ctx->rs_Q, &ctx->rs_R, &ctx->rs_Ql, &ctx->rs_Rl, &ctx->rs_quad})
         b->release();
     for (auto& p : ctx->pending) {
         (void)hipEventDestroy(p.second.first);
@@ -879,30 +902,170 @@ int hk_sync(hk_ctx* ctx)
     return HK_OK;
 }
 
-int hk_load_lines(hk_ctx* ctx, const hk_lines* L, const hk_species* sp)
+}  // extern "C"
+
+namespace {
+
+// The message of line i of a list that breaks a rule of hk_load_lines
+// (values in L at index i; `shown` is the index the message names).
+int bad_line(hk_ctx* ctx, const hk_lines* L, int64_t i, int64_t shown)
+{
+    const long long li = (long long)shown;
+    if (!isfin(L->nu[i]) || !(L->nu[i] > 0.0))
+        return fail(ctx, HK_EINVAL, "nu[%lld] = %g must be finite and > 0", li, L->nu[i]);
+    if (!isfin(L->S_ref[i]) || !(L->S_ref[i] >= 0.0))
+        return fail(ctx, HK_EINVAL, "S_ref[%lld] = %g must be finite and >= 0", li, L->S_ref[i]);
+    if (!isfin(L->E_lower[i])) return fail(ctx, HK_EINVAL, "E_lower[%lld] is not finite", li);
+    if (!isfin(L->gamma_air[i]) || !(L->gamma_air[i] >= 0.0))
+        return fail(ctx, HK_EINVAL, "gamma_air[%lld] must be finite and >= 0", li);
+    if (!isfin(L->n_air[i])) return fail(ctx, HK_EINVAL, "n_air[%lld] is not finite", li);
+    if (L->gamma_self && (!isfin(L->gamma_self[i]) || !(L->gamma_self[i] >= 0.0)))
+        return fail(ctx, HK_EINVAL, "gamma_self[%lld] must be finite and >= 0", li);
+    if (L->delta && !isfin(L->delta[i])) return fail(ctx, HK_EINVAL, "delta[%lld] is not finite", li);
+    return fail(ctx, HK_EINVAL, "A21[%lld] must be finite and >= 0", li);
+}
+
+// The check of a list in device memory (the rules of check_lines) and its
+// bounds (list_info), by a kernel; one synchronisation.  *sorted: nu is
+// already non-decreasing.
+int check_lines_device(hk_ctx* ctx, const hk_lines* L, ListInfo* li, bool* sorted)
+{
+    const int64_t n = L->n;
+    *li = ListInfo();
+    li->has_self = L->gamma_self != nullptr;
+    li->has_delta = L->delta != nullptr;
+    li->has_A = L->A21 != nullptr;
+    *sorted = true;
+    if (n == 0) return HK_OK;
+    LinesDev D;
+    D.nu = L->nu;
+    D.S_ref = L->S_ref;
+    D.E_lower = L->E_lower;
+    D.gamma_air = L->gamma_air;
+    D.n_air = L->n_air;
+    D.gamma_self = L->gamma_self;
+    D.delta = L->delta;
+    D.A21 = L->A21;
+    D.n = n;
+    const int32_t nb = check_lines_blocks(n);
+    DevBuf part;
+    std::vector<CheckPart> h((size_t)nb);
+    hipError_t e = part.ensure((size_t)nb * sizeof(CheckPart));
+    if (e == hipSuccess) e = launch_check_lines(D, part.p, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h.data(), part.p, h.size() * sizeof(CheckPart), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    part.release();
+    if (e != hipSuccess) return hip_fail(ctx, e, "checking the line list on the device");
+    CheckPart c = h[0];
+    for (const CheckPart& b : h) {
+        c.first_bad = std::min(c.first_bad, b.first_bad);
+        c.first_unordered = std::min(c.first_unordered, b.first_unordered);
+        c.max_abs_delta = std::max(c.max_abs_delta, b.max_abs_delta);
+        c.max_gamma_air = std::max(c.max_gamma_air, b.max_gamma_air);
+        c.max_gamma_self = std::max(c.max_gamma_self, b.max_gamma_self);
+        c.max_A21 = std::max(c.max_A21, b.max_A21);
+        c.min_n_air = std::min(c.min_n_air, b.min_n_air);
+        c.max_n_air = std::max(c.max_n_air, b.max_n_air);
+        c.nu_max = std::max(c.nu_max, b.nu_max);
+    }
+    if (c.first_bad < n) {  // read that line back for the message
+        const int64_t i = c.first_bad;
+        double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const double* src[8] = {L->nu, L->S_ref, L->E_lower, L->gamma_air, L->n_air, L->gamma_self, L->delta, L->A21};
+        for (int k = 0; k < 8; ++k)
+            if (src[k]) HK_HIP(ctx, hipMemcpy(&v[k], src[k] + i, sizeof(double), hipMemcpyDeviceToHost), "reading a line");
+        hk_lines one{1, &v[0], &v[1], &v[2], &v[3], &v[4], L->gamma_self ? &v[5] : nullptr,
+                     L->delta ? &v[6] : nullptr, L->A21 ? &v[7] : nullptr};
+        return bad_line(ctx, &one, 0, i);
+    }
+    li->max_abs_delta = c.max_abs_delta;
+    li->max_gamma_air = c.max_gamma_air;
+    li->max_gamma_self = c.max_gamma_self;
+    li->max_A21 = c.max_A21;
+    li->min_n_air = c.min_n_air;
+    li->max_n_air = c.max_n_air;
+    li->nu_max = c.nu_max;
+    *sorted = c.first_unordered >= n;
+    return HK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hk_load_lines(hk_ctx* ctx, const hk_lines* L, const hk_species* sp, int lines_on_device)
 {
     if (!L || !sp) return fail(ctx, HK_EINVAL, "lines and species must not be NULL");
     if (L->n < 0 || L->n > (int64_t)INT32_MAX) return fail(ctx, HK_EINVAL, "line count %lld out of range", (long long)L->n);
     if (int rc = check_species(ctx, sp)) return rc;
-    if (int rc = check_lines(ctx, L, -1)) return rc;
+    if (!lines_on_device)
+        if (int rc = check_lines(ctx, L, -1)) return rc;
     if (int rc = check_ctx(ctx)) return rc;
-    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     const int64_t n = L->n;
-    const size_t cap = (size_t)8 * (size_t)(n > 0 ? n : 1);
-    std::unique_ptr<double[]> host(new (std::nothrow) double[cap]);
-    if (!host) return fail(ctx, HK_ENOMEM, "out of host memory for %lld lines", (long long)n);
-    order_lines(L, host.get());
-    const ListInfo li = list_info(L);
+    if (lines_on_device && n > 0 && (!L->nu || !L->S_ref || !L->E_lower || !L->gamma_air || !L->n_air))
+        return fail(ctx, HK_EINVAL, "nu, S_ref, E_lower, gamma_air and n_air are required");
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    ListInfo li;
+    bool sorted = true;
+    if (lines_on_device) {
+        if (int rc = check_lines_device(ctx, L, &li, &sorted)) return rc;
+    } else {
+        li = list_info(L);
+        std::vector<char> ok(8, 1);
+        host_ranges(n, 8, [&](int64_t i0, int64_t i1, int t) {
+            for (int64_t i = std::max<int64_t>(i0, 1); i < i1; ++i)
+                if (L->nu[i] < L->nu[i - 1]) {
+                    ok[(size_t)t] = 0;
+                    return;
+                }
+        });
+        for (char c : ok) sorted = sorted && c;
+    }
     HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     ctx->n_lines = n;
     ctx->lines_loaded = false;
     ctx->have_run = false;
     ctx->last_stream_chunks = 0;
+    const size_t cap = (size_t)8 * (size_t)(n > 0 ? n : 1);
     HK_HIP(ctx, ctx->lines.ensure(cap * sizeof(double)), "allocating the line list");
-    for (const auto& f : present_fields(L))  // the fields order_lines wrote
-        HK_HIP(ctx, hipMemcpy(static_cast<double*>(ctx->lines.p) + f.first * n, host.get() + f.first * n,
-                              (size_t)f.second * n * sizeof(double), hipMemcpyHostToDevice),
-               "copying the line list");
+    const double* src[8] = {L->nu, L->S_ref, L->E_lower, L->gamma_air, L->n_air, L->gamma_self, L->delta, L->A21};
+    double* dst = static_cast<double*>(ctx->lines.p);
+    const hipMemcpyKind kind = lines_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const auto fields = present_fields(L);
+    if (sorted) {
+        for (const auto& f : fields)
+            for (size_t k = f.first; k < f.first + f.second; ++k)
+                HK_HIP(ctx, hipMemcpyAsync(dst + k * n, src[k], (size_t)n * sizeof(double), kind, ctx->stream),
+                       "copying the line list");
+    } else {
+        // ordered on the device: a host list is first copied as it is
+        DevBuf staging, scratch;
+        hipError_t e = hipSuccess;
+        const double* dsrc[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+        if (lines_on_device) {
+            for (int k = 0; k < 8; ++k) dsrc[k] = src[k];
+        } else {
+            e = staging.ensure(cap * sizeof(double));
+            for (const auto& f : fields)
+                for (size_t k = f.first; k < f.first + f.second && e == hipSuccess; ++k) {
+                    double* d = static_cast<double*>(staging.p) + k * n;
+                    e = hipMemcpyAsync(d, src[k], (size_t)n * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+                    dsrc[k] = d;
+                }
+        }
+        const uint32_t* perm = nullptr;
+        if (e == hipSuccess) e = scratch.ensure(line_sort_scratch_bytes(n));
+        if (e == hipSuccess) e = launch_line_order(dsrc[0], n, scratch.p, &perm, ctx->stream);
+        for (const auto& f : fields)
+            for (size_t k = f.first; k < f.first + f.second && e == hipSuccess; ++k)
+                e = launch_gather(dsrc[k], perm, n, dst + k * n, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        staging.release();
+        scratch.release();
+        if (e != hipSuccess) return hip_fail(ctx, e, "ordering the line list");
+    }
+    HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     ctx->li = li;
     ctx->species = *sp;
     ctx->lines_loaded = true;
@@ -965,7 +1128,7 @@ static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, double reach, double re
         // segments of whole 256-line compensation blocks for the wing
         if (int rc = make_plan(ctx, ctx->wplan, ranges, n_tiles, 1, &reach, tp, 256, grid, false, &wwp, ctx->stream))
             return rc;
-        if (int rc = make_plan(ctx, ctx->cplan, ranges_c, n_tiles_c, 1, &reach_core, opacity_f32_tile_points(4), 64,
+        if (int rc = make_plan(ctx, ctx->cplan, ranges_c, n_tiles_c, 1, &reach_core, core_f32_tile_points(), 64,
                                grid, false, &cwp, ctx->stream))
             return rc;
         tm.stop();
@@ -974,10 +1137,19 @@ static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, double reach, double re
     HK_HIP(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0), "hipStreamWaitEvent");
     {
         StageTimer tm(ctx, HK_STAGE_CORE, ctx->side);
+        const int64_t used_n = surrogate ? plan_blocks(cwp.launch_items) : 0;
+        if (surrogate)
+            HK_HIP(ctx, ctx->sg_used.ensure((size_t)std::max<int64_t>(used_n, 1) * sizeof(int64_t)),
+                   "allocating surrogate counters");
         HK_HIP(ctx, launch_core_f32(widx, c32, ranges_c, n, n_tiles_c, 1, cwp, np, series,
                                     static_cast<float*>(ctx->cplan.partial.p), surrogate ? ctx->sg_copy.p : nullptr,
-                                    surrogate ? static_cast<const uint8_t*>(ctx->sg_mask.p) : nullptr, ctx->side),
+                                    surrogate ? static_cast<const uint8_t*>(ctx->sg_mask.p) : nullptr,
+                                    surrogate ? static_cast<int64_t*>(ctx->sg_used.p) : nullptr, used_n, ctx->side),
                "core_f32");
+        if (surrogate && n_tiles_c > 0)
+            HK_HIP(ctx, launch_sum_counts(static_cast<int64_t*>(ctx->sg_used.p), used_n,
+                                          static_cast<int64_t*>(ctx->sg_used_total.p), 1, ctx->side),
+                   "sum_counts");
         tm.stop();
     }
     HK_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->side), "hipEventRecord");
@@ -1025,7 +1197,7 @@ static int opacity_run(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int
     const int ppl = ctx->f64_points_per_lane;
     const int32_t tp = opacity_f64_tile_points(ppl);
     const int64_t n_tiles = ((int64_t)np + tp - 1) / tp;
-    const int32_t tpc = core_f64_tile_points();
+    const int32_t tpc = precision == HK_F64 ? core_f64_tile_points() : core_f32_tile_points();
     const int64_t n_tiles_c = ((int64_t)np + tpc - 1) / tpc;
     HK_HIP(ctx, ctx->ranges.ensure((size_t)std::max<int64_t>(n_tiles, 1) * 2 * sizeof(int64_t)),
            "allocating tile ranges");
@@ -1113,6 +1285,7 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
     HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     ctx->last_tables_states = 0;
     ctx->last_stream_chunks = 0;
+    if (int rc = reset_surrogate_count(ctx)) return rc;
     return opacity_run(ctx, st, grid, precision, static_cast<double*>(kappa), accumulate);
 }
 
@@ -1197,6 +1370,7 @@ int hk_opacity_stream(hk_ctx* ctx, const hk_lines* chunks, int32_t n_chunks, con
     HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     if (int rc = reserve_line_buffers(ctx, n_max, precision)) return rc;
     if (int rc = stream_resources(ctx, (size_t)8 * (size_t)std::max<int64_t>(n_max, 1))) return rc;
+    if (int rc = reset_surrogate_count(ctx)) return rc;
     HK_HIP(ctx, ctx->st_counts.ensure((size_t)kCountBlocks * 3 * (size_t)n_chunks * sizeof(int64_t)),
            "allocating counters");
     ctx->species = *sp;
@@ -1242,11 +1416,11 @@ int hk_kdist(hk_ctx* ctx, const void* kappa, int precision, int64_t n_points, co
     if (int rc = check_ctx(ctx)) return rc;
     HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     const int eb = precision == HK_F64 ? 8 : 4;
-    const size_t sb = kdist_scratch_bytes(eb, n_points, bins->points_per_bin, ctx->lds_bytes);
+    const size_t sb = kdist_scratch_bytes(eb, n_points, bins->points_per_bin, ctx->lds_bytes, ctx->lds_max);
     if (sb) HK_HIP(ctx, ctx->kscratch.ensure(sb), "allocating sort scratch");
     StageTimer tm(ctx, HK_STAGE_KDIST);
     HK_HIP(ctx, launch_kdist(kappa, eb, n_points, bins->points_per_bin, gv, k_out, sorted_out,
-                             ctx->kscratch.p, ctx->lds_bytes, ctx->stream),
+                             ctx->kscratch.p, ctx->lds_bytes, ctx->lds_max, 1, ctx->stream),
            "kdist");
     tm.stop();
     return HK_OK;
@@ -1289,7 +1463,7 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
     const int64_t n = ctx->n_lines;
     const bool f64 = precision == HK_F64;
     const LinesDev L = lines_dev(ctx);
-    const int32_t tpc = f64 ? core_f64_tile_points() : opacity_f32_tile_points(4);
+    const int32_t tpc = f64 ? core_f64_tile_points() : core_f32_tile_points();
     const int64_t n_tiles_c = ((int64_t)np + tpc - 1) / tpc;
     const int64_t n_tiles_max = ((int64_t)np + opacity_f64_tile_points(2) - 1) / opacity_f64_tile_points(2);
     const int64_t n_tiles_max32 = ((int64_t)np + opacity_f32_tile_points(2) - 1) / opacity_f32_tile_points(2);
@@ -1300,7 +1474,7 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
                                   : (int64_t)(sizeof(WingIdx) + sizeof(WingRec32) + sizeof(CoreRec32));
     // records, tile ranges, the opacity grid and the series grid (binary32:
     // sums, compensations and series in binary32)
-    const int64_t per_state = n * rec_bytes + (ranges_per_state + 2 * n_tiles_c) * 8 + (int64_t)np * (f64 ? 16 : 12);
+    const int64_t per_state = n * rec_bytes + (ranges_per_state + 2 * n_tiles_c) * 8 + (int64_t)np * (f64 ? 16 : 20);
     int64_t B = ctx->tables_batch > 0 ? ctx->tables_batch : std::max<int64_t>(1, ctx->tables_mem / per_state);
     B = std::min<int64_t>(B, n_states);
     const int64_t n_batches = (n_states + B - 1) / B;
@@ -1312,16 +1486,20 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
         HK_HIP(ctx, ctx->tb_wing.ensure(nb * sizeof(WingRec)), "allocating batch records");
         HK_HIP(ctx, ctx->tb_core.ensure(nb * sizeof(CoreRec)), "allocating batch records");
     } else {
-        const size_t n1 = (size_t)std::max<int64_t>(n, 1);
+        // binary64 records of up to kSub states at a time, from which the
+        // binary32 ones are made
+        const size_t n1 = (size_t)std::max<int64_t>(n, 1) * (size_t)std::min<int64_t>(B, kTablesSub);
         HK_HIP(ctx, ctx->wing.ensure(n1 * sizeof(WingRec)), "allocating line records");
         HK_HIP(ctx, ctx->core.ensure(n1 * sizeof(CoreRec)), "allocating line records");
         HK_HIP(ctx, ctx->tb_w32.ensure(nb * sizeof(WingRec32)), "allocating batch records");
         HK_HIP(ctx, ctx->tb_c32.ensure(nb * sizeof(CoreRec32)), "allocating batch records");
         HK_HIP(ctx, ctx->tb_comp.ensure((size_t)B * np * sizeof(float)), "allocating batch sums");
         HK_HIP(ctx, ctx->tb_scale.ensure((size_t)B * sizeof(int32_t)), "allocating batch scales");
-        HK_HIP(ctx, ctx->tb_kappa.ensure((size_t)np * sizeof(double)), "allocating the opacity");
-        HK_HIP(ctx, ctx->f32partial.ensure((size_t)256 * sizeof(double)), "allocating the scale");
+        HK_HIP(ctx, ctx->tb_kappa.ensure((size_t)B * np * sizeof(double)), "allocating the opacities");
+        HK_HIP(ctx, ctx->f32partial.ensure((size_t)256 * kTablesSub * sizeof(double)), "allocating the scale");
     }
+    // per-state constants and reaches of a batch, on the device
+    HK_HIP(ctx, ctx->tb_prep.ensure((size_t)B * (sizeof(PrepParams) + 2 * sizeof(double))), "allocating batch constants");
     HK_HIP(ctx, ctx->tb_out.ensure((size_t)B * np * (f64 ? sizeof(double) : sizeof(float))),
            "allocating batch opacities");
     HK_HIP(ctx, ctx->tb_series.ensure((size_t)B * np * (f64 ? sizeof(double) : sizeof(float))),
@@ -1330,8 +1508,10 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
     HK_HIP(ctx, ctx->tb_ranges_c.ensure((size_t)B * 2 * n_tiles_c * sizeof(int64_t)), "allocating tile ranges");
     HK_HIP(ctx, ctx->tb_counts.ensure((size_t)n_states * kCountBlocks * 3 * sizeof(int64_t)),
            "allocating counters");
-    const size_t sb = kdist_scratch_bytes(8, np, bins->points_per_bin, ctx->lds_bytes);
+    const size_t sb = kdist_scratch_bytes(8, np, bins->points_per_bin, ctx->lds_bytes, ctx->lds_max);
     if (sb) HK_HIP(ctx, ctx->kscratch.ensure(sb), "allocating sort scratch");
+    // bins of one LDS radix sort: every state of a batch in one sort launch
+    const bool sort_batched = bins->points_per_bin <= kdist_radix_max_keys(8, ctx->lds_max);
 
     WingIdx* tidx = static_cast<WingIdx*>(ctx->tb_idx.p);
     int64_t* rc_all = static_cast<int64_t*>(ctx->tb_ranges_c.p);
@@ -1353,43 +1533,63 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
 
     for (int64_t b0 = 0; b0 < n_states; b0 += B) {
         const int32_t nbat = (int32_t)std::min<int64_t>(B, n_states - b0);
-        std::vector<double> reach_c((size_t)nbat);
+        std::vector<double> reach_c((size_t)nbat), reach((size_t)nbat);
+        std::vector<PrepParams> pps((size_t)nbat);
+        for (int32_t s = 0; s < nbat; ++s) {
+            pps[(size_t)s] = prep_params(ctx, &states[b0 + s], grid);
+            reach_c[(size_t)s] = core_reach(ctx, &states[b0 + s], grid, pps[(size_t)s]);
+            reach[(size_t)s] = wing_reach(ctx, &states[b0 + s], grid);
+        }
+        PrepParams* d_pps = static_cast<PrepParams*>(ctx->tb_prep.p);
+        double* d_reach_c = reinterpret_cast<double*>(d_pps + B);
+        double* d_reach = d_reach_c + B;
         {
+            // the host arrays live until the batch's plans are read back
+            // (a synchronisation), after these copies have run
+            HK_HIP(ctx, hipMemcpyAsync(d_pps, pps.data(), pps.size() * sizeof(PrepParams), hipMemcpyHostToDevice,
+                                       ctx->stream),
+                   "copying batch constants");
+            HK_HIP(ctx, hipMemcpyAsync(d_reach_c, reach_c.data(), reach_c.size() * sizeof(double),
+                                       hipMemcpyHostToDevice, ctx->stream),
+                   "copying batch constants");
+            HK_HIP(ctx, hipMemcpyAsync(d_reach, reach.data(), reach.size() * sizeof(double), hipMemcpyHostToDevice,
+                                       ctx->stream),
+                   "copying batch constants");
+        }
+        {
+            // every state of the batch in one launch per step
             StageTimer tm(ctx, HK_STAGE_LINE_PREP);
-            for (int32_t s = 0; s < nbat; ++s) {
-                const hk_state* st = &states[b0 + s];
-                const PrepParams pp = prep_params(ctx, st, grid);
-                WingIdx* ix = tidx + (int64_t)s * n;
-                if (f64) {
-                    HK_HIP(ctx, launch_line_prep_f64(L, pp, static_cast<WingRec*>(ctx->tb_wing.p) + (int64_t)s * n, ix,
-                                                     static_cast<CoreRec*>(ctx->tb_core.p) + (int64_t)s * n,
-                                                     ctx->stream),
-                           "line_prep_f64");
-                } else {
+            if (f64) {
+                HK_HIP(ctx, launch_line_prep_f64_batch(L, d_pps, nbat, static_cast<WingRec*>(ctx->tb_wing.p), tidx,
+                                                       static_cast<CoreRec*>(ctx->tb_core.p), ctx->stream),
+                       "line_prep_f64");
+            } else {
+                for (int32_t s0 = 0; s0 < nbat; s0 += (int32_t)kTablesSub) {
+                    const int32_t ns = std::min<int32_t>((int32_t)kTablesSub, nbat - s0);
                     WingRec* w = static_cast<WingRec*>(ctx->wing.p);
                     CoreRec* c = static_cast<CoreRec*>(ctx->core.p);
-                    int32_t* scale = static_cast<int32_t*>(ctx->tb_scale.p) + s;
-                    HK_HIP(ctx, launch_line_prep_f64(L, pp, w, ix, c, ctx->stream), "line_prep_f64");
+                    int32_t* scale = static_cast<int32_t*>(ctx->tb_scale.p) + s0;
+                    WingIdx* ix = tidx + (int64_t)s0 * n;
+                    HK_HIP(ctx, launch_line_prep_f64_batch(L, d_pps + s0, ns, w, ix, c, ctx->stream), "line_prep_f64");
                     if (n > 0) {
                         HK_HIP(ctx, launch_f32_scale(w, c, n, static_cast<double*>(ctx->f32partial.p), 256, scale,
-                                                     ctx->stream),
+                                                     ctx->stream, ns),
                                "f32_scale");
                         HK_HIP(ctx, launch_line_prep_f32(w, ix, c, n, grid->nu_min, grid->dnu, scale,
-                                                         static_cast<WingRec32*>(ctx->tb_w32.p) + (int64_t)s * n,
-                                                         static_cast<CoreRec32*>(ctx->tb_c32.p) + (int64_t)s * n,
-                                                         ctx->stream),
+                                                         static_cast<WingRec32*>(ctx->tb_w32.p) + (int64_t)s0 * n,
+                                                         static_cast<CoreRec32*>(ctx->tb_c32.p) + (int64_t)s0 * n,
+                                                         ctx->stream, ns),
                                "line_prep_f32");
                     } else {
-                        HK_HIP(ctx, launch_zero(scale, sizeof(int32_t), ctx->stream), "zero");
+                        HK_HIP(ctx, launch_zero(scale, (size_t)ns * sizeof(int32_t), ctx->stream), "zero");
                     }
                 }
-                HK_HIP(ctx, launch_eval_counts(ix, n, counts + (b0 + s) * kCountBlocks * 3, kCountBlocks, ctx->stream),
-                       "eval_counts");
-                reach_c[(size_t)s] = core_reach(ctx, st, grid, pp);
-                HK_HIP(ctx, launch_tile_ranges(L.nu, n, n_tiles_c, tpc, grid->nu_min, grid->dnu, np, reach_c[(size_t)s],
-                                               rc_all + (int64_t)s * 2 * n_tiles_c, ctx->stream),
-                       "tile_ranges");
             }
+            HK_HIP(ctx, launch_eval_counts(tidx, n, counts + b0 * kCountBlocks * 3, kCountBlocks, ctx->stream, nbat),
+                   "eval_counts");
+            HK_HIP(ctx, launch_tile_ranges(L.nu, n, n_tiles_c, tpc, grid->nu_min, grid->dnu, np, 0.0, rc_all,
+                                           ctx->stream, d_reach_c, nbat),
+                   "tile_ranges");
             tm.stop();
         }
         if (tune) {
@@ -1401,21 +1601,18 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
         const int32_t tp = f64 ? opacity_f64_tile_points(ppl) : opacity_f32_tile_points(ppl);
         const int64_t n_tiles = ((int64_t)np + tp - 1) / tp;
         int64_t* rw = static_cast<int64_t*>(ctx->tb_ranges.p);
-        std::vector<double> reach((size_t)nbat);
-        for (int32_t s = 0; s < nbat; ++s) reach[(size_t)s] = wing_reach(ctx, &states[b0 + s], grid);
         WorkPlan wwp, cwp;
         {
             StageTimer tm(ctx, HK_STAGE_LINE_PREP);
-            for (int32_t s = 0; s < nbat; ++s)
-                HK_HIP(ctx, launch_tile_ranges(L.nu, n, n_tiles, tp, grid->nu_min, grid->dnu, np, reach[(size_t)s],
-                                               rw + (int64_t)s * 2 * n_tiles, ctx->stream),
-                       "tile_ranges");
+            HK_HIP(ctx, launch_tile_ranges(L.nu, n, n_tiles, tp, grid->nu_min, grid->dnu, np, 0.0, rw, ctx->stream,
+                                           d_reach, nbat),
+                   "tile_ranges");
             // the plans of the whole batch, read back to size the launches
             if (int rc = make_plan(ctx, ctx->wplan, rw, n_tiles, nbat, reach.data(), tp, f64 ? 64 : 256, grid, true,
-                                   &wwp, ctx->stream))
+                                   &wwp, ctx->stream, d_reach))
                 return rc;
             if (int rc = make_plan(ctx, ctx->cplan, rc_all, n_tiles_c, nbat, reach_c.data(), tpc, 64, grid, true, &cwp,
-                                   ctx->stream))
+                                   ctx->stream, d_reach_c))
                 return rc;
             tm.stop();
         }
@@ -1435,7 +1632,8 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
             else
                 HK_HIP(ctx, launch_core_f32(tidx, static_cast<CoreRec32*>(ctx->tb_c32.p), rc_all, n, n_tiles_c, nbat,
                                             cwp, np, static_cast<float*>(ctx->tb_series.p),
-                                            static_cast<float*>(ctx->cplan.partial.p), nullptr, nullptr, ctx->side),
+                                            static_cast<float*>(ctx->cplan.partial.p), nullptr, nullptr, nullptr,
+                                            0, ctx->side),
                        "core_f32");
             tm.stop();
         }
@@ -1462,22 +1660,27 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
                    "add_f64");
         {
             StageTimer tm(ctx, HK_STAGE_KDIST);
-            for (int32_t s = 0; s < nbat; ++s) {
-                const double* kap;
-                if (f64) {
-                    kap = static_cast<double*>(ctx->tb_out.p) + (int64_t)s * np;
-                } else {
-                    double* kk = static_cast<double*>(ctx->tb_kappa.p);
-                    HK_HIP(ctx, launch_f32_finish(static_cast<float*>(ctx->tb_out.p) + (int64_t)s * np,
-                                                  static_cast<float*>(ctx->tb_comp.p) + (int64_t)s * np,
-                                                  static_cast<float*>(ctx->tb_series.p) + (int64_t)s * np,
-                                                  static_cast<int32_t*>(ctx->tb_scale.p) + s, np, kk, 0, ctx->stream),
-                           "f32_finish");
-                    kap = kk;
-                }
-                HK_HIP(ctx, launch_kdist(kap, 8, np, bins->points_per_bin, gv, k_out + (b0 + s) * n_bins * gv.n,
-                                         nullptr, ctx->kscratch.p, ctx->lds_bytes, ctx->stream),
+            // the batch's binary64 opacities: the wing grids (binary64), or
+            // the binary32 Kahan pairs and series finished into tb_kappa
+            const double* kap = static_cast<double*>(ctx->tb_out.p);
+            if (!f64) {
+                HK_HIP(ctx, launch_f32_finish(static_cast<float*>(ctx->tb_out.p), static_cast<float*>(ctx->tb_comp.p),
+                                              static_cast<float*>(ctx->tb_series.p),
+                                              static_cast<int32_t*>(ctx->tb_scale.p), np,
+                                              static_cast<double*>(ctx->tb_kappa.p), 0, ctx->stream, nbat),
+                       "f32_finish");
+                kap = static_cast<double*>(ctx->tb_kappa.p);
+            }
+            if (sort_batched) {
+                HK_HIP(ctx, launch_kdist(kap, 8, np, bins->points_per_bin, gv, k_out + b0 * n_bins * gv.n, nullptr,
+                                         ctx->kscratch.p, ctx->lds_bytes, ctx->lds_max, nbat, ctx->stream),
                        "kdist");
+            } else {
+                for (int32_t s = 0; s < nbat; ++s)
+                    HK_HIP(ctx, launch_kdist(kap + (int64_t)s * np, 8, np, bins->points_per_bin, gv,
+                                             k_out + (b0 + s) * n_bins * gv.n, nullptr, ctx->kscratch.p,
+                                             ctx->lds_bytes, ctx->lds_max, 1, ctx->stream),
+                           "kdist");
             }
             tm.stop();
         }
@@ -1652,6 +1855,94 @@ int hk_surrogate_certify(hk_ctx* ctx, double budget, double* err, int32_t* n_cer
     if (err) std::memcpy(err, e.data(), e.size() * sizeof(double));
     if (n_certified) *n_certified = cnt;
     ctx->sg_certified = true;
+    ctx->sg_budget = budget;
+    return HK_OK;
+}
+
+namespace {
+// The surrogate blob: a 32-byte header, the binary32 parameters and, when
+// certified, the binary64 cell errors (the mask is err <= budget).
+constexpr char kSurrMagic[8] = {'H', 'K', 'S', 'U', 'R', 'R', '0', '1'};
+struct SurrHeader {
+    char magic[8];
+    int32_t n_params, n_cells, certified, reserved;
+    double budget;
+};
+static_assert(sizeof(SurrHeader) == 32, "surrogate blob header");
+size_t surr_blob_bytes(bool certified)
+{
+    return sizeof(SurrHeader) + (size_t)HK_SURR_N_PARAMS * sizeof(float) +
+           (certified ? (size_t)HK_SURR_CELLS_X * HK_SURR_CELLS_Y * sizeof(double) : 0);
+}
+}  // namespace
+
+int hk_surrogate_save(hk_ctx* ctx, void* blob, size_t capacity, size_t* size)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (int rc = sg_ready(ctx)) return rc;
+    if (!size) return fail(ctx, HK_EINVAL, "size is NULL");
+    const size_t need = surr_blob_bytes(ctx->sg_certified);
+    *size = need;
+    if (!blob) return HK_OK;
+    if (capacity < need) return fail(ctx, HK_EINVAL, "blob capacity %zu < %zu bytes", capacity, need);
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    SurrHeader h{};
+    std::memcpy(h.magic, kSurrMagic, sizeof kSurrMagic);
+    h.n_params = HK_SURR_N_PARAMS;
+    h.n_cells = HK_SURR_CELLS_X * HK_SURR_CELLS_Y;
+    h.certified = ctx->sg_certified ? 1 : 0;
+    h.budget = ctx->sg_certified ? ctx->sg_budget : 0.0;
+    char* out = static_cast<char*>(blob);
+    std::memcpy(out, &h, sizeof h);
+    HK_HIP(ctx, hipMemcpyAsync(out + sizeof h, ctx->sg_theta.p, (size_t)HK_SURR_N_PARAMS * sizeof(float),
+                               hipMemcpyDeviceToHost, ctx->stream),
+           "copying parameters");
+    if (ctx->sg_certified)
+        HK_HIP(ctx, hipMemcpyAsync(out + sizeof h + (size_t)HK_SURR_N_PARAMS * sizeof(float), ctx->sg_err.p,
+                                   (size_t)h.n_cells * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+               "copying certification");
+    HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    return HK_OK;
+}
+
+int hk_surrogate_load(hk_ctx* ctx, const void* blob, size_t size)
+{
+    if (!blob) return fail(ctx, HK_EINVAL, "blob is NULL");
+    if (size < sizeof(SurrHeader)) return fail(ctx, HK_EINVAL, "blob of %zu bytes has no header", size);
+    SurrHeader h;
+    std::memcpy(&h, blob, sizeof h);
+    if (std::memcmp(h.magic, kSurrMagic, sizeof kSurrMagic) != 0)
+        return fail(ctx, HK_EINVAL, "not a surrogate blob (magic)");
+    if (h.n_params != HK_SURR_N_PARAMS || h.n_cells != HK_SURR_CELLS_X * HK_SURR_CELLS_Y ||
+        (h.certified != 0 && h.certified != 1))
+        return fail(ctx, HK_EINVAL, "surrogate blob layout (%d parameters, %d cells) differs from this library's",
+                    h.n_params, h.n_cells);
+    if (size != surr_blob_bytes(h.certified != 0))
+        return fail(ctx, HK_EINVAL, "blob of %zu bytes, expected %zu", size, surr_blob_bytes(h.certified != 0));
+    if (h.certified && !(h.budget > 0.0 && std::isfinite(h.budget)))
+        return fail(ctx, HK_EINVAL, "blob's certification budget is not finite and > 0");
+    const char* in = static_cast<const char*>(blob);
+    std::vector<float> theta((size_t)HK_SURR_N_PARAMS);
+    std::memcpy(theta.data(), in + sizeof h, theta.size() * sizeof(float));
+    std::vector<double> err;
+    if (h.certified) {
+        err.resize((size_t)h.n_cells);
+        std::memcpy(err.data(), in + sizeof h + theta.size() * sizeof(float), err.size() * sizeof(double));
+        for (double e : err)
+            if (std::isnan(e) || e < 0.0) return fail(ctx, HK_EINVAL, "blob holds an invalid cell error");
+    }
+    if (int rc = hk_surrogate_set_params(ctx, theta.data())) return rc;
+    if (!h.certified) return HK_OK;
+    const int nc = h.n_cells;
+    HK_HIP(ctx, ctx->sg_err.ensure((size_t)nc * sizeof(double)), "allocating certification");
+    HK_HIP(ctx, ctx->sg_mask.ensure((size_t)nc), "allocating certification");
+    std::vector<uint8_t> mask((size_t)nc);
+    for (int c = 0; c < nc; ++c) mask[(size_t)c] = err[(size_t)c] <= h.budget ? 1 : 0;
+    HK_HIP(ctx, hipMemcpy(ctx->sg_err.p, err.data(), err.size() * sizeof(double), hipMemcpyHostToDevice),
+           "copying certification");
+    HK_HIP(ctx, hipMemcpy(ctx->sg_mask.p, mask.data(), mask.size(), hipMemcpyHostToDevice), "copying the mask");
+    ctx->sg_certified = true;
+    ctx->sg_budget = h.budget;
     return HK_OK;
 }
 
@@ -1779,6 +2070,13 @@ int hk_stats(hk_ctx* ctx, hk_run_stats* out)
         out->evals_core = c;
         out->evals_gh3 = g - c;
         out->evals_gh1 = e - g;
+        if (!tables && ctx->sg_used_total.p) {  // 0 after hk_tables, which has no surrogate
+            int64_t u = 0;
+            HK_HIP(ctx, hipMemcpyAsync(&u, ctx->sg_used_total.p, sizeof u, hipMemcpyDeviceToHost, ctx->stream),
+                   "copying counters");
+            HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+            out->evals_surrogate = u;
+        }
     }
     return HK_OK;
 }

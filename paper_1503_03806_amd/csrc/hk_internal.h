@@ -112,6 +112,15 @@ struct LinesDev {
     int64_t n;
 };
 
+// Per-workgroup result of the device-side check of a line list (the rules
+// of hk_load_lines): the first line index that breaks a rule and the first
+// whose nu is below its predecessor's (n if none), and the bounds of the
+// valid lines that size the launches.
+struct CheckPart {
+    int64_t first_bad, first_unordered;
+    double max_abs_delta, max_gamma_air, max_gamma_self, max_A21, min_n_air, max_n_air, nu_max;
+};
+
 // State-dependent constants of the line preparation, computed on the host.
 struct PrepParams {
     double T, T_ref, P, P_self, q_ratio;
@@ -244,13 +253,21 @@ __device__ inline bool work_item(int64_t r, const WorkPlan& wp, const int64_t* r
 // ---- launches (stream-ordered, no synchronisation) ----
 hipError_t launch_line_prep_f64(const LinesDev& L, const PrepParams& pp, WingRec* wing,
                                 WingIdx* idx, CoreRec* core, hipStream_t s);
+// Every state of a batch in one launch: pps [device] n_states constants,
+// records L.n apart per state.
+hipError_t launch_line_prep_f64_batch(const LinesDev& L, const PrepParams* pps, int32_t n_states, WingRec* wing,
+                                      WingIdx* idx, CoreRec* core, hipStream_t s);
+// Tile line ranges for `reach`; or, with reach_of ([device] n_states values),
+// the ranges of n_states states in one launch, 2 n_tiles apart.
 hipError_t launch_tile_ranges(const double* nu_sorted, int64_t n_lines, int64_t n_tiles,
                               int32_t tile_points, double nu_min, double dnu, int32_t n_points,
-                              double reach, int64_t* ranges, hipStream_t s);
+                              double reach, int64_t* ranges, hipStream_t s, const double* reach_of = nullptr,
+                              int32_t n_states = 1);
 // Binary64 opacity: the wing kernel writes kappa (points_per_lane 2, 4 or
 // 8), the core kernel then adds the series terms.
 int32_t opacity_f64_tile_points(int points_per_lane);
 int32_t core_f64_tile_points();
+int32_t core_f32_tile_points();  // points per work item of the binary32 series
 // The wing items of n_states states (records n_lines apart, ranges 2 n_tiles
 // apart, kappa n_points apart); items cut by the plan write partial (binary64,
 // tile_points per slot), which the reduction then adds into kappa.  With
@@ -272,16 +289,21 @@ hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRe
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // a[j] += b[j], j < n.
 hipError_t launch_add_f64(double* a, const double* b, int64_t n, hipStream_t s);
+// n_blocks partial triples per state; n_states states (records n_lines
+// apart, partials 3 n_blocks apart) in one launch.
 hipError_t launch_eval_counts(const WingIdx* idx, int64_t n_lines, int64_t* partial,
-                              int32_t n_blocks, hipStream_t s);
+                              int32_t n_blocks, hipStream_t s, int32_t n_states = 1);
 
 // Binary32 path: the state's scale exponent from the lines' peak heights
 // (two reductions into scale[0]), the record conversion, and the kernels.
+// With n_states > 1, the states of a batch in one launch each (records
+// n_lines apart, partial n_blocks apart, one scale per state).
 hipError_t launch_f32_scale(const WingRec* wing, const CoreRec* core, int64_t n_lines,
-                            double* partial, int32_t n_blocks, int32_t* scale, hipStream_t s);
+                            double* partial, int32_t n_blocks, int32_t* scale, hipStream_t s,
+                            int32_t n_states = 1);
 hipError_t launch_line_prep_f32(const WingRec* wing, WingIdx* idx, const CoreRec* core,
                                 int64_t n_lines, double nu_min, double dnu, const int32_t* scale,
-                                WingRec32* w32, CoreRec32* c32, hipStream_t s);
+                                WingRec32* w32, CoreRec32* c32, hipStream_t s, int32_t n_states = 1);
 int32_t opacity_f32_tile_points(int points_per_lane);
 // As launch_wing_f64: the Kahan pairs (sum, comp) of n_states states; cut
 // items write (sum, comp) pairs to partial (tile_points float2 per slot).
@@ -294,13 +316,27 @@ hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const Win
 // state): the learned surrogate in the cells `mask` certifies.
 hipError_t launch_core_f32(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges, int64_t n_lines,
                            int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int32_t n_points, float* series,
-                           float* partial, const void* surrogate, const uint8_t* mask, hipStream_t s);
+                           float* partial, const void* surrogate, const uint8_t* mask, int64_t* used,
+                           int64_t used_cap, hipStream_t s);
+// line_sort.hip: the (nu, index) order of a list on the device, and the
+// check of a list in device memory.
+size_t line_sort_scratch_bytes(int64_t n);
+// perm_out: points into scratch, the input indices in (nu, index) order
+hipError_t launch_line_order(const double* nu, int64_t n, void* scratch, const uint32_t** perm_out, hipStream_t s);
+hipError_t launch_gather(const double* src, const uint32_t* perm, int64_t n, double* dst, hipStream_t s);
+int32_t check_lines_blocks(int64_t n);  // CheckPart results launch_check_lines writes
+hipError_t launch_check_lines(const LinesDev& L, void* part, hipStream_t s);
+
+// total[0] = (add ? total[0] : 0) + used[0] + ... + used[n-1]
+hipError_t launch_sum_counts(const int64_t* used, int64_t n, int64_t* total, int add, hipStream_t s);
 
 
 // kappa (binary64) = (the Kahan pair (sum, comp) with the series sum, when
 // not zero, Kahan-added) * 2^-s, or += when accumulating; series may be NULL.
+// n_states grids of n_points each (one scale per state) in one launch.
 hipError_t launch_f32_finish(const float* sum, const float* comp, const float* series, const int32_t* scale,
-                             int32_t n_points, double* kappa, int accumulate, hipStream_t s);
+                             int32_t n_points, double* kappa, int accumulate, hipStream_t s,
+                             int32_t n_states = 1);
 
 // k-distribution.  elem_bytes 8 (binary64 keys) or 4 (binary32 keys).
 int64_t kdist_lds_max_points(int elem_bytes, int64_t lds_bytes);
@@ -310,10 +346,15 @@ int64_t kdist_lds_max_points(int elem_bytes, int64_t lds_bytes);
 // 0.22 in 64 KB and 0.30 ms in one 128 KB sort each (more, smaller sorts
 // share the CUs; the merges are cheap).
 constexpr int64_t kSortLdsBytes = 32768;
+// Bins of up to kdist_radix_max_keys(lds_max) keys (16384 on gfx950's
+// 160 KB of LDS per workgroup) are sorted by an LDS radix sort, one
+// workgroup per bin, the bins of n_states contiguous grids (each n_points)
+// in one launch; larger bins (one grid per call) by the chunks below.
+int64_t kdist_radix_max_keys(int elem_bytes, int64_t lds_max);
 hipError_t launch_kdist(const void* kappa, int elem_bytes, int64_t n_points, int64_t ppb,
                         const GValues& g, double* k_out, void* sorted_out, void* scratch,
-                        int64_t lds_bytes, hipStream_t s);
-size_t kdist_scratch_bytes(int elem_bytes, int64_t n_points, int64_t ppb, int64_t lds_bytes);
+                        int64_t lds_bytes, int64_t lds_max, int32_t n_states, hipStream_t s);
+size_t kdist_scratch_bytes(int elem_bytes, int64_t n_points, int64_t ppb, int64_t lds_bytes, int64_t lds_max);
 
 // Learned K(x, y) surrogate (surrogate.hip): sizes, labels, the compute
 // copy of the parameters, one training step and its Adam update, a plain

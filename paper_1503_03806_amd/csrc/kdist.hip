@@ -12,6 +12,7 @@
 #include "hk_internal.h"
 
 namespace hk {
+size_t radix_lds_bytes(int elem_bytes, int64_t keys);
 namespace {
 
 // threads per sort workgroup (300 bins of 1e4 binary64 keys: 0.177 ms, against
@@ -87,6 +88,128 @@ __device__ inline double k_of_g(const K* s, int64_t m, double g, int rule)
     const int64_t i = (int64_t)fl;  // 0 <= i <= m - 2
     const double a = key_value<K>(s[i]), b = key_value<K>(s[i + 1]);
     return a + (u - fl) * (b - a);
+}
+
+// LDS radix sort of one bin per workgroup (bins of up to kRadixMaxKeys keys):
+// kRadixThreads threads hold the bin's keys in registers, key r of thread t
+// at position r * kRadixThreads + t, and sort them least significant digit
+// first, 8 bits per pass (8 passes of binary64 keys, 4 of binary32).  Each
+// pass is stable: a wavefront ranks the keys of one round among equal
+// digits with eight ballots (the lanes sharing a lane's digit are the AND
+// over the digit's bits of each bit's ballot or its complement) and keeps a
+// running count per digit in its own LDS counters, so its keys are ranked in
+// position order with no barrier between rounds; then the counters become
+// offsets (waves in order, digits by a scan), every key is written to its
+// place in LDS and read back in position order.  Four barriers per pass.
+constexpr int kRadixThreads = 1024;
+constexpr int kRadixWaves = kRadixThreads / 64;
+constexpr int kRadixMaxRounds = 16;
+constexpr int64_t kRadixMaxKeys = (int64_t)kRadixThreads * kRadixMaxRounds;
+static_assert(kRadixMaxKeys <= (1 << 16), "LDS positions and counters fit 32 bits with room");
+
+template <typename K>
+__device__ inline void radix_sort_block(K (&key)[kRadixMaxRounds], int rounds, int m, K* buf, uint32_t* cnt,
+                                        uint32_t* wsum)
+{
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    volatile uint32_t* wc = cnt + wave * 256;  // this wavefront's counters
+    uint32_t rank[kRadixMaxRounds];
+    for (int shift = 0; shift < (int)(8 * sizeof(K)); shift += 8) {
+        for (int q = lane; q < 256; q += 64) wc[q] = 0u;
+#pragma unroll
+        for (int r = 0; r < kRadixMaxRounds; ++r) {
+            if (r < rounds) {
+                const bool valid = r * kRadixThreads + t < m;
+                const uint32_t d = (uint32_t)(key[r] >> shift) & 0xffu;
+                uint64_t peers = __ballot(valid);
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const uint64_t bal = __ballot((d >> b) & 1u);
+                    peers &= ((d >> b) & 1u) ? bal : ~bal;
+                }
+                const uint32_t rk = (uint32_t)__builtin_popcountll(peers & below);
+                const uint32_t old = wc[d];
+                rank[r] = old + rk;
+                if (valid && rk == 0) wc[d] = old + (uint32_t)__builtin_popcountll(peers);
+            }
+        }
+        __syncthreads();
+        // digit t (threads 0 .. 255): the waves' starts in wave order, then
+        // the digits' starts by an exclusive scan of their totals
+        uint32_t tot = 0;
+        if (t < 256) {
+            for (int w = 0; w < kRadixWaves; ++w) {
+                const uint32_t c = cnt[w * 256 + t];
+                cnt[w * 256 + t] = tot;
+                tot += c;
+            }
+        }
+        uint32_t incl = tot;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        if (t < 256 && lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        if (t < 256) {
+            uint32_t base = incl - tot;
+            for (int w = 0; w < wave; ++w) base += wsum[w];
+            for (int w = 0; w < kRadixWaves; ++w) cnt[w * 256 + t] += base;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kRadixMaxRounds; ++r) {
+            if (r < rounds && r * kRadixThreads + t < m) {
+                const uint32_t d = (uint32_t)(key[r] >> shift) & 0xffu;
+                const uint32_t pos = cnt[wave * 256 + d] + rank[r];
+                if (pos < (uint32_t)m) buf[pos] = key[r];  // pos < m always
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kRadixMaxRounds; ++r) {
+            const int p = r * kRadixThreads + t;
+            if (r < rounds && p < m) key[r] = buf[p];
+        }
+    }
+}
+
+// One workgroup per bin: bins of ppb consecutive points of n_states grids
+// of n_points each (grid s at s * n_points; a grid's last bin may be short).
+// Sorted keys to dst (optional, same layout) and k(g) to k_out[bin][g.n].
+template <typename K>
+__global__ __launch_bounds__(kRadixThreads) void radix_bin_kernel(const K* __restrict__ src, int64_t n_points,
+                                                                  int64_t ppb, int64_t bins_per_grid,
+                                                                  K* __restrict__ dst, GValues g,
+                                                                  double* __restrict__ k_out)
+{
+    extern __shared__ __align__(16) unsigned char radix_lds[];
+    const int64_t bin = blockIdx.x;
+    const int64_t st = bin / bins_per_grid, lb = bin - st * bins_per_grid;
+    const int64_t b0 = st * n_points + lb * ppb;
+    const int m = (int)min(ppb, n_points - lb * ppb);
+    const int rounds = (m + kRadixThreads - 1) / kRadixThreads;
+    K* buf = reinterpret_cast<K*>(radix_lds);
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(radix_lds + (size_t)rounds * kRadixThreads * sizeof(K));
+    uint32_t* wsum = cnt + kRadixWaves * 256;
+    K key[kRadixMaxRounds];
+#pragma unroll
+    for (int r = 0; r < kRadixMaxRounds; ++r) {
+        const int p = r * kRadixThreads + (int)threadIdx.x;
+        key[r] = (r < rounds && p < m) ? src[b0 + p] : KeyMax<K>::v;
+    }
+    radix_sort_block<K>(key, rounds, m, buf, cnt, wsum);
+    if (dst) {
+#pragma unroll
+        for (int r = 0; r < kRadixMaxRounds; ++r) {
+            const int p = r * kRadixThreads + (int)threadIdx.x;
+            if (r < rounds && p < m) dst[b0 + p] = key[r];
+        }
+    }
+    // buf holds the bin in order after the last pass
+    if ((int)threadIdx.x < g.n) k_out[bin * g.n + threadIdx.x] = k_of_g<K>(buf, m, g.g[threadIdx.x], g.rule);
 }
 
 // One workgroup per bin (bins <= chunk), or per chunk of a larger bin when
@@ -179,9 +302,23 @@ int pow2_at_least(int64_t m)
 
 template <typename K>
 hipError_t run_kdist(const K* kappa, int64_t n_points, int64_t ppb, const GValues& g,
-                     double* k_out, K* sorted_out, K* scratch, int64_t lds_bytes, hipStream_t s)
+                     double* k_out, K* sorted_out, K* scratch, int64_t lds_bytes, int64_t radix_keys,
+                     int32_t n_states, hipStream_t s)
 {
     const int64_t n_bins = (n_points + ppb - 1) / ppb;
+    if (ppb <= radix_keys) {  // one LDS radix sort per bin, every grid in one launch
+        const int rounds = (int)((ppb + kRadixThreads - 1) / kRadixThreads);
+        const size_t shm = radix_lds_bytes(sizeof(K), rounds * kRadixThreads);
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&radix_bin_kernel<K>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+        const int64_t nb = n_bins * n_states;
+        if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+        radix_bin_kernel<K><<<dim3((unsigned)nb), dim3(kRadixThreads), shm, s>>>(kappa, n_points, ppb, n_bins,
+                                                                                  sorted_out, g, k_out);
+        return hipGetLastError();
+    }
+    if (n_states != 1) return hipErrorInvalidValue;  // bins above one LDS sort: one grid per call
     const int64_t cap = kdist_lds_max_points(sizeof(K), lds_bytes);
     if (ppb <= cap) {
         const int npad = pow2_at_least(ppb);
@@ -229,6 +366,19 @@ hipError_t run_kdist(const K* kappa, int64_t n_points, int64_t ppb, const GValue
 
 }  // namespace
 
+size_t radix_lds_bytes(int elem_bytes, int64_t keys)
+{
+    return (size_t)keys * elem_bytes + (size_t)kRadixWaves * 256 * 4 + 64;
+}
+
+int64_t kdist_radix_max_keys(int elem_bytes, int64_t lds_max)
+{
+    // whole rounds of kRadixThreads keys whose sort fits the workgroup's LDS
+    int64_t r = kRadixMaxRounds;
+    while (r > 0 && radix_lds_bytes(elem_bytes, r * kRadixThreads) > (size_t)lds_max) --r;
+    return r * kRadixThreads;
+}
+
 int64_t kdist_lds_max_points(int elem_bytes, int64_t lds_bytes)
 {
     // largest power of two whose keys fit in the workgroup's LDS
@@ -237,24 +387,26 @@ int64_t kdist_lds_max_points(int elem_bytes, int64_t lds_bytes)
     return p;
 }
 
-size_t kdist_scratch_bytes(int elem_bytes, int64_t n_points, int64_t ppb, int64_t lds_bytes)
+size_t kdist_scratch_bytes(int elem_bytes, int64_t n_points, int64_t ppb, int64_t lds_bytes, int64_t lds_max)
 {
-    if (ppb <= kdist_lds_max_points(elem_bytes, lds_bytes)) return 0;
+    if (ppb <= kdist_radix_max_keys(elem_bytes, lds_max) || ppb <= kdist_lds_max_points(elem_bytes, lds_bytes))
+        return 0;
     return (size_t)2 * (size_t)n_points * (size_t)elem_bytes;
 }
 
 hipError_t launch_kdist(const void* kappa, int elem_bytes, int64_t n_points, int64_t ppb,
                         const GValues& g, double* k_out, void* sorted_out, void* scratch,
-                        int64_t lds_bytes, hipStream_t s)
+                        int64_t lds_bytes, int64_t lds_max, int32_t n_states, hipStream_t s)
 {
-    if (n_points == 0) return hipSuccess;
+    if (n_points == 0 || n_states == 0) return hipSuccess;
+    const int64_t rk = kdist_radix_max_keys(elem_bytes, lds_max);
     if (elem_bytes == 8)
         return run_kdist<uint64_t>(static_cast<const uint64_t*>(kappa), n_points, ppb, g, k_out,
                                    static_cast<uint64_t*>(sorted_out),
-                                   static_cast<uint64_t*>(scratch), lds_bytes, s);
+                                   static_cast<uint64_t*>(scratch), lds_bytes, rk, n_states, s);
     return run_kdist<uint32_t>(static_cast<const uint32_t*>(kappa), n_points, ppb, g, k_out,
                                static_cast<uint32_t*>(sorted_out), static_cast<uint32_t*>(scratch),
-                               lds_bytes, s);
+                               lds_bytes, rk, n_states, s);
 }
 
 }  // namespace hk

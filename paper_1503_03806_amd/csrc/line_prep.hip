@@ -53,13 +53,11 @@ __device__ void region_interval(double R, double nu_min, double dnu, int32_t n, 
     *hi_out = (int32_t)hi;
 }
 
-__global__ __launch_bounds__(256) void line_prep_f64_kernel(LinesDev L, PrepParams pp,
-                                                            WingRec* __restrict__ wing,
-                                                            WingIdx* __restrict__ idx,
-                                                            CoreRec* __restrict__ core)
+// The records of line i for one state (constants pp).
+__device__ __forceinline__ void line_prep_one(const LinesDev& L, const PrepParams& pp, int64_t i,
+                                              WingRec* __restrict__ wing, WingIdx* __restrict__ idx,
+                                              CoreRec* __restrict__ core)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= L.n) return;
     const double nu = L.nu[i];
     const double E = L.E_lower[i];
     const double g_air = L.gamma_air[i];
@@ -145,17 +143,45 @@ __global__ __launch_bounds__(256) void line_prep_f64_kernel(LinesDev L, PrepPara
     core[i] = c;
 }
 
+__global__ __launch_bounds__(256) void line_prep_f64_kernel(LinesDev L, PrepParams pp,
+                                                            WingRec* __restrict__ wing,
+                                                            WingIdx* __restrict__ idx,
+                                                            CoreRec* __restrict__ core)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < L.n) line_prep_one(L, pp, i, wing, idx, core);
+}
+
+// Every state of a batch in one launch: state blockIdx.y, constants pps[st],
+// records n_lines apart per state.
+__global__ __launch_bounds__(256) void line_prep_f64_batch_kernel(LinesDev L, const PrepParams* __restrict__ pps,
+                                                                  WingRec* __restrict__ wing,
+                                                                  WingIdx* __restrict__ idx,
+                                                                  CoreRec* __restrict__ core)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t o = (int64_t)blockIdx.y * L.n;
+    if (i < L.n) line_prep_one(L, pps[blockIdx.y], i, wing + o, idx + o, core + o);
+}
+
 // Line index range [first, last) of every grid tile: the lines whose
 // unshifted centre lies within `reach` of the tile's points.  Each line in
 // the range is still tested against its exact window by the opacity kernel.
+// reach_of: NULL, or one reach per state (state blockIdx.y, ranges
+// 2 n_tiles apart per state).
 __global__ __launch_bounds__(256) void tile_ranges_kernel(const double* __restrict__ nu, int64_t n,
                                                           int64_t n_tiles, int32_t tile_points,
                                                           double nu_min, double dnu,
                                                           int32_t n_points, double reach,
+                                                          const double* __restrict__ reach_of,
                                                           int64_t* __restrict__ ranges)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tiles) return;
+    if (reach_of) {
+        reach = reach_of[blockIdx.y];
+        ranges += (int64_t)blockIdx.y * 2 * n_tiles;
+    }
     int64_t j0 = t * tile_points;
     int64_t j1 = j0 + tile_points;
     if (j1 > n_points) j1 = n_points;
@@ -189,6 +215,9 @@ __device__ inline int64_t overlap(int64_t alo, int64_t ahi, int64_t blo, int64_t
 __global__ __launch_bounds__(256) void eval_counts_kernel(const WingIdx* __restrict__ idx,
                                                           int64_t n, int64_t* __restrict__ partial)
 {
+    // state blockIdx.y of a batch: records n apart, partials 3 gridDim.x apart
+    idx += (int64_t)blockIdx.y * n;
+    partial += (int64_t)blockIdx.y * 3 * gridDim.x;
     __shared__ int64_t red[3][256];
     int64_t e = 0, c = 0, g = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -221,6 +250,10 @@ __global__ __launch_bounds__(256) void f32_peak_kernel(const WingRec* __restrict
                                                        double* __restrict__ partial)
 {
     __shared__ double red[256];
+    // state blockIdx.y of a batch: records n apart, partials gridDim.x apart
+    wing += (int64_t)blockIdx.y * n;
+    core += (int64_t)blockIdx.y * n;
+    partial += (int64_t)blockIdx.y * gridDim.x;
     double m = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -243,6 +276,8 @@ __global__ void f32_scale_kernel(const double* __restrict__ partial, int32_t n_b
                                  int32_t* __restrict__ scale)
 {
     if (threadIdx.x != 0) return;
+    partial += (int64_t)blockIdx.x * n_blocks;  // state blockIdx.x of a batch
+    scale += blockIdx.x;
     double m = 0.0;
     for (int32_t b = 0; b < n_blocks; ++b) m = fmax(m, partial[b]);
     scale[0] = m > 0.0 ? 100 - ilogb(m) : 0;
@@ -255,6 +290,15 @@ __global__ __launch_bounds__(256) void line_prep_f32_kernel(
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    {  // state blockIdx.y of a batch: records n apart
+        const int64_t o = (int64_t)blockIdx.y * n;
+        wing += o;
+        idx += o;
+        core += o;
+        w32 += o;
+        c32 += o;
+        scale += blockIdx.y;
+    }
     const WingRec w = wing[i];
     const CoreRec c = core[i];
     const int s = scale[0];
@@ -304,6 +348,14 @@ __global__ __launch_bounds__(256) void f32_finish_kernel(const float* __restrict
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
+    {  // state blockIdx.y of a batch: grids n apart
+        const int64_t o = (int64_t)blockIdx.y * n;
+        sum += o;
+        comp += o;
+        if (series) series += o;
+        kappa += o;
+        scale += blockIdx.y;
+    }
     float s = sum[j], c = -comp[j];
     const float x = series ? series[j] : 0.0f;
     if (x != 0.0f) {
@@ -319,31 +371,32 @@ __global__ __launch_bounds__(256) void f32_finish_kernel(const float* __restrict
 }  // namespace
 
 hipError_t launch_f32_scale(const WingRec* wing, const CoreRec* core, int64_t n_lines,
-                            double* partial, int32_t n_blocks, int32_t* scale, hipStream_t s)
+                            double* partial, int32_t n_blocks, int32_t* scale, hipStream_t s, int32_t n_states)
 {
-    f32_peak_kernel<<<dim3(n_blocks), dim3(256), 0, s>>>(wing, core, n_lines, partial);
-    f32_scale_kernel<<<dim3(1), dim3(64), 0, s>>>(partial, n_blocks, scale);
+    if (n_states <= 0) return hipSuccess;
+    f32_peak_kernel<<<dim3(n_blocks, n_states), dim3(256), 0, s>>>(wing, core, n_lines, partial);
+    f32_scale_kernel<<<dim3(n_states), dim3(64), 0, s>>>(partial, n_blocks, scale);
     return hipGetLastError();
 }
 
 hipError_t launch_line_prep_f32(const WingRec* wing, WingIdx* idx, const CoreRec* core,
                                 int64_t n_lines, double nu_min, double dnu, const int32_t* scale,
-                                WingRec32* w32, CoreRec32* c32, hipStream_t s)
+                                WingRec32* w32, CoreRec32* c32, hipStream_t s, int32_t n_states)
 {
-    if (n_lines == 0) return hipSuccess;
+    if (n_lines == 0 || n_states <= 0) return hipSuccess;
     const int64_t blocks = (n_lines + 255) / 256;
-    line_prep_f32_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(wing, idx, core, n_lines, nu_min,
-                                                                       dnu, scale, w32, c32);
+    line_prep_f32_kernel<<<dim3((unsigned)blocks, n_states), dim3(256), 0, s>>>(wing, idx, core, n_lines, nu_min,
+                                                                                 dnu, scale, w32, c32);
     return hipGetLastError();
 }
 
 hipError_t launch_f32_finish(const float* sum, const float* comp, const float* series, const int32_t* scale,
-                             int32_t n_points, double* kappa, int accumulate, hipStream_t s)
+                             int32_t n_points, double* kappa, int accumulate, hipStream_t s, int32_t n_states)
 {
-    if (n_points == 0) return hipSuccess;
+    if (n_points == 0 || n_states <= 0) return hipSuccess;
     const int64_t blocks = ((int64_t)n_points + 255) / 256;
-    f32_finish_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(sum, comp, series, scale, n_points, kappa,
-                                                                    accumulate);
+    f32_finish_kernel<<<dim3((unsigned)blocks, n_states), dim3(256), 0, s>>>(sum, comp, series, scale, n_points,
+                                                                              kappa, accumulate);
     return hipGetLastError();
 }
 
@@ -356,21 +409,32 @@ hipError_t launch_line_prep_f64(const LinesDev& L, const PrepParams& pp, WingRec
     return hipGetLastError();
 }
 
+hipError_t launch_line_prep_f64_batch(const LinesDev& L, const PrepParams* pps, int32_t n_states, WingRec* wing,
+                                      WingIdx* idx, CoreRec* core, hipStream_t s)
+{
+    if (L.n == 0 || n_states <= 0) return hipSuccess;
+    int64_t blocks = (L.n + 255) / 256;
+    line_prep_f64_batch_kernel<<<dim3((unsigned)blocks, n_states), dim3(256), 0, s>>>(L, pps, wing, idx, core);
+    return hipGetLastError();
+}
+
 hipError_t launch_tile_ranges(const double* nu_sorted, int64_t n_lines, int64_t n_tiles,
                               int32_t tile_points, double nu_min, double dnu, int32_t n_points,
-                              double reach, int64_t* ranges, hipStream_t s)
+                              double reach, int64_t* ranges, hipStream_t s, const double* reach_of,
+                              int32_t n_states)
 {
-    if (n_tiles == 0) return hipSuccess;
+    if (n_tiles == 0 || n_states <= 0) return hipSuccess;
     int64_t blocks = (n_tiles + 255) / 256;
-    tile_ranges_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(
-        nu_sorted, n_lines, n_tiles, tile_points, nu_min, dnu, n_points, reach, ranges);
+    tile_ranges_kernel<<<dim3((unsigned)blocks, reach_of ? n_states : 1), dim3(256), 0, s>>>(
+        nu_sorted, n_lines, n_tiles, tile_points, nu_min, dnu, n_points, reach, reach_of, ranges);
     return hipGetLastError();
 }
 
 hipError_t launch_eval_counts(const WingIdx* idx, int64_t n_lines, int64_t* partial,
-                              int32_t n_blocks, hipStream_t s)
+                              int32_t n_blocks, hipStream_t s, int32_t n_states)
 {
-    eval_counts_kernel<<<dim3(n_blocks), dim3(256), 0, s>>>(idx, n_lines, partial);
+    if (n_states <= 0) return hipSuccess;
+    eval_counts_kernel<<<dim3(n_blocks, n_states), dim3(256), 0, s>>>(idx, n_lines, partial);
     return hipGetLastError();
 }
 

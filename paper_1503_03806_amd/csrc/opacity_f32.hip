@@ -353,103 +353,186 @@ __device__ float voigt_core_f32(float x, float y, float ex, float T1, const floa
     return E * fmaf(ex, cos2, sn * sy * inv_pi) + (y * inv_pi) * fmaf(-cos2 * E, T1, 0.5f * (s2 + s3));
 }
 
-// Core-region terms: as core_f64_kernel (point ownership, compacted 64-point
-// chunks of the line's core interval, lane rotation); the run's ordered
-// binary32 series sums go to a grid of their own, which the finish adds to
-// the wing's Kahan pairs (so the two kernels can run at the same time).
-// With kSurr, points of certified (x, y) cells take the learned surrogate
-// instead of the series (the wavefront runs the network when any of its
-// lanes needs it, the series when any needs that).  Lines [L0, L1) of tile
-// t; direct: series_j = the run's sum (every point, 0 where no line
-// reaches); else every point's sum to partial[j - obase].
-template <int kP, bool kSurr = false>
-__device__ __forceinline__ void core_f32_tile(int64_t t, int64_t L0, int64_t L1, const WingIdx* __restrict__ idx,
-                                              const CoreRec32* __restrict__ core, int32_t n,
-                                              float* __restrict__ series, float* __restrict__ partial, int64_t obase,
-                                              bool direct, const surr::MlpBf16* __restrict__ P,
-                                              const uint8_t* __restrict__ mask)
+// Core-region terms: as core_f64_kernel (each wavefront owns a run of
+// kCoreRun points; the series pieces of the lines that meet it are packed
+// into 64-lane chunks, at most kChunkPieces per chunk; each lane adds its
+// point's value to the run's sums in LDS, pieces in line order); the run's
+// ordered binary32 series sums go to a grid of their own, which the finish
+// adds to the wing's Kahan pairs (so the two kernels can run at the same
+// time).  With kSurr, points of certified (x, y) cells take the learned
+// surrogate instead of the series (the wavefront runs the network when any
+// of its lanes needs it, the series when any needs that), and the count of
+// such points is returned.  Lines [L0, L1) of tile t; direct: series_j = the
+// run's sum (every point, 0 where no line reaches); else every point's sum
+// to partial[j - obase].
+constexpr int kCoreRun = 256;
+constexpr int kCoreTilePoints = kCoreRun * kWaves;
+constexpr int kCoreBatch = 32;
+constexpr int kChunkPieces = 16;
+
+struct alignas(16) CorePiece32 {  // one line's series points within a run
+    float dx, fx, y, y2, ex, norm, T1;
+    int32_t jc;     // the line's nearest grid point
+    int32_t a;      // its first point in the run
+    int32_t start;  // where its points begin in the batch's flattened list
+};
+
+__device__ inline int32_t wave_incl_scan(int32_t v, int lane)
 {
-    constexpr int kTilePoints = 64 * kP * kWaves;
-    __shared__ float inv_tab[kWaves][kMaxTerms];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+template <bool kSurr = false>
+__device__ __forceinline__ int64_t core_f32_tile(int64_t t, int64_t L0, int64_t L1, const WingIdx* __restrict__ idx,
+                                                 const CoreRec32* __restrict__ core, int32_t n,
+                                                 float* __restrict__ series, float* __restrict__ partial,
+                                                 int64_t obase, bool direct, const surr::MlpBf16* __restrict__ P,
+                                                 const uint8_t* __restrict__ mask)
+{
+    __shared__ float acc_tab[kWaves][kCoreRun];
+    __shared__ CorePiece32 piece_tab[kWaves][kCoreBatch];
+    __shared__ float w_tab[kWaves][kChunkPieces * kMaxTerms];
     __shared__ __align__(16) uint16_t act_tab[kSurr ? kWaves : 1][kSurr ? 64 * surr::kLd : 1];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int32_t run0 = (int32_t)(t * kTilePoints) + wave * 64 * kP;
-    const int32_t run1 = min(run0 + 64 * kP, n) - 1;
-    if (run0 > run1) return;
-    float* inv = inv_tab[wave];
-    float acc[kP];
-#pragma unroll
-    for (int p = 0; p < kP; ++p) acc[p] = 0.0f;
+    const int32_t run0 = (int32_t)(t * kCoreTilePoints) + wave * kCoreRun;
+    const int32_t run1 = min(run0 + kCoreRun, n) - 1;
+    if (run0 > run1) return 0;
+    float* acc = acc_tab[wave];
+    CorePiece32* pc = piece_tab[wave];
+    float* wt = w_tab[wave];
+    for (int q = lane; q < kCoreRun; q += 64) acc[q] = 0.0f;
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    int64_t n_used = 0;  // points of this wavefront the network evaluated
 
-    for (int64_t i = L0; i < L1; ++i) {
-        const int32_t a = max(max(idx[i].clo, idx[i].wlo), run0);
-        const int32_t b = min(min(idx[i].chi, idx[i].whi), run1);
-        if (a > b) continue;
-        const int32_t jc = idx[i].jc;
-        const CoreRec32 cr = core[i];
-        if (lane < kMaxTerms) {
-            const float m = 0.5f * (float)(lane + 1);
-            inv[lane] = 1.0f / fmaf(m, m, cr.y2);
+    for (int64_t base = L0; base < L1; base += kCoreBatch) {
+        const int64_t i = base + lane;
+        int32_t a = 1, b = 0, jc = 0;
+        if (lane < kCoreBatch && i < L1) {
+            const WingIdx r = idx[i];
+            a = max(max(r.clo, r.wlo), run0);
+            b = min(min(r.chi, r.whi), run1);
+            jc = r.jc;
+        }
+        const bool has = a <= b;
+        const uint64_t m = __ballot(has);
+        if (m == 0) continue;
+        const int np = __builtin_popcountll(m);
+        const int32_t cnt = has ? b - a + 1 : 0;
+        const int32_t incl = wave_incl_scan(cnt, lane);
+        const int32_t total = __shfl(incl, 63, 64);
+        if (has) {
+            const CoreRec32 cr = core[i];
+            CorePiece32 pp;
+            pp.dx = cr.dx;
+            pp.fx = cr.fx;
+            pp.y = cr.y;
+            pp.y2 = cr.y2;
+            pp.ex = cr.ex;
+            pp.norm = cr.norm;
+            pp.T1 = cr.T1;
+            pp.jc = jc;
+            pp.a = a;
+            pp.start = incl - cnt;
+            pc[__builtin_popcountll(m & below)] = pp;
         }
         __builtin_amdgcn_wave_barrier();
-        for (int32_t c0 = a; c0 <= b; c0 += 64) {
-            const int32_t j = c0 + lane;
+        const int32_t st_k = lane < np ? pc[lane].start : total;
+        int s_lo = 0;
+        for (int32_t f0 = 0; f0 < total;) {
+            int s_end = __builtin_popcountll(__ballot(lane < np && st_k < f0 + 64));
+            s_end = min(s_end, s_lo + kChunkPieces);
+            const int32_t next_start = __shfl(st_k, min(s_end, 63), 64);
+            const int32_t f_end = s_end < np ? min(next_start, f0 + 64) : min(total, f0 + 64);
+            const int n_tab = (s_end - s_lo) * kMaxTerms;
+            for (int e = lane; e < n_tab; e += 64) {
+                const int k = e / kMaxTerms, nn = e - k * kMaxTerms;
+                const float mm = 0.5f * (float)(nn + 1);
+                wt[e] = 1.0f / fmaf(mm, mm, pc[s_lo + k].y2);
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int32_t f = f0 + lane;
+            const bool act = f < f_end;
+            int my = s_lo;
+            for (int s = s_lo + 1; s < s_end; ++s) my = __shfl(st_k, s, 64) <= f ? s : my;
+            const CorePiece32& pp = pc[my];
+            const int32_t j = pp.a + (f - pp.start);
+            const int32_t jr = act ? j - run0 : 0;
+            const float x = act ? fabsf(fmaf((float)(j - pp.jc), pp.dx, -pp.fx)) : 0.0f;
+            const float* w = wt + (my - s_lo) * kMaxTerms;
             float v = 0.0f;
             if constexpr (kSurr) {
-                const bool valid = j <= b;
-                const float x = valid ? fabsf(fmaf((float)(j - jc), cr.dx, -cr.fx)) : 0.0f;
-                const bool use = valid && surr::certified(mask, x, cr.y);
-                if (__ballot(valid && !use)) {
-                    if (valid && !use) v = cr.norm * voigt_core_f32(x, cr.y, cr.ex, cr.T1, inv);
+                const bool use = act && surr::certified(mask, x, pp.y);
+                if (__ballot(act && !use)) {
+                    if (act && !use) v = pp.norm * voigt_core_f32(x, pp.y, pp.ex, pp.T1, w);
                 }
-                if (__ballot(use)) {
+                const uint64_t used = __ballot(use);
+                n_used += __builtin_popcountll(used);
+                if (used) {
                     const float z = surr::mlp_forward<false>(P, act_tab[wave], surr::feature_x(x),
-                                                             surr::feature_y(use ? cr.y : 1.0f));
-                    if (use) v = cr.norm * surr::surrogate_K(x, cr.y, z);
+                                                             surr::feature_y(use ? pp.y : 1.0f));
+                    if (use) v = pp.norm * surr::surrogate_K(x, pp.y, z);
                 }
-            } else if (j <= b) {
-                const float x = fabsf(fmaf((float)(j - jc), cr.dx, -cr.fx));
-                v = cr.norm * voigt_core_f32(x, cr.y, cr.ex, cr.T1, inv);
+            } else if (act) {
+                v = pp.norm * voigt_core_f32(x, pp.y, pp.ex, pp.T1, w);
             }
-            const int src = (lane - (c0 - run0)) & 63;
-            const float w = __shfl(v, src, 64);
-            const int32_t jo = c0 + src;
-            const int slot = (jo - run0 - lane) >> 6;
-#pragma unroll
-            for (int p = 0; p < kP; ++p) acc[p] += (jo <= b && slot == p) ? w : 0.0f;
+            // add in line order (see core_f64_tile)
+            volatile float* vacc = acc;
+            for (int s = s_lo; s < s_end; ++s)
+                if (act && my == s) vacc[jr] = vacc[jr] + v;
+            s_lo = (s_end < np && f_end >= next_start) ? s_end : s_end - 1;
+            f0 = f_end;
         }
         __builtin_amdgcn_wave_barrier();
     }
-#pragma unroll
-    for (int p = 0; p < kP; ++p) {
-        const int32_t j = run0 + lane + 64 * p;
-        if (j <= run1) {
+    __builtin_amdgcn_wave_barrier();
+    for (int q = lane; q < kCoreRun; q += 64) {
+        const int32_t jj = run0 + q;
+        if (jj <= run1) {
             if (direct)
-                series[j] = acc[p];
+                series[jj] = acc[q];
             else
-                partial[j - obase] = acc[p];
+                partial[jj - obase] = acc[q];
         }
     }
+    return n_used;
 }
 
 // One workgroup per work item of the series (the layout of wing_f32_kernel),
 // in plan order as in the binary64 series kernel;
-// kSurr: the learned surrogate where certified (single state).
-template <int kP, bool kSurr>
+// kSurr: the learned surrogate where certified (single state), and
+// used[blockIdx.x] = the points of the item the network evaluated (every
+// launched workgroup writes its slot, so the counts need no clearing).
+template <bool kSurr>
 __global__ __launch_bounds__(64 * kWaves) void core_f32_kernel(
     const WingIdx* __restrict__ idx, const CoreRec32* __restrict__ core, const int64_t* __restrict__ ranges,
     int64_t n_lines, int64_t n_tiles, int32_t n_states, WorkPlan wp, int32_t n, float* __restrict__ series,
-    float* __restrict__ partial, const surr::MlpBf16* __restrict__ P, const uint8_t* __restrict__ mask)
+    float* __restrict__ partial, const surr::MlpBf16* __restrict__ P, const uint8_t* __restrict__ mask,
+    int64_t* __restrict__ used)
 {
-    constexpr int64_t kTilePoints = 64 * kP * kWaves;
     WorkItem it;
+    int64_t n_used = 0;
     if (work_item(blockIdx.x, wp, ranges, n_tiles, n_states, it)) {
         const int64_t o = it.st * n_lines, so = it.st * (int64_t)n;
         const bool direct = it.slot < 0;
-        core_f32_tile<kP, kSurr>(it.tile, it.lo, it.hi, idx + o, core + o, n, series + so,
-                                 partial + (direct ? 0 : it.slot * kTilePoints), it.tile * kTilePoints, direct, P,
-                                 mask);
+        n_used = core_f32_tile<kSurr>(it.tile, it.lo, it.hi, idx + o, core + o, n, series + so,
+                                      partial + (direct ? 0 : it.slot * kCoreTilePoints),
+                                      it.tile * kCoreTilePoints, direct, P, mask);
+    }
+    if constexpr (kSurr) {
+        __shared__ int64_t wave_used[kWaves];
+        if ((threadIdx.x & 63) == 0) wave_used[threadIdx.x >> 6] = n_used;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t t = 0;
+            for (int w = 0; w < kWaves; ++w) t += wave_used[w];
+            used[blockIdx.x] = t;
+        }
     }
 }
 
@@ -478,6 +561,23 @@ __global__ __launch_bounds__(256) void core_f32_reduce_kernel(WorkPlan wp, int64
     }
 }
 
+// total[0] (+)= used[0] + ... + used[n-1], one workgroup (the surrogate's
+// per-workgroup counts of a launch).
+__global__ __launch_bounds__(256) void sum_counts_kernel(const int64_t* __restrict__ used, int64_t n,
+                                                         int64_t* __restrict__ total, int add)
+{
+    __shared__ int64_t part[256];
+    int64_t t = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) t += used[i];
+    part[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) total[0] = add ? total[0] + part[0] : part[0];
+}
+
 template <int kP>
 hipError_t launch_wing(const WingRec32* wing, const WingIdx* idx, const int64_t* ranges, int64_t n_lines,
                        int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int32_t n, float* sum, float* comp,
@@ -496,6 +596,7 @@ hipError_t launch_wing(const WingRec32* wing, const WingIdx* idx, const int64_t*
 }  // namespace
 
 int32_t opacity_f32_tile_points(int points_per_lane) { return 64 * points_per_lane * kWaves; }
+int32_t core_f32_tile_points() { return kCoreTilePoints; }
 
 hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const WingIdx* idx, const int64_t* ranges,
                            int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int32_t n_points,
@@ -512,22 +613,31 @@ hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const Win
 
 hipError_t launch_core_f32(const WingIdx* idx, const CoreRec32* core, const int64_t* ranges, int64_t n_lines,
                            int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int32_t n_points, float* series,
-                           float* partial, const void* surrogate, const uint8_t* mask, hipStream_t s)
+                           float* partial, const void* surrogate, const uint8_t* mask, int64_t* used,
+                           int64_t used_cap, hipStream_t s)
 {
     if (n_tiles == 0 || n_states == 0) return hipSuccess;
     if (surrogate && n_states != 1) return hipErrorInvalidValue;
     const int64_t nb = plan_blocks(wp.launch_items);
     if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+    if (surrogate && (!used || nb > used_cap)) return hipErrorInvalidValue;
     const auto* P = static_cast<const surr::MlpBf16*>(surrogate);
     if (surrogate)
-        core_f32_kernel<4, true><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(
-            idx, core, ranges, n_lines, n_tiles, n_states, wp, n_points, series, partial, P, mask);
+        core_f32_kernel<true><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(
+            idx, core, ranges, n_lines, n_tiles, n_states, wp, n_points, series, partial, P, mask, used);
     else
-        core_f32_kernel<4, false><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(
-            idx, core, ranges, n_lines, n_tiles, n_states, wp, n_points, series, partial, nullptr, nullptr);
+        core_f32_kernel<false><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(
+            idx, core, ranges, n_lines, n_tiles, n_states, wp, n_points, series, partial, nullptr, nullptr,
+            nullptr);
     const int64_t nr = std::min<int64_t>(wp.n_pairs, 8192);
-    core_f32_reduce_kernel<<<dim3((unsigned)nr), dim3(256), 0, s>>>(wp, n_tiles, n_states, 64 * 4 * kWaves,
+    core_f32_reduce_kernel<<<dim3((unsigned)nr), dim3(256), 0, s>>>(wp, n_tiles, n_states, kCoreTilePoints,
                                                                     n_points, partial, series);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_counts(const int64_t* used, int64_t n, int64_t* total, int add, hipStream_t s)
+{
+    sum_counts_kernel<<<dim3(1), dim3(256), 0, s>>>(used, n, total, add);
     return hipGetLastError();
 }
 

@@ -438,73 +438,142 @@ __device__ double voigt_core(double x, double y, double ex, double T1, const dou
     return E * (fma(ex, cos2, s * sy * kInvPi) + (y * kInvPi) * fma(-cos2, T1, 0.5 * sc));
 }
 
-// Core-region contributions: each wavefront owns a run of 64*P points as in
-// the wing kernel and walks, in order, the lines whose a^2+u^2 < 100 points
-// meet its run.  Those points form one contiguous interval [a, b]; lanes
-// take them 64 at a time, and each value moves to the lane owning its point
-// (a rotation of the wavefront) to be added there.  Lines [L0, L1) of tile t;
-// direct: series_j = the run's sum (every point, 0 where no line reaches);
-// else every point's sum to partial[j - obase].  The series has a grid of
-// its own, added to the wing's afterwards (the two kernels can then run at
-// the same time).
-template <int kP>
+// Core-region contributions.  Each wavefront owns a run of kCoreRun
+// consecutive points and walks, in line order, the lines whose a^2+u^2 < 100
+// points meet its run; a line's such points form one interval (a piece).
+// Pieces are packed into 64-lane chunks: the lines are examined kCoreBatch
+// at a time, their pieces' points laid end to end, and each chunk takes the
+// next 64 of them (at most kChunkPieces pieces per chunk), so lanes stay
+// full when pieces are short.  A lane evaluates the series for its point and
+// adds it to the run's sums in LDS; lanes of one chunk that share a point
+// (two lines covering it) add in line order, piece by piece.  So each point
+// still sums its lines in ascending (nu, index) order, with the same values:
+// the result does not depend on how pieces fall into chunks.
+// Lines [L0, L1) of tile t; direct: series_j = the run's sum (every point,
+// 0 where no line reaches); else every point's sum to partial[j - obase].
+// The series has a grid of its own, added to the wing's afterwards (the two
+// kernels can then run at the same time).
+constexpr int kCoreRun = 256;                        // points per wavefront
+constexpr int kCoreTilePoints = kCoreRun * kWaves;   // points per work item
+constexpr int kCoreBatch = 32;                       // lines examined at once
+constexpr int kChunkPieces = 16;                     // pieces per 64-lane chunk
+
+struct alignas(16) CorePiece {  // one line's series points within a run
+    double nu0, invA, y, y2, ex, norm, T1;
+    int32_t a;      // its first grid point
+    int32_t start;  // where its points begin in the batch's flattened list
+};
+
+__device__ inline int32_t wave_incl_scan(int32_t v, int lane)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
 __device__ __forceinline__ void core_f64_tile(int64_t t, int64_t L0, int64_t L1, const WingRec* __restrict__ wing,
                                               const WingIdx* __restrict__ idx, const CoreRec* __restrict__ core,
                                               double nu_min, double dnu, int32_t n, double* __restrict__ series,
                                               double* __restrict__ partial, int64_t obase, bool direct)
 {
-    constexpr int kTilePoints = 64 * kP * kWaves;
-    __shared__ double inv_tab[kWaves][kMaxTerms];
+    __shared__ double acc_tab[kWaves][kCoreRun];
+    __shared__ CorePiece piece_tab[kWaves][kCoreBatch];
+    __shared__ double w_tab[kWaves][kChunkPieces * kMaxTerms];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int32_t run0 = (int32_t)(t * kTilePoints) + wave * 64 * kP;
-    const int32_t run1 = min(run0 + 64 * kP, n) - 1;
+    const int32_t run0 = (int32_t)(t * kCoreTilePoints) + wave * kCoreRun;
+    const int32_t run1 = min(run0 + kCoreRun, n) - 1;
     if (run0 > run1) return;
-    double* inv = inv_tab[wave];
-    double acc[kP];
-#pragma unroll
-    for (int p = 0; p < kP; ++p) acc[p] = 0.0;
+    double* acc = acc_tab[wave];
+    CorePiece* pc = piece_tab[wave];
+    double* wt = w_tab[wave];
+    for (int q = lane; q < kCoreRun; q += 64) acc[q] = 0.0;
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
-    for (int64_t i = L0; i < L1; ++i) {
-        const int32_t a = max(max(idx[i].clo, idx[i].wlo), run0);
-        const int32_t b = min(min(idx[i].chi, idx[i].whi), run1);
-        if (a > b) continue;
-        const double nu0 = wing[i].nu0;
-        const CoreRec cr = core[i];
-        if (lane < kMaxTerms) {
-            const double m = 0.5 * (double)(lane + 1);
-            inv[lane] = kGauss[lane] * qrcp(fma(m, m, cr.y2));
+    for (int64_t base = L0; base < L1; base += kCoreBatch) {
+        // lanes below kCoreBatch examine one line each
+        const int64_t i = base + lane;
+        int32_t a = 1, b = 0;
+        if (lane < kCoreBatch && i < L1) {
+            const WingIdx r = idx[i];
+            a = max(max(r.clo, r.wlo), run0);
+            b = min(min(r.chi, r.whi), run1);
+        }
+        const bool has = a <= b;
+        const uint64_t m = __ballot(has);
+        if (m == 0) continue;
+        const int np = __builtin_popcountll(m);
+        const int32_t cnt = has ? b - a + 1 : 0;
+        const int32_t incl = wave_incl_scan(cnt, lane);
+        const int32_t total = __shfl(incl, 63, 64);
+        if (has) {
+            const CoreRec cr = core[i];
+            CorePiece pp;
+            pp.nu0 = wing[i].nu0;
+            pp.invA = cr.invA;
+            pp.y = cr.y;
+            pp.y2 = cr.y2;
+            pp.ex = cr.ex;
+            pp.norm = cr.norm;
+            pp.T1 = cr.T1;
+            pp.a = a;
+            pp.start = incl - cnt;
+            pc[__builtin_popcountll(m & below)] = pp;
         }
         __builtin_amdgcn_wave_barrier();
-        for (int32_t c0 = a; c0 <= b; c0 += 64) {
-            const int32_t j = c0 + lane;
-            double v = 0.0;
-            if (j <= b) {
-                const double dv = fma((double)j, dnu, nu_min) - nu0;
-                v = cr.norm * voigt_core(fabs(dv) * cr.invA, cr.y, cr.ex, cr.T1, inv);
+        // lane k holds piece k's start (pieces in line order, starts rising)
+        const int32_t st_k = lane < np ? pc[lane].start : total;
+        int s_lo = 0;  // the piece holding point f0 of the flattened list
+        for (int32_t f0 = 0; f0 < total;) {
+            int s_end = __builtin_popcountll(__ballot(lane < np && st_k < f0 + 64));
+            s_end = min(s_end, s_lo + kChunkPieces);
+            const int32_t next_start = __shfl(st_k, min(s_end, 63), 64);
+            const int32_t f_end = s_end < np ? min(next_start, f0 + 64) : min(total, f0 + 64);
+            // the 1 / (n^2/4 + y^2) e^{-n^2/4} tables of pieces s_lo .. s_end-1
+            const int n_tab = (s_end - s_lo) * kMaxTerms;
+            for (int e = lane; e < n_tab; e += 64) {
+                const int k = e / kMaxTerms, nn = e - k * kMaxTerms;
+                const double mm = 0.5 * (double)(nn + 1);
+                wt[e] = kGauss[nn] * qrcp(fma(mm, mm, pc[s_lo + k].y2));
             }
-            // lane L owns point run0 + L + 64 s; its value for this chunk
-            // sits in lane (L - (c0 - run0)) mod 64
-            const int src = (lane - (c0 - run0)) & 63;
-            const double w = __shfl(v, src, 64);
-            const int32_t jo = c0 + src;
-            const int slot = (jo - run0 - lane) >> 6;
-#pragma unroll
-            for (int p = 0; p < kP; ++p) acc[p] += (jo <= b && slot == p) ? w : 0.0;
+            __builtin_amdgcn_wave_barrier();
+            // this lane's point f and its piece
+            const int32_t f = f0 + lane;
+            const bool act = f < f_end;
+            int my = s_lo;
+            for (int s = s_lo + 1; s < s_end; ++s) my = __shfl(st_k, s, 64) <= f ? s : my;
+            double v = 0.0;
+            int32_t jr = 0;  // the point, relative to run0
+            if (act) {
+                const CorePiece& pp = pc[my];
+                const int32_t j = pp.a + (f - pp.start);
+                jr = j - run0;
+                const double dv = fma((double)j, dnu, nu_min) - pp.nu0;
+                v = pp.norm * voigt_core(fabs(dv) * pp.invA, pp.y, pp.ex, pp.T1, wt + (my - s_lo) * kMaxTerms);
+            }
+            // add in line order: lanes of one piece hold distinct points, and
+            // the pieces' read-add-writes stay in order (volatile: neither
+            // merged nor reordered by the compiler; a wavefront's LDS
+            // operations complete in order)
+            volatile double* vacc = acc;
+            for (int s = s_lo; s < s_end; ++s)
+                if (act && my == s) vacc[jr] = vacc[jr] + v;
+            s_lo = (s_end < np && f_end >= next_start) ? s_end : s_end - 1;
+            f0 = f_end;
         }
         __builtin_amdgcn_wave_barrier();
     }
-    if (direct) {
-#pragma unroll
-        for (int p = 0; p < kP; ++p) {
-            const int32_t j = run0 + lane + 64 * p;
-            if (j <= run1) series[j] = acc[p];
-        }
-    } else {
-#pragma unroll
-        for (int p = 0; p < kP; ++p) {
-            const int32_t j = run0 + lane + 64 * p;
-            if (j <= run1) partial[j - obase] = acc[p];
+    __builtin_amdgcn_wave_barrier();
+    for (int q = lane; q < kCoreRun; q += 64) {
+        const int32_t j = run0 + q;
+        if (j <= run1) {
+            if (direct)
+                series[j] = acc[q];
+            else
+                partial[j - obase] = acc[q];
         }
     }
 }
@@ -512,20 +581,18 @@ __device__ __forceinline__ void core_f64_tile(int64_t t, int64_t L0, int64_t L1,
 // One workgroup per work item of the series (the layout of wing_f64_kernel),
 // taken in plan order: a series tile reads few lines, so dealing neighbouring
 // tiles to one XCD does not pay here (measured: it costs ~5%).
-template <int kP>
 __global__ __launch_bounds__(64 * kWaves) void core_f64_kernel(
     const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx, const CoreRec* __restrict__ core,
     const int64_t* __restrict__ ranges, int64_t n_lines, int64_t n_tiles, int32_t n_states, WorkPlan wp,
     double nu_min, double dnu, int32_t n, double* __restrict__ series, double* __restrict__ partial)
 {
-    constexpr int64_t kTilePoints = 64 * kP * kWaves;
     WorkItem it;
     if (work_item(blockIdx.x, wp, ranges, n_tiles, n_states, it)) {
         const int64_t o = it.st * n_lines;
         const bool direct = it.slot < 0;
-        core_f64_tile<kP>(it.tile, it.lo, it.hi, wing + o, idx + o, core + o, nu_min, dnu, n,
-                          series + it.st * (int64_t)n, partial + (direct ? 0 : it.slot * kTilePoints),
-                          it.tile * kTilePoints, direct);
+        core_f64_tile(it.tile, it.lo, it.hi, wing + o, idx + o, core + o, nu_min, dnu, n,
+                      series + it.st * (int64_t)n, partial + (direct ? 0 : it.slot * kCoreTilePoints),
+                      it.tile * kCoreTilePoints, direct);
     }
 }
 
@@ -574,7 +641,7 @@ hipError_t launch_wing(const WingRec* wing, const WingIdx* idx, const int64_t* r
 }  // namespace
 
 int32_t opacity_f64_tile_points(int points_per_lane) { return 64 * points_per_lane * kWaves; }
-int32_t core_f64_tile_points() { return 64 * 4 * kWaves; }
+int32_t core_f64_tile_points() { return kCoreTilePoints; }
 
 hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingIdx* idx, const int64_t* ranges,
                            int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, double nu_min,
@@ -597,9 +664,9 @@ hipError_t launch_core_f64(const WingRec* wing, const WingIdx* idx, const CoreRe
     if (n_tiles == 0 || n_states == 0) return hipSuccess;
     const int64_t nb = plan_blocks(wp.launch_items);
     if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
-    core_f64_kernel<4><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(wing, idx, core, ranges, n_lines, n_tiles,
-                                                                       n_states, wp, nu_min, dnu, n_points, series,
-                                                                       partial);
+    core_f64_kernel<<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(wing, idx, core, ranges, n_lines, n_tiles,
+                                                                    n_states, wp, nu_min, dnu, n_points, series,
+                                                                    partial);
     const int64_t nr = std::min<int64_t>(wp.n_pairs, 8192);
     core_f64_reduce_kernel<<<dim3((unsigned)nr), dim3(256), 0, s>>>(wp, n_tiles, n_states, core_f64_tile_points(),
                                                                     n_points, partial, series);

@@ -204,6 +204,30 @@ def test_surrogate_calls_validate_arguments():
     assert L.hk_surrogate_certify(None, 0.0, None, None) == hk.HK_EINVAL
     assert L.hk_surrogate_certify(None, 1e-5, None, None) == hk.HK_EINVAL
     assert "context" in hk.hk_last_error(None)
+    # the saved-surrogate blob: header and size are checked before anything
+    # else; the layout is 32 + 4 * N_PARAMS (+ 8 * cells when certified)
+    assert L.hk_surrogate_load(None, None, 0) == hk.HK_EINVAL
+    assert L.hk_surrogate_load(None, b"HKSURR01", 8) == hk.HK_EINVAL
+    assert "header" in hk.hk_last_error(None)
+    n_cells = hk.HK_SURR_CELLS_X * hk.HK_SURR_CELLS_Y
+    head = np.zeros(1, dtype=[("m", "S8"), ("p", "<i4"), ("c", "<i4"), ("cert", "<i4"), ("r", "<i4"),
+                              ("b", "<f8")])
+    head["m"], head["p"], head["c"], head["cert"], head["b"] = b"HKSURR0X", hk.HK_SURR_N_PARAMS, n_cells, 0, 0.0
+    body = np.zeros(hk.HK_SURR_N_PARAMS, dtype="<f4").tobytes()
+    assert L.hk_surrogate_load(None, head.tobytes() + body, 32 + len(body)) == hk.HK_EINVAL
+    assert "magic" in hk.hk_last_error(None)
+    head["m"] = b"HKSURR01"
+    assert L.hk_surrogate_load(None, head.tobytes() + body[:-4], 28 + len(body)) == hk.HK_EINVAL
+    assert "expected" in hk.hk_last_error(None)
+    head["p"] = 100
+    assert L.hk_surrogate_load(None, head.tobytes() + body, 32 + len(body)) == hk.HK_EINVAL
+    assert "layout" in hk.hk_last_error(None)
+    head["p"] = hk.HK_SURR_N_PARAMS
+    # a well-formed blob reaches the context check
+    assert L.hk_surrogate_load(None, head.tobytes() + body, 32 + len(body)) == hk.HK_EINVAL
+    assert "context" in hk.hk_last_error(None)
+    size = C.c_size_t(0)
+    assert L.hk_surrogate_save(None, None, 0, C.byref(size)) == hk.HK_EINVAL
 
 
 def test_resample_and_transmission_validate_arguments():

@@ -140,10 +140,12 @@ def test_f32_rejects_too_wide_windows(ctx):
     assert ex.value.code == hk.HK_EINVAL and "2^23" in str(ex.value)
 
 
-def test_f32_lines1e7_sampled_bins(ctx):
-    """The precision workload at full size (1e7 lines, 2000 K, 0.1 bar): the
-    oracle evaluates three whole bins (first, middle, last); the per-bin
-    error of kappa and of k(g) is printed (the workload reports it)."""
+def test_f32_lines1e7_seeded_bins(ctx):
+    """The precision workload at full size (1e7 lines, 2000 K, 0.1 bar) in
+    the benchmark's launch configuration: 16 whole bins drawn with seed 3,
+    kappa and k(g) against the oracle at 1e-4 (the oracle is given the lines
+    that can reach each bin); per-bin max and p99.9 errors printed."""
+    from parity_util import near_lines, rel_errors, seeded_bins
     w = synth.WORKLOADS["lines1e7_fp32"]
     lines, cond, grid = w.lines(), w.conditions(), w.grid()
     say("workload", w.name)
@@ -153,10 +155,13 @@ def test_f32_lines1e7_sampled_bins(ctx):
     ppb = w.points_per_bin
     g, _ = oracle.g_nodes(w.n_g)
     kd = ctx.kdist(k, ppb, g).cpu().numpy()
-    for b in (0, 150, 299):
-        ref, _ = oracle.opacity(lines, cond, grid, b * ppb, (b + 1) * ppb)
-        e = rel_err(kk[b * ppb:(b + 1) * ppb], ref)
+    worst = 0.0
+    for b in seeded_bins(w.n_bins):
+        j0, j1 = b * ppb, (b + 1) * ppb
+        ref, _ = oracle.opacity(near_lines(lines, grid, j0, j1), cond, grid, j0, j1)
+        e = rel_errors(kk[j0:j1], ref)
         kr, _ = oracle.kdist_bin(ref, g)
         ek = np.abs(kd[b] / kr - 1).max()
         say("  bin %d: kappa max %.2e p99.9 %.2e, k(g) max %.2e" % (b, e.max(), np.quantile(e, 0.999), ek))
-        assert e.max() <= TOL and ek <= TOL
+        worst = max(worst, e.max(), ek)
+    assert worst <= TOL

@@ -266,9 +266,16 @@ def test_kdist_linear_rule_matches_oracle_bitwise(ctx, n, ppb, precision):
     assert np.array_equal(kd0, oracle.kdist(kap, ppb, g))
 
 
-# ---- the mid-scale workload at full size (the benchmark's launch), sampled ----
+# ---- the mid-scale workload at full size (the benchmark's launch), whole grid ----
 
-def test_lines1e6_grid3e6_sampled(ctx):
+def test_lines1e6_grid3e6_full(ctx):
+    """The mid-scale binary64 workload (1e6 lines, 3e6 points, 100 cm^-1
+    cutoff, 1500 K, 1 atm) in the benchmark's launch configuration: every
+    one of the 3e6 grid points and all 300 k(g) rows against the oracle at
+    1e-6; the per-bin max and p99.9 errors are printed.  The k-distribution
+    of the oracle's own grid, computed on the GPU, equals the oracle's bit
+    for bit (sorting and picking involve no arithmetic)."""
+    from parity_util import per_bin, rel_errors
     w = synth.WORKLOADS["lines1e6_grid3e6"]
     lines, cond, grid = w.lines(), w.conditions(), w.grid()
     say("workload", w.name)
@@ -276,13 +283,14 @@ def test_lines1e6_grid3e6_sampled(ctx):
     k = kg.cpu().numpy()
     N = grid["n_points"]
     assert np.all(np.isfinite(k)) and np.all(k > 0)
-    rng = np.random.default_rng(31)
-    for j0 in (0, N // 2 - 1000, N - 2000) + tuple(int(v) for v in rng.integers(0, N - 300, 3)):
-        j1 = min(j0 + 2000, N)
-        ref, _ = oracle.opacity(lines, cond, grid, j0, j1)
-        assert_close(k[j0:j1], ref, what="points %d..%d" % (j0, j1))
     st = ctx.stats()
-    assert st["evals"] > 1.9e10 and st["evals_core"] > 0
+    ref, n_ora = oracle.opacity(lines, cond, grid)
+    assert st["evals"] == n_ora
+    e = rel_errors(k, ref)
+    pb = per_bin(e, w.points_per_bin)
+    say("  kappa: worst bin max %.2e, worst bin p99.9 %.2e, median bin max %.2e"
+        % (pb[:, 0].max(), pb[:, 1].max(), np.median(pb[:, 0])))
+    assert e.max() <= TOL, ("point", int(e.argmax()), float(e.max()))
     # the tile shape changes no bit
     ctx.set_option("f64_points_per_lane", 8)
     k2 = gpu_opacity(ctx, lines, cond, grid).cpu().numpy()
@@ -290,13 +298,15 @@ def test_lines1e6_grid3e6_sampled(ctx):
     assert np.array_equal(k.view(np.uint64), k2.view(np.uint64))
     g_gpu, _ = hk.hk_gauss_legendre(w.n_g)
     g_ora, _ = oracle.g_nodes(w.n_g)
-    kd = ctx.kdist(kg, w.points_per_bin, g_gpu).cpu().numpy()
-    assert kd.shape == (300, 20)
     ppb = w.points_per_bin
-    for b in (0, 137, 299):
-        ref, _ = oracle.opacity(lines, cond, grid, b * ppb, (b + 1) * ppb)
-        kr, _ = oracle.kdist_bin(ref, g_ora)
-        assert_close(kd[b], kr, what="k(g) bin %d" % b)
+    kd = ctx.kdist(kg, ppb, g_gpu).cpu().numpy()
+    assert kd.shape == (300, 20)
+    kr = oracle.kdist(ref, ppb, g_ora)
+    ek = np.abs(kd / kr - 1.0)
+    say("  k(g): worst bin max %.2e, median bin max %.2e" % (ek.max(), np.median(ek.max(axis=1))))
+    assert ek.max() <= TOL, ("k(g) bin", int(ek.max(axis=1).argmax()), float(ek.max()))
+    kd_of_ref = ctx.kdist(torch.from_numpy(ref).cuda(), ppb, g_ora).cpu().numpy()
+    assert np.array_equal(kd_of_ref, kr)
 
 
 def test_follows_a_non_default_torch_stream(ctx):

@@ -145,6 +145,33 @@ def trained(ctx):
     return {"hist": hist, "err": err, "count": count, "theta": ctx.surrogate_params()}
 
 
+def test_saved_surrogate_loads_into_a_new_context(ctx, trained):
+    """hk_surrogate_save / hk_surrogate_load: a new context given the blob
+    holds the same parameters and certification, and its surrogate opacity
+    equals the training context's bit for bit."""
+    blob = ctx.surrogate_save()
+    n_cells = hk.HK_SURR_CELLS_X * hk.HK_SURR_CELLS_Y
+    assert len(blob) == 32 + 4 * hk.HK_SURR_N_PARAMS + 8 * n_cells
+    w = synth.WORKLOADS["lines1e4_grid3e5"]
+    lines, cond, grid = w.lines(), w.conditions(), w.grid()
+    st = {k: cond[k] for k in ("T", "P", "P_self", "q_ratio")}
+    ctx.load_lines(lines, cond["mass_amu"], cond["T0"])
+    a = ctx.opacity(st, grid, hk.HK_F32_SURROGATE).cpu().numpy()
+    c2 = hk.Context(0)
+    try:
+        with pytest.raises(hk.HKError):  # no certification yet
+            c2.load_lines(lines, cond["mass_amu"], cond["T0"])
+            c2.opacity(st, grid, hk.HK_F32_SURROGATE)
+        c2.surrogate_load(blob)
+        assert np.array_equal(c2.surrogate_params(), trained["theta"])
+        b = c2.opacity(st, grid, hk.HK_F32_SURROGATE).cpu().numpy()
+        assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+        assert c2.stats()["evals_surrogate"] == ctx.stats()["evals_surrogate"] > 0
+        assert c2.surrogate_save() == blob
+    finally:
+        c2.close()
+
+
 def test_training_reduces_the_loss(trained):
     h = trained["hist"]
     assert np.all(np.isfinite(h))
@@ -184,11 +211,19 @@ def test_opacity_with_surrogate_matches_oracle(ctx, trained):
     ctx.load_lines(lines, cond["mass_amu"], cond["T0"])
     st = {k: cond[k] for k in ("T", "P", "P_self", "q_ratio")}
     k_s = ctx.opacity(st, grid, hk.HK_F32_SURROGATE).cpu().numpy()
+    st_s = ctx.stats()
     k_f = ctx.opacity(st, grid, hk.HK_F32_KAHAN).cpu().numpy()
+    st_f = ctx.stats()
     ref, _ = oracle.opacity(lines, cond, grid)
     e = np.abs(k_s / ref - 1)
-    say("surrogate opacity: max rel err vs oracle %.2e (binary32 path %.2e)"
-        % (e.max(), np.abs(k_f / ref - 1).max()))
+    say("surrogate opacity: max rel err vs oracle %.2e (binary32 path %.2e); the network evaluated"
+        " %d of %d series-region points (%.1f%%)"
+        % (e.max(), np.abs(k_f / ref - 1).max(), st_s["evals_surrogate"], st_s["evals_core"],
+           100.0 * st_s["evals_surrogate"] / max(st_s["evals_core"], 1)))
+    # the network ran, and changed results where it did
+    assert 0 < st_s["evals_surrogate"] <= st_s["evals_core"]
+    assert st_f["evals_surrogate"] == 0
+    assert np.count_nonzero(k_s != k_f) > 0
     assert e.max() <= 1e-4
     g, _ = oracle.g_nodes(w.n_g)
     kd = ctx.kdist(torch.tensor(k_s, device="cuda"), w.points_per_bin, g).cpu().numpy()
@@ -213,37 +248,49 @@ def test_surrogate_gain_is_reported(ctx, trained):
             k = ctx.opacity(st, grid, prec)
         tm = ctx.timing()
         ctx.set_timing(False)
-        out[prec] = (k.cpu().numpy(), tm["core"][0] / 3, sum(v[0] for v in tm.values()) / 3)
+        out[prec] = (k.cpu().numpy(), tm["core"][0] / 3, sum(v[0] for v in tm.values()) / 3, ctx.stats())
     e = np.abs(out[hk.HK_F32_SURROGATE][0] / out[hk.HK_F32_KAHAN][0] - 1).max()
+    ss = out[hk.HK_F32_SURROGATE][3]
     say("gain: series-kernel ms %.3f -> %.3f with the surrogate; whole opacity ms %.3f -> %.3f;"
-        " certified cells %d; max rel diff %.2e"
+        " certified cells %d; network share of series-region points %.1f%%; max rel diff %.2e"
         % (out[hk.HK_F32_KAHAN][1], out[hk.HK_F32_SURROGATE][1], out[hk.HK_F32_KAHAN][2],
-           out[hk.HK_F32_SURROGATE][2], trained["count"], e))
+           out[hk.HK_F32_SURROGATE][2], trained["count"],
+           100.0 * ss["evals_surrogate"] / max(ss["evals_core"], 1), e))
+    assert ss["evals_surrogate"] > 0 and out[hk.HK_F32_KAHAN][3]["evals_surrogate"] == 0
     assert e <= 1e-4
 
 
-def test_surrogate_workload_full_size_sampled(ctx, trained):
+def test_surrogate_workload_seeded_bins(ctx, trained):
     """The surrogate configuration at its full size (1e8 lines over
     0-30000 cm^-1, 3e6 points, 25 cm^-1 cutoff, 1500 K, 1 atm), in the launch
-    configuration the benchmark times: four windows of 8 points against the
-    oracle.  The oracle is given the lines within the cutoff (+1 cm^-1) of
-    each window -- every other line adds exactly nothing there -- so that it
-    does not sort and prepare all 1e8 lines per window."""
+    configuration the benchmark times: 16 whole bins drawn with seed 3,
+    kappa and k(g) against the oracle at 1e-4.  The oracle is given the lines
+    that can reach each bin -- every other line adds exactly nothing there --
+    so that it does not sort and prepare all 1e8 lines per bin."""
+    from parity_util import near_lines, rel_errors, seeded_bins
     w = synth.WORKLOADS["lines1e8_surrogate"]
     lines, cond, grid = w.lines(), w.conditions(), w.grid()
     say("full size: %d lines, %d points" % (len(lines["nu"]), grid["n_points"]))
     ctx.load_lines(lines, cond["mass_amu"], cond["T0"])
     st = {k: cond[k] for k in ("T", "P", "P_self", "q_ratio")}
     k = ctx.opacity(st, grid, hk.HK_F32_SURROGATE)
+    sts = ctx.stats()
+    say("  the network evaluated %d of %d series-region points (%.1f%%)"
+        % (sts["evals_surrogate"], sts["evals_core"], 100.0 * sts["evals_surrogate"] / max(sts["evals_core"], 1)))
+    assert sts["evals_surrogate"] > 0
+    ppb = w.points_per_bin
+    g, _ = oracle.g_nodes(w.n_g)
+    kd = ctx.kdist(k, ppb, g).cpu().numpy()
+    kk = k.cpu().numpy()
     worst = 0.0
-    for j0 in (1000, 1_000_003, 2_000_017, 2_999_990):
-        got = k[j0:j0 + 8].cpu().numpy()
-        lo = grid["nu_min"] + j0 * grid["dnu"] - grid["cutoff"] - 1.0
-        hi = grid["nu_min"] + (j0 + 7) * grid["dnu"] + grid["cutoff"] + 1.0
-        near = (lines["nu"] >= lo) & (lines["nu"] <= hi)
-        ref, _ = oracle.opacity({f: v[near] for f, v in lines.items()}, cond, grid, j0, j0 + 8)
-        worst = max(worst, float(np.abs(got / ref - 1).max()))
-    say("  max rel err vs oracle %.2e over 32 sampled points" % worst)
+    for b in seeded_bins(w.n_bins):
+        j0, j1 = b * ppb, (b + 1) * ppb
+        ref, _ = oracle.opacity(near_lines(lines, grid, j0, j1), cond, grid, j0, j1)
+        e = rel_errors(kk[j0:j1], ref)
+        kr, _ = oracle.kdist_bin(ref, g)
+        ek = np.abs(kd[b] / kr - 1).max()
+        say("  bin %d: kappa max %.2e p99.9 %.2e, k(g) max %.2e" % (b, e.max(), np.quantile(e, 0.999), ek))
+        worst = max(worst, e.max(), ek)
     assert worst <= 1e-4
     del k
     ctx.load_lines(synth.line_list(10, 10.0), cond["mass_amu"], cond["T0"])  # release the list's device memory

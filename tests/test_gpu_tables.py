@@ -154,8 +154,10 @@ def test_tables_edge_cases(ctx):
 
 def test_tables200_full_size_sampled(ctx):
     """The table workload at full size: 1e6 lines, 3e6 points, 20 x 10
-    (T, P) states, binary32 profiles; oracle k(g) on three bins of three
-    states (coldest/lowest pressure, hottest/highest, a middle one)."""
+    (T, P) states, binary32 profiles; oracle k(g) on 16 (state, bin) pairs
+    drawn with seed 3, plus the table's corners (coldest/lowest pressure,
+    hottest/highest)."""
+    from parity_util import SAMPLE_SEED, near_lines
     w = synth.WORKLOADS["lines1e6_tables200"]
     lines, grid = w.lines(), w.grid()
     conds = [synth.conditions(T, P) for T, P in w.states]
@@ -170,11 +172,14 @@ def test_tables200_full_size_sampled(ctx):
     assert tab.shape == (200, w.n_bins, w.n_g)
     assert np.all(np.isfinite(tab)) and np.all(tab >= 0)
     assert np.all(np.diff(tab, axis=2) >= 0)  # k(g) is monotone in g
-    for s in (0, 105, 199):
-        for b in (0, 150, 299):
-            ref, _ = oracle.opacity(lines, conds[s], grid, b * ppb, (b + 1) * ppb)
-            kr, _ = oracle.kdist_bin(ref, g)
-            e = np.abs(tab[s, b] / kr - 1).max()
-            say("  state %d (T=%.0f K, P=%.2e atm) bin %d: k(g) max rel err %.2e"
-                % (s, conds[s]["T"], conds[s]["P"], b, e))
-            assert e <= TOL[hk.HK_F32_KAHAN]
+    rng = np.random.default_rng(SAMPLE_SEED)
+    pairs = [(0, 0), (199, 299)] + [(int(s), int(b)) for s, b in
+                                    zip(rng.choice(200, 16, replace=False), rng.choice(w.n_bins, 16))]
+    for s, b in pairs:
+        j0, j1 = b * ppb, (b + 1) * ppb
+        ref, _ = oracle.opacity(near_lines(lines, grid, j0, j1), conds[s], grid, j0, j1)
+        kr, _ = oracle.kdist_bin(ref, g)
+        e = np.abs(tab[s, b] / kr - 1).max()
+        say("  state %d (T=%.0f K, P=%.2e atm) bin %d: k(g) max rel err %.2e"
+            % (s, conds[s]["T"], conds[s]["P"], b, e))
+        assert e <= TOL[hk.HK_F32_KAHAN]

@@ -59,6 +59,25 @@ def test_transmission_of_constant_and_exponential_kappa():
     assert np.allclose(R.transmission_fit(c, m), ref, rtol=1e-10, atol=1e-14)
 
 
+def test_direct_transmission_closed_forms():
+    """Eq. (5) on bins whose k-distribution is a step function: a constant
+    bin gives exp(-k m); a bin of two values in proportions p and 1 - p gives
+    p exp(-k1 m) + (1 - p) exp(-k2 m); a bin of values k_i = i c (i = 0 ..
+    M-1) gives the geometric sum (1 - r^M) / (M (1 - r)), r = exp(-c m)."""
+    m = np.logspace(-4, 4, 41)
+    k = np.full(1000, 0.37)
+    assert np.allclose(R.transmission_direct(k, m), np.exp(-0.37 * m), rtol=1e-14, atol=0)
+    k1, k2 = 0.02, 5.0
+    k = np.array([k1] * 300 + [k2] * 700)
+    ref = 0.3 * np.exp(-k1 * m) + 0.7 * np.exp(-k2 * m)
+    assert np.allclose(R.transmission_direct(k, m), ref, rtol=1e-13, atol=1e-300)
+    M, c = 257, 0.01
+    k = c * np.arange(M)
+    r = np.exp(-c * m)
+    ref = (1.0 - r ** M) / (M * (1.0 - r))
+    assert np.allclose(R.transmission_direct(k, m), ref, rtol=1e-12, atol=0)
+
+
 def test_direct_transmission_ignores_the_order():
     rng = np.random.default_rng(3)
     k = 10.0 ** rng.uniform(-3, 3, 777)
