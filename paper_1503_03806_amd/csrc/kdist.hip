@@ -91,16 +91,17 @@ __device__ inline double k_of_g(const K* s, int64_t m, double g, int rule)
 }
 
 // LDS radix sort of one bin per workgroup (bins of up to kRadixMaxKeys keys):
-// kRadixThreads threads hold the bin's keys in registers, key r of thread t
-// at position r * kRadixThreads + t, and sort them least significant digit
-// first, 8 bits per pass (8 passes of binary64 keys, 4 of binary32).  Each
-// pass is stable: a wavefront ranks the keys of one round among equal
-// digits with eight ballots (the lanes sharing a lane's digit are the AND
-// over the digit's bits of each bit's ballot or its complement) and keeps a
-// running count per digit in its own LDS counters, so its keys are ranked in
-// position order with no barrier between rounds; then the counters become
-// offsets (waves in order, digits by a scan), every key is written to its
-// place in LDS and read back in position order.  Four barriers per pass.
+// kRadixThreads threads hold the bin's keys in registers -- wavefront w
+// holds positions [w R 64, (w+1) R 64), lane l of it key r at position
+// w R 64 + r 64 + l (R keys per thread) -- and sort them least significant
+// digit first, 8 bits per pass (8 passes of binary64 keys, 4 of binary32).
+// Each pass is stable: a wavefront ranks its keys round by round (so in
+// position order) among equal digits with eight ballots (the lanes sharing a
+// lane's digit are the AND over the digit's bits of each bit's ballot or its
+// complement) and keeps a running count per digit in its own LDS counters,
+// with no barrier between rounds; then the counters become offsets (waves in
+// order, digits by a scan), every key is written to its place in LDS and read
+// back in position order.  Four barriers per pass.
 constexpr int kRadixThreads = 1024;
 constexpr int kRadixWaves = kRadixThreads / 64;
 constexpr int kRadixMaxRounds = 16;
@@ -120,7 +121,7 @@ __device__ inline void radix_sort_block(K (&key)[kRadixMaxRounds], int rounds, i
 #pragma unroll
         for (int r = 0; r < kRadixMaxRounds; ++r) {
             if (r < rounds) {
-                const bool valid = r * kRadixThreads + t < m;
+                const bool valid = wave * 64 * rounds + r * 64 + lane < m;
                 const uint32_t d = (uint32_t)(key[r] >> shift) & 0xffu;
                 uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -161,7 +162,7 @@ __device__ inline void radix_sort_block(K (&key)[kRadixMaxRounds], int rounds, i
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < kRadixMaxRounds; ++r) {
-            if (r < rounds && r * kRadixThreads + t < m) {
+            if (r < rounds && wave * 64 * rounds + r * 64 + lane < m) {
                 const uint32_t d = (uint32_t)(key[r] >> shift) & 0xffu;
                 const uint32_t pos = cnt[wave * 256 + d] + rank[r];
                 if (pos < (uint32_t)m) buf[pos] = key[r];  // pos < m always
@@ -170,7 +171,7 @@ __device__ inline void radix_sort_block(K (&key)[kRadixMaxRounds], int rounds, i
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < kRadixMaxRounds; ++r) {
-            const int p = r * kRadixThreads + t;
+            const int p = wave * 64 * rounds + r * 64 + lane;
             if (r < rounds && p < m) key[r] = buf[p];
         }
     }
@@ -195,18 +196,15 @@ __global__ __launch_bounds__(kRadixThreads) void radix_bin_kernel(const K* __res
     uint32_t* cnt = reinterpret_cast<uint32_t*>(radix_lds + (size_t)rounds * kRadixThreads * sizeof(K));
     uint32_t* wsum = cnt + kRadixWaves * 256;
     K key[kRadixMaxRounds];
+    const int base_p = (int)(threadIdx.x >> 6) * 64 * rounds + (int)(threadIdx.x & 63);
 #pragma unroll
     for (int r = 0; r < kRadixMaxRounds; ++r) {
-        const int p = r * kRadixThreads + (int)threadIdx.x;
+        const int p = base_p + r * 64;
         key[r] = (r < rounds && p < m) ? src[b0 + p] : KeyMax<K>::v;
     }
     radix_sort_block<K>(key, rounds, m, buf, cnt, wsum);
-    if (dst) {
-#pragma unroll
-        for (int r = 0; r < kRadixMaxRounds; ++r) {
-            const int p = r * kRadixThreads + (int)threadIdx.x;
-            if (r < rounds && p < m) dst[b0 + p] = key[r];
-        }
+    if (dst) {  // the sorted bin, from LDS (coalesced)
+        for (int p = (int)threadIdx.x; p < m; p += kRadixThreads) dst[b0 + p] = buf[p];
     }
     // buf holds the bin in order after the last pass
     if ((int)threadIdx.x < g.n) k_out[bin * g.n + threadIdx.x] = k_of_g<K>(buf, m, g.g[threadIdx.x], g.rule);
