@@ -281,6 +281,22 @@ int hk_opacity_stream(hk_ctx* ctx, const hk_lines* chunks, int32_t n_chunks, con
 int hk_kdist(hk_ctx* ctx, const void* kappa, int precision, int64_t n_points,
              const hk_bins* bins, double* k_out, void* sorted_out);
 
+/* hk_kdist without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same arguments and results, bit for bit.  Bins
+ * larger than one LDS sort (16384 keys on gfx950) are merged through a
+ * fixed device array of HK_KDIST_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every device it runs on until the process ends, instead of the
+ * context's scratch; such calls need n_points * (8 or 4 key bytes) * 2 <=
+ * HK_KDIST_NOALLOC_SCRATCH_BYTES, else HK_EINVAL (nothing enqueued).  Every
+ * call on one device shares that array, and nothing in it needs clearing
+ * (each call overwrites what it reads); calls that overlap on one device --
+ * on different streams or from different contexts -- race on it and must
+ * be ordered by the caller.  No timing is recorded for these calls. */
+#define HK_KDIST_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int hk_kdist_noalloc(hk_ctx* ctx, const void* kappa, int precision, int64_t n_points, const hk_bins* bins,
+                     double* k_out, void* sorted_out);
+
 /* Opacity tables over many thermodynamic states (§2.5: the k-distribution
  * is repeated for every combination of temperature and pressure of the
  * table).  For each states[i] the result equals hk_opacity(states[i], grid,

@@ -18,7 +18,8 @@ __all__ = ["HK_OK", "HK_EINVAL", "HK_ENOMEM", "HK_EDEVICE", "HK_EUNSUPPORTED", "
            "HK_F64", "HK_F32_KAHAN", "HK_MAX_G", "HK_RULE_STEP", "HK_RULE_LINEAR", "HKError", "lib",
            "hk_version", "hk_create",
            "hk_destroy", "hk_set_stream", "hk_sync", "hk_last_error", "hk_load_lines",
-           "hk_opacity", "hk_kdist", "hk_gauss_legendre", "hk_stats", "hk_set_timing",
+           "hk_opacity", "hk_kdist", "hk_kdist_noalloc", "HK_KDIST_NOALLOC_SCRATCH_BYTES",
+           "hk_gauss_legendre", "hk_stats", "hk_set_timing",
            "hk_get_timing", "hk_set_option", "hk_get_option", "hk_tables", "HK_F32_SURROGATE",
            "HK_SURR_N_PARAMS", "HK_SURR_CELLS_X", "HK_SURR_CELLS_Y", "hk_train_cfg",
            "hk_surrogate_labels", "hk_surrogate_set_params", "hk_surrogate_get_params",
@@ -39,6 +40,7 @@ HK_MAX_G = 64
 HK_RULE_STEP, HK_RULE_LINEAR = 0, 1
 HK_MAX_POINTS = 1 << 30
 HK_MAX_CHUNKS = 65536
+HK_KDIST_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _pd = C.POINTER(C.c_double)
 
@@ -120,6 +122,8 @@ def lib():
         L.hk_read_par.restype = i32
         L.hk_kdist.argtypes = [vp, vp, i32, i64, C.POINTER(hk_bins), vp, vp]
         L.hk_kdist.restype = i32
+        L.hk_kdist_noalloc.argtypes = [vp, vp, i32, i64, C.POINTER(hk_bins), vp, vp]
+        L.hk_kdist_noalloc.restype = i32
         L.hk_gauss_legendre.argtypes = [C.c_int32, _pd, _pd]; L.hk_gauss_legendre.restype = i32
         L.hk_stats.argtypes = [vp, C.POINTER(hk_run_stats)]; L.hk_stats.restype = i32
         L.hk_set_timing.argtypes = [vp, i32]; L.hk_set_timing.restype = i32
@@ -293,6 +297,16 @@ def hk_kdist(ctx, kappa, precision: int, n_points: int, points_per_bin: int, g, 
     b = hk_bins(int(points_per_bin), len(gg), gg.ctypes.data_as(_pd), int(rule))
     _check(lib().hk_kdist(ctx, _ptr(kappa), int(precision), int(n_points), C.byref(b),
                           _ptr(k_out), _ptr(sorted_out)), ctx)
+
+
+def hk_kdist_noalloc(ctx, kappa, precision: int, n_points: int, points_per_bin: int, g, k_out,
+                     sorted_out=None, rule: int = 0):
+    """hk_kdist that allocates nothing (a fixed device array serves large
+    bins; see hk.h)."""
+    gg = _f64(g)
+    b = hk_bins(int(points_per_bin), len(gg), gg.ctypes.data_as(_pd), int(rule))
+    _check(lib().hk_kdist_noalloc(ctx, _ptr(kappa), int(precision), int(n_points), C.byref(b),
+                                  _ptr(k_out), _ptr(sorted_out)), ctx)
 
 
 def hk_tables(ctx, states, grid: dict, points_per_bin: int, g, precision: int, k_out,

@@ -69,6 +69,7 @@ struct hk_ctx {
     hipStream_t stream = nullptr;  // where work is enqueued (may be the null stream)
     int64_t lds_bytes = kSortLdsBytes;  // LDS a sort workgroup may use
     int64_t lds_max = 65536;            // the device's LDS per workgroup (the radix sorts)
+    void* noalloc_scratch = nullptr;    // this device's hk_kdist_noalloc array
     std::string err;
     // line list, ascending (nu, index)
     int64_t n_lines = 0;
@@ -830,6 +831,15 @@ int hk_create(int device, hk_ctx** out)
         return rc;
     }
     ctx->stream = ctx->own;
+    // the no-allocation sort array of this device: its address, taken once
+    // per context with the device current
+    e = noalloc_scratch_address(&ctx->noalloc_scratch);
+    if (e != hipSuccess) {
+        int rc = hip_fail(nullptr, e, "hk_create: address of the fixed sort scratch");
+        (void)hipStreamDestroy(ctx->own);
+        delete ctx;
+        return rc;
+    }
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0) {
         ctx->lds_bytes = std::min<int64_t>(lds, kSortLdsBytes);
@@ -1423,6 +1433,33 @@ int hk_kdist(hk_ctx* ctx, const void* kappa, int precision, int64_t n_points, co
                              ctx->kscratch.p, ctx->lds_bytes, ctx->lds_max, 1, ctx->stream),
            "kdist");
     tm.stop();
+    return HK_OK;
+}
+
+static_assert((size_t)HK_KDIST_NOALLOC_SCRATCH_BYTES == kNoAllocScratchBytes, "no-allocation scratch size");
+
+int hk_kdist_noalloc(hk_ctx* ctx, const void* kappa, int precision, int64_t n_points, const hk_bins* bins,
+                     double* k_out, void* sorted_out)
+{
+    GValues gv;
+    if (int rc = check_bins(ctx, bins, &gv)) return rc;
+    if (precision != HK_F64 && precision != HK_F32_KAHAN)
+        return fail(ctx, HK_EINVAL, "unknown precision %d", precision);
+    if (n_points < 0 || n_points > HK_MAX_POINTS) return fail(ctx, HK_EINVAL, "n_points out of range");
+    if (n_points > 0 && (!kappa || !k_out)) return fail(ctx, HK_EINVAL, "kappa and k_out must not be NULL");
+    if (int rc = check_ctx(ctx)) return rc;
+    const int eb = precision == HK_F64 ? 8 : 4;
+    const size_t sb = kdist_scratch_bytes(eb, n_points, bins->points_per_bin, ctx->lds_bytes, ctx->lds_max);
+    if (sb > kNoAllocScratchBytes)
+        return fail(ctx, HK_EINVAL,
+                    "hk_kdist_noalloc: bins of %lld points above one LDS sort need %zu bytes of scratch, more than "
+                    "its fixed %zu (n_points * key bytes * 2)",
+                    (long long)bins->points_per_bin, sb, kNoAllocScratchBytes);
+    if (!ctx->noalloc_scratch) return fail(ctx, HK_EDEVICE, "no fixed sort scratch on this device");
+    HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    HK_HIP(ctx, launch_kdist(kappa, eb, n_points, bins->points_per_bin, gv, k_out, sorted_out, ctx->noalloc_scratch,
+                             ctx->lds_bytes, ctx->lds_max, 1, ctx->stream),
+           "kdist");
     return HK_OK;
 }
 

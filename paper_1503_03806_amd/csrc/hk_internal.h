@@ -355,6 +355,10 @@ hipError_t launch_kdist(const void* kappa, int elem_bytes, int64_t n_points, int
                         const GValues& g, double* k_out, void* sorted_out, void* scratch,
                         int64_t lds_bytes, int64_t lds_max, int32_t n_states, hipStream_t s);
 size_t kdist_scratch_bytes(int elem_bytes, int64_t n_points, int64_t ppb, int64_t lds_bytes, int64_t lds_max);
+// The fixed device array of hk_kdist_noalloc (HK_KDIST_NOALLOC_SCRATCH_BYTES),
+// its address on the current device (call with that device current).
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+hipError_t noalloc_scratch_address(void** ptr);
 
 // Learned K(x, y) surrogate (surrogate.hip): sizes, labels, the compute
 // copy of the parameters, one training step and its Adam update, a plain

@@ -407,4 +407,16 @@ hipError_t launch_kdist(const void* kappa, int elem_bytes, int64_t n_points, int
                                lds_bytes, rk, n_states, s);
 }
 
+// The fixed sort scratch of hk_kdist_noalloc: one array per device, made
+// when the code object is loaded and held until the process ends.  Host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device (the array's name is a host-side stand-in).
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch_address(void** ptr)
+{
+    *ptr = nullptr;
+    return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+}
+
 }  // namespace hk
