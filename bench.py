@@ -40,7 +40,7 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X binary64 vector peak
 FLOPS_PER_EVAL = {"gh1": 8, "gh3": 19, "core": 277}
 DOMINANT_KERNEL = "wing_f64_kernel"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
-# LDS read rate assumed for the sort: 32 banks x 4 B per clock per CU, 256 CUs,
+# LDS rate assumed for the sort: 32 banks x 4 B per clock per CU, 256 CUs,
 # 2.4 GHz
 PEAK_LDS_GBS = 256 * 128 * 2.4
 # surrogate training recipe: (Adam steps, learning rate) phases, batch 4096
@@ -173,26 +173,23 @@ def bench_resample(hk, torch, ctx, kappa, N, ppb, g):
             "ms_sort_fit_transmission": 1e3 * dt, "ms_fit": 1e3 * t_fit, "ms_transmission": 1e3 * t_tr}
 
 
-def kdist_stage(ms, N, ppb, n_g, key_bytes=8, sort_lds_bytes=32768):
+def kdist_stage(ms, N, ppb, n_g, key_bytes=8, radix_max_keys=16384):
     """The Sort + k(g) stage against HBM and LDS: its algorithmic bytes (each
-    opacity read once, k(g) written once) and the keys the bitonic networks
-    read in LDS (each of log2(n)(log2(n)+1)/2 stages reads every padded key
-    once; bins above the 32 KB a sort workgroup uses are sorted in chunks of
-    that size, then merged through global memory, one pass per doubling)."""
+    opacity read once, k(g) written once) and the LDS traffic of the
+    per-bin radix sort (bins of up to 16384 keys, one workgroup each): every
+    pass (8 bits of the key) writes each key to its place and reads it back,
+    in 32-bit words."""
     n_bins = -(-N // ppb)
     hbm = key_bytes * N + 8 * n_bins * n_g
     out = {"ms": ms, "hbm_bytes": hbm, "GB_s": hbm / (ms * 1e-3) / 1e9,
            "frac_of_hbm_peak": hbm / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
-    cap = sort_lds_bytes // key_bytes
-    chunk = min(1 << (ppb - 1).bit_length(), cap)
-    per_bin = -(-ppb // chunk)
-    lg = chunk.bit_length() - 1
-    lds = n_bins * per_bin * (lg * (lg + 1) // 2) * chunk * key_bytes
-    merges = max(0, (per_bin - 1).bit_length())
-    out.update({"bound": "lds", "sort_chunk_keys": chunk, "chunks_per_bin": per_bin, "merge_passes": merges,
-                "merge_bytes": merges * 2 * key_bytes * N, "lds_read_bytes": lds,
-                "lds_read_GB_s": lds / (ms * 1e-3) / 1e9,
-                "frac_of_lds_read_peak": lds / (ms * 1e-3) / 1e9 / PEAK_LDS_GBS})
+    if ppb <= radix_max_keys:
+        passes = 8 * key_bytes // 8
+        lds = passes * 2 * key_bytes * N
+        out.update({"sort": "LDS radix, one workgroup per bin", "passes": passes,
+                    "lds_bytes": lds, "lds_GB_s": lds / (ms * 1e-3) / 1e9,
+                    "frac_of_lds_peak": lds / (ms * 1e-3) / 1e9 / PEAK_LDS_GBS,
+                    "bound": "latency of the ranking and the workgroup barriers (32 per bin)"})
     return out
 
 

@@ -408,8 +408,9 @@ int hk_surrogate_train(hk_ctx* ctx, const float* x, const float* y, const float*
 int hk_surrogate_eval(hk_ctx* ctx, const float* x, const float* y, int64_t n, float* z, float* K);
 /* Certification: for each cell (ix, iy) -- x in [ix, ix+1) * 0.125,
  * log10 y in -4 + [iy, iy+1) * 0.125 -- the largest relative error of K_hat
- * against the binary64 series over the cell's 8x8 lattice of points (edges
+ * against the binary64 series over the cell's 16x16 lattice of points (edges
  * included); cells with error <= budget are certified for HK_F32_SURROGATE.
+ * A dense-sampling check, not a proven bound between lattice points.
  * err: [host] double[HK_SURR_CELLS_Y][HK_SURR_CELLS_X] or NULL;
  * n_certified: [host] or NULL.  Synchronises. */
 int hk_surrogate_certify(hk_ctx* ctx, double budget, double* err, int32_t* n_certified);
@@ -449,6 +450,11 @@ int hk_gauss_legendre(int32_t n, double* g, double* w);
  *   "tables_autotune"      1 (default): hk_tables times the tile shapes;
  *                          0: it uses the *_points_per_lane setting and the
  *                          cached choices are dropped.
+ *   "wing_edge_paths"      1 (default): the Gauss-Hermite kernels take a
+ *                          wavefront's run that a line's window covers only
+ *                          in part on that rule's own path with a window
+ *                          mask; 0: on the general path (a check: both give
+ *                          the same bits).
  * Unknown names or values: HK_EINVAL. */
 int hk_set_option(hk_ctx* ctx, const char* name, int64_t value);
 /* Reads a knob into *value; also, read-only: "tables_points_per_lane", the

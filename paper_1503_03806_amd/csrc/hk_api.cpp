@@ -105,6 +105,7 @@ struct hk_ctx {
     bool have_run = false;
     int f64_points_per_lane = 4;  // tile shape of the binary64 opacity kernel (4 or 8)
     int f32_points_per_lane = 2;  // tile shape of the binary32 opacity kernel
+    int wing_edge_paths = 1;      // 0: window-edge runs take the general path (same bits)
     // batched tables: per-state records, ranges and sums of one batch, the
     // per-state evaluation counters of the last call, and the tile shapes
     // chosen by timing, per (precision, lines, points, cutoff/dnu)
@@ -629,12 +630,12 @@ int wing_stage(hk_ctx* ctx, int precision, int ppl, const void* recs, const Wing
     if (f64)
         HK_HIP(ctx, launch_wing_f64(ppl, static_cast<const WingRec*>(recs), idx, ranges, n, n_tiles, n_states, wp,
                                     grid->nu_min, grid->dnu, np, static_cast<double*>(out),
-                                    static_cast<double*>(ctx->wplan.partial.p), accumulate, ctx->stream),
+                                    static_cast<double*>(ctx->wplan.partial.p), accumulate, ctx->wing_edge_paths, ctx->stream),
                "wing_f64");
     else
         HK_HIP(ctx, launch_wing_f32(ppl, static_cast<const WingRec32*>(recs), idx, ranges, n, n_tiles, n_states, wp,
                                     np, static_cast<float*>(out), comp,
-                                    static_cast<float2*>(ctx->wplan.partial.p), ctx->stream),
+                                    static_cast<float2*>(ctx->wplan.partial.p), ctx->wing_edge_paths, ctx->stream),
                "wing_f32");
     return HK_OK;
 }
@@ -1166,7 +1167,7 @@ static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, double reach, double re
     {
         StageTimer tm(ctx, HK_STAGE_OPACITY);
         HK_HIP(ctx, launch_wing_f32(ppl, w32, widx, ranges, n, n_tiles, 1, wwp, np, fs, fc,
-                                    static_cast<float2*>(ctx->wplan.partial.p), ctx->stream),
+                                    static_cast<float2*>(ctx->wplan.partial.p), ctx->wing_edge_paths, ctx->stream),
                "wing_f32");
         tm.stop();
     }
@@ -1269,7 +1270,7 @@ static int opacity_run(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int
     {
         StageTimer tm(ctx, HK_STAGE_OPACITY);
         HK_HIP(ctx, launch_wing_f64(ppl, wing, widx, ranges, n, n_tiles, 1, wwp, grid->nu_min, grid->dnu, np, kappa,
-                                    static_cast<double*>(ctx->wplan.partial.p), accumulate ? 1 : 0, ctx->stream),
+                                    static_cast<double*>(ctx->wplan.partial.p), accumulate ? 1 : 0, ctx->wing_edge_paths, ctx->stream),
                "wing_f64");
         tm.stop();
     }
@@ -1680,13 +1681,13 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
             if (f64)
                 HK_HIP(ctx, launch_wing_f64(ppl, static_cast<WingRec*>(ctx->tb_wing.p), tidx, rw, n, n_tiles, nbat, wwp,
                                             grid->nu_min, grid->dnu, np, static_cast<double*>(ctx->tb_out.p),
-                                            static_cast<double*>(ctx->wplan.partial.p), 0, ctx->stream),
+                                            static_cast<double*>(ctx->wplan.partial.p), 0, ctx->wing_edge_paths, ctx->stream),
                        "wing_f64");
             else
                 HK_HIP(ctx, launch_wing_f32(ppl, static_cast<WingRec32*>(ctx->tb_w32.p), tidx, rw, n, n_tiles, nbat,
                                             wwp, np, static_cast<float*>(ctx->tb_out.p),
                                             static_cast<float*>(ctx->tb_comp.p),
-                                            static_cast<float2*>(ctx->wplan.partial.p), ctx->stream),
+                                            static_cast<float2*>(ctx->wplan.partial.p), ctx->wing_edge_paths, ctx->stream),
                        "wing_f32");
             tm.stop();
         }
@@ -2145,6 +2146,12 @@ int hk_set_option(hk_ctx* ctx, const char* name, int64_t value)
         ctx->tables_mem = value << 20;
         return HK_OK;
     }
+    if (std::strcmp(name, "wing_edge_paths") == 0) {
+        if (value != 0 && value != 1) return fail(ctx, HK_EINVAL, "wing_edge_paths must be 0 or 1");
+        if (int rc = check_ctx(ctx)) return rc;
+        ctx->wing_edge_paths = (int)value;
+        return HK_OK;
+    }
     if (std::strcmp(name, "tables_autotune") == 0) {
         if (value != 0 && value != 1) return fail(ctx, HK_EINVAL, "tables_autotune must be 0 or 1");
         if (int rc = check_ctx(ctx)) return rc;
@@ -2164,6 +2171,7 @@ int hk_get_option(hk_ctx* ctx, const char* name, int64_t* value)
     else if (std::strcmp(name, "tables_batch") == 0) *value = ctx->tables_batch;
     else if (std::strcmp(name, "tables_mem_mib") == 0) *value = ctx->tables_mem >> 20;
     else if (std::strcmp(name, "tables_autotune") == 0) *value = ctx->tables_autotune;
+    else if (std::strcmp(name, "wing_edge_paths") == 0) *value = ctx->wing_edge_paths;
     else if (std::strcmp(name, "tables_points_per_lane") == 0) *value = ctx->tables_ppl_used;
     else if (std::strcmp(name, "wing_items") == 0 || std::strcmp(name, "wing_segment_lines") == 0) {
         // the last wing stage's plan (for its first state), read back

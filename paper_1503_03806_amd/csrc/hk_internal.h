@@ -276,7 +276,7 @@ int32_t core_f32_tile_points();  // points per work item of the binary32 series
 hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingIdx* idx, const int64_t* ranges,
                            int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, double nu_min,
                            double dnu, int32_t n_points, double* kappa, double* partial, int accumulate,
-                           hipStream_t s);
+                           int edge_paths, hipStream_t s);
 // The series items of n_states states (tiles of core_f64_tile_points(),
 // their own plan): series = the series sums, every point written (a grid of
 // its own, n_points per state, added to the wing's afterwards, so that the
@@ -309,7 +309,7 @@ int32_t opacity_f32_tile_points(int points_per_lane);
 // items write (sum, comp) pairs to partial (tile_points float2 per slot).
 hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const WingIdx* idx, const int64_t* ranges,
                            int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int32_t n_points,
-                           float* sum, float* comp, float2* partial, hipStream_t s);
+                           float* sum, float* comp, float2* partial, int edge_paths, hipStream_t s);
 // The series items (tiles of opacity_f32_tile_points(4)): series = the
 // binary32 series sums, every point written (added to the wing's Kahan pairs
 // by launch_f32_finish); surrogate (the bfloat16 parameter copy, single

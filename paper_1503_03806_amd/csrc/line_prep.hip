@@ -11,6 +11,50 @@
 namespace hk {
 namespace {
 
+// e^{-k^2/4}, k = 1 .. 40: the weights of the series' line constant T1
+__constant__ double kGauss40[40] = {
+    0.77880078307140488,
+    0.36787944117144233,
+    0.10539922456186433,
+    0.018315638888734179,
+    0.0019304541362277093,
+    0.00012340980408667956,
+    4.7851173921290088e-06,
+    1.1253517471925912e-07,
+    1.6052280551856116e-09,
+    1.3887943864964021e-11,
+    7.2877240958196922e-14,
+    2.3195228302435696e-16,
+    4.4777324417183015e-19,
+    5.2428856633634639e-22,
+    3.7233631217505106e-25,
+    1.6038108905486379e-28,
+    4.1900931944943974e-32,
+    6.6396771995807348e-36,
+    6.3815034480607908e-40,
+    3.7200759760208361e-44,
+    1.3153258948574645e-48,
+    2.8207700884601352e-53,
+    3.6690596154291634e-58,
+    2.8946403116483003e-63,
+    1.3851193699226017e-68,
+    4.0200602157433552e-74,
+    7.0766981754295491e-80,
+    7.5558190197119609e-86,
+    4.8931122620973616e-92,
+    1.9219477278238491e-98,
+    4.5787899692915775e-105,
+    6.6162610567094853e-112,
+    5.7986554185640377e-119,
+    3.0824406969490981e-126,
+    9.9383644134836838e-134,
+    1.9435148500492928e-141,
+    2.3052263152355648e-149,
+    1.6584104776811452e-157,
+    7.2364115192480096e-166,
+    1.9151695967140057e-174,
+};
+
 // a^2 + u^2 at grid point j for a line (u = (nu_j - nu0) / alpha, a = y).
 __device__ inline double r2_at(int64_t j, double nu_min, double dnu, double nu0, double invA,
                                double y2)
@@ -131,7 +175,7 @@ __device__ __forceinline__ void line_prep_one(const LinesDev& L, const PrepParam
         double t1 = 0.0;
         for (int k = 1; k <= 40; ++k) {
             double hk2 = 0.25 * (double)(k * k);
-            t1 += exp(-hk2) / (hk2 + y2);
+            t1 += kGauss40[k - 1] / (hk2 + y2);
         }
         c.T1 = t1;
     } else {

@@ -38,14 +38,16 @@ enum : uint32_t { kSkip = 0, kGH1 = 1, kGH3 = 2, kGeneral = 3, kGH1Edge = 4, kGH
 // is the run's nominal last point.  A run cut short by the grid end takes
 // the general path, which leaves 3-node points whose pair partner lies
 // beyond the grid unpaired (so a point's bits do not depend on the tile
-// shape).
-__device__ inline uint32_t classify(const WingIdx& r, int32_t run0, int32_t run1, int32_t run_end)
+// shape).  edges == false sends runs the window covers in part down the
+// general path too (a check of the window-edge paths, which give the same
+// bits).
+__device__ inline uint32_t classify(const WingIdx& r, int32_t run0, int32_t run1, int32_t run_end, bool edges)
 {
     if (run0 > run1 || r.whi < run0 || r.wlo > run1) return kSkip;
     if (run1 < run_end) return kGeneral;
     const bool full = r.wlo <= run0 && r.whi >= run1;
     const bool nocore = run1 < r.clo || run0 > r.chi;
-    if (!nocore) return kGeneral;
+    if (!nocore || (!full && !edges)) return kGeneral;
     if (run1 < r.g3lo || run0 > r.g3hi) return full ? kGH1 : kGH1Edge;
     if (r.g3lo <= run0 && r.g3hi >= run1) return full ? kGH3 : kGH3Edge;
     return kGeneral;
@@ -71,7 +73,7 @@ template <int kP>
 __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1, const WingRec32* __restrict__ wing,
                                               const WingIdx* __restrict__ idx, int32_t n, float* __restrict__ sum_out,
                                               float* __restrict__ comp_out, float2* __restrict__ partial,
-                                              int64_t obase, bool direct)
+                                              int64_t obase, bool direct, bool edges)
 {
     static_assert(kP % 2 == 0, "3-node points pair up within a lane");
     constexpr int kTilePoints = 64 * kP * kWaves;
@@ -105,7 +107,7 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
             for (int w = 0; w < kWaves; ++w) {
                 const int32_t r0 = tile0 + w * 64 * kP;
                 const int32_t r1 = min(r0 + 64 * kP, n) - 1;
-                cw |= classify(r, r0, r1, r0 + 64 * kP - 1) << (8 * w);
+                cw |= classify(r, r0, r1, r0 + 64 * kP - 1, edges) << (8 * w);
             }
             code[threadIdx.x] = cw;
         }
@@ -265,7 +267,7 @@ template <int kP>
 __global__ __launch_bounds__(64 * kWaves) void wing_f32_kernel(
     const WingRec32* __restrict__ wing, const WingIdx* __restrict__ idx, const int64_t* __restrict__ ranges,
     int64_t n_lines, int64_t n_tiles, int32_t n_states, WorkPlan wp, int32_t n, float* __restrict__ sum,
-    float* __restrict__ comp, float2* __restrict__ partial)
+    float* __restrict__ comp, float2* __restrict__ partial, int edges)
 {
     constexpr int64_t kTilePoints = 64 * kP * kWaves;
     WorkItem it;
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(64 * kWaves) void wing_f32_kernel(
         const int64_t o = it.st * n_lines, so = it.st * (int64_t)n;
         const bool direct = it.slot < 0;
         wing_f32_tile<kP>(it.tile, it.lo, it.hi, wing + o, idx + o, n, sum + so, comp + so,
-                          partial + (direct ? 0 : it.slot * kTilePoints), it.tile * kTilePoints, direct);
+                          partial + (direct ? 0 : it.slot * kTilePoints), it.tile * kTilePoints, direct, edges != 0);
     }
 }
 
@@ -359,12 +361,9 @@ __device__ float voigt_core_f32(float x, float y, float ex, float T1, const floa
 // point's value to the run's sums in LDS, pieces in line order); the run's
 // ordered binary32 series sums go to a grid of their own, which the finish
 // adds to the wing's Kahan pairs (so the two kernels can run at the same
-// time).  With kSurr, points of certified (x, y) cells take the learned
-// surrogate instead of the series (the wavefront runs the network when any
-// of its lanes needs it, the series when any needs that), and the count of
-// such points is returned.  Lines [L0, L1) of tile t; direct: series_j = the
-// run's sum (every point, 0 where no line reaches); else every point's sum
-// to partial[j - obase].
+// time).  Lines [L0, L1) of tile t; direct: series_j = the run's sum (every
+// point, 0 where no line reaches); else every point's sum to
+// partial[j - obase].
 constexpr int kCoreRun = 256;
 constexpr int kCoreTilePoints = kCoreRun * kWaves;
 constexpr int kCoreBatch = 32;
@@ -387,28 +386,23 @@ __device__ inline int32_t wave_incl_scan(int32_t v, int lane)
     return v;
 }
 
-template <bool kSurr = false>
-__device__ __forceinline__ int64_t core_f32_tile(int64_t t, int64_t L0, int64_t L1, const WingIdx* __restrict__ idx,
-                                                 const CoreRec32* __restrict__ core, int32_t n,
-                                                 float* __restrict__ series, float* __restrict__ partial,
-                                                 int64_t obase, bool direct, const surr::MlpBf16* __restrict__ P,
-                                                 const uint8_t* __restrict__ mask)
+__device__ __forceinline__ void core_f32_tile(int64_t t, int64_t L0, int64_t L1, const WingIdx* __restrict__ idx,
+                                              const CoreRec32* __restrict__ core, int32_t n, float* __restrict__ series,
+                                              float* __restrict__ partial, int64_t obase, bool direct)
 {
     __shared__ float acc_tab[kWaves][kCoreRun];
     __shared__ CorePiece32 piece_tab[kWaves][kCoreBatch];
     __shared__ float w_tab[kWaves][kChunkPieces * kMaxTerms];
-    __shared__ __align__(16) uint16_t act_tab[kSurr ? kWaves : 1][kSurr ? 64 * surr::kLd : 1];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int32_t run0 = (int32_t)(t * kCoreTilePoints) + wave * kCoreRun;
     const int32_t run1 = min(run0 + kCoreRun, n) - 1;
-    if (run0 > run1) return 0;
+    if (run0 > run1) return;
     float* acc = acc_tab[wave];
     CorePiece32* pc = piece_tab[wave];
     float* wt = w_tab[wave];
     for (int q = lane; q < kCoreRun; q += 64) acc[q] = 0.0f;
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    int64_t n_used = 0;  // points of this wavefront the network evaluated
 
     for (int64_t base = L0; base < L1; base += kCoreBatch) {
         const int64_t i = base + lane;
@@ -466,27 +460,177 @@ __device__ __forceinline__ int64_t core_f32_tile(int64_t t, int64_t L0, int64_t 
             const float x = act ? fabsf(fmaf((float)(j - pp.jc), pp.dx, -pp.fx)) : 0.0f;
             const float* w = wt + (my - s_lo) * kMaxTerms;
             float v = 0.0f;
-            if constexpr (kSurr) {
-                const bool use = act && surr::certified(mask, x, pp.y);
-                if (__ballot(act && !use)) {
-                    if (act && !use) v = pp.norm * voigt_core_f32(x, pp.y, pp.ex, pp.T1, w);
-                }
-                const uint64_t used = __ballot(use);
-                n_used += __builtin_popcountll(used);
-                if (used) {
-                    const float z = surr::mlp_forward<false>(P, act_tab[wave], surr::feature_x(x),
-                                                             surr::feature_y(use ? pp.y : 1.0f));
-                    if (use) v = pp.norm * surr::surrogate_K(x, pp.y, z);
-                }
-            } else if (act) {
-                v = pp.norm * voigt_core_f32(x, pp.y, pp.ex, pp.T1, w);
-            }
+            if (act) v = pp.norm * voigt_core_f32(x, pp.y, pp.ex, pp.T1, w);
             // add in line order (see core_f64_tile)
             volatile float* vacc = acc;
             for (int s = s_lo; s < s_end; ++s)
                 if (act && my == s) vacc[jr] = vacc[jr] + v;
             s_lo = (s_end < np && f_end >= next_start) ? s_end : s_end - 1;
             f0 = f_end;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int q = lane; q < kCoreRun; q += 64) {
+        const int32_t jj = run0 + q;
+        if (jj <= run1) {
+            if (direct)
+                series[jj] = acc[q];
+            else
+                partial[jj - obase] = acc[q];
+        }
+    }
+}
+
+// The series-region terms with the learned surrogate (HK_F32_SURROGATE): the
+// pieces of a wavefront's run are flattened as in core_f32_tile, and every
+// window of kSurrWin flattened points is taken in four passes, so that the
+// network and the series each run on full 64-lane batches and never both for
+// one batch: (A) each point's cell is looked up and the point's index goes to
+// the list of certified points or to that of the others (order kept);
+// (B) the series for the others, 64 at a time; (C) the network for the
+// certified ones, 64 at a time, its bfloat16 weights staged in LDS once per
+// workgroup; (D) the values, kept per point in LDS, are added to the run's
+// sums in line order as in core_f32_tile.  Returns the points the network
+// evaluated.  (The values are those core_f32_tile<true> computes: the same
+// per-point arithmetic, only grouped differently.)
+constexpr int kSurrWin = 256;
+
+__device__ __forceinline__ int64_t core_f32_surr_tile(int64_t t, int64_t L0, int64_t L1,
+                                                      const WingIdx* __restrict__ idx,
+                                                      const CoreRec32* __restrict__ core, int32_t n,
+                                                      float* __restrict__ series, float* __restrict__ partial,
+                                                      int64_t obase, bool direct, const surr::MlpBf16* P,
+                                                      const uint8_t* __restrict__ mask)
+{
+    __shared__ __align__(16) uint16_t mlp_tab[kWaves][64 * surr::kLd];
+    __shared__ float acc_tab[kWaves][kCoreRun];
+    __shared__ CorePiece32 piece_tab[kWaves][kCoreBatch];
+    __shared__ float w_tab[kWaves][kCoreBatch * kMaxTerms];
+    __shared__ float val_tab[kWaves][kSurrWin];
+    __shared__ uint8_t own_tab[kWaves][kSurrWin];
+    __shared__ uint16_t list_tab[kWaves][2][kSurrWin];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int32_t run0 = (int32_t)(t * kCoreTilePoints) + wave * kCoreRun;
+    const int32_t run1 = min(run0 + kCoreRun, n) - 1;
+    if (run0 > run1) return 0;
+    float* acc = acc_tab[wave];
+    CorePiece32* pc = piece_tab[wave];
+    float* wt = w_tab[wave];
+    float* val = val_tab[wave];
+    uint8_t* own = own_tab[wave];
+    uint16_t* cert = list_tab[wave][0];
+    uint16_t* plain = list_tab[wave][1];
+    for (int q = lane; q < kCoreRun; q += 64) acc[q] = 0.0f;
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    int64_t n_used = 0;
+
+    for (int64_t base = L0; base < L1; base += kCoreBatch) {
+        const int64_t i = base + lane;
+        int32_t a = 1, b = 0, jc = 0;
+        if (lane < kCoreBatch && i < L1) {
+            const WingIdx r = idx[i];
+            a = max(max(r.clo, r.wlo), run0);
+            b = min(min(r.chi, r.whi), run1);
+            jc = r.jc;
+        }
+        const bool has = a <= b;
+        const uint64_t m = __ballot(has);
+        if (m == 0) continue;
+        const int np = __builtin_popcountll(m);
+        const int32_t cnt = has ? b - a + 1 : 0;
+        const int32_t incl = wave_incl_scan(cnt, lane);
+        const int32_t total = __shfl(incl, 63, 64);
+        if (has) {
+            const CoreRec32 cr = core[i];
+            CorePiece32 pp;
+            pp.dx = cr.dx;
+            pp.fx = cr.fx;
+            pp.y = cr.y;
+            pp.y2 = cr.y2;
+            pp.ex = cr.ex;
+            pp.norm = cr.norm;
+            pp.T1 = cr.T1;
+            pp.jc = jc;
+            pp.a = a;
+            pp.start = incl - cnt;
+            pc[__builtin_popcountll(m & below)] = pp;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // the series tables of every piece of the batch
+        for (int e = lane; e < np * kMaxTerms; e += 64) {
+            const int k = e / kMaxTerms, nn = e - k * kMaxTerms;
+            const float mm = 0.5f * (float)(nn + 1);
+            wt[e] = 1.0f / fmaf(mm, mm, pc[k].y2);
+        }
+        const int32_t st_k = lane < np ? pc[lane].start : total;
+        __builtin_amdgcn_wave_barrier();
+        int s_lo = 0;  // the piece holding point f0
+        for (int32_t f0 = 0; f0 < total; f0 += kSurrWin) {
+            const int32_t f1 = min(total, f0 + kSurrWin);
+            // (A) each point's piece and cell; the two lists
+            int n_cert = 0, n_plain = 0;
+            int s_at = s_lo;
+            for (int32_t c0 = f0; c0 < f1; c0 += 64) {
+                const int32_t f = c0 + lane;
+                const bool act = f < f1;
+                while (s_at + 1 < np && __shfl(st_k, s_at + 1, 64) <= c0) ++s_at;
+                int my = s_at;
+                for (int s = s_at + 1; s < np && __shfl(st_k, s, 64) < c0 + 64; ++s)
+                    my = __shfl(st_k, s, 64) <= f ? s : my;
+                const CorePiece32& pp = pc[my];
+                const int32_t j = pp.a + (f - pp.start);
+                const float x = act ? fabsf(fmaf((float)(j - pp.jc), pp.dx, -pp.fx)) : 0.0f;
+                const bool use = act && surr::certified(mask, x, pp.y);
+                const uint64_t um = __ballot(use), pm = __ballot(act && !use);
+                if (act) own[f - f0] = (uint8_t)my;
+                if (use) cert[n_cert + __builtin_popcountll(um & below)] = (uint16_t)(f - f0);
+                if (act && !use) plain[n_plain + __builtin_popcountll(pm & below)] = (uint16_t)(f - f0);
+                n_cert += __builtin_popcountll(um);
+                n_plain += __builtin_popcountll(pm);
+            }
+            n_used += n_cert;
+            __builtin_amdgcn_wave_barrier();
+            // (B) the series, full batches of the other points
+            for (int c = 0; c < n_plain; c += 64) {
+                if (c + lane < n_plain) {
+                    const int q = plain[c + lane];
+                    const int my = own[q];
+                    const CorePiece32& pp = pc[my];
+                    const int32_t j = pp.a + (f0 + q - pp.start);
+                    const float x = fabsf(fmaf((float)(j - pp.jc), pp.dx, -pp.fx));
+                    val[q] = pp.norm * voigt_core_f32(x, pp.y, pp.ex, pp.T1, wt + my * kMaxTerms);
+                }
+            }
+            // (C) the network, full batches of the certified points
+            for (int c = 0; c < n_cert; c += 64) {
+                const bool act = c + lane < n_cert;
+                const int q = act ? cert[c + lane] : 0;
+                const CorePiece32& pp = pc[own[q]];
+                const int32_t j = pp.a + (f0 + q - pp.start);
+                const float x = act ? fabsf(fmaf((float)(j - pp.jc), pp.dx, -pp.fx)) : 0.0f;
+                const float z = surr::mlp_forward<false>(P, mlp_tab[wave], surr::feature_x(x),
+                                                         surr::feature_y(act ? pp.y : 1.0f));
+                if (act) val[q] = pp.norm * surr::surrogate_K(x, pp.y, z);
+            }
+            __builtin_amdgcn_wave_barrier();
+            // (D) add in line order (see core_f64_tile)
+            for (int32_t c0 = f0; c0 < f1; c0 += 64) {
+                const int32_t f = c0 + lane;
+                const bool act = f < f1;
+                const int my = act ? own[f - f0] : 0;
+                const int s_first = __shfl(my, 0, 64);
+                const int s_last = __shfl(my, min(f1 - c0, 64) - 1, 64);
+                const CorePiece32& pp = pc[my];
+                const int32_t jr = act ? pp.a + (f - pp.start) - run0 : 0;
+                const float v = act ? val[f - f0] : 0.0f;
+                volatile float* vacc = acc;
+                for (int s = s_first; s <= s_last; ++s)
+                    if (act && my == s) vacc[jr] = vacc[jr] + v;
+            }
+            s_lo = s_at;
+            __builtin_amdgcn_wave_barrier();
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -520,9 +664,13 @@ __global__ __launch_bounds__(64 * kWaves) void core_f32_kernel(
     if (work_item(blockIdx.x, wp, ranges, n_tiles, n_states, it)) {
         const int64_t o = it.st * n_lines, so = it.st * (int64_t)n;
         const bool direct = it.slot < 0;
-        n_used = core_f32_tile<kSurr>(it.tile, it.lo, it.hi, idx + o, core + o, n, series + so,
-                                      partial + (direct ? 0 : it.slot * kCoreTilePoints),
-                                      it.tile * kCoreTilePoints, direct, P, mask);
+        if constexpr (kSurr)
+            n_used = core_f32_surr_tile(it.tile, it.lo, it.hi, idx + o, core + o, n, series + so,
+                                        partial + (direct ? 0 : it.slot * kCoreTilePoints),
+                                        it.tile * kCoreTilePoints, direct, P, mask);
+        else
+            core_f32_tile(it.tile, it.lo, it.hi, idx + o, core + o, n, series + so,
+                          partial + (direct ? 0 : it.slot * kCoreTilePoints), it.tile * kCoreTilePoints, direct);
     }
     if constexpr (kSurr) {
         __shared__ int64_t wave_used[kWaves];
@@ -581,12 +729,12 @@ __global__ __launch_bounds__(256) void sum_counts_kernel(const int64_t* __restri
 template <int kP>
 hipError_t launch_wing(const WingRec32* wing, const WingIdx* idx, const int64_t* ranges, int64_t n_lines,
                        int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int32_t n, float* sum, float* comp,
-                       float2* partial, hipStream_t s)
+                       float2* partial, int edges, hipStream_t s)
 {
     const int64_t nb = plan_blocks(wp.launch_items);
     if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
     wing_f32_kernel<kP><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(wing, idx, ranges, n_lines, n_tiles,
-                                                                        n_states, wp, n, sum, comp, partial);
+                                                                        n_states, wp, n, sum, comp, partial, edges);
     const int64_t nr = std::min<int64_t>(wp.n_pairs, 8192);
     wing_f32_reduce_kernel<<<dim3((unsigned)nr), dim3(256), 0, s>>>(wp, n_tiles, n_states, 64 * kP * kWaves, n,
                                                                     partial, sum, comp);
@@ -600,13 +748,16 @@ int32_t core_f32_tile_points() { return kCoreTilePoints; }
 
 hipError_t launch_wing_f32(int points_per_lane, const WingRec32* wing, const WingIdx* idx, const int64_t* ranges,
                            int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, int32_t n_points,
-                           float* sum, float* comp, float2* partial, hipStream_t s)
+                           float* sum, float* comp, float2* partial, int edges, hipStream_t s)
 {
     if (n_tiles == 0 || n_states == 0) return hipSuccess;
     switch (points_per_lane) {
-    case 2: return launch_wing<2>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, n_points, sum, comp, partial, s);
-    case 4: return launch_wing<4>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, n_points, sum, comp, partial, s);
-    case 8: return launch_wing<8>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, n_points, sum, comp, partial, s);
+    case 2:
+        return launch_wing<2>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, n_points, sum, comp, partial, edges, s);
+    case 4:
+        return launch_wing<4>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, n_points, sum, comp, partial, edges, s);
+    case 8:
+        return launch_wing<8>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, n_points, sum, comp, partial, edges, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -62,14 +62,17 @@ __device__ inline double qrcp(double den)
 // The path of one line for the points [run0, run1] of a wavefront; run_end
 // is the run's nominal last point.  A run cut short by the grid end takes
 // the general path, which evaluates points whose group reaches beyond the
-// grid one by one.
-__device__ inline uint32_t classify(const WingIdx& r, int32_t run0, int32_t run1, int32_t run_end)
+// grid one by one.  A run wholly in one rule's region that the line's window
+// covers only in part takes the rule's own path with a window mask
+// (kGH1Edge, kGH3Edge); edges == false sends such runs down the general path
+// instead (a check: both give the same bits).
+__device__ inline uint32_t classify(const WingIdx& r, int32_t run0, int32_t run1, int32_t run_end, bool edges)
 {
     if (run0 > run1 || r.whi < run0 || r.wlo > run1) return kSkip;
     if (run1 < run_end) return kGeneral;
     const bool full = r.wlo <= run0 && r.whi >= run1;
     const bool nocore = run1 < r.clo || run0 > r.chi;
-    if (!(nocore && (r.flags & kGroupSafe))) return kGeneral;
+    if (!(nocore && (r.flags & kGroupSafe)) || (!full && !edges)) return kGeneral;
     if (run1 < r.g3lo || run0 > r.g3hi) return full ? kGH1 : kGH1Edge;
     if (r.g3lo <= run0 && r.g3hi >= run1) return full ? kGH3 : kGH3Edge;
     return kGeneral;
@@ -101,7 +104,7 @@ __device__ inline void gh3_nm(double dv, double M2, double M1, double M0, double
 template <int kP>
 __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1, const WingRec* __restrict__ wing,
                                               const WingIdx* __restrict__ idx, double nu_min, double dnu, int32_t n,
-                                              double* __restrict__ out, int64_t obase, int accumulate)
+                                              double* __restrict__ out, int64_t obase, int accumulate, bool edges)
 {
     static_assert(kP % 4 == 0, "points are processed in groups of four");
     constexpr int kTilePoints = 64 * kP * kWaves;
@@ -130,7 +133,7 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
             for (int w = 0; w < kWaves; ++w) {
                 const int32_t r0 = tile0 + w * 64 * kP;
                 const int32_t r1 = min(r0 + 64 * kP, n) - 1;
-                code[w][threadIdx.x] = (uint8_t)classify(r, r0, r1, r0 + 64 * kP - 1);
+                code[w][threadIdx.x] = (uint8_t)classify(r, r0, r1, r0 + 64 * kP - 1, edges);
             }
         }
         __syncthreads();
@@ -251,9 +254,10 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
             }
             const double nu0 = tile[k].nu0, Lg = tile[k].Lg, G2 = tile[k].G2;
             const double M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Bn = tile[k].Bn, Cn = tile[k].Cn;
-            // general path: window edges, region edges, core points (left to
-            // the core kernel), the grid end, lines outside the grouping range
-            // (rare: the index record is read from memory, not staged)
+            // general path: window edges (with edges == false), region edges,
+            // core points (left to the core kernel), the grid end, lines
+            // outside the grouping range (rare: the index record is read from
+            // memory, not staged)
             const WingIdx ri = idx[base + k];
             const int32_t wlo = ri.wlo, whi = ri.whi;
             const int32_t g3lo = ri.g3lo, g3hi = ri.g3hi;
@@ -323,7 +327,7 @@ template <int kP>
 __global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
     const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx, const int64_t* __restrict__ ranges,
     int64_t n_lines, int64_t n_tiles, int32_t n_states, WorkPlan wp, double nu_min, double dnu, int32_t n,
-    double* __restrict__ kappa, double* __restrict__ partial, int accumulate)
+    double* __restrict__ kappa, double* __restrict__ partial, int accumulate, int edges)
 {
     constexpr int64_t kTilePoints = 64 * kP * kWaves;
     WorkItem it;
@@ -332,7 +336,7 @@ __global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
         const bool direct = it.slot < 0;
         double* out = direct ? kappa + it.st * (int64_t)n : partial + it.slot * kTilePoints;
         wing_f64_tile<kP>(it.tile, it.lo, it.hi, wing + o, idx + o, nu_min, dnu, n, out,
-                          direct ? 0 : it.tile * kTilePoints, direct ? accumulate : 0);
+                          direct ? 0 : it.tile * kTilePoints, direct ? accumulate : 0, edges != 0);
     }
 }
 
@@ -624,12 +628,12 @@ __global__ __launch_bounds__(256) void core_f64_reduce_kernel(WorkPlan wp, int64
 template <int kP>
 hipError_t launch_wing(const WingRec* wing, const WingIdx* idx, const int64_t* ranges, int64_t n_lines,
                        int64_t n_tiles, int32_t n_states, const WorkPlan& wp, double nu_min, double dnu, int32_t n,
-                       double* kappa, double* partial, int accumulate, hipStream_t s)
+                       double* kappa, double* partial, int accumulate, int edges, hipStream_t s)
 {
     const int64_t nb = plan_blocks(wp.launch_items);
     if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
     wing_f64_kernel<kP><<<dim3((unsigned)nb), dim3(64 * kWaves), 0, s>>>(
-        wing, idx, ranges, n_lines, n_tiles, n_states, wp, nu_min, dnu, n, kappa, partial, accumulate);
+        wing, idx, ranges, n_lines, n_tiles, n_states, wp, nu_min, dnu, n, kappa, partial, accumulate, edges);
     const int64_t nr = std::min<int64_t>(wp.n_pairs, 8192);
     wing_f64_reduce_kernel<<<dim3((unsigned)nr), dim3(256), 0, s>>>(wp, n_tiles, n_states, 64 * kP * kWaves, n,
                                                                     partial, kappa, accumulate);
@@ -645,14 +649,15 @@ int32_t core_f64_tile_points() { return kCoreTilePoints; }
 
 hipError_t launch_wing_f64(int points_per_lane, const WingRec* wing, const WingIdx* idx, const int64_t* ranges,
                            int64_t n_lines, int64_t n_tiles, int32_t n_states, const WorkPlan& wp, double nu_min,
-                           double dnu, int32_t n_points, double* kappa, double* partial, int accumulate, hipStream_t s)
+                           double dnu, int32_t n_points, double* kappa, double* partial, int accumulate, int edges,
+                           hipStream_t s)
 {
     if (n_tiles == 0 || n_states == 0) return hipSuccess;
     switch (points_per_lane) {
     case 4: return launch_wing<4>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, nu_min, dnu, n_points, kappa,
-                                  partial, accumulate, s);
+                                  partial, accumulate, edges, s);
     case 8: return launch_wing<8>(wing, idx, ranges, n_lines, n_tiles, n_states, wp, nu_min, dnu, n_points, kappa,
-                                  partial, accumulate, s);
+                                  partial, accumulate, edges, s);
     default: return hipErrorInvalidValue;
     }
 }

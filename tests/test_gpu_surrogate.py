@@ -188,7 +188,7 @@ def test_certification_matches_oracle(ctx, trained):
     err = trained["err"]
     rng = np.random.default_rng(8)
     cells = rng.choice(err.size, 200, replace=False)
-    lat = np.arange(8) / 7.0
+    lat = np.arange(16) / 15.0  # the certification's 16x16 lattice per cell
     agree = 0
     for c in cells:
         iy, ix = divmod(int(c), hk.HK_SURR_CELLS_X)
