@@ -78,6 +78,19 @@ __device__ inline uint32_t classify(const WingIdx& r, int32_t run0, int32_t run1
     return kGeneral;
 }
 
+// An index interval [lo, hi] relative to a tile's first point t0, each end
+// clipped to [-1, tp] (tp = the tile's points), packed as two int16: for the
+// tile's points 0 .. tp-1 every comparison with an end comes out as with the
+// unclipped interval.
+__device__ inline uint32_t bnd_pack(int32_t lo, int32_t hi, int32_t t0, int32_t tp)
+{
+    const int64_t l = min<int64_t>(max<int64_t>((int64_t)lo - t0, -1), tp);
+    const int64_t h = min<int64_t>(max<int64_t>((int64_t)hi - t0, -1), tp);
+    return ((uint32_t)l & 0xffffu) | ((uint32_t)h << 16);
+}
+__device__ inline int32_t bnd_lo(uint32_t w) { return (int32_t)(int16_t)(w & 0xffffu); }
+__device__ inline int32_t bnd_hi(uint32_t w) { return (int32_t)w >> 16; }
+
 // 3-node rule of one point: S Phi = Lg n / m with q = dv^2,
 // n = q (q + Bn) + Cn, m = (q + G2)(q (q + B) + C) = ((q + M2) q + M1) q + M0.
 __device__ inline void gh3_nm(double dv, double M2, double M1, double M0, double Bn, double Cn,
@@ -110,10 +123,14 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
     constexpr int kTilePoints = 64 * kP * kWaves;
     __shared__ WingRec tile[kTL];
     __shared__ uint8_t code[kWaves][kTL];  // path of each staged line, per wavefront
+    // each staged line's window, 3-node and series intervals and flags,
+    // relative to the tile (bnd_pack), for the window-edge and general paths
+    __shared__ uint4 bnd[kTL];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int32_t tile0 = (int32_t)(t * kTilePoints);
     const int32_t run0 = tile0 + wave * 64 * kP;
+    const int32_t rel0 = wave * 64 * kP;  // run0 relative to the tile
 
     double nuj[kP], acc[kP];
 #pragma unroll
@@ -129,6 +146,9 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
         if ((int)threadIdx.x < cnt) {
             tile[threadIdx.x] = wing[base + threadIdx.x];
             const WingIdx r = idx[base + threadIdx.x];
+            bnd[threadIdx.x] = make_uint4(bnd_pack(r.wlo, r.whi, tile0, kTilePoints),
+                                          bnd_pack(r.g3lo, r.g3hi, tile0, kTilePoints),
+                                          bnd_pack(r.clo, r.chi, tile0, kTilePoints), (uint32_t)r.flags);
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) {
                 const int32_t r0 = tile0 + w * 64 * kP;
@@ -205,13 +225,14 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                 // the rule's own sequence, points outside the window adding
                 // zero: the general path's sequence for these groups, bit
                 // for bit, without evaluating the other rule
-                const WingIdx ri = idx[base + k];
+                const uint32_t wb = (uint32_t)__builtin_amdgcn_readfirstlane((int)bnd[k].x);
+                const int32_t wlo = bnd_lo(wb), whi = bnd_hi(wb);
                 const double nu0 = tile[k].nu0, Lg = tile[k].Lg;
                 bool take[kP];
 #pragma unroll
                 for (int p = 0; p < kP; ++p) {
-                    const int32_t j = run0 + lane + 64 * p;
-                    take[p] = j >= ri.wlo && j <= ri.whi;
+                    const int32_t jr = rel0 + lane + 64 * p;
+                    take[p] = jr >= wlo && jr <= whi;
                 }
                 if (path == kGH1Edge) {
                     const double G2 = tile[k].G2;
@@ -256,26 +277,29 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
             const double M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Bn = tile[k].Bn, Cn = tile[k].Cn;
             // general path: window edges (with edges == false), region edges,
             // core points (left to the core kernel), the grid end, lines
-            // outside the grouping range (rare: the index record is read from
-            // memory, not staged)
-            const WingIdx ri = idx[base + k];
-            const int32_t wlo = ri.wlo, whi = ri.whi;
-            const int32_t g3lo = ri.g3lo, g3hi = ri.g3hi;
-            const int32_t clo = ri.clo, chi = ri.chi;
-            const bool safe = (ri.flags & kGroupSafe) != 0;
+            // outside the grouping range (rare)
+            const uint4 b4 = bnd[k];
+            const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b4.x);
+            const uint32_t b1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b4.y);
+            const uint32_t b2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b4.z);
+            const uint32_t b3 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b4.w);
+            const int32_t wlo = bnd_lo(b0), whi = bnd_hi(b0);
+            const int32_t g3lo = bnd_lo(b1), g3hi = bnd_hi(b1);
+            const int32_t clo = bnd_lo(b2), chi = bnd_hi(b2);
+            const bool safe = (b3 & kGroupSafe) != 0;
 #pragma unroll
             for (int p = 0; p < kP; p += 4) {
                 double num[4], den[4];
                 bool take[4], one[4], core_pt[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int32_t j = run0 + lane + 64 * (p + e);
+                    const int32_t jr = rel0 + lane + 64 * (p + e);
                     const double dv = nuj[p + e] - nu0;
                     double n3, m3;
                     gh3_nm(dv, M2, M1, M0, Bn, Cn, n3, m3);
-                    one[e] = j < g3lo || j > g3hi;
-                    core_pt[e] = j >= clo && j <= chi;
-                    take[e] = j >= wlo && j <= whi && !core_pt[e];
+                    one[e] = jr < g3lo || jr > g3hi;
+                    core_pt[e] = jr >= clo && jr <= chi;
+                    take[e] = jr >= wlo && jr <= whi && !core_pt[e];
                     num[e] = one[e] ? 1.0 : n3;
                     den[e] = one[e] ? fma(dv, dv, G2) : m3;
                 }
