@@ -550,7 +550,6 @@ std::vector<std::pair<size_t, size_t>> present_fields(const hk_lines* L)
 namespace {
 
 constexpr int32_t kCountBlocks = 256;  // partial sums per evaluation count
-constexpr int64_t kTablesSub = 16;      // binary32 tables: states per binary64 record pass
 
 // Partial sums sized by their bound up to this many bytes; beyond it (grids
 // above ~2e7 points) the plan is read back instead.
@@ -1524,17 +1523,12 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
         HK_HIP(ctx, ctx->tb_wing.ensure(nb * sizeof(WingRec)), "allocating batch records");
         HK_HIP(ctx, ctx->tb_core.ensure(nb * sizeof(CoreRec)), "allocating batch records");
     } else {
-        // binary64 records of up to kSub states at a time, from which the
-        // binary32 ones are made
-        const size_t n1 = (size_t)std::max<int64_t>(n, 1) * (size_t)std::min<int64_t>(B, kTablesSub);
-        HK_HIP(ctx, ctx->wing.ensure(n1 * sizeof(WingRec)), "allocating line records");
-        HK_HIP(ctx, ctx->core.ensure(n1 * sizeof(CoreRec)), "allocating line records");
         HK_HIP(ctx, ctx->tb_w32.ensure(nb * sizeof(WingRec32)), "allocating batch records");
         HK_HIP(ctx, ctx->tb_c32.ensure(nb * sizeof(CoreRec32)), "allocating batch records");
         HK_HIP(ctx, ctx->tb_comp.ensure((size_t)B * np * sizeof(float)), "allocating batch sums");
         HK_HIP(ctx, ctx->tb_scale.ensure((size_t)B * sizeof(int32_t)), "allocating batch scales");
         HK_HIP(ctx, ctx->tb_kappa.ensure((size_t)B * np * sizeof(double)), "allocating the opacities");
-        HK_HIP(ctx, ctx->f32partial.ensure((size_t)256 * kTablesSub * sizeof(double)), "allocating the scale");
+        HK_HIP(ctx, ctx->f32partial.ensure((size_t)256 * B * sizeof(double)), "allocating the scale");
     }
     // per-state constants and reaches of a batch, on the device
     HK_HIP(ctx, ctx->tb_prep.ensure((size_t)B * (sizeof(PrepParams) + 2 * sizeof(double))), "allocating batch constants");
@@ -1602,26 +1596,16 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
                                                        static_cast<CoreRec*>(ctx->tb_core.p), ctx->stream),
                        "line_prep_f64");
             } else {
-                for (int32_t s0 = 0; s0 < nbat; s0 += (int32_t)kTablesSub) {
-                    const int32_t ns = std::min<int32_t>((int32_t)kTablesSub, nbat - s0);
-                    WingRec* w = static_cast<WingRec*>(ctx->wing.p);
-                    CoreRec* c = static_cast<CoreRec*>(ctx->core.p);
-                    int32_t* scale = static_cast<int32_t*>(ctx->tb_scale.p) + s0;
-                    WingIdx* ix = tidx + (int64_t)s0 * n;
-                    HK_HIP(ctx, launch_line_prep_f64_batch(L, d_pps + s0, ns, w, ix, c, ctx->stream), "line_prep_f64");
-                    if (n > 0) {
-                        HK_HIP(ctx, launch_f32_scale(w, c, n, static_cast<double*>(ctx->f32partial.p), 256, scale,
-                                                     ctx->stream, ns),
-                               "f32_scale");
-                        HK_HIP(ctx, launch_line_prep_f32(w, ix, c, n, grid->nu_min, grid->dnu, scale,
-                                                         static_cast<WingRec32*>(ctx->tb_w32.p) + (int64_t)s0 * n,
-                                                         static_cast<CoreRec32*>(ctx->tb_c32.p) + (int64_t)s0 * n,
-                                                         ctx->stream, ns),
-                               "line_prep_f32");
-                    } else {
-                        HK_HIP(ctx, launch_zero(scale, (size_t)ns * sizeof(int32_t), ctx->stream), "zero");
-                    }
-                }
+                // the binary32 records straight from the line list: the
+                // states' scales from a pass over the peaks, then the records
+                int32_t* scale = static_cast<int32_t*>(ctx->tb_scale.p);
+                HK_HIP(ctx, launch_f32_scale_lines(L, d_pps, static_cast<double*>(ctx->f32partial.p), 256, scale,
+                                                   ctx->stream, nbat),
+                       "f32_scale");
+                HK_HIP(ctx, launch_line_prep_f32_direct(L, d_pps, nbat, grid->nu_min, grid->dnu, scale, tidx,
+                                                        static_cast<WingRec32*>(ctx->tb_w32.p),
+                                                        static_cast<CoreRec32*>(ctx->tb_c32.p), ctx->stream),
+                       "line_prep_f32");
             }
             HK_HIP(ctx, launch_eval_counts(tidx, n, counts + b0 * kCountBlocks * 3, kCountBlocks, ctx->stream, nbat),
                    "eval_counts");

@@ -20,6 +20,12 @@ constexpr double kInvPi = 0.31830988618379067154;
 constexpr double kInvSqrtPi = 0.56418958354775628695;
 
 // Region radii of the Voigt scheme on a^2 + u^2 (§2.4).
+// A volatile object in LDS, named with its address space: a volatile access
+// through a plain pointer into LDS compiles to a flat access (the generic
+// path, with a wait on the vector memory counter), this one to an LDS access.
+template <typename T>
+using lds_volatile = volatile __attribute__((address_space(3))) T;
+
 constexpr double kCoreR2 = 100.0;
 constexpr double kGH1R2 = 1.0e6;
 
@@ -301,6 +307,17 @@ hipError_t launch_eval_counts(const WingIdx* idx, int64_t n_lines, int64_t* part
 hipError_t launch_f32_scale(const WingRec* wing, const CoreRec* core, int64_t n_lines,
                             double* partial, int32_t n_blocks, int32_t* scale, hipStream_t s,
                             int32_t n_states = 1);
+// Binary32 tables straight from the line list, every state of a batch in
+// one launch each (state blockIdx.y, constants pps[state]): the peak bound's
+// per-block maxima (n_blocks per state) and the scale of each state; then
+// the index records and the binary32 records (n_lines apart per state),
+// equal to those of launch_line_prep_f64 + launch_f32_scale +
+// launch_line_prep_f32.
+hipError_t launch_f32_scale_lines(const LinesDev& L, const PrepParams* pps, double* partial, int32_t n_blocks,
+                                  int32_t* scale, hipStream_t s, int32_t n_states);
+hipError_t launch_line_prep_f32_direct(const LinesDev& L, const PrepParams* pps, int32_t n_states, double nu_min,
+                                       double dnu, const int32_t* scale, WingIdx* idx, WingRec32* w32,
+                                       CoreRec32* c32, hipStream_t s);
 hipError_t launch_line_prep_f32(const WingRec* wing, WingIdx* idx, const CoreRec* core,
                                 int64_t n_lines, double nu_min, double dnu, const int32_t* scale,
                                 WingRec32* w32, CoreRec32* c32, hipStream_t s, int32_t n_states = 1);

@@ -113,8 +113,7 @@ __device__ inline void radix_sort_block(K (&key)[kRadixMaxRounds], int rounds, i
                                         uint32_t* wsum)
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    volatile uint32_t* wc = cnt + wave * 256;  // this wavefront's counters
+    lds_volatile<uint32_t>* wc = (lds_volatile<uint32_t>*)(cnt + wave * 256);  // this wavefront's counters
     uint32_t rank[kRadixMaxRounds];
     for (int shift = 0; shift < (int)(8 * sizeof(K)); shift += 8) {
         for (int q = lane; q < 256; q += 64) wc[q] = 0u;
@@ -123,26 +122,38 @@ __device__ inline void radix_sort_block(K (&key)[kRadixMaxRounds], int rounds, i
             if (r < rounds) {
                 const bool valid = wave * 64 * rounds + r * 64 + lane < m;
                 const uint32_t d = (uint32_t)(key[r] >> shift) & 0xffu;
-                uint64_t peers = __ballot(valid);
+                // peers: the lanes whose digit equals this lane's, as two
+                // 32-bit halves; bit b of the digit takes each lane's mask
+                // mb = 0 where the bit is set and all ones where it is not,
+                // and keeps the lanes of the ballot (bit set) XOR mb
+                const uint64_t vb = __ballot(valid);
+                uint32_t plo = (uint32_t)vb, phi = (uint32_t)(vb >> 32);
+                const uint32_t nd = ~d;
 #pragma unroll
                 for (int b = 0; b < 8; ++b) {
-                    const uint64_t bal = __ballot((d >> b) & 1u);
-                    peers &= ((d >> b) & 1u) ? bal : ~bal;
+                    const uint32_t mb = (uint32_t)((int32_t)(nd << (31 - b)) >> 31);
+                    const uint64_t bal = __ballot(mb == 0u);
+                    plo &= (uint32_t)bal ^ mb;
+                    phi &= (uint32_t)(bal >> 32) ^ mb;
                 }
-                const uint32_t rk = (uint32_t)__builtin_popcountll(peers & below);
+                const uint32_t rk = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
                 const uint32_t old = wc[d];
                 rank[r] = old + rk;
-                if (valid && rk == 0) wc[d] = old + (uint32_t)__builtin_popcountll(peers);
+                if (valid && rk == 0) wc[d] = old + (uint32_t)(__builtin_popcount(plo) + __builtin_popcount(phi));
             }
         }
         __syncthreads();
         // digit t (threads 0 .. 255): the waves' starts in wave order, then
         // the digits' starts by an exclusive scan of their totals
         uint32_t tot = 0;
+        uint32_t pre[kRadixWaves];  // digit t's count in the waves before each
         if (t < 256) {
+#pragma unroll
+            for (int w = 0; w < kRadixWaves; ++w) pre[w] = cnt[w * 256 + t];
+#pragma unroll
             for (int w = 0; w < kRadixWaves; ++w) {
-                const uint32_t c = cnt[w * 256 + t];
-                cnt[w * 256 + t] = tot;
+                const uint32_t c = pre[w];
+                pre[w] = tot;
                 tot += c;
             }
         }
@@ -157,7 +168,8 @@ __device__ inline void radix_sort_block(K (&key)[kRadixMaxRounds], int rounds, i
         if (t < 256) {
             uint32_t base = incl - tot;
             for (int w = 0; w < wave; ++w) base += wsum[w];
-            for (int w = 0; w < kRadixWaves; ++w) cnt[w * 256 + t] += base;
+#pragma unroll
+            for (int w = 0; w < kRadixWaves; ++w) cnt[w * 256 + t] = base + pre[w];
         }
         __syncthreads();
 #pragma unroll

@@ -97,10 +97,11 @@ __device__ void region_interval(double R, double nu_min, double dnu, int32_t n, 
     *hi_out = (int32_t)hi;
 }
 
-// The records of line i for one state (constants pp).
-__device__ __forceinline__ void line_prep_one(const LinesDev& L, const PrepParams& pp, int64_t i,
-                                              WingRec* __restrict__ wing, WingIdx* __restrict__ idx,
-                                              CoreRec* __restrict__ core)
+// Line i scaled to one state (constants pp): strength, widths, centre.
+struct LineScaled {
+    double S, alpha, GL, nu0;
+};
+__device__ __forceinline__ LineScaled line_scaled(const LinesDev& L, const PrepParams& pp, int64_t i)
 {
     const double nu = L.nu[i];
     const double E = L.E_lower[i];
@@ -109,21 +110,38 @@ __device__ __forceinline__ void line_prep_one(const LinesDev& L, const PrepParam
     const double delta = L.delta ? L.delta[i] : 0.0;
     const double A21 = L.A21 ? L.A21[i] : 0.0;
 
+    LineScaled r;
     // eq. (18), with E'' for Delta E and 1 - exp(-z) = -expm1(-z)
     const double boltz = exp(-kC2 * E / pp.T + kC2 * E / pp.T_ref);
     const double stim = expm1(-kC2 * nu / pp.T) / expm1(-kC2 * nu / pp.T_ref);
-    const double S = L.S_ref[i] * pp.q_ratio * boltz * stim;
+    r.S = L.S_ref[i] * pp.q_ratio * boltz * stim;
     // eq. (19): alpha = Gamma_D / sqrt(ln 2) = nu sqrt(2 k_B T / m) / c
-    const double alpha = nu * pp.dop;
+    r.alpha = nu * pp.dop;
     // eq. (20), P0 = 1 atm
-    const double GL = A21 * pp.nat +
-                      pow(pp.tscale, -L.n_air[i]) * (g_air * (pp.P - pp.P_self) + g_self * pp.P_self);
+    r.GL = A21 * pp.nat + pow(pp.tscale, -L.n_air[i]) * (g_air * (pp.P - pp.P_self) + g_self * pp.P_self);
     // eq. (21); kept free of contraction so the window bounds below are the
     // exact binary64 expressions of the definition
-    const double nu0 = __dadd_rn(nu, __dmul_rn(delta, pp.P));
+    r.nu0 = __dadd_rn(nu, __dmul_rn(delta, pp.P));
+    return r;
+}
 
-    WingRec w;
-    WingIdx x;
+// S Phi bounded above by the smaller of the Doppler and the Lorentz peak
+// heights, S / (alpha sqrt(pi)) and S / (pi Gamma_L): the same products
+// as the records' norm and Lg / G2.
+__device__ __forceinline__ double line_peak(const LineScaled& ls)
+{
+    const double doppler = ls.S * (1.0 / ls.alpha) * kInvSqrtPi;
+    const double G2 = ls.GL * ls.GL;
+    const double lorentz = G2 > 0.0 ? (ls.S * ls.GL * kInvPi) / G2 : doppler;
+    return fmin(doppler, lorentz);
+}
+
+// The records of line i for one state (constants pp), in registers.
+__device__ __forceinline__ void line_prep_vals(const LinesDev& L, const PrepParams& pp, int64_t i, WingRec& w,
+                                               WingIdx& x, CoreRec& c)
+{
+    const LineScaled ls = line_scaled(L, pp, i);
+    const double S = ls.S, alpha = ls.alpha, GL = ls.GL, nu0 = ls.nu0;
     w.nu0 = nu0;
     w.Lg = S * GL * kInvPi;
     w.G2 = GL * GL;
@@ -162,10 +180,7 @@ __device__ __forceinline__ void line_prep_one(const LinesDev& L, const PrepParam
     const double y2 = y * y;
     region_interval(kGH1R2, pp.nu_min, pp.dnu, n, nu0, invA, y2, &x.g3lo, &x.g3hi);
     region_interval(kCoreR2, pp.nu_min, pp.dnu, n, nu0, invA, y2, &x.clo, &x.chi);
-    wing[i] = w;
-    idx[i] = x;
 
-    CoreRec c;
     c.invA = invA;
     c.y = y;
     c.y2 = y2;
@@ -184,6 +199,19 @@ __device__ __forceinline__ void line_prep_one(const LinesDev& L, const PrepParam
     }
     c.pad0 = 0.0;
     c.pad1 = 0.0;
+}
+
+// The records of line i for one state, to memory.
+__device__ __forceinline__ void line_prep_one(const LinesDev& L, const PrepParams& pp, int64_t i,
+                                              WingRec* __restrict__ wing, WingIdx* __restrict__ idx,
+                                              CoreRec* __restrict__ core)
+{
+    WingRec w;
+    WingIdx x;
+    CoreRec c;
+    line_prep_vals(L, pp, i, w, x, c);
+    wing[i] = w;
+    idx[i] = x;
     core[i] = c;
 }
 
@@ -327,6 +355,41 @@ __global__ void f32_scale_kernel(const double* __restrict__ partial, int32_t n_b
     scale[0] = m > 0.0 ? 100 - ilogb(m) : 0;
 }
 
+// The binary32 records of one line from its binary64 ones (scale s: peaks
+// times 2^s), and its nearest grid point jc.
+__device__ __forceinline__ void to_f32(const WingRec& w, const CoreRec& c, double nu_min, double dnu, int s,
+                                       WingRec32& r, CoreRec32& k, int32_t& jc_out)
+{
+    const double alpha = 1.0 / c.invA;
+    const double G = sqrt(w.G2);
+    const bool use_alpha = c.y2 < kGH1R2;  // the line has 3-node or core points
+    const double lam = use_alpha ? alpha : (G > 0.0 ? G : alpha);
+    const double il = 1.0 / lam;
+    // nearest grid point to the centre, clamped to int32 range
+    double fjc = rint((w.nu0 - nu_min) / dnu);
+    fjc = fmin(fmax(fjc, -1.0e9), 1.0e9);
+    const int32_t jc = (int32_t)fjc;
+    const double f = w.nu0 - fma((double)jc, dnu, nu_min);  // |f| <~ dnu/2
+    r.du = (float)(dnu * il);
+    r.fu = (float)(f * il);
+    r.Lg = (float)ldexp(w.Lg * il * il, s);
+    r.G2 = (float)(w.G2 * il * il);
+    const double il2 = il * il;
+    r.M2 = (float)(w.M2 * il2);
+    r.M1 = (float)(w.M1 * il2 * il2);
+    r.M0 = (float)(w.M0 * il2 * il2 * il2);
+    r.Cn = (float)(w.Cn * il2 * il2);
+    jc_out = jc;
+    k.dx = (float)(dnu * c.invA);
+    k.fx = (float)(f * c.invA);
+    k.y = (float)c.y;
+    k.y2 = (float)c.y2;
+    k.ex = (float)c.ex;
+    k.norm = (float)ldexp(c.norm, s);
+    k.T1 = (float)c.T1;
+    k.pad = 0.0f;
+}
+
 __global__ __launch_bounds__(256) void line_prep_f32_kernel(
     const WingRec* __restrict__ wing, WingIdx* __restrict__ idx, const CoreRec* __restrict__ core,
     int64_t n, double nu_min, double dnu, const int32_t* __restrict__ scale,
@@ -343,42 +406,62 @@ __global__ __launch_bounds__(256) void line_prep_f32_kernel(
         c32 += o;
         scale += blockIdx.y;
     }
-    const WingRec w = wing[i];
-    const CoreRec c = core[i];
-    const int s = scale[0];
-    const double alpha = 1.0 / c.invA;
-    const double G = sqrt(w.G2);
-    const bool use_alpha = c.y2 < kGH1R2;  // the line has 3-node or core points
-    const double lam = use_alpha ? alpha : (G > 0.0 ? G : alpha);
-    const double il = 1.0 / lam;
-    // nearest grid point to the centre, clamped to int32 range
-    double fjc = rint((w.nu0 - nu_min) / dnu);
-    fjc = fmin(fmax(fjc, -1.0e9), 1.0e9);
-    const int32_t jc = (int32_t)fjc;
-    const double f = w.nu0 - fma((double)jc, dnu, nu_min);  // |f| <~ dnu/2
     WingRec32 r;
-    r.du = (float)(dnu * il);
-    r.fu = (float)(f * il);
-    r.Lg = (float)ldexp(w.Lg * il * il, s);
-    r.G2 = (float)(w.G2 * il * il);
-    const double il2 = il * il;
-    r.M2 = (float)(w.M2 * il2);
-    r.M1 = (float)(w.M1 * il2 * il2);
-    r.M0 = (float)(w.M0 * il2 * il2 * il2);
-    r.Cn = (float)(w.Cn * il2 * il2);
-    w32[i] = r;
-    idx[i].jc = jc;
     CoreRec32 k;
-    k.dx = (float)(dnu * c.invA);
-    k.fx = (float)(f * c.invA);
-    k.y = (float)c.y;
-    k.y2 = (float)c.y2;
-    k.ex = (float)c.ex;
-    k.norm = (float)ldexp(c.norm, s);
-    k.T1 = (float)c.T1;
-    k.pad = 0.0f;
+    to_f32(wing[i], core[i], nu_min, dnu, scale[0], r, k, idx[i].jc);
+    w32[i] = r;
     c32[i] = k;
 }
+
+// Line prep straight to the binary32 records: the binary64 records of line
+// i for state blockIdx.y (constants pps[blockIdx.y]) in registers, the
+// index record with its centre to idx, the binary32 records to w32 and c32
+// (records n_lines apart per state).  The same values as the binary64 prep
+// followed by line_prep_f32_kernel.
+__global__ __launch_bounds__(256) void line_prep_f32_direct_kernel(LinesDev L, const PrepParams* __restrict__ pps,
+                                                                   double nu_min, double dnu,
+                                                                   const int32_t* __restrict__ scale,
+                                                                   WingIdx* __restrict__ idx,
+                                                                   WingRec32* __restrict__ w32,
+                                                                   CoreRec32* __restrict__ c32)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.n) return;
+    const int64_t o = (int64_t)blockIdx.y * L.n;
+    WingRec w;
+    WingIdx x;
+    CoreRec c;
+    line_prep_vals(L, pps[blockIdx.y], i, w, x, c);
+    WingRec32 r;
+    CoreRec32 k;
+    to_f32(w, c, nu_min, dnu, scale[blockIdx.y], r, k, x.jc);
+    idx[o + i] = x;
+    w32[o + i] = r;
+    c32[o + i] = k;
+}
+
+// Per-block maxima of the peak bound over the lines of state blockIdx.y,
+// from the line list (the values f32_peak_kernel takes from the records).
+__global__ __launch_bounds__(256) void f32_peak_lines_kernel(LinesDev L, const PrepParams* __restrict__ pps,
+                                                             double* __restrict__ partial)
+{
+    __shared__ double red[256];
+    const PrepParams& pp = pps[blockIdx.y];
+    partial += (int64_t)blockIdx.y * gridDim.x;
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = fmax(m, line_peak(line_scaled(L, pp, i)));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + k]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+
 
 // The wing's Kahan pair (sum, comp) of each point; the series sum, when not
 // zero, Kahan-added to it (value = s - c, c the running correction); then
@@ -420,6 +503,26 @@ hipError_t launch_f32_scale(const WingRec* wing, const CoreRec* core, int64_t n_
     if (n_states <= 0) return hipSuccess;
     f32_peak_kernel<<<dim3(n_blocks, n_states), dim3(256), 0, s>>>(wing, core, n_lines, partial);
     f32_scale_kernel<<<dim3(n_states), dim3(64), 0, s>>>(partial, n_blocks, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_f32_scale_lines(const LinesDev& L, const PrepParams* pps, double* partial, int32_t n_blocks,
+                                  int32_t* scale, hipStream_t s, int32_t n_states)
+{
+    if (n_states <= 0) return hipSuccess;
+    f32_peak_lines_kernel<<<dim3(n_blocks, n_states), dim3(256), 0, s>>>(L, pps, partial);
+    f32_scale_kernel<<<dim3(n_states), dim3(64), 0, s>>>(partial, n_blocks, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_line_prep_f32_direct(const LinesDev& L, const PrepParams* pps, int32_t n_states, double nu_min,
+                                       double dnu, const int32_t* scale, WingIdx* idx, WingRec32* w32,
+                                       CoreRec32* c32, hipStream_t s)
+{
+    if (L.n == 0 || n_states <= 0) return hipSuccess;
+    const int64_t blocks = (L.n + 255) / 256;
+    line_prep_f32_direct_kernel<<<dim3((unsigned)blocks, n_states), dim3(256), 0, s>>>(L, pps, nu_min, dnu, scale,
+                                                                                        idx, w32, c32);
     return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ namespace {
 constexpr int kWaves = 4;
 constexpr int kTL = 64 * kWaves;  // 256 lines per LDS block, one per thread
 constexpr int kMaxTerms = 2 * 10 + 14;
+static_assert(kMaxTerms <= 64, "one lane per series term builds the tables");
 // (kGH1Edge, kGH3Edge: a run wholly in one rule's region that the line's
 // window covers in part)
 enum : uint32_t { kSkip = 0, kGH1 = 1, kGH3 = 2, kGeneral = 3, kGH1Edge = 4, kGH3Edge = 5 };
@@ -403,6 +404,8 @@ __device__ __forceinline__ void core_f32_tile(int64_t t, int64_t L0, int64_t L1,
     float* wt = w_tab[wave];
     for (int q = lane; q < kCoreRun; q += 64) acc[q] = 0.0f;
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    // lane nn < kMaxTerms builds entry nn of each piece's table
+    const float m_lane = 0.5f * (float)(lane + 1);
 
     for (int64_t base = L0; base < L1; base += kCoreBatch) {
         const int64_t i = base + lane;
@@ -439,21 +442,21 @@ __device__ __forceinline__ void core_f32_tile(int64_t t, int64_t L0, int64_t L1,
         const int32_t st_k = lane < np ? pc[lane].start : total;
         int s_lo = 0;
         for (int32_t f0 = 0; f0 < total;) {
+            // (s_lo, s_end: the same in every lane, kept in scalar registers)
+            s_lo = __builtin_amdgcn_readfirstlane(s_lo);
             int s_end = __builtin_popcountll(__ballot(lane < np && st_k < f0 + 64));
-            s_end = min(s_end, s_lo + kChunkPieces);
-            const int32_t next_start = __shfl(st_k, min(s_end, 63), 64);
+            s_end = __builtin_amdgcn_readfirstlane(min(s_end, s_lo + kChunkPieces));
+            const int32_t next_start = __builtin_amdgcn_readlane(st_k, min(s_end, 63));
             const int32_t f_end = s_end < np ? min(next_start, f0 + 64) : min(total, f0 + 64);
-            const int n_tab = (s_end - s_lo) * kMaxTerms;
-            for (int e = lane; e < n_tab; e += 64) {
-                const int k = e / kMaxTerms, nn = e - k * kMaxTerms;
-                const float mm = 0.5f * (float)(nn + 1);
-                wt[e] = 1.0f / fmaf(mm, mm, pc[s_lo + k].y2);
+            for (int k = s_lo; k < s_end; ++k) {
+                const float y2 = pc[k].y2;
+                if (lane < kMaxTerms) wt[(k - s_lo) * kMaxTerms + lane] = 1.0f / fmaf(m_lane, m_lane, y2);
             }
             __builtin_amdgcn_wave_barrier();
             const int32_t f = f0 + lane;
             const bool act = f < f_end;
             int my = s_lo;
-            for (int s = s_lo + 1; s < s_end; ++s) my = __shfl(st_k, s, 64) <= f ? s : my;
+            for (int s = s_lo + 1; s < s_end; ++s) my = __builtin_amdgcn_readlane(st_k, s) <= f ? s : my;
             const CorePiece32& pp = pc[my];
             const int32_t j = pp.a + (f - pp.start);
             const int32_t jr = act ? j - run0 : 0;
@@ -461,10 +464,17 @@ __device__ __forceinline__ void core_f32_tile(int64_t t, int64_t L0, int64_t L1,
             const float* w = wt + (my - s_lo) * kMaxTerms;
             float v = 0.0f;
             if (act) v = pp.norm * voigt_core_f32(x, pp.y, pp.ex, pp.T1, w);
-            // add in line order (see core_f64_tile)
-            volatile float* vacc = acc;
-            for (int s = s_lo; s < s_end; ++s)
+            // add in line order: lanes of one piece hold distinct points, and
+            // the pieces' read-add-writes stay in order (volatile, and the
+            // fence: neither merged nor reordered by the compiler; a
+            // wavefront's LDS operations are carried out in issue order).
+            // (The LDS atomic add that core_f64_tile uses measured slower
+            // here.)
+            lds_volatile<float>* vacc = (lds_volatile<float>*)acc;
+            for (int s = s_lo; s < s_end; ++s) {
                 if (act && my == s) vacc[jr] = vacc[jr] + v;
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            }
             s_lo = (s_end < np && f_end >= next_start) ? s_end : s_end - 1;
             f0 = f_end;
         }
@@ -625,9 +635,11 @@ __device__ __forceinline__ int64_t core_f32_surr_tile(int64_t t, int64_t L0, int
                 const CorePiece32& pp = pc[my];
                 const int32_t jr = act ? pp.a + (f - pp.start) - run0 : 0;
                 const float v = act ? val[f - f0] : 0.0f;
-                volatile float* vacc = acc;
-                for (int s = s_first; s <= s_last; ++s)
+                lds_volatile<float>* vacc = (lds_volatile<float>*)acc;
+                for (int s = s_first; s <= s_last; ++s) {
                     if (act && my == s) vacc[jr] = vacc[jr] + v;
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                }
             }
             s_lo = s_at;
             __builtin_amdgcn_wave_barrier();

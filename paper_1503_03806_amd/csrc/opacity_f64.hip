@@ -29,6 +29,7 @@ namespace {
 constexpr int kWaves = 4;            // wavefronts per workgroup
 constexpr int kTL = 64 * kWaves;     // line records per LDS tile: one per thread
 constexpr int kMaxTerms = 2 * 10 + 14;  // series terms: n = 1 .. 2 ceil(x) + 14, x < 10
+static_assert(kMaxTerms <= 64, "one lane per series term builds the tables");
 
 // Per-(line, wavefront) path, decided once per LDS tile.
 // (kGH1Edge, kGH3Edge: a run wholly in one rule's region that the line's
@@ -509,9 +510,12 @@ __device__ __forceinline__ void core_f64_tile(int64_t t, int64_t L0, int64_t L1,
 {
     __shared__ double acc_tab[kWaves][kCoreRun];
     __shared__ CorePiece piece_tab[kWaves][kCoreBatch];
-    __shared__ double w_tab[kWaves][kChunkPieces * kMaxTerms];
+    __shared__ __align__(16) double w_tab[kWaves][kChunkPieces * kMaxTerms];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
+    // lane nn < kMaxTerms builds term nn + 1 of each piece's table
+    const double g_lane = kGauss[min(lane, kMaxTerms - 1)];
+    const double m_lane = 0.5 * (double)(lane + 1);
     const int32_t run0 = (int32_t)(t * kCoreTilePoints) + wave * kCoreRun;
     const int32_t run1 = min(run0 + kCoreRun, n) - 1;
     if (run0 > run1) return;
@@ -556,23 +560,23 @@ __device__ __forceinline__ void core_f64_tile(int64_t t, int64_t L0, int64_t L1,
         const int32_t st_k = lane < np ? pc[lane].start : total;
         int s_lo = 0;  // the piece holding point f0 of the flattened list
         for (int32_t f0 = 0; f0 < total;) {
+            // (s_lo, s_end: the same in every lane, kept in scalar registers)
+            s_lo = __builtin_amdgcn_readfirstlane(s_lo);
             int s_end = __builtin_popcountll(__ballot(lane < np && st_k < f0 + 64));
-            s_end = min(s_end, s_lo + kChunkPieces);
-            const int32_t next_start = __shfl(st_k, min(s_end, 63), 64);
+            s_end = __builtin_amdgcn_readfirstlane(min(s_end, s_lo + kChunkPieces));
+            const int32_t next_start = __builtin_amdgcn_readlane(st_k, min(s_end, 63));
             const int32_t f_end = s_end < np ? min(next_start, f0 + 64) : min(total, f0 + 64);
             // the 1 / (n^2/4 + y^2) e^{-n^2/4} tables of pieces s_lo .. s_end-1
-            const int n_tab = (s_end - s_lo) * kMaxTerms;
-            for (int e = lane; e < n_tab; e += 64) {
-                const int k = e / kMaxTerms, nn = e - k * kMaxTerms;
-                const double mm = 0.5 * (double)(nn + 1);
-                wt[e] = kGauss[nn] * qrcp(fma(mm, mm, pc[s_lo + k].y2));
+            for (int k = s_lo; k < s_end; ++k) {
+                const double y2 = pc[k].y2;
+                if (lane < kMaxTerms) wt[(k - s_lo) * kMaxTerms + lane] = g_lane * qrcp(fma(m_lane, m_lane, y2));
             }
             __builtin_amdgcn_wave_barrier();
             // this lane's point f and its piece
             const int32_t f = f0 + lane;
             const bool act = f < f_end;
             int my = s_lo;
-            for (int s = s_lo + 1; s < s_end; ++s) my = __shfl(st_k, s, 64) <= f ? s : my;
+            for (int s = s_lo + 1; s < s_end; ++s) my = __builtin_amdgcn_readlane(st_k, s) <= f ? s : my;
             double v = 0.0;
             int32_t jr = 0;  // the point, relative to run0
             if (act) {
@@ -582,13 +586,15 @@ __device__ __forceinline__ void core_f64_tile(int64_t t, int64_t L0, int64_t L1,
                 const double dv = fma((double)j, dnu, nu_min) - pp.nu0;
                 v = pp.norm * voigt_core(fabs(dv) * pp.invA, pp.y, pp.ex, pp.T1, wt + (my - s_lo) * kMaxTerms);
             }
-            // add in line order: lanes of one piece hold distinct points, and
-            // the pieces' read-add-writes stay in order (volatile: neither
-            // merged nor reordered by the compiler; a wavefront's LDS
-            // operations complete in order)
-            volatile double* vacc = acc;
-            for (int s = s_lo; s < s_end; ++s)
-                if (act && my == s) vacc[jr] = vacc[jr] + v;
+            // add in line order: one LDS add instruction per piece, whose
+            // lanes hold distinct points; a wavefront's LDS operations are
+            // carried out in the order they are issued, and the fence keeps
+            // the compiler from merging or reordering the pieces' adds
+            for (int s = s_lo; s < s_end; ++s) {
+                if (act && my == s)
+                    __hip_atomic_fetch_add(&acc[jr], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            }
             s_lo = (s_end < np && f_end >= next_start) ? s_end : s_end - 1;
             f0 = f_end;
         }
