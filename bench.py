@@ -177,19 +177,21 @@ def kdist_stage(ms, N, ppb, n_g, key_bytes=8, radix_max_keys=16384):
     """The Sort + k(g) stage against HBM and LDS: its algorithmic bytes (each
     opacity read once, k(g) written once) and the LDS traffic of the
     per-bin radix sort (bins of up to 16384 keys, one workgroup each): every
-    pass (8 bits of the key) writes each key to its place and reads it back,
-    in 32-bit words."""
+    pass (8 bits of the key) writes each key to its place and reads it back;
+    binary64 keys take the 4 passes of their high words, then a finish of the
+    runs of equal high words (the full 8 passes only when a run is long)."""
     n_bins = -(-N // ppb)
     hbm = key_bytes * N + 8 * n_bins * n_g
     out = {"ms": ms, "hbm_bytes": hbm, "GB_s": hbm / (ms * 1e-3) / 1e9,
            "frac_of_hbm_peak": hbm / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
     if ppb <= radix_max_keys:
-        passes = 8 * key_bytes // 8
+        passes = 4
         lds = passes * 2 * key_bytes * N
         out.update({"sort": "LDS radix, one workgroup per bin", "passes": passes,
                     "lds_bytes": lds, "lds_GB_s": lds / (ms * 1e-3) / 1e9,
                     "frac_of_lds_peak": lds / (ms * 1e-3) / 1e9 / PEAK_LDS_GBS,
-                    "bound": "latency of the ranking and the workgroup barriers (32 per bin)"})
+                    "bound": "VALU work of the ballot ranking per CU, and the tail of 300 workgroups "
+                             "on 256 CUs"})
     return out
 
 

@@ -94,7 +94,8 @@ __device__ inline double k_of_g(const K* s, int64_t m, double g, int rule)
 // kRadixThreads threads hold the bin's keys in registers -- wavefront w
 // holds positions [w R 64, (w+1) R 64), lane l of it key r at position
 // w R 64 + r 64 + l (R keys per thread) -- and sort them least significant
-// digit first, 8 bits per pass (8 passes of binary64 keys, 4 of binary32).
+// digit first, 8 bits per pass (binary32 keys: 4 passes; binary64 keys: the
+// 4 passes of the high words and a finish, below).
 // Each pass is stable: a wavefront ranks its keys round by round (so in
 // position order) among equal digits with eight ballots (the lanes sharing a
 // lane's digit are the AND over the digit's bits of each bit's ballot or its
@@ -108,6 +109,16 @@ constexpr int kRadixMaxRounds = 16;
 constexpr int64_t kRadixMaxKeys = (int64_t)kRadixThreads * kRadixMaxRounds;
 static_assert(kRadixMaxKeys <= (1 << 16), "LDS positions and counters fit 32 bits with room");
 
+// The bin sorted into buf[0, m).  Binary32 keys: four passes.  Binary64
+// keys: the four passes of their high words first; keys whose high words
+// are equal (values within about 2^-20 of each other: few, in short runs)
+// are then put in order by one thread per run, by insertion on the whole
+// key.  Should a run be longer than kRunMax, the eight passes of the whole
+// key follow instead.  Either way buf ends in ascending order of the keys.
+constexpr int kRunMax = 32;
+
+__device__ inline uint32_t key_hi(uint64_t k) { return (uint32_t)(k >> 32); }
+
 template <typename K>
 __device__ inline void radix_sort_block(K (&key)[kRadixMaxRounds], int rounds, int m, K* buf, uint32_t* cnt,
                                         uint32_t* wsum)
@@ -115,7 +126,12 @@ __device__ inline void radix_sort_block(K (&key)[kRadixMaxRounds], int rounds, i
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     lds_volatile<uint32_t>* wc = (lds_volatile<uint32_t>*)(cnt + wave * 256);  // this wavefront's counters
     uint32_t rank[kRadixMaxRounds];
-    for (int shift = 0; shift < (int)(8 * sizeof(K)); shift += 8) {
+    constexpr bool wide = sizeof(K) == 8;
+    int n_pass = 4;
+    for (int it = 0; it < n_pass; ++it) {
+        // binary64: the high word's bytes, then (only after a long run) all
+        // eight from the lowest
+        const int shift = !wide ? 8 * it : (it < 4 ? 32 + 8 * it : 8 * (it - 4));
         for (int q = lane; q < 256; q += 64) wc[q] = 0u;
 #pragma unroll
         for (int r = 0; r < kRadixMaxRounds; ++r) {
@@ -186,7 +202,32 @@ __device__ inline void radix_sort_block(K (&key)[kRadixMaxRounds], int rounds, i
             const int p = wave * 64 * rounds + r * 64 + lane;
             if (r < rounds && p < m) key[r] = buf[p];
         }
+        if (wide && it == 3) {
+            bool long_run = false;
+            for (int p = t; p + kRunMax < m; p += kRadixThreads)
+                long_run |= key_hi((uint64_t)buf[p]) == key_hi((uint64_t)buf[p + kRunMax]);
+            // (also the barrier after every thread's read-back)
+            if (__syncthreads_or(long_run)) n_pass = 12;
+        }
     }
+    if (!wide || n_pass > 4) return;
+    for (int p = t; p < m; p += kRadixThreads) {
+        const uint32_t h = key_hi((uint64_t)buf[p]);
+        if ((p > 0 && key_hi((uint64_t)buf[p - 1]) == h) || p + 1 >= m || key_hi((uint64_t)buf[p + 1]) != h)
+            continue;
+        int q = p + 1;  // the run [p, q] of high word h: at most kRunMax keys
+        while (q + 1 < m && key_hi((uint64_t)buf[q + 1]) == h) ++q;
+        for (int i = p + 1; i <= q; ++i) {
+            const K v = buf[i];
+            int j = i - 1;
+            while (j >= p && buf[j] > v) {
+                buf[j + 1] = buf[j];
+                --j;
+            }
+            buf[j + 1] = v;
+        }
+    }
+    __syncthreads();
 }
 
 // One workgroup per bin: bins of ppb consecutive points of n_states grids

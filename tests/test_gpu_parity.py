@@ -238,6 +238,37 @@ def test_kdist_matches_oracle_bitwise(ctx, n, ppb):
         assert np.array_equal(s[b0:b0 + ppb], np.sort(kap[b0:b0 + ppb]))
 
 
+@pytest.mark.parametrize("run", [2, 5, 31, 32, 33, 200])
+def test_kdist_runs_of_equal_high_words(ctx, run):
+    """Binary64 keys are sorted by their high 32 bits first; keys equal there
+    are put in order afterwards (or, past a run length of 32, by a full sort
+    of all 64 bits).  Bins holding groups of `run` keys that share a high
+    word and differ in the low word, among distinct keys: the sorted bins
+    equal numpy's and k(g) the oracle's, bit for bit."""
+    say("kdist runs", run)
+    rng = np.random.default_rng(100 + run)
+    ppb, n = 10000, 30000
+    keys = (10.0 ** rng.uniform(-30, -18, n)).view(np.uint64).copy()
+    for b0 in range(0, n, ppb):
+        # a few groups per bin, each of `run` keys with one high word
+        for _ in range(3):
+            at = b0 + rng.integers(0, ppb)
+            pos = b0 + rng.choice(ppb, run, replace=False)
+            hi = keys[at] & np.uint64(0xFFFFFFFF00000000)
+            lo = rng.choice(2 ** 32, run, replace=False).astype(np.uint64)
+            keys[pos] = hi | lo
+    kap = keys.view(np.float64)
+    assert np.all(np.isfinite(kap)) and np.all(kap > 0)
+    g, _ = oracle.g_nodes(20)
+    kt = torch.from_numpy(kap.copy()).cuda()
+    srt = torch.empty_like(kt)
+    kd = ctx.kdist(kt, ppb, g, sorted_out=srt).cpu().numpy()
+    assert np.array_equal(kd, oracle.kdist(kap, ppb, g))
+    s = srt.cpu().numpy()
+    for b0 in range(0, n, ppb):
+        assert np.array_equal(s[b0:b0 + ppb].view(np.uint64), np.sort(kap[b0:b0 + ppb]).view(np.uint64))
+
+
 # The midpoint-linear rule: the same binary64 expression on both sides,
 # evaluated without contraction, so the results agree bit for bit; binary32
 # keys enter as their exact binary64 values.
