@@ -318,7 +318,9 @@ __global__ __launch_bounds__(256) void wing_f32_reduce_kernel(WorkPlan wp, int64
 //     recurrence g(n+1) = g(n) e^{x - n/2 - 1/4}, started at its largest
 //     term so that nothing underflows before it matters;
 //   e^{-(n/2 + x)^2}: n = 1 .. 9 (below e^{-20} of e^{-x^2} beyond).
-// The trip counts are the same for every lane.
+// The trip counts are the same for every lane.  The reciprocals here and in
+// the tables (inv[n-1] = 1/(n^2/4 + y^2)) are the hardware's (within 1 ulp),
+// well inside the binary32 path's error budget.
 __device__ float voigt_core_f32(float x, float y, float ex, float T1, const float* inv)
 {
     const float d = 0.60653065971263342f;  // e^{-1/2}
@@ -351,7 +353,7 @@ __device__ float voigt_core_f32(float x, float y, float ex, float T1, const floa
     float sn, cs;
     sincosf(x * y, &sn, &cs);
     const float cos2 = (cs - sn) * (cs + sn);
-    const float sy = (y > 0.0f) ? sn / y : x;
+    const float sy = (y > 0.0f) ? sn * __builtin_amdgcn_rcpf(y) : x;
     const float inv_pi = 0.31830988618379067f;
     return E * fmaf(ex, cos2, sn * sy * inv_pi) + (y * inv_pi) * fmaf(-cos2 * E, T1, 0.5f * (s2 + s3));
 }
@@ -450,7 +452,8 @@ __device__ __forceinline__ void core_f32_tile(int64_t t, int64_t L0, int64_t L1,
             const int32_t f_end = s_end < np ? min(next_start, f0 + 64) : min(total, f0 + 64);
             for (int k = s_lo; k < s_end; ++k) {
                 const float y2 = pc[k].y2;
-                if (lane < kMaxTerms) wt[(k - s_lo) * kMaxTerms + lane] = 1.0f / fmaf(m_lane, m_lane, y2);
+                if (lane < kMaxTerms)
+                    wt[(k - s_lo) * kMaxTerms + lane] = __builtin_amdgcn_rcpf(fmaf(m_lane, m_lane, y2));
             }
             __builtin_amdgcn_wave_barrier();
             const int32_t f = f0 + lane;
@@ -572,7 +575,7 @@ __device__ __forceinline__ int64_t core_f32_surr_tile(int64_t t, int64_t L0, int
         for (int e = lane; e < np * kMaxTerms; e += 64) {
             const int k = e / kMaxTerms, nn = e - k * kMaxTerms;
             const float mm = 0.5f * (float)(nn + 1);
-            wt[e] = 1.0f / fmaf(mm, mm, pc[k].y2);
+            wt[e] = __builtin_amdgcn_rcpf(fmaf(mm, mm, pc[k].y2));
         }
         const int32_t st_k = lane < np ? pc[lane].start : total;
         __builtin_amdgcn_wave_barrier();

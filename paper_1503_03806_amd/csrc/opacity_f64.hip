@@ -33,8 +33,9 @@ static_assert(kMaxTerms <= 64, "one lane per series term builds the tables");
 
 // Per-(line, wavefront) path, decided once per LDS tile.
 // (kGH1Edge, kGH3Edge: a run wholly in one rule's region that the line's
-// window covers in part)
-enum : uint32_t { kSkip = 0, kGH1 = 1, kGH3 = 2, kGeneral = 3, kGH1Edge = 4, kGH3Edge = 5 };
+// window covers in part; kGH3Core: a run wholly in the 3-node region and the
+// window that holds series points)
+enum : uint32_t { kSkip = 0, kGH1 = 1, kGH3 = 2, kGeneral = 3, kGH1Edge = 4, kGH3Edge = 5, kGH3Core = 6 };
 
 // num / den to about 2^-48 relative: the hardware reciprocal (relative
 // error below 2^-24 on gfx950) and one Newton correction of the quotient.
@@ -63,19 +64,28 @@ __device__ inline double qrcp(double den)
 // The path of one line for the points [run0, run1] of a wavefront; run_end
 // is the run's nominal last point.  A run cut short by the grid end takes
 // the general path, which evaluates points whose group reaches beyond the
-// grid one by one.  A run wholly in one rule's region that the line's window
-// covers only in part takes the rule's own path with a window mask
-// (kGH1Edge, kGH3Edge); edges == false sends such runs down the general path
-// instead (a check: both give the same bits).
+// grid one by one, and so do lines outside the grouping range.  A run
+// wholly in one rule's region that the line's window covers only in part
+// takes the rule's own path with a window mask (kGH1Edge, kGH3Edge); a run
+// in the window and the 3-node region that holds series points takes the
+// 3-node path with the series points masked (kGH3Core).  edges == false
+// sends these down the general path instead (a check: both give the same
+// bits).
 __device__ inline uint32_t classify(const WingIdx& r, int32_t run0, int32_t run1, int32_t run_end, bool edges)
 {
     if (run0 > run1 || r.whi < run0 || r.wlo > run1) return kSkip;
-    if (run1 < run_end) return kGeneral;
+    if (run1 < run_end || !(r.flags & kGroupSafe)) return kGeneral;
     const bool full = r.wlo <= run0 && r.whi >= run1;
     const bool nocore = run1 < r.clo || run0 > r.chi;
-    if (!(nocore && (r.flags & kGroupSafe)) || (!full && !edges)) return kGeneral;
-    if (run1 < r.g3lo || run0 > r.g3hi) return full ? kGH1 : kGH1Edge;
-    if (r.g3lo <= run0 && r.g3hi >= run1) return full ? kGH3 : kGH3Edge;
+    const bool out3 = run1 < r.g3lo || run0 > r.g3hi;  // wholly 1-node
+    const bool in3 = r.g3lo <= run0 && r.g3hi >= run1;  // wholly 3-node
+    if (!edges) {
+        if (!full || !nocore) return kGeneral;
+        return out3 ? kGH1 : in3 ? kGH3 : kGeneral;
+    }
+    if (!nocore) return (full && in3) ? kGH3Core : kGeneral;
+    if (out3) return full ? kGH1 : kGH1Edge;
+    if (in3) return full ? kGH3 : kGH3Edge;
     return kGeneral;
 }
 
@@ -269,6 +279,43 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                         acc[p + 1] = fma(take[p + 1] ? x1 : 0.0, nn[1], acc[p + 1]);
                         acc[p + 2] = fma(take[p + 2] ? x2 : 0.0, nn[2], acc[p + 2]);
                         acc[p + 3] = fma(take[p + 3] ? x3 : 0.0, nn[3], acc[p + 3]);
+                    }
+                }
+                ++k;
+                continue;
+            }
+            if (path == kGH3Core) {
+                // the general path's sequences for these groups: a group
+                // without series points the 3-node path's, one with them a
+                // division per point, the series points adding zero
+                const uint32_t cb = (uint32_t)__builtin_amdgcn_readfirstlane((int)bnd[k].z);
+                const int32_t clo = bnd_lo(cb), chi = bnd_hi(cb);
+                const double nu0 = tile[k].nu0, Lg = tile[k].Lg;
+                const double M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Bn = tile[k].Bn, Cn = tile[k].Cn;
+#pragma unroll
+                for (int p = 0; p < kP; p += 4) {
+                    double nn[4], mm[4];
+                    bool cp[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        gh3_nm(nuj[p + e] - nu0, M2, M1, M0, Bn, Cn, nn[e], mm[e]);
+                        const int32_t jr = rel0 + lane + 64 * (p + e);
+                        cp[e] = jr >= clo && jr <= chi;
+                    }
+                    if (!cp[0] && !cp[1] && !cp[2] && !cp[3]) {
+                        const double P01 = mm[0] * mm[1], P23 = mm[2] * mm[3];
+                        const double c = qrcp(P01 * P23) * Lg;
+                        const double c01 = c * P23, c23 = c * P01;
+                        acc[p] = fma(c01 * mm[1], nn[0], acc[p]);
+                        acc[p + 1] = fma(c01 * mm[0], nn[1], acc[p + 1]);
+                        acc[p + 2] = fma(c23 * mm[3], nn[2], acc[p + 2]);
+                        acc[p + 3] = fma(c23 * mm[2], nn[3], acc[p + 3]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const double v = qdiv(Lg * nn[e], mm[e]);
+                            acc[p + e] += cp[e] ? 0.0 : v;
+                        }
                     }
                 }
                 ++k;
