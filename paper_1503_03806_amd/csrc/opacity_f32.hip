@@ -30,7 +30,10 @@ namespace {
 constexpr int kWaves = 4;
 constexpr int kTL = 64 * kWaves;  // 256 lines per LDS block, one per thread
 constexpr int kMaxTerms = 2 * 10 + 14;
-static_assert(kMaxTerms <= 64, "one lane per series term builds the tables");
+// Entries of a line's table 1/(n^2/4 + y^2) that voigt_core_f32 reads:
+// n - 1 <= st + 17 with st <= 12 (x < 10.75; series points have x < 10).
+constexpr int kTermsF32 = 30;
+static_assert(2 * kTermsF32 <= 64, "two pieces' tables per 64 lanes");
 // (kGH1Edge, kGH3Edge: a run wholly in one rule's region that the line's
 // window covers in part)
 enum : uint32_t { kSkip = 0, kGH1 = 1, kGH3 = 2, kGeneral = 3, kGH1Edge = 4, kGH3Edge = 5 };
@@ -325,7 +328,7 @@ __device__ float voigt_core_f32(float x, float y, float ex, float T1, const floa
 {
     const float d = 0.60653065971263342f;  // e^{-1/2}
     const float E = expf(-x * x);
-    const int st = max(1, (int)rintf(2.0f * x) - 9);
+    const int st = min(max(1, (int)rintf(2.0f * x) - 9), kTermsF32 - 18);
     float s3 = 0.0f;
     {
         const float h = 0.5f * (float)st - x;
@@ -395,7 +398,7 @@ __device__ __forceinline__ void core_f32_tile(int64_t t, int64_t L0, int64_t L1,
 {
     __shared__ float acc_tab[kWaves][kCoreRun];
     __shared__ CorePiece32 piece_tab[kWaves][kCoreBatch];
-    __shared__ float w_tab[kWaves][kChunkPieces * kMaxTerms];
+    __shared__ float w_tab[kWaves][kChunkPieces * kTermsF32];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int32_t run0 = (int32_t)(t * kCoreTilePoints) + wave * kCoreRun;
@@ -406,8 +409,11 @@ __device__ __forceinline__ void core_f32_tile(int64_t t, int64_t L0, int64_t L1,
     float* wt = w_tab[wave];
     for (int q = lane; q < kCoreRun; q += 64) acc[q] = 0.0f;
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    // lane nn < kMaxTerms builds entry nn of each piece's table
-    const float m_lane = 0.5f * (float)(lane + 1);
+    // two pieces' tables at a time: lane l < 2 kTermsF32 builds entry nn of
+    // the first (l < kTermsF32) or the second piece
+    const int half = lane >= kTermsF32 ? 1 : 0;
+    const int nn_lane = lane - half * kTermsF32;
+    const float m_lane = 0.5f * (float)(nn_lane + 1);
 
     for (int64_t base = L0; base < L1; base += kCoreBatch) {
         const int64_t i = base + lane;
@@ -450,10 +456,10 @@ __device__ __forceinline__ void core_f32_tile(int64_t t, int64_t L0, int64_t L1,
             s_end = __builtin_amdgcn_readfirstlane(min(s_end, s_lo + kChunkPieces));
             const int32_t next_start = __builtin_amdgcn_readlane(st_k, min(s_end, 63));
             const int32_t f_end = s_end < np ? min(next_start, f0 + 64) : min(total, f0 + 64);
-            for (int k = s_lo; k < s_end; ++k) {
-                const float y2 = pc[k].y2;
-                if (lane < kMaxTerms)
-                    wt[(k - s_lo) * kMaxTerms + lane] = __builtin_amdgcn_rcpf(fmaf(m_lane, m_lane, y2));
+            for (int k = s_lo; k < s_end; k += 2) {
+                const int kk = k + half;
+                if (lane < 2 * kTermsF32 && kk < s_end)
+                    wt[(kk - s_lo) * kTermsF32 + nn_lane] = __builtin_amdgcn_rcpf(fmaf(m_lane, m_lane, pc[kk].y2));
             }
             __builtin_amdgcn_wave_barrier();
             const int32_t f = f0 + lane;
@@ -464,7 +470,7 @@ __device__ __forceinline__ void core_f32_tile(int64_t t, int64_t L0, int64_t L1,
             const int32_t j = pp.a + (f - pp.start);
             const int32_t jr = act ? j - run0 : 0;
             const float x = act ? fabsf(fmaf((float)(j - pp.jc), pp.dx, -pp.fx)) : 0.0f;
-            const float* w = wt + (my - s_lo) * kMaxTerms;
+            const float* w = wt + (my - s_lo) * kTermsF32;
             float v = 0.0f;
             if (act) v = pp.norm * voigt_core_f32(x, pp.y, pp.ex, pp.T1, w);
             // add in line order: lanes of one piece hold distinct points, and
