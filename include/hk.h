@@ -453,8 +453,14 @@ int hk_gauss_legendre(int32_t n, double* g, double* w);
  *   "wing_edge_paths"      1 (default): the Gauss-Hermite kernels take a
  *                          wavefront's run that a line's window covers only
  *                          in part on that rule's own path with a window
- *                          mask; 0: on the general path (a check: both give
+ *                          mask, and runs that hold series points or both
+ *                          rules' points on paths of their own; 0: all of
+ *                          these on the general path (a check: both give
  *                          the same bits).
+ *   "tables_overlap"       0 (default): hk_tables runs each batch's series
+ *                          kernel, then its wing kernel, on the caller's
+ *                          stream; 1: the series on a second stream of the
+ *                          context while the wing runs (same bits).
  * Unknown names or values: HK_EINVAL. */
 int hk_set_option(hk_ctx* ctx, const char* name, int64_t value);
 /* Reads a knob into *value; also, read-only: "tables_points_per_lane", the

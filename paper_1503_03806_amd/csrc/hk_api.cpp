@@ -106,6 +106,7 @@ struct hk_ctx {
     int f64_points_per_lane = 4;  // tile shape of the binary64 opacity kernel (4 or 8)
     int f32_points_per_lane = 2;  // tile shape of the binary32 opacity kernel
     int wing_edge_paths = 1;      // 0: window-edge runs take the general path (same bits)
+    int tables_overlap = 0;       // 1: tables run the series beside the wing on the second stream
     // batched tables: per-state records, ranges and sums of one batch, the
     // per-state evaluation counters of the last call, and the tile shapes
     // chosen by timing, per (precision, lines, points, cutoff/dnu)
@@ -1638,28 +1639,34 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
                 return rc;
             tm.stop();
         }
-        // the series of the batch on the second stream, into its own grids,
-        // while the wing runs
-        if (int rc = ensure_side(ctx)) return rc;
-        HK_HIP(ctx, hipEventRecord(ctx->ev_fork, ctx->stream), "hipEventRecord");
-        HK_HIP(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0), "hipStreamWaitEvent");
+        // the series of the batch into its own grids: on the second stream
+        // while the wing runs (tables_overlap = 1), or before the wing on the
+        // caller's stream
+        const bool overlap = ctx->tables_overlap != 0;
+        hipStream_t cs = ctx->stream;
+        if (overlap) {
+            if (int rc = ensure_side(ctx)) return rc;
+            cs = ctx->side;
+            HK_HIP(ctx, hipEventRecord(ctx->ev_fork, ctx->stream), "hipEventRecord");
+            HK_HIP(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0), "hipStreamWaitEvent");
+        }
         {
-            StageTimer tm(ctx, HK_STAGE_CORE, ctx->side);
+            StageTimer tm(ctx, HK_STAGE_CORE, cs);
             if (f64)
                 HK_HIP(ctx, launch_core_f64(static_cast<WingRec*>(ctx->tb_wing.p), tidx,
                                             static_cast<CoreRec*>(ctx->tb_core.p), rc_all, n, n_tiles_c, nbat, cwp,
                                             grid->nu_min, grid->dnu, np, static_cast<double*>(ctx->tb_series.p),
-                                            static_cast<double*>(ctx->cplan.partial.p), ctx->side),
+                                            static_cast<double*>(ctx->cplan.partial.p), cs),
                        "core_f64");
             else
                 HK_HIP(ctx, launch_core_f32(tidx, static_cast<CoreRec32*>(ctx->tb_c32.p), rc_all, n, n_tiles_c, nbat,
                                             cwp, np, static_cast<float*>(ctx->tb_series.p),
                                             static_cast<float*>(ctx->cplan.partial.p), nullptr, nullptr, nullptr,
-                                            0, ctx->side),
+                                            0, cs),
                        "core_f32");
             tm.stop();
         }
-        HK_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->side), "hipEventRecord");
+        if (overlap) HK_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->side), "hipEventRecord");
         {
             StageTimer tm(ctx, HK_STAGE_OPACITY);
             if (f64)
@@ -1675,7 +1682,7 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
                        "wing_f32");
             tm.stop();
         }
-        HK_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "hipStreamWaitEvent");
+        if (overlap) HK_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "hipStreamWaitEvent");
         if (f64)
             HK_HIP(ctx, launch_add_f64(static_cast<double*>(ctx->tb_out.p), static_cast<double*>(ctx->tb_series.p),
                                        (int64_t)nbat * np, ctx->stream),
@@ -2130,6 +2137,11 @@ int hk_set_option(hk_ctx* ctx, const char* name, int64_t value)
         ctx->tables_mem = value << 20;
         return HK_OK;
     }
+    if (std::strcmp(name, "tables_overlap") == 0) {
+        if (value != 0 && value != 1) return fail(ctx, HK_EINVAL, "tables_overlap must be 0 or 1");
+        ctx->tables_overlap = (int)value;
+        return HK_OK;
+    }
     if (std::strcmp(name, "wing_edge_paths") == 0) {
         if (value != 0 && value != 1) return fail(ctx, HK_EINVAL, "wing_edge_paths must be 0 or 1");
         if (int rc = check_ctx(ctx)) return rc;
@@ -2156,6 +2168,7 @@ int hk_get_option(hk_ctx* ctx, const char* name, int64_t* value)
     else if (std::strcmp(name, "tables_mem_mib") == 0) *value = ctx->tables_mem >> 20;
     else if (std::strcmp(name, "tables_autotune") == 0) *value = ctx->tables_autotune;
     else if (std::strcmp(name, "wing_edge_paths") == 0) *value = ctx->wing_edge_paths;
+    else if (std::strcmp(name, "tables_overlap") == 0) *value = ctx->tables_overlap;
     else if (std::strcmp(name, "tables_points_per_lane") == 0) *value = ctx->tables_ppl_used;
     else if (std::strcmp(name, "wing_items") == 0 || std::strcmp(name, "wing_segment_lines") == 0) {
         // the last wing stage's plan (for its first state), read back

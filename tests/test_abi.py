@@ -183,6 +183,8 @@ def test_options_need_a_context_and_valid_values():
     assert "context" in hk.hk_last_error(None)
     assert hk.lib().hk_set_option(None, b"wing_edge_paths", 2) == hk.HK_EINVAL
     assert "0 or 1" in hk.hk_last_error(None)
+    assert hk.lib().hk_set_option(None, b"tables_overlap", -1) == hk.HK_EINVAL
+    assert "0 or 1" in hk.hk_last_error(None)
 
 
 def test_surrogate_calls_validate_arguments():

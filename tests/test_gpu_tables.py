@@ -127,6 +127,25 @@ def test_tables_batches_and_shapes_are_bitwise_identical(ctx):
         ctx.set_option("f32_points_per_lane", 2)
 
 
+def test_tables_overlap_is_bitwise_identical(ctx):
+    """The series beside the wing on a second stream, or before it on the
+    caller's stream: the same tables, bit for bit, in both precisions."""
+    w, lines, grid, conds = small_setup()
+    g, _ = oracle.g_nodes(w.n_g)
+    states = [state_of(c) for c in conds]
+    ctx.load_lines(lines, conds[0]["mass_amu"], conds[0]["T0"])
+    assert ctx.get_option("tables_overlap") == 0
+    try:
+        for precision in (hk.HK_F64, hk.HK_F32_KAHAN):
+            a = ctx.tables(states, grid, 10_000, g, precision).cpu().numpy()
+            ctx.set_option("tables_overlap", 1)
+            b = ctx.tables(states, grid, 10_000, g, precision).cpu().numpy()
+            ctx.set_option("tables_overlap", 0)
+            assert np.array_equal(a.view(np.uint64), b.view(np.uint64)), precision
+    finally:
+        ctx.set_option("tables_overlap", 0)
+
+
 def test_tables_edge_cases(ctx):
     w, lines, grid, conds = small_setup()
     g, _ = oracle.g_nodes(4)
