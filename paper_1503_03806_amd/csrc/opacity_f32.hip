@@ -35,25 +35,29 @@ constexpr int kMaxTerms = 2 * 10 + 14;
 constexpr int kTermsF32 = 30;
 static_assert(2 * kTermsF32 <= 64, "two pieces' tables per 64 lanes");
 // (kGH1Edge, kGH3Edge: a run wholly in one rule's region that the line's
-// window covers in part)
-enum : uint32_t { kSkip = 0, kGH1 = 1, kGH3 = 2, kGeneral = 3, kGH1Edge = 4, kGH3Edge = 5 };
+// window covers in part; kGH3Core: a run wholly in the 3-node region and the
+// window that holds series points)
+enum : uint32_t { kSkip = 0, kGH1 = 1, kGH3 = 2, kGeneral = 3, kGH1Edge = 4, kGH3Edge = 5, kGH3Core = 6 };
 
 // The path of one line for the points [run0, run1] of a wavefront; run_end
 // is the run's nominal last point.  A run cut short by the grid end takes
 // the general path, which leaves 3-node points whose pair partner lies
 // beyond the grid unpaired (so a point's bits do not depend on the tile
-// shape).  edges == false sends runs the window covers in part down the
-// general path too (a check of the window-edge paths, which give the same
-// bits).
+// shape).  A run in the window and the 3-node region that holds series
+// points takes the 3-node path with those points masked (kGH3Core).
+// edges == false sends runs the window covers in part, and those, down the
+// general path too (a check of the other paths, which give the same bits).
 __device__ inline uint32_t classify(const WingIdx& r, int32_t run0, int32_t run1, int32_t run_end, bool edges)
 {
     if (run0 > run1 || r.whi < run0 || r.wlo > run1) return kSkip;
     if (run1 < run_end) return kGeneral;
     const bool full = r.wlo <= run0 && r.whi >= run1;
     const bool nocore = run1 < r.clo || run0 > r.chi;
-    if (!nocore || (!full && !edges)) return kGeneral;
+    const bool in3 = r.g3lo <= run0 && r.g3hi >= run1;
+    if (!nocore) return (edges && full && in3) ? kGH3Core : kGeneral;
+    if (!full && !edges) return kGeneral;
     if (run1 < r.g3lo || run0 > r.g3hi) return full ? kGH1 : kGH1Edge;
-    if (r.g3lo <= run0 && r.g3hi >= run1) return full ? kGH3 : kGH3Edge;
+    if (in3) return full ? kGH3 : kGH3Edge;
     return kGeneral;
 }
 
@@ -200,6 +204,40 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
                             const float acc = fmaf(cp * mm[1 - e], nn[e], part[p + e]);
                             part[p + e] = (j >= wlo && j <= whi) ? acc : part[p + e];
                         }
+                    }
+                }
+                ++k;
+                continue;
+            }
+            if (path == kGH3Core) {
+                // the general path's sequence for these points: pairs without
+                // series points as on the 3-node path, the others one by one,
+                // the series points left as they are
+                const float fjc = fjct[k];
+                const float du = tile[k].du, fu = tile[k].fu, Lg = tile[k].Lg;
+                const float M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Cn = tile[k].Cn;
+                const float Bn = fmaf(2.0f, tile[k].G2, -1.5f);
+                const int32_t clo = tidx[k].clo, chi = tidx[k].chi;
+#pragma unroll
+                for (int p = 0; p < kP; p += 2) {
+                    float nn[2], mm[2];
+                    bool cpt[2];
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const int32_t j = run0 + lane + 64 * (p + e);
+                        cpt[e] = j >= clo && j <= chi;
+                        const float dv = fmaf(fj[p + e] - fjc, du, -fu);
+                        const float q = dv * dv;
+                        nn[e] = fmaf(q, q + Bn, Cn);
+                        mm[e] = fmaf(fmaf(q + M2, q, M1), q, M0);
+                    }
+                    const bool paired = !cpt[0] && !cpt[1];
+                    const float cp = rcpf(mm[0] * mm[1]) * Lg;
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const float acc = paired ? fmaf(cp * mm[1 - e], nn[e], part[p + e])
+                                                 : fmaf(Lg, nn[e] * rcpf(mm[e]), part[p + e]);
+                        part[p + e] = cpt[e] ? part[p + e] : acc;
                     }
                 }
                 ++k;
