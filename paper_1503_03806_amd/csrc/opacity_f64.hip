@@ -499,14 +499,29 @@ __device__ double voigt_core(double x, double y, double ex, double T1, const dou
     // sum): a fixed trip count, the same for every lane.  2 cosh(n x) by the
     // three-term recurrence c_{n+1} = c_1 c_n - c_{n-1}, c_0 = 2, which
     // follows the growing solution e^{nx} stably (relative error ~n eps).
+    // (w is read a pair of terms at a time, each pair one pair ahead of its
+    // use, so that a read is in flight while the previous pair is summed)
+    static_assert(kMaxTerms % 4 == 2, "8 double pairs in the loop, one after it");
+    const double2* w2 = reinterpret_cast<const double2*>(w);
     double cm = 2.0, cc = c1, sc = 0.0;
-#pragma unroll 2
-    for (int n = 0; n < kMaxTerms; ++n) {
-        sc = fma(w[n], cc, sc);
+    auto term = [&](double wn) {
+        sc = fma(wn, cc, sc);
         const double cn = fma(c1, cc, -cm);
         cm = cc;
         cc = cn;
+    };
+    double2 wa = w2[0];
+#pragma unroll 1
+    for (int h = 0; h < kMaxTerms / 2 - 1; h += 2) {
+        const double2 wb = w2[h + 1];
+        term(wa.x);
+        term(wa.y);
+        wa = w2[h + 2];
+        term(wb.x);
+        term(wb.y);
     }
+    term(wa.x);
+    term(wa.y);
     double s, co;
     sincos(x * y, &s, &co);
     const double cos2 = (co - s) * (co + s);
