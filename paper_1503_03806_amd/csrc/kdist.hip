@@ -3,20 +3,23 @@
 // the step or the midpoint-linear rule.
 //
 // The paper sorts the whole grid at once with bin tags (Thrust, §2.6).  Here
-// bins are independent: a bin that fits in LDS is sorted there by one
-// workgroup (bitonic network on the keys' bit patterns: non-negative IEEE
-// values order like their unsigned integer images); larger bins are cut
-// into LDS-sized chunks, each sorted in LDS, then merged pairwise in global
-// memory (each element finds its rank in the partner run by binary search;
-// ties keep left-before-right, so the merge is stable).
+// bins are independent, and keys are the opacities' bit patterns
+// (non-negative IEEE values order like their unsigned integer images).  A
+// bin of up to kRadixMaxKeys keys is sorted by one workgroup in registers
+// and LDS, by a radix sort whose ranking uses wavefront ballots (below); a
+// larger bin is cut into LDS-sized chunks, each sorted in LDS by a bitonic
+// network, then merged pairwise in global memory (each element finds its
+// rank in the partner run by binary search; ties keep left-before-right, so
+// the merge is stable).
 #include "hk_internal.h"
 
 namespace hk {
 size_t radix_lds_bytes(int elem_bytes, int64_t keys);
 namespace {
 
-// threads per sort workgroup (300 bins of 1e4 binary64 keys: 0.177 ms, against
-// 0.185 ms with 1024 threads and 0.188 ms with 256)
+// threads per chunk-sort workgroup (measured on 300 bins of 1e4 binary64
+// keys sorted this way: 0.177 ms, against 0.185 ms with 1024 threads and
+// 0.188 ms with 256)
 constexpr int kSortThreads = 512;
 
 template <typename K>
@@ -211,6 +214,9 @@ __device__ inline void radix_sort_block(K (&key)[kRadixMaxRounds], int rounds, i
         }
     }
     if (!wide || n_pass > 4) return;
+    // (a thread reads the high words next to its run while other threads
+    // reorder theirs: within a run every key has the same high word, so what
+    // it reads does not depend on their progress)
     for (int p = t; p < m; p += kRadixThreads) {
         const uint32_t h = key_hi((uint64_t)buf[p]);
         if ((p > 0 && key_hi((uint64_t)buf[p - 1]) == h) || p + 1 >= m || key_hi((uint64_t)buf[p + 1]) != h)
