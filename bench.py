@@ -82,13 +82,22 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(w, points: int, one_thread_bins: int, kappa_gpu=None, k_gpu=None):
+def synth_conditions(T, P):
+    import synth
+    return synth.conditions(T, P)
+
+
+def cpu_baseline(w, points: int, one_thread_bins: int, kappa_gpu=None, k_gpu=None, f32=None, tables=None):
     """The oracle, built -O3 -march=native on this host, timed on all host
     threads over `points` grid points (whole bins, centred; the whole grid
     by default) and on one thread over `one_thread_bins` bins, opacity +
     k(g) each.  With the GPU's binary64 grid and k(g) table (host arrays),
     also their error against the oracle's: max and p99.9 per bin for kappa,
-    max per bin for k(g)."""
+    max per bin for k(g); likewise, summarised, for the binary32 step's
+    (f32 = (kappa, k(g))).  With the batched tables' k(g) (tables =
+    (workload, array [state][bin][g])), their error against the oracle's on
+    16 (state, bin) pairs drawn with seed 3 and the table's two corners (the
+    oracle given the lines that can reach each bin); untimed."""
     import tempfile
 
     import numpy as np
@@ -133,6 +142,42 @@ def cpu_baseline(w, points: int, one_thread_bins: int, kappa_gpu=None, k_gpu=Non
             "kappa_max_per_bin": r3(eb.max(axis=1)),
             "kappa_p999_per_bin": r3(np.quantile(eb, 0.999, axis=1)),
             "kg_max_per_bin": r3(ek)}
+        if f32 is not None:
+            k32, kd32 = f32
+            assert np.array_equal(pos, k32 > 0)
+            e = np.zeros(N)
+            e[pos] = np.abs(k32[pos] / kap[pos] - 1.0)
+            eb = e.reshape(-1, ppb)
+            rec["error_vs_oracle_f32"] = {
+                "what": "relative error of the GPU binary32 + compensated step's results against the oracle's",
+                "kappa_max": float(eb.max()),
+                "kappa_p999_worst_bin": float(np.quantile(eb, 0.999, axis=1).max()),
+                "kg_max": float(np.abs(kd32 / kd - 1.0).max()), "bins": int(eb.shape[0])}
+    if tables is not None:
+        tw, tab = tables
+        t_lines, t_grid = tw.lines(), tw.grid()
+        t_ppb = tw.points_per_bin
+        tg, _ = oracle.g_nodes(tw.n_g)
+        n_states, n_bins = tab.shape[0], tab.shape[1]
+        rng = np.random.default_rng(3)
+        pairs = [(0, 0), (n_states - 1, n_bins - 1)] + [
+            (int(a), int(b)) for a, b in zip(rng.choice(n_states, 16, replace=False), rng.choice(n_bins, 16))]
+        worst = 0.0
+        for s_, b in pairs:
+            T, P = tw.states[s_]
+            c = synth_conditions(T, P)
+            j0, j1 = b * t_ppb, min((b + 1) * t_ppb, t_grid["n_points"])
+            lo = t_grid["nu_min"] + j0 * t_grid["dnu"] - t_grid["cutoff"] - 1.0
+            hi = t_grid["nu_min"] + (j1 - 1) * t_grid["dnu"] + t_grid["cutoff"] + 1.0
+            keep = (t_lines["nu"] >= lo) & (t_lines["nu"] <= hi)
+            near = {k: v[keep] for k, v in t_lines.items() if v is not None}
+            ref, _ = oracle.opacity(near, c, t_grid, j0, j1)
+            kr, _ = oracle.kdist_bin(ref, tg)
+            worst = max(worst, float(np.abs(tab[s_, b] / kr - 1.0).max()))
+        rec["error_vs_oracle_tables"] = {
+            "what": "max relative error of the batched binary32 tables' k(g) against the oracle's, "
+                    "on 16 (state, bin) pairs drawn with seed 3 and the table's two corners",
+            "kg_max": worst, "pairs": len(pairs)}
     oracle.set_num_threads(1)
     j0, j1, _, _, evals1, dt1 = run(one_thread_bins * ppb)
     oracle.set_num_threads(cores)
@@ -264,10 +309,10 @@ def bench_tables(hk, torch, ctx, g):
     tm = ctx.timing()
     ctx.set_timing(False)
     evals = ctx.stats()["evals"]
-    return {"workload": w.name, "states": len(states), "precision": "f32_kahan",
-            "value": evals / dt, "unit": "evals/s", "ms_per_call": 1e3 * dt, "evals": evals,
-            "points_per_lane": ctx.get_option("tables_points_per_lane"),
-            "stage_ms": {k: v[0] for k, v in tm.items()}}
+    return ({"workload": w.name, "states": len(states), "precision": "f32_kahan",
+             "value": evals / dt, "unit": "evals/s", "ms_per_call": 1e3 * dt, "evals": evals,
+             "points_per_lane": ctx.get_option("tables_points_per_lane"),
+             "stage_ms": {k: v[0] for k, v in tm.items()}}, (w, out.cpu().numpy()))
 
 
 def bench_surrogate(hk, torch, ctx, n_lines: int = 0, train_steps: int = 0):
@@ -410,9 +455,10 @@ def main(argv=None):
 
     # the binary32 + compensated-sum variant of the same step, reported beside
     # the binary64 headline (its result differs from binary64 by ~1e-6)
-    f32_elapsed, f32_tm = (None, None)
+    f32_elapsed, f32_tm, f32_host = (None, None, None)
     if not a.no_f32:
         f32_elapsed, f32_tm = timed(hk.HK_F32_KAHAN, max(1, a.steps // 2))
+        f32_host = (kappa.cpu().numpy(), k_out.cpu().numpy())
     elapsed, tm = timed(hk.HK_F64, a.steps)
     st = ctx.stats()
     kappa_host, k_host = kappa.cpu().numpy(), k_out.cpu().numpy()  # for the error against the oracle
@@ -475,15 +521,21 @@ def main(argv=None):
             "speedup_vs_f64": (1e3 * elapsed / a.steps) / (1e3 * f32_elapsed / f32_steps)}
     if not a.no_resample:
         rec["resample"] = bench_resample(hk, torch, ctx, kappa, N, ppb, g)
+    tables_host = None
     if not a.no_tables:
-        rec["tables"] = bench_tables(hk, torch, ctx, g)
+        rec["tables"], tables_host = bench_tables(hk, torch, ctx, g)
     if not a.no_stream:
         rec["stream"] = bench_stream(hk, torch, ctx)
     if not a.no_cpu_baseline:
         log("bench: timing the oracle on a sample")
-        rec["cpu_baseline"] = cpu_baseline(w, a.cpu_points, a.cpu_one_thread_bins, kappa_host, k_host)
+        rec["cpu_baseline"] = cpu_baseline(w, a.cpu_points, a.cpu_one_thread_bins, kappa_host, k_host,
+                                           f32_host, tables_host)
         if "error_vs_oracle" in rec["cpu_baseline"]:
             rec["error_vs_oracle"] = rec["cpu_baseline"].pop("error_vs_oracle")
+        if "error_vs_oracle_f32" in rec["cpu_baseline"] and "f32_kahan" in rec:
+            rec["f32_kahan"]["error_vs_oracle"] = rec["cpu_baseline"].pop("error_vs_oracle_f32")
+        if "error_vs_oracle_tables" in rec["cpu_baseline"] and "tables" in rec:
+            rec["tables"]["error_vs_oracle"] = rec["cpu_baseline"].pop("error_vs_oracle_tables")
     if not a.no_surrogate:
         rec["surrogate"] = bench_surrogate(hk, torch, ctx, a.surrogate_lines, a.surrogate_train_steps)
     ctx.close()
