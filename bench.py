@@ -413,7 +413,7 @@ def main(argv=None):
                          "calibration)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(got --gpus %d)" % a.gpus, file=sys.stderr)
         return 2
 

@@ -40,7 +40,7 @@ extern "C" {
 #define HK_EINVAL (-1)        /* invalid argument; nothing was enqueued */
 #define HK_ENOMEM (-2)        /* device or host allocation failed */
 #define HK_EDEVICE (-3)       /* a HIP runtime call failed */
-#define HK_EUNSUPPORTED (-4)  /* valid request this build does not provide */
+#define HK_EUNSUPPORTED (-4)  /* valid request the library does not provide */
 #define HK_ENOTREADY (-5)     /* call order: e.g. opacity before lines */
 
 #define HK_MAX_G 64           /* most g values per k-distribution */

@@ -6,7 +6,7 @@ TEST INFRASTRUCTURE ONLY, like the rest of ``oracle/``: imported by
 The surrogate is not part of the paper's method.  It is a small network that
 stands in for the series evaluation of K(x, y) = H_V(a = y, u = x) (§2.4)
 where a certification against that series shows it accurate enough; the
-series remains the fallback and the judge of its error.  Definitions:
+series remains the fallback and the measure of its error.  Definitions:
 
 * Features: f1 = x/25 - 1, f2 = (log10 y + 1)/3 (the training domain
   x in [0, 50], y in [1e-4, 1e2] maps onto [-1, 1]^2).

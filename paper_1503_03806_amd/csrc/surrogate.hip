@@ -1,6 +1,6 @@
 // surrogate.hip -- training, evaluation and certification of the learned
 // K(x, y) surrogate (not part of the paper's method; the series of §2.4
-// stays its fallback and the judge of its error).
+// stays its fallback and the measure of its error).
 //
 //  * labels: the plain method's K in binary64 (series for x^2+y^2 < 100,
 //    3-node rule beyond, §2.4), turned into the target
