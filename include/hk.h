@@ -244,8 +244,9 @@ int hk_opacity(hk_ctx* ctx, const hk_state* state, const hk_grid* grid,
 #define HK_MAX_CHUNKS 65536
 
 /* The opacity of a line list given in chunks (§3.5: a list shipped as many
- * files whose opacities are added), with the host work and the copy to the
- * device of chunk c+1 overlapping the kernels of chunk c.  The result is
+ * files whose opacities are added), with the host work, the copy to the
+ * device and the preparation of chunk c+1 overlapping the kernels of chunk
+ * c (whose updates of kappa stay in chunk order).  The result is
  * bitwise that of calling, for c = 0 .. n_chunks-1, hk_load_lines(&chunks[c],
  * species) and then hk_opacity(state, grid, precision, kappa, NULL,
  * accumulate || c > 0); only two chunks are on the device at a time.
@@ -257,8 +258,10 @@ int hk_opacity(hk_ctx* ctx, const hk_state* state, const hk_grid* grid,
  *     it is zeroed (accumulate == 0) or left as it is.
  * The host arrays are copied into pinned staging buffers of the context
  * during the call and may be freed on return; the device work is
- * asynchronous, as for hk_opacity.  Copies run on a second non-blocking
- * stream of the context, ordered against ctx's stream by events.
+ * asynchronous, as for hk_opacity.  Copies, preparation and the updates of
+ * kappa run on ctx's stream, the series and the wing kernels on two
+ * non-blocking streams of the context, ordered by events; the call ends on
+ * ctx's stream.
  * Afterwards the loaded list is the last chunk, and hk_stats counts the
  * whole stream. */
 int hk_opacity_stream(hk_ctx* ctx, const hk_lines* chunks, int32_t n_chunks, const hk_species* species,

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <limits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -63,6 +64,29 @@ struct PlanBufs {
     }
 };
 
+// The device state of one opacity pass over one line list: per-line records,
+// tile ranges, the work plans of the wing and the series kernels, the series
+// grid and the binary32 sums.  A context holds two: hk_opacity_stream
+// alternates them between chunks, so that one chunk is prepared while the
+// kernels of the one before it still run.
+struct Lane {
+    DevBuf wing, widx, core, ranges, ranges_core;
+    PlanBufs wplan, cplan;
+    DevBuf kc;
+    DevBuf w32, c32, f32sum, f32comp, f32scale, f32partial;
+    // per-workgroup counts of the points the network evaluated in a
+    // HK_F32_SURROGATE series launch
+    DevBuf sg_used;
+    void release()
+    {
+        for (DevBuf* b : {&wing, &widx, &core, &ranges, &ranges_core, &kc, &w32, &c32, &f32sum, &f32comp,
+                          &f32scale, &f32partial, &sg_used})
+            b->release();
+        wplan.release();
+        cplan.release();
+    }
+};
+
 struct hk_ctx {
     int device = 0;
     hipStream_t own = nullptr;     // created with the context
@@ -79,29 +103,30 @@ struct hk_ctx {
     hk_species species{296.0, 0.0};
     DevBuf lines;  // 8 arrays of n doubles
     // streamed lists: the second device line buffer, pinned host staging
-    // (two buffers of pin_cap doubles), a copy stream and its events, and
+    // (two buffers of pin_cap doubles) and the events of their copies, and
     // the per-chunk evaluation counters of the last hk_opacity_stream call
     DevBuf lines_alt;
     double* pin[2] = {nullptr, nullptr};
     size_t pin_cap = 0;
-    hipStream_t copy = nullptr;
-    hipEvent_t ev_copied[2] = {nullptr, nullptr}, ev_used[2] = {nullptr, nullptr};
+    hipEvent_t ev_copied[2] = {nullptr, nullptr};
     DevBuf st_counts;
     int32_t last_stream_chunks = 0;  // > 0: hk_stats reports that call
     int64_t stream_lines = 0;
-    // per-state records and tile ranges
-    DevBuf wing, widx, core, ranges, ranges_core;
-    DevBuf partial;
-    DevBuf kscratch;
-    // work plans of the wing and the series kernels
-    PlanBufs wplan, cplan;
-    // binary64 series on a second stream, concurrent with the wing: its grid,
-    // the stream and the fork / join events
-    DevBuf kc;
+    // the state of an opacity pass (ln), and the second one that a stream
+    // of chunks alternates with
+    Lane ln, ln_alt;
+    // the series on a second stream, concurrent with the wing: the stream
+    // and the fork / join events
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    // binary32 path: records, Kahan pair, scale
-    DevBuf w32, c32, f32sum, f32comp, f32scale, f32partial;
+    // streamed chunks: the wing's own stream, and per chunk parity the
+    // events of the fork and of the series' and the wing's ends; ev_kappa
+    // marks the last update of kappa (a binary64 wing adds to it)
+    hipStream_t wing_s = nullptr;
+    hipEvent_t ev_cfork[2] = {nullptr, nullptr}, ev_ccore[2] = {nullptr, nullptr},
+               ev_cwing[2] = {nullptr, nullptr}, ev_kappa = nullptr;
+    DevBuf partial;  // evaluation counters of hk_stats
+    DevBuf kscratch;
     bool have_run = false;
     int f64_points_per_lane = 4;  // tile shape of the binary64 opacity kernel (4 or 8)
     int f32_points_per_lane = 2;  // tile shape of the binary32 opacity kernel
@@ -127,10 +152,9 @@ struct hk_ctx {
     // compute copy, training partials, certification errors and mask
     DevBuf sg_theta, sg_m, sg_v, sg_copy, sg_part, sg_ploss, sg_err, sg_mask;
     bool sg_loaded = false, sg_certified = false;
-    // per-workgroup counts of the points the network evaluated in a
-    // HK_F32_SURROGATE series launch, and their running total (element 0 of
-    // sg_used_total) over the calls of one hk_opacity / hk_opacity_stream
-    DevBuf sg_used, sg_used_total;
+    // the running total of the points the network evaluated (element 0),
+    // over the passes of one hk_opacity / hk_opacity_stream call
+    DevBuf sg_used_total;
     double sg_budget = 0.0;  // of the current certification
     // resampling: QR factors of the Chebyshev design matrix for the bin
     // sizes of the last call (main and ragged last bin), and the quadrature
@@ -368,9 +392,26 @@ int check_species(hk_ctx* ctx, const hk_species* sp)
     return HK_OK;
 }
 
-// The value rules of a line list (hk_load_lines); chunk >= 0 names the
-// chunk of a streamed list in the message.  The first offending line, in
-// input order, is reported.
+// Whether line i of L breaks a value rule of hk_load_lines.
+bool line_bad(const hk_lines* L, int64_t i)
+{
+    return !isfin(L->nu[i]) || !(L->nu[i] > 0.0) || !isfin(L->S_ref[i]) || !(L->S_ref[i] >= 0.0) ||
+           !isfin(L->E_lower[i]) || !isfin(L->gamma_air[i]) || !(L->gamma_air[i] >= 0.0) || !isfin(L->n_air[i]) ||
+           (L->gamma_self && (!isfin(L->gamma_self[i]) || !(L->gamma_self[i] >= 0.0))) ||
+           (L->delta && !isfin(L->delta[i])) || (L->A21 && (!isfin(L->A21[i]) || !(L->A21[i] >= 0.0)));
+}
+
+// The shape rules of a line list: a count in range, the required fields there.
+bool lines_shape_ok(const hk_lines* L)
+{
+    return L && L->n >= 0 && L->n <= (int64_t)INT32_MAX &&
+           (L->n == 0 || (L->nu && L->S_ref && L->E_lower && L->gamma_air && L->n_air));
+}
+
+// The rules of a line list (hk_load_lines), with the error of the first
+// offending line, in input order; chunk >= 0 names the chunk of a streamed
+// list in the message.  Used to report: scan_lists tests the rules in the
+// same pass that gathers the bounds.
 int check_lines(hk_ctx* ctx, const hk_lines* L, int64_t chunk)
 {
     char pre[40] = "";
@@ -381,17 +422,10 @@ int check_lines(hk_ctx* ctx, const hk_lines* L, int64_t chunk)
     const int64_t n = L->n;
     if (n > 0 && (!L->nu || !L->S_ref || !L->E_lower || !L->gamma_air || !L->n_air))
         return fail(ctx, HK_EINVAL, "%snu, S_ref, E_lower, gamma_air and n_air are required", pre);
-    auto bad = [L](int64_t i) {
-        return !isfin(L->nu[i]) || !(L->nu[i] > 0.0) || !isfin(L->S_ref[i]) || !(L->S_ref[i] >= 0.0) ||
-               !isfin(L->E_lower[i]) || !isfin(L->gamma_air[i]) || !(L->gamma_air[i] >= 0.0) ||
-               !isfin(L->n_air[i]) ||
-               (L->gamma_self && (!isfin(L->gamma_self[i]) || !(L->gamma_self[i] >= 0.0))) ||
-               (L->delta && !isfin(L->delta[i])) || (L->A21 && (!isfin(L->A21[i]) || !(L->A21[i] >= 0.0)));
-    };
     std::vector<int64_t> first(8, n);
     host_ranges(n, 8, [&](int64_t i0, int64_t i1, int t) {
         for (int64_t i = i0; i < i1; ++i)
-            if (bad(i)) {
+            if (line_bad(L, i)) {
                 first[(size_t)t] = i;
                 return;
             }
@@ -413,45 +447,119 @@ int check_lines(hk_ctx* ctx, const hk_lines* L, int64_t chunk)
     return fail(ctx, HK_EINVAL, "%sA21[%lld] must be finite and >= 0", pre, li);
 }
 
-// Flags and bounds of a validated list.
-ListInfo list_info(const hk_lines* L)
+// One list's result of scan_lists: whether a line breaks a value rule; if
+// none does, the list's flags and bounds and whether nu is non-decreasing.
+struct ListScan {
+    bool bad = false, sorted = true;
+    ListInfo info;
+};
+
+// One pass over the values of lists L[0 .. k) (each of valid shape), by one
+// team of up to 8 host threads that each take the same share of every list:
+// the value rules, the bounds and the order test read each value once.
+std::vector<ListScan> scan_lists(const hk_lines* L, int64_t k)
 {
-    ListInfo li;
-    li.has_self = L->gamma_self != nullptr;
-    li.has_delta = L->delta != nullptr;
-    li.has_A = L->A21 != nullptr;
-    const int64_t n = L->n;
-    if (n == 0) return li;
-    std::vector<ListInfo> part(8);
-    host_ranges(n, 8, [&](int64_t i0, int64_t i1, int t) {
+    struct Part {
+        bool any = false, bad = false, sorted = true;
         ListInfo b;
-        b.min_n_air = L->n_air[i0];
-        b.max_n_air = L->n_air[i0];
+    };
+    int64_t total = 0;
+    for (int64_t c = 0; c < k; ++c) total += L[c].n;
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int T = total < ((int64_t)1 << 16) ? 1 : (int)std::min(8u, hw);
+    std::vector<Part> part((size_t)(k * T));
+    // column by column (each value is still read once), in loops without
+    // branches that the compiler vectorises: a comparison with NaN is false
+    constexpr double kMax = std::numeric_limits<double>::max();
+    auto nonneg = [](const double* v, int64_t i0, int64_t i1, double& mx) {
+        int ok = 1;
+        double m = mx;
         for (int64_t i = i0; i < i1; ++i) {
-            if (L->delta) b.max_abs_delta = std::max(b.max_abs_delta, std::fabs(L->delta[i]));
-            b.max_gamma_air = std::max(b.max_gamma_air, L->gamma_air[i]);
-            b.max_gamma_self = std::max(b.max_gamma_self, L->gamma_self ? L->gamma_self[i] : L->gamma_air[i]);
-            if (L->A21) b.max_A21 = std::max(b.max_A21, L->A21[i]);
-            b.min_n_air = std::min(b.min_n_air, L->n_air[i]);
-            b.max_n_air = std::max(b.max_n_air, L->n_air[i]);
-            b.nu_max = std::max(b.nu_max, L->nu[i]);
+            ok &= (v[i] >= 0.0) & (v[i] <= kMax);
+            m = v[i] > m ? v[i] : m;
         }
-        part[(size_t)t] = b;
-    });
-    bool first = true;
-    for (unsigned k = 0; k < part.size(); ++k) {
-        const ListInfo& b = part[k];
-        if (!(b.nu_max > 0.0)) continue;  // no range of that thread (nu > 0 on every line)
-        li.max_abs_delta = std::max(li.max_abs_delta, b.max_abs_delta);
-        li.max_gamma_air = std::max(li.max_gamma_air, b.max_gamma_air);
-        li.max_gamma_self = std::max(li.max_gamma_self, b.max_gamma_self);
-        li.max_A21 = std::max(li.max_A21, b.max_A21);
-        li.min_n_air = first ? b.min_n_air : std::min(li.min_n_air, b.min_n_air);
-        li.max_n_air = first ? b.max_n_air : std::max(li.max_n_air, b.max_n_air);
-        li.nu_max = std::max(li.nu_max, b.nu_max);
-        first = false;
+        mx = m;
+        return ok;
+    };
+    auto work = [&](int t) {
+        for (int64_t c = 0; c < k; ++c) {
+            const hk_lines* l = &L[c];
+            const int64_t i0 = l->n * t / T, i1 = l->n * (t + 1) / T;
+            if (i0 >= i1) continue;
+            Part& p = part[(size_t)(c * T + t)];
+            ListInfo& b = p.b;
+            p.any = true;
+            int ok = 1, up = 1;
+            double nu_max = 0.0;
+            for (int64_t i = i0; i < i1; ++i) {
+                ok &= (l->nu[i] > 0.0) & (l->nu[i] <= kMax);
+                nu_max = l->nu[i] > nu_max ? l->nu[i] : nu_max;
+            }
+            for (int64_t i = std::max<int64_t>(i0, 1); i < i1; ++i) up &= !(l->nu[i] < l->nu[i - 1]);
+            double s_max = 0.0;
+            ok &= nonneg(l->S_ref, i0, i1, s_max);
+            for (int64_t i = i0; i < i1; ++i) ok &= std::fabs(l->E_lower[i]) <= kMax;
+            ok &= nonneg(l->gamma_air, i0, i1, b.max_gamma_air);
+            double n_lo = l->n_air[i0], n_hi = l->n_air[i0];
+            for (int64_t i = i0; i < i1; ++i) {
+                ok &= std::fabs(l->n_air[i]) <= kMax;
+                n_lo = l->n_air[i] < n_lo ? l->n_air[i] : n_lo;
+                n_hi = l->n_air[i] > n_hi ? l->n_air[i] : n_hi;
+            }
+            if (l->gamma_self)
+                ok &= nonneg(l->gamma_self, i0, i1, b.max_gamma_self);
+            else
+                b.max_gamma_self = b.max_gamma_air;
+            if (l->delta) {
+                double d = 0.0;
+                for (int64_t i = i0; i < i1; ++i) {
+                    const double a = std::fabs(l->delta[i]);
+                    ok &= a <= kMax;
+                    d = a > d ? a : d;
+                }
+                b.max_abs_delta = d;
+            }
+            if (l->A21) ok &= nonneg(l->A21, i0, i1, b.max_A21);
+            b.nu_max = nu_max;
+            b.min_n_air = n_lo;
+            b.max_n_air = n_hi;
+            p.bad = !ok;
+            p.sorted = up;
+        }
+    };
+    if (T == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> th;
+        th.reserve((size_t)T);
+        for (int t = 0; t < T; ++t) th.emplace_back(work, t);
+        for (auto& x : th) x.join();
     }
-    return li;
+    std::vector<ListScan> out((size_t)k);
+    for (int64_t c = 0; c < k; ++c) {
+        ListScan& r = out[(size_t)c];
+        ListInfo& li = r.info;
+        li.has_self = L[c].gamma_self != nullptr;
+        li.has_delta = L[c].delta != nullptr;
+        li.has_A = L[c].A21 != nullptr;
+        bool first = true;
+        for (int t = 0; t < T; ++t) {
+            const Part& p = part[(size_t)(c * T + t)];
+            if (!p.any) continue;
+            r.bad = r.bad || p.bad;
+            r.sorted = r.sorted && p.sorted;
+            const ListInfo& b = p.b;
+            li.max_abs_delta = std::max(li.max_abs_delta, b.max_abs_delta);
+            li.max_gamma_air = std::max(li.max_gamma_air, b.max_gamma_air);
+            li.max_gamma_self = std::max(li.max_gamma_self, b.max_gamma_self);
+            li.max_A21 = std::max(li.max_A21, b.max_A21);
+            li.min_n_air = first ? b.min_n_air : std::min(li.min_n_air, b.min_n_air);
+            li.max_n_air = first ? b.max_n_air : std::max(li.max_n_air, b.max_n_air);
+            li.nu_max = std::max(li.nu_max, b.nu_max);
+            first = false;
+        }
+    }
+    return out;
 }
 
 // The indices of an unordered list sorted by (nu, index) -- the order a
@@ -498,26 +606,13 @@ std::vector<int64_t> line_order(const double* nu, int64_t n)
 // .. 7: nu, S_ref, E_lower, gamma_air, n_air, gamma_self, delta, A21) in
 // ascending (nu, input index) order; absent optional fields are not written
 // (the launches use gamma_air for gamma_self and read no delta or A21).  A
-// list already in non-decreasing nu is copied as it is (a stable sort would
-// not move it).
-void order_lines(const hk_lines* L, double* dst)
+// list already in non-decreasing nu (sorted, as scan_lists found) is copied
+// as it is (a stable sort would not move it).
+void order_lines(const hk_lines* L, bool sorted, double* dst)
 {
     const int64_t n = L->n;
     if (n == 0) return;
     const double* src[8] = {L->nu, L->S_ref, L->E_lower, L->gamma_air, L->n_air, L->gamma_self, L->delta, L->A21};
-    bool sorted = true;
-    {
-        std::vector<char> ok(8, 1);
-        host_ranges(n, 8, [&](int64_t i0, int64_t i1, int t) {
-            const int64_t a = std::max<int64_t>(i0, 1);
-            for (int64_t i = a; i < i1; ++i)
-                if (L->nu[i] < L->nu[i - 1]) {
-                    ok[(size_t)t] = 0;
-                    return;
-                }
-        });
-        for (char c : ok) sorted = sorted && c;
-    }
     std::vector<int64_t> perm;
     if (!sorted) perm = line_order(L->nu, n);
     host_ranges(n, 8, [&](int64_t i0, int64_t i1, int) {
@@ -622,7 +717,7 @@ int wing_stage(hk_ctx* ctx, int precision, int ppl, const void* recs, const Wing
     const int32_t tp = f64 ? opacity_f64_tile_points(ppl) : opacity_f32_tile_points(ppl);
     WorkPlan wp;
     // binary32: segments of whole 256-line compensation blocks
-    if (int rc = make_plan(ctx, ctx->wplan, ranges, n_tiles, n_states, reach, tp, f64 ? 64 : 256, grid, exact, &wp,
+    if (int rc = make_plan(ctx, ctx->ln.wplan, ranges, n_tiles, n_states, reach, tp, f64 ? 64 : 256, grid, exact, &wp,
                            ctx->stream))
         return rc;
     const int64_t n = ctx->n_lines;
@@ -630,17 +725,18 @@ int wing_stage(hk_ctx* ctx, int precision, int ppl, const void* recs, const Wing
     if (f64)
         HK_HIP(ctx, launch_wing_f64(ppl, static_cast<const WingRec*>(recs), idx, ranges, n, n_tiles, n_states, wp,
                                     grid->nu_min, grid->dnu, np, static_cast<double*>(out),
-                                    static_cast<double*>(ctx->wplan.partial.p), accumulate, ctx->wing_edge_paths, ctx->stream),
+                                    static_cast<double*>(ctx->ln.wplan.partial.p), accumulate, ctx->wing_edge_paths, ctx->stream),
                "wing_f64");
     else
         HK_HIP(ctx, launch_wing_f32(ppl, static_cast<const WingRec32*>(recs), idx, ranges, n, n_tiles, n_states, wp,
                                     np, static_cast<float*>(out), comp,
-                                    static_cast<float2*>(ctx->wplan.partial.p), ctx->wing_edge_paths, ctx->stream),
+                                    static_cast<float2*>(ctx->ln.wplan.partial.p), ctx->wing_edge_paths, ctx->stream),
                "wing_f32");
     return HK_OK;
 }
 
-// The second stream and its fork / join events, made on first use.
+// The current lane's second stream and its fork / join events, made on
+// first use.
 int ensure_side(hk_ctx* ctx)
 {
     if (ctx->side) return HK_OK;
@@ -855,38 +951,30 @@ int hk_destroy(hk_ctx* ctx)
     if (!ctx) return HK_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    if (ctx->copy) (void)hipStreamSynchronize(ctx->copy);
+    for (hipStream_t x : {ctx->side, ctx->wing_s})
+        if (x) (void)hipStreamSynchronize(x);
     ctx->lines.release();
     ctx->lines_alt.release();
     ctx->st_counts.release();
-    for (int x = 0; x < 2; ++x) {
+    for (int x = 0; x < 2; ++x)
         if (ctx->pin[x]) (void)hipHostFree(ctx->pin[x]);
-        if (ctx->ev_copied[x]) (void)hipEventDestroy(ctx->ev_copied[x]);
-        if (ctx->ev_used[x]) (void)hipEventDestroy(ctx->ev_used[x]);
-    }
-    if (ctx->copy) (void)hipStreamDestroy(ctx->copy);
-    ctx->wing.release();
-    ctx->widx.release();
-    ctx->core.release();
-    ctx->ranges.release();
-    ctx->ranges_core.release();
+    ctx->ln.release();
+    ctx->ln_alt.release();
+    for (hipEvent_t e : {ctx->ev_copied[0], ctx->ev_copied[1], ctx->ev_cfork[0], ctx->ev_cfork[1], ctx->ev_ccore[0],
+                         ctx->ev_ccore[1], ctx->ev_cwing[0], ctx->ev_cwing[1], ctx->ev_kappa, ctx->ev_fork,
+                         ctx->ev_join})
+        if (e) (void)hipEventDestroy(e);
+    for (hipStream_t x : {ctx->side, ctx->wing_s})
+        if (x) (void)hipStreamDestroy(x);
     ctx->partial.release();
     ctx->kscratch.release();
-    ctx->wplan.release();
-    ctx->cplan.release();
-    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
-    ctx->kc.release();
-    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
-    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
-    if (ctx->side) (void)hipStreamDestroy(ctx->side);
-    for (DevBuf* b : {&ctx->w32, &ctx->c32, &ctx->f32sum, &ctx->f32comp, &ctx->f32scale, &ctx->f32partial})
-        b->release();
     for (DevBuf* b : {&ctx->tb_idx, &ctx->tb_wing, &ctx->tb_core, &ctx->tb_w32, &ctx->tb_c32, &ctx->tb_ranges,
                       &ctx->tb_ranges_c, &ctx->tb_out, &ctx->tb_comp, &ctx->tb_scale, &ctx->tb_kappa,
                       &ctx->tb_counts, &ctx->tb_series, &ctx->tb_prep})
         b->release();
     for (DevBuf* b : {&ctx->sg_theta, &ctx->sg_m, &ctx->sg_v, &ctx->sg_copy, &ctx->sg_part, &ctx->sg_ploss,
-                      &ctx->sg_err, &ctx->sg_mask, &ctx->sg_used, &ctx->sg_used_total, &ctx->rs_Q, &ctx->rs_R, &ctx->rs_Ql, &ctx->rs_Rl, &ctx->rs_quad})
+                      &ctx->sg_err, &ctx->sg_mask, &ctx->sg_used_total, &ctx->rs_Q, &ctx->rs_R, &ctx->rs_Ql, &ctx->rs_Rl,
+                      &ctx->rs_quad})
         b->release();
     for (auto& p : ctx->pending) {
         (void)hipEventDestroy(p.second.first);
@@ -937,8 +1025,8 @@ int bad_line(hk_ctx* ctx, const hk_lines* L, int64_t i, int64_t shown)
 }
 
 // The check of a list in device memory (the rules of check_lines) and its
-// bounds (list_info), by a kernel; one synchronisation.  *sorted: nu is
-// already non-decreasing.
+// bounds (as scan_lists finds them), by a kernel; one synchronisation.
+// *sorted: nu is already non-decreasing.
 int check_lines_device(hk_ctx* ctx, const hk_lines* L, ListInfo* li, bool* sorted)
 {
     const int64_t n = L->n;
@@ -1010,8 +1098,12 @@ int hk_load_lines(hk_ctx* ctx, const hk_lines* L, const hk_species* sp, int line
     if (!L || !sp) return fail(ctx, HK_EINVAL, "lines and species must not be NULL");
     if (L->n < 0 || L->n > (int64_t)INT32_MAX) return fail(ctx, HK_EINVAL, "line count %lld out of range", (long long)L->n);
     if (int rc = check_species(ctx, sp)) return rc;
-    if (!lines_on_device)
-        if (int rc = check_lines(ctx, L, -1)) return rc;
+    ListScan scan;
+    if (!lines_on_device) {
+        if (!lines_shape_ok(L)) return check_lines(ctx, L, -1);
+        scan = scan_lists(L, 1)[0];
+        if (scan.bad) return check_lines(ctx, L, -1);
+    }
     if (int rc = check_ctx(ctx)) return rc;
     const int64_t n = L->n;
     if (lines_on_device && n > 0 && (!L->nu || !L->S_ref || !L->E_lower || !L->gamma_air || !L->n_air))
@@ -1022,16 +1114,8 @@ int hk_load_lines(hk_ctx* ctx, const hk_lines* L, const hk_species* sp, int line
     if (lines_on_device) {
         if (int rc = check_lines_device(ctx, L, &li, &sorted)) return rc;
     } else {
-        li = list_info(L);
-        std::vector<char> ok(8, 1);
-        host_ranges(n, 8, [&](int64_t i0, int64_t i1, int t) {
-            for (int64_t i = std::max<int64_t>(i0, 1); i < i1; ++i)
-                if (L->nu[i] < L->nu[i - 1]) {
-                    ok[(size_t)t] = 0;
-                    return;
-                }
-        });
-        for (char c : ok) sorted = sorted && c;
+        li = scan.info;
+        sorted = scan.sorted;
     }
     HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     ctx->n_lines = n;
@@ -1083,97 +1167,125 @@ int hk_load_lines(hk_ctx* ctx, const hk_lines* L, const hk_species* sp, int line
     return HK_OK;
 }
 
+// One opacity pass between its launch and its finish: the streams of its
+// preparation and finish and of its series, the fork event after which the
+// wing may run and the series' end, and what the wing launch and the finish
+// take.  Its
+// pointers are those of the lane it was launched with.
+struct Flight {
+    int precision = HK_F64;
+    hipStream_t s = nullptr, cs = nullptr;  // preparation and finish; the series
+    hipEvent_t fork = nullptr, core_done = nullptr;
+    double* kappa = nullptr;
+    int accumulate = 0;
+    int32_t np = 0;
+    int64_t n = 0;
+    // the wing
+    int ppl = 0;
+    const void* recs = nullptr;  // WingRec (binary64) or WingRec32
+    const WingIdx* widx = nullptr;
+    const int64_t* ranges = nullptr;
+    int64_t n_tiles = 0;
+    WorkPlan wwp{};
+    void* wpartial = nullptr;
+    double nu_min = 0.0, dnu = 0.0;
+    // the finish: the series grid, the binary32 sums and scale
+    void* series = nullptr;
+    float *fs = nullptr, *fc = nullptr;
+    int32_t* scale = nullptr;
+    // HK_F32_SURROGATE: the series launch's per-workgroup counts
+    const int64_t* sg_used = nullptr;
+    int64_t used_n = 0;
+};
+
 // Binary32 profiles with compensated binary32 sums, after the binary64 line
-// preparation: scale, binary32 records, tile ranges, wing and core kernels,
-// then kappa = (sum + comp) 2^-s in binary64.
-static int opacity_f32(hk_ctx* ctx, const hk_grid* grid, double reach, double reach_core, WingRec* wing,
-                       WingIdx* widx, CoreRec* core,
-                       const int64_t* ranges_c, int64_t n_tiles_c, double* kappa, int accumulate, bool surrogate)
+// preparation: scale, binary32 records, tile ranges and both plans on f->s,
+// then the series on f->cs; the wing and kappa = (sum + comp) 2^-s in
+// binary64 are left to flight_wing and flight_finish.
+static int launch_f32_pass(hk_ctx* ctx, const hk_grid* grid, double reach, double reach_core, WingRec* wing,
+                           WingIdx* widx, CoreRec* core, const int64_t* ranges_c, int64_t n_tiles_c, bool surrogate,
+                           Flight* f)
 {
+    const hipStream_t s = f->s;
     const int64_t n = ctx->n_lines;
     const int32_t np = (int32_t)grid->n_points;
     const size_t nb = (size_t)std::max<int64_t>(n, 1);
     const int32_t nblk = 256;
-    HK_HIP(ctx, ctx->w32.ensure(nb * sizeof(WingRec32)), "allocating binary32 records");
-    HK_HIP(ctx, ctx->c32.ensure(nb * sizeof(CoreRec32)), "allocating binary32 records");
-    HK_HIP(ctx, ctx->f32sum.ensure((size_t)std::max(np, 1) * sizeof(float)), "allocating binary32 sums");
-    HK_HIP(ctx, ctx->f32comp.ensure((size_t)std::max(np, 1) * sizeof(float)), "allocating binary32 sums");
-    HK_HIP(ctx, ctx->f32scale.ensure(sizeof(int32_t)), "allocating the scale");
-    HK_HIP(ctx, ctx->f32partial.ensure((size_t)nblk * sizeof(double)), "allocating the scale");
-    WingRec32* w32 = static_cast<WingRec32*>(ctx->w32.p);
-    CoreRec32* c32 = static_cast<CoreRec32*>(ctx->c32.p);
-    float* fs = static_cast<float*>(ctx->f32sum.p);
-    float* fc = static_cast<float*>(ctx->f32comp.p);
-    int32_t* scale = static_cast<int32_t*>(ctx->f32scale.p);
+    HK_HIP(ctx, ctx->ln.w32.ensure(nb * sizeof(WingRec32)), "allocating binary32 records");
+    HK_HIP(ctx, ctx->ln.c32.ensure(nb * sizeof(CoreRec32)), "allocating binary32 records");
+    HK_HIP(ctx, ctx->ln.f32sum.ensure((size_t)std::max(np, 1) * sizeof(float)), "allocating binary32 sums");
+    HK_HIP(ctx, ctx->ln.f32comp.ensure((size_t)std::max(np, 1) * sizeof(float)), "allocating binary32 sums");
+    HK_HIP(ctx, ctx->ln.f32scale.ensure(sizeof(int32_t)), "allocating the scale");
+    HK_HIP(ctx, ctx->ln.f32partial.ensure((size_t)nblk * sizeof(double)), "allocating the scale");
+    WingRec32* w32 = static_cast<WingRec32*>(ctx->ln.w32.p);
+    CoreRec32* c32 = static_cast<CoreRec32*>(ctx->ln.c32.p);
+    int32_t* scale = static_cast<int32_t*>(ctx->ln.f32scale.p);
     const int ppl = ctx->f32_points_per_lane;
     const int32_t tp = opacity_f32_tile_points(ppl);
     const int64_t n_tiles = ((int64_t)np + tp - 1) / tp;
-    HK_HIP(ctx, ctx->ranges.ensure((size_t)std::max<int64_t>(n_tiles, 1) * 2 * sizeof(int64_t)),
+    HK_HIP(ctx, ctx->ln.ranges.ensure((size_t)std::max<int64_t>(n_tiles, 1) * 2 * sizeof(int64_t)),
            "allocating tile ranges");
-    int64_t* ranges = static_cast<int64_t*>(ctx->ranges.p);
+    int64_t* ranges = static_cast<int64_t*>(ctx->ln.ranges.p);
     {
-        StageTimer tm(ctx, HK_STAGE_LINE_PREP);
+        StageTimer tm(ctx, HK_STAGE_LINE_PREP, s);
         if (n > 0) {
-            HK_HIP(ctx, launch_f32_scale(wing, core, n, static_cast<double*>(ctx->f32partial.p), nblk, scale,
-                                         ctx->stream),
+            HK_HIP(ctx, launch_f32_scale(wing, core, n, static_cast<double*>(ctx->ln.f32partial.p), nblk, scale, s),
                    "f32_scale");
-            HK_HIP(ctx, launch_line_prep_f32(wing, widx, core, n, grid->nu_min, grid->dnu, scale, w32, c32,
-                                             ctx->stream),
+            HK_HIP(ctx, launch_line_prep_f32(wing, widx, core, n, grid->nu_min, grid->dnu, scale, w32, c32, s),
                    "line_prep_f32");
         } else {
-            HK_HIP(ctx, launch_zero(scale, sizeof(int32_t), ctx->stream), "zero");
+            HK_HIP(ctx, launch_zero(scale, sizeof(int32_t), s), "zero");
         }
         HK_HIP(ctx, launch_tile_ranges(static_cast<double*>(ctx->lines.p), n, n_tiles, tp, grid->nu_min,
-                                       grid->dnu, np, reach, ranges, ctx->stream),
+                                       grid->dnu, np, reach, ranges, s),
                "tile_ranges");
         tm.stop();
     }
-    // as in binary64: both plans, then the series on the second stream into
-    // its own grid while the wing runs; the finish adds it
-    if (int rc = ensure_side(ctx)) return rc;
-    HK_HIP(ctx, ctx->kc.ensure((size_t)std::max(np, 1) * sizeof(double)), "allocating the series grid");
-    float* series = static_cast<float*>(ctx->kc.p);
+    // as in binary64: both plans, then the series on its stream into its own
+    // grid while the wing runs; the finish adds it
+    HK_HIP(ctx, ctx->ln.kc.ensure((size_t)std::max(np, 1) * sizeof(double)), "allocating the series grid");
     WorkPlan wwp, cwp;
     {
-        StageTimer tm(ctx, HK_STAGE_LINE_PREP);
+        StageTimer tm(ctx, HK_STAGE_LINE_PREP, s);
         // segments of whole 256-line compensation blocks for the wing
-        if (int rc = make_plan(ctx, ctx->wplan, ranges, n_tiles, 1, &reach, tp, 256, grid, false, &wwp, ctx->stream))
+        if (int rc = make_plan(ctx, ctx->ln.wplan, ranges, n_tiles, 1, &reach, tp, 256, grid, false, &wwp, s))
             return rc;
-        if (int rc = make_plan(ctx, ctx->cplan, ranges_c, n_tiles_c, 1, &reach_core, core_f32_tile_points(), 64,
-                               grid, false, &cwp, ctx->stream))
+        if (int rc = make_plan(ctx, ctx->ln.cplan, ranges_c, n_tiles_c, 1, &reach_core, core_f32_tile_points(), 64,
+                               grid, false, &cwp, s))
             return rc;
         tm.stop();
     }
-    HK_HIP(ctx, hipEventRecord(ctx->ev_fork, ctx->stream), "hipEventRecord");
-    HK_HIP(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0), "hipStreamWaitEvent");
+    HK_HIP(ctx, hipEventRecord(f->fork, s), "hipEventRecord");
+    HK_HIP(ctx, hipStreamWaitEvent(f->cs, f->fork, 0), "hipStreamWaitEvent");
+    const int64_t used_n = surrogate ? plan_blocks(cwp.launch_items) : 0;
     {
-        StageTimer tm(ctx, HK_STAGE_CORE, ctx->side);
-        const int64_t used_n = surrogate ? plan_blocks(cwp.launch_items) : 0;
+        StageTimer tm(ctx, HK_STAGE_CORE, f->cs);
         if (surrogate)
-            HK_HIP(ctx, ctx->sg_used.ensure((size_t)std::max<int64_t>(used_n, 1) * sizeof(int64_t)),
+            HK_HIP(ctx, ctx->ln.sg_used.ensure((size_t)std::max<int64_t>(used_n, 1) * sizeof(int64_t)),
                    "allocating surrogate counters");
-        HK_HIP(ctx, launch_core_f32(widx, c32, ranges_c, n, n_tiles_c, 1, cwp, np, series,
-                                    static_cast<float*>(ctx->cplan.partial.p), surrogate ? ctx->sg_copy.p : nullptr,
+        HK_HIP(ctx, launch_core_f32(widx, c32, ranges_c, n, n_tiles_c, 1, cwp, np, static_cast<float*>(ctx->ln.kc.p),
+                                    static_cast<float*>(ctx->ln.cplan.partial.p), surrogate ? ctx->sg_copy.p : nullptr,
                                     surrogate ? static_cast<const uint8_t*>(ctx->sg_mask.p) : nullptr,
-                                    surrogate ? static_cast<int64_t*>(ctx->sg_used.p) : nullptr, used_n, ctx->side),
+                                    surrogate ? static_cast<int64_t*>(ctx->ln.sg_used.p) : nullptr, used_n,
+                                    f->cs),
                "core_f32");
-        if (surrogate && n_tiles_c > 0)
-            HK_HIP(ctx, launch_sum_counts(static_cast<int64_t*>(ctx->sg_used.p), used_n,
-                                          static_cast<int64_t*>(ctx->sg_used_total.p), 1, ctx->side),
-                   "sum_counts");
         tm.stop();
     }
-    HK_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->side), "hipEventRecord");
-    {
-        StageTimer tm(ctx, HK_STAGE_OPACITY);
-        HK_HIP(ctx, launch_wing_f32(ppl, w32, widx, ranges, n, n_tiles, 1, wwp, np, fs, fc,
-                                    static_cast<float2*>(ctx->wplan.partial.p), ctx->wing_edge_paths, ctx->stream),
-               "wing_f32");
-        tm.stop();
+    HK_HIP(ctx, hipEventRecord(f->core_done, f->cs), "hipEventRecord");
+    f->ppl = ppl;
+    f->recs = w32;
+    f->ranges = ranges;
+    f->n_tiles = n_tiles;
+    f->wwp = wwp;
+    f->wpartial = ctx->ln.wplan.partial.p;
+    f->series = ctx->ln.kc.p;
+    f->fs = static_cast<float*>(ctx->ln.f32sum.p);
+    f->fc = static_cast<float*>(ctx->ln.f32comp.p);
+    f->scale = scale;
+    if (surrogate && n_tiles_c > 0) {
+        f->sg_used = static_cast<const int64_t*>(ctx->ln.sg_used.p);
+        f->used_n = used_n;
     }
-    HK_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "hipStreamWaitEvent");
-    HK_HIP(ctx, launch_f32_finish(fs, fc, series, scale, np, kappa, accumulate, ctx->stream), "f32_finish");
-    ctx->have_run = true;
     return HK_OK;
 }
 
@@ -1190,94 +1302,163 @@ static int check_opacity_args(hk_ctx* ctx, const hk_state* st, const hk_grid* gr
     return HK_OK;
 }
 
-// The launch sequence of one state over the loaded list (line preparation,
-// tile ranges, wing and core kernels), on ctx->stream.
-static int opacity_run(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precision, double* kappa,
-                       int accumulate)
+// Launches one state over the loaded list, with ctx->ln's buffers: line
+// preparation, tile ranges and both work plans on s, then (event fork) the
+// series on stream cs (event core_done at its end).  The wing (flight_wing)
+// and the finish (flight_finish) follow.
+static int opacity_launch(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precision, double* kappa,
+                          int accumulate, hipStream_t s, hipStream_t cs, hipEvent_t fork, hipEvent_t core_done,
+                          Flight* f)
 {
     const int64_t n = ctx->n_lines;
     const int32_t np = (int32_t)grid->n_points;
+    *f = Flight{};
+    f->precision = precision;
+    f->s = s;
+    f->cs = cs;
+    f->fork = fork;
+    f->core_done = core_done;
+    f->kappa = kappa;
+    f->accumulate = accumulate;
+    f->np = np;
+    f->n = n;
+    f->nu_min = grid->nu_min;
+    f->dnu = grid->dnu;
 
     const PrepParams pp = prep_params(ctx, st, grid);
     ctx->last_P = st->P;
 
     const size_t nb = (size_t)std::max<int64_t>(n, 1);
-    HK_HIP(ctx, ctx->wing.ensure(nb * sizeof(WingRec)), "allocating line records");
-    HK_HIP(ctx, ctx->widx.ensure(nb * sizeof(WingIdx)), "allocating line records");
-    HK_HIP(ctx, ctx->core.ensure(nb * sizeof(CoreRec)), "allocating line records");
+    HK_HIP(ctx, ctx->ln.wing.ensure(nb * sizeof(WingRec)), "allocating line records");
+    HK_HIP(ctx, ctx->ln.widx.ensure(nb * sizeof(WingIdx)), "allocating line records");
+    HK_HIP(ctx, ctx->ln.core.ensure(nb * sizeof(CoreRec)), "allocating line records");
     const int ppl = ctx->f64_points_per_lane;
     const int32_t tp = opacity_f64_tile_points(ppl);
     const int64_t n_tiles = ((int64_t)np + tp - 1) / tp;
     const int32_t tpc = precision == HK_F64 ? core_f64_tile_points() : core_f32_tile_points();
     const int64_t n_tiles_c = ((int64_t)np + tpc - 1) / tpc;
-    HK_HIP(ctx, ctx->ranges.ensure((size_t)std::max<int64_t>(n_tiles, 1) * 2 * sizeof(int64_t)),
+    HK_HIP(ctx, ctx->ln.ranges.ensure((size_t)std::max<int64_t>(n_tiles, 1) * 2 * sizeof(int64_t)),
            "allocating tile ranges");
-    HK_HIP(ctx, ctx->ranges_core.ensure((size_t)std::max<int64_t>(n_tiles_c, 1) * 2 * sizeof(int64_t)),
+    HK_HIP(ctx, ctx->ln.ranges_core.ensure((size_t)std::max<int64_t>(n_tiles_c, 1) * 2 * sizeof(int64_t)),
            "allocating tile ranges");
 
     const LinesDev L = lines_dev(ctx);
-    WingRec* wing = static_cast<WingRec*>(ctx->wing.p);
-    WingIdx* widx = static_cast<WingIdx*>(ctx->widx.p);
-    CoreRec* core = static_cast<CoreRec*>(ctx->core.p);
-    int64_t* ranges = static_cast<int64_t*>(ctx->ranges.p);
+    WingRec* wing = static_cast<WingRec*>(ctx->ln.wing.p);
+    WingIdx* widx = static_cast<WingIdx*>(ctx->ln.widx.p);
+    CoreRec* core = static_cast<CoreRec*>(ctx->ln.core.p);
+    int64_t* ranges = static_cast<int64_t*>(ctx->ln.ranges.p);
     const double reach = wing_reach(ctx, st, grid);
     const double reach_core = core_reach(ctx, st, grid, pp);
-    int64_t* ranges_c = static_cast<int64_t*>(ctx->ranges_core.p);
+    int64_t* ranges_c = static_cast<int64_t*>(ctx->ln.ranges_core.p);
+    f->widx = widx;
 
     {
-        StageTimer tm(ctx, HK_STAGE_LINE_PREP);
-        HK_HIP(ctx, launch_line_prep_f64(L, pp, wing, widx, core, ctx->stream), "line_prep_f64");
-        HK_HIP(ctx, launch_tile_ranges(L.nu, n, n_tiles, tp, grid->nu_min, grid->dnu, np, reach, ranges,
-                                       ctx->stream),
-               "tile_ranges");
+        StageTimer tm(ctx, HK_STAGE_LINE_PREP, s);
+        HK_HIP(ctx, launch_line_prep_f64(L, pp, wing, widx, core, s), "line_prep_f64");
+        if (precision == HK_F64)  // binary32 wing tiles have their own ranges
+            HK_HIP(ctx, launch_tile_ranges(L.nu, n, n_tiles, tp, grid->nu_min, grid->dnu, np, reach, ranges, s),
+                   "tile_ranges");
         HK_HIP(ctx, launch_tile_ranges(L.nu, n, n_tiles_c, tpc, grid->nu_min, grid->dnu, np, reach_core,
-                                       ranges_c, ctx->stream),
+                                       ranges_c, s),
                "tile_ranges");
         tm.stop();
     }
     if (precision != HK_F64)
-        return opacity_f32(ctx, grid, reach, reach_core, wing, widx, core, ranges_c, n_tiles_c, kappa, accumulate,
-                           precision == HK_F32_SURROGATE);
+        return launch_f32_pass(ctx, grid, reach, reach_core, wing, widx, core, ranges_c, n_tiles_c,
+                               precision == HK_F32_SURROGATE, f);
     // The series runs on a second stream, concurrent with the wing (each
     // leaves the VALU idle ~20% of the time, which the other fills), into a
-    // grid of its own; the join adds it to the wing's: kappa_j = wing_j +
+    // grid of its own; the finish adds it to the wing's: kappa_j = wing_j +
     // series_j, the same single addition as adding in place.  Both work plans
-    // are made first, on ctx's stream, so that only the two big kernels run
-    // side by side (small kernels queued behind a running one wait for CUs).
-    if (int rc = ensure_side(ctx)) return rc;
-    HK_HIP(ctx, ctx->kc.ensure((size_t)std::max(np, 1) * sizeof(double)), "allocating the series grid");
+    // are made first, on s, so that only the two big kernels run side by
+    // side (small kernels queued behind a running one wait for CUs).
+    HK_HIP(ctx, ctx->ln.kc.ensure((size_t)std::max(np, 1) * sizeof(double)), "allocating the series grid");
     WorkPlan wwp, cwp;
     {
-        StageTimer tm(ctx, HK_STAGE_LINE_PREP);
-        if (int rc = make_plan(ctx, ctx->wplan, ranges, n_tiles, 1, &reach, tp, 64, grid, false, &wwp, ctx->stream))
+        StageTimer tm(ctx, HK_STAGE_LINE_PREP, s);
+        if (int rc = make_plan(ctx, ctx->ln.wplan, ranges, n_tiles, 1, &reach, tp, 64, grid, false, &wwp, s))
             return rc;
-        if (int rc = make_plan(ctx, ctx->cplan, ranges_c, n_tiles_c, 1, &reach_core, tpc, 64, grid, false, &cwp,
-                               ctx->stream))
+        if (int rc = make_plan(ctx, ctx->ln.cplan, ranges_c, n_tiles_c, 1, &reach_core, tpc, 64, grid, false, &cwp,
+                               s))
             return rc;
         tm.stop();
     }
-    HK_HIP(ctx, hipEventRecord(ctx->ev_fork, ctx->stream), "hipEventRecord");
-    HK_HIP(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0), "hipStreamWaitEvent");
+    HK_HIP(ctx, hipEventRecord(fork, s), "hipEventRecord");
+    HK_HIP(ctx, hipStreamWaitEvent(f->cs, fork, 0), "hipStreamWaitEvent");
     {
-        StageTimer tm(ctx, HK_STAGE_CORE, ctx->side);
+        StageTimer tm(ctx, HK_STAGE_CORE, f->cs);
         HK_HIP(ctx, launch_core_f64(wing, widx, core, ranges_c, n, n_tiles_c, 1, cwp, grid->nu_min, grid->dnu, np,
-                                    static_cast<double*>(ctx->kc.p), static_cast<double*>(ctx->cplan.partial.p),
-                                    ctx->side),
+                                    static_cast<double*>(ctx->ln.kc.p), static_cast<double*>(ctx->ln.cplan.partial.p),
+                                    f->cs),
                "core_f64");
         tm.stop();
     }
-    HK_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->side), "hipEventRecord");
-    {
-        StageTimer tm(ctx, HK_STAGE_OPACITY);
-        HK_HIP(ctx, launch_wing_f64(ppl, wing, widx, ranges, n, n_tiles, 1, wwp, grid->nu_min, grid->dnu, np, kappa,
-                                    static_cast<double*>(ctx->wplan.partial.p), accumulate ? 1 : 0, ctx->wing_edge_paths, ctx->stream),
+    HK_HIP(ctx, hipEventRecord(core_done, f->cs), "hipEventRecord");
+    f->ppl = ppl;
+    f->recs = wing;
+    f->ranges = ranges;
+    f->n_tiles = n_tiles;
+    f->wwp = wwp;
+    f->wpartial = ctx->ln.wplan.partial.p;
+    f->series = ctx->ln.kc.p;
+    return HK_OK;
+}
+
+// The wing of a launched pass, on w: f->s's own stream, or another one
+// (which then waits for the fork, and for kappa_ready when not null: a
+// binary64 wing adds to kappa; wing_done is recorded at its end).
+static int flight_wing(hk_ctx* ctx, const Flight& f, hipStream_t w, hipEvent_t kappa_ready, hipEvent_t wing_done)
+{
+    if (w != f.s) HK_HIP(ctx, hipStreamWaitEvent(w, f.fork, 0), "hipStreamWaitEvent");
+    if (kappa_ready) HK_HIP(ctx, hipStreamWaitEvent(w, kappa_ready, 0), "hipStreamWaitEvent");
+    StageTimer tm(ctx, HK_STAGE_OPACITY, w);
+    if (f.precision == HK_F64)
+        HK_HIP(ctx, launch_wing_f64(f.ppl, static_cast<const WingRec*>(f.recs), f.widx, f.ranges, f.n, f.n_tiles, 1,
+                                    f.wwp, f.nu_min, f.dnu, f.np, f.kappa, static_cast<double*>(f.wpartial),
+                                    f.accumulate ? 1 : 0, ctx->wing_edge_paths, w),
                "wing_f64");
-        tm.stop();
-    }
-    HK_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "hipStreamWaitEvent");
-    HK_HIP(ctx, launch_add_f64(kappa, static_cast<const double*>(ctx->kc.p), np, ctx->stream), "add_f64");
+    else
+        HK_HIP(ctx, launch_wing_f32(f.ppl, static_cast<const WingRec32*>(f.recs), f.widx, f.ranges, f.n, f.n_tiles,
+                                    1, f.wwp, f.np, f.fs, f.fc, static_cast<float2*>(f.wpartial),
+                                    ctx->wing_edge_paths, w),
+               "wing_f32");
+    tm.stop();
+    if (w != f.s) HK_HIP(ctx, hipEventRecord(wing_done, w), "hipEventRecord");
+    return HK_OK;
+}
+
+// The finish of a pass on f.s, after the series (and the wing, when it ran
+// on another stream: wing_done): the surrogate's count added to the running
+// total, then kappa from the binary32 sums, or the series grid added to it.
+static int flight_finish(hk_ctx* ctx, const Flight& f, hipEvent_t wing_done)
+{
+    if (wing_done) HK_HIP(ctx, hipStreamWaitEvent(f.s, wing_done, 0), "hipStreamWaitEvent");
+    HK_HIP(ctx, hipStreamWaitEvent(f.s, f.core_done, 0), "hipStreamWaitEvent");
+    if (f.sg_used)
+        HK_HIP(ctx, launch_sum_counts(f.sg_used, f.used_n, static_cast<int64_t*>(ctx->sg_used_total.p), 1, f.s),
+               "sum_counts");
+    if (f.precision == HK_F64)
+        HK_HIP(ctx, launch_add_f64(f.kappa, static_cast<const double*>(f.series), f.np, f.s), "add_f64");
+    else
+        HK_HIP(ctx, launch_f32_finish(f.fs, f.fc, static_cast<const float*>(f.series), f.scale, f.np, f.kappa,
+                                      f.accumulate, f.s),
+               "f32_finish");
     ctx->have_run = true;
     return HK_OK;
+}
+
+// One state over the loaded list on ctx's stream: the launch, the wing on
+// the same stream, the finish.
+static int opacity_run(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precision, double* kappa,
+                       int accumulate)
+{
+    if (int rc = ensure_side(ctx)) return rc;  // makes ev_fork and ev_join
+    Flight f;
+    if (int rc = opacity_launch(ctx, st, grid, precision, kappa, accumulate, ctx->stream, ctx->side, ctx->ev_fork,
+                                ctx->ev_join, &f))
+        return rc;
+    if (int rc = flight_wing(ctx, f, ctx->stream, nullptr, nullptr)) return rc;
+    return flight_finish(ctx, f, nullptr);
 }
 
 int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precision, void* kappa,
@@ -1306,12 +1487,14 @@ int hk_opacity(hk_ctx* ctx, const hk_state* st, const hk_grid* grid, int precisi
 static int reserve_line_buffers(hk_ctx* ctx, int64_t n, int precision)
 {
     const size_t nb = (size_t)std::max<int64_t>(n, 1);
-    HK_HIP(ctx, ctx->wing.ensure(nb * sizeof(WingRec)), "allocating line records");
-    HK_HIP(ctx, ctx->widx.ensure(nb * sizeof(WingIdx)), "allocating line records");
-    HK_HIP(ctx, ctx->core.ensure(nb * sizeof(CoreRec)), "allocating line records");
-    if (precision != HK_F64) {
-        HK_HIP(ctx, ctx->w32.ensure(nb * sizeof(WingRec32)), "allocating binary32 records");
-        HK_HIP(ctx, ctx->c32.ensure(nb * sizeof(CoreRec32)), "allocating binary32 records");
+    for (Lane* l : {&ctx->ln, &ctx->ln_alt}) {
+        HK_HIP(ctx, l->wing.ensure(nb * sizeof(WingRec)), "allocating line records");
+        HK_HIP(ctx, l->widx.ensure(nb * sizeof(WingIdx)), "allocating line records");
+        HK_HIP(ctx, l->core.ensure(nb * sizeof(CoreRec)), "allocating line records");
+        if (precision != HK_F64) {
+            HK_HIP(ctx, l->w32.ensure(nb * sizeof(WingRec32)), "allocating binary32 records");
+            HK_HIP(ctx, l->c32.ensure(nb * sizeof(CoreRec32)), "allocating binary32 records");
+        }
     }
     HK_HIP(ctx, ctx->lines.ensure((size_t)8 * nb * sizeof(double)), "allocating the line list");
     HK_HIP(ctx, ctx->lines_alt.ensure((size_t)8 * nb * sizeof(double)), "allocating the line list");
@@ -1320,15 +1503,11 @@ static int reserve_line_buffers(hk_ctx* ctx, int64_t n, int precision)
 
 static int stream_resources(hk_ctx* ctx, size_t pin_doubles)
 {
-    if (!ctx->copy) HK_HIP(ctx, hipStreamCreateWithFlags(&ctx->copy, hipStreamNonBlocking), "hipStreamCreate");
-    for (int x = 0; x < 2; ++x) {
-        if (!ctx->ev_copied[x])
-            HK_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_copied[x], hipEventDisableTiming), "hipEventCreate");
-        if (!ctx->ev_used[x])
-            HK_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_used[x], hipEventDisableTiming), "hipEventCreate");
-    }
-    // copies of an earlier call read the staging buffers: let them finish
-    HK_HIP(ctx, hipStreamSynchronize(ctx->copy), "hipStreamSynchronize");
+    if (int rc = ensure_side(ctx)) return rc;
+    if (!ctx->wing_s) HK_HIP(ctx, hipStreamCreateWithFlags(&ctx->wing_s, hipStreamNonBlocking), "hipStreamCreate");
+    for (hipEvent_t* e : {&ctx->ev_copied[0], &ctx->ev_copied[1], &ctx->ev_cfork[0], &ctx->ev_cfork[1],
+                          &ctx->ev_ccore[0], &ctx->ev_ccore[1], &ctx->ev_cwing[0], &ctx->ev_cwing[1], &ctx->ev_kappa})
+        if (!*e) HK_HIP(ctx, hipEventCreateWithFlags(e, hipEventDisableTiming), "hipEventCreate");
     if (pin_doubles > ctx->pin_cap) {
         for (int x = 0; x < 2; ++x) {
             if (ctx->pin[x]) (void)hipHostFree(ctx->pin[x]);
@@ -1351,12 +1530,17 @@ int hk_opacity_stream(hk_ctx* ctx, const hk_lines* chunks, int32_t n_chunks, con
         return fail(ctx, HK_EINVAL, "n_chunks = %d out of [0, %d]", n_chunks, HK_MAX_CHUNKS);
     if (n_chunks > 0 && !chunks) return fail(ctx, HK_EINVAL, "chunks is NULL");
     if (int rc = check_species(ctx, sp)) return rc;
-    // every chunk is checked before any work is enqueued
+    // every chunk is checked before any work is enqueued: the shapes, then
+    // one pass over the values of the chunks before the first misshapen one;
+    // errors are reported in chunk order
+    int32_t n_shaped = 0;
+    while (n_shaped < n_chunks && lines_shape_ok(&chunks[n_shaped])) ++n_shaped;
+    const std::vector<ListScan> scan = scan_lists(chunks, n_shaped);
     std::vector<ListInfo> info((size_t)n_chunks);
     int64_t n_max = 0, n_total = 0;
     for (int32_t c = 0; c < n_chunks; ++c) {
-        if (int rc = check_lines(ctx, &chunks[c], c)) return rc;
-        info[(size_t)c] = list_info(&chunks[c]);
+        if (c == n_shaped || scan[(size_t)c].bad) return check_lines(ctx, &chunks[c], c);
+        info[(size_t)c] = scan[(size_t)c].info;
         if (precision != HK_F64 && !(max_cutoff(info[(size_t)c], sp->T_ref, st, grid) / grid->dnu < 8388608.0))
             return fail(ctx, HK_EINVAL, "chunk %d: binary32 profiles need (largest cutoff)/dnu < 2^23 (got %g)", c,
                         max_cutoff(info[(size_t)c], sp->T_ref, st, grid) / grid->dnu);
@@ -1385,30 +1569,70 @@ int hk_opacity_stream(hk_ctx* ctx, const hk_lines* chunks, int32_t n_chunks, con
     HK_HIP(ctx, ctx->st_counts.ensure((size_t)kCountBlocks * 3 * (size_t)n_chunks * sizeof(int64_t)),
            "allocating counters");
     ctx->species = *sp;
-    for (int32_t c = 0; c < n_chunks; ++c) {
+    // Chunk c is copied and prepared on ctx's stream S with lane c & 1 (device
+    // line buffer, records, plans and sums); its series and its wing run on
+    // the two other streams (which trade roles from chunk to chunk); its
+    // finish (the update of kappa) is enqueued on S after the preparation of
+    // chunk c+1, so that chunk c+1 is copied and prepared, and its kernels
+    // start, while the kernels of chunk c still run.  The finishes, on S, keep kappa's
+    // updates in chunk order (a binary64 wing, which adds to kappa, waits
+    // for the previous finish), so the result is that of the chunks one at
+    // a time; S waits for both streams in each finish, so the call ends on
+    // it.  Lane c & 1 is free again when the finish of chunk c-2, enqueued
+    // on S before the copy of chunk c, has run.
+    Flight prev;
+    auto finish = [&](int32_t c, const Flight& f) -> int {
+        if (int rc = flight_finish(ctx, f, ctx->ev_cwing[c & 1])) return rc;
+        HK_HIP(ctx, launch_eval_counts(f.widx, f.n,
+                                       static_cast<int64_t*>(ctx->st_counts.p) + (size_t)kCountBlocks * 3 * c,
+                                       kCountBlocks, ctx->stream),
+               "eval_counts");
+        return HK_OK;
+    };
+    auto one_chunk = [&](int32_t c) -> int {
         const int x = c & 1;
         const int64_t n = chunks[c].n;
         // staging x last held chunk c-2: its copy must be done before it is rewritten
         if (c >= 2) HK_HIP(ctx, hipEventSynchronize(ctx->ev_copied[x]), "hipEventSynchronize");
-        order_lines(&chunks[c], ctx->pin[x]);
-        if (c > 0) std::swap(ctx->lines, ctx->lines_alt);  // device buffer x holds chunk c
-        // device buffer x last held chunk c-2: wait until its kernels are done
-        if (c >= 2) HK_HIP(ctx, hipStreamWaitEvent(ctx->copy, ctx->ev_used[x], 0), "hipStreamWaitEvent");
+        order_lines(&chunks[c], scan[(size_t)c].sorted, ctx->pin[x]);
+        if (c > 0) {  // device buffer and lane x hold chunk c
+            std::swap(ctx->lines, ctx->lines_alt);
+            std::swap(ctx->ln, ctx->ln_alt);
+        }
         for (const auto& f : present_fields(&chunks[c]))
             HK_HIP(ctx, hipMemcpyAsync(static_cast<double*>(ctx->lines.p) + f.first * n, ctx->pin[x] + f.first * n,
-                                       (size_t)f.second * n * sizeof(double), hipMemcpyHostToDevice, ctx->copy),
+                                       (size_t)f.second * n * sizeof(double), hipMemcpyHostToDevice, ctx->stream),
                    "copying a chunk");
-        HK_HIP(ctx, hipEventRecord(ctx->ev_copied[x], ctx->copy), "hipEventRecord");
-        HK_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_copied[x], 0), "hipStreamWaitEvent");
+        HK_HIP(ctx, hipEventRecord(ctx->ev_copied[x], ctx->stream), "hipEventRecord");
         ctx->n_lines = n;
         ctx->li = info[(size_t)c];
         ctx->lines_loaded = true;
-        if (int rc = opacity_run(ctx, st, grid, precision, kappa, (accumulate || c > 0) ? 1 : 0)) return rc;
-        HK_HIP(ctx, launch_eval_counts(static_cast<WingIdx*>(ctx->widx.p), n,
-                                       static_cast<int64_t*>(ctx->st_counts.p) + (size_t)kCountBlocks * 3 * c,
-                                       kCountBlocks, ctx->stream),
-               "eval_counts");
-        HK_HIP(ctx, hipEventRecord(ctx->ev_used[x], ctx->stream), "hipEventRecord");
+        // the series and the wing trade streams from chunk to chunk, so that
+        // the wing of chunk c+1 need not wait for that of chunk c to end
+        const hipStream_t ws = x ? ctx->side : ctx->wing_s, cs = x ? ctx->wing_s : ctx->side;
+        Flight f;
+        if (int rc = opacity_launch(ctx, st, grid, precision, kappa, (accumulate || c > 0) ? 1 : 0, ctx->stream,
+                                    cs, ctx->ev_cfork[x], ctx->ev_ccore[x], &f))
+            return rc;
+        hipEvent_t kappa_ready = nullptr;
+        if (c > 0) {
+            if (int rc = finish(c - 1, prev)) return rc;
+            if (precision == HK_F64) {
+                HK_HIP(ctx, hipEventRecord(ctx->ev_kappa, ctx->stream), "hipEventRecord");
+                kappa_ready = ctx->ev_kappa;
+            }
+        }
+        if (int rc = flight_wing(ctx, f, ws, kappa_ready, ctx->ev_cwing[x])) return rc;
+        prev = f;
+        return HK_OK;
+    };
+    int rc = HK_OK;
+    for (int32_t c = 0; c < n_chunks && rc == HK_OK; ++c) rc = one_chunk(c);
+    if (rc == HK_OK) rc = finish(n_chunks - 1, prev);
+    if (rc != HK_OK) {  // nothing may still run on the other streams
+        (void)hipStreamSynchronize(ctx->wing_s);
+        (void)hipStreamSynchronize(ctx->side);
+        return rc;
     }
     ctx->last_stream_chunks = n_chunks;
     ctx->stream_lines = n_total;
@@ -1529,7 +1753,7 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
         HK_HIP(ctx, ctx->tb_comp.ensure((size_t)B * np * sizeof(float)), "allocating batch sums");
         HK_HIP(ctx, ctx->tb_scale.ensure((size_t)B * sizeof(int32_t)), "allocating batch scales");
         HK_HIP(ctx, ctx->tb_kappa.ensure((size_t)B * np * sizeof(double)), "allocating the opacities");
-        HK_HIP(ctx, ctx->f32partial.ensure((size_t)256 * B * sizeof(double)), "allocating the scale");
+        HK_HIP(ctx, ctx->ln.f32partial.ensure((size_t)256 * B * sizeof(double)), "allocating the scale");
     }
     // per-state constants and reaches of a batch, on the device
     HK_HIP(ctx, ctx->tb_prep.ensure((size_t)B * (sizeof(PrepParams) + 2 * sizeof(double))), "allocating batch constants");
@@ -1600,7 +1824,7 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
                 // the binary32 records straight from the line list: the
                 // states' scales from a pass over the peaks, then the records
                 int32_t* scale = static_cast<int32_t*>(ctx->tb_scale.p);
-                HK_HIP(ctx, launch_f32_scale_lines(L, d_pps, static_cast<double*>(ctx->f32partial.p), 256, scale,
+                HK_HIP(ctx, launch_f32_scale_lines(L, d_pps, static_cast<double*>(ctx->ln.f32partial.p), 256, scale,
                                                    ctx->stream, nbat),
                        "f32_scale");
                 HK_HIP(ctx, launch_line_prep_f32_direct(L, d_pps, nbat, grid->nu_min, grid->dnu, scale, tidx,
@@ -1631,10 +1855,10 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
                                            d_reach, nbat),
                    "tile_ranges");
             // the plans of the whole batch, read back to size the launches
-            if (int rc = make_plan(ctx, ctx->wplan, rw, n_tiles, nbat, reach.data(), tp, f64 ? 64 : 256, grid, true,
+            if (int rc = make_plan(ctx, ctx->ln.wplan, rw, n_tiles, nbat, reach.data(), tp, f64 ? 64 : 256, grid, true,
                                    &wwp, ctx->stream, d_reach))
                 return rc;
-            if (int rc = make_plan(ctx, ctx->cplan, rc_all, n_tiles_c, nbat, reach_c.data(), tpc, 64, grid, true, &cwp,
+            if (int rc = make_plan(ctx, ctx->ln.cplan, rc_all, n_tiles_c, nbat, reach_c.data(), tpc, 64, grid, true, &cwp,
                                    ctx->stream, d_reach_c))
                 return rc;
             tm.stop();
@@ -1656,12 +1880,12 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
                 HK_HIP(ctx, launch_core_f64(static_cast<WingRec*>(ctx->tb_wing.p), tidx,
                                             static_cast<CoreRec*>(ctx->tb_core.p), rc_all, n, n_tiles_c, nbat, cwp,
                                             grid->nu_min, grid->dnu, np, static_cast<double*>(ctx->tb_series.p),
-                                            static_cast<double*>(ctx->cplan.partial.p), cs),
+                                            static_cast<double*>(ctx->ln.cplan.partial.p), cs),
                        "core_f64");
             else
                 HK_HIP(ctx, launch_core_f32(tidx, static_cast<CoreRec32*>(ctx->tb_c32.p), rc_all, n, n_tiles_c, nbat,
                                             cwp, np, static_cast<float*>(ctx->tb_series.p),
-                                            static_cast<float*>(ctx->cplan.partial.p), nullptr, nullptr, nullptr,
+                                            static_cast<float*>(ctx->ln.cplan.partial.p), nullptr, nullptr, nullptr,
                                             0, cs),
                        "core_f32");
             tm.stop();
@@ -1672,13 +1896,13 @@ int hk_tables(hk_ctx* ctx, const hk_state* states, int32_t n_states, const hk_gr
             if (f64)
                 HK_HIP(ctx, launch_wing_f64(ppl, static_cast<WingRec*>(ctx->tb_wing.p), tidx, rw, n, n_tiles, nbat, wwp,
                                             grid->nu_min, grid->dnu, np, static_cast<double*>(ctx->tb_out.p),
-                                            static_cast<double*>(ctx->wplan.partial.p), 0, ctx->wing_edge_paths, ctx->stream),
+                                            static_cast<double*>(ctx->ln.wplan.partial.p), 0, ctx->wing_edge_paths, ctx->stream),
                        "wing_f64");
             else
                 HK_HIP(ctx, launch_wing_f32(ppl, static_cast<WingRec32*>(ctx->tb_w32.p), tidx, rw, n, n_tiles, nbat,
                                             wwp, np, static_cast<float*>(ctx->tb_out.p),
                                             static_cast<float*>(ctx->tb_comp.p),
-                                            static_cast<float2*>(ctx->wplan.partial.p), ctx->wing_edge_paths, ctx->stream),
+                                            static_cast<float2*>(ctx->ln.wplan.partial.p), ctx->wing_edge_paths, ctx->stream),
                        "wing_f32");
             tm.stop();
         }
@@ -2080,7 +2304,7 @@ int hk_stats(hk_ctx* ctx, hk_run_stats* out)
     HK_HIP(ctx, ctx->partial.ensure((size_t)kCountBlocks * 3 * sizeof(int64_t)), "allocating counters");
     if (out->n_lines > 0) {
         if (!tables && !streamed)
-            HK_HIP(ctx, launch_eval_counts(static_cast<WingIdx*>(ctx->widx.p), ctx->n_lines,
+            HK_HIP(ctx, launch_eval_counts(static_cast<WingIdx*>(ctx->ln.widx.p), ctx->n_lines,
                                            static_cast<int64_t*>(ctx->partial.p), kCountBlocks, ctx->stream),
                    "eval_counts");
         std::vector<int64_t> h((size_t)nblk * 3);
@@ -2173,10 +2397,10 @@ int hk_get_option(hk_ctx* ctx, const char* name, int64_t* value)
     else if (std::strcmp(name, "wing_items") == 0 || std::strcmp(name, "wing_segment_lines") == 0) {
         // the last wing stage's plan (for its first state), read back
         *value = 0;
-        if (!ctx->wplan.total.p) return HK_OK;
+        if (!ctx->ln.wplan.total.p) return HK_OK;
         HK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
         const bool items = name[5] == 'i';
-        HK_HIP(ctx, hipMemcpyAsync(value, items ? ctx->wplan.total.p : ctx->wplan.seg.p, sizeof *value,
+        HK_HIP(ctx, hipMemcpyAsync(value, items ? ctx->ln.wplan.total.p : ctx->ln.wplan.seg.p, sizeof *value,
                                    hipMemcpyDeviceToHost, ctx->stream),
                "reading the work plan");
         HK_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");

@@ -122,6 +122,61 @@ def test_load_lines_rejects_bad_lists():
     assert "context" in str(e.value)
 
 
+def test_load_lines_scan_of_large_lists():
+    """Lists long enough for the threaded one-pass check: every value rule,
+    also of the optional fields, and the first offending line in input order
+    when several lines, in different threads' shares, break rules."""
+    import synth
+    base = synth.line_list(200_000, 3000.0, seed=4)
+    base = dict(base, gamma_self=base["gamma_air"] * 1.5, delta=np.full(200_000, -0.002),
+                A21=np.full(200_000, 10.0))
+    cases = [("n_air", 150_000, np.inf, "n_air[150000]"), ("E_lower", 3, np.nan, "E_lower[3]"),
+             ("gamma_self", 199_999, -1e-9, "gamma_self[199999]"), ("delta", 77_777, np.nan, "delta[77777]"),
+             ("A21", 123_456, np.inf, "A21[123456]"), ("nu", 100_000, -np.inf, "nu[100000]")]
+    for k, i, v, msg in cases:
+        L = {f: a.copy() for f, a in base.items()}
+        L[k][i] = v
+        with pytest.raises(hk.HKError) as e:
+            hk.hk_load_lines(None, L, {"mass_amu": 18.0})
+        assert e.value.code == hk.HK_EINVAL and msg in str(e.value), (k, str(e.value))
+    L = {f: a.copy() for f, a in base.items()}
+    L["S_ref"][190_000] = -1.0
+    L["gamma_air"][60_000] = np.nan
+    with pytest.raises(hk.HKError) as e:
+        hk.hk_load_lines(None, L, {"mass_amu": 18.0})
+    assert "gamma_air[60000]" in str(e.value)
+    # a valid list, unordered or not, reaches the context check
+    for L in (base, {f: a[::-1].copy() for f, a in base.items()}):
+        with pytest.raises(hk.HKError) as e:
+            hk.hk_load_lines(None, L, {"mass_amu": 18.0})
+        assert "context" in str(e.value)
+
+
+def test_opacity_stream_reports_chunks_in_order():
+    """Every chunk is checked before any work: the first failing chunk in
+    chunk order decides the error, be it a value or a shape rule."""
+    good = [_chunk(5, 0), _chunk(70_000, 1), _chunk(7, 2)]
+    bad_value = {k: v.copy() for k, v in good[1].items()}
+    bad_value["gamma_air"][69_000] = -1.0
+    missing = hk.hk_lines(5, None, None, None, None, None, None, None, None)
+    sp = hk.hk_species(296.0, 18.0)
+    st, gr = hk._state(GOOD_STATE), hk._grid(GOOD_GRID)
+
+    def rc(chunks):
+        pairs = [(c, None) if isinstance(c, hk.hk_lines) else hk._lines(c) for c in chunks]
+        arr = (hk.hk_lines * len(pairs))(*[m for m, _ in pairs])
+        return hk.lib().hk_opacity_stream(None, arr, len(pairs), C.byref(sp), C.byref(st), C.byref(gr),
+                                          hk.HK_F64, 1, 0)
+
+    assert rc([good[0], bad_value, missing]) == hk.HK_EINVAL
+    assert hk.hk_last_error(None).startswith("chunk 1: gamma_air[69000]")
+    assert rc([good[0], missing, bad_value]) == hk.HK_EINVAL
+    assert hk.hk_last_error(None).startswith("chunk 1: nu, S_ref")
+    assert rc([good[0], good[1], missing]) == hk.HK_EINVAL
+    assert hk.hk_last_error(None).startswith("chunk 2: nu, S_ref")
+    assert rc(good) == hk.HK_EINVAL and "context" in hk.hk_last_error(None)
+
+
 def test_null_context_calls():
     for f in ("hk_sync", "hk_set_stream"):
         fn = getattr(hk.lib(), f)

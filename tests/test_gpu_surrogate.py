@@ -230,6 +230,31 @@ def test_opacity_with_surrogate_matches_oracle(ctx, trained):
     assert np.abs(kd / oracle.kdist(ref, w.points_per_bin, g) - 1).max() <= 1e-4
 
 
+def test_surrogate_stream_is_bitwise_the_chunk_sequence(ctx, trained):
+    """A streamed list with the surrogate: consecutive chunks run on two
+    streams, their updates of kappa and of the network's evaluation count in
+    chunk order; bitwise the chunks loaded and accumulated one call at a
+    time, with the same count."""
+    w = synth.WORKLOADS["lines1e4_grid3e5"]
+    lines, cond, grid = w.lines(), w.conditions(), w.grid()
+    st = {k: cond[k] for k in ("T", "P", "P_self", "q_ratio")}
+    order = np.argsort(lines["nu"], kind="stable")
+    cuts = np.linspace(0, len(order), 8).astype(int)
+    chunks = [{k: v[order[a:b]] for k, v in lines.items()} for a, b in zip(cuts[:-1], cuts[1:])]
+    seq = torch.empty(grid["n_points"], dtype=torch.float64, device="cuda")
+    used = 0
+    for i, c in enumerate(chunks):
+        ctx.load_lines(c, cond["mass_amu"], cond["T0"])
+        ctx.opacity(st, grid, hk.HK_F32_SURROGATE, out=seq, accumulate=i > 0)
+        used += ctx.stats()["evals_surrogate"]
+    got = ctx.opacity_stream(chunks, cond["mass_amu"], st, grid, hk.HK_F32_SURROGATE, T_ref=cond["T0"])
+    torch.cuda.synchronize()
+    s = ctx.stats()
+    say("surrogate stream: %d chunks, network evaluations %d" % (len(chunks), s["evals_surrogate"]))
+    assert np.array_equal(got.cpu().numpy().view(np.uint64), seq.cpu().numpy().view(np.uint64))
+    assert s["evals_surrogate"] == used > 0
+
+
 def test_surrogate_gain_is_reported(ctx, trained):
     """What the trained network gains over the method without it: the
     binary32 path with and without the surrogate on 1e6 lines, 3e6 points,
