@@ -120,16 +120,26 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
             code[threadIdx.x] = cw;
         }
         __syncthreads();
-        // runs of consecutive lines on the same path are looped over
-        // without leaving the path (keeps the partial sums in place)
-        auto path_of = [&](int kk) -> uint32_t {
-            return ((uint32_t)__builtin_amdgcn_readfirstlane((int)code[kk]) >> (8 * wave)) & 0xffu;
-        };
+        // Maximal runs of consecutive lines on one path: a run's end is found
+        // once, 64 codes at a time by a wavefront ballot, and the 1-node and
+        // 3-node runs are looped over with nothing but a counter (the
+        // partial sums stay in place)
         int k = 0;
         while (k < cnt) {
-            const uint32_t path = path_of(k);
+            const uint32_t path = ((uint32_t)__builtin_amdgcn_readfirstlane((int)code[k]) >> (8 * wave)) & 0xffu;
+            int kend = k + 1;
+            for (;;) {
+                const int kk = kend + lane;
+                const uint32_t ck = (code[min(kk, kTL - 1)] >> (8 * wave)) & 0xffu;
+                const uint64_t m = __ballot(kk >= cnt || ck != path);
+                if (m) {
+                    kend += (int)__builtin_ctzll(m);
+                    break;
+                }
+                kend += 64;
+            }
             if (path == kSkip) {
-                ++k;
+                k = kend;
                 continue;
             }
             if (path == kGH1) {
@@ -142,7 +152,7 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
                         part[p] = fmaf(Lg, rcpf(fmaf(dv, dv, G2)), part[p]);
                     }
                     ++k;
-                } while (k < cnt && path_of(k) == kGH1);
+                } while (k < kend);
                 continue;
             }
             if (path == kGH3) {
@@ -166,7 +176,7 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
                         part[p + 1] = fmaf(cp * mm[0], nn[1], part[p + 1]);
                     }
                     ++k;
-                } while (k < cnt && path_of(k) == kGH3);
+                } while (k < kend);
                 continue;
             }
             if (path == kGH1Edge || path == kGH3Edge) {

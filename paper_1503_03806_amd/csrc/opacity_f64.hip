@@ -168,24 +168,27 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
             }
         }
         __syncthreads();
-        // runs of consecutive lines on the same path are looped over
-        // without leaving the path (keeps the accumulators in place)
-        // (the codes of four consecutive lines are read at once)
-        const uint32_t* codes = reinterpret_cast<const uint32_t*>(code[wave]);
-        uint32_t cword = 0;
-        int cbase = -4;
-        auto path_of = [&](int kk) -> uint32_t {
-            if ((kk & ~3) != cbase) {
-                cbase = kk & ~3;
-                cword = (uint32_t)__builtin_amdgcn_readfirstlane((int)codes[kk >> 2]);
-            }
-            return (cword >> (8 * (kk & 3))) & 0xffu;
-        };
+        // Maximal runs of consecutive lines on one path: a run's end is found
+        // once, 64 codes at a time by a wavefront ballot, and the 1-node and
+        // 3-node runs are looped over with nothing but a counter (few scalar
+        // instructions per line beside the path's own work; the accumulators
+        // stay in place)
+        const uint8_t* cw = code[wave];
         int k = 0;
         while (k < cnt) {
-            const uint32_t path = path_of(k);
+            const uint32_t path = (uint32_t)__builtin_amdgcn_readfirstlane((int)cw[k]);
+            int kend = k + 1;
+            for (;;) {
+                const int kk = kend + lane;
+                const uint64_t m = __ballot(kk >= cnt || cw[min(kk, kTL - 1)] != path);
+                if (m) {
+                    kend += (int)__builtin_ctzll(m);
+                    break;
+                }
+                kend += 64;
+            }
             if (path == kSkip) {
-                ++k;
+                k = kend;
                 continue;
             }
             if (path == kGH1) {
@@ -208,7 +211,7 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                         acc[p + 3] = fma(c23, D[2], acc[p + 3]);
                     }
                     ++k;
-                } while (k < cnt && path_of(k) == kGH1);
+                } while (k < kend);
                 continue;
             }
             if (path == kGH3) {
@@ -229,7 +232,7 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                         acc[p + 3] = fma(c23 * mm[2], nn[3], acc[p + 3]);
                     }
                     ++k;
-                } while (k < cnt && path_of(k) == kGH3);
+                } while (k < kend);
                 continue;
             }
             if (path == kGH1Edge || path == kGH3Edge) {
@@ -396,7 +399,7 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
 // and n points apart; a cut item writes its slot of partial (kTilePoints
 // values).
 template <int kP>
-__global__ __launch_bounds__(64 * kWaves) void wing_f64_kernel(
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kP == 4 ? 7 : 1))) void wing_f64_kernel(
     const WingRec* __restrict__ wing, const WingIdx* __restrict__ idx, const int64_t* __restrict__ ranges,
     int64_t n_lines, int64_t n_tiles, int32_t n_states, WorkPlan wp, double nu_min, double dnu, int32_t n,
     double* __restrict__ kappa, double* __restrict__ partial, int accumulate, int edges)
