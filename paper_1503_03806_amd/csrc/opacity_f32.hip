@@ -180,115 +180,121 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
                 continue;
             }
             if (path == kGH1Edge || path == kGH3Edge) {
-                // the rule's own sequence, points outside the window left as
-                // they are: the general path's sequence for these points, bit
-                // for bit, without evaluating the other rule
-                const float fjc = fjct[k];
-                const float du = tile[k].du, fu = tile[k].fu, Lg = tile[k].Lg, G2 = tile[k].G2;
-                const int32_t wlo = tidx[k].wlo, whi = tidx[k].whi;
-                if (path == kGH1Edge) {
-#pragma unroll
-                    for (int p = 0; p < kP; ++p) {
-                        const int32_t j = run0 + lane + 64 * p;
-                        const float dv = fmaf(fj[p] - fjc, du, -fu);
-                        const float acc = fmaf(Lg, rcpf(fmaf(dv, dv, G2)), part[p]);
-                        part[p] = (j >= wlo && j <= whi) ? acc : part[p];
+                do {
+                    // the rule's own sequence, points outside the window left as
+                    // they are: the general path's sequence for these points, bit
+                    // for bit, without evaluating the other rule
+                    const float fjc = fjct[k];
+                    const float du = tile[k].du, fu = tile[k].fu, Lg = tile[k].Lg, G2 = tile[k].G2;
+                    const int32_t wlo = tidx[k].wlo, whi = tidx[k].whi;
+                    if (path == kGH1Edge) {
+    #pragma unroll
+                        for (int p = 0; p < kP; ++p) {
+                            const int32_t j = run0 + lane + 64 * p;
+                            const float dv = fmaf(fj[p] - fjc, du, -fu);
+                            const float acc = fmaf(Lg, rcpf(fmaf(dv, dv, G2)), part[p]);
+                            part[p] = (j >= wlo && j <= whi) ? acc : part[p];
+                        }
+                    } else {
+                        const float M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Cn = tile[k].Cn;
+                        const float Bn = fmaf(2.0f, G2, -1.5f);
+    #pragma unroll
+                        for (int p = 0; p < kP; p += 2) {
+                            float nn[2], mm[2];
+    #pragma unroll
+                            for (int e = 0; e < 2; ++e) {
+                                const float dv = fmaf(fj[p + e] - fjc, du, -fu);
+                                const float q = dv * dv;
+                                nn[e] = fmaf(q, q + Bn, Cn);
+                                mm[e] = fmaf(fmaf(q + M2, q, M1), q, M0);
+                            }
+                            const float cp = rcpf(mm[0] * mm[1]) * Lg;
+    #pragma unroll
+                            for (int e = 0; e < 2; ++e) {
+                                const int32_t j = run0 + lane + 64 * (p + e);
+                                const float acc = fmaf(cp * mm[1 - e], nn[e], part[p + e]);
+                                part[p + e] = (j >= wlo && j <= whi) ? acc : part[p + e];
+                            }
+                        }
                     }
-                } else {
+                    ++k;
+                } while (k < kend);
+                continue;
+            }
+            if (path == kGH3Core) {
+                do {
+                    // the general path's sequence for these points: pairs without
+                    // series points as on the 3-node path, the others one by one,
+                    // the series points left as they are
+                    const float fjc = fjct[k];
+                    const float du = tile[k].du, fu = tile[k].fu, Lg = tile[k].Lg;
                     const float M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Cn = tile[k].Cn;
-                    const float Bn = fmaf(2.0f, G2, -1.5f);
-#pragma unroll
+                    const float Bn = fmaf(2.0f, tile[k].G2, -1.5f);
+                    const int32_t clo = tidx[k].clo, chi = tidx[k].chi;
+    #pragma unroll
                     for (int p = 0; p < kP; p += 2) {
                         float nn[2], mm[2];
-#pragma unroll
+                        bool cpt[2];
+    #pragma unroll
                         for (int e = 0; e < 2; ++e) {
+                            const int32_t j = run0 + lane + 64 * (p + e);
+                            cpt[e] = j >= clo && j <= chi;
                             const float dv = fmaf(fj[p + e] - fjc, du, -fu);
                             const float q = dv * dv;
                             nn[e] = fmaf(q, q + Bn, Cn);
                             mm[e] = fmaf(fmaf(q + M2, q, M1), q, M0);
                         }
+                        const bool paired = !cpt[0] && !cpt[1];
                         const float cp = rcpf(mm[0] * mm[1]) * Lg;
-#pragma unroll
+    #pragma unroll
                         for (int e = 0; e < 2; ++e) {
-                            const int32_t j = run0 + lane + 64 * (p + e);
-                            const float acc = fmaf(cp * mm[1 - e], nn[e], part[p + e]);
-                            part[p + e] = (j >= wlo && j <= whi) ? acc : part[p + e];
+                            const float acc = paired ? fmaf(cp * mm[1 - e], nn[e], part[p + e])
+                                                     : fmaf(Lg, nn[e] * rcpf(mm[e]), part[p + e]);
+                            part[p + e] = cpt[e] ? part[p + e] : acc;
                         }
                     }
-                }
-                ++k;
+                    ++k;
+                } while (k < kend);
                 continue;
             }
-            if (path == kGH3Core) {
-                // the general path's sequence for these points: pairs without
-                // series points as on the 3-node path, the others one by one,
-                // the series points left as they are
+            do {
                 const float fjc = fjct[k];
-                const float du = tile[k].du, fu = tile[k].fu, Lg = tile[k].Lg;
+                const float du = tile[k].du, fu = tile[k].fu, Lg = tile[k].Lg, G2 = tile[k].G2;
                 const float M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Cn = tile[k].Cn;
-                const float Bn = fmaf(2.0f, tile[k].G2, -1.5f);
+                const float Bn = fmaf(2.0f, G2, -1.5f);
+                const int32_t wlo = tidx[k].wlo, whi = tidx[k].whi;
+                const int32_t g3lo = tidx[k].g3lo, g3hi = tidx[k].g3hi;
                 const int32_t clo = tidx[k].clo, chi = tidx[k].chi;
-#pragma unroll
+    #pragma unroll
                 for (int p = 0; p < kP; p += 2) {
-                    float nn[2], mm[2];
-                    bool cpt[2];
-#pragma unroll
+                    float nn[2], mm[2], v1[2];
+                    bool take[2], one[2], core_pt[2];
+    #pragma unroll
                     for (int e = 0; e < 2; ++e) {
                         const int32_t j = run0 + lane + 64 * (p + e);
-                        cpt[e] = j >= clo && j <= chi;
+                        core_pt[e] = j >= clo && j <= chi;
+                        take[e] = j >= wlo && j <= whi && !core_pt[e];
+                        one[e] = j < g3lo || j > g3hi;
                         const float dv = fmaf(fj[p + e] - fjc, du, -fu);
                         const float q = dv * dv;
+                        v1[e] = rcpf(fmaf(dv, dv, G2));
                         nn[e] = fmaf(q, q + Bn, Cn);
                         mm[e] = fmaf(fmaf(q + M2, q, M1), q, M0);
                     }
-                    const bool paired = !cpt[0] && !cpt[1];
+                    // two 3-node points outside the core, both on the grid: the
+                    // sequence of the 3-node path above
+                    const bool paired = !one[0] && !one[1] && !core_pt[0] && !core_pt[1] &&
+                                        run0 + lane + 64 * (p + 1) < n;
                     const float cp = rcpf(mm[0] * mm[1]) * Lg;
-#pragma unroll
+    #pragma unroll
                     for (int e = 0; e < 2; ++e) {
                         const float acc = paired ? fmaf(cp * mm[1 - e], nn[e], part[p + e])
-                                                 : fmaf(Lg, nn[e] * rcpf(mm[e]), part[p + e]);
-                        part[p + e] = cpt[e] ? part[p + e] : acc;
+                                                 : fmaf(Lg, one[e] ? v1[e] : nn[e] * rcpf(mm[e]), part[p + e]);
+                        part[p + e] = take[e] ? acc : part[p + e];
                     }
                 }
                 ++k;
-                continue;
-            }
-            const float fjc = fjct[k];
-            const float du = tile[k].du, fu = tile[k].fu, Lg = tile[k].Lg, G2 = tile[k].G2;
-            const float M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Cn = tile[k].Cn;
-            const float Bn = fmaf(2.0f, G2, -1.5f);
-            const int32_t wlo = tidx[k].wlo, whi = tidx[k].whi;
-            const int32_t g3lo = tidx[k].g3lo, g3hi = tidx[k].g3hi;
-            const int32_t clo = tidx[k].clo, chi = tidx[k].chi;
-#pragma unroll
-            for (int p = 0; p < kP; p += 2) {
-                float nn[2], mm[2], v1[2];
-                bool take[2], one[2], core_pt[2];
-#pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    const int32_t j = run0 + lane + 64 * (p + e);
-                    core_pt[e] = j >= clo && j <= chi;
-                    take[e] = j >= wlo && j <= whi && !core_pt[e];
-                    one[e] = j < g3lo || j > g3hi;
-                    const float dv = fmaf(fj[p + e] - fjc, du, -fu);
-                    const float q = dv * dv;
-                    v1[e] = rcpf(fmaf(dv, dv, G2));
-                    nn[e] = fmaf(q, q + Bn, Cn);
-                    mm[e] = fmaf(fmaf(q + M2, q, M1), q, M0);
-                }
-                // two 3-node points outside the core, both on the grid: the
-                // sequence of the 3-node path above
-                const bool paired = !one[0] && !one[1] && !core_pt[0] && !core_pt[1] &&
-                                    run0 + lane + 64 * (p + 1) < n;
-                const float cp = rcpf(mm[0] * mm[1]) * Lg;
-#pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    const float acc = paired ? fmaf(cp * mm[1 - e], nn[e], part[p + e])
-                                             : fmaf(Lg, one[e] ? v1[e] : nn[e] * rcpf(mm[e]), part[p + e]);
-                    part[p + e] = take[e] ? acc : part[p + e];
-                }
-            }
-            ++k;
+            } while (k < kend);
         }
 #pragma unroll
         for (int p = 0; p < kP; ++p) {
@@ -316,7 +322,7 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
 // One workgroup per work item (a grid tile of a state, or its lines in one
 // segment); the layout of the binary64 kernel.
 template <int kP>
-__global__ __launch_bounds__(64 * kWaves) void wing_f32_kernel(
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kP == 4 ? 7 : 1))) void wing_f32_kernel(
     const WingRec32* __restrict__ wing, const WingIdx* __restrict__ idx, const int64_t* __restrict__ ranges,
     int64_t n_lines, int64_t n_tiles, int32_t n_states, WorkPlan wp, int32_t n, float* __restrict__ sum,
     float* __restrict__ comp, float2* __restrict__ partial, int edges)

@@ -236,152 +236,158 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                 continue;
             }
             if (path == kGH1Edge || path == kGH3Edge) {
-                // the rule's own sequence, points outside the window adding
-                // zero: the general path's sequence for these groups, bit
-                // for bit, without evaluating the other rule
-                const uint32_t wb = (uint32_t)__builtin_amdgcn_readfirstlane((int)bnd[k].x);
-                const int32_t wlo = bnd_lo(wb), whi = bnd_hi(wb);
-                const double nu0 = tile[k].nu0, Lg = tile[k].Lg;
-                bool take[kP];
-#pragma unroll
-                for (int p = 0; p < kP; ++p) {
-                    const int32_t jr = rel0 + lane + 64 * p;
-                    take[p] = jr >= wlo && jr <= whi;
-                }
-                if (path == kGH1Edge) {
-                    const double G2 = tile[k].G2;
-#pragma unroll
-                    for (int p = 0; p < kP; p += 4) {
-                        double D[4];
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const double dv = nuj[p + e] - nu0;
-                            D[e] = fma(dv, dv, G2);
+                do {
+                    // the rule's own sequence, points outside the window adding
+                    // zero: the general path's sequence for these groups, bit
+                    // for bit, without evaluating the other rule
+                    const uint32_t wb = (uint32_t)__builtin_amdgcn_readfirstlane((int)bnd[k].x);
+                    const int32_t wlo = bnd_lo(wb), whi = bnd_hi(wb);
+                    const double nu0 = tile[k].nu0, Lg = tile[k].Lg;
+                    bool take[kP];
+    #pragma unroll
+                    for (int p = 0; p < kP; ++p) {
+                        const int32_t jr = rel0 + lane + 64 * p;
+                        take[p] = jr >= wlo && jr <= whi;
+                    }
+                    if (path == kGH1Edge) {
+                        const double G2 = tile[k].G2;
+    #pragma unroll
+                        for (int p = 0; p < kP; p += 4) {
+                            double D[4];
+    #pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const double dv = nuj[p + e] - nu0;
+                                D[e] = fma(dv, dv, G2);
+                            }
+                            const double P01 = D[0] * D[1], P23 = D[2] * D[3];
+                            const double c = qrcp(P01 * P23) * Lg;
+                            const double c01 = c * P23, c23 = c * P01;
+                            acc[p] = fma(take[p] ? c01 : 0.0, D[1], acc[p]);
+                            acc[p + 1] = fma(take[p + 1] ? c01 : 0.0, D[0], acc[p + 1]);
+                            acc[p + 2] = fma(take[p + 2] ? c23 : 0.0, D[3], acc[p + 2]);
+                            acc[p + 3] = fma(take[p + 3] ? c23 : 0.0, D[2], acc[p + 3]);
                         }
-                        const double P01 = D[0] * D[1], P23 = D[2] * D[3];
-                        const double c = qrcp(P01 * P23) * Lg;
-                        const double c01 = c * P23, c23 = c * P01;
-                        acc[p] = fma(take[p] ? c01 : 0.0, D[1], acc[p]);
-                        acc[p + 1] = fma(take[p + 1] ? c01 : 0.0, D[0], acc[p + 1]);
-                        acc[p + 2] = fma(take[p + 2] ? c23 : 0.0, D[3], acc[p + 2]);
-                        acc[p + 3] = fma(take[p + 3] ? c23 : 0.0, D[2], acc[p + 3]);
+                    } else {
+                        const double M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Bn = tile[k].Bn,
+                                     Cn = tile[k].Cn;
+    #pragma unroll
+                        for (int p = 0; p < kP; p += 4) {
+                            double nn[4], mm[4];
+    #pragma unroll
+                            for (int e = 0; e < 4; ++e) gh3_nm(nuj[p + e] - nu0, M2, M1, M0, Bn, Cn, nn[e], mm[e]);
+                            const double P01 = mm[0] * mm[1], P23 = mm[2] * mm[3];
+                            const double c = qrcp(P01 * P23) * Lg;
+                            const double c01 = c * P23, c23 = c * P01;
+                            const double x0 = c01 * mm[1], x1 = c01 * mm[0], x2 = c23 * mm[3], x3 = c23 * mm[2];
+                            acc[p] = fma(take[p] ? x0 : 0.0, nn[0], acc[p]);
+                            acc[p + 1] = fma(take[p + 1] ? x1 : 0.0, nn[1], acc[p + 1]);
+                            acc[p + 2] = fma(take[p + 2] ? x2 : 0.0, nn[2], acc[p + 2]);
+                            acc[p + 3] = fma(take[p + 3] ? x3 : 0.0, nn[3], acc[p + 3]);
+                        }
                     }
-                } else {
-                    const double M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Bn = tile[k].Bn,
-                                 Cn = tile[k].Cn;
-#pragma unroll
-                    for (int p = 0; p < kP; p += 4) {
-                        double nn[4], mm[4];
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) gh3_nm(nuj[p + e] - nu0, M2, M1, M0, Bn, Cn, nn[e], mm[e]);
-                        const double P01 = mm[0] * mm[1], P23 = mm[2] * mm[3];
-                        const double c = qrcp(P01 * P23) * Lg;
-                        const double c01 = c * P23, c23 = c * P01;
-                        const double x0 = c01 * mm[1], x1 = c01 * mm[0], x2 = c23 * mm[3], x3 = c23 * mm[2];
-                        acc[p] = fma(take[p] ? x0 : 0.0, nn[0], acc[p]);
-                        acc[p + 1] = fma(take[p + 1] ? x1 : 0.0, nn[1], acc[p + 1]);
-                        acc[p + 2] = fma(take[p + 2] ? x2 : 0.0, nn[2], acc[p + 2]);
-                        acc[p + 3] = fma(take[p + 3] ? x3 : 0.0, nn[3], acc[p + 3]);
-                    }
-                }
-                ++k;
+                    ++k;
+                } while (k < kend);
                 continue;
             }
             if (path == kGH3Core) {
-                // the general path's sequences for these groups: a group
-                // without series points the 3-node path's, one with them a
-                // division per point, the series points adding zero
-                const uint32_t cb = (uint32_t)__builtin_amdgcn_readfirstlane((int)bnd[k].z);
-                const int32_t clo = bnd_lo(cb), chi = bnd_hi(cb);
-                const double nu0 = tile[k].nu0, Lg = tile[k].Lg;
-                const double M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Bn = tile[k].Bn, Cn = tile[k].Cn;
-#pragma unroll
-                for (int p = 0; p < kP; p += 4) {
-                    double nn[4], mm[4];
-                    bool cp[4];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        gh3_nm(nuj[p + e] - nu0, M2, M1, M0, Bn, Cn, nn[e], mm[e]);
-                        const int32_t jr = rel0 + lane + 64 * (p + e);
-                        cp[e] = jr >= clo && jr <= chi;
+                do {
+                    // the general path's sequences for these groups: a group
+                    // without series points the 3-node path's, one with them a
+                    // division per point, the series points adding zero
+                    const uint32_t cb = (uint32_t)__builtin_amdgcn_readfirstlane((int)bnd[k].z);
+                    const int32_t clo = bnd_lo(cb), chi = bnd_hi(cb);
+                    const double nu0 = tile[k].nu0, Lg = tile[k].Lg;
+                    const double M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Bn = tile[k].Bn, Cn = tile[k].Cn;
+    #pragma unroll
+                    for (int p = 0; p < kP; p += 4) {
+                        double nn[4], mm[4];
+                        bool cp[4];
+    #pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            gh3_nm(nuj[p + e] - nu0, M2, M1, M0, Bn, Cn, nn[e], mm[e]);
+                            const int32_t jr = rel0 + lane + 64 * (p + e);
+                            cp[e] = jr >= clo && jr <= chi;
+                        }
+                        if (!cp[0] && !cp[1] && !cp[2] && !cp[3]) {
+                            const double P01 = mm[0] * mm[1], P23 = mm[2] * mm[3];
+                            const double c = qrcp(P01 * P23) * Lg;
+                            const double c01 = c * P23, c23 = c * P01;
+                            acc[p] = fma(c01 * mm[1], nn[0], acc[p]);
+                            acc[p + 1] = fma(c01 * mm[0], nn[1], acc[p + 1]);
+                            acc[p + 2] = fma(c23 * mm[3], nn[2], acc[p + 2]);
+                            acc[p + 3] = fma(c23 * mm[2], nn[3], acc[p + 3]);
+                        } else {
+    #pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const double v = qdiv(Lg * nn[e], mm[e]);
+                                acc[p + e] += cp[e] ? 0.0 : v;
+                            }
+                        }
                     }
-                    if (!cp[0] && !cp[1] && !cp[2] && !cp[3]) {
-                        const double P01 = mm[0] * mm[1], P23 = mm[2] * mm[3];
+                    ++k;
+                } while (k < kend);
+                continue;
+            }
+            do {
+                const double nu0 = tile[k].nu0, Lg = tile[k].Lg, G2 = tile[k].G2;
+                const double M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Bn = tile[k].Bn, Cn = tile[k].Cn;
+                // general path: window edges (with edges == false), region edges,
+                // core points (left to the core kernel), the grid end, lines
+                // outside the grouping range (rare)
+                const uint4 b4 = bnd[k];
+                const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b4.x);
+                const uint32_t b1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b4.y);
+                const uint32_t b2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b4.z);
+                const uint32_t b3 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b4.w);
+                const int32_t wlo = bnd_lo(b0), whi = bnd_hi(b0);
+                const int32_t g3lo = bnd_lo(b1), g3hi = bnd_hi(b1);
+                const int32_t clo = bnd_lo(b2), chi = bnd_hi(b2);
+                const bool safe = (b3 & kGroupSafe) != 0;
+    #pragma unroll
+                for (int p = 0; p < kP; p += 4) {
+                    double num[4], den[4];
+                    bool take[4], one[4], core_pt[4];
+    #pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int32_t jr = rel0 + lane + 64 * (p + e);
+                        const double dv = nuj[p + e] - nu0;
+                        double n3, m3;
+                        gh3_nm(dv, M2, M1, M0, Bn, Cn, n3, m3);
+                        one[e] = jr < g3lo || jr > g3hi;
+                        core_pt[e] = jr >= clo && jr <= chi;
+                        take[e] = jr >= wlo && jr <= whi && !core_pt[e];
+                        num[e] = one[e] ? 1.0 : n3;
+                        den[e] = one[e] ? fma(dv, dv, G2) : m3;
+                    }
+                    if (safe && !core_pt[0] && !core_pt[1] && !core_pt[2] && !core_pt[3] &&
+                        run0 + lane + 64 * (p + 3) < n) {
+                        const double P01 = den[0] * den[1], P23 = den[2] * den[3];
                         const double c = qrcp(P01 * P23) * Lg;
                         const double c01 = c * P23, c23 = c * P01;
-                        acc[p] = fma(c01 * mm[1], nn[0], acc[p]);
-                        acc[p + 1] = fma(c01 * mm[0], nn[1], acc[p + 1]);
-                        acc[p + 2] = fma(c23 * mm[3], nn[2], acc[p + 2]);
-                        acc[p + 3] = fma(c23 * mm[2], nn[3], acc[p + 3]);
+                        double xs[4], ys[4];
+                        if (one[0] && one[1] && one[2] && one[3]) {
+                            xs[0] = c01; ys[0] = den[1];
+                            xs[1] = c01; ys[1] = den[0];
+                            xs[2] = c23; ys[2] = den[3];
+                            xs[3] = c23; ys[3] = den[2];
+                        } else {
+                            xs[0] = c01 * den[1]; ys[0] = num[0];
+                            xs[1] = c01 * den[0]; ys[1] = num[1];
+                            xs[2] = c23 * den[3]; ys[2] = num[2];
+                            xs[3] = c23 * den[2]; ys[3] = num[3];
+                        }
+    #pragma unroll
+                        for (int e = 0; e < 4; ++e) acc[p + e] = fma(take[e] ? xs[e] : 0.0, ys[e], acc[p + e]);
                     } else {
-#pragma unroll
+    #pragma unroll
                         for (int e = 0; e < 4; ++e) {
-                            const double v = qdiv(Lg * nn[e], mm[e]);
-                            acc[p + e] += cp[e] ? 0.0 : v;
+                            const double v = qdiv(Lg * num[e], den[e]);
+                            acc[p + e] += take[e] ? v : 0.0;
                         }
                     }
                 }
                 ++k;
-                continue;
-            }
-            const double nu0 = tile[k].nu0, Lg = tile[k].Lg, G2 = tile[k].G2;
-            const double M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Bn = tile[k].Bn, Cn = tile[k].Cn;
-            // general path: window edges (with edges == false), region edges,
-            // core points (left to the core kernel), the grid end, lines
-            // outside the grouping range (rare)
-            const uint4 b4 = bnd[k];
-            const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b4.x);
-            const uint32_t b1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b4.y);
-            const uint32_t b2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b4.z);
-            const uint32_t b3 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b4.w);
-            const int32_t wlo = bnd_lo(b0), whi = bnd_hi(b0);
-            const int32_t g3lo = bnd_lo(b1), g3hi = bnd_hi(b1);
-            const int32_t clo = bnd_lo(b2), chi = bnd_hi(b2);
-            const bool safe = (b3 & kGroupSafe) != 0;
-#pragma unroll
-            for (int p = 0; p < kP; p += 4) {
-                double num[4], den[4];
-                bool take[4], one[4], core_pt[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int32_t jr = rel0 + lane + 64 * (p + e);
-                    const double dv = nuj[p + e] - nu0;
-                    double n3, m3;
-                    gh3_nm(dv, M2, M1, M0, Bn, Cn, n3, m3);
-                    one[e] = jr < g3lo || jr > g3hi;
-                    core_pt[e] = jr >= clo && jr <= chi;
-                    take[e] = jr >= wlo && jr <= whi && !core_pt[e];
-                    num[e] = one[e] ? 1.0 : n3;
-                    den[e] = one[e] ? fma(dv, dv, G2) : m3;
-                }
-                if (safe && !core_pt[0] && !core_pt[1] && !core_pt[2] && !core_pt[3] &&
-                    run0 + lane + 64 * (p + 3) < n) {
-                    const double P01 = den[0] * den[1], P23 = den[2] * den[3];
-                    const double c = qrcp(P01 * P23) * Lg;
-                    const double c01 = c * P23, c23 = c * P01;
-                    double xs[4], ys[4];
-                    if (one[0] && one[1] && one[2] && one[3]) {
-                        xs[0] = c01; ys[0] = den[1];
-                        xs[1] = c01; ys[1] = den[0];
-                        xs[2] = c23; ys[2] = den[3];
-                        xs[3] = c23; ys[3] = den[2];
-                    } else {
-                        xs[0] = c01 * den[1]; ys[0] = num[0];
-                        xs[1] = c01 * den[0]; ys[1] = num[1];
-                        xs[2] = c23 * den[3]; ys[2] = num[2];
-                        xs[3] = c23 * den[2]; ys[3] = num[3];
-                    }
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) acc[p + e] = fma(take[e] ? xs[e] : 0.0, ys[e], acc[p + e]);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const double v = qdiv(Lg * num[e], den[e]);
-                        acc[p + e] += take[e] ? v : 0.0;
-                    }
-                }
-            }
-            ++k;
+            } while (k < kend);
         }
         __syncthreads();
     }
