@@ -445,7 +445,7 @@ int hk_gauss_legendre(int32_t n, double* g, double* w);
  *   "f64_points_per_lane"  4 or 8 grid points per lane in the binary64
  *                          opacity kernel (default 4; its points form groups
  *                          of four that share one reciprocal).
- *   "f32_points_per_lane"  2, 4 or 8 for the binary32 kernel (default 2).
+ *   "f32_points_per_lane"  2, 4 or 8 for the binary32 kernel (default 4).
  *   "tables_batch"         states per hk_tables launch, 0 = automatic
  *                          (default).
  *   "tables_mem_mib"       device scratch budget of an automatic batch

@@ -129,7 +129,7 @@ struct hk_ctx {
     DevBuf kscratch;
     bool have_run = false;
     int f64_points_per_lane = 4;  // tile shape of the binary64 opacity kernel (4 or 8)
-    int f32_points_per_lane = 2;  // tile shape of the binary32 opacity kernel
+    int f32_points_per_lane = 4;  // tile shape of the binary32 opacity kernel
     int wing_edge_paths = 1;      // 0: window-edge runs take the general path (same bits)
     int tables_overlap = 0;       // 1: tables run the series beside the wing on the second stream
     // batched tables: per-state records, ranges and sums of one batch, the

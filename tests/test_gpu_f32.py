@@ -85,11 +85,11 @@ def test_f32_lines1e4_grid3e5_full_and_tile_shapes(ctx):
     kd = ctx.kdist(k, ppb, g).cpu().numpy()
     kd_ref = oracle.kdist(ref, ppb, g)
     assert np.max(np.abs(kd / kd_ref - 1)) <= TOL
-    for ppl in (4, 8):
+    for ppl in (2, 4, 8):
         ctx.set_option("f32_points_per_lane", ppl)
         k2 = run(ctx, lines, cond, grid).cpu().numpy()
         assert np.array_equal(kk.view(np.uint64), k2.view(np.uint64)), ppl
-    ctx.set_option("f32_points_per_lane", 2)
+    ctx.set_option("f32_points_per_lane", 4)
 
 
 def test_f32_ragged_grid_end_does_not_depend_on_the_tile_shape(ctx):
@@ -110,7 +110,7 @@ def test_f32_ragged_grid_end_does_not_depend_on_the_tile_shape(ctx):
     for ppl in (2, 4, 8):
         ctx.set_option("f32_points_per_lane", ppl)
         outs.append(run(ctx, lines, cond, grid).cpu().numpy())
-    ctx.set_option("f32_points_per_lane", 2)
+    ctx.set_option("f32_points_per_lane", 4)
     for o in outs[1:]:
         assert np.array_equal(outs[0].view(np.uint64), o.view(np.uint64))
     ref, _ = oracle.opacity(lines, cond, grid)

@@ -27,7 +27,7 @@ def ctx():
     c = hk.Context(0)
     yield c
     c.set_option("f64_points_per_lane", 4)
-    c.set_option("f32_points_per_lane", 2)
+    c.set_option("f32_points_per_lane", 4)
     c.close()
 
 

@@ -124,7 +124,7 @@ def test_tables_batches_and_shapes_are_bitwise_identical(ctx):
     finally:
         ctx.set_option("tables_batch", 0)
         ctx.set_option("tables_autotune", 1)
-        ctx.set_option("f32_points_per_lane", 2)
+        ctx.set_option("f32_points_per_lane", 4)
 
 
 def test_tables_overlap_is_bitwise_identical(ctx):
