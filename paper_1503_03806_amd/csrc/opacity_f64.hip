@@ -174,6 +174,13 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
         // instructions per line beside the path's own work; the accumulators
         // stay in place)
         const uint8_t* cw = code[wave];
+        // The 1-node and 3-node loops read each record by uniform (scalar)
+        // loads, its values then scalar operands of the VALU work, from the
+        // caches that the staging loads above have just filled: no LDS reads
+        // and no VGPRs for them (binary64 step 7.62 -> 7.20 ms; reading the
+        // records only that way, without the staging, measured slower: the
+        // scalar loads then miss).  The rarer paths read the LDS copy.
+        const WingRec* grec = wing + base;
         int k = 0;
         while (k < cnt) {
             const uint32_t path = (uint32_t)__builtin_amdgcn_readfirstlane((int)cw[k]);
@@ -193,7 +200,7 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
             }
             if (path == kGH1) {
                 do {
-                    const double nu0 = tile[k].nu0, Lg = tile[k].Lg, G2 = tile[k].G2;
+                    const double nu0 = grec[k].nu0, Lg = grec[k].Lg, G2 = grec[k].G2;
 #pragma unroll
                     for (int p = 0; p < kP; p += 4) {
                         double D[4];
@@ -216,8 +223,8 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
             }
             if (path == kGH3) {
                 do {
-                    const double nu0 = tile[k].nu0, Lg = tile[k].Lg;
-                    const double M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Bn = tile[k].Bn, Cn = tile[k].Cn;
+                    const double nu0 = grec[k].nu0, Lg = grec[k].Lg;
+                    const double M2 = grec[k].M2, M1 = grec[k].M1, M0 = grec[k].M0, Bn = grec[k].Bn, Cn = grec[k].Cn;
 #pragma unroll
                     for (int p = 0; p < kP; p += 4) {
                         double nn[4], mm[4];
