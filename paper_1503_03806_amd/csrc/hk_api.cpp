@@ -735,8 +735,8 @@ int wing_stage(hk_ctx* ctx, int precision, int ppl, const void* recs, const Wing
     return HK_OK;
 }
 
-// The current lane's second stream and its fork / join events, made on
-// first use.
+// The side stream (the series beside the wing) and its fork / join
+// events, made on first use.
 int ensure_side(hk_ctx* ctx)
 {
     if (ctx->side) return HK_OK;
