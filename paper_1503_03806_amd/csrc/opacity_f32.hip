@@ -188,7 +188,7 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
                     const float du = tile[k].du, fu = tile[k].fu, Lg = tile[k].Lg, G2 = tile[k].G2;
                     const int32_t wlo = tidx[k].wlo, whi = tidx[k].whi;
                     if (path == kGH1Edge) {
-    #pragma unroll
+#pragma unroll
                         for (int p = 0; p < kP; ++p) {
                             const int32_t j = run0 + lane + 64 * p;
                             const float dv = fmaf(fj[p] - fjc, du, -fu);
@@ -198,10 +198,10 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
                     } else {
                         const float M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Cn = tile[k].Cn;
                         const float Bn = fmaf(2.0f, G2, -1.5f);
-    #pragma unroll
+#pragma unroll
                         for (int p = 0; p < kP; p += 2) {
                             float nn[2], mm[2];
-    #pragma unroll
+#pragma unroll
                             for (int e = 0; e < 2; ++e) {
                                 const float dv = fmaf(fj[p + e] - fjc, du, -fu);
                                 const float q = dv * dv;
@@ -209,7 +209,7 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
                                 mm[e] = fmaf(fmaf(q + M2, q, M1), q, M0);
                             }
                             const float cp = rcpf(mm[0] * mm[1]) * Lg;
-    #pragma unroll
+#pragma unroll
                             for (int e = 0; e < 2; ++e) {
                                 const int32_t j = run0 + lane + 64 * (p + e);
                                 const float acc = fmaf(cp * mm[1 - e], nn[e], part[p + e]);
@@ -231,11 +231,11 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
                     const float M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Cn = tile[k].Cn;
                     const float Bn = fmaf(2.0f, tile[k].G2, -1.5f);
                     const int32_t clo = tidx[k].clo, chi = tidx[k].chi;
-    #pragma unroll
+#pragma unroll
                     for (int p = 0; p < kP; p += 2) {
                         float nn[2], mm[2];
                         bool cpt[2];
-    #pragma unroll
+#pragma unroll
                         for (int e = 0; e < 2; ++e) {
                             const int32_t j = run0 + lane + 64 * (p + e);
                             cpt[e] = j >= clo && j <= chi;
@@ -246,7 +246,7 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
                         }
                         const bool paired = !cpt[0] && !cpt[1];
                         const float cp = rcpf(mm[0] * mm[1]) * Lg;
-    #pragma unroll
+#pragma unroll
                         for (int e = 0; e < 2; ++e) {
                             const float acc = paired ? fmaf(cp * mm[1 - e], nn[e], part[p + e])
                                                      : fmaf(Lg, nn[e] * rcpf(mm[e]), part[p + e]);
@@ -265,11 +265,11 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
                 const int32_t wlo = tidx[k].wlo, whi = tidx[k].whi;
                 const int32_t g3lo = tidx[k].g3lo, g3hi = tidx[k].g3hi;
                 const int32_t clo = tidx[k].clo, chi = tidx[k].chi;
-    #pragma unroll
+#pragma unroll
                 for (int p = 0; p < kP; p += 2) {
                     float nn[2], mm[2], v1[2];
                     bool take[2], one[2], core_pt[2];
-    #pragma unroll
+#pragma unroll
                     for (int e = 0; e < 2; ++e) {
                         const int32_t j = run0 + lane + 64 * (p + e);
                         core_pt[e] = j >= clo && j <= chi;
@@ -286,7 +286,7 @@ __device__ __forceinline__ void wing_f32_tile(int64_t t, int64_t L0, int64_t L1,
                     const bool paired = !one[0] && !one[1] && !core_pt[0] && !core_pt[1] &&
                                         run0 + lane + 64 * (p + 1) < n;
                     const float cp = rcpf(mm[0] * mm[1]) * Lg;
-    #pragma unroll
+#pragma unroll
                     for (int e = 0; e < 2; ++e) {
                         const float acc = paired ? fmaf(cp * mm[1 - e], nn[e], part[p + e])
                                                  : fmaf(Lg, one[e] ? v1[e] : nn[e] * rcpf(mm[e]), part[p + e]);
