@@ -613,16 +613,16 @@ void order_lines(const hk_lines* L, bool sorted, double* dst)
     const int64_t n = L->n;
     if (n == 0) return;
     const double* src[8] = {L->nu, L->S_ref, L->E_lower, L->gamma_air, L->n_air, L->gamma_self, L->delta, L->A21};
-    std::vector<int64_t> perm;
-    if (!sorted) perm = line_order(L->nu, n);
+    if (sorted) {  // one thread: the copy runs at memory speed (as fast as eight threads made per piece)
+        for (int k = 0; k < 8; ++k)
+            if (src[k]) std::memcpy(dst + (size_t)k * n, src[k], (size_t)n * sizeof(double));
+        return;
+    }
+    const std::vector<int64_t> perm = line_order(L->nu, n);
     host_ranges(n, 8, [&](int64_t i0, int64_t i1, int) {
         for (int k = 0; k < 8; ++k) {
             double* d = dst + (size_t)k * n;
-            if (!src[k])
-                continue;
-            else if (sorted)
-                std::memcpy(d + i0, src[k] + i0, (size_t)(i1 - i0) * sizeof(double));
-            else
+            if (src[k])
                 for (int64_t i = i0; i < i1; ++i) d[i] = src[k][perm[(size_t)i]];
         }
     });
