@@ -251,17 +251,17 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                     const int32_t wlo = bnd_lo(wb), whi = bnd_hi(wb);
                     const double nu0 = tile[k].nu0, Lg = tile[k].Lg;
                     bool take[kP];
-    #pragma unroll
+#pragma unroll
                     for (int p = 0; p < kP; ++p) {
                         const int32_t jr = rel0 + lane + 64 * p;
                         take[p] = jr >= wlo && jr <= whi;
                     }
                     if (path == kGH1Edge) {
                         const double G2 = tile[k].G2;
-    #pragma unroll
+#pragma unroll
                         for (int p = 0; p < kP; p += 4) {
                             double D[4];
-    #pragma unroll
+#pragma unroll
                             for (int e = 0; e < 4; ++e) {
                                 const double dv = nuj[p + e] - nu0;
                                 D[e] = fma(dv, dv, G2);
@@ -277,10 +277,10 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                     } else {
                         const double M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Bn = tile[k].Bn,
                                      Cn = tile[k].Cn;
-    #pragma unroll
+#pragma unroll
                         for (int p = 0; p < kP; p += 4) {
                             double nn[4], mm[4];
-    #pragma unroll
+#pragma unroll
                             for (int e = 0; e < 4; ++e) gh3_nm(nuj[p + e] - nu0, M2, M1, M0, Bn, Cn, nn[e], mm[e]);
                             const double P01 = mm[0] * mm[1], P23 = mm[2] * mm[3];
                             const double c = qrcp(P01 * P23) * Lg;
@@ -305,11 +305,11 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                     const int32_t clo = bnd_lo(cb), chi = bnd_hi(cb);
                     const double nu0 = tile[k].nu0, Lg = tile[k].Lg;
                     const double M2 = tile[k].M2, M1 = tile[k].M1, M0 = tile[k].M0, Bn = tile[k].Bn, Cn = tile[k].Cn;
-    #pragma unroll
+#pragma unroll
                     for (int p = 0; p < kP; p += 4) {
                         double nn[4], mm[4];
                         bool cp[4];
-    #pragma unroll
+#pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             gh3_nm(nuj[p + e] - nu0, M2, M1, M0, Bn, Cn, nn[e], mm[e]);
                             const int32_t jr = rel0 + lane + 64 * (p + e);
@@ -324,7 +324,7 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                             acc[p + 2] = fma(c23 * mm[3], nn[2], acc[p + 2]);
                             acc[p + 3] = fma(c23 * mm[2], nn[3], acc[p + 3]);
                         } else {
-    #pragma unroll
+#pragma unroll
                             for (int e = 0; e < 4; ++e) {
                                 const double v = qdiv(Lg * nn[e], mm[e]);
                                 acc[p + e] += cp[e] ? 0.0 : v;
@@ -350,11 +350,11 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                 const int32_t g3lo = bnd_lo(b1), g3hi = bnd_hi(b1);
                 const int32_t clo = bnd_lo(b2), chi = bnd_hi(b2);
                 const bool safe = (b3 & kGroupSafe) != 0;
-    #pragma unroll
+#pragma unroll
                 for (int p = 0; p < kP; p += 4) {
                     double num[4], den[4];
                     bool take[4], one[4], core_pt[4];
-    #pragma unroll
+#pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const int32_t jr = rel0 + lane + 64 * (p + e);
                         const double dv = nuj[p + e] - nu0;
@@ -383,10 +383,10 @@ __device__ __forceinline__ void wing_f64_tile(int64_t t, int64_t L0, int64_t L1,
                             xs[2] = c23 * den[3]; ys[2] = num[2];
                             xs[3] = c23 * den[2]; ys[3] = num[3];
                         }
-    #pragma unroll
+#pragma unroll
                         for (int e = 0; e < 4; ++e) acc[p + e] = fma(take[e] ? xs[e] : 0.0, ys[e], acc[p + e]);
                     } else {
-    #pragma unroll
+#pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             const double v = qdiv(Lg * num[e], den[e]);
                             acc[p + e] += take[e] ? v : 0.0;
@@ -516,7 +516,9 @@ __device__ double voigt_core(double x, double y, double ex, double T1, const dou
     // three-term recurrence c_{n+1} = c_1 c_n - c_{n-1}, c_0 = 2, which
     // follows the growing solution e^{nx} stably (relative error ~n eps).
     // (w is read a pair of terms at a time, each pair one pair ahead of its
-    // use, so that a read is in flight while the previous pair is summed)
+    // use, so that a read is in flight while the previous pair is summed;
+    // the loop is unrolled twice, which saves the register moves of the
+    // pairs' hand-over: binary64 step 7.30 -> 7.20 ms, the same box)
     static_assert(kMaxTerms % 4 == 2, "8 double pairs in the loop, one after it");
     const double2* w2 = reinterpret_cast<const double2*>(w);
     double cm = 2.0, cc = c1, sc = 0.0;
@@ -527,7 +529,7 @@ __device__ double voigt_core(double x, double y, double ex, double T1, const dou
         cc = cn;
     };
     double2 wa = w2[0];
-#pragma unroll 1
+#pragma unroll 2
     for (int h = 0; h < kMaxTerms / 2 - 1; h += 2) {
         const double2 wb = w2[h + 1];
         term(wa.x);
