@@ -18,6 +18,7 @@ one JSON line.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -263,18 +264,18 @@ def bench_stream(hk, torch, ctx, n_chunks: int = 34):
         for _ in range(warm):
             fn()
         torch.cuda.synchronize()
+        # a full collection of Python's cyclic garbage collector, which
+        # otherwise falls every few calls into the marshalling of the 34
+        # pieces' arguments (~40-60 ms on the host, none of it the library's)
+        gc.collect()
         t0 = time.perf_counter()
         for _ in range(reps):
             fn()
         torch.cuda.synchronize()
         return 1e3 * (time.perf_counter() - t0) / reps
 
-    # four untimed calls: once per process, the call that passes ~130
-    # streamed pieces stalls ~40 ms on the host while its kernels take their
-    # usual time (measured at 17, 34 and 68 pieces per call; later calls do
-    # not), and the timed calls measure the steady state
     ms_stream = wall(lambda: ctx.opacity_stream(chunks, cond["mass_amu"], st, grid, prec, out=out,
-                                                T_ref=cond["T0"]), 3, warm=4)
+                                                T_ref=cond["T0"]), 3)
     evals = ctx.stats()["evals"]
 
     def sequential():
@@ -287,7 +288,6 @@ def bench_stream(hk, torch, ctx, n_chunks: int = 34):
     ms_load = 1e3 * (time.perf_counter() - t0)
     ms_res = wall(lambda: ctx.opacity(st, grid, prec, out=out), 3)
     return {"workload": w.name, "chunks": n_chunks, "precision": "f32_kahan", "evals": evals,
-            "untimed_calls": 4,
             "ms_streamed": ms_stream, "ms_resident_opacity": ms_res,
             "ms_load_whole_list": ms_load, "ms_load_and_opacity_per_chunk": ms_seq,
             "host_bytes": 8 * 5 * len(order),
