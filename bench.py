@@ -449,6 +449,7 @@ def main(argv=None):
             step()
         torch.cuda.synchronize()
         ctx.set_timing(True)
+        gc.collect()  # no collection of Python's garbage collector in the timed steps
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
