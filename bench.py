@@ -202,6 +202,7 @@ def bench_resample(hk, torch, ctx, kappa, N, ppb, g):
     once()
     torch.cuda.synchronize()
     reps = 5
+    gc.collect()
     t0 = time.perf_counter()
     for _ in range(reps):
         once()
@@ -308,6 +309,7 @@ def bench_tables(hk, torch, ctx, g):
     ctx.tables(states, grid, w.points_per_bin, g, hk.HK_F32_KAHAN, out=out)
     torch.cuda.synchronize()
     ctx.set_timing(True)
+    gc.collect()
     t0 = time.perf_counter()
     ctx.tables(states, grid, w.points_per_bin, g, hk.HK_F32_KAHAN, out=out)
     torch.cuda.synchronize()
@@ -365,6 +367,7 @@ def bench_surrogate(hk, torch, ctx, n_lines: int = 0, train_steps: int = 0):
         k = ctx.opacity(st, grid, prec)
         torch.cuda.synchronize()
         ctx.set_timing(True)
+        gc.collect()
         t0 = time.perf_counter()
         for _ in range(2):
             ctx.opacity(st, grid, prec, out=k)
