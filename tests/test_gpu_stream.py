@@ -127,6 +127,30 @@ def test_stream_many_chunks_both_buffers(ctx, precision):
         assert (ref[0] == 0 and v == 0) or abs(v / ref[0] - 1) <= tol
 
 
+@pytest.mark.parametrize("precision", [hk.HK_F64, hk.HK_F32_KAHAN])
+def test_stream_on_a_non_default_torch_stream(ctx, precision):
+    """A context given a caller's stream: the pieces' work, spread over that
+    stream and the context's own two, ends on the caller's stream, so the
+    grid read there right after the call is complete, and bitwise the same
+    as on the default stream."""
+    lines, cond, grid = W.lines(), W.conditions(), W.grid()
+    chunks = chunks_of(lines)
+    ref = ctx.opacity_stream(chunks, cond["mass_amu"], state_of(cond), grid, precision,
+                             T_ref=cond["T0"]).cpu().numpy()
+    s = torch.cuda.Stream()
+    c2 = hk.Context(0)
+    try:
+        with torch.cuda.stream(s):
+            c2.use_current_stream()
+            for _ in range(2):  # twice: the second call reuses both lanes of device state
+                k = c2.opacity_stream(chunks, cond["mass_amu"], state_of(cond), grid, precision,
+                                      T_ref=cond["T0"])
+                host = k.to("cpu", non_blocking=False).numpy()
+                assert np.array_equal(host.view(np.uint64), ref.view(np.uint64))
+    finally:
+        c2.close()
+
+
 def test_read_par_then_stream(ctx, tmp_path):
     """Input -> Line -> kappa: records written in the HITRAN layout, read in
     chunks of 1500 records, streamed; against the oracle on the values read."""
