@@ -249,7 +249,9 @@ int hk_opacity(hk_ctx* ctx, const hk_state* state, const hk_grid* grid,
  * c (whose updates of kappa stay in chunk order).  The result is
  * bitwise that of calling, for c = 0 .. n_chunks-1, hk_load_lines(&chunks[c],
  * species) and then hk_opacity(state, grid, precision, kappa, NULL,
- * accumulate || c > 0); only two chunks are on the device at a time.
+ * accumulate || c > 0); only two chunks are on the device at a time, each
+ * with its own set of the context's per-list buffers (records, tile
+ * ranges, work plans, sums: about 300 MB per set at 3e6 points).
  *   chunks: [host] n_chunks (0 .. HK_MAX_CHUNKS) line lists, each under the
  *     rules of hk_load_lines.  All are checked before any work is enqueued
  *     (HK_EINVAL names the chunk); chunks in non-decreasing nu are copied
